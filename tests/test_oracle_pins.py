@@ -1,0 +1,374 @@
+"""Pins for the CPU oracle (no GPU).
+
+Each test checks the oracle against something that does not come from the
+oracle's own code: closed-form eigenpairs of tridiagonal-Toeplitz Kronecker
+sums, the adjoint identity, row-sum invariants of the generators, LAPACK
+dense and banded solves, exact finite termination of Krylov methods,
+a-posteriori error certificates, and central finite differences of a dense
+solve.  ``test_oracle_mutants.py`` shows that plausible mistakes planted in a
+copy of the oracle fail these pins.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg
+import scipy.sparse
+import scipy.sparse.linalg
+
+from paper_2211_15605_amd import workloads as W
+
+EPS = np.finfo(np.float64).eps
+
+
+# ---------------------------------------------------------------- stencil product
+
+def toeplitz_mode(n, p, sub, sup):
+    """Eigenvector of tridiag(sub, 0, sup) (n x n): v_i = (sub/sup)^(i/2) sin(i p pi/(n+1)),
+    eigenvalue 2 sqrt(sub*sup) cos(p pi/(n+1)); i = 1..n."""
+    i = np.arange(1, n + 1)
+    th = p * math.pi / (n + 1)
+    return (sub / sup) ** (i / 2.0) * np.sin(i * th), 2.0 * math.sqrt(sub * sup) * math.cos(th)
+
+
+def const_coeffs(shape, c, e, w):
+    """Every slot constant, including slots that point out of the grid (must be ignored)."""
+    nx, ny, nz = shape
+    n = nx * ny * nz
+    return [np.full(n, c), np.full(n, e[0]), np.full(n, w[0]), np.full(n, e[1]), np.full(n, w[1]),
+            np.full(n, e[2]), np.full(n, w[2])]
+
+
+@pytest.mark.parametrize("shape", [(5, 4, 3), (7, 6, 5), (9, 2, 4)])
+@pytest.mark.parametrize("transpose", [False, True])
+def test_apply_closed_form_eigenpairs(orc, shape, transpose):
+    # A = c I - (S_x (+) S_y (+) S_z), S_d = tridiag(a_W, 0, a_E) along axis d:
+    # a Kronecker sum, so its eigenvectors are outer products of the 1-D modes.
+    c = 13.0
+    e = (0.7, 1.9, 0.35)   # a_E, a_N, a_T
+    w = (2.3, 0.45, 1.6)   # a_W, a_S, a_B
+    diags = const_coeffs(shape, c, e, w)
+    nx, ny, nz = shape
+    for modes in [(1, 1, 1), (2, 1, 1), (1, 2, 3), (nx, ny, nz)]:
+        vs, lam = [], c
+        for d, (n, p) in enumerate(zip(shape, modes)):
+            sub, sup = (e[d], w[d]) if transpose else (w[d], e[d])
+            v, mu = toeplitz_mode(n, min(p, n), sub, sup)
+            vs.append(v)
+            lam -= mu
+        V = np.einsum("k,j,i->kji", vs[2], vs[1], vs[0]).ravel()
+        AV = orc.apply(shape, diags, V, transpose=transpose)
+        assert np.max(np.abs(AV - lam * V)) <= 64 * EPS * (c + sum(e) + sum(w)) * np.max(np.abs(V))
+
+
+def test_apply_dirichlet_laplacian_eigenpair(orc):
+    # the constant-coefficient 7-point Laplacian with zero ghost values
+    shape = (6, 5, 4)
+    diags = const_coeffs(shape, 6.0, (1, 1, 1), (1, 1, 1))
+    p = (2, 3, 1)
+    vs = [np.sin(np.pi * pp * np.arange(1, n + 1) / (n + 1)) for n, pp in zip(shape, p)]
+    V = np.einsum("k,j,i->kji", vs[2], vs[1], vs[0]).ravel()
+    lam = sum(2 - 2 * np.cos(np.pi * pp / (n + 1)) for n, pp in zip(shape, p))
+    np.testing.assert_allclose(orc.apply(shape, diags, V), lam * V, atol=1e-13)
+
+
+@pytest.mark.parametrize("recipe,margin", [("cd", 0.1), ("sym", 1e-3)])
+def test_apply_row_sums_of_generated_systems(orc, recipe, margin):
+    # the generators set a_P = sum(in-grid a_nb) + margin, so A 1 = margin in every row
+    g = W.Grid(9, 7, 5)
+    diags = W.coefficients(g, recipe, W.rng_for(7, 0))
+    r = orc.apply(g.shape, diags, np.ones(g.n))
+    np.testing.assert_allclose(r, margin, atol=32 * EPS * np.max(diags[0]))
+
+
+def test_apply_row_sums_ignore_outward_slots(orc):
+    # random values in every slot, outward ones included; a_P = sum(in-grid) + 0.5
+    g = W.Grid(6, 5, 4)
+    diags = W.random_general(g, seed=3)
+    r = orc.apply(g.shape, diags, np.ones(g.n))
+    np.testing.assert_allclose(r, 0.5, atol=1e-14)
+
+
+@pytest.mark.parametrize("shape", [(6, 5, 4), (1, 7, 3), (8, 1, 1)])
+def test_apply_adjoint_identity(orc, shape):
+    g = W.Grid(*shape)
+    diags = W.random_general(g, seed=5)
+    rng = np.random.default_rng(1)
+    x, y = rng.standard_normal(g.n), rng.standard_normal(g.n)
+    lhs = np.dot(orc.apply(shape, diags, y, transpose=True), x)
+    rhs = np.dot(y, orc.apply(shape, diags, x))
+    assert abs(lhs - rhs) <= 1e-13 * (abs(lhs) + np.linalg.norm(x) * np.linalg.norm(y))
+
+
+def test_apply_symmetric_recipe_is_self_adjoint(orc):
+    g = W.Grid(7, 6, 5)
+    diags = W.coefficients(g, "sym", W.rng_for(7, 1))
+    x = np.random.default_rng(2).standard_normal(g.n)
+    np.testing.assert_allclose(orc.apply(g.shape, diags, x, True), orc.apply(g.shape, diags, x),
+                               rtol=0, atol=1e-13)
+
+
+def test_dot_against_exactly_rounded_sum(orc):
+    rng = np.random.default_rng(3)
+    n = 100_003
+    u, v = rng.standard_normal(n), rng.standard_normal(n)
+    exact = math.fsum((u * v).tolist())
+    nch = -(-n // 4096)
+    bound = (4096 + nch) * EPS * float(np.sum(np.abs(u * v)))
+    assert abs(orc.dot(u, v) - exact) <= bound
+
+
+def test_dot_independent_of_thread_count(orc):
+    rng = np.random.default_rng(4)
+    u, v = rng.standard_normal(300_001), rng.standard_normal(300_001)
+    old = orc.get_threads()
+    try:
+        orc.set_threads(1)
+        d1 = orc.dot(u, v)
+        orc.set_threads(5)
+        d5 = orc.dot(u, v)
+    finally:
+        orc.set_threads(old)
+    assert d1 == d5
+
+
+# ---------------------------------------------------------------- solve
+
+def dense_of(orc, g, diags):
+    return orc.dense(g.shape, diags)
+
+
+@pytest.mark.parametrize("side", [8, 16])
+def test_bicgstab_matches_dense_lu(orc, side):
+    g = W.Grid(side, side, side)
+    s = W.make_set(0, 0, grid=g)
+    A = dense_of(orc, g, s["diags"])
+    b = A @ s["x_star"]
+    x_lu = np.linalg.solve(A, b)
+    x, info = orc.bicgstab(g.shape, s["diags"], b, tol=1e-13, maxit=1000)
+    assert info["status"] == 0
+    assert np.linalg.norm(b - A @ x) <= 1e-13 * np.linalg.norm(b)
+    assert np.linalg.norm(x - x_lu) <= 1e-10 * np.linalg.norm(x_lu)
+
+
+@pytest.mark.parametrize("tol", [1e-6, 1e-10, 1e-12])
+@pytest.mark.parametrize("cfg", [0, 1])
+def test_bicgstab_residual_invariant_and_certificate(orc, tol, cfg):
+    g = W.Grid(12, 20, 10)
+    s = W.make_set(cfg, 0, grid=g)
+    A = scipy.sparse.csr_matrix(dense_of(orc, g, s["diags"]))
+    b = A @ s["x_star"]
+    x, info = orc.bicgstab(g.shape, s["diags"], b, tol=tol, maxit=5000)
+    assert info["status"] == 0
+    rel = np.linalg.norm(b - A @ x) / np.linalg.norm(b)
+    assert rel <= tol
+    assert abs(rel - info["rel_res"]) <= 1e-3 * rel + 1e-16
+    # Varah: ||x - x*||_inf <= ||b - A x||_inf / min_c(a_P - sum|a_nb|)
+    margin = 0.1 if cfg == 0 else 1e-3
+    cert = np.max(np.abs(b - A @ x)) / margin
+    assert np.max(np.abs(x - s["x_star"])) <= cert * (1 + 1e-6) + 1e-15
+
+
+def test_bicgstab_jacobi_off_matches_lu(orc):
+    # the paper's verification setting: no preconditioner
+    g = W.Grid(8, 8, 8)
+    s = W.make_set(0, 0, grid=g)
+    A = dense_of(orc, g, s["diags"])
+    b = A @ s["x_star"]
+    x, info = orc.bicgstab(g.shape, s["diags"], b, tol=1e-13, maxit=2000, jacobi=False)
+    assert info["status"] == 0
+    np.testing.assert_allclose(x, np.linalg.solve(A, b), rtol=0, atol=1e-10)
+
+
+def test_bicgstab_one_dimensional_matches_banded_lu(orc):
+    g = W.Grid(40, 1, 1)
+    s = W.make_set(0, 0, grid=g)
+    P, E, Wd = s["diags"][0], s["diags"][1], s["diags"][2]
+    n = g.n
+    ab = np.zeros((3, n))
+    ab[0, 1:] = -E[:-1]   # superdiagonal: row c, column c+1
+    ab[1, :] = P
+    ab[2, :-1] = -Wd[1:]  # subdiagonal: row c+1, column c
+    b = np.random.default_rng(5).uniform(-1, 1, n)
+    x_band = scipy.linalg.solve_banded((1, 1), ab, b)
+    x, info = orc.bicgstab(g.shape, s["diags"], b, tol=1e-14, maxit=200)
+    assert info["status"] == 0
+    np.testing.assert_allclose(x, x_band, rtol=0, atol=1e-12)
+
+
+def test_bicgstab_diagonal_system_exits_after_one_half_step(orc):
+    # a_nb = 0: A M^{-1} = I, so s = r - alpha A p^ = 0 after the first product
+    g = W.Grid(5, 4, 3)
+    rng = np.random.default_rng(6)
+    P = rng.uniform(1, 3, g.n)
+    diags = [P] + [np.zeros(g.n)] * 6
+    b = rng.uniform(-1, 1, g.n)
+    x, info = orc.bicgstab(g.shape, diags, b, tol=1e-12, maxit=10)
+    assert info["status"] == 0 and info["iters"] == 1 and info["half_exit"] == 1
+    np.testing.assert_allclose(x, b / P, rtol=4 * EPS, atol=0)
+
+
+@pytest.mark.parametrize("nx", [2, 3])
+def test_bicgstab_finite_termination(orc, nx):
+    # Krylov methods are exact after at most n steps in exact arithmetic
+    g = W.Grid(nx, 1, 1)
+    diags = W.random_general(g, seed=7 + nx)
+    b = np.random.default_rng(8).uniform(-1, 1, g.n)
+    x, info = orc.bicgstab(g.shape, diags, b, tol=1e-14, maxit=nx)
+    A = dense_of(orc, g, diags)
+    assert info["status"] == 0 and info["iters"] <= nx
+    np.testing.assert_allclose(x, np.linalg.solve(A, b), rtol=1e-13, atol=1e-14)
+
+
+def test_bicgstab_exact_initial_guess_takes_no_iteration(orc):
+    g = W.Grid(6, 6, 6)
+    s = W.make_set(0, 0, grid=g)
+    b = orc.apply(g.shape, s["diags"], s["x_star"])
+    x, info = orc.bicgstab(g.shape, s["diags"], b, x0=s["x_star"], tol=1e-10)
+    assert info["status"] == 0 and info["iters"] == 0
+    assert np.array_equal(x, s["x_star"])
+
+
+def test_bicgstab_zero_rhs_gives_zero(orc):
+    g = W.Grid(4, 4, 4)
+    s = W.make_set(0, 0, grid=g)
+    x, info = orc.bicgstab(g.shape, s["diags"], np.zeros(g.n), x0=np.ones(g.n))
+    assert info["status"] == 0 and info["iters"] == 0 and not np.any(x)
+
+
+def test_bicgstab_status_codes(orc):
+    g = W.Grid(6, 6, 6)
+    s = W.make_set(0, 0, grid=g)
+    b = orc.apply(g.shape, s["diags"], s["x_star"])
+    # maxit too small: computed, not converged
+    x, info = orc.bicgstab(g.shape, s["diags"], b, tol=1e-12, maxit=1)
+    assert info["status"] == 1 and info["iters"] == 1 and info["rel_res"] > 1e-12
+    # NaN in b
+    bn = b.copy(); bn[7] = np.nan
+    _, info = orc.bicgstab(g.shape, s["diags"], bn)
+    assert info["status"] == 3
+    # zero diagonal is an argument error
+    d = [a.copy() for a in s["diags"]]; d[0][3] = 0.0
+    _, info = orc.bicgstab(g.shape, d, b)
+    assert info["status"] == -1
+    # bad tolerance / maxit
+    assert orc.bicgstab(g.shape, s["diags"], b, tol=0.0)[1]["status"] == -1
+    assert orc.bicgstab(g.shape, s["diags"], b, maxit=0)[1]["status"] == -1
+
+
+def test_bicgstab_breakdown_on_exact_integer_system(orc):
+    # A = [[1, -2], [0, 1]] (a_P = 1, a_E(0) = 2), b = (1, 1), x0 = 0:
+    # r = r^ = (1, 1) and (r^, A M^{-1} r) = 1 + 1 - 2 = 0 exactly.
+    g = W.Grid(2, 1, 1)
+    z = np.zeros(2)
+    diags = [np.ones(2), np.array([2.0, 0.0]), z, z, z, z, z]
+    x, info = orc.bicgstab(g.shape, diags, np.ones(2), tol=1e-10, maxit=10)
+    assert info["status"] == 2 and info["iters"] == 1
+
+
+def test_bicgstab_agrees_with_scipy_bicgstab(orc):
+    # run-only cross-check against an independent library implementation
+    g = W.Grid(10, 16, 8)
+    s = W.make_set(1, 0, grid=g)
+    A = scipy.sparse.csr_matrix(dense_of(orc, g, s["diags"]))
+    b = A @ s["x_star"]
+    Minv = scipy.sparse.diags(1.0 / s["diags"][0])
+    xs, flag = scipy.sparse.linalg.bicgstab(A, b, rtol=1e-12, atol=0, maxiter=5000, M=Minv)
+    assert flag == 0
+    x, info = orc.bicgstab(g.shape, s["diags"], b, tol=1e-12, maxit=5000)
+    assert info["status"] == 0
+    xl = scipy.sparse.linalg.spsolve(A.tocsc(), b)
+    assert np.linalg.norm(x - xl) <= 1e-6 * np.linalg.norm(xl)
+    assert np.linalg.norm(xs - xl) <= 1e-6 * np.linalg.norm(xl)
+
+
+def test_bicgstab_thread_count_does_not_change_result(orc):
+    g = W.Grid(20, 24, 16)
+    s = W.make_set(0, 0, grid=g)
+    b = orc.apply(g.shape, s["diags"], s["x_star"])
+    old = orc.get_threads()
+    try:
+        orc.set_threads(1)
+        x1, i1 = orc.bicgstab(g.shape, s["diags"], b)
+        orc.set_threads(7)
+        x7, i7 = orc.bicgstab(g.shape, s["diags"], b)
+    finally:
+        orc.set_threads(old)
+    assert i1 == i7 and np.array_equal(x1, x7)
+
+
+# ---------------------------------------------------------------- gradient
+
+def test_grad_matches_finite_differences_of_dense_solve(orc):
+    # L(a) = w . A(a)^{-1} b, differentiated entry by entry with central differences
+    g = W.Grid(3, 3, 2)
+    diags = W.random_general(g, seed=11)
+    rng = np.random.default_rng(12)
+    b, w = rng.standard_normal(g.n), rng.standard_normal(g.n)
+
+    def loss(ds, bb):
+        return float(w @ np.linalg.solve(orc.dense(g.shape, ds), bb))
+
+    A = orc.dense(g.shape, diags)
+    x = np.linalg.solve(A, b)
+    lam = np.linalg.solve(A.T, w)
+    G = orc.grad(g.shape, lam, x)
+    h = 1e-6
+    for slot in range(7):
+        for c in range(g.n):
+            dp = [a.copy() for a in diags]; dm = [a.copy() for a in diags]
+            dp[slot][c] += h; dm[slot][c] -= h
+            fd = (loss(dp, b) - loss(dm, b)) / (2 * h)
+            assert abs(fd - G[slot][c]) <= 1e-7 * (1 + abs(fd)), (slot, c, fd, G[slot][c])
+    # dL/db = lambda
+    for c in range(g.n):
+        bp = b.copy(); bm = b.copy(); bp[c] += h; bm[c] -= h
+        assert abs((loss(diags, bp) - loss(diags, bm)) / (2 * h) - lam[c]) <= 1e-7 * (1 + abs(lam[c]))
+
+
+def test_grad_through_oracle_solves_matches_directional_fd(orc):
+    # the whole adjoint path on the oracle: x by BiCGSTAB, lambda by BiCGSTAB on A^T
+    g = W.Grid(8, 8, 8)
+    s = W.make_set(3, 0, grid=g, with_weights=True)
+    diags, w = s["diags"], s["w"]
+    b = orc.apply(g.shape, diags, s["x_star"])
+    x, i1 = orc.bicgstab(g.shape, diags, b, tol=1e-15, maxit=2000)
+    rng = np.random.default_rng(13)
+    # lambda = A^{-T} w by the oracle's transpose product and a dense solve of it
+    AT = orc.dense(g.shape, diags, transpose=True)
+    lam = np.linalg.solve(AT, w)
+    G = orc.grad(g.shape, lam, x)
+    h = 1e-6
+    for _ in range(4):
+        dirs = [rng.choice([-1.0, 0.0, 1.0], g.n, p=[0.05, 0.9, 0.05]) for _ in range(7)]
+        dirs[0] = np.abs(dirs[0])
+        db = rng.choice([-1.0, 0.0, 1.0], g.n, p=[0.05, 0.9, 0.05])
+        pred = sum(float(G[k] @ dirs[k]) for k in range(7)) + float(lam @ db)
+
+        def L(sign):
+            d2 = [a + sign * h * dd for a, dd in zip(diags, dirs)]
+            xx, ii = orc.bicgstab(g.shape, d2, b + sign * h * db, x0=x, tol=1e-15, maxit=2000)
+            return float(w @ xx)
+
+        fd = (L(+1) - L(-1)) / (2 * h)
+        assert abs(fd - pred) <= 1e-5 * max(1.0, abs(pred)), (fd, pred)
+
+
+# ---------------------------------------------------------------- helpers
+
+def test_matching_digits_equation_6(orc):
+    ref = np.array([1.0, 2.0, -3.0, 0.0])
+    val = np.array([1.0 + 1e-9, 2.0, -3.003, 5.0])
+    d = orc.matching_digits(ref, val)
+    assert d.size == 3
+    assert abs(d[0] - 9.0) < 1e-6 and d[1] == 17.0 and abs(d[2] - 3.0) < 1e-9
+
+
+def test_bicgstab_transpose_matches_dense_lu(orc):
+    # the adjoint system A^T lam = w against LAPACK on the numpy transpose of A
+    g = W.Grid(8, 6, 5)
+    s = W.make_set(3, 0, grid=g, with_weights=True)
+    A = orc.dense(g.shape, s["diags"])
+    lam, info = orc.bicgstab(g.shape, s["diags"], s["w"], tol=1e-13, maxit=1000, transpose=True)
+    assert info["status"] == 0
+    np.testing.assert_allclose(lam, np.linalg.solve(A.T, s["w"]), rtol=0, atol=1e-10)
