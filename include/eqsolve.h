@@ -1,0 +1,149 @@
+/*
+ * eqsolve.h -- C ABI of the MI355X (gfx950) equation-set solver.
+ *
+ * The operation: each equation set of a time step (u, v, w momentum and the
+ * pressure correction) is one linear system that equation decomposition
+ * hands, whole, to one device (Woo et al., arXiv 2211.15605, Sec. 2.2.2).
+ * Its cost is the system's stencil product and the global dot products the
+ * Krylov solver takes on every iteration (Sec. 2.2.2).  This library solves
+ * such a system on one GPU with Jacobi-preconditioned BiCGSTAB, in FP64
+ * (the paper's precision, Sec. 3.1), in FP32 with FP64 iterative refinement,
+ * or in FP32 alone, for one set or for all sets of a time step in one call
+ * (the single-device assignment "111[1]" of Sec. 2.2.2), and gives the
+ * adjoint (gradients of a loss with respect to b and the coefficients).
+ *
+ * System (Patankar form of the 7-point finite-volume discretisation):
+ *     a_P[c] x[c] - sum_{nb in E,W,N,S,T,B} a_nb[c] x[nb(c)] = b[c]
+ * on an nx*ny*nz structured grid, flat cell index c = i + nx*(j + ny*k)
+ * (i fastest; fields are flat rank-1 arrays, Sec. 2.2.3).  E/W = +x/-x,
+ * N/S = +y/-y, T/B = +z/-z.  A neighbour outside the grid contributes
+ * nothing: coefficients that point out of the grid are ignored, whatever
+ * they hold.
+ *
+ * Conventions for every entry point:
+ *  - Array arguments are DEVICE pointers (the device current when the
+ *    context was created) to contiguous FP64 arrays of n = nx*ny*nz entries.
+ *    The caller owns them; they must stay valid until the call returns.
+ *  - diag[7] is an array of 7 device pointers in the order P, E, W, N, S, T, B.
+ *  - x must not alias b or any diag array.
+ *  - Work is enqueued on the context's stream; every call returns only after
+ *    its results are complete (one small device-to-host copy of the status).
+ *  - A context is bound to one stream and is not thread-safe.
+ *  - Return value: < 0 is an error found before any work was done (x is
+ *    untouched); 0 means converged; > 0 means x holds a computed iterate that
+ *    did not meet the tolerance (see the EQS_* codes).
+ *  - Convergence: ||b - A x||_2 <= tol * ||b||_2, recomputed in FP64 from the
+ *    final x.  b = 0 gives x = 0.
+ */
+#ifndef EQSOLVE_H
+#define EQSOLVE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct eqs_ctx eqs_ctx;
+
+typedef struct {
+    int32_t nx, ny, nz;
+} eqs_grid;
+
+/* precision of the iteration */
+enum {
+    EQS_FP64 = 0,        /* plain FP64 BiCGSTAB */
+    EQS_FP32_REFINE = 1, /* FP32 inner BiCGSTAB, FP64 residual / update / norms */
+    EQS_FP32 = 2         /* one FP32 BiCGSTAB solve of the FP64 residual system */
+};
+
+/* result codes */
+enum {
+    EQS_OK = 0,
+    EQS_NOT_CONVERGED = 1, /* maxit reached, or refinement stopped reducing ||r|| */
+    EQS_BREAKDOWN = 2,     /* (r^, v) = 0, omega = 0, or rho = 0 twice */
+    EQS_NONFINITE = 3,     /* NaN/Inf in b, x0 or an iterate (x: last iterate, or untouched if in b/x0) */
+    EQS_ERR_ARG = -1,      /* bad argument: null pointer, bad sizes, tol not in (0,1), maxit < 1, a_P = 0 */
+    EQS_ERR_NOMEM = -2,    /* device allocation failed in eqsolve_create */
+    EQS_ERR_HIP = -3,      /* a HIP runtime call failed */
+    EQS_ERR_STATE = -4     /* context unusable (null, or a previous HIP failure) */
+};
+
+typedef struct {
+    int32_t status;  /* EQS_* of this set */
+    int32_t iters;   /* BiCGSTAB iterations (inner iterations for the FP32 forms) */
+    int32_t outer;   /* refinement steps (FP32 forms), restarts (FP64) */
+    int32_t pad;
+    double rel_res;  /* ||b - A x||_2 / ||b||_2 of the returned x, in FP64 */
+} eqs_info;
+
+/*
+ * Create a context for nsets equation sets with the given grids (the sets
+ * of one time step, e.g. p', u, v, w on their staggered grids).  Allocates
+ * all device workspace for `precision` once (no allocation happens in the
+ * solve calls).  hip_stream is a hipStream_t (NULL = the default stream).
+ * Grids need 1 <= nx, ny, nz and nx*ny*nz < 2^31.
+ */
+int eqsolve_create(eqs_ctx **ctx, const eqs_grid *grids, int32_t nsets, int32_t precision,
+                   void *hip_stream);
+
+/*
+ * Solve set `set` of the context: x (x0 on entry, solution on return).
+ * tol in (0, 1); maxit >= 1 (for the FP32 forms: the cap on total inner
+ * iterations).  info (host pointer) receives the outcome.
+ */
+int eqsolve_solve(eqs_ctx *ctx, int32_t set, const double *const diag[7], const double *b,
+                  double *x, double tol, int32_t maxit, eqs_info *info);
+
+/*
+ * Solve all nsets sets of the context in one call, sharing every launch
+ * (the time step's equation sets on one device).  diag[s][7], b[s], x[s],
+ * tol[s], maxit[s] and info[s] are host arrays indexed by set.  Each set
+ * converges on its own; a converged set does no further work.  Per-set
+ * results equal eqsolve_solve's bit for bit.
+ */
+int eqsolve_solve_batched(eqs_ctx *ctx, const double *const *const *diag, const double *const *b,
+                          double *const *x, const double *tol, const int32_t *maxit,
+                          eqs_info *info);
+
+/*
+ * Adjoint of x = A^{-1} b for a loss L(x): given x (the converged forward
+ * solution) and w = dL/dx, solve A^T lambda = w in FP64 BiCGSTAB (Jacobi on
+ * the same a_P) and return
+ *     grad_b = lambda,
+ *     grad_diag[P][c] = -lambda[c] x[c],
+ *     grad_diag[nb][c] = +lambda[c] x[nb(c)]  (0 where nb(c) is outside the grid),
+ * i.e. the gradients with respect to the arrays as passed (Patankar signs).
+ * grad_b also serves as the solver's iterate (its input value is ignored).
+ * Any grad_diag[k] may be NULL to skip it.
+ */
+int eqsolve_adjoint(eqs_ctx *ctx, int32_t set, const double *const diag[7], const double *x,
+                    const double *w, double *grad_b, double *const grad_diag[7], double tol,
+                    int32_t maxit, eqs_info *info);
+
+/*
+ * y = A x (transpose = 0) or y = A^T x (transpose = 1) for set `set`, in FP64.
+ * y must not alias x.
+ */
+int eqsolve_apply(eqs_ctx *ctx, int32_t set, const double *const diag[7], const double *x, double *y,
+                  int32_t transpose);
+
+/* Release the context and its workspace (NULL is allowed). */
+int eqsolve_destroy(eqs_ctx *ctx);
+
+/* Static description of a result code. */
+const char *eqsolve_strerror(int code);
+
+/*
+ * Diagnostics: the launch layout chosen for set `set` at create time.
+ * out6 (host, 6 entries) receives cells per thread, segments per plane,
+ * planes per chunk, chunks, tiles, and the number of host state readbacks
+ * so far.  Returns EQS_OK or EQS_ERR_ARG.
+ */
+int eqsolve_debug_layout(const eqs_ctx *ctx, int32_t set, int32_t *out6);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EQSOLVE_H */

@@ -1,0 +1,146 @@
+"""ctypes binding of libeqsolve.so (the C ABI in include/eqsolve.h).
+
+Argument marshalling only: every step of a solve runs in the HIP library.
+PyTorch provides device memory and the stream.  The library is loaded after
+torch so that both share one HIP runtime; if it is missing this module raises
+at load time, there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libeqsolve.so")
+
+EQS_FP64, EQS_FP32_REFINE, EQS_FP32 = 0, 1, 2
+EQS_OK, EQS_NOT_CONVERGED, EQS_BREAKDOWN, EQS_NONFINITE = 0, 1, 2, 3
+EQS_ERR_ARG, EQS_ERR_NOMEM, EQS_ERR_HIP, EQS_ERR_STATE = -1, -2, -3, -4
+PRECISIONS = {"fp64": EQS_FP64, "fp32_refine": EQS_FP32_REFINE, "fp32": EQS_FP32}
+
+# symbols declared in include/eqsolve.h
+SYMBOLS = ("eqsolve_create", "eqsolve_solve", "eqsolve_solve_batched", "eqsolve_adjoint", "eqsolve_apply",
+           "eqsolve_destroy", "eqsolve_strerror", "eqsolve_debug_layout")
+
+
+class EqsGrid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32)]
+
+
+class EqsInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("outer", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("rel_res", ctypes.c_double)]
+
+    def as_dict(self):
+        return {"status": self.status, "iters": self.iters, "outer": self.outer, "rel_res": self.rel_res}
+
+
+_lock = threading.Lock()
+_lib = None
+
+VP = ctypes.c_void_p
+VPP = ctypes.POINTER(ctypes.c_void_p)
+
+
+def load(path: str | None = None):
+    """Load libeqsolve.so (once).  Raises if it has not been built."""
+    global _lib
+    with _lock:
+        if _lib is not None and path is None:
+            return _lib
+        p = path or LIB_PATH
+        if not os.path.exists(p):
+            raise RuntimeError("libeqsolve.so is not built (%s); run `python -m paper_2211_15605_amd.build`" % p)
+        L = ctypes.CDLL(p)
+        L.eqsolve_create.argtypes = [ctypes.POINTER(VP), ctypes.POINTER(EqsGrid), ctypes.c_int32, ctypes.c_int32, VP]
+        L.eqsolve_create.restype = ctypes.c_int
+        L.eqsolve_solve.argtypes = [VP, ctypes.c_int32, VPP, VP, VP, ctypes.c_double, ctypes.c_int32,
+                                    ctypes.POINTER(EqsInfo)]
+        L.eqsolve_solve.restype = ctypes.c_int
+        L.eqsolve_solve_batched.argtypes = [VP, ctypes.POINTER(VPP), VPP, VPP, ctypes.POINTER(ctypes.c_double),
+                                            ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(EqsInfo)]
+        L.eqsolve_solve_batched.restype = ctypes.c_int
+        L.eqsolve_adjoint.argtypes = [VP, ctypes.c_int32, VPP, VP, VP, VP, VPP, ctypes.c_double, ctypes.c_int32,
+                                      ctypes.POINTER(EqsInfo)]
+        L.eqsolve_adjoint.restype = ctypes.c_int
+        L.eqsolve_apply.argtypes = [VP, ctypes.c_int32, VPP, VP, VP, ctypes.c_int32]
+        L.eqsolve_apply.restype = ctypes.c_int
+        L.eqsolve_destroy.argtypes = [VP]
+        L.eqsolve_destroy.restype = ctypes.c_int
+        L.eqsolve_strerror.argtypes = [ctypes.c_int]
+        L.eqsolve_strerror.restype = ctypes.c_char_p
+        L.eqsolve_debug_layout.argtypes = [VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+        L.eqsolve_debug_layout.restype = ctypes.c_int
+        if path is None:
+            _lib = L
+        return L
+
+
+def strerror(code: int) -> str:
+    return load().eqsolve_strerror(int(code)).decode()
+
+
+def ptr_array(ptrs):
+    arr = (ctypes.c_void_p * len(ptrs))(*[ctypes.c_void_p(p) if p else None for p in ptrs])
+    return ctypes.cast(arr, VPP), arr
+
+
+# ---------------------------------------------------------------- thin wrappers (same names as the C ABI)
+
+def eqsolve_create(grids, precision: int, stream: int | None):
+    L = load()
+    g = (EqsGrid * len(grids))(*[EqsGrid(*map(int, gr)) for gr in grids])
+    h = VP()
+    rc = L.eqsolve_create(ctypes.byref(h), g, len(grids), int(precision), VP(stream or 0))
+    return rc, h
+
+
+def eqsolve_solve(h, set_id, diag_ptrs, b_ptr, x_ptr, tol, maxit):
+    L = load()
+    dp, keep = ptr_array(diag_ptrs)
+    info = EqsInfo()
+    rc = L.eqsolve_solve(h, int(set_id), dp, VP(b_ptr), VP(x_ptr), float(tol), int(maxit), ctypes.byref(info))
+    return rc, info
+
+
+def eqsolve_solve_batched(h, diag_ptrs_per_set, b_ptrs, x_ptrs, tols, maxits):
+    L = load()
+    n = len(b_ptrs)
+    inner = [ptr_array(d) for d in diag_ptrs_per_set]
+    outer = (VPP * n)(*[i[0] for i in inner])
+    bp, kb = ptr_array(b_ptrs)
+    xp, kx = ptr_array(x_ptrs)
+    t = (ctypes.c_double * n)(*map(float, tols))
+    m = (ctypes.c_int32 * n)(*map(int, maxits))
+    infos = (EqsInfo * n)()
+    rc = L.eqsolve_solve_batched(h, outer, bp, xp, t, m, infos)
+    return rc, list(infos)
+
+
+def eqsolve_adjoint(h, set_id, diag_ptrs, x_ptr, w_ptr, gb_ptr, gdiag_ptrs, tol, maxit):
+    L = load()
+    dp, k1 = ptr_array(diag_ptrs)
+    gp, k2 = ptr_array(gdiag_ptrs) if gdiag_ptrs is not None else (None, None)
+    info = EqsInfo()
+    rc = L.eqsolve_adjoint(h, int(set_id), dp, VP(x_ptr), VP(w_ptr), VP(gb_ptr), gp, float(tol), int(maxit),
+                           ctypes.byref(info))
+    return rc, info
+
+
+def eqsolve_apply(h, set_id, diag_ptrs, x_ptr, y_ptr, transpose):
+    L = load()
+    dp, keep = ptr_array(diag_ptrs)
+    return L.eqsolve_apply(h, int(set_id), dp, VP(x_ptr), VP(y_ptr), int(bool(transpose)))
+
+
+def eqsolve_destroy(h):
+    return load().eqsolve_destroy(h)
+
+
+def eqsolve_debug_layout(h, set_id):
+    out = (ctypes.c_int32 * 6)()
+    rc = load().eqsolve_debug_layout(h, int(set_id), out)
+    return rc, list(out)

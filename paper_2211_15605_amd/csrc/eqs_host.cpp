@@ -1,0 +1,596 @@
+// eqs_host.cpp -- context, workspace and solve drivers behind the eqsolve C ABI.
+//
+// A context owns, per equation set, the FP64 (and for the FP32 forms, FP32)
+// Krylov vectors, tile partials and a device-resident SolveState, all sized
+// once in eqsolve_create.  A solve call only updates the set's descriptor
+// (the caller's pointers, tol, maxit) and enqueues kernels on the context's
+// stream; the BiCGSTAB scalars never leave the device.  The host reads the
+// small state block back once per chunk of iterations to decide what to
+// enqueue next (more iterations, the true-residual recheck, the refinement
+// update), and sizes the next chunk from the observed convergence rate, so
+// a solve costs a handful of host round trips, not one per iteration.
+//
+// This mirrors the paper's runtime shape (arXiv 2211.15605, Sec. 2.2.1 and
+// 2.2.2): state stays resident on the device between calls and only scalars
+// cross the host boundary.
+
+#include <hip/hip_runtime_api.h>
+
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "eqs_internal.h"
+#include "eqs_launch.h"
+#include "eqsolve.h"
+
+using namespace eqs;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr size_t kMaxLds = 64 * 1024;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct SetHost {
+    eqs_grid g;
+    int n, plane;
+    int S, KC, NKC, ntiles;
+    // workspace offsets resolved to pointers
+    double *r, *rh, *p[2], *v[2], *t;
+    float *a32[7];
+    float *r32, *rh32, *p32[2], *v32[2], *t32, *d32;
+    double *partials;
+    uint32_t *counter;
+    // convergence-rate tracking for chunk sizing
+    int last_iters;
+    double last_log_rr;
+};
+
+int env_int(const char *name, int dflt) {
+    const char *s = getenv(name);
+    if (!s || !*s) return dflt;
+    return atoi(s);
+}
+
+}  // namespace
+
+struct eqs_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int nsets = 0;
+    int precision = 0;
+    int cpt = 2;
+    int max_nx = 1;
+    std::vector<SetHost> sets;
+    SetDesc *h_desc = nullptr;
+    SetDesc *d_desc = nullptr;
+    SolveState *h_state = nullptr;
+    SolveState *d_state = nullptr;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    bool broken = false;
+    uint64_t launches = 0, readbacks = 0;
+};
+
+namespace {
+
+#define EQS_HIP(call)                                 \
+    do {                                              \
+        if ((call) != hipSuccess) {                   \
+            (void)hipGetLastError();                  \
+            c->broken = true;                         \
+            return EQS_ERR_HIP;                       \
+        }                                             \
+    } while (0)
+
+bool grid_ok(const eqs_grid &g) {
+    if (g.nx < 1 || g.ny < 1 || g.nz < 1) return false;
+    const long long n = (long long)g.nx * g.ny * g.nz;
+    return n < (1ll << 31) - (1ll << 20);
+}
+
+// tiles: segments of Q = 256*cpt cells per plane, KC planes per chunk
+void choose_tiling(SetHost &s, int cpt) {
+    const int Q = kBlock * cpt;
+    s.S = (s.plane + Q - 1) / Q;
+    const int target = std::max(1, env_int("EQS_TILE_TARGET", 2048));
+    int kc = env_int("EQS_KC", 0);
+    if (kc <= 0) {
+        const long long want = ((long long)s.S * s.g.nz + target - 1) / target;
+        kc = (int)std::min<long long>(std::max<long long>(want, 1), 32);
+    }
+    s.KC = std::min(kc, s.g.nz);
+    s.NKC = (s.g.nz + s.KC - 1) / s.KC;
+    s.ntiles = s.S * s.NKC;
+}
+
+void fill_desc(eqs_ctx *c, int s) {
+    SetHost &h = c->sets[s];
+    SetDesc &d = c->h_desc[s];
+    d.nx = h.g.nx;
+    d.ny = h.g.ny;
+    d.nz = h.g.nz;
+    d.plane = h.plane;
+    d.n = h.n;
+    d.S = h.S;
+    d.KC = h.KC;
+    d.NKC = h.NKC;
+    d.ntiles = h.ntiles;
+    d.r = h.r;
+    d.rh = h.rh;
+    d.p[0] = h.p[0];
+    d.p[1] = h.p[1];
+    d.v[0] = h.v[0];
+    d.v[1] = h.v[1];
+    d.t = h.t;
+    for (int k = 0; k < 7; ++k) d.a32[k] = h.a32[k];
+    d.r32 = h.r32;
+    d.rh32 = h.rh32;
+    d.p32[0] = h.p32[0];
+    d.p32[1] = h.p32[1];
+    d.v32[0] = h.v32[0];
+    d.v32[1] = h.v32[1];
+    d.t32 = h.t32;
+    d.d32 = h.d32;
+    d.partials = h.partials;
+    d.counter = h.counter;
+    d.st = c->d_state + s;
+}
+
+LaunchSets launch_table(eqs_ctx *c, int first, int count, int *total) {
+    LaunchSets ls;
+    memset(&ls, 0, sizeof(ls));
+    ls.nsets = count;
+    int acc = 0;
+    for (int i = 0; i < count; ++i) {
+        ls.tile_begin[i] = acc;
+        acc += c->sets[first + i].ntiles;
+    }
+    for (int i = count; i <= kMaxSets; ++i) ls.tile_begin[i] = acc;
+    ls.desc = c->d_desc + first;
+    *total = acc;
+    return ls;
+}
+
+struct Run {
+    eqs_ctx *c;
+    int first, count;
+    LaunchSets ls;
+    int ntiles;
+    int max_nx;
+    bool fp32, trans;
+    long guard_limit;
+
+    int L(Kern k, const double *x = nullptr, double *y = nullptr, int arg = 0, bool f32 = false) {
+        c->launches++;
+        if (launch_kernel(k, ls, ntiles, c->cpt, max_nx, f32, trans, c->stream, x, y, arg) != hipSuccess) {
+            (void)hipGetLastError();
+            c->broken = true;
+            return EQS_ERR_HIP;
+        }
+        return 0;
+    }
+    int readback() {
+        c->readbacks++;
+        EQS_HIP(hipMemcpyAsync(c->h_state + first, c->d_state + first, sizeof(SolveState) * count,
+                               hipMemcpyDeviceToHost, c->stream));
+        EQS_HIP(hipStreamSynchronize(c->stream));
+        return 0;
+    }
+    const SolveState &st(int i) const { return c->h_state[first + i]; }
+    bool all_done() const {
+        for (int i = 0; i < count; ++i)
+            if (!st(i).done) return false;
+        return true;
+    }
+    template <class F>
+    bool any(F f) const {
+        for (int i = 0; i < count; ++i)
+            if (f(st(i))) return true;
+        return false;
+    }
+    void reset_rate() {
+        for (int i = 0; i < count; ++i) c->sets[first + i].last_iters = -1;
+    }
+    // iterations to enqueue before the next look at the state
+    int chunk() {
+        int best = 2;
+        bool any_active = false;
+        for (int i = 0; i < count; ++i) {
+            const SolveState &s = st(i);
+            SetHost &h = c->sets[first + i];
+            if (!s.active) continue;
+            any_active = true;
+            const double lrr = s.rr > 0 ? log(s.rr) : -700.0;
+            const double lgoal = s.lim2 > 0 ? 2.0 * log(s.lim2) : -700.0;
+            int want;
+            if (h.last_iters >= 0 && s.iters > h.last_iters && lrr < h.last_log_rr) {
+                const double slope = (lrr - h.last_log_rr) / (double)(s.iters - h.last_iters);
+                const double rem = (lgoal - lrr) / slope;
+                want = (int)std::min(1e6, ceil(1.1 * std::max(0.0, rem))) + 2;
+                const int prev = std::max(8, s.iters - h.last_iters);
+                want = std::min(want, 4 * prev);
+            } else {
+                want = h.last_iters < 0 ? 8 : std::max(8, 2 * (s.iters - std::max(0, h.last_iters)));
+            }
+            h.last_iters = s.iters;
+            h.last_log_rr = lrr;
+            want = std::min(want, s.maxit - s.iters);
+            best = std::max(best, want);
+        }
+        if (!any_active) return 0;
+        return std::min(best, 1024);
+    }
+};
+
+int run_fp64(Run &R) {
+    int rc;
+    if ((rc = R.L(K_SETUP))) return rc;
+    if ((rc = R.readback())) return rc;
+    R.reset_rate();
+    for (long guard = 0;; ++guard) {
+        if (guard > R.guard_limit) { R.c->broken = true; return EQS_ERR_STATE; }
+        if (R.all_done()) break;
+        if (R.any([](const SolveState &s) { return s.converged || s.need_report; })) {
+            if ((rc = R.L(K_RECHECK))) return rc;
+            if ((rc = R.L(K_REPORT))) return rc;
+            if ((rc = R.readback())) return rc;
+            R.reset_rate();
+            continue;
+        }
+        const int C = R.chunk();
+        if (C <= 0) { R.c->broken = true; return EQS_ERR_STATE; }
+        for (int i = 0; i < C; ++i) {
+            if ((rc = R.L(K_K1))) return rc;
+            if ((rc = R.L(K_K2))) return rc;
+            if ((rc = R.L(K_K3))) return rc;
+        }
+        if ((rc = R.readback())) return rc;
+    }
+    if (R.any([](const SolveState &s) { return s.zero_rhs != 0; }))
+        if ((rc = R.L(K_ZERO, nullptr, nullptr, 0))) return rc;
+    return 0;
+}
+
+int run_fp32(Run &R) {
+    int rc;
+    if ((rc = R.L(K_CAST))) return rc;
+    if ((rc = R.L(K_OUTER))) return rc;
+    if ((rc = R.readback())) return rc;
+    R.reset_rate();
+    for (long guard = 0;; ++guard) {
+        if (guard > R.guard_limit) { R.c->broken = true; return EQS_ERR_STATE; }
+        if (R.all_done()) break;
+        if (R.any([](const SolveState &s) { return s.inner_done != 0 && !s.done; })) {
+            if ((rc = R.L(K_UPDATE))) return rc;
+            if ((rc = R.L(K_OUTER))) return rc;
+            if ((rc = R.readback())) return rc;
+            R.reset_rate();
+            continue;
+        }
+        const int C = R.chunk();
+        if (C <= 0) { R.c->broken = true; return EQS_ERR_STATE; }
+        for (int i = 0; i < C; ++i) {
+            if ((rc = R.L(K_K1, nullptr, nullptr, 0, true))) return rc;
+            if ((rc = R.L(K_K2, nullptr, nullptr, 0, true))) return rc;
+            if ((rc = R.L(K_K3, nullptr, nullptr, 0, true))) return rc;
+        }
+        if ((rc = R.readback())) return rc;
+    }
+    if (R.any([](const SolveState &s) { return s.zero_rhs != 0; }))
+        if ((rc = R.L(K_ZERO, nullptr, nullptr, 0))) return rc;
+    return 0;
+}
+
+Run make_run(eqs_ctx *c, int first, int count, bool trans) {
+    Run R;
+    R.c = c;
+    R.first = first;
+    R.count = count;
+    R.ls = launch_table(c, first, count, &R.ntiles);
+    R.max_nx = 1;
+    for (int i = 0; i < count; ++i) R.max_nx = std::max(R.max_nx, c->sets[first + i].g.nx);
+    R.fp32 = false;
+    R.trans = trans;
+    // every host loop turn either runs >= 1 iteration or one housekeeping
+    // step that only follows an iteration, so 2*maxit + slack turns suffice
+    long mx = 0;
+    for (int i = 0; i < count; ++i) mx = std::max<long>(mx, c->h_desc[first + i].maxit);
+    R.guard_limit = 2 * mx + 64;
+    return R;
+}
+
+void write_info(eqs_ctx *c, int s, eqs_info *info) {
+    if (!info) return;
+    const SolveState &st = c->h_state[s];
+    info->status = st.status;
+    info->iters = st.iters;
+    info->outer = (st.mode == MODE_REFINE || st.mode == MODE_FP32) ? st.outer : st.restarts;
+    info->pad = 0;
+    if (st.zero_rhs)
+        info->rel_res = 0.0;
+    else if (st.bb_outer > 0)
+        info->rel_res = sqrt(st.rr_true / st.bb_outer);
+    else
+        info->rel_res = NAN;
+}
+
+bool diag_ok(const double *const diag[7]) {
+    if (!diag) return false;
+    for (int k = 0; k < 7; ++k)
+        if (!diag[k]) return false;
+    return true;
+}
+
+bool aliases(const void *x, const double *const diag[7], const void *b) {
+    if (x == b) return true;
+    for (int k = 0; k < 7; ++k)
+        if ((const void *)diag[k] == x) return true;
+    return false;
+}
+
+int set_mode_for(int precision) {
+    return precision == EQS_FP32_REFINE ? MODE_REFINE : (precision == EQS_FP32 ? MODE_FP32 : MODE_FP64);
+}
+
+int upload_desc(eqs_ctx *c, int first, int count) {
+    EQS_HIP(hipMemcpyAsync(c->d_desc + first, c->h_desc + first, sizeof(SetDesc) * count, hipMemcpyHostToDevice,
+                           c->stream));
+    return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int eqsolve_create(eqs_ctx **out, const eqs_grid *grids, int32_t nsets, int32_t precision, void *hip_stream) {
+    if (!out) return EQS_ERR_ARG;
+    *out = nullptr;
+    if (!grids || nsets < 1 || nsets > kMaxSets) return EQS_ERR_ARG;
+    if (precision != EQS_FP64 && precision != EQS_FP32_REFINE && precision != EQS_FP32) return EQS_ERR_ARG;
+    for (int s = 0; s < nsets; ++s)
+        if (!grid_ok(grids[s])) return EQS_ERR_ARG;
+
+    eqs_ctx *c = new (std::nothrow) eqs_ctx();
+    if (!c) return EQS_ERR_NOMEM;
+    c->stream = (hipStream_t)hip_stream;
+    c->nsets = nsets;
+    c->precision = precision;
+    if (hipGetDevice(&c->device) != hipSuccess) { delete c; return EQS_ERR_HIP; }
+
+    int max_nx = 1;
+    long long max_plane = 1;
+    for (int s = 0; s < nsets; ++s) {
+        max_nx = std::max(max_nx, grids[s].nx);
+        max_plane = std::max(max_plane, (long long)grids[s].nx * grids[s].ny);
+    }
+    int cpt = env_int("EQS_CPT", 0);
+    if (cpt != 1 && cpt != 2 && cpt != 4) cpt = max_plane >= 4 * kBlock ? 2 : 1;
+    while (cpt > 1 && march_lds_bytes(cpt, max_nx, 8) > kMaxLds) cpt /= 2;
+    if (march_lds_bytes(cpt, max_nx, 8) > kMaxLds) { delete c; return EQS_ERR_ARG; }  // nx beyond the LDS plane
+    c->cpt = cpt;
+    c->max_nx = max_nx;
+
+    c->sets.resize(nsets);
+    size_t bytes = 0;
+    const bool f32 = precision != EQS_FP64;
+    std::vector<size_t> base(nsets);
+    for (int s = 0; s < nsets; ++s) {
+        SetHost &h = c->sets[s];
+        memset(&h, 0, sizeof(h));
+        h.g = grids[s];
+        h.plane = grids[s].nx * grids[s].ny;
+        h.n = h.plane * grids[s].nz;
+        choose_tiling(h, cpt);
+        base[s] = bytes;
+        bytes += 7 * align_up((size_t)h.n * 8);
+        if (f32) bytes += 15 * align_up((size_t)h.n * 4);
+        bytes += align_up((size_t)h.ntiles * kMaxRed * 8);
+        bytes += kAlign;  // counter
+    }
+    c->ws_bytes = bytes;
+    if (hipMalloc(&c->ws, bytes) != hipSuccess) { (void)hipGetLastError(); delete c; return EQS_ERR_NOMEM; }
+    if (hipMalloc((void **)&c->d_desc, sizeof(SetDesc) * nsets) != hipSuccess ||
+        hipMalloc((void **)&c->d_state, sizeof(SolveState) * nsets) != hipSuccess ||
+        hipHostMalloc((void **)&c->h_desc, sizeof(SetDesc) * nsets, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&c->h_state, sizeof(SolveState) * nsets, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        eqsolve_destroy(c);
+        return EQS_ERR_NOMEM;
+    }
+    memset(c->h_desc, 0, sizeof(SetDesc) * nsets);
+    memset(c->h_state, 0, sizeof(SolveState) * nsets);
+    char *w = (char *)c->ws;
+    for (int s = 0; s < nsets; ++s) {
+        SetHost &h = c->sets[s];
+        char *q = w + base[s];
+        auto take = [&](size_t nb) { char *r = q; q += align_up(nb); return r; };
+        h.r = (double *)take((size_t)h.n * 8);
+        h.rh = (double *)take((size_t)h.n * 8);
+        h.p[0] = (double *)take((size_t)h.n * 8);
+        h.p[1] = (double *)take((size_t)h.n * 8);
+        h.v[0] = (double *)take((size_t)h.n * 8);
+        h.v[1] = (double *)take((size_t)h.n * 8);
+        h.t = (double *)take((size_t)h.n * 8);
+        if (f32) {
+            for (int k = 0; k < 7; ++k) h.a32[k] = (float *)take((size_t)h.n * 4);
+            h.r32 = (float *)take((size_t)h.n * 4);
+            h.rh32 = (float *)take((size_t)h.n * 4);
+            h.p32[0] = (float *)take((size_t)h.n * 4);
+            h.p32[1] = (float *)take((size_t)h.n * 4);
+            h.v32[0] = (float *)take((size_t)h.n * 4);
+            h.v32[1] = (float *)take((size_t)h.n * 4);
+            h.t32 = (float *)take((size_t)h.n * 4);
+            h.d32 = (float *)take((size_t)h.n * 4);
+        }
+        h.partials = (double *)take((size_t)h.ntiles * kMaxRed * 8);
+        h.counter = (uint32_t *)take(kAlign);
+        h.last_iters = -1;
+        fill_desc(c, s);
+    }
+    // zero counters and states once (kernels leave every counter at zero)
+    if (hipMemsetAsync(c->ws, 0, bytes, c->stream) != hipSuccess ||
+        hipMemsetAsync(c->d_state, 0, sizeof(SolveState) * nsets, c->stream) != hipSuccess ||
+        hipMemcpyAsync(c->d_desc, c->h_desc, sizeof(SetDesc) * nsets, hipMemcpyHostToDevice, c->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+        (void)hipGetLastError();
+        eqsolve_destroy(c);
+        return EQS_ERR_HIP;
+    }
+    *out = c;
+    return EQS_OK;
+}
+
+int eqsolve_destroy(eqs_ctx *c) {
+    if (!c) return EQS_OK;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->ws) (void)hipFree(c->ws);
+    if (c->d_desc) (void)hipFree(c->d_desc);
+    if (c->d_state) (void)hipFree(c->d_state);
+    if (c->h_desc) (void)hipHostFree(c->h_desc);
+    if (c->h_state) (void)hipHostFree(c->h_state);
+    (void)hipGetLastError();
+    delete c;
+    return EQS_OK;
+}
+
+int eqsolve_solve(eqs_ctx *c, int32_t set, const double *const diag[7], const double *b, double *x, double tol,
+                  int32_t maxit, eqs_info *info) {
+    if (!c || c->broken) return EQS_ERR_STATE;
+    if (set < 0 || set >= c->nsets || !diag_ok(diag) || !b || !x) return EQS_ERR_ARG;
+    if (!(tol > 0.0 && tol < 1.0) || maxit < 1) return EQS_ERR_ARG;
+    if (aliases(x, diag, b)) return EQS_ERR_ARG;
+    SetDesc &d = c->h_desc[set];
+    for (int k = 0; k < 7; ++k) d.a[k] = diag[k];
+    d.b = b;
+    d.x = x;
+    d.xf = nullptr;
+    for (int k = 0; k < 7; ++k) d.g[k] = nullptr;
+    d.mode = set_mode_for(c->precision);
+    d.tol = tol;
+    d.tol_inner = d.mode == MODE_FP32 ? tol : 1e-5;
+    d.maxit = maxit;
+    int rc = upload_desc(c, set, 1);
+    if (rc) return rc;
+    Run R = make_run(c, set, 1, false);
+    rc = d.mode == MODE_FP64 ? run_fp64(R) : run_fp32(R);
+    if (rc) return rc;
+    if ((rc = R.readback())) return rc;
+    write_info(c, set, info);
+    return c->h_state[set].status;
+}
+
+int eqsolve_solve_batched(eqs_ctx *c, const double *const *const *diag, const double *const *b, double *const *x,
+                          const double *tol, const int32_t *maxit, eqs_info *info) {
+    if (!c || c->broken) return EQS_ERR_STATE;
+    if (!diag || !b || !x || !tol || !maxit) return EQS_ERR_ARG;
+    for (int s = 0; s < c->nsets; ++s) {
+        if (!diag_ok(diag[s]) || !b[s] || !x[s]) return EQS_ERR_ARG;
+        if (!(tol[s] > 0.0 && tol[s] < 1.0) || maxit[s] < 1) return EQS_ERR_ARG;
+        if (aliases(x[s], diag[s], b[s])) return EQS_ERR_ARG;
+    }
+    for (int s = 0; s < c->nsets; ++s) {
+        SetDesc &d = c->h_desc[s];
+        for (int k = 0; k < 7; ++k) d.a[k] = diag[s][k];
+        d.b = b[s];
+        d.x = x[s];
+        d.xf = nullptr;
+        for (int k = 0; k < 7; ++k) d.g[k] = nullptr;
+        d.mode = set_mode_for(c->precision);
+        d.tol = tol[s];
+        d.tol_inner = d.mode == MODE_FP32 ? tol[s] : 1e-5;
+        d.maxit = maxit[s];
+    }
+    int rc = upload_desc(c, 0, c->nsets);
+    if (rc) return rc;
+    Run R = make_run(c, 0, c->nsets, false);
+    rc = c->precision == EQS_FP64 ? run_fp64(R) : run_fp32(R);
+    if (rc) return rc;
+    if ((rc = R.readback())) return rc;
+    int worst = EQS_OK;
+    for (int s = 0; s < c->nsets; ++s) {
+        if (info) write_info(c, s, info + s);
+        worst = std::max(worst, (int)c->h_state[s].status);
+    }
+    for (int s = 0; s < c->nsets; ++s)
+        if (c->h_state[s].status < 0) return c->h_state[s].status;
+    return worst;
+}
+
+int eqsolve_adjoint(eqs_ctx *c, int32_t set, const double *const diag[7], const double *x, const double *w,
+                    double *grad_b, double *const grad_diag[7], double tol, int32_t maxit, eqs_info *info) {
+    if (!c || c->broken) return EQS_ERR_STATE;
+    if (set < 0 || set >= c->nsets || !diag_ok(diag) || !x || !w || !grad_b) return EQS_ERR_ARG;
+    if (!(tol > 0.0 && tol < 1.0) || maxit < 1) return EQS_ERR_ARG;
+    if (aliases(grad_b, diag, w) || (const double *)grad_b == x) return EQS_ERR_ARG;
+    SetDesc &d = c->h_desc[set];
+    for (int k = 0; k < 7; ++k) d.a[k] = diag[k];
+    d.b = w;
+    d.x = grad_b;
+    d.xf = x;
+    for (int k = 0; k < 7; ++k) d.g[k] = grad_diag ? grad_diag[k] : nullptr;
+    d.mode = MODE_ADJOINT;
+    d.tol = tol;
+    d.tol_inner = tol;
+    d.maxit = maxit;
+    int rc = upload_desc(c, set, 1);
+    if (rc) return rc;
+    Run R = make_run(c, set, 1, true);
+    if ((rc = R.L(K_ZERO, nullptr, nullptr, 1))) return rc;  // lambda0 = 0
+    if ((rc = run_fp64(R))) return rc;
+    if ((rc = R.L(K_GRAD))) return rc;
+    if ((rc = R.readback())) return rc;
+    write_info(c, set, info);
+    return c->h_state[set].status;
+}
+
+int eqsolve_apply(eqs_ctx *c, int32_t set, const double *const diag[7], const double *x, double *y,
+                  int32_t transpose) {
+    if (!c || c->broken) return EQS_ERR_STATE;
+    if (set < 0 || set >= c->nsets || !diag_ok(diag) || !x || !y || (const void *)x == (const void *)y)
+        return EQS_ERR_ARG;
+    SetDesc &d = c->h_desc[set];
+    for (int k = 0; k < 7; ++k) d.a[k] = diag[k];
+    int rc = upload_desc(c, set, 1);
+    if (rc) return rc;
+    Run R = make_run(c, set, 1, transpose != 0);
+    if ((rc = R.L(K_APPLY, x, y))) return rc;
+    EQS_HIP(hipStreamSynchronize(c->stream));
+    return EQS_OK;
+}
+
+const char *eqsolve_strerror(int code) {
+    switch (code) {
+    case EQS_OK: return "converged";
+    case EQS_NOT_CONVERGED: return "not converged (iteration limit, or refinement stopped reducing the residual)";
+    case EQS_BREAKDOWN: return "BiCGSTAB breakdown";
+    case EQS_NONFINITE: return "non-finite value in the input or an iterate";
+    case EQS_ERR_ARG: return "invalid argument";
+    case EQS_ERR_NOMEM: return "device allocation failed";
+    case EQS_ERR_HIP: return "HIP runtime error";
+    case EQS_ERR_STATE: return "context unusable";
+    default: return "unknown eqsolve code";
+    }
+}
+
+// introspection used by tests and the benchmark (not part of the solver contract)
+int eqsolve_debug_layout(const eqs_ctx *c, int32_t set, int32_t *out6) {
+    if (!c || set < 0 || set >= c->nsets || !out6) return EQS_ERR_ARG;
+    const SetHost &h = c->sets[set];
+    out6[0] = c->cpt;
+    out6[1] = h.S;
+    out6[2] = h.KC;
+    out6[3] = h.NKC;
+    out6[4] = h.ntiles;
+    out6[5] = (int32_t)std::min<uint64_t>(c->readbacks, 0x7fffffff);
+    return EQS_OK;
+}
+
+}  // extern "C"

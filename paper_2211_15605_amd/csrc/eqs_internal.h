@@ -1,0 +1,90 @@
+// eqs_internal.h -- structures shared by the host driver and the gfx950 kernels.
+//
+// Every equation set owns one SetDesc (device-resident table entry) and one
+// SolveState.  Kernels take a launch table (LaunchSets) by value that maps
+// the blocks of one launch onto the tiles of one or more sets, so a single
+// set and the whole batch of a time step go through the same kernels, with
+// the same tiles and the same reduction order: per-set results do not depend
+// on how many sets share a launch.
+#pragma once
+
+#include <stdint.h>
+
+namespace eqs {
+
+constexpr int kBlock = 256;      // threads per block (4 wave64)
+constexpr int kMaxSets = 8;      // sets per launch table
+constexpr int kMaxRed = 4;       // reduction values per tile
+
+// per-set iteration mode
+enum : int32_t { MODE_FP64 = 0, MODE_REFINE = 1, MODE_FP32 = 2, MODE_ADJOINT = 3 };
+
+// computed statuses (the public EQS_* codes)
+enum : int32_t { ST_OK = 0, ST_NOT_CONVERGED = 1, ST_BREAKDOWN = 2, ST_NONFINITE = 3, ST_ERR_ARG = -1 };
+
+// Device-side state of one set's solve.  Written only by the finalising
+// block of a launch (after all tiles' partial sums are in) and read by every
+// block at the start of the next launch.
+struct SolveState {
+    double bb;        // (b, b) of the system being iterated
+    double lim2;      // (tol_iter)^2 * bb: stop when (r, r) <= lim2
+    double rho, rho_prev, alpha, omega;
+    double sigma, ts, tt, ss, rr;   // latest reductions
+    double rr_true;   // (b - A x, b - A x) in FP64 of the returned x
+    double bb_outer;  // (b, b) of the FP64 system (refinement)
+    double lim2_outer;
+    double rr_prev;   // outer residual of the previous refinement step
+    double scale;     // power of two applied to the residual cast to FP32
+    double upd_inv_scale;  // 1/scale of the inner solve being applied
+    int32_t iters;    // BiCGSTAB iterations so far (inner, for the FP32 forms)
+    int32_t maxit;
+    int32_t active;   // BiCGSTAB iterating
+    int32_t done;     // final status reached
+    int32_t status;
+    int32_t fresh;    // next K1 starts afresh: p = r, r^ = r
+    int32_t half;     // half-step exit taken in this iteration
+    int32_t converged;    // FP64: recursive residual met tol; true-residual recheck pending
+    int32_t inner_done;   // FP32 forms: inner solve finished; update + outer residual pending
+    int32_t need_report;  // final true residual pending
+    int32_t rho_restarts; // fresh starts forced by rho = 0
+    int32_t restarts;     // all fresh starts after the first
+    int32_t outer;        // refinement steps started
+    int32_t zero_rhs;     // b = 0: x must be set to 0
+    int32_t mode;
+    int32_t outer_pending;  // FP32 forms: first outer residual pending
+};
+
+struct SetDesc {
+    int32_t nx, ny, nz, plane, n;
+    // march tiling: S segments of Q = kBlock*cpt cells per plane, KC planes per chunk
+    int32_t S, KC, NKC, ntiles;
+    // pointwise tiling (same tiles)
+    int32_t mode;
+    double tol, tol_inner;
+    int32_t maxit, pad;
+    // caller arrays
+    const double *a[7];
+    const double *b;
+    double *x;
+    // FP64 work (r^ = rh); p and v are double-buffered by iteration parity
+    double *r, *rh, *p[2], *v[2], *t;
+    // FP32 work; d32 is the inner iterate
+    float *a32[7];
+    float *r32, *rh32, *p32[2], *v32[2], *t32, *d32;
+    // adjoint: forward solution and gradient outputs (grad_b is the iterate x)
+    const double *xf;
+    double *g[7];
+    // reductions
+    double *partials;   // [ntiles * kMaxRed]
+    uint32_t *counter;  // last-block ticket
+    SolveState *st;
+};
+
+// blocks of one launch -> (set, tile); set s owns logical tiles [tile_begin[s], tile_begin[s+1])
+struct LaunchSets {
+    int32_t nsets;
+    int32_t tile_begin[kMaxSets + 1];
+    const SetDesc *desc;   // device table, nsets entries
+};
+
+}  // namespace eqs

@@ -1,0 +1,162 @@
+"""Python API of the equation-set solver on torch tensors.
+
+    ctx = Context([(nx, ny, nz)], precision="fp64")
+    x, info = ctx.solve(diags, b, tol=1e-10, maxit=1000)
+
+``diags`` is a sequence of 7 float64 CUDA tensors (P, E, W, N, S, T, B), each
+holding nx*ny*nz values (flat, or shaped (nz, ny, nx)); ``b`` and ``x`` are
+likewise.  Arguments are checked here (TypeError / ValueError) before the C
+library is called; the library's own codes come back as ``info["status"]``
+and, unless ``check=False``, as exceptions for status != 0.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import binding as B
+
+
+class EqSolveError(RuntimeError):
+    def __init__(self, code, what=""):
+        self.code = code
+        super().__init__("%s: %s (%d)" % (what, B.strerror(code), code))
+
+
+class EqSolveNotConverged(EqSolveError):
+    def __init__(self, code, info, what="solve"):
+        self.info = info
+        super().__init__(code, what)
+
+
+def _check_vec(t, n, name, device):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch.Tensor" % name)
+    if t.dtype != torch.float64:
+        raise TypeError("%s must be float64, got %s" % (name, t.dtype))
+    if t.device.type != "cuda" or (device is not None and t.device != device):
+        raise ValueError("%s must be on %s" % (name, device))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if t.numel() != n:
+        raise ValueError("%s has %d values, the grid has %d" % (name, t.numel(), n))
+    return t.data_ptr()
+
+
+class Context:
+    """One eqs_ctx: the workspace for a fixed list of grids, bound to a stream."""
+
+    def __init__(self, grids, precision: str = "fp64", stream: torch.cuda.Stream | None = None, device=None):
+        if precision not in B.PRECISIONS:
+            raise ValueError("precision must be one of %s" % sorted(B.PRECISIONS))
+        grids = [tuple(int(v) for v in g) for g in grids]
+        if not grids or any(len(g) != 3 or min(g) < 1 for g in grids):
+            raise ValueError("grids must be (nx, ny, nz) triples of positive sizes")
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else
+                                   torch.device(device).index or 0)
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            rc, h = B.eqsolve_create(grids, B.PRECISIONS[precision], self.stream.cuda_stream)
+        if rc != 0:
+            raise EqSolveError(rc, "eqsolve_create")
+        self.h = h
+        self.grids = grids
+        self.precision = precision
+
+    def close(self):
+        if getattr(self, "h", None):
+            B.eqsolve_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def n(self, set_id=0):
+        nx, ny, nz = self.grids[set_id]
+        return nx * ny * nz
+
+    def _diag_ptrs(self, diags, n):
+        if len(diags) != 7:
+            raise ValueError("need 7 coefficient tensors (P, E, W, N, S, T, B)")
+        return [_check_vec(d, n, "diag[%d]" % k, self.device) for k, d in enumerate(diags)]
+
+    def layout(self, set_id=0):
+        rc, v = B.eqsolve_debug_layout(self.h, set_id)
+        keys = ("cpt", "segments", "kc", "chunks", "tiles", "readbacks")
+        return dict(zip(keys, v))
+
+    def solve(self, diags, b, x=None, tol=1e-10, maxit=1000, set_id=0, check=True):
+        n = self.n(set_id)
+        dp = self._diag_ptrs(diags, n)
+        bp = _check_vec(b, n, "b", self.device)
+        if x is None:
+            x = torch.zeros_like(b)
+        xp = _check_vec(x, n, "x", self.device)
+        if not (0.0 < tol < 1.0) or int(maxit) < 1:
+            raise ValueError("tol must be in (0, 1) and maxit >= 1")
+        rc, info = B.eqsolve_solve(self.h, set_id, dp, bp, xp, tol, maxit)
+        d = info.as_dict()
+        if rc < 0:
+            raise EqSolveError(rc, "eqsolve_solve")
+        if rc > 0 and check:
+            raise EqSolveNotConverged(rc, d)
+        return x, d
+
+    def solve_batched(self, diags_list, b_list, x_list=None, tol=1e-10, maxit=1000, check=True):
+        ns = len(self.grids)
+        if len(diags_list) != ns or len(b_list) != ns:
+            raise ValueError("need one system per set (%d)" % ns)
+        if x_list is None:
+            x_list = [torch.zeros_like(b) for b in b_list]
+        tols = list(tol) if isinstance(tol, (list, tuple)) else [tol] * ns
+        maxits = list(maxit) if isinstance(maxit, (list, tuple)) else [maxit] * ns
+        dps, bps, xps = [], [], []
+        for s in range(ns):
+            n = self.n(s)
+            dps.append(self._diag_ptrs(diags_list[s], n))
+            bps.append(_check_vec(b_list[s], n, "b[%d]" % s, self.device))
+            xps.append(_check_vec(x_list[s], n, "x[%d]" % s, self.device))
+            if not (0.0 < tols[s] < 1.0) or int(maxits[s]) < 1:
+                raise ValueError("tol must be in (0, 1) and maxit >= 1")
+        rc, infos = B.eqsolve_solve_batched(self.h, dps, bps, xps, tols, maxits)
+        ds = [i.as_dict() for i in infos]
+        if rc < 0:
+            raise EqSolveError(rc, "eqsolve_solve_batched")
+        if rc > 0 and check:
+            raise EqSolveNotConverged(rc, ds, "solve_batched")
+        return x_list, ds
+
+    def adjoint(self, diags, x, w, tol=1e-10, maxit=1000, set_id=0, want_diag=True, check=True):
+        n = self.n(set_id)
+        dp = self._diag_ptrs(diags, n)
+        xp = _check_vec(x, n, "x", self.device)
+        wp = _check_vec(w, n, "w", self.device)
+        gb = torch.empty_like(w)
+        gd = [torch.empty_like(w) for _ in range(7)] if want_diag else None
+        rc, info = B.eqsolve_adjoint(self.h, set_id, dp, xp, wp, gb.data_ptr(),
+                                     [g.data_ptr() for g in gd] if gd is not None else None, tol, maxit)
+        d = info.as_dict()
+        if rc < 0:
+            raise EqSolveError(rc, "eqsolve_adjoint")
+        if rc > 0 and check:
+            raise EqSolveNotConverged(rc, d, "adjoint")
+        return gb, gd, d
+
+    def apply(self, diags, x, transpose=False, set_id=0, out=None):
+        n = self.n(set_id)
+        dp = self._diag_ptrs(diags, n)
+        xp = _check_vec(x, n, "x", self.device)
+        y = torch.empty_like(x) if out is None else out
+        yp = _check_vec(y, n, "y", self.device)
+        rc = B.eqsolve_apply(self.h, set_id, dp, xp, yp, transpose)
+        if rc != 0:
+            raise EqSolveError(rc, "eqsolve_apply")
+        return y

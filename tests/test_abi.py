@@ -1,0 +1,65 @@
+"""The C-ABI library loads and exports every function include/eqsolve.h declares (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "eqsolve.h")
+LIB = os.path.join(ROOT, "paper_2211_15605_amd", "libeqsolve.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(eqsolve_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_2211_15605_amd import build
+        build.build()
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_entry_points():
+    fns = declared_functions()
+    for f in ("eqsolve_create", "eqsolve_solve", "eqsolve_solve_batched", "eqsolve_adjoint",
+              "eqsolve_apply", "eqsolve_destroy", "eqsolve_strerror"):
+        assert f in fns
+
+
+def test_library_exports_every_declared_symbol(lib):
+    missing = [f for f in declared_functions() if not hasattr(lib, f)]
+    assert not missing, missing
+
+
+def test_binding_symbol_list_matches_header():
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("b", os.path.join(ROOT, "paper_2211_15605_amd", "binding.py"))
+    src = open(spec.origin).read()
+    m = re.search(r"SYMBOLS = \((.*?)\)", src, re.S)
+    listed = sorted(re.findall(r'"(eqsolve_\w+)"', m.group(1)))
+    assert listed == declared_functions()
+
+
+def test_library_is_built_for_gfx950_only(lib):
+    # the offload bundle ids of the library built here name its device targets
+    data = open(LIB, "rb").read()
+    targets = set(re.findall(rb"amdgcn-amd-amdhsa--(gfx\w+)", data))
+    assert targets == {b"gfx950"}, targets
+
+
+def test_strerror_and_argument_errors_without_device(lib):
+    lib.eqsolve_strerror.restype = ctypes.c_char_p
+    assert b"converged" in lib.eqsolve_strerror(0)
+    assert b"invalid argument" in lib.eqsolve_strerror(-1)
+    # argument errors are found before any HIP call
+    lib.eqsolve_create.restype = ctypes.c_int
+    h = ctypes.c_void_p()
+    assert lib.eqsolve_create(ctypes.byref(h), None, 1, 0, None) == -1
+    lib.eqsolve_solve.restype = ctypes.c_int
+    assert lib.eqsolve_solve(None, 0, None, None, None, ctypes.c_double(1e-10), 10, None) == -4
+    assert lib.eqsolve_destroy(None) == 0

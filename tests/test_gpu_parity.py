@@ -1,0 +1,318 @@
+"""GPU parity: the HIP path against the CPU oracle, through the C ABI.
+
+Bars (FP64 unless stated):
+ * stencil product: every cell within 16 u (sum of |terms|), u = 2^-53;
+ * solves: the oracle recomputes ||b - A x|| / ||b|| <= tol for the GPU's x;
+   at tol 1e-13 the GPU and oracle solutions agree to 1e-10 relative on
+   systems whose condition number keeps that meaningful (cd recipe);
+ * pure FP32: the oracle's FP64 residual of the GPU's x <= 1e-5;
+ * batched == one-at-a-time, bit for bit;
+ * adjoint: lambda and the 7 gradients against dense LAPACK (8^3) and against
+   the oracle's own transpose solve and gradient formulas (64^3).
+"""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2211_15605_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+EPS = np.finfo(np.float64).eps
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2211_15605_amd import binding
+    binding.load()  # raises if the HIP library is missing: there is no fallback
+    return torch, torch.device("cuda", 0)
+
+
+def dev_arrays(torch, dev, arrs):
+    return [torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev) for a in arrs]
+
+
+def host(t):
+    return t.detach().cpu().numpy().ravel()
+
+
+def context(grids, precision="fp64", env=None):
+    from paper_2211_15605_amd.solver import Context
+    old = {}
+    env = env or {}
+    for k, v in env.items():
+        old[k] = os.environ.get(k)
+        os.environ[k] = str(v)
+    try:
+        return Context(grids, precision=precision)
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
+def abs_terms(orc, shape, diags, x):
+    """|a_P x| + sum |a_nb x_nb| per cell (forward operator)."""
+    neg = [np.abs(diags[0])] + [-np.abs(d) for d in diags[1:]]
+    return orc.apply(shape, neg, np.abs(x))
+
+
+SHAPES = [(16, 16, 16), (33, 17, 9), (97, 31, 5), (1, 1, 7), (5, 1, 1), (1, 300, 2), (130, 3, 40),
+          (64, 64, 4), (200, 7, 3)]
+TILINGS = [dict(), dict(EQS_CPT=1, EQS_KC=1), dict(EQS_CPT=4, EQS_KC=3), dict(EQS_CPT=2, EQS_KC=7)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("transpose", [False, True])
+def test_apply_matches_oracle_per_cell(torch_dev, orc, shape, transpose):
+    torch, dev = torch_dev
+    g = W.Grid(*shape)
+    diags = W.random_general(g, seed=21)
+    x = np.random.default_rng(22).standard_normal(g.n)
+    ref = orc.apply(shape, diags, x, transpose)
+    bound = 16 * EPS * (abs_terms(orc, shape, diags, x) if not transpose else
+                        orc.apply(shape, [np.abs(diags[0])] + [-np.abs(d) for d in diags[1:]], np.abs(x), True))
+    for tl in TILINGS:
+        ctx = context([shape], env=tl)
+        y = host(ctx.apply(dev_arrays(torch, dev, diags), dev_arrays(torch, dev, [x])[0], transpose=transpose))
+        assert np.all(np.abs(y - ref) <= bound + 1e-300), (tl, np.max(np.abs(y - ref) - bound))
+        ctx.close()
+
+
+def manufactured(orc, cfg, grid=None, recipe=None, set_id=0):
+    s = W.make_set(cfg, set_id, grid=grid, recipe=recipe)
+    g = s["grid"]
+    b = orc.apply(g.shape, s["diags"], s["x_star"])
+    return g, s["diags"], b, s["x_star"]
+
+
+def test_fp64_config0_residual_and_iterations(torch_dev, orc):
+    torch, dev = torch_dev
+    g, diags, b, xs = manufactured(orc, 0)
+    ctx = context([g.shape])
+    x, info = ctx.solve(dev_arrays(torch, dev, diags), dev_arrays(torch, dev, [b])[0], tol=1e-10, maxit=1000)
+    xg = host(x)
+    assert info["status"] == 0
+    rel = orc.rel_residual(g.shape, diags, b, xg)
+    assert rel <= 1e-10
+    assert abs(rel - info["rel_res"]) <= 1e-3 * rel
+    _, oinfo = orc.bicgstab(g.shape, diags, b, tol=1e-10, maxit=1000)
+    # rounding differs, so iteration counts may differ slightly (parity unpinned)
+    assert abs(info["iters"] - oinfo["iters"]) <= 3, (info, oinfo)
+    assert np.max(np.abs(xg - xs)) <= orc.forward_error_certificate(g.shape, diags, b, xg) * (1 + 1e-6)
+
+
+@pytest.mark.parametrize("cfg,shape", [(0, (16, 16, 16)), (0, (37, 23, 11)), (3, (64, 64, 64)),
+                                       (2, (97, 31, 5)), (0, (130, 3, 40)), (0, (5, 1, 1))])
+def test_fp64_matches_oracle_solution(torch_dev, orc, cfg, shape):
+    torch, dev = torch_dev
+    g, diags, b, xs = manufactured(orc, cfg, grid=W.Grid(*shape))
+    xo, oinfo = orc.bicgstab(g.shape, diags, b, tol=1e-13, maxit=5000)
+    assert oinfo["status"] == 0
+    for tl in TILINGS[:3]:
+        ctx = context([g.shape], env=tl)
+        x, info = ctx.solve(dev_arrays(torch, dev, diags), dev_arrays(torch, dev, [b])[0], tol=1e-13, maxit=5000)
+        xg = host(x)
+        assert info["status"] == 0, info
+        assert orc.rel_residual(g.shape, diags, b, xg) <= 1e-13
+        assert np.linalg.norm(xg - xo) <= 1e-10 * np.linalg.norm(xo), tl
+        ctx.close()
+
+
+def test_fp64_repeatable_bitwise(torch_dev, orc):
+    torch, dev = torch_dev
+    g, diags, b, _ = manufactured(orc, 0, grid=W.Grid(40, 30, 20))
+    ctx = context([g.shape])
+    D = dev_arrays(torch, dev, diags)
+    bd = dev_arrays(torch, dev, [b])[0]
+    outs = [host(ctx.solve(D, bd, tol=1e-11, maxit=2000)[0]) for _ in range(4)]
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
+def test_fp64_status_codes(torch_dev, orc):
+    torch, dev = torch_dev
+    from paper_2211_15605_amd.solver import EqSolveError
+    g, diags, b, xs = manufactured(orc, 0, grid=W.Grid(6, 6, 6))
+    ctx = context([g.shape])
+    D = dev_arrays(torch, dev, diags)
+    bd, xsd = dev_arrays(torch, dev, [b, xs])
+    # maxit too small: computed, not converged
+    x, info = ctx.solve(D, bd, tol=1e-12, maxit=1, check=False)
+    _, oinfo = orc.bicgstab(g.shape, diags, b, tol=1e-12, maxit=1)
+    assert info["status"] == 1 and info["iters"] == 1 and oinfo["status"] == 1
+    assert abs(info["rel_res"] - oinfo["rel_res"]) <= 1e-8 * oinfo["rel_res"]
+    # exact initial guess: no iteration, x untouched
+    x0 = xsd.clone()
+    x, info = ctx.solve(D, bd, x=x0, tol=1e-10)
+    assert info["iters"] == 0 and np.array_equal(host(x), xs)
+    # b = 0 gives x = 0
+    x, info = ctx.solve(D, torch.zeros_like(bd), x=torch.ones_like(bd), tol=1e-10)
+    assert info["status"] == 0 and not np.any(host(x))
+    # NaN in b: non-finite, x untouched
+    bn = bd.clone(); bn[5] = float("nan")
+    x0 = torch.full_like(bd, 3.0)
+    x, info = ctx.solve(D, bn, x=x0, check=False)
+    assert info["status"] == 3 and np.all(host(x) == 3.0)
+    # zero diagonal entry: argument error found on the device, x untouched
+    Dz = [d.clone() for d in D]; Dz[0][4] = 0.0
+    with pytest.raises(EqSolveError):
+        ctx.solve(Dz, bd, x=x0)
+    assert np.all(host(x0) == 3.0)
+    # bad tolerance rejected before the call
+    with pytest.raises(ValueError):
+        ctx.solve(D, bd, tol=0.0)
+
+
+def test_fp64_diagonal_system_one_half_step(torch_dev, orc):
+    torch, dev = torch_dev
+    g = W.Grid(9, 8, 7)
+    rng = np.random.default_rng(6)
+    P = rng.uniform(1, 3, g.n)
+    diags = [P] + [np.zeros(g.n)] * 6
+    b = rng.uniform(-1, 1, g.n)
+    ctx = context([g.shape])
+    x, info = ctx.solve(dev_arrays(torch, dev, diags), dev_arrays(torch, dev, [b])[0], tol=1e-12, maxit=10)
+    assert info["status"] == 0 and info["iters"] == 1
+    np.testing.assert_allclose(host(x), b / P, rtol=4 * EPS, atol=0)
+
+
+def test_fp64_breakdown_integer_system(torch_dev, orc):
+    torch, dev = torch_dev
+    z = np.zeros(2)
+    diags = [np.ones(2), np.array([2.0, 0.0]), z, z, z, z, z]
+    ctx = context([(2, 1, 1)])
+    x, info = ctx.solve(dev_arrays(torch, dev, diags), dev_arrays(torch, dev, [np.ones(2)])[0], tol=1e-10,
+                        maxit=10, check=False)
+    _, oinfo = orc.bicgstab((2, 1, 1), diags, np.ones(2), tol=1e-10, maxit=10)
+    assert info["status"] == 2 == oinfo["status"] and info["iters"] == 1 == oinfo["iters"]
+
+
+@pytest.mark.parametrize("cfg,shape", [(0, (16, 16, 16)), (1, (32, 64, 32)), (2, (49, 97, 23))])
+def test_fp32_refine_reaches_fp64_tolerance(torch_dev, orc, cfg, shape):
+    torch, dev = torch_dev
+    g, diags, b, xs = manufactured(orc, cfg, grid=W.Grid(*shape))
+    ctx = context([g.shape], precision="fp32_refine")
+    x, info = ctx.solve(dev_arrays(torch, dev, diags), dev_arrays(torch, dev, [b])[0], tol=1e-10, maxit=20000)
+    assert info["status"] == 0, info
+    assert info["outer"] >= 2
+    rel = orc.rel_residual(g.shape, diags, b, host(x))
+    assert rel <= 1e-10
+    assert abs(rel - info["rel_res"]) <= 1e-3 * rel
+
+
+def test_fp32_pure_residual(torch_dev, orc):
+    torch, dev = torch_dev
+    g, diags, b, xs = manufactured(orc, 0)
+    ctx = context([g.shape], precision="fp32")
+    x, info = ctx.solve(dev_arrays(torch, dev, diags), dev_arrays(torch, dev, [b])[0], tol=1e-5, maxit=2000)
+    assert info["status"] == 0, info
+    assert orc.rel_residual(g.shape, diags, b, host(x)) <= 1e-5
+    xo, _ = orc.bicgstab(g.shape, diags, b, tol=1e-13)
+    # forward error against the FP64 oracle: bounded by the Varah certificate of
+    # the FP32 result (a 1e-5 residual fixes the error only up to the condition number)
+    cert = orc.forward_error_certificate(g.shape, diags, b, host(x))
+    err = np.max(np.abs(host(x) - xo))
+    print("fp32 pure: residual %.2e, max forward error vs oracle %.2e, certificate %.2e" % (
+        info["rel_res"], err, cert), flush=True)
+    assert err <= cert * (1 + 1e-6) + 1e-12
+
+
+STAGGERED_SMALL = [(24, 96, 24), (25, 96, 24), (24, 97, 24), (24, 96, 25)]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+def test_batched_equals_sequential_bitwise(torch_dev, orc, precision):
+    torch, dev = torch_dev
+    systems = [manufactured(orc, 2, grid=W.Grid(*s), set_id=i) for i, s in enumerate(STAGGERED_SMALL)]
+    ctx = context(STAGGERED_SMALL, precision=precision)
+    Ds = [dev_arrays(torch, dev, s[1]) for s in systems]
+    bs = [dev_arrays(torch, dev, [s[2]])[0] for s in systems]
+    xb, infos = ctx.solve_batched(Ds, bs, tol=1e-10, maxit=2000)
+    for i, s in enumerate(systems):
+        xi, info = ctx.solve(Ds[i], bs[i], tol=1e-10, maxit=2000, set_id=i)
+        assert np.array_equal(host(xi), host(xb[i])), i
+        assert info == infos[i]
+        assert orc.rel_residual(s[0].shape, s[1], s[2], host(xb[i])) <= 1e-10
+
+
+def test_adjoint_matches_dense_reference(torch_dev, orc):
+    torch, dev = torch_dev
+    g = W.Grid(8, 8, 8)
+    s = W.make_set(3, 0, grid=g, with_weights=True)
+    diags, w = s["diags"], s["w"]
+    A = orc.dense(g.shape, diags)
+    b = A @ s["x_star"]
+    x = np.linalg.solve(A, b)
+    lam = np.linalg.solve(A.T, w)
+    G = orc.grad(g.shape, lam, x)
+    ctx = context([g.shape])
+    D = dev_arrays(torch, dev, diags)
+    xd, wd = dev_arrays(torch, dev, [x, w])
+    gb, gd, info = ctx.adjoint(D, xd, wd, tol=1e-13, maxit=1000)
+    assert info["status"] == 0
+    np.testing.assert_allclose(host(gb), lam, rtol=0, atol=1e-10 * np.max(np.abs(lam)))
+    for k in range(7):
+        np.testing.assert_allclose(host(gd[k]), G[k], rtol=0, atol=1e-10 * np.max(np.abs(G[k])) + 1e-300)
+
+
+def test_adjoint_config3_matches_oracle(torch_dev, orc):
+    torch, dev = torch_dev
+    g = W.Grid(64, 64, 64)
+    s = W.make_set(3, 0, grid=g, with_weights=True)
+    diags, w = s["diags"], s["w"]
+    b = orc.apply(g.shape, diags, s["x_star"])
+    xo, _ = orc.bicgstab(g.shape, diags, b, tol=1e-13, maxit=2000)
+    lo, linfo = orc.bicgstab(g.shape, diags, w, tol=1e-13, maxit=2000, transpose=True)
+    assert linfo["status"] == 0
+    Go = orc.grad(g.shape, lo, xo)
+    ctx = context([g.shape])
+    D = dev_arrays(torch, dev, diags)
+    xd, wd = dev_arrays(torch, dev, [xo, w])
+    gb, gd, info = ctx.adjoint(D, xd, wd, tol=1e-13, maxit=2000)
+    assert info["status"] == 0
+    assert orc.rel_residual(g.shape, diags, w, host(gb), transpose=True) <= 1e-13
+    assert np.linalg.norm(host(gb) - lo) <= 1e-10 * np.linalg.norm(lo)
+    for k in range(7):
+        assert np.linalg.norm(host(gd[k]) - Go[k]) <= 1e-10 * np.linalg.norm(Go[k]) + 1e-300, k
+
+
+def test_autograd_function_backward(torch_dev, orc):
+    torch, dev = torch_dev
+    from paper_2211_15605_amd.autograd import EqSolveFn
+    g = W.Grid(6, 5, 4)
+    s = W.make_set(3, 0, grid=g, with_weights=True)
+    shp = (g.nz, g.ny, g.nx)
+    T = [torch.tensor(d.reshape(shp), device=dev, requires_grad=True) for d in s["diags"]]
+    A = orc.dense(g.shape, s["diags"])
+    bnp = A @ s["x_star"]
+    bt = torch.tensor(bnp.reshape(shp), device=dev, requires_grad=True)
+    x = EqSolveFn.apply(*T, bt, None, 1e-13, 1000)
+    wt = torch.tensor(s["w"].reshape(shp), device=dev)
+    (x * wt).sum().backward()
+    xx = np.linalg.solve(A, bnp)
+    lam = np.linalg.solve(A.T, s["w"])
+    G = orc.grad(g.shape, lam, xx)
+    np.testing.assert_allclose(host(bt.grad), lam, rtol=0, atol=1e-10 * np.max(np.abs(lam)))
+    for k in range(7):
+        np.testing.assert_allclose(host(T[k].grad), G[k], rtol=0, atol=1e-10 * np.max(np.abs(G[k])) + 1e-300)
+
+
+# ---------------------------------------------------------------- full-size workloads (as benchmarked)
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+def test_config1_full_size_residual(torch_dev, orc, precision):
+    torch, dev = torch_dev
+    g, diags, b, xs = manufactured(orc, 1)
+    ctx = context([g.shape], precision=precision)
+    x, info = ctx.solve(dev_arrays(torch, dev, diags), dev_arrays(torch, dev, [b])[0], tol=1e-10, maxit=20000)
+    print("config1", precision, info, ctx.layout(), flush=True)
+    assert info["status"] == 0
+    xg = host(x)
+    rel = orc.rel_residual(g.shape, diags, b, xg)
+    assert rel <= 1e-10
+    assert np.max(np.abs(xg - xs)) <= orc.forward_error_certificate(g.shape, diags, b, xg) * (1 + 1e-6)
