@@ -1,0 +1,222 @@
+#!/usr/bin/env python
+"""Benchmark of the equation-set solve on one MI355X; prints one JSON line.
+
+Workload (default): the pressure-correction-like symmetric 7-point system on
+128 x 256 x 128 cells (near-singular, a_P = sum a_nb + 1e-3), b = A x* with
+x* ~ U[-1, 1], x0 = 0, relative tolerance 1e-10.  One step is the whole hot
+path on that system: a plain FP64 Jacobi-BiCGSTAB solve, then an FP32-inner /
+FP64-refinement solve, each from x0 = 0 to ||b - A x|| <= 1e-10 ||b||.
+
+  value      FP64 BiCGSTAB cell-iterations per second (cells x iterations /
+             solve time, setup and exit recheck included), inputs resident in HBM
+  roofline   the dominant kernel (FP64 K1: p update + Jacobi + stencil product
+             + dot), algorithmic bytes per launch / mean launch time from HIP
+             events on the solver's stream, against 8 TB/s
+  cpu_baseline  the CPU oracle (plain C, OpenMP) on the same system, a bounded
+             number of iterations
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "BiCGSTAB cell-iters/s & %HBM roofline; time to 1e-10 rel residual vs FP64"
+HBM_PEAK_GBS = 8000.0
+# algorithmic HBM words per cell per launch of each kernel (reads + writes)
+WORDS = {"k1": 13, "k2": 10, "k3": 9, "setup": 10, "recheck": 11, "report": 9}
+
+
+def kernel_source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("eqs_kernels.hip", "eqs_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2211_15605_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(cfg):
+    """HBM bytes per FP64 K1 launch from the committed rocprofv3 counter record
+    (FETCH_SIZE + WRITE_SIZE, scaled by a 1 GiB copy), or None when the kernel
+    source has changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "k1_fp64_sym128x256x128_traffic.json")
+    if cfg != 1 or not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernel_source_sha256") != kernel_source_digest():
+        return None
+    return rec["bytes_per_launch"]
+
+
+def gpu_leg(args):
+    import numpy as np
+    import torch
+
+    from paper_2211_15605_amd import workloads as W
+    from paper_2211_15605_amd.solver import Context
+
+    dev = torch.device("cuda", 0)
+    cfg = W.CONFIGS[args.config]
+    g = cfg["grids"][0]
+    s = W.make_set(args.config, 0)
+    D = [torch.from_numpy(d).to(dev) for d in s["diags"]]
+    xs = torch.from_numpy(s["x_star"]).to(dev)
+    del s
+    c64 = Context([g.shape], precision="fp64")
+    c32 = Context([g.shape], precision="fp32_refine")
+    b = c64.apply(D, xs)  # b = A x* on the device
+    tol, maxit = cfg["tol"], cfg["maxit"]
+
+    def step(rec):
+        x64 = torch.zeros_like(b)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x64, i64 = c64.solve(D, b, x64, tol=tol, maxit=maxit)
+        t1 = time.perf_counter()
+        x32 = torch.zeros_like(b)
+        x32, i32 = c32.solve(D, b, x32, tol=tol, maxit=maxit)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if rec is not None:
+            rec.append((t1 - t0, t2 - t1, i64, i32))
+        return x64, x32
+
+    for _ in range(args.warmup):
+        step(None)
+    # HIP events around every 8th K1 launch of the timed FP64 solves (sampling keeps the
+    # events' own cost out of the measured solve time)
+    c64.profile(["k1"], every=8)
+    rec = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        x64, x32 = step(rec)
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+
+    n = g.n
+    t64 = float(np.mean([r[0] for r in rec]))
+    t32 = float(np.mean([r[1] for r in rec]))
+    it64 = float(np.mean([r[2]["iters"] for r in rec]))
+    it32 = float(np.mean([r[3]["iters"] for r in rec]))
+    kstats = {}
+    for k in ("k1",):
+        cnt, ms = c64.kernel_stats(k)
+        if cnt:
+            kstats[k] = (cnt, ms)
+    # the library counts only launches that did work (not the few enqueued past convergence)
+    k1_cnt, k1_ms = kstats["k1"]
+    k1_avg_ms = k1_ms / k1_cnt
+    k1_bytes = WORDS["k1"] * 8 * n
+    achieved = k1_bytes / (k1_avg_ms * 1e-3) / 1e9
+    err64 = float(torch.max(torch.abs(x64 - xs)))
+    err32 = float(torch.max(torch.abs(x32 - xs)))
+    res = {
+        "value": n * it64 / t64,
+        "ms_per_step": 1e3 * t_total / args.steps,
+        "fp64": {"time_to_tol_ms": 1e3 * t64, "iters": it64, "rel_res": rec[-1][2]["rel_res"],
+                 "cell_iters_per_s": n * it64 / t64, "model_GBps": n * it64 * 256 / t64 / 1e9,
+                 "max_abs_err_vs_xstar": err64},
+        "fp32_refine": {"time_to_tol_ms": 1e3 * t32, "inner_iters": it32, "outer": rec[-1][3]["outer"],
+                        "rel_res": rec[-1][3]["rel_res"], "cell_iters_per_s": n * it32 / t32,
+                        "model_GBps": n * it32 * 128 / t32 / 1e9, "max_abs_err_vs_xstar": err32,
+                        "speedup_vs_fp64": t64 / t32},
+        "roofline": {"bound": "hbm", "kernel": "k1_fp64", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.config),
+                     "bytes_per_launch": k1_bytes, "mean_launch_ms": k1_avg_ms, "launches": k1_cnt},
+        "kernels_fp64_ms": {k: {"launches": v[0], "mean_ms": v[1] / v[0]} for k, v in kstats.items()},
+        "layout": c64.layout(),
+        "cells": n,
+    }
+    if args.calibrate_copy:
+        # a plain copy of known size, for scaling the HBM byte counters of a profiled run
+        nb = 1 << 30
+        src = torch.ones(nb // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        res["copy_calibration_bytes"] = {"read": nb, "write": nb}
+    c64.close()
+    c32.close()
+    return res
+
+
+def cpu_leg(args):
+    import numpy as np
+
+    from oracle import oracle as O
+    from paper_2211_15605_amd import workloads as W
+
+    o = O.default()
+    s = W.make_set(args.config, 0)
+    g = s["grid"]
+    b = o.apply(g.shape, s["diags"], s["x_star"])
+    t0 = time.perf_counter()
+    _, info = o.bicgstab(g.shape, s["diags"], b, tol=1e-10, maxit=4)
+    t_probe = time.perf_counter() - t0
+    per_it = t_probe / max(info["iters"], 1)
+    maxit = int(max(8, min(2000, args.cpu_seconds / per_it)))
+    t0 = time.perf_counter()
+    _, info = o.bicgstab(g.shape, s["diags"], b, tol=1e-10, maxit=maxit)
+    t = time.perf_counter() - t0
+    return {"value": g.n * info["iters"] / t, "unit": "cell-iters/s", "cores": o.get_threads(), "kind": "oracle",
+            "sample": "%d FP64 BiCGSTAB iterations (of a full solve) on the same %dx%dx%d system, %.1f s" % (
+                info["iters"], g.nx, g.ny, g.nz, t)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="after the timed steps, copy 1 GiB three times (reference for HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the equation sets of a time step are solved on a single "
+              "device here; --gpus %d is not supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    from paper_2211_15605_amd import workloads as W
+
+    cfg = W.CONFIGS[args.config]
+    g = cfg["grids"][0]
+    r = gpu_leg(args)
+    cpu = None if args.no_cpu_baseline else cpu_leg(args)
+    line = {
+        "metric": METRIC,
+        "value": r["value"],
+        "unit": "cell-iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "%s: %s 7-point system on %dx%dx%d cells, b = A x*, x0 = 0, tol %g; step = "
+                               "FP64 solve + FP32-inner/FP64-refinement solve" % (
+                                   cfg["name"], "symmetric near-singular" if cfg["recipe"] == "sym"
+                                   else "convection-diffusion", g.nx, g.ny, g.nz, cfg["tol"]),
+                   "cells": r["cells"], "layout": r["layout"]},
+        "roofline": r["roofline"],
+        "cpu_baseline": cpu,
+        "fp64": r["fp64"],
+        "fp32_refine": r["fp32_refine"],
+        "kernels_fp64_ms": r["kernels_fp64_ms"],
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -142,6 +142,26 @@ const char *eqsolve_strerror(int code);
  */
 int eqsolve_debug_layout(const eqs_ctx *ctx, int32_t set, int32_t *out6);
 
+/*
+ * Diagnostics: every `every`-th launch of a kernel kind whose bit is set in
+ * kind_mask (bit k for kind k, see eqsolve_debug_kernel_stats) is bracketed
+ * by two HIP events on the context's stream, and its duration is added to a
+ * per-kind total (resolved at each state readback).  kind_mask 0 turns timing
+ * off.  Any call resets the totals.  Returns EQS_OK, EQS_ERR_ARG (every < 1)
+ * or EQS_ERR_STATE.
+ */
+int eqsolve_debug_profile(eqs_ctx *ctx, int32_t kind_mask, int32_t every);
+
+/*
+ * Diagnostics: launches and total milliseconds recorded for kernel `kind`
+ * (for the three BiCGSTAB iteration kernels, only launches that did work:
+ * those enqueued past a set's convergence are left out)
+ * (0 setup, 1 recheck, 2 report, 3 K1, 4 K2, 5 K3, 6 cast, 7 outer residual,
+ * 8 update, 9 zero, 10 gradient, 11 product) in FP32 (fp32 = 1) or FP64.
+ */
+int eqsolve_debug_kernel_stats(const eqs_ctx *ctx, int32_t kind, int32_t fp32, int64_t *count,
+                               double *total_ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -23,7 +23,10 @@ PRECISIONS = {"fp64": EQS_FP64, "fp32_refine": EQS_FP32_REFINE, "fp32": EQS_FP32
 
 # symbols declared in include/eqsolve.h
 SYMBOLS = ("eqsolve_create", "eqsolve_solve", "eqsolve_solve_batched", "eqsolve_adjoint", "eqsolve_apply",
-           "eqsolve_destroy", "eqsolve_strerror", "eqsolve_debug_layout")
+           "eqsolve_destroy", "eqsolve_strerror", "eqsolve_debug_layout", "eqsolve_debug_profile",
+           "eqsolve_debug_kernel_stats")
+KERNEL_KINDS = {"setup": 0, "recheck": 1, "report": 2, "k1": 3, "k2": 4, "k3": 5, "cast": 6, "outer": 7,
+                "update": 8, "zero": 9, "grad": 10, "apply": 11}
 
 
 class EqsGrid(ctypes.Structure):
@@ -74,6 +77,11 @@ def load(path: str | None = None):
         L.eqsolve_strerror.restype = ctypes.c_char_p
         L.eqsolve_debug_layout.argtypes = [VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
         L.eqsolve_debug_layout.restype = ctypes.c_int
+        L.eqsolve_debug_profile.argtypes = [VP, ctypes.c_int32, ctypes.c_int32]
+        L.eqsolve_debug_profile.restype = ctypes.c_int
+        L.eqsolve_debug_kernel_stats.argtypes = [VP, ctypes.c_int32, ctypes.c_int32,
+                                                 ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]
+        L.eqsolve_debug_kernel_stats.restype = ctypes.c_int
         if path is None:
             _lib = L
         return L
@@ -144,3 +152,14 @@ def eqsolve_debug_layout(h, set_id):
     out = (ctypes.c_int32 * 6)()
     rc = load().eqsolve_debug_layout(h, int(set_id), out)
     return rc, list(out)
+
+
+def eqsolve_debug_profile(h, kind_mask, every=1):
+    return load().eqsolve_debug_profile(h, int(kind_mask), int(every))
+
+
+def eqsolve_debug_kernel_stats(h, kind, fp32):
+    cnt = ctypes.c_int64()
+    ms = ctypes.c_double()
+    rc = load().eqsolve_debug_kernel_stats(h, int(kind), int(bool(fp32)), ctypes.byref(cnt), ctypes.byref(ms))
+    return rc, int(cnt.value), float(ms.value)

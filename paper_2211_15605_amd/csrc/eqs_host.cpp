@@ -17,6 +17,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <math.h>
+#include <stdio.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -40,7 +41,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 struct SetHost {
     eqs_grid g;
     int n, plane;
-    int S, KC, NKC, ntiles;
+    int S, KC, NKC, ntiles, nflat;
     // workspace offsets resolved to pointers
     double *r, *rh, *p[2], *v[2], *t;
     float *a32[7];
@@ -57,6 +58,18 @@ int env_int(const char *name, int dflt) {
     if (!s || !*s) return dflt;
     return atoi(s);
 }
+
+double env_double(const char *name, double dflt) {
+    const char *s = getenv(name);
+    if (!s || !*s) return dflt;
+    return atof(s);
+}
+
+// Relative tolerance of each FP32 inner solve of the refinement.  FP32
+// BiCGSTAB stops gaining true (FP64) residual reduction after about two to
+// three decades on these systems, so solving each correction loosely and
+// taking a few more outer steps minimises the total inner iterations.
+double inner_tol() { return env_double("EQS_TOL_INNER", 3e-3); }
 
 }  // namespace
 
@@ -76,6 +89,18 @@ struct eqs_ctx {
     size_t ws_bytes = 0;
     bool broken = false;
     uint64_t launches = 0, readbacks = 0;
+    // optional per-launch event timing (diagnostics)
+    uint32_t profile_mask = 0;  // bit k: time launches of kernel kind k
+    int profile_every = 1;      // time every n-th launch of a timed kind
+    int64_t kseen[2 * 16] = {0};  // launches of each kind since profiling started
+    int kpos[2 * 16] = {0};       // launches of each kind since the last readback
+    std::vector<int> ev_pos;      // position of each timed launch since the last readback
+    bool trace = false;         // print the state at every readback (EQS_TRACE=1)
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<int> ev_kind;     // pending (start, stop) pairs: kind per pair
+    size_t ev_used = 0;
+    int64_t kcount[2 * 16] = {0};
+    double kms[2 * 16] = {0};
 };
 
 namespace {
@@ -99,7 +124,7 @@ bool grid_ok(const eqs_grid &g) {
 void choose_tiling(SetHost &s, int cpt) {
     const int Q = kBlock * cpt;
     s.S = (s.plane + Q - 1) / Q;
-    const int target = std::max(1, env_int("EQS_TILE_TARGET", 2048));
+    const int target = std::max(1, env_int("EQS_TILE_TARGET", 1024));
     int kc = env_int("EQS_KC", 0);
     if (kc <= 0) {
         const long long want = ((long long)s.S * s.g.nz + target - 1) / target;
@@ -108,6 +133,8 @@ void choose_tiling(SetHost &s, int cpt) {
     s.KC = std::min(kc, s.g.nz);
     s.NKC = (s.g.nz + s.KC - 1) / s.KC;
     s.ntiles = s.S * s.NKC;
+    const int fmax = std::min(std::max(1, env_int("EQS_FLAT_MAX", 1024)), kMaxFlatBlocks);
+    s.nflat = std::min((s.n + kFlatChunk - 1) / kFlatChunk, fmax);
 }
 
 void fill_desc(eqs_ctx *c, int s) {
@@ -122,6 +149,7 @@ void fill_desc(eqs_ctx *c, int s) {
     d.KC = h.KC;
     d.NKC = h.NKC;
     d.ntiles = h.ntiles;
+    d.nflat = h.nflat;
     d.r = h.r;
     d.rh = h.rh;
     d.p[0] = h.p[0];
@@ -143,18 +171,24 @@ void fill_desc(eqs_ctx *c, int s) {
     d.st = c->d_state + s;
 }
 
-LaunchSets launch_table(eqs_ctx *c, int first, int count, int *total) {
+LaunchSets launch_table(eqs_ctx *c, int first, int count, int *total, int *total_flat) {
     LaunchSets ls;
     memset(&ls, 0, sizeof(ls));
     ls.nsets = count;
-    int acc = 0;
+    int acc = 0, accf = 0;
     for (int i = 0; i < count; ++i) {
         ls.tile_begin[i] = acc;
+        ls.flat_begin[i] = accf;
         acc += c->sets[first + i].ntiles;
+        accf += c->sets[first + i].nflat;
     }
-    for (int i = count; i <= kMaxSets; ++i) ls.tile_begin[i] = acc;
+    for (int i = count; i <= kMaxSets; ++i) {
+        ls.tile_begin[i] = acc;
+        ls.flat_begin[i] = accf;
+    }
     ls.desc = c->d_desc + first;
     *total = acc;
+    *total_flat = accf;
     return ls;
 }
 
@@ -162,25 +196,75 @@ struct Run {
     eqs_ctx *c;
     int first, count;
     LaunchSets ls;
-    int ntiles;
+    int ntiles, nflat;
     int max_nx;
     bool fp32, trans;
     long guard_limit;
 
     int L(Kern k, const double *x = nullptr, double *y = nullptr, int arg = 0, bool f32 = false) {
         c->launches++;
-        if (launch_kernel(k, ls, ntiles, c->cpt, max_nx, f32, trans, c->stream, x, y, arg) != hipSuccess) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        const int kind = (int)k * 2 + (f32 ? 1 : 0);
+        const int pos = c->kpos[kind]++;
+        const bool timed = ((c->profile_mask >> (int)k) & 1u) && (c->kseen[kind]++ % c->profile_every == 0);
+        if (timed) {
+            while (c->ev_pool.size() < c->ev_used + 2) {
+                hipEvent_t e;
+                EQS_HIP(hipEventCreate(&e));
+                c->ev_pool.push_back(e);
+            }
+            e0 = c->ev_pool[c->ev_used];
+            e1 = c->ev_pool[c->ev_used + 1];
+            c->ev_used += 2;
+            c->ev_kind.push_back(kind);
+            c->ev_pos.push_back(pos);
+            EQS_HIP(hipEventRecord(e0, c->stream));
+        }
+        if (launch_kernel(k, ls, ntiles, nflat, c->cpt, max_nx, f32, trans, c->stream, x, y, arg) != hipSuccess) {
             (void)hipGetLastError();
             c->broken = true;
             return EQS_ERR_HIP;
         }
+        if (timed) EQS_HIP(hipEventRecord(e1, c->stream));
         return 0;
     }
     int readback() {
         c->readbacks++;
+        int before = 0;
+        for (int i = 0; i < count; ++i) before = std::max(before, (int)c->h_state[first + i].iters);
         EQS_HIP(hipMemcpyAsync(c->h_state + first, c->d_state + first, sizeof(SolveState) * count,
                                hipMemcpyDeviceToHost, c->stream));
         EQS_HIP(hipStreamSynchronize(c->stream));
+        if (c->trace) {
+            for (int i = 0; i < count; ++i) {
+                const SolveState &q = c->h_state[first + i];
+                fprintf(stderr, "eqsolve trace set %d: iters %d outer %d active %d done %d status %d |r| %.3e lim %.3e true %.3e\n",
+                        first + i, q.iters, q.outer, q.active, q.done, q.status, sqrt(q.rr), q.lim2, sqrt(q.rr_true));
+            }
+        }
+        if (c->profile_mask) {
+            // A set that stops iterating stays stopped until the host acts, so
+            // of the iteration launches since the last look, the first
+            // (iterations done) did work and the rest exited at once: only
+            // the former enter the per-kernel means.
+            int after = 0;
+            for (int i = 0; i < count; ++i) after = std::max(after, (int)c->h_state[first + i].iters);
+            const int worked = std::max(0, after - before);
+            for (size_t i = 0; i < c->ev_kind.size(); ++i) {
+                const int kind = c->ev_kind[i];
+                const int kk = kind / 2;
+                const bool iter_kernel = kk == K_K1 || kk == K_K2 || kk == K_K3;
+                if (iter_kernel && c->ev_pos[i] >= worked) continue;
+                float ms = 0.f;
+                EQS_HIP(hipEventElapsedTime(&ms, c->ev_pool[2 * i], c->ev_pool[2 * i + 1]));
+                c->kcount[kind]++;
+                c->kms[kind] += ms;
+            }
+            c->ev_kind.clear();
+            c->ev_pos.clear();
+            c->ev_used = 0;
+        }
+        for (int i = 0; i < 2 * 16; ++i) c->kpos[i] = 0;
         return 0;
     }
     const SolveState &st(int i) const { return c->h_state[first + i]; }
@@ -213,11 +297,13 @@ struct Run {
             if (h.last_iters >= 0 && s.iters > h.last_iters && lrr < h.last_log_rr) {
                 const double slope = (lrr - h.last_log_rr) / (double)(s.iters - h.last_iters);
                 const double rem = (lgoal - lrr) / slope;
-                want = (int)std::min(1e6, ceil(1.1 * std::max(0.0, rem))) + 2;
+                // BiCGSTAB residuals plateau and drop, so aim short of the
+                // prediction and never more than double the last chunk
+                want = (int)std::min(1e6, ceil(0.8 * std::max(0.0, rem))) + 1;
                 const int prev = std::max(8, s.iters - h.last_iters);
-                want = std::min(want, 4 * prev);
+                want = std::min(want, 2 * prev);
             } else {
-                want = h.last_iters < 0 ? 8 : std::max(8, 2 * (s.iters - std::max(0, h.last_iters)));
+                want = h.last_iters < 0 ? 8 : std::max(8, s.iters - std::max(0, h.last_iters));
             }
             h.last_iters = s.iters;
             h.last_log_rr = lrr;
@@ -293,7 +379,7 @@ Run make_run(eqs_ctx *c, int first, int count, bool trans) {
     R.c = c;
     R.first = first;
     R.count = count;
-    R.ls = launch_table(c, first, count, &R.ntiles);
+    R.ls = launch_table(c, first, count, &R.ntiles, &R.nflat);
     R.max_nx = 1;
     for (int i = 0; i < count; ++i) R.max_nx = std::max(R.max_nx, c->sets[first + i].g.nx);
     R.fp32 = false;
@@ -360,6 +446,7 @@ int eqsolve_create(eqs_ctx **out, const eqs_grid *grids, int32_t nsets, int32_t 
     eqs_ctx *c = new (std::nothrow) eqs_ctx();
     if (!c) return EQS_ERR_NOMEM;
     c->stream = (hipStream_t)hip_stream;
+    c->trace = env_int("EQS_TRACE", 0) != 0;
     c->nsets = nsets;
     c->precision = precision;
     if (hipGetDevice(&c->device) != hipSuccess) { delete c; return EQS_ERR_HIP; }
@@ -371,9 +458,10 @@ int eqsolve_create(eqs_ctx **out, const eqs_grid *grids, int32_t nsets, int32_t 
         max_plane = std::max(max_plane, (long long)grids[s].nx * grids[s].ny);
     }
     int cpt = env_int("EQS_CPT", 0);
-    if (cpt != 1 && cpt != 2 && cpt != 4) cpt = max_plane >= 4 * kBlock ? 2 : 1;
+    if (cpt != 1 && cpt != 2) cpt = max_plane >= 4 * kBlock ? 2 : 1;
     while (cpt > 1 && march_lds_bytes(cpt, max_nx, 8) > kMaxLds) cpt /= 2;
-    if (march_lds_bytes(cpt, max_nx, 8) > kMaxLds) { delete c; return EQS_ERR_ARG; }  // nx beyond the LDS plane
+    // nx beyond what one LDS plane buffer or the halo slots cover
+    if (march_lds_bytes(cpt, max_nx, 8) > kMaxLds || halo_slots(max_nx) < 0) { delete c; return EQS_ERR_ARG; }
     c->cpt = cpt;
     c->max_nx = max_nx;
 
@@ -391,7 +479,7 @@ int eqsolve_create(eqs_ctx **out, const eqs_grid *grids, int32_t nsets, int32_t 
         base[s] = bytes;
         bytes += 7 * align_up((size_t)h.n * 8);
         if (f32) bytes += 15 * align_up((size_t)h.n * 4);
-        bytes += align_up((size_t)h.ntiles * kMaxRed * 8);
+        bytes += align_up((size_t)std::max(h.ntiles, h.nflat) * kMaxRed * 8);
         bytes += kAlign;  // counter
     }
     c->ws_bytes = bytes;
@@ -429,7 +517,7 @@ int eqsolve_create(eqs_ctx **out, const eqs_grid *grids, int32_t nsets, int32_t 
             h.t32 = (float *)take((size_t)h.n * 4);
             h.d32 = (float *)take((size_t)h.n * 4);
         }
-        h.partials = (double *)take((size_t)h.ntiles * kMaxRed * 8);
+        h.partials = (double *)take((size_t)std::max(h.ntiles, h.nflat) * kMaxRed * 8);
         h.counter = (uint32_t *)take(kAlign);
         h.last_iters = -1;
         fill_desc(c, s);
@@ -451,6 +539,7 @@ int eqsolve_create(eqs_ctx **out, const eqs_grid *grids, int32_t nsets, int32_t 
 int eqsolve_destroy(eqs_ctx *c) {
     if (!c) return EQS_OK;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     if (c->ws) (void)hipFree(c->ws);
     if (c->d_desc) (void)hipFree(c->d_desc);
     if (c->d_state) (void)hipFree(c->d_state);
@@ -475,7 +564,7 @@ int eqsolve_solve(eqs_ctx *c, int32_t set, const double *const diag[7], const do
     for (int k = 0; k < 7; ++k) d.g[k] = nullptr;
     d.mode = set_mode_for(c->precision);
     d.tol = tol;
-    d.tol_inner = d.mode == MODE_FP32 ? tol : 1e-5;
+    d.tol_inner = d.mode == MODE_FP32 ? tol : inner_tol();
     d.maxit = maxit;
     int rc = upload_desc(c, set, 1);
     if (rc) return rc;
@@ -505,7 +594,7 @@ int eqsolve_solve_batched(eqs_ctx *c, const double *const *const *diag, const do
         for (int k = 0; k < 7; ++k) d.g[k] = nullptr;
         d.mode = set_mode_for(c->precision);
         d.tol = tol[s];
-        d.tol_inner = d.mode == MODE_FP32 ? tol[s] : 1e-5;
+        d.tol_inner = d.mode == MODE_FP32 ? tol[s] : inner_tol();
         d.maxit = maxit[s];
     }
     int rc = upload_desc(c, 0, c->nsets);
@@ -590,6 +679,27 @@ int eqsolve_debug_layout(const eqs_ctx *c, int32_t set, int32_t *out6) {
     out6[3] = h.NKC;
     out6[4] = h.ntiles;
     out6[5] = (int32_t)std::min<uint64_t>(c->readbacks, 0x7fffffff);
+    return EQS_OK;
+}
+
+int eqsolve_debug_profile(eqs_ctx *c, int32_t kind_mask, int32_t every) {
+    if (!c || c->broken) return EQS_ERR_STATE;
+    if (every < 1) return EQS_ERR_ARG;
+    c->profile_mask = (uint32_t)kind_mask;
+    c->profile_every = every;
+    for (int i = 0; i < 32; ++i) {
+        c->kcount[i] = 0;
+        c->kms[i] = 0.0;
+        c->kseen[i] = 0;
+    }
+    return EQS_OK;
+}
+
+int eqsolve_debug_kernel_stats(const eqs_ctx *c, int32_t kind, int32_t fp32, int64_t *count, double *total_ms) {
+    if (!c || kind < 0 || kind >= 16 || !count || !total_ms) return EQS_ERR_ARG;
+    const int i = kind * 2 + (fp32 ? 1 : 0);
+    *count = c->kcount[i];
+    *total_ms = c->kms[i];
     return EQS_OK;
 }
 

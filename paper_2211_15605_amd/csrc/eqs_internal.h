@@ -15,6 +15,9 @@ namespace eqs {
 constexpr int kBlock = 256;      // threads per block (4 wave64)
 constexpr int kMaxSets = 8;      // sets per launch table
 constexpr int kMaxRed = 4;       // reduction values per tile
+constexpr int kFlatU = 4;        // pointwise kernels: cells per thread per chunk
+constexpr int kFlatChunk = kBlock * kFlatU;
+constexpr int kMaxFlatBlocks = 4096;
 
 // per-set iteration mode
 enum : int32_t { MODE_FP64 = 0, MODE_REFINE = 1, MODE_FP32 = 2, MODE_ADJOINT = 3 };
@@ -58,7 +61,8 @@ struct SetDesc {
     int32_t nx, ny, nz, plane, n;
     // march tiling: S segments of Q = kBlock*cpt cells per plane, KC planes per chunk
     int32_t S, KC, NKC, ntiles;
-    // pointwise tiling (same tiles)
+    // pointwise kernels: nflat blocks, block b takes chunks b, b + nflat, ... of kFlatChunk cells
+    int32_t nflat;
     int32_t mode;
     double tol, tol_inner;
     int32_t maxit, pad;
@@ -75,15 +79,17 @@ struct SetDesc {
     const double *xf;
     double *g[7];
     // reductions
-    double *partials;   // [ntiles * kMaxRed]
+    double *partials;   // [max(ntiles, nflat) * kMaxRed]
     uint32_t *counter;  // last-block ticket
     SolveState *st;
 };
 
 // blocks of one launch -> (set, tile); set s owns logical tiles [tile_begin[s], tile_begin[s+1])
+// (pointwise kernels use flat_begin over the sets' nflat blocks instead)
 struct LaunchSets {
     int32_t nsets;
     int32_t tile_begin[kMaxSets + 1];
+    int32_t flat_begin[kMaxSets + 1];
     const SetDesc *desc;   // device table, nsets entries
 };
 

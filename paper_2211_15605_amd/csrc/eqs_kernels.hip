@@ -53,13 +53,26 @@ struct TileRef {
     int tile;
 };
 
+// block -> (set, tile) for march kernels (FLAT = false) or (set, block) for pointwise ones
+template <bool FLAT>
 __device__ __forceinline__ TileRef locate(const LaunchSets &ls) {
     const int L = xcd_remap((int)blockIdx.x, (int)gridDim.x);
     int s = 0;
 #pragma unroll
     for (int q = 1; q < kMaxSets; ++q)
-        if (q < ls.nsets && L >= ls.tile_begin[q]) s = q;
-    return TileRef{ls.desc + s, L - ls.tile_begin[s]};
+        if (q < ls.nsets && L >= (FLAT ? ls.flat_begin[q] : ls.tile_begin[q])) s = q;
+    return TileRef{ls.desc + s, L - (FLAT ? ls.flat_begin[s] : ls.tile_begin[s])};
+}
+
+// global-address-space accessors: pointers taken from the set table are
+// generic; these make every access a global (not flat) memory operation
+template <typename T>
+__device__ __forceinline__ T ld(const T *p, int i) {
+    return ((const __attribute__((address_space(1))) T *)p)[i];
+}
+template <typename T>
+__device__ __forceinline__ void st(T *p, int i, T v) {
+    ((__attribute__((address_space(1))) T *)p)[i] = v;
 }
 
 template <int NV>
@@ -83,37 +96,47 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *red) {
     }
 }
 
-// Tile partials -> last block sums them in tile order -> fin(state, sums).
+// Per-block partials -> the last of the set's `count` blocks sums them in
+// block order -> fin(state, sums).
+//
+// Visibility: the partials are written with agent-scope atomic stores, which
+// go through to the device's coherence point, and read back by the last
+// block with agent-scope atomic loads.  A block therefore only has to wait
+// until its partial stores are complete (vmcnt = 0) before taking its
+// ticket; an agent-scope release there would write back the XCD's whole L2,
+// once per block.  Nothing else written by the kernel is read by the last
+// block.
 template <int NV, class Fin>
-__device__ __forceinline__ void reduce_and_finalize(const SetDesc &d, int tile, double (&acc)[NV], Fin fin) {
+__device__ __forceinline__ void reduce_and_finalize(const SetDesc &d, int tile, int count, double (&acc)[NV],
+                                                    Fin fin) {
     __shared__ double red[4 * kMaxRed];
     __shared__ int last;
+    double *partials = d.partials;
+    uint32_t *counter = d.counter;
     block_sum<NV>(acc, red);
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int i = 0; i < NV; ++i)
-            __hip_atomic_store(d.partials + (size_t)tile * NV + i, acc[i], __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t prev =
-            __hip_atomic_fetch_add(d.counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        last = prev == (uint32_t)(d.ntiles - 1);
+            __hip_atomic_store(partials + (size_t)tile * NV + i, acc[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_s_waitcnt(0);  // all counters zero: the partial stores are complete
+        const uint32_t prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        last = prev == (uint32_t)(count - 1);
     }
     __syncthreads();
     if (!last) return;
     double s[NV];
 #pragma unroll
     for (int i = 0; i < NV; ++i) s[i] = 0.0;
-    for (int b = threadIdx.x; b < d.ntiles; b += kBlock) {
+    for (int b = threadIdx.x; b < count; b += kBlock) {
 #pragma unroll
         for (int i = 0; i < NV; ++i)
-            s[i] += __hip_atomic_load(d.partials + (size_t)b * NV + i, __ATOMIC_RELAXED,
-                                      __HIP_MEMORY_SCOPE_AGENT);
+            s[i] += __hip_atomic_load(partials + (size_t)b * NV + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
     block_sum<NV>(s, red);
     if (threadIdx.x == 0) {
         fin(d.st, s);
-        __hip_atomic_store(d.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -320,28 +343,37 @@ struct Nb {
 
 // coefficients paired with the neighbour values xE, xW, xN, xS, xT, xB of
 // row idx of A (TR = false) or of A^T (TR = true); zero where the neighbour
-// is outside the grid, so out-of-grid slots are never read.
+// is outside the grid, so out-of-grid slots never contribute.  The loads
+// are unconditional (indices clamped into the array) and masked afterwards,
+// so a block's loads issue together without control flow between them.
 template <typename T, bool TR>
 struct Coef6 {
     T e, w, n, s, t, b;
-    __device__ __forceinline__ void load(const T *const *a, int idx, int nx, int P, Nb nb, bool up, bool dn) {
+    __device__ __forceinline__ void load(const T *const *a, int idx, int nx, int P, int ncell, Nb nb, bool up,
+                                         bool dn) {
         if (!TR) {
-            e = nb.e ? a[1][idx] : T(0);
-            w = nb.w ? a[2][idx] : T(0);
-            n = nb.n ? a[3][idx] : T(0);
-            s = nb.s ? a[4][idx] : T(0);
-            t = up ? a[5][idx] : T(0);
-            b = dn ? a[6][idx] : T(0);
+            e = ld(a[1], idx);
+            w = ld(a[2], idx);
+            n = ld(a[3], idx);
+            s = ld(a[4], idx);
+            t = ld(a[5], idx);
+            b = ld(a[6], idx);
         } else {
             // column idx of A: idx is the west neighbour of idx+1 (a_W[idx+1]),
             // the east neighbour of idx-1 (a_E[idx-1]), and so on.
-            e = nb.e ? a[2][idx + 1] : T(0);
-            w = nb.w ? a[1][idx - 1] : T(0);
-            n = nb.n ? a[4][idx + nx] : T(0);
-            s = nb.s ? a[3][idx - nx] : T(0);
-            t = up ? a[6][idx + P] : T(0);
-            b = dn ? a[5][idx - P] : T(0);
+            e = ld(a[2], min(idx + 1, ncell - 1));
+            w = ld(a[1], max(idx - 1, 0));
+            n = ld(a[4], min(idx + nx, ncell - 1));
+            s = ld(a[3], max(idx - nx, 0));
+            t = ld(a[6], min(idx + P, ncell - 1));
+            b = ld(a[5], max(idx - P, 0));
         }
+        e = nb.e ? e : T(0);
+        w = nb.w ? w : T(0);
+        n = nb.n ? n : T(0);
+        s = nb.s ? s : T(0);
+        t = up ? t : T(0);
+        b = dn ? b : T(0);
     }
     __device__ __forceinline__ T apply(T ap, T xc, T xE, T xW, T xN, T xS, T xT, T xB) const {
         T acc = ap * xc;
@@ -356,35 +388,65 @@ struct Coef6 {
 };
 
 // ------------------------------------------------------------------ march skeleton
+//
+// Geometry and pointers are copied into registers at kernel entry: the set
+// table lives in global memory, and after the first store the compiler could
+// no longer keep table fields in registers (it cannot rule out aliasing), so
+// every reload would drain the loads in flight.
+struct Geo {
+    int nx, ny, nz, P, n, S, KC;
+};
+__device__ __forceinline__ Geo geo_of(const SetDesc &d) {
+    return Geo{d.nx, d.ny, d.nz, d.plane, d.n, d.S, d.KC};
+}
+//
+// A phase Ph supplies:
+//   Raw  load(idx)                 raw inputs of the stencil operand at a cell
+//   T    own(raw, idx, Aux&)       operand value of an own cell (+ its stores)
+//   T    halo(raw)                 operand value of any other cell (no stores)
+//   void pre(idx, nb, up, dn, Pre&)  loads for the centre pass of an own cell
+//   void center(idx, Pre, Aux, xc, xE..xB, acc)
+// Every step issues all of its loads (centre operands of plane k, raw inputs
+// of plane k+1 for the own cells and H halo slots per thread) before any
+// store, so they are in flight together.
 
-template <typename T, int CPT, class Ph>
-__device__ __forceinline__ void ext_plane(Ph &ph, const SetDesc &d, int k, T *buf, const int *qo,
+template <typename T, int CPT, int H, class Ph>
+__device__ __forceinline__ void ext_plane(Ph &ph, const Geo &d, int k, T *buf, const int *qo,
                                           const bool *ok, int q0, T *vown, typename Ph::Aux *ax) {
     constexpr int Q = kBlock * CPT;
-    const int nx = d.nx, P = d.plane;
+    const int nx = d.nx, P = d.P;
     const int kb = k * P;
+    typename Ph::Raw ro[CPT], rh[H];
+    int he[H];
+    bool hv[H];
+#pragma unroll
+    for (int m = 0; m < CPT; ++m) ro[m] = ph.load(min(qo[m], P - 1) + kb);
+#pragma unroll
+    for (int hh = 0; hh < H; ++hh) {
+        const int h = (int)threadIdx.x + kBlock * hh;
+        const int e = h < nx ? h : h + Q;
+        const int q = q0 - nx + e;
+        he[hh] = h < 2 * nx ? e : -1;
+        hv[hh] = h < 2 * nx && q >= 0 && q < P;
+        rh[hh] = ph.load(min(max(q, 0), P - 1) + kb);
+    }
 #pragma unroll
     for (int m = 0; m < CPT; ++m) {
         const int e = nx + (int)threadIdx.x + kBlock * m;
-        T v = T(0);
-        if (ok[m]) v = ph.ext_own(qo[m] + kb, ax[m]);
+        const T v = ok[m] ? ph.own(ro[m], qo[m] + kb, ax[m]) : T(0);
         buf[e] = v;
         vown[m] = v;
     }
-    for (int h = threadIdx.x; h < 2 * nx; h += kBlock) {
-        const int e = h < nx ? h : h + Q;
-        const int q = q0 - nx + e;
-        T v = T(0);
-        if (q >= 0 && q < P) v = ph.ext_halo(q + kb);
-        buf[e] = v;
-    }
+#pragma unroll
+    for (int hh = 0; hh < H; ++hh)
+        if (he[hh] >= 0) buf[he[hh]] = hv[hh] ? ph.halo(rh[hh]) : T(0);
 }
 
-template <typename T, int CPT, class Ph>
-__device__ __forceinline__ void march(Ph &ph, const SetDesc &d, int tile, T *lds, double (&acc)[Ph::NV]) {
+template <typename T, int CPT, int H, class Ph>
+__device__ __forceinline__ void march(Ph &ph, const Geo &d, int tile, T *lds, double (&acc)[Ph::NV]) {
     constexpr int Q = kBlock * CPT;
     const int tid = threadIdx.x;
-    const int nx = d.nx, ny = d.ny, nz = d.nz, P = d.plane;
+    const int nx = d.nx, ny = d.ny, nz = d.nz, P = d.P;
     const int seg = tile % d.S, chunk = tile / d.S;
     const int q0 = seg * Q;
     const int k0 = chunk * d.KC;
@@ -406,31 +468,29 @@ __device__ __forceinline__ void march(Ph &ph, const SetDesc &d, int tile, T *lds
     typename Ph::Aux axc[CPT], axp[CPT];
     typename Ph::Pre pre[CPT];
 
-    if (k0 > 0) {
+    {
+        typename Ph::Raw rb[CPT];
 #pragma unroll
-        for (int m = 0; m < CPT; ++m) vm[m] = ok[m] ? ph.value_only(qo[m] + (k0 - 1) * P) : T(0);
-    } else {
+        for (int m = 0; m < CPT; ++m) rb[m] = ph.load(min(qo[m], P - 1) + max(k0 - 1, 0) * P);
 #pragma unroll
-        for (int m = 0; m < CPT; ++m) vm[m] = T(0);
+        for (int m = 0; m < CPT; ++m) vm[m] = (k0 > 0 && ok[m]) ? ph.halo(rb[m]) : T(0);
     }
-    ext_plane<T, CPT>(ph, d, k0, lds, qo, ok, q0, vc, axc);
+    ext_plane<T, CPT, H>(ph, d, k0, lds, qo, ok, q0, vc, axc);
 
     int bc = 0;  // buffer of plane k
     for (int k = k0; k < k1; ++k) {
         const bool up = k + 1 < nz, dn = k > 0;
         const int bn = bc == 2 ? 0 : bc + 1;
-        // operands of the centre pass of plane k, issued before the barrier
 #pragma unroll
-        for (int m = 0; m < CPT; ++m)
-            if (ok[m]) ph.pre(qo[m] + k * P, nb[m], up, dn, pre[m]);
+        for (int m = 0; m < CPT; ++m) ph.pre(min(qo[m], P - 1) + k * P, nb[m], up, dn, pre[m]);
         if (up && k + 1 < k1) {
-            ext_plane<T, CPT>(ph, d, k + 1, lds + bn * L, qo, ok, q0, vp, axp);
-        } else if (up) {
-#pragma unroll
-            for (int m = 0; m < CPT; ++m) vp[m] = ok[m] ? ph.value_only(qo[m] + (k + 1) * P) : T(0);
+            ext_plane<T, CPT, H>(ph, d, k + 1, lds + bn * L, qo, ok, q0, vp, axp);
         } else {
+            typename Ph::Raw rb[CPT];
 #pragma unroll
-            for (int m = 0; m < CPT; ++m) vp[m] = T(0);
+            for (int m = 0; m < CPT; ++m) rb[m] = ph.load(min(qo[m], P - 1) + min(k + 1, nz - 1) * P);
+#pragma unroll
+            for (int m = 0; m < CPT; ++m) vp[m] = (up && ok[m]) ? ph.halo(rb[m]) : T(0);
         }
         __syncthreads();
         const T *bufc = lds + bc * L;
@@ -466,8 +526,8 @@ struct Vecs<double> {
     __device__ static const double *const *a(const SetDesc &d) { return d.a; }
     __device__ static double *r(const SetDesc &d) { return d.r; }
     __device__ static double *rh(const SetDesc &d) { return d.rh; }
-    __device__ static double *p(const SetDesc &d, int i) { return d.p[i]; }
-    __device__ static double *v(const SetDesc &d, int i) { return d.v[i]; }
+    __device__ static double *p(const SetDesc &d, int i) { return i ? d.p[1] : d.p[0]; }
+    __device__ static double *v(const SetDesc &d, int i) { return i ? d.v[1] : d.v[0]; }
     __device__ static double *t(const SetDesc &d) { return d.t; }
     __device__ static double *x(const SetDesc &d) { return d.x; }
 };
@@ -476,8 +536,8 @@ struct Vecs<float> {
     __device__ static const float *const *a(const SetDesc &d) { return (const float *const *)d.a32; }
     __device__ static float *r(const SetDesc &d) { return d.r32; }
     __device__ static float *rh(const SetDesc &d) { return d.rh32; }
-    __device__ static float *p(const SetDesc &d, int i) { return d.p32[i]; }
-    __device__ static float *v(const SetDesc &d, int i) { return d.v32[i]; }
+    __device__ static float *p(const SetDesc &d, int i) { return i ? d.p32[1] : d.p32[0]; }
+    __device__ static float *v(const SetDesc &d, int i) { return i ? d.v32[1] : d.v32[0]; }
     __device__ static float *t(const SetDesc &d) { return d.t32; }
     __device__ static float *x(const SetDesc &d) { return d.d32; }
 };
@@ -486,36 +546,42 @@ struct Vecs<float> {
 template <typename T, bool TR>
 struct PhK1 {
     static constexpr int NV = 1;
+    struct Raw { T r, p, v, ap; };
     struct Aux { T ap; };
     struct Pre { Coef6<T, TR> c; T rh; };
-    const T *const *a;
+    const T *a[7];
     const T *r, *rhd, *pold, *vold;
     T *pnew, *vnew, *rhw;
     T beta, omega;
-    int nx, P;
+    int nx, P, ncell;
     bool fresh;
-    __device__ __forceinline__ T pval(int idx, T rv) const {
-        return fresh ? rv : fma(beta, fma(-omega, vold[idx], pold[idx]), rv);
+    __device__ __forceinline__ Raw load(int idx) const {
+        Raw w;
+        w.r = ld(r, idx);
+        w.ap = ld(a[0], idx);
+        w.p = ld(pold, idx);
+        w.v = ld(vold, idx);
+        return w;
     }
-    __device__ __forceinline__ T ext_own(int idx, Aux &ax) {
-        const T rv = r[idx];
-        const T p = pval(idx, rv);
-        const T ap = a[0][idx];
-        pnew[idx] = p;
-        if (fresh) rhw[idx] = rv;
-        ax.ap = ap;
-        return p / ap;
+    __device__ __forceinline__ T pval(const Raw &w) const {
+        return fresh ? w.r : fma(beta, fma(-omega, w.v, w.p), w.r);
     }
-    __device__ __forceinline__ T ext_halo(int idx) const { return pval(idx, r[idx]) / a[0][idx]; }
-    __device__ __forceinline__ T value_only(int idx) const { return pval(idx, r[idx]) / a[0][idx]; }
+    __device__ __forceinline__ T own(const Raw &w, int idx, Aux &ax) {
+        const T p = pval(w);
+        st(pnew, idx, p);
+        if (fresh) st(rhw, idx, w.r);
+        ax.ap = w.ap;
+        return p / w.ap;
+    }
+    __device__ __forceinline__ T halo(const Raw &w) const { return pval(w) / w.ap; }
     __device__ __forceinline__ void pre(int idx, Nb nb, bool up, bool dn, Pre &pr) const {
-        pr.c.load(a, idx, nx, P, nb, up, dn);
-        pr.rh = rhd[idx];
+        pr.c.load(a, idx, nx, P, ncell, nb, up, dn);
+        pr.rh = ld(rhd, idx);
     }
     __device__ __forceinline__ void center(int idx, const Pre &pr, const Aux &ax, T xc, T xE, T xW, T xN,
                                            T xS, T xT, T xB, double (&acc)[NV]) {
         const T v = pr.c.apply(ax.ap, xc, xE, xW, xN, xS, xT, xB);
-        vnew[idx] = v;
+        st(vnew, idx, v);
         acc[0] += (double)pr.rh * (double)v;
     }
 };
@@ -524,29 +590,35 @@ struct PhK1 {
 template <typename T, bool TR>
 struct PhK2 {
     static constexpr int NV = 3;
+    struct Raw { T r, v, ap; };
     struct Aux { T ap, s; };
     struct Pre { Coef6<T, TR> c; };
-    const T *const *a;
+    const T *a[7];
     const T *r, *v;
     T *tout;
     T alpha;
-    int nx, P;
-    __device__ __forceinline__ T ext_own(int idx, Aux &ax) {
-        const T s = fma(-alpha, v[idx], r[idx]);
-        const T ap = a[0][idx];
-        ax.ap = ap;
-        ax.s = s;
-        return s / ap;
+    int nx, P, ncell;
+    __device__ __forceinline__ Raw load(int idx) const {
+        Raw w;
+        w.r = ld(r, idx);
+        w.v = ld(v, idx);
+        w.ap = ld(a[0], idx);
+        return w;
     }
-    __device__ __forceinline__ T ext_halo(int idx) const { return fma(-alpha, v[idx], r[idx]) / a[0][idx]; }
-    __device__ __forceinline__ T value_only(int idx) const { return fma(-alpha, v[idx], r[idx]) / a[0][idx]; }
+    __device__ __forceinline__ T own(const Raw &w, int, Aux &ax) {
+        const T s = fma(-alpha, w.v, w.r);
+        ax.ap = w.ap;
+        ax.s = s;
+        return s / w.ap;
+    }
+    __device__ __forceinline__ T halo(const Raw &w) const { return fma(-alpha, w.v, w.r) / w.ap; }
     __device__ __forceinline__ void pre(int idx, Nb nb, bool up, bool dn, Pre &pr) const {
-        pr.c.load(a, idx, nx, P, nb, up, dn);
+        pr.c.load(a, idx, nx, P, ncell, nb, up, dn);
     }
     __device__ __forceinline__ void center(int idx, const Pre &pr, const Aux &ax, T xc, T xE, T xW, T xN,
                                            T xS, T xT, T xB, double (&acc)[NV]) {
         const T t = pr.c.apply(ax.ap, xc, xE, xW, xN, xS, xT, xB);
-        tout[idx] = t;
+        st(tout, idx, t);
         const double td = (double)t, sd = (double)ax.s;
         acc[0] += td * sd;
         acc[1] += td * td;
@@ -554,32 +626,36 @@ struct PhK2 {
     }
 };
 
+// stencil operand = x itself (residual and product phases)
+struct RawX { double x; };
+
 // r = b - A x (FP64).  SETUP and RECHECK write r and r^ = r; REPORT only sums.
 template <bool TR>
 struct PhRes {
     static constexpr int NV = 3;
+    using Raw = RawX;
     struct Aux {};
     struct Pre { Coef6<double, TR> c; double ap, b; };
-    const double *const *a;
+    const double *a[7];
     const double *x, *b;
     double *r, *rh;
-    int nx, P;
+    int nx, P, ncell;
     bool write;
-    __device__ __forceinline__ double ext_own(int idx, Aux &) { return x[idx]; }
-    __device__ __forceinline__ double ext_halo(int idx) const { return x[idx]; }
-    __device__ __forceinline__ double value_only(int idx) const { return x[idx]; }
+    __device__ __forceinline__ Raw load(int idx) const { return Raw{ld(x, idx)}; }
+    __device__ __forceinline__ double own(const Raw &w, int, Aux &) { return w.x; }
+    __device__ __forceinline__ double halo(const Raw &w) const { return w.x; }
     __device__ __forceinline__ void pre(int idx, Nb nb, bool up, bool dn, Pre &pr) const {
-        pr.c.load(a, idx, nx, P, nb, up, dn);
-        pr.ap = a[0][idx];
-        pr.b = b[idx];
+        pr.c.load(a, idx, nx, P, ncell, nb, up, dn);
+        pr.ap = ld(a[0], idx);
+        pr.b = ld(b, idx);
     }
     __device__ __forceinline__ void center(int idx, const Pre &pr, const Aux &, double xc, double xE, double xW,
                                            double xN, double xS, double xT, double xB, double (&acc)[NV]) {
         const double ax = pr.c.apply(pr.ap, xc, xE, xW, xN, xS, xT, xB);
         const double rv = pr.b - ax;
         if (write) {
-            r[idx] = rv;
-            rh[idx] = rv;
+            st(r, idx, rv);
+            st(rh, idx, rv);
         }
         acc[0] += pr.b * pr.b;
         acc[1] += rv * rv;
@@ -590,28 +666,29 @@ struct PhRes {
 // refinement residual: r = b - A x in FP64, emitted as FP32 r * scale (also r^ and a zero inner iterate)
 struct PhOuter {
     static constexpr int NV = 2;
+    using Raw = RawX;
     struct Aux {};
     struct Pre { Coef6<double, false> c; double ap, b; };
-    const double *const *a;
+    const double *a[7];
     const double *x, *b;
     float *r32, *rh32, *d32;
     double scale;
-    int nx, P;
-    __device__ __forceinline__ double ext_own(int idx, Aux &) { return x[idx]; }
-    __device__ __forceinline__ double ext_halo(int idx) const { return x[idx]; }
-    __device__ __forceinline__ double value_only(int idx) const { return x[idx]; }
+    int nx, P, ncell;
+    __device__ __forceinline__ Raw load(int idx) const { return Raw{ld(x, idx)}; }
+    __device__ __forceinline__ double own(const Raw &w, int, Aux &) { return w.x; }
+    __device__ __forceinline__ double halo(const Raw &w) const { return w.x; }
     __device__ __forceinline__ void pre(int idx, Nb nb, bool up, bool dn, Pre &pr) const {
-        pr.c.load(a, idx, nx, P, nb, up, dn);
-        pr.ap = a[0][idx];
-        pr.b = b[idx];
+        pr.c.load(a, idx, nx, P, ncell, nb, up, dn);
+        pr.ap = ld(a[0], idx);
+        pr.b = ld(b, idx);
     }
     __device__ __forceinline__ void center(int idx, const Pre &pr, const Aux &, double xc, double xE, double xW,
                                            double xN, double xS, double xT, double xB, double (&acc)[NV]) {
         const double rv = pr.b - pr.c.apply(pr.ap, xc, xE, xW, xN, xS, xT, xB);
         const float f = (float)(rv * scale);
-        r32[idx] = f;
-        rh32[idx] = f;
-        d32[idx] = 0.0f;
+        st(r32, idx, f);
+        st(rh32, idx, f);
+        st(d32, idx, 0.0f);
         acc[0] += rv * rv;
         acc[1] += (double)f * (double)f;
     }
@@ -621,22 +698,23 @@ struct PhOuter {
 template <bool TR>
 struct PhApply {
     static constexpr int NV = 1;
+    using Raw = RawX;
     struct Aux {};
     struct Pre { Coef6<double, TR> c; double ap; };
-    const double *const *a;
+    const double *a[7];
     const double *x;
     double *y;
-    int nx, P;
-    __device__ __forceinline__ double ext_own(int idx, Aux &) { return x[idx]; }
-    __device__ __forceinline__ double ext_halo(int idx) const { return x[idx]; }
-    __device__ __forceinline__ double value_only(int idx) const { return x[idx]; }
+    int nx, P, ncell;
+    __device__ __forceinline__ Raw load(int idx) const { return Raw{ld(x, idx)}; }
+    __device__ __forceinline__ double own(const Raw &w, int, Aux &) { return w.x; }
+    __device__ __forceinline__ double halo(const Raw &w) const { return w.x; }
     __device__ __forceinline__ void pre(int idx, Nb nb, bool up, bool dn, Pre &pr) const {
-        pr.c.load(a, idx, nx, P, nb, up, dn);
-        pr.ap = a[0][idx];
+        pr.c.load(a, idx, nx, P, ncell, nb, up, dn);
+        pr.ap = ld(a[0], idx);
     }
     __device__ __forceinline__ void center(int idx, const Pre &pr, const Aux &, double xc, double xE, double xW,
                                            double xN, double xS, double xT, double xB, double (&)[NV]) {
-        y[idx] = pr.c.apply(pr.ap, xc, xE, xW, xN, xS, xT, xB);
+        st(y, idx, pr.c.apply(pr.ap, xc, xE, xW, xN, xS, xT, xB));
     }
 };
 
@@ -648,62 +726,64 @@ __device__ __forceinline__ T *lds_base() {
     return reinterpret_cast<T *>(eqs_smem);
 }
 
-template <typename T, int CPT, bool TR>
+template <typename T, int CPT, int H, bool TR>
 __global__ void __launch_bounds__(kBlock) k1_kernel(LaunchSets ls) {
-    const TileRef tr = locate(ls);
+    const TileRef tr = locate<false>(ls);
     const SetDesc &d = *tr.d;
-    const SolveState *st = d.st;
-    if (!st->active) return;
-    const int par = st->iters & 1;
+    const SolveState *st_ = d.st;
+    if (!st_->active) return;
+    const int par = st_->iters & 1;
     PhK1<T, TR> ph;
-    ph.a = Vecs<T>::a(d);
+    for (int k = 0; k < 7; ++k) ph.a[k] = Vecs<T>::a(d)[k];
     ph.r = Vecs<T>::r(d);
-    ph.fresh = st->fresh != 0;
+    ph.fresh = st_->fresh != 0;
     ph.rhd = ph.fresh ? Vecs<T>::r(d) : Vecs<T>::rh(d);
     ph.rhw = Vecs<T>::rh(d);
     ph.pold = Vecs<T>::p(d, par);
     ph.vold = Vecs<T>::v(d, par);
     ph.pnew = Vecs<T>::p(d, par ^ 1);
     ph.vnew = Vecs<T>::v(d, par ^ 1);
-    ph.beta = (T)((st->rho / st->rho_prev) * (st->alpha / st->omega));
-    ph.omega = (T)st->omega;
+    ph.beta = (T)((st_->rho / st_->rho_prev) * (st_->alpha / st_->omega));
+    ph.omega = (T)st_->omega;
     ph.nx = d.nx;
     ph.P = d.plane;
+    ph.ncell = d.n;
     double acc[1] = {0.0};
-    march<T, CPT>(ph, d, tr.tile, lds_base<T>(), acc);
-    reduce_and_finalize<1>(d, tr.tile, acc, FinK1{});
+    march<T, CPT, H>(ph, geo_of(d), tr.tile, lds_base<T>(), acc);
+    reduce_and_finalize<1>(d, tr.tile, d.ntiles, acc, FinK1{});
 }
 
-template <typename T, int CPT, bool TR>
+template <typename T, int CPT, int H, bool TR>
 __global__ void __launch_bounds__(kBlock) k2_kernel(LaunchSets ls) {
-    const TileRef tr = locate(ls);
+    const TileRef tr = locate<false>(ls);
     const SetDesc &d = *tr.d;
-    const SolveState *st = d.st;
-    if (!st->active) return;
-    const int par = st->iters & 1;
+    const SolveState *st_ = d.st;
+    if (!st_->active) return;
+    const int par = st_->iters & 1;
     PhK2<T, TR> ph;
-    ph.a = Vecs<T>::a(d);
+    for (int k = 0; k < 7; ++k) ph.a[k] = Vecs<T>::a(d)[k];
     ph.r = Vecs<T>::r(d);
     ph.v = Vecs<T>::v(d, par);
     ph.tout = Vecs<T>::t(d);
-    ph.alpha = (T)st->alpha;
+    ph.alpha = (T)st_->alpha;
     ph.nx = d.nx;
     ph.P = d.plane;
+    ph.ncell = d.n;
     double acc[3] = {0.0, 0.0, 0.0};
-    march<T, CPT>(ph, d, tr.tile, lds_base<T>(), acc);
-    reduce_and_finalize<3>(d, tr.tile, acc, FinK2{});
+    march<T, CPT, H>(ph, geo_of(d), tr.tile, lds_base<T>(), acc);
+    reduce_and_finalize<3>(d, tr.tile, d.ntiles, acc, FinK2{});
 }
 
 // mode: 0 setup, 1 recheck, 2 report
-template <int CPT, bool TR>
+template <int CPT, int H, bool TR>
 __global__ void __launch_bounds__(kBlock) res_kernel(LaunchSets ls, int mode) {
-    const TileRef tr = locate(ls);
+    const TileRef tr = locate<false>(ls);
     const SetDesc &d = *tr.d;
-    const SolveState *st = d.st;
-    if (mode == 1 && !st->converged) return;
-    if (mode == 2 && !st->need_report) return;
+    const SolveState *st_ = d.st;
+    if (mode == 1 && !st_->converged) return;
+    if (mode == 2 && !st_->need_report) return;
     PhRes<TR> ph;
-    ph.a = d.a;
+    for (int k = 0; k < 7; ++k) ph.a[k] = d.a[k];
     ph.x = d.x;
     ph.b = d.b;
     ph.r = d.r;
@@ -711,78 +791,69 @@ __global__ void __launch_bounds__(kBlock) res_kernel(LaunchSets ls, int mode) {
     ph.write = mode != 2;
     ph.nx = d.nx;
     ph.P = d.plane;
+    ph.ncell = d.n;
     double acc[3] = {0.0, 0.0, 0.0};
-    march<double, CPT>(ph, d, tr.tile, lds_base<double>(), acc);
+    march<double, CPT, H>(ph, geo_of(d), tr.tile, lds_base<double>(), acc);
     if (mode == 0)
-        reduce_and_finalize<3>(d, tr.tile, acc, FinSetup{&d});
+        reduce_and_finalize<3>(d, tr.tile, d.ntiles, acc, FinSetup{&d});
     else if (mode == 1)
-        reduce_and_finalize<3>(d, tr.tile, acc, FinRecheck{});
+        reduce_and_finalize<3>(d, tr.tile, d.ntiles, acc, FinRecheck{});
     else
-        reduce_and_finalize<3>(d, tr.tile, acc, FinReport{});
+        reduce_and_finalize<3>(d, tr.tile, d.ntiles, acc, FinReport{});
 }
 
-template <int CPT>
+template <int CPT, int H>
 __global__ void __launch_bounds__(kBlock) outer_kernel(LaunchSets ls) {
-    const TileRef tr = locate(ls);
+    const TileRef tr = locate<false>(ls);
     const SetDesc &d = *tr.d;
-    const SolveState *st = d.st;
-    if (st->done || !(st->outer_pending || st->inner_done)) return;
+    const SolveState *st_ = d.st;
+    if (st_->done || !(st_->outer_pending || st_->inner_done)) return;
     PhOuter ph;
-    ph.a = d.a;
+    for (int k = 0; k < 7; ++k) ph.a[k] = d.a[k];
     ph.x = d.x;
     ph.b = d.b;
     ph.r32 = d.r32;
     ph.rh32 = d.rh32;
     ph.d32 = d.d32;
-    ph.scale = st->scale;
+    ph.scale = st_->scale;
     ph.nx = d.nx;
     ph.P = d.plane;
+    ph.ncell = d.n;
     double acc[2] = {0.0, 0.0};
-    march<double, CPT>(ph, d, tr.tile, lds_base<double>(), acc);
-    reduce_and_finalize<2>(d, tr.tile, acc, FinOuter{&d});
+    march<double, CPT, H>(ph, geo_of(d), tr.tile, lds_base<double>(), acc);
+    reduce_and_finalize<2>(d, tr.tile, d.ntiles, acc, FinOuter{&d});
 }
 
-template <int CPT, bool TR>
+template <int CPT, int H, bool TR>
 __global__ void __launch_bounds__(kBlock) apply_kernel(LaunchSets ls, const double *x, double *y) {
-    const TileRef tr = locate(ls);
+    const TileRef tr = locate<false>(ls);
     const SetDesc &d = *tr.d;
     PhApply<TR> ph;
-    ph.a = d.a;
+    for (int k = 0; k < 7; ++k) ph.a[k] = d.a[k];
     ph.x = x;
     ph.y = y;
     ph.nx = d.nx;
     ph.P = d.plane;
+    ph.ncell = d.n;
     double acc[1] = {0.0};
-    march<double, CPT>(ph, d, tr.tile, lds_base<double>(), acc);
+    march<double, CPT, H>(ph, geo_of(d), tr.tile, lds_base<double>(), acc);
 }
 
-// ------------------------------------------------------------------ pointwise kernels (same tiles)
+// ------------------------------------------------------------------ pointwise kernels
+//
+// Block b of a set takes chunks b, b + nflat, ... of kFlatChunk cells; each
+// thread loads all kFlatU cells of a chunk (strided by the block size) before
+// computing and storing.
 
-// visits the tile's own cells: for each plane of the chunk, the segment's cells
-template <int CPT, class F>
-__device__ __forceinline__ void for_tile_cells(const SetDesc &d, int tile, F f) {
-    constexpr int Q = kBlock * CPT;
-    const int seg = tile % d.S, chunk = tile / d.S;
-    const int q0 = seg * Q;
-    const int k0 = chunk * d.KC;
-    const int k1 = min(k0 + d.KC, d.nz);
-    for (int k = k0; k < k1; ++k) {
-#pragma unroll
-        for (int m = 0; m < CPT; ++m) {
-            const int q = q0 + (int)threadIdx.x + kBlock * m;
-            if (q < d.plane) f(q + k * d.plane, q, k);
-        }
-    }
-}
 
 // K3: x += alpha p^ + omega s^; r = s - omega t; (r^, r), (r, r)
-template <typename T, int CPT>
+template <typename T>
 __global__ void __launch_bounds__(kBlock) k3_kernel(LaunchSets ls) {
-    const TileRef tr = locate(ls);
+    const TileRef tr = locate<true>(ls);
     const SetDesc &d = *tr.d;
-    const SolveState *st = d.st;
-    if (!st->active) return;
-    const int par = st->iters & 1;
+    const SolveState *st_ = d.st;
+    if (!st_->active) return;
+    const int par = st_->iters & 1;
     const T *a0 = Vecs<T>::a(d)[0];
     const T *p = Vecs<T>::p(d, par);
     const T *v = Vecs<T>::v(d, par);
@@ -790,75 +861,150 @@ __global__ void __launch_bounds__(kBlock) k3_kernel(LaunchSets ls) {
     const T *rh = Vecs<T>::rh(d);
     T *r = Vecs<T>::r(d);
     T *x = Vecs<T>::x(d);
-    const T alpha = (T)st->alpha, omega = (T)st->omega;
+    const T alpha = (T)st_->alpha, omega = (T)st_->omega;
+    const int n = d.n, nflat = d.nflat;
     double acc[2] = {0.0, 0.0};
-    for_tile_cells<CPT>(d, tr.tile, [&](int idx, int, int) {
-        const T ap = a0[idx];
-        const T s = fma(-alpha, v[idx], r[idx]);
-        const T ph = p[idx] / ap, sh = s / ap;
-        x[idx] = x[idx] + fma(alpha, ph, omega * sh);
-        const T rn = fma(-omega, t[idx], s);
-        r[idx] = rn;
-        acc[0] += (double)rh[idx] * (double)rn;
-        acc[1] += (double)rn * (double)rn;
-    });
-    reduce_and_finalize<2>(d, tr.tile, acc, FinK3{});
+    for (int ch = tr.tile; ch * kFlatChunk < n; ch += nflat) {
+        const int base = ch * kFlatChunk + (int)threadIdx.x;
+        T A[kFlatU], Pv[kFlatU], V[kFlatU], R[kFlatU], Tt[kFlatU], X[kFlatU], RH[kFlatU];
+#pragma unroll
+        for (int u = 0; u < kFlatU; ++u) {
+            const int i = min(base + kBlock * u, n - 1);
+            A[u] = ld(a0, i); Pv[u] = ld(p, i); V[u] = ld(v, i); R[u] = ld(r, i);
+            Tt[u] = ld(t, i); X[u] = ld(x, i); RH[u] = ld(rh, i);
+        }
+#pragma unroll
+        for (int u = 0; u < kFlatU; ++u) {
+            const int i = base + kBlock * u;
+            if (i < n) {
+                const T s = fma(-alpha, V[u], R[u]);
+                const T ph = Pv[u] / A[u], sh = s / A[u];
+                st(x, i, X[u] + fma(alpha, ph, omega * sh));
+                const T rn = fma(-omega, Tt[u], s);
+                st(r, i, rn);
+                acc[0] += (double)RH[u] * (double)rn;
+                acc[1] += (double)rn * (double)rn;
+            }
+        }
+    }
+    reduce_and_finalize<2>(d, tr.tile, nflat, acc, FinK3{});
 }
 
 // FP64 -> FP32 coefficient copies (round to nearest even), (b, b), a_P check
-template <int CPT>
 __global__ void __launch_bounds__(kBlock) cast_kernel(LaunchSets ls) {
-    const TileRef tr = locate(ls);
+    const TileRef tr = locate<true>(ls);
     const SetDesc &d = *tr.d;
+    const int n = d.n, nflat = d.nflat;
+    const double *a64[7];
+    float *a32[7];
+    for (int s = 0; s < 7; ++s) {
+        a64[s] = d.a[s];
+        a32[s] = d.a32[s];
+    }
+    const double *bvec = d.b;
     double acc[2] = {0.0, 0.0};
-    for_tile_cells<CPT>(d, tr.tile, [&](int idx, int, int) {
+    for (int ch = tr.tile; ch * kFlatChunk < n; ch += nflat) {
+        const int base = ch * kFlatChunk + (int)threadIdx.x;
+        double A[7][kFlatU], B[kFlatU];
 #pragma unroll
-        for (int s = 0; s < 7; ++s) d.a32[s][idx] = (float)d.a[s][idx];
-        const double ap = d.a[0][idx], bv = d.b[idx];
-        acc[0] += bv * bv;
-        acc[1] += (ap == 0.0 || !isfinite(ap) || (float)ap == 0.0f) ? 1.0 : 0.0;
-    });
-    reduce_and_finalize<2>(d, tr.tile, acc, FinCast{&d});
+        for (int u = 0; u < kFlatU; ++u) {
+            const int i = min(base + kBlock * u, n - 1);
+#pragma unroll
+            for (int s = 0; s < 7; ++s) A[s][u] = ld(a64[s], i);
+            B[u] = ld(bvec, i);
+        }
+#pragma unroll
+        for (int u = 0; u < kFlatU; ++u) {
+            const int i = base + kBlock * u;
+            if (i < n) {
+#pragma unroll
+                for (int s = 0; s < 7; ++s) st(a32[s], i, (float)A[s][u]);
+                acc[0] += B[u] * B[u];
+                acc[1] += (A[0][u] == 0.0 || !isfinite(A[0][u]) || (float)A[0][u] == 0.0f) ? 1.0 : 0.0;
+            }
+        }
+    }
+    reduce_and_finalize<2>(d, tr.tile, nflat, acc, FinCast{&d});
 }
 
 // x += d32 / scale (FP64), for sets whose inner solve has finished
-template <int CPT>
 __global__ void __launch_bounds__(kBlock) update_kernel(LaunchSets ls) {
-    const TileRef tr = locate(ls);
+    const TileRef tr = locate<true>(ls);
     const SetDesc &d = *tr.d;
-    const SolveState *st = d.st;
-    if (st->done || !st->inner_done) return;
-    const double is = st->upd_inv_scale;
-    for_tile_cells<CPT>(d, tr.tile, [&](int idx, int, int) { d.x[idx] = fma(is, (double)d.d32[idx], d.x[idx]); });
+    const SolveState *st_ = d.st;
+    if (st_->done || !st_->inner_done) return;
+    const double is = st_->upd_inv_scale;
+    const int n = d.n, nflat = d.nflat;
+    double *xv = d.x;
+    const float *dv = d.d32;
+    for (int ch = tr.tile; ch * kFlatChunk < n; ch += nflat) {
+        const int base = ch * kFlatChunk + (int)threadIdx.x;
+        double X[kFlatU];
+        float D[kFlatU];
+#pragma unroll
+        for (int u = 0; u < kFlatU; ++u) {
+            const int i = min(base + kBlock * u, n - 1);
+            X[u] = ld(xv, i);
+            D[u] = ld(dv, i);
+        }
+#pragma unroll
+        for (int u = 0; u < kFlatU; ++u) {
+            const int i = base + kBlock * u;
+            if (i < n) st(xv, i, fma(is, (double)D[u], X[u]));
+        }
+    }
 }
 
 // x = 0 where b = 0 (flagged by setup), or unconditionally (force)
-template <int CPT>
 __global__ void __launch_bounds__(kBlock) zero_kernel(LaunchSets ls, int force) {
-    const TileRef tr = locate(ls);
+    const TileRef tr = locate<true>(ls);
     const SetDesc &d = *tr.d;
     if (!force && !d.st->zero_rhs) return;
-    for_tile_cells<CPT>(d, tr.tile, [&](int idx, int, int) { d.x[idx] = 0.0; });
+    const int n = d.n, nflat = d.nflat;
+    double *xv = d.x;
+    for (int ch = tr.tile; ch * kFlatChunk < n; ch += nflat) {
+        const int base = ch * kFlatChunk + (int)threadIdx.x;
+#pragma unroll
+        for (int u = 0; u < kFlatU; ++u) {
+            const int i = base + kBlock * u;
+            if (i < n) st(xv, i, 0.0);
+        }
+    }
 }
 
 // adjoint gradients: g_P = -lambda x; g_nb = lambda x_nb (0 out of the grid)
-template <int CPT>
 __global__ void __launch_bounds__(kBlock) grad_kernel(LaunchSets ls) {
-    const TileRef tr = locate(ls);
+    const TileRef tr = locate<true>(ls);
     const SetDesc &d = *tr.d;
     const double *lam = d.x, *xf = d.xf;
-    const int nx = d.nx, ny = d.ny, nz = d.nz, P = d.plane;
-    for_tile_cells<CPT>(d, tr.tile, [&](int idx, int q, int k) {
-        const int j = q / nx, i = q - j * nx;
-        const double l = lam[idx];
-        if (d.g[0]) d.g[0][idx] = -l * xf[idx];
-        if (d.g[1]) d.g[1][idx] = i + 1 < nx ? l * xf[idx + 1] : 0.0;
-        if (d.g[2]) d.g[2][idx] = i > 0 ? l * xf[idx - 1] : 0.0;
-        if (d.g[3]) d.g[3][idx] = j + 1 < ny ? l * xf[idx + nx] : 0.0;
-        if (d.g[4]) d.g[4][idx] = j > 0 ? l * xf[idx - nx] : 0.0;
-        if (d.g[5]) d.g[5][idx] = k + 1 < nz ? l * xf[idx + P] : 0.0;
-        if (d.g[6]) d.g[6][idx] = k > 0 ? l * xf[idx - P] : 0.0;
-    });
+    const int nx = d.nx, ny = d.ny, nz = d.nz, P = d.plane, n = d.n, nflat = d.nflat;
+    double *g[7];
+    for (int s = 0; s < 7; ++s) g[s] = d.g[s];
+    for (int ch = tr.tile; ch * kFlatChunk < n; ch += nflat) {
+        const int base = ch * kFlatChunk + (int)threadIdx.x;
+#pragma unroll
+        for (int u = 0; u < kFlatU; ++u) {
+            const int idx = base + kBlock * u;
+            if (idx < n) {
+                const int k = idx / P, q = idx - k * P, j = q / nx, i = q - j * nx;
+                const double l = ld(lam, idx);
+                const double xc = ld(xf, idx);
+                const double xE = i + 1 < nx ? ld(xf, idx + 1) : 0.0;
+                const double xW = i > 0 ? ld(xf, idx - 1) : 0.0;
+                const double xN = j + 1 < ny ? ld(xf, idx + nx) : 0.0;
+                const double xS = j > 0 ? ld(xf, idx - nx) : 0.0;
+                const double xT = k + 1 < nz ? ld(xf, idx + P) : 0.0;
+                const double xB = k > 0 ? ld(xf, idx - P) : 0.0;
+                if (g[0]) st(g[0], idx, -l * xc);
+                if (g[1]) st(g[1], idx, l * xE);
+                if (g[2]) st(g[2], idx, l * xW);
+                if (g[3]) st(g[3], idx, l * xN);
+                if (g[4]) st(g[4], idx, l * xS);
+                if (g[5]) st(g[5], idx, l * xT);
+                if (g[6]) st(g[6], idx, l * xB);
+            }
+        }
+    }
 }
 
 // ------------------------------------------------------------------ host launchers
@@ -867,66 +1013,75 @@ size_t march_lds_bytes(int cpt, int max_nx, int elem) {
     return (size_t)3 * (size_t)(kBlock * cpt + 2 * max_nx) * (size_t)elem;
 }
 
-#define EQS_DISPATCH_CPT(cpt, BODY)                                   \
-    do {                                                              \
-        if ((cpt) == 1) { constexpr int C = 1; BODY; }                \
-        else if ((cpt) == 2) { constexpr int C = 2; BODY; }           \
-        else { constexpr int C = 4; BODY; }                           \
+int halo_slots(int max_nx) {
+    const int need = (2 * max_nx + kBlock - 1) / kBlock;
+    return need <= 1 ? 1 : need <= 2 ? 2 : need <= 4 ? 4 : need <= 8 ? 8 : -1;
+}
+
+#define EQS_DISPATCH(cpt, h, BODY)                                                   \
+    do {                                                                             \
+        if ((cpt) == 1) {                                                            \
+            constexpr int C = 1;                                                     \
+            if ((h) == 1) { constexpr int HH = 1; BODY; }                            \
+            else if ((h) == 2) { constexpr int HH = 2; BODY; }                       \
+            else if ((h) == 4) { constexpr int HH = 4; BODY; }                       \
+            else { constexpr int HH = 8; BODY; }                                     \
+        } else {                                                                     \
+            constexpr int C = 2;                                                     \
+            if ((h) == 1) { constexpr int HH = 1; BODY; }                            \
+            else if ((h) == 2) { constexpr int HH = 2; BODY; }                       \
+            else if ((h) == 4) { constexpr int HH = 4; BODY; }                       \
+            else { constexpr int HH = 8; BODY; }                                     \
+        }                                                                            \
     } while (0)
 
-hipError_t launch_kernel(Kern k, const LaunchSets &ls, int ntiles, int cpt, int max_nx, bool fp32, bool trans,
-                         hipStream_t stream, const double *x, double *y, int arg) {
-    const dim3 grid(ntiles), block(kBlock);
+hipError_t launch_kernel(Kern k, const LaunchSets &ls, int ntiles, int nflat, int cpt, int max_nx, bool fp32,
+                         bool trans, hipStream_t stream, const double *x, double *y, int arg) {
+    const dim3 grid(ntiles), fgrid(nflat), block(kBlock);
+    const int h = halo_slots(max_nx);
+    if (h < 0 || (cpt != 1 && cpt != 2)) return hipErrorInvalidValue;
     const size_t lds64 = march_lds_bytes(cpt, max_nx, 8), lds32 = march_lds_bytes(cpt, max_nx, 4);
     switch (k) {
     case K_K1:
-        if (fp32) {
-            if (trans) EQS_DISPATCH_CPT(cpt, hipLaunchKernelGGL((k1_kernel<float, C, true>), grid, block, lds32, stream, ls));
-            else EQS_DISPATCH_CPT(cpt, hipLaunchKernelGGL((k1_kernel<float, C, false>), grid, block, lds32, stream, ls));
-        } else {
-            if (trans) EQS_DISPATCH_CPT(cpt, hipLaunchKernelGGL((k1_kernel<double, C, true>), grid, block, lds64, stream, ls));
-            else EQS_DISPATCH_CPT(cpt, hipLaunchKernelGGL((k1_kernel<double, C, false>), grid, block, lds64, stream, ls));
-        }
+        if (fp32) EQS_DISPATCH(cpt, h, hipLaunchKernelGGL((k1_kernel<float, C, HH, false>), grid, block, lds32, stream, ls));
+        else if (trans) EQS_DISPATCH(cpt, h, hipLaunchKernelGGL((k1_kernel<double, C, HH, true>), grid, block, lds64, stream, ls));
+        else EQS_DISPATCH(cpt, h, hipLaunchKernelGGL((k1_kernel<double, C, HH, false>), grid, block, lds64, stream, ls));
         break;
     case K_K2:
-        if (fp32) {
-            if (trans) EQS_DISPATCH_CPT(cpt, hipLaunchKernelGGL((k2_kernel<float, C, true>), grid, block, lds32, stream, ls));
-            else EQS_DISPATCH_CPT(cpt, hipLaunchKernelGGL((k2_kernel<float, C, false>), grid, block, lds32, stream, ls));
-        } else {
-            if (trans) EQS_DISPATCH_CPT(cpt, hipLaunchKernelGGL((k2_kernel<double, C, true>), grid, block, lds64, stream, ls));
-            else EQS_DISPATCH_CPT(cpt, hipLaunchKernelGGL((k2_kernel<double, C, false>), grid, block, lds64, stream, ls));
-        }
+        if (fp32) EQS_DISPATCH(cpt, h, hipLaunchKernelGGL((k2_kernel<float, C, HH, false>), grid, block, lds32, stream, ls));
+        else if (trans) EQS_DISPATCH(cpt, h, hipLaunchKernelGGL((k2_kernel<double, C, HH, true>), grid, block, lds64, stream, ls));
+        else EQS_DISPATCH(cpt, h, hipLaunchKernelGGL((k2_kernel<double, C, HH, false>), grid, block, lds64, stream, ls));
         break;
     case K_K3:
-        if (fp32) EQS_DISPATCH_CPT(cpt, hipLaunchKernelGGL((k3_kernel<float, C>), grid, block, 0, stream, ls));
-        else EQS_DISPATCH_CPT(cpt, hipLaunchKernelGGL((k3_kernel<double, C>), grid, block, 0, stream, ls));
+        if (fp32) hipLaunchKernelGGL((k3_kernel<float>), fgrid, block, 0, stream, ls);
+        else hipLaunchKernelGGL((k3_kernel<double>), fgrid, block, 0, stream, ls);
         break;
     case K_SETUP:
     case K_RECHECK:
     case K_REPORT: {
         const int mode = k == K_SETUP ? 0 : (k == K_RECHECK ? 1 : 2);
-        if (trans) EQS_DISPATCH_CPT(cpt, hipLaunchKernelGGL((res_kernel<C, true>), grid, block, lds64, stream, ls, mode));
-        else EQS_DISPATCH_CPT(cpt, hipLaunchKernelGGL((res_kernel<C, false>), grid, block, lds64, stream, ls, mode));
+        if (trans) EQS_DISPATCH(cpt, h, hipLaunchKernelGGL((res_kernel<C, HH, true>), grid, block, lds64, stream, ls, mode));
+        else EQS_DISPATCH(cpt, h, hipLaunchKernelGGL((res_kernel<C, HH, false>), grid, block, lds64, stream, ls, mode));
         break;
     }
     case K_OUTER:
-        EQS_DISPATCH_CPT(cpt, hipLaunchKernelGGL((outer_kernel<C>), grid, block, lds64, stream, ls));
+        EQS_DISPATCH(cpt, h, hipLaunchKernelGGL((outer_kernel<C, HH>), grid, block, lds64, stream, ls));
         break;
     case K_CAST:
-        EQS_DISPATCH_CPT(cpt, hipLaunchKernelGGL((cast_kernel<C>), grid, block, 0, stream, ls));
+        hipLaunchKernelGGL(cast_kernel, fgrid, block, 0, stream, ls);
         break;
     case K_UPDATE:
-        EQS_DISPATCH_CPT(cpt, hipLaunchKernelGGL((update_kernel<C>), grid, block, 0, stream, ls));
+        hipLaunchKernelGGL(update_kernel, fgrid, block, 0, stream, ls);
         break;
     case K_ZERO:
-        EQS_DISPATCH_CPT(cpt, hipLaunchKernelGGL((zero_kernel<C>), grid, block, 0, stream, ls, arg));
+        hipLaunchKernelGGL(zero_kernel, fgrid, block, 0, stream, ls, arg);
         break;
     case K_GRAD:
-        EQS_DISPATCH_CPT(cpt, hipLaunchKernelGGL((grad_kernel<C>), grid, block, 0, stream, ls));
+        hipLaunchKernelGGL(grad_kernel, fgrid, block, 0, stream, ls);
         break;
     case K_APPLY:
-        if (trans) EQS_DISPATCH_CPT(cpt, hipLaunchKernelGGL((apply_kernel<C, true>), grid, block, lds64, stream, ls, x, y));
-        else EQS_DISPATCH_CPT(cpt, hipLaunchKernelGGL((apply_kernel<C, false>), grid, block, lds64, stream, ls, x, y));
+        if (trans) EQS_DISPATCH(cpt, h, hipLaunchKernelGGL((apply_kernel<C, HH, true>), grid, block, lds64, stream, ls, x, y));
+        else EQS_DISPATCH(cpt, h, hipLaunchKernelGGL((apply_kernel<C, HH, false>), grid, block, lds64, stream, ls, x, y));
         break;
     }
     return hipGetLastError();

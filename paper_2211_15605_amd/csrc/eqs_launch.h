@@ -26,8 +26,12 @@ enum Kern {
 // LDS bytes of a march kernel (three plane buffers of Q + 2 nx values)
 size_t march_lds_bytes(int cpt, int max_nx, int elem);
 
-// Launch kernel k over ntiles blocks (the sum of the sets' tile counts).
-hipError_t launch_kernel(Kern k, const LaunchSets &ls, int ntiles, int cpt, int max_nx, bool fp32, bool trans,
-                         hipStream_t stream, const double *x, double *y, int arg);
+// halo cells per thread per plane (1, 2, 4 or 8), or -1 if nx is too wide
+int halo_slots(int max_nx);
+
+// Launch kernel k: march kernels over ntiles blocks (the sum of the sets'
+// tile counts), pointwise kernels over nflat blocks (the sum of their nflat).
+hipError_t launch_kernel(Kern k, const LaunchSets &ls, int ntiles, int nflat, int cpt, int max_nx, bool fp32,
+                         bool trans, hipStream_t stream, const double *x, double *y, int arg);
 
 }  // namespace eqs

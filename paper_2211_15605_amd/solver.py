@@ -93,6 +93,24 @@ class Context:
         keys = ("cpt", "segments", "kc", "chunks", "tiles", "readbacks")
         return dict(zip(keys, v))
 
+    def profile(self, kinds=("k1",), every=1):
+        """Time every `every`-th launch of the given kernel kinds with HIP events on this
+        context's stream (resets the totals); an empty list turns timing off."""
+        mask = 0
+        for k in kinds:
+            mask |= 1 << (B.KERNEL_KINDS[k] if isinstance(k, str) else int(k))
+        rc = B.eqsolve_debug_profile(self.h, mask, every)
+        if rc != 0:
+            raise EqSolveError(rc, "eqsolve_debug_profile")
+
+    def kernel_stats(self, kind, fp32=False):
+        """(launches, total ms) recorded for a kernel kind (see binding.KERNEL_KINDS)."""
+        k = B.KERNEL_KINDS[kind] if isinstance(kind, str) else int(kind)
+        rc, cnt, ms = B.eqsolve_debug_kernel_stats(self.h, k, fp32)
+        if rc != 0:
+            raise EqSolveError(rc, "eqsolve_debug_kernel_stats")
+        return cnt, ms
+
     def solve(self, diags, b, x=None, tol=1e-10, maxit=1000, set_id=0, check=True):
         n = self.n(set_id)
         dp = self._diag_ptrs(diags, n)
