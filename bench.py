@@ -28,8 +28,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "BiCGSTAB cell-iters/s & %HBM roofline; time to 1e-10 rel residual vs FP64"
 HBM_PEAK_GBS = 8000.0
-# algorithmic HBM words per cell per launch of each kernel (reads + writes)
-WORDS = {"k1": 13, "k2": 10, "k3": 9, "setup": 10, "recheck": 11, "report": 9}
+# algorithmic HBM words per cell per launch of each iteration kernel (reads + writes) on the
+# column-scaled operator: K1 r, p, v, 6 coefficients, r^ / p, v; K2 r, v, 6 coefficients / t;
+# K3 y, p, r, v, t, r^ / y, r  (29 words per iteration)
+WORDS = {"k1": 12, "k2": 9, "k3": 8}
 
 
 def kernel_source_digest():
@@ -69,6 +71,10 @@ def gpu_leg(args):
     del s
     c64 = Context([g.shape], precision="fp64")
     c32 = Context([g.shape], precision="fp32_refine")
+    if not args.no_tune:
+        # launch shapes by measurement on synthetic systems of this shape (untimed)
+        c64.autotune(os.environ.get("EQS_TUNE_CACHE"))
+        c32.autotune(os.environ.get("EQS_TUNE_CACHE"))
     b = c64.apply(D, xs)  # b = A x* on the device
     tol, maxit = cfg["tol"], cfg["maxit"]
 
@@ -120,11 +126,11 @@ def gpu_leg(args):
         "value": n * it64 / t64,
         "ms_per_step": 1e3 * t_total / args.steps,
         "fp64": {"time_to_tol_ms": 1e3 * t64, "iters": it64, "rel_res": rec[-1][2]["rel_res"],
-                 "cell_iters_per_s": n * it64 / t64, "model_GBps": n * it64 * 256 / t64 / 1e9,
+                 "cell_iters_per_s": n * it64 / t64, "model_GBps": n * it64 * 232 / t64 / 1e9,
                  "max_abs_err_vs_xstar": err64},
         "fp32_refine": {"time_to_tol_ms": 1e3 * t32, "inner_iters": it32, "outer": rec[-1][3]["outer"],
                         "rel_res": rec[-1][3]["rel_res"], "cell_iters_per_s": n * it32 / t32,
-                        "model_GBps": n * it32 * 128 / t32 / 1e9, "max_abs_err_vs_xstar": err32,
+                        "model_GBps": n * it32 * 116 / t32 / 1e9, "max_abs_err_vs_xstar": err32,
                         "speedup_vs_fp64": t64 / t32},
         "roofline": {"bound": "hbm", "kernel": "k1_fp64", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.config),
@@ -142,6 +148,100 @@ def gpu_leg(args):
             dst.copy_(src)
         torch.cuda.synchronize()
         res["copy_calibration_bytes"] = {"read": nb, "write": nb}
+    c64.close()
+    c32.close()
+    return res
+
+
+def gpu_leg_batched(args):
+    """All equation sets of the workload in one call (configs 2 and 4)."""
+    import numpy as np
+    import torch
+
+    from paper_2211_15605_amd import workloads as W
+    from paper_2211_15605_amd.solver import Context
+
+    dev = torch.device("cuda", 0)
+    cfg = W.CONFIGS[args.config]
+    grids = [g.shape for g in cfg["grids"]]
+    Ds, bs, xss = [], [], []
+    c64 = Context(grids, precision="fp64")
+    c32 = Context(grids, precision="fp32_refine")
+    if not args.no_tune:
+        c64.autotune(os.environ.get("EQS_TUNE_CACHE"))
+        c32.autotune(os.environ.get("EQS_TUNE_CACHE"))
+    for i in range(len(grids)):
+        s = W.make_set(args.config, i)
+        D = [torch.from_numpy(d).to(dev) for d in s["diags"]]
+        xs = torch.from_numpy(s["x_star"]).to(dev)
+        del s
+        Ds.append(D)
+        xss.append(xs)
+        bs.append(c64.apply(D, xs, set_id=i))
+    tol, maxit = cfg["tol"], cfg["maxit"]
+    n_all = [int(np.prod(g)) for g in grids]
+
+    def step(rec):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x64, i64 = c64.solve_batched(Ds, bs, tol=tol, maxit=maxit)
+        t1 = time.perf_counter()
+        x32, i32 = c32.solve_batched(Ds, bs, tol=tol, maxit=maxit)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if rec is not None:
+            rec.append((t1 - t0, t2 - t1, i64, i32))
+        return x64, x32
+
+    for _ in range(args.warmup):
+        step(None)
+    c64.profile(["k1"], every=1)
+    rec = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        x64, x32 = step(rec)
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    k1_cnt, k1_ms = c64.kernel_stats("k1")
+    c64.profile([])
+    # the same sets one after another (plain FP64, the comparison the batched forms are measured against)
+    seq = []
+    for _ in range(max(1, args.steps // 2)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(len(grids)):
+            c64.solve(Ds[i], bs[i], tol=tol, maxit=maxit, set_id=i)
+        torch.cuda.synchronize()
+        seq.append(time.perf_counter() - t0)
+    t64 = float(np.mean([r[0] for r in rec]))
+    t32 = float(np.mean([r[1] for r in rec]))
+    ci64 = sum(n * inf["iters"] for n, inf in zip(n_all, rec[-1][2]))
+    ci32 = sum(n * inf["iters"] for n, inf in zip(n_all, rec[-1][3]))
+    k1_bytes_total = sum(WORDS["k1"] * 8 * n * inf["iters"] for n, inf in zip(n_all, rec[-1][2])) * len(rec)
+    achieved = k1_bytes_total / (k1_ms * 1e-3) / 1e9
+    err64 = max(float(torch.max(torch.abs(x - xs))) for x, xs in zip(x64, xss))
+    res = {
+        "value": ci64 / t64,
+        "ms_per_step": 1e3 * t_total / args.steps,
+        "fp64": {"time_to_tol_ms": 1e3 * t64, "iters": [i["iters"] for i in rec[-1][2]],
+                 "rel_res": [i["rel_res"] for i in rec[-1][2]], "cell_iters_per_s": ci64 / t64,
+                 "model_GBps": ci64 * 232 / t64 / 1e9, "max_abs_err_vs_xstar": err64,
+                 "sequential_time_to_tol_ms": 1e3 * float(np.mean(seq)),
+                 "batched_speedup_vs_sequential": float(np.mean(seq)) / t64},
+        "fp32_refine": {"time_to_tol_ms": 1e3 * t32, "inner_iters": [i["iters"] for i in rec[-1][3]],
+                        "outer": [i["outer"] for i in rec[-1][3]], "rel_res": [i["rel_res"] for i in rec[-1][3]],
+                        "cell_iters_per_s": ci32 / t32, "model_GBps": ci32 * 116 / t32 / 1e9,
+                        "speedup_vs_fp64_batched": t64 / t32,
+                        "speedup_vs_fp64_sequential": float(np.mean(seq)) / t32},
+        "roofline": {"bound": "hbm", "kernel": "k1_fp64 (batched launch)", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes": "12 words x 8 B per active cell, summed over sets", "launches": k1_cnt,
+                     "mean_launch_ms": k1_ms / max(k1_cnt, 1)},
+        "kernels_fp64_ms": {"k1": {"launches": k1_cnt, "mean_ms": k1_ms / max(k1_cnt, 1)}},
+        "layout": [c64.layout(i) for i in range(len(grids))],
+        "cells": sum(n_all),
+    }
     c64.close()
     c32.close()
     return res
@@ -166,8 +266,8 @@ def cpu_leg(args):
     _, info = o.bicgstab(g.shape, s["diags"], b, tol=1e-10, maxit=maxit)
     t = time.perf_counter() - t0
     return {"value": g.n * info["iters"] / t, "unit": "cell-iters/s", "cores": o.get_threads(), "kind": "oracle",
-            "sample": "%d FP64 BiCGSTAB iterations (of a full solve) on the same %dx%dx%d system, %.1f s" % (
-                info["iters"], g.nx, g.ny, g.nz, t)}
+            "sample": "%d FP64 BiCGSTAB iterations (of a full solve) on the %dx%dx%d system%s, %.1f s" % (
+                info["iters"], g.nx, g.ny, g.nz, " of set 0" if len(W.CONFIGS[args.config]["grids"]) > 1 else "", t)}
 
 
 def main():
@@ -178,6 +278,7 @@ def main():
     ap.add_argument("--config", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-tune", action="store_true", help="use the default launch shapes (no autotuning)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the timed steps, copy 1 GiB three times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -189,7 +290,8 @@ def main():
 
     cfg = W.CONFIGS[args.config]
     g = cfg["grids"][0]
-    r = gpu_leg(args)
+    batched = len(cfg["grids"]) > 1
+    r = gpu_leg_batched(args) if batched else gpu_leg(args)
     cpu = None if args.no_cpu_baseline else cpu_leg(args)
     line = {
         "metric": METRIC,
@@ -204,10 +306,12 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "%s: %s 7-point system on %dx%dx%d cells, b = A x*, x0 = 0, tol %g; step = "
-                               "FP64 solve + FP32-inner/FP64-refinement solve" % (
-                                   cfg["name"], "symmetric near-singular" if cfg["recipe"] == "sym"
-                                   else "convection-diffusion", g.nx, g.ny, g.nz, cfg["tol"]),
+        "config": {"workload": "%s: %s%s 7-point system%s on %s cells, b = A x*, x0 = 0, tol %g; step = "
+                               "FP64 solve + FP32-inner/FP64-refinement solve%s" % (
+                                   cfg["name"], "%d " % len(cfg["grids"]) if batched else "",
+                                   "symmetric near-singular" if cfg["recipe"] == "sym" else "convection-diffusion",
+                                   "s" if batched else "", " + ".join("%dx%dx%d" % gg.shape for gg in cfg["grids"]),
+                                   cfg["tol"], " (all sets in one call)" if batched else ""),
                    "cells": r["cells"], "layout": r["layout"]},
         "roofline": r["roofline"],
         "cpu_baseline": cpu,

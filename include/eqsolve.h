@@ -128,6 +128,20 @@ int eqsolve_adjoint(eqs_ctx *ctx, int32_t set, const double *const diag[7], cons
 int eqsolve_apply(eqs_ctx *ctx, int32_t set, const double *const diag[7], const double *x, double *y,
                   int32_t transpose);
 
+/*
+ * Pick the launch shape of every set by measurement: for each candidate
+ * (cells per thread of the stencil passes, planes per k-chunk, then the block
+ * count of the pointwise pass) time `iters` BiCGSTAB iterations with HIP
+ * events on a synthetic system of the set's exact shape in the context's
+ * precision, and keep the fastest.  The result applies to the context at once
+ * and is appended to the JSON-lines file cache_path (or $EQS_TUNE_CACHE if
+ * cache_path is NULL; nothing is written if both are unset), which
+ * eqsolve_create consults when $EQS_TUNE_CACHE is set.  Allocates and frees
+ * 9 temporary arrays of the largest set while it runs.  Returns EQS_OK,
+ * EQS_ERR_NOMEM or EQS_ERR_HIP / EQS_ERR_STATE.
+ */
+int eqsolve_autotune(eqs_ctx *ctx, const char *cache_path, int32_t iters);
+
 /* Release the context and its workspace (NULL is allowed). */
 int eqsolve_destroy(eqs_ctx *ctx);
 

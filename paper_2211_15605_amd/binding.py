@@ -23,8 +23,8 @@ PRECISIONS = {"fp64": EQS_FP64, "fp32_refine": EQS_FP32_REFINE, "fp32": EQS_FP32
 
 # symbols declared in include/eqsolve.h
 SYMBOLS = ("eqsolve_create", "eqsolve_solve", "eqsolve_solve_batched", "eqsolve_adjoint", "eqsolve_apply",
-           "eqsolve_destroy", "eqsolve_strerror", "eqsolve_debug_layout", "eqsolve_debug_profile",
-           "eqsolve_debug_kernel_stats")
+           "eqsolve_destroy", "eqsolve_strerror", "eqsolve_autotune", "eqsolve_debug_layout",
+           "eqsolve_debug_profile", "eqsolve_debug_kernel_stats")
 KERNEL_KINDS = {"setup": 0, "recheck": 1, "report": 2, "k1": 3, "k2": 4, "k3": 5, "cast": 6, "outer": 7,
                 "update": 8, "zero": 9, "grad": 10, "apply": 11}
 
@@ -75,6 +75,8 @@ def load(path: str | None = None):
         L.eqsolve_destroy.restype = ctypes.c_int
         L.eqsolve_strerror.argtypes = [ctypes.c_int]
         L.eqsolve_strerror.restype = ctypes.c_char_p
+        L.eqsolve_autotune.argtypes = [VP, ctypes.c_char_p, ctypes.c_int32]
+        L.eqsolve_autotune.restype = ctypes.c_int
         L.eqsolve_debug_layout.argtypes = [VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
         L.eqsolve_debug_layout.restype = ctypes.c_int
         L.eqsolve_debug_profile.argtypes = [VP, ctypes.c_int32, ctypes.c_int32]
@@ -163,3 +165,7 @@ def eqsolve_debug_kernel_stats(h, kind, fp32):
     ms = ctypes.c_double()
     rc = load().eqsolve_debug_kernel_stats(h, int(kind), int(bool(fp32)), ctypes.byref(cnt), ctypes.byref(ms))
     return rc, int(cnt.value), float(ms.value)
+
+
+def eqsolve_autotune(h, cache_path=None, iters=6):
+    return load().eqsolve_autotune(h, cache_path.encode() if cache_path else None, int(iters))

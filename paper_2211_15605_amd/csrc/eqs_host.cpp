@@ -23,6 +23,10 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
+#include <map>
+#include <string>
+#include <tuple>
 #include <vector>
 
 #include "eqs_internal.h"
@@ -43,8 +47,9 @@ struct SetHost {
     int n, plane;
     int S, KC, NKC, ntiles, nflat;
     // workspace offsets resolved to pointers
-    double *r, *rh, *p[2], *v[2], *t;
-    float *a32[7];
+    double *r, *rh, *p[2], *v[2], *t, *y;
+    double *as[6];
+    float *as32[6];
     float *r32, *rh32, *p32[2], *v32[2], *t32, *d32;
     double *partials;
     uint32_t *counter;
@@ -95,6 +100,11 @@ struct eqs_ctx {
     int64_t kseen[2 * 16] = {0};  // launches of each kind since profiling started
     int kpos[2 * 16] = {0};       // launches of each kind since the last readback
     std::vector<int> ev_pos;      // position of each timed launch since the last readback
+    // captured iteration chunks: (first set, set count, transpose, fp32) -> graphs of 2^k iterations
+    bool use_graphs = true;
+    bool use_small = true;      // one-block persistent solve for tiny FP64 sets (EQS_SMALL=0 disables)
+    hipStream_t capture_stream = nullptr;
+    std::map<std::tuple<int, int, bool, bool>, std::array<hipGraphExec_t, 9>> graphs;
     bool trace = false;         // print the state at every readback (EQS_TRACE=1)
     std::vector<hipEvent_t> ev_pool;
     std::vector<int> ev_kind;     // pending (start, stop) pairs: kind per pair
@@ -137,6 +147,22 @@ void choose_tiling(SetHost &s, int cpt) {
     s.nflat = std::min((s.n + kFlatChunk - 1) / kFlatChunk, fmax);
 }
 
+// explicit tiling (tuner, tuning cache)
+void set_tiling(SetHost &s, int cpt, int kc, int nflat) {
+    const int Q = kBlock * cpt;
+    s.S = (s.plane + Q - 1) / Q;
+    s.KC = std::max(1, std::min(kc, s.g.nz));
+    s.NKC = (s.g.nz + s.KC - 1) / s.KC;
+    s.ntiles = s.S * s.NKC;
+    s.nflat = std::max(1, std::min(nflat, std::min((s.n + kFlatChunk - 1) / kFlatChunk, kMaxFlatBlocks)));
+}
+
+// partial sums are sized for any tiling the tuner may choose
+size_t max_partials(const SetHost &s) {
+    const long long tiles = (long long)((s.plane + kBlock - 1) / kBlock) * s.g.nz;  // cpt = 1, KC = 1
+    return (size_t)std::max<long long>(tiles, kMaxFlatBlocks);
+}
+
 void fill_desc(eqs_ctx *c, int s) {
     SetHost &h = c->sets[s];
     SetDesc &d = c->h_desc[s];
@@ -157,7 +183,9 @@ void fill_desc(eqs_ctx *c, int s) {
     d.v[0] = h.v[0];
     d.v[1] = h.v[1];
     d.t = h.t;
-    for (int k = 0; k < 7; ++k) d.a32[k] = h.a32[k];
+    d.y = h.y;
+    for (int k = 0; k < 6; ++k) d.as[k] = h.as[k];
+    for (int k = 0; k < 6; ++k) d.as32[k] = h.as32[k];
     d.r32 = h.r32;
     d.rh32 = h.rh32;
     d.p32[0] = h.p32[0];
@@ -267,6 +295,56 @@ struct Run {
         for (int i = 0; i < 2 * 16; ++i) c->kpos[i] = 0;
         return 0;
     }
+    // C BiCGSTAB iterations (K1, K2, K3 each): replayed from captured graphs of
+    // 2^k iterations (the launch table and the set table's device address
+    // are fixed per context, so a graph stays valid across calls), or
+    // launched one by one when per-launch timing is on.
+    int iterate(int C, bool f32) {
+        int rc;
+        if (c->profile_mask || !c->use_graphs) {
+            for (int i = 0; i < C; ++i) {
+                if ((rc = L(K_K1, nullptr, nullptr, 0, f32))) return rc;
+                if ((rc = L(K_K2, nullptr, nullptr, 0, f32))) return rc;
+                if ((rc = L(K_K3, nullptr, nullptr, 0, f32))) return rc;
+            }
+            return 0;
+        }
+        auto &slots = c->graphs[std::make_tuple(first, count, trans, f32)];
+        for (int b = 8; b >= 0; --b) {
+            while (C >= (1 << b)) {
+                if (!slots[b]) {
+                    if (!c->capture_stream) EQS_HIP(hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
+                    EQS_HIP(hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
+                    bool ok = true;
+                    for (int i = 0; i < (1 << b) && ok; ++i)
+                        for (Kern k : {K_K1, K_K2, K_K3})
+                            ok = ok && launch_kernel(k, ls, ntiles, nflat, c->cpt, max_nx, f32, trans,
+                                                     c->capture_stream, nullptr, nullptr, 0) == hipSuccess;
+                    hipGraph_t g = nullptr;
+                    const hipError_t e = hipStreamEndCapture(c->capture_stream, &g);
+                    if (!ok || e != hipSuccess || !g) {
+                        if (g) (void)hipGraphDestroy(g);
+                        (void)hipGetLastError();
+                        c->broken = true;
+                        return EQS_ERR_HIP;
+                    }
+                    hipGraphExec_t ex = nullptr;
+                    const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+                    (void)hipGraphDestroy(g);
+                    if (ei != hipSuccess) {
+                        (void)hipGetLastError();
+                        c->broken = true;
+                        return EQS_ERR_HIP;
+                    }
+                    slots[b] = ex;
+                }
+                EQS_HIP(hipGraphLaunch(slots[b], c->stream));
+                c->launches += 3u << b;
+                C -= 1 << b;
+            }
+        }
+        return 0;
+    }
     const SolveState &st(int i) const { return c->h_state[first + i]; }
     bool all_done() const {
         for (int i = 0; i < count; ++i)
@@ -317,6 +395,19 @@ struct Run {
 
 int run_fp64(Run &R) {
     int rc;
+    // tiny sets: the whole solve in one launch, one block per set
+    int max_n = 0;
+    for (int i = 0; i < R.count; ++i) max_n = std::max(max_n, R.c->sets[R.first + i].n);
+    if (max_n <= kSmallSolveMaxCells && R.c->use_small) {
+        R.c->launches++;
+        if (launch_small(R.ls, max_n, R.trans, R.c->stream) != hipSuccess) {
+            (void)hipGetLastError();
+            R.c->broken = true;
+            return EQS_ERR_HIP;
+        }
+        return R.readback();
+    }
+    if ((rc = R.L(K_SCALE))) return rc;  // coefficients of A D^-1 (A^T D^-1), once per solve
     if ((rc = R.L(K_SETUP))) return rc;
     if ((rc = R.readback())) return rc;
     R.reset_rate();
@@ -324,6 +415,7 @@ int run_fp64(Run &R) {
         if (guard > R.guard_limit) { R.c->broken = true; return EQS_ERR_STATE; }
         if (R.all_done()) break;
         if (R.any([](const SolveState &s) { return s.converged || s.need_report; })) {
+            if ((rc = R.L(K_UNSCALE))) return rc;  // x = y / a_P
             if ((rc = R.L(K_RECHECK))) return rc;
             if ((rc = R.L(K_REPORT))) return rc;
             if ((rc = R.readback())) return rc;
@@ -332,11 +424,7 @@ int run_fp64(Run &R) {
         }
         const int C = R.chunk();
         if (C <= 0) { R.c->broken = true; return EQS_ERR_STATE; }
-        for (int i = 0; i < C; ++i) {
-            if ((rc = R.L(K_K1))) return rc;
-            if ((rc = R.L(K_K2))) return rc;
-            if ((rc = R.L(K_K3))) return rc;
-        }
+        if ((rc = R.iterate(C, false))) return rc;
         if ((rc = R.readback())) return rc;
     }
     if (R.any([](const SolveState &s) { return s.zero_rhs != 0; }))
@@ -362,11 +450,7 @@ int run_fp32(Run &R) {
         }
         const int C = R.chunk();
         if (C <= 0) { R.c->broken = true; return EQS_ERR_STATE; }
-        for (int i = 0; i < C; ++i) {
-            if ((rc = R.L(K_K1, nullptr, nullptr, 0, true))) return rc;
-            if ((rc = R.L(K_K2, nullptr, nullptr, 0, true))) return rc;
-            if ((rc = R.L(K_K3, nullptr, nullptr, 0, true))) return rc;
-        }
+        if ((rc = R.iterate(C, true))) return rc;
         if ((rc = R.readback())) return rc;
     }
     if (R.any([](const SolveState &s) { return s.zero_rhs != 0; }))
@@ -431,6 +515,125 @@ int upload_desc(eqs_ctx *c, int first, int count) {
     return 0;
 }
 
+
+// ------------------------------------------------------------------ tuning
+
+std::string arch_name(int device) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+        (void)hipGetLastError();
+        return "unknown";
+    }
+    std::string a = prop.gcnArchName;
+    const size_t colon = a.find(':');
+    return colon == std::string::npos ? a : a.substr(0, colon);
+}
+
+struct TuneEntry {
+    int cpt, kc, nflat;
+    double us;
+};
+
+// JSON lines, one object per tuned (arch, grid, precision); the last match wins
+bool cache_lookup(const char *path, const std::string &arch, const eqs_grid &g, int precision, TuneEntry *out) {
+    if (!path || !*path) return false;
+    FILE *f = fopen(path, "r");
+    if (!f) return false;
+    char line[512], a[64];
+    bool found = false;
+    while (fgets(line, sizeof line, f)) {
+        int nx, ny, nz, pr, cpt, kc, nflat;
+        double us;
+        if (sscanf(line,
+                   "{\"arch\": \"%63[^\"]\", \"nx\": %d, \"ny\": %d, \"nz\": %d, \"precision\": %d, \"cpt\": %d, "
+                   "\"kc\": %d, \"nflat\": %d, \"us_per_iter\": %lf}",
+                   a, &nx, &ny, &nz, &pr, &cpt, &kc, &nflat, &us) == 9 &&
+            arch == a && nx == g.nx && ny == g.ny && nz == g.nz && pr == precision && (cpt == 1 || cpt == 2)) {
+            *out = TuneEntry{cpt, kc, nflat, us};
+            found = true;
+        }
+    }
+    fclose(f);
+    return found;
+}
+
+void cache_store(const char *path, const std::string &arch, const eqs_grid &g, int precision, const TuneEntry &e) {
+    if (!path || !*path) return;
+    FILE *f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f,
+            "{\"arch\": \"%s\", \"nx\": %d, \"ny\": %d, \"nz\": %d, \"precision\": %d, \"cpt\": %d, \"kc\": %d, "
+            "\"nflat\": %d, \"us_per_iter\": %.3f}\n",
+            arch.c_str(), g.nx, g.ny, g.nz, precision, e.cpt, e.kc, e.nflat, e.us);
+    fclose(f);
+}
+
+void clear_graphs(eqs_ctx *c) {
+    for (auto &kv : c->graphs)
+        for (hipGraphExec_t ex : kv.second)
+            if (ex) (void)hipGraphExecDestroy(ex);
+    c->graphs.clear();
+}
+
+// Mean time of one BiCGSTAB iteration (K1 + K2 + K3) of set s under its
+// current tiling, on the synthetic system held in `tmp` (7 diagonals, b, x).
+// Returns -1 on a HIP failure and -2 if the measurement is not a full-work timing
+// (the synthetic system stopped iterating meanwhile).
+double time_iterations(eqs_ctx *c, int s, double *tmp, int iters) {
+    SetHost &h = c->sets[s];
+    const size_t n = (size_t)h.n;
+    fill_desc(c, s);
+    SetDesc &d = c->h_desc[s];
+    for (int k = 0; k < 7; ++k) d.a[k] = tmp + k * n;
+    d.b = tmp + 7 * n;
+    d.x = tmp + 8 * n;
+    d.xf = nullptr;
+    for (int k = 0; k < 7; ++k) d.g[k] = nullptr;
+    const bool f32 = c->precision != EQS_FP64;
+    d.mode = f32 ? MODE_REFINE : MODE_FP64;
+    d.tol = 1e-15;
+    d.tol_inner = 1e-15;
+    d.maxit = 1 << 30;
+    if (upload_desc(c, s, 1)) return -1.0;
+    if (launch_fill(d.x, (long)n, 0.0, c->stream) != hipSuccess) return -1.0;
+    Run R = make_run(c, s, 1, false);
+    const int saved = c->profile_mask;
+    c->profile_mask = 0;
+    if (f32) {
+        if (R.L(K_CAST) || R.L(K_OUTER)) return -1.0;
+    } else if (R.L(K_SCALE) || R.L(K_SETUP)) {
+        return -1.0;
+    }
+    for (int i = 0; i < 2; ++i)
+        for (Kern k : {K_K1, K_K2, K_K3})
+            if (R.L(k, nullptr, nullptr, 0, f32)) return -1.0;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return -1.0;
+    (void)hipEventRecord(e0, c->stream);
+    for (int i = 0; i < iters; ++i)
+        for (Kern k : {K_K1, K_K2, K_K3})
+            if (R.L(k, nullptr, nullptr, 0, f32)) return -1.0;
+    (void)hipEventRecord(e1, c->stream);
+    float ms = 0.f;
+    const bool ok = hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->profile_mask = saved;
+    if (!ok || R.readback()) return -1.0;
+    if (!c->h_state[s].active) return -2.0;  // stopped during the measurement: not a full-work timing
+    return 1e3 * ms / iters;
+}
+
+int apply_tuning(eqs_ctx *c, int cpt, const std::vector<TuneEntry> &e) {
+    c->cpt = cpt;
+    for (int s = 0; s < c->nsets; ++s) {
+        set_tiling(c->sets[s], cpt, e[s].kc, e[s].nflat);
+        fill_desc(c, s);
+    }
+    clear_graphs(c);
+    return upload_desc(c, 0, c->nsets);
+}
+
 }  // namespace
 
 extern "C" {
@@ -447,6 +650,8 @@ int eqsolve_create(eqs_ctx **out, const eqs_grid *grids, int32_t nsets, int32_t 
     if (!c) return EQS_ERR_NOMEM;
     c->stream = (hipStream_t)hip_stream;
     c->trace = env_int("EQS_TRACE", 0) != 0;
+    c->use_graphs = env_int("EQS_GRAPHS", 1) != 0;
+    c->use_small = env_int("EQS_SMALL", 1) != 0;
     c->nsets = nsets;
     c->precision = precision;
     if (hipGetDevice(&c->device) != hipSuccess) { delete c; return EQS_ERR_HIP; }
@@ -462,6 +667,20 @@ int eqsolve_create(eqs_ctx **out, const eqs_grid *grids, int32_t nsets, int32_t 
     while (cpt > 1 && march_lds_bytes(cpt, max_nx, 8) > kMaxLds) cpt /= 2;
     // nx beyond what one LDS plane buffer or the halo slots cover
     if (march_lds_bytes(cpt, max_nx, 8) > kMaxLds || halo_slots(max_nx) < 0) { delete c; return EQS_ERR_ARG; }
+    // a tuning cache (EQS_TUNE_CACHE) entry for every set, with one common cpt, overrides the defaults
+    std::vector<TuneEntry> tuned(nsets);
+    bool tuned_ok = getenv("EQS_TUNE_CACHE") != nullptr && env_int("EQS_CPT", 0) == 0 && env_int("EQS_KC", 0) == 0;
+    int tuned_cpt = 0;
+    if (tuned_ok) {
+        const std::string arch = arch_name(c->device);
+        for (int s = 0; s < nsets && tuned_ok; ++s) {
+            tuned_ok = cache_lookup(getenv("EQS_TUNE_CACHE"), arch, grids[s], precision, &tuned[s]);
+            if (tuned_ok && s > 0 && tuned[s].cpt != tuned[0].cpt) tuned_ok = false;
+        }
+        if (tuned_ok) tuned_cpt = tuned[0].cpt;
+        if (tuned_ok && march_lds_bytes(tuned_cpt, max_nx, 8) > kMaxLds) tuned_ok = false;
+        if (tuned_ok) cpt = tuned_cpt;
+    }
     c->cpt = cpt;
     c->max_nx = max_nx;
 
@@ -476,10 +695,11 @@ int eqsolve_create(eqs_ctx **out, const eqs_grid *grids, int32_t nsets, int32_t 
         h.plane = grids[s].nx * grids[s].ny;
         h.n = h.plane * grids[s].nz;
         choose_tiling(h, cpt);
+        if (tuned_ok) set_tiling(h, tuned_cpt, tuned[s].kc, tuned[s].nflat);
         base[s] = bytes;
-        bytes += 7 * align_up((size_t)h.n * 8);
-        if (f32) bytes += 15 * align_up((size_t)h.n * 4);
-        bytes += align_up((size_t)std::max(h.ntiles, h.nflat) * kMaxRed * 8);
+        bytes += 14 * align_up((size_t)h.n * 8);   // r, r^, p[2], v[2], t, y, 6 scaled coefficients
+        if (f32) bytes += 14 * align_up((size_t)h.n * 4);  // 6 scaled coefficients, r, r^, p[2], v[2], t, d
+        bytes += align_up(max_partials(h) * kMaxRed * 8);
         bytes += kAlign;  // counter
     }
     c->ws_bytes = bytes;
@@ -506,8 +726,10 @@ int eqsolve_create(eqs_ctx **out, const eqs_grid *grids, int32_t nsets, int32_t 
         h.v[0] = (double *)take((size_t)h.n * 8);
         h.v[1] = (double *)take((size_t)h.n * 8);
         h.t = (double *)take((size_t)h.n * 8);
+        h.y = (double *)take((size_t)h.n * 8);
+        for (int k = 0; k < 6; ++k) h.as[k] = (double *)take((size_t)h.n * 8);
         if (f32) {
-            for (int k = 0; k < 7; ++k) h.a32[k] = (float *)take((size_t)h.n * 4);
+            for (int k = 0; k < 6; ++k) h.as32[k] = (float *)take((size_t)h.n * 4);
             h.r32 = (float *)take((size_t)h.n * 4);
             h.rh32 = (float *)take((size_t)h.n * 4);
             h.p32[0] = (float *)take((size_t)h.n * 4);
@@ -517,7 +739,7 @@ int eqsolve_create(eqs_ctx **out, const eqs_grid *grids, int32_t nsets, int32_t 
             h.t32 = (float *)take((size_t)h.n * 4);
             h.d32 = (float *)take((size_t)h.n * 4);
         }
-        h.partials = (double *)take((size_t)std::max(h.ntiles, h.nflat) * kMaxRed * 8);
+        h.partials = (double *)take(max_partials(h) * kMaxRed * 8);
         h.counter = (uint32_t *)take(kAlign);
         h.last_iters = -1;
         fill_desc(c, s);
@@ -540,6 +762,8 @@ int eqsolve_destroy(eqs_ctx *c) {
     if (!c) return EQS_OK;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    clear_graphs(c);
+    if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     if (c->ws) (void)hipFree(c->ws);
     if (c->d_desc) (void)hipFree(c->d_desc);
     if (c->d_state) (void)hipFree(c->d_state);
@@ -679,6 +903,82 @@ int eqsolve_debug_layout(const eqs_ctx *c, int32_t set, int32_t *out6) {
     out6[3] = h.NKC;
     out6[4] = h.ntiles;
     out6[5] = (int32_t)std::min<uint64_t>(c->readbacks, 0x7fffffff);
+    return EQS_OK;
+}
+
+int eqsolve_autotune(eqs_ctx *c, const char *cache_path, int32_t iters) {
+    if (!c || c->broken) return EQS_ERR_STATE;
+    if (iters < 1) iters = 6;
+    iters = std::min(iters, 64);
+    const std::string arch = arch_name(c->device);
+    size_t nmax = 0;
+    for (const SetHost &h : c->sets) nmax = std::max(nmax, (size_t)h.n);
+    double *tmp = nullptr;
+    if (hipMalloc((void **)&tmp, 9 * nmax * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        return EQS_ERR_NOMEM;
+    }
+    // a well-conditioned synthetic system of each set's shape: a_P = 7, a_nb = 1, b = 1
+    int rc = EQS_OK;
+    for (int k = 0; k < 9 && rc == EQS_OK; ++k)
+        if (launch_fill(tmp + k * nmax, (long)nmax, k == 0 ? 7.0 : 1.0, c->stream) != hipSuccess) rc = EQS_ERR_HIP;
+    const int kcs[] = {1, 2, 4, 8, 16, 32};
+    const int flats[] = {256, 512, 1024, 2048, 4096};
+    const int old_cpt = c->cpt;
+    double best_total = 1e300;
+    int best_cpt = old_cpt;
+    std::vector<TuneEntry> best(c->nsets), cur(c->nsets);
+    for (int cpt = 1; cpt <= 2 && rc == EQS_OK; ++cpt) {
+        if (march_lds_bytes(cpt, c->max_nx, 8) > kMaxLds) continue;
+        c->cpt = cpt;
+        clear_graphs(c);
+        double total = 0.0;
+        for (int s = 0; s < c->nsets && rc == EQS_OK; ++s) {
+            SetHost &h = c->sets[s];
+            const int kc0 = h.KC;
+            TuneEntry b{cpt, kc0, h.nflat, 1e300};
+            for (int kc : kcs) {
+                if (kc > h.g.nz) continue;
+                set_tiling(h, cpt, kc, h.nflat);
+                const double us = time_iterations(c, s, tmp, iters);
+                if (us == -1.0) { rc = EQS_ERR_HIP; break; }
+                if (us > 0 && us < b.us) b = TuneEntry{cpt, kc, h.nflat, us};
+            }
+            if (rc != EQS_OK) break;
+            // a set too small to iterate this long keeps its default depth
+            if (b.us >= 1e300) b = TuneEntry{cpt, kc0, h.nflat, 0.0};
+            cur[s] = b;
+            total += b.us;
+        }
+        if (rc == EQS_OK && total < best_total) {
+            best_total = total;
+            best_cpt = cpt;
+            best = cur;
+        }
+    }
+    // pointwise block count, with the chosen march tiling
+    c->cpt = best_cpt;
+    clear_graphs(c);
+    for (int s = 0; s < c->nsets && rc == EQS_OK; ++s) {
+        SetHost &h = c->sets[s];
+        for (int nf : flats) {
+            set_tiling(h, best_cpt, best[s].kc, nf);
+            if (h.nflat != nf) continue;
+            const double us = time_iterations(c, s, tmp, iters);
+            if (us == -1.0) { rc = EQS_ERR_HIP; break; }
+            if (us > 0 && us < best[s].us) best[s] = TuneEntry{best_cpt, best[s].kc, nf, us};
+        }
+    }
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(tmp);
+    (void)hipGetLastError();
+    if (rc != EQS_OK) {
+        c->broken = true;
+        return rc;
+    }
+    if ((rc = apply_tuning(c, best_cpt, best))) return rc;
+    const char *path = cache_path ? cache_path : getenv("EQS_TUNE_CACHE");
+    for (int s = 0; s < c->nsets; ++s) cache_store(path, arch, c->sets[s].g, c->precision, best[s]);
     return EQS_OK;
 }
 

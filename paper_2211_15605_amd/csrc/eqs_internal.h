@@ -70,10 +70,14 @@ struct SetDesc {
     const double *a[7];
     const double *b;
     double *x;
-    // FP64 work (r^ = rh); p and v are double-buffered by iteration parity
-    double *r, *rh, *p[2], *v[2], *t;
-    // FP32 work; d32 is the inner iterate
-    float *a32[7];
+    // FP64 work (r^ = rh); p and v are double-buffered by iteration parity.
+    // The iteration runs on the column-scaled operator A D^-1 (unit diagonal,
+    // D = diag(a_P)): as[0..5] hold its E, W, N, S, T, B coefficients (for
+    // the adjoint, those of A^T D^-1) and y = D x is its iterate.
+    double *r, *rh, *p[2], *v[2], *t, *y;
+    double *as[6];
+    // FP32 work (refinement): scaled coefficients, vectors, d32 = inner iterate (scaled)
+    float *as32[6];
     float *r32, *rh32, *p32[2], *v32[2], *t32, *d32;
     // adjoint: forward solution and gradient outputs (grad_b is the iterate x)
     const double *xf;

@@ -518,47 +518,83 @@ __device__ __forceinline__ void march(Ph &ph, const Geo &d, int tile, T *lds, do
 }
 
 // ------------------------------------------------------------------ phases
+//
+// The BiCGSTAB iteration runs on the column-scaled operator A D^-1 (unit
+// diagonal, D = diag(a_P)) with iterate y = D x: this is right-Jacobi
+// BiCGSTAB on A with the preconditioner folded into the matrix once per
+// solve, so the iteration reads six coefficient arrays, never a_P, and
+// divides nowhere.  (A D^-1 y)[c] = y[c] - sum_nb s_nb[c] y[nb(c)] with
+// s_nb[c] = a_nb[c] / a_P[nb(c)].
 
 template <typename T>
 struct Vecs;
 template <>
 struct Vecs<double> {
-    __device__ static const double *const *a(const SetDesc &d) { return d.a; }
+    __device__ static double *const *as(const SetDesc &d) { return d.as; }
     __device__ static double *r(const SetDesc &d) { return d.r; }
     __device__ static double *rh(const SetDesc &d) { return d.rh; }
     __device__ static double *p(const SetDesc &d, int i) { return i ? d.p[1] : d.p[0]; }
     __device__ static double *v(const SetDesc &d, int i) { return i ? d.v[1] : d.v[0]; }
     __device__ static double *t(const SetDesc &d) { return d.t; }
-    __device__ static double *x(const SetDesc &d) { return d.x; }
+    __device__ static double *y(const SetDesc &d) { return d.y; }
 };
 template <>
 struct Vecs<float> {
-    __device__ static const float *const *a(const SetDesc &d) { return (const float *const *)d.a32; }
+    __device__ static float *const *as(const SetDesc &d) { return d.as32; }
     __device__ static float *r(const SetDesc &d) { return d.r32; }
     __device__ static float *rh(const SetDesc &d) { return d.rh32; }
     __device__ static float *p(const SetDesc &d, int i) { return i ? d.p32[1] : d.p32[0]; }
     __device__ static float *v(const SetDesc &d, int i) { return i ? d.v32[1] : d.v32[0]; }
     __device__ static float *t(const SetDesc &d) { return d.t32; }
-    __device__ static float *x(const SetDesc &d) { return d.d32; }
+    __device__ static float *y(const SetDesc &d) { return d.d32; }
 };
 
-// K1: p = r + beta (p - omega v); p^ = p / a_P; v = A p^; (r^, v)
-template <typename T, bool TR>
+// the six scaled coefficients of a row, zero where the neighbour is outside
+// the grid (loads unconditional, masked afterwards, as in Coef6)
+template <typename T>
+struct Unit6 {
+    T e, w, n, s, t, b;
+    __device__ __forceinline__ void load(const T *const *as, int idx, Nb nb, bool up, bool dn) {
+        e = ld(as[0], idx);
+        w = ld(as[1], idx);
+        n = ld(as[2], idx);
+        s = ld(as[3], idx);
+        t = ld(as[4], idx);
+        b = ld(as[5], idx);
+        e = nb.e ? e : T(0);
+        w = nb.w ? w : T(0);
+        n = nb.n ? n : T(0);
+        s = nb.s ? s : T(0);
+        t = up ? t : T(0);
+        b = dn ? b : T(0);
+    }
+    __device__ __forceinline__ T apply(T xc, T xE, T xW, T xN, T xS, T xT, T xB) const {
+        T acc = xc;
+        acc = fma(-e, xE, acc);
+        acc = fma(-w, xW, acc);
+        acc = fma(-n, xN, acc);
+        acc = fma(-s, xS, acc);
+        acc = fma(-t, xT, acc);
+        acc = fma(-b, xB, acc);
+        return acc;
+    }
+};
+
+// K1: p = r + beta (p - omega v); v = (A D^-1) p; (r^, v)
+template <typename T>
 struct PhK1 {
     static constexpr int NV = 1;
-    struct Raw { T r, p, v, ap; };
-    struct Aux { T ap; };
-    struct Pre { Coef6<T, TR> c; T rh; };
-    const T *a[7];
+    struct Raw { T r, p, v; };
+    struct Aux {};
+    struct Pre { Unit6<T> c; T rh; };
+    const T *as[6];
     const T *r, *rhd, *pold, *vold;
     T *pnew, *vnew, *rhw;
     T beta, omega;
-    int nx, P, ncell;
     bool fresh;
     __device__ __forceinline__ Raw load(int idx) const {
         Raw w;
         w.r = ld(r, idx);
-        w.ap = ld(a[0], idx);
         w.p = ld(pold, idx);
         w.v = ld(vold, idx);
         return w;
@@ -566,58 +602,53 @@ struct PhK1 {
     __device__ __forceinline__ T pval(const Raw &w) const {
         return fresh ? w.r : fma(beta, fma(-omega, w.v, w.p), w.r);
     }
-    __device__ __forceinline__ T own(const Raw &w, int idx, Aux &ax) {
+    __device__ __forceinline__ T own(const Raw &w, int idx, Aux &) {
         const T p = pval(w);
         st(pnew, idx, p);
         if (fresh) st(rhw, idx, w.r);
-        ax.ap = w.ap;
-        return p / w.ap;
+        return p;
     }
-    __device__ __forceinline__ T halo(const Raw &w) const { return pval(w) / w.ap; }
+    __device__ __forceinline__ T halo(const Raw &w) const { return pval(w); }
     __device__ __forceinline__ void pre(int idx, Nb nb, bool up, bool dn, Pre &pr) const {
-        pr.c.load(a, idx, nx, P, ncell, nb, up, dn);
+        pr.c.load(as, idx, nb, up, dn);
         pr.rh = ld(rhd, idx);
     }
-    __device__ __forceinline__ void center(int idx, const Pre &pr, const Aux &ax, T xc, T xE, T xW, T xN,
-                                           T xS, T xT, T xB, double (&acc)[NV]) {
-        const T v = pr.c.apply(ax.ap, xc, xE, xW, xN, xS, xT, xB);
+    __device__ __forceinline__ void center(int idx, const Pre &pr, const Aux &, T xc, T xE, T xW, T xN, T xS,
+                                           T xT, T xB, double (&acc)[NV]) {
+        const T v = pr.c.apply(xc, xE, xW, xN, xS, xT, xB);
         st(vnew, idx, v);
         acc[0] += (double)pr.rh * (double)v;
     }
 };
 
-// K2: s = r - alpha v; s^ = s / a_P; t = A s^; (t, s), (t, t), (s, s)
-template <typename T, bool TR>
+// K2: s = r - alpha v; t = (A D^-1) s; (t, s), (t, t), (s, s)
+template <typename T>
 struct PhK2 {
     static constexpr int NV = 3;
-    struct Raw { T r, v, ap; };
-    struct Aux { T ap, s; };
-    struct Pre { Coef6<T, TR> c; };
-    const T *a[7];
+    struct Raw { T r, v; };
+    struct Aux { T s; };
+    struct Pre { Unit6<T> c; };
+    const T *as[6];
     const T *r, *v;
     T *tout;
     T alpha;
-    int nx, P, ncell;
     __device__ __forceinline__ Raw load(int idx) const {
         Raw w;
         w.r = ld(r, idx);
         w.v = ld(v, idx);
-        w.ap = ld(a[0], idx);
         return w;
     }
     __device__ __forceinline__ T own(const Raw &w, int, Aux &ax) {
-        const T s = fma(-alpha, w.v, w.r);
-        ax.ap = w.ap;
-        ax.s = s;
-        return s / w.ap;
+        ax.s = fma(-alpha, w.v, w.r);
+        return ax.s;
     }
-    __device__ __forceinline__ T halo(const Raw &w) const { return fma(-alpha, w.v, w.r) / w.ap; }
+    __device__ __forceinline__ T halo(const Raw &w) const { return fma(-alpha, w.v, w.r); }
     __device__ __forceinline__ void pre(int idx, Nb nb, bool up, bool dn, Pre &pr) const {
-        pr.c.load(a, idx, nx, P, ncell, nb, up, dn);
+        pr.c.load(as, idx, nb, up, dn);
     }
-    __device__ __forceinline__ void center(int idx, const Pre &pr, const Aux &ax, T xc, T xE, T xW, T xN,
-                                           T xS, T xT, T xB, double (&acc)[NV]) {
-        const T t = pr.c.apply(ax.ap, xc, xE, xW, xN, xS, xT, xB);
+    __device__ __forceinline__ void center(int idx, const Pre &pr, const Aux &ax, T xc, T xE, T xW, T xN, T xS,
+                                           T xT, T xB, double (&acc)[NV]) {
+        const T t = pr.c.apply(xc, xE, xW, xN, xS, xT, xB);
         st(tout, idx, t);
         const double td = (double)t, sd = (double)ax.s;
         acc[0] += td * sd;
@@ -626,10 +657,9 @@ struct PhK2 {
     }
 };
 
-// stencil operand = x itself (residual and product phases)
+// stencil operand = x itself (residual and product phases, original operator)
 struct RawX { double x; };
 
-// r = b - A x (FP64).  SETUP and RECHECK write r and r^ = r; REPORT only sums.
 template <bool TR>
 struct PhRes {
     static constexpr int NV = 3;
@@ -638,7 +668,7 @@ struct PhRes {
     struct Pre { Coef6<double, TR> c; double ap, b; };
     const double *a[7];
     const double *x, *b;
-    double *r, *rh;
+    double *r, *rh, *y;
     int nx, P, ncell;
     bool write;
     __device__ __forceinline__ Raw load(int idx) const { return Raw{ld(x, idx)}; }
@@ -656,6 +686,7 @@ struct PhRes {
         if (write) {
             st(r, idx, rv);
             st(rh, idx, rv);
+            st(y, idx, pr.ap * xc);  // the scaled iterate y = D x that the iteration continues from
         }
         acc[0] += pr.b * pr.b;
         acc[1] += rv * rv;
@@ -726,15 +757,15 @@ __device__ __forceinline__ T *lds_base() {
     return reinterpret_cast<T *>(eqs_smem);
 }
 
-template <typename T, int CPT, int H, bool TR>
+template <typename T, int CPT, int H>
 __global__ void __launch_bounds__(kBlock) k1_kernel(LaunchSets ls) {
     const TileRef tr = locate<false>(ls);
     const SetDesc &d = *tr.d;
     const SolveState *st_ = d.st;
     if (!st_->active) return;
     const int par = st_->iters & 1;
-    PhK1<T, TR> ph;
-    for (int k = 0; k < 7; ++k) ph.a[k] = Vecs<T>::a(d)[k];
+    PhK1<T> ph;
+    for (int k = 0; k < 6; ++k) ph.as[k] = Vecs<T>::as(d)[k];
     ph.r = Vecs<T>::r(d);
     ph.fresh = st_->fresh != 0;
     ph.rhd = ph.fresh ? Vecs<T>::r(d) : Vecs<T>::rh(d);
@@ -745,30 +776,24 @@ __global__ void __launch_bounds__(kBlock) k1_kernel(LaunchSets ls) {
     ph.vnew = Vecs<T>::v(d, par ^ 1);
     ph.beta = (T)((st_->rho / st_->rho_prev) * (st_->alpha / st_->omega));
     ph.omega = (T)st_->omega;
-    ph.nx = d.nx;
-    ph.P = d.plane;
-    ph.ncell = d.n;
     double acc[1] = {0.0};
     march<T, CPT, H>(ph, geo_of(d), tr.tile, lds_base<T>(), acc);
     reduce_and_finalize<1>(d, tr.tile, d.ntiles, acc, FinK1{});
 }
 
-template <typename T, int CPT, int H, bool TR>
+template <typename T, int CPT, int H>
 __global__ void __launch_bounds__(kBlock) k2_kernel(LaunchSets ls) {
     const TileRef tr = locate<false>(ls);
     const SetDesc &d = *tr.d;
     const SolveState *st_ = d.st;
     if (!st_->active) return;
     const int par = st_->iters & 1;
-    PhK2<T, TR> ph;
-    for (int k = 0; k < 7; ++k) ph.a[k] = Vecs<T>::a(d)[k];
+    PhK2<T> ph;
+    for (int k = 0; k < 6; ++k) ph.as[k] = Vecs<T>::as(d)[k];
     ph.r = Vecs<T>::r(d);
     ph.v = Vecs<T>::v(d, par);
     ph.tout = Vecs<T>::t(d);
     ph.alpha = (T)st_->alpha;
-    ph.nx = d.nx;
-    ph.P = d.plane;
-    ph.ncell = d.n;
     double acc[3] = {0.0, 0.0, 0.0};
     march<T, CPT, H>(ph, geo_of(d), tr.tile, lds_base<T>(), acc);
     reduce_and_finalize<3>(d, tr.tile, d.ntiles, acc, FinK2{});
@@ -788,6 +813,7 @@ __global__ void __launch_bounds__(kBlock) res_kernel(LaunchSets ls, int mode) {
     ph.b = d.b;
     ph.r = d.r;
     ph.rh = d.rh;
+    ph.y = d.y;
     ph.write = mode != 2;
     ph.nx = d.nx;
     ph.P = d.plane;
@@ -846,7 +872,7 @@ __global__ void __launch_bounds__(kBlock) apply_kernel(LaunchSets ls, const doub
 // computing and storing.
 
 
-// K3: x += alpha p^ + omega s^; r = s - omega t; (r^, r), (r, r)
+// K3: y += alpha p + omega s; r = s - omega t; (r^, r), (r, r)
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k3_kernel(LaunchSets ls) {
     const TileRef tr = locate<true>(ls);
@@ -854,32 +880,30 @@ __global__ void __launch_bounds__(kBlock) k3_kernel(LaunchSets ls) {
     const SolveState *st_ = d.st;
     if (!st_->active) return;
     const int par = st_->iters & 1;
-    const T *a0 = Vecs<T>::a(d)[0];
     const T *p = Vecs<T>::p(d, par);
     const T *v = Vecs<T>::v(d, par);
     const T *t = Vecs<T>::t(d);
     const T *rh = Vecs<T>::rh(d);
     T *r = Vecs<T>::r(d);
-    T *x = Vecs<T>::x(d);
+    T *y = Vecs<T>::y(d);
     const T alpha = (T)st_->alpha, omega = (T)st_->omega;
     const int n = d.n, nflat = d.nflat;
     double acc[2] = {0.0, 0.0};
     for (int ch = tr.tile; ch * kFlatChunk < n; ch += nflat) {
         const int base = ch * kFlatChunk + (int)threadIdx.x;
-        T A[kFlatU], Pv[kFlatU], V[kFlatU], R[kFlatU], Tt[kFlatU], X[kFlatU], RH[kFlatU];
+        T Pv[kFlatU], V[kFlatU], R[kFlatU], Tt[kFlatU], Y[kFlatU], RH[kFlatU];
 #pragma unroll
         for (int u = 0; u < kFlatU; ++u) {
             const int i = min(base + kBlock * u, n - 1);
-            A[u] = ld(a0, i); Pv[u] = ld(p, i); V[u] = ld(v, i); R[u] = ld(r, i);
-            Tt[u] = ld(t, i); X[u] = ld(x, i); RH[u] = ld(rh, i);
+            Pv[u] = ld(p, i); V[u] = ld(v, i); R[u] = ld(r, i);
+            Tt[u] = ld(t, i); Y[u] = ld(y, i); RH[u] = ld(rh, i);
         }
 #pragma unroll
         for (int u = 0; u < kFlatU; ++u) {
             const int i = base + kBlock * u;
             if (i < n) {
                 const T s = fma(-alpha, V[u], R[u]);
-                const T ph = Pv[u] / A[u], sh = s / A[u];
-                st(x, i, X[u] + fma(alpha, ph, omega * sh));
+                st(y, i, Y[u] + fma(alpha, Pv[u], omega * s));
                 const T rn = fma(-omega, Tt[u], s);
                 st(r, i, rn);
                 acc[0] += (double)RH[u] * (double)rn;
@@ -890,44 +914,119 @@ __global__ void __launch_bounds__(kBlock) k3_kernel(LaunchSets ls) {
     reduce_and_finalize<2>(d, tr.tile, nflat, acc, FinK3{});
 }
 
-// FP64 -> FP32 coefficient copies (round to nearest even), (b, b), a_P check
-__global__ void __launch_bounds__(kBlock) cast_kernel(LaunchSets ls) {
+// coefficients of A D^-1 (TR = false) or A^T D^-1 (TR = true), FP64 (for the
+// FP64 iteration) or FP32 (for the refinement's inner iteration, rounded
+// once from the FP64 quotient)
+template <bool TR, typename T>
+__device__ __forceinline__ void scaled_row(const double *const *a, int idx, int i, int j, int k, int nx, int ny,
+                                           int nz, int P, T (&o)[6]) {
+    const bool e = i + 1 < nx, w = i > 0, nn = j + 1 < ny, ss = j > 0, up = k + 1 < nz, dn = k > 0;
+    double c[6];
+    if (!TR) {
+        c[0] = e ? ld(a[1], idx) / ld(a[0], idx + 1) : 0.0;
+        c[1] = w ? ld(a[2], idx) / ld(a[0], idx - 1) : 0.0;
+        c[2] = nn ? ld(a[3], idx) / ld(a[0], idx + nx) : 0.0;
+        c[3] = ss ? ld(a[4], idx) / ld(a[0], idx - nx) : 0.0;
+        c[4] = up ? ld(a[5], idx) / ld(a[0], idx + P) : 0.0;
+        c[5] = dn ? ld(a[6], idx) / ld(a[0], idx - P) : 0.0;
+    } else {
+        // row idx of A^T D^-1: the link to neighbour nb is row nb's coefficient towards idx, over a_P[nb]
+        c[0] = e ? ld(a[2], idx + 1) / ld(a[0], idx + 1) : 0.0;
+        c[1] = w ? ld(a[1], idx - 1) / ld(a[0], idx - 1) : 0.0;
+        c[2] = nn ? ld(a[4], idx + nx) / ld(a[0], idx + nx) : 0.0;
+        c[3] = ss ? ld(a[3], idx - nx) / ld(a[0], idx - nx) : 0.0;
+        c[4] = up ? ld(a[6], idx + P) / ld(a[0], idx + P) : 0.0;
+        c[5] = dn ? ld(a[5], idx - P) / ld(a[0], idx - P) : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q) o[q] = (T)c[q];
+}
+
+template <bool TR>
+__global__ void __launch_bounds__(kBlock) scale_kernel(LaunchSets ls) {
     const TileRef tr = locate<true>(ls);
     const SetDesc &d = *tr.d;
-    const int n = d.n, nflat = d.nflat;
-    const double *a64[7];
-    float *a32[7];
-    for (int s = 0; s < 7; ++s) {
-        a64[s] = d.a[s];
-        a32[s] = d.a32[s];
-    }
-    const double *bvec = d.b;
-    double acc[2] = {0.0, 0.0};
+    const int nx = d.nx, ny = d.ny, nz = d.nz, P = d.plane, n = d.n, nflat = d.nflat;
+    const double *a[7];
+    double *as[6];
+    for (int q = 0; q < 7; ++q) a[q] = d.a[q];
+    for (int q = 0; q < 6; ++q) as[q] = d.as[q];
     for (int ch = tr.tile; ch * kFlatChunk < n; ch += nflat) {
         const int base = ch * kFlatChunk + (int)threadIdx.x;
-        double A[7][kFlatU], B[kFlatU];
+#pragma unroll
+        for (int u = 0; u < kFlatU; ++u) {
+            const int idx = base + kBlock * u;
+            if (idx < n) {
+                const int k = idx / P, q = idx - k * P, j = q / nx, i = q - j * nx;
+                double o[6];
+                scaled_row<TR>(a, idx, i, j, k, nx, ny, nz, P, o);
+#pragma unroll
+                for (int z = 0; z < 6; ++z) st(as[z], idx, o[z]);
+            }
+        }
+    }
+}
+
+// x = y / a_P for sets about to be rechecked or reported
+__global__ void __launch_bounds__(kBlock) unscale_kernel(LaunchSets ls) {
+    const TileRef tr = locate<true>(ls);
+    const SetDesc &d = *tr.d;
+    const SolveState *st_ = d.st;
+    if (!st_->converged && !st_->need_report) return;
+    const int n = d.n, nflat = d.nflat;
+    const double *a0 = d.a[0], *y = d.y;
+    double *x = d.x;
+    for (int ch = tr.tile; ch * kFlatChunk < n; ch += nflat) {
+        const int base = ch * kFlatChunk + (int)threadIdx.x;
+        double Y[kFlatU], A[kFlatU];
 #pragma unroll
         for (int u = 0; u < kFlatU; ++u) {
             const int i = min(base + kBlock * u, n - 1);
-#pragma unroll
-            for (int s = 0; s < 7; ++s) A[s][u] = ld(a64[s], i);
-            B[u] = ld(bvec, i);
+            Y[u] = ld(y, i);
+            A[u] = ld(a0, i);
         }
 #pragma unroll
         for (int u = 0; u < kFlatU; ++u) {
             const int i = base + kBlock * u;
-            if (i < n) {
+            if (i < n) st(x, i, Y[u] / A[u]);
+        }
+    }
+}
+
+// FP32 coefficients of A D^-1 (each rounded to nearest once from the FP64
+// quotient), (b, b), a_P check
+__global__ void __launch_bounds__(kBlock) cast_kernel(LaunchSets ls) {
+    const TileRef tr = locate<true>(ls);
+    const SetDesc &d = *tr.d;
+    const int nx = d.nx, ny = d.ny, nz = d.nz, P = d.plane, n = d.n, nflat = d.nflat;
+    const double *a[7];
+    float *as32[6];
+    for (int q = 0; q < 7; ++q) a[q] = d.a[q];
+    for (int q = 0; q < 6; ++q) as32[q] = d.as32[q];
+    const double *bvec = d.b;
+    double acc[2] = {0.0, 0.0};
+    for (int ch = tr.tile; ch * kFlatChunk < n; ch += nflat) {
+        const int base = ch * kFlatChunk + (int)threadIdx.x;
 #pragma unroll
-                for (int s = 0; s < 7; ++s) st(a32[s], i, (float)A[s][u]);
-                acc[0] += B[u] * B[u];
-                acc[1] += (A[0][u] == 0.0 || !isfinite(A[0][u]) || (float)A[0][u] == 0.0f) ? 1.0 : 0.0;
+        for (int u = 0; u < kFlatU; ++u) {
+            const int idx = base + kBlock * u;
+            if (idx < n) {
+                const int k = idx / P, q = idx - k * P, j = q / nx, i = q - j * nx;
+                float o[6];
+                scaled_row<false>(a, idx, i, j, k, nx, ny, nz, P, o);
+#pragma unroll
+                for (int z = 0; z < 6; ++z) st(as32[z], idx, o[z]);
+                const double ap = ld(a[0], idx), bv = ld(bvec, idx);
+                acc[0] += bv * bv;
+                acc[1] += (ap == 0.0 || !isfinite(ap)) ? 1.0 : 0.0;
             }
         }
     }
     reduce_and_finalize<2>(d, tr.tile, nflat, acc, FinCast{&d});
 }
 
-// x += d32 / scale (FP64), for sets whose inner solve has finished
+// x += (d32 / scale) / a_P (FP64), for sets whose inner solve has finished
+// (d32 is the inner iterate of the scaled system, D times the correction)
 __global__ void __launch_bounds__(kBlock) update_kernel(LaunchSets ls) {
     const TileRef tr = locate<true>(ls);
     const SetDesc &d = *tr.d;
@@ -937,20 +1036,22 @@ __global__ void __launch_bounds__(kBlock) update_kernel(LaunchSets ls) {
     const int n = d.n, nflat = d.nflat;
     double *xv = d.x;
     const float *dv = d.d32;
+    const double *a0 = d.a[0];
     for (int ch = tr.tile; ch * kFlatChunk < n; ch += nflat) {
         const int base = ch * kFlatChunk + (int)threadIdx.x;
-        double X[kFlatU];
+        double X[kFlatU], A[kFlatU];
         float D[kFlatU];
 #pragma unroll
         for (int u = 0; u < kFlatU; ++u) {
             const int i = min(base + kBlock * u, n - 1);
             X[u] = ld(xv, i);
             D[u] = ld(dv, i);
+            A[u] = ld(a0, i);
         }
 #pragma unroll
         for (int u = 0; u < kFlatU; ++u) {
             const int i = base + kBlock * u;
-            if (i < n) st(xv, i, fma(is, (double)D[u], X[u]));
+            if (i < n) st(xv, i, X[u] + (is * (double)D[u]) / A[u]);
         }
     }
 }
@@ -1007,7 +1108,222 @@ __global__ void __launch_bounds__(kBlock) grad_kernel(LaunchSets ls) {
     }
 }
 
+
+// ------------------------------------------------------------------ one-block persistent solve (tiny sets)
+//
+// For a set of at most kSmallThreads * 8 cells, one 512-thread block runs the
+// whole FP64 solve in a single launch: every cell's coefficients and vectors
+// live in registers (cell c = tid + kSmallThreads * m), the stencil operand is
+// exchanged through LDS, and the scalar updates are the same state-machine
+// functions the multi-kernel path uses.  Several tiny sets of one call run as
+// independent blocks of one launch.
+
+constexpr int kSmallThreads = 512;  // 2 waves per SIMD: up to 256 VGPRs per lane for the register-resident vectors
+constexpr int kSmallMaxCells = kSmallThreads * 8;
+
+template <int NV>
+__device__ __forceinline__ void small_block_sum(double (&v)[NV], double *red) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        double x = v[i];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        v[i] = x;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) red[wave * NV + i] = v[i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            double t = 0.0;
+            for (int w = 0; w < kSmallThreads / 64; ++w) t += red[w * NV + i];
+            v[i] = t;
+        }
+    }
+}
+
+template <int CPC, bool TR>
+__global__ void __launch_bounds__(kSmallThreads) small_kernel(LaunchSets ls) {
+    const SetDesc &d = ls.desc[blockIdx.x];
+    SolveState *st_ = d.st;
+    const int nx = d.nx, ny = d.ny, nz = d.nz, P = d.plane, n = d.n;
+    __shared__ double op[kSmallMaxCells];
+    __shared__ double red[(kSmallThreads / 64) * 4];
+    const double *a[7];
+    for (int q = 0; q < 7; ++q) a[q] = d.a[q];
+    const double *bp = d.b;
+    double *xp = d.x, *rhp = d.rh;
+    const int tid = threadIdx.x;
+
+    // r, p, v and t of this thread's cells stay in registers; x, r^ and the
+    // coefficients are read from L2 (the whole set is L2-resident) when needed
+    double r[CPC], p[CPC], v[CPC], t[CPC];
+#pragma unroll
+    for (int m = 0; m < CPC; ++m) p[m] = v[m] = t[m] = r[m] = 0.0;
+    auto valid = [&](int m) { return tid + kSmallThreads * m < n; };
+    // A applied to the operand held in op[] at cell c of the m-th slot
+    auto stencil = [&](int m) {
+        const int c = min(tid + kSmallThreads * m, n - 1);
+        const int k = c / P, q = c - k * P, j = q / nx, i = q - j * nx;
+        const Nb nb{i + 1 < nx, i > 0, j + 1 < ny, j > 0};
+        const bool up = k + 1 < nz, dn = k > 0;
+        Coef6<double, TR> cf;
+        cf.load(a, c, nx, P, n, nb, up, dn);
+        const double xE = nb.e ? op[c + 1] : 0.0, xW = nb.w ? op[c - 1] : 0.0;
+        const double xN = nb.n ? op[c + nx] : 0.0, xS = nb.s ? op[c - nx] : 0.0;
+        const double xT = up ? op[c + P] : 0.0, xB = dn ? op[c - P] : 0.0;
+        return cf.apply(ld(a[0], c), op[c], xE, xW, xN, xS, xT, xB);
+    };
+    auto diag = [&](int m) { return ld(a[0], min(tid + kSmallThreads * m, n - 1)); };
+    // r = b - A x with setup semantics (mode 0), recheck (1) or report (2)
+    auto residual = [&](int mode) {
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < CPC; ++m)
+            if (valid(m)) op[tid + kSmallThreads * m] = ld(xp, tid + kSmallThreads * m);
+        __syncthreads();
+        double acc[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int m = 0; m < CPC; ++m) {
+            if ((m & 3) == 0) __builtin_amdgcn_sched_barrier(0);
+            if (!valid(m)) continue;
+            const int c = tid + kSmallThreads * m;
+            const double bv = ld(bp, c), apv = ld(a[0], c);
+            const double rv = bv - stencil(m);
+            if (mode != 2) {
+                r[m] = rv;
+                st(rhp, c, rv);
+            }
+            acc[0] += bv * bv;
+            acc[1] += rv * rv;
+            acc[2] += (apv == 0.0 || !isfinite(apv)) ? 1.0 : 0.0;
+        }
+        small_block_sum<3>(acc, red);
+        if (tid == 0) {
+            if (mode == 0) FinSetup{&d}(st_, acc);
+            else if (mode == 1) FinRecheck{}(st_, acc);
+            else FinReport{}(st_, acc);
+        }
+        __syncthreads();
+    };
+
+    residual(0);
+    const long guard = 4l * (long)d.maxit + 16;
+    for (long turn = 0; turn < guard; ++turn) {
+        // keep the coefficient loads inside the loop (re-read from L2 each pass)
+        // rather than hoisted into registers for all cells
+        __asm__ volatile("" ::: "memory");
+        if (st_->done) break;
+        if (st_->converged) { residual(1); continue; }
+        if (st_->need_report) { residual(2); continue; }
+        if (!st_->active) break;
+        // K1: p update, p^ = p / a_P into LDS, v = A p^, (r^, v)
+        const bool fresh = st_->fresh != 0;
+        const double beta = (st_->rho / st_->rho_prev) * (st_->alpha / st_->omega), omega0 = st_->omega;
+#pragma unroll
+        for (int m = 0; m < CPC; ++m) {
+            p[m] = fresh ? r[m] : fma(beta, fma(-omega0, v[m], p[m]), r[m]);
+            if (valid(m)) {
+                op[tid + kSmallThreads * m] = p[m] / diag(m);
+                if (fresh) st(rhp, tid + kSmallThreads * m, r[m]);
+            }
+        }
+        __syncthreads();
+        double a1[1] = {0.0};
+#pragma unroll
+        for (int m = 0; m < CPC; ++m) {
+            if (valid(m)) {
+                v[m] = stencil(m);
+                a1[0] += ld(rhp, tid + kSmallThreads * m) * v[m];
+            }
+            if ((m & 3) == 3) __builtin_amdgcn_sched_barrier(0);  // bound the loads in flight (registers)
+        }
+        small_block_sum<1>(a1, red);
+        if (tid == 0) FinK1{}(st_, a1);
+        __syncthreads();
+        if (!st_->active) continue;
+        // K2: s = r - alpha v, s^ into LDS (after every thread has read p^), t = A s^
+        const double alpha = st_->alpha;
+#pragma unroll
+        for (int m = 0; m < CPC; ++m)
+            if (valid(m)) op[tid + kSmallThreads * m] = fma(-alpha, v[m], r[m]) / diag(m);
+        __syncthreads();
+        double a2[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int m = 0; m < CPC; ++m) {
+            if (valid(m)) {
+                const double sv = fma(-alpha, v[m], r[m]);
+                t[m] = stencil(m);
+                a2[0] += t[m] * sv;
+                a2[1] += t[m] * t[m];
+                a2[2] += sv * sv;
+            }
+            if ((m & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+        }
+        small_block_sum<3>(a2, red);
+        if (tid == 0) FinK2{}(st_, a2);
+        __syncthreads();
+        if (!st_->active) continue;
+        // K3: x += alpha p^ + omega s^, r = s - omega t, (r^, r), (r, r)
+        const double om = st_->omega;
+        double a3[2] = {0.0, 0.0};
+#pragma unroll
+        for (int m = 0; m < CPC; ++m) {
+            if (!valid(m)) continue;
+            const int c = tid + kSmallThreads * m;
+            const double apv = diag(m), sv = fma(-alpha, v[m], r[m]);
+            st(xp, c, ld(xp, c) + fma(alpha, p[m] / apv, om * (sv / apv)));
+            r[m] = fma(-om, t[m], sv);
+            a3[0] += ld(rhp, c) * r[m];
+            a3[1] += r[m] * r[m];
+        }
+        small_block_sum<2>(a3, red);
+        if (tid == 0) FinK3{}(st_, a3);
+        __syncthreads();
+    }
+    if (st_->zero_rhs) {
+#pragma unroll
+        for (int m = 0; m < CPC; ++m)
+            if (valid(m)) st(xp, tid + kSmallThreads * m, 0.0);
+    }
+}
+
+// p[0..n) = v (synthetic systems for the tuner)
+__global__ void __launch_bounds__(kBlock) fill_kernel(double *p, long n, double v) {
+    for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) p[i] = v;
+}
+
 // ------------------------------------------------------------------ host launchers
+
+hipError_t launch_small(const LaunchSets &ls, int max_n, bool trans, hipStream_t stream) {
+    const dim3 grid(ls.nsets), block(kSmallThreads);
+    const int cpc = (max_n + kSmallThreads - 1) / kSmallThreads;
+    if (max_n > kSmallMaxCells || cpc < 1) return hipErrorInvalidValue;
+    if (cpc == 1) {
+        if (trans) hipLaunchKernelGGL((small_kernel<1, true>), grid, block, 0, stream, ls);
+        else hipLaunchKernelGGL((small_kernel<1, false>), grid, block, 0, stream, ls);
+    } else if (cpc == 2) {
+        if (trans) hipLaunchKernelGGL((small_kernel<2, true>), grid, block, 0, stream, ls);
+        else hipLaunchKernelGGL((small_kernel<2, false>), grid, block, 0, stream, ls);
+    } else if (cpc <= 4) {
+        if (trans) hipLaunchKernelGGL((small_kernel<4, true>), grid, block, 0, stream, ls);
+        else hipLaunchKernelGGL((small_kernel<4, false>), grid, block, 0, stream, ls);
+    } else {
+        if (trans) hipLaunchKernelGGL((small_kernel<8, true>), grid, block, 0, stream, ls);
+        else hipLaunchKernelGGL((small_kernel<8, false>), grid, block, 0, stream, ls);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(double *p, long n, double v, hipStream_t stream) {
+    hipLaunchKernelGGL(fill_kernel, dim3(2048), dim3(kBlock), 0, stream, p, n, v);
+    return hipGetLastError();
+}
 
 size_t march_lds_bytes(int cpt, int max_nx, int elem) {
     return (size_t)3 * (size_t)(kBlock * cpt + 2 * max_nx) * (size_t)elem;
@@ -1042,15 +1358,20 @@ hipError_t launch_kernel(Kern k, const LaunchSets &ls, int ntiles, int nflat, in
     if (h < 0 || (cpt != 1 && cpt != 2)) return hipErrorInvalidValue;
     const size_t lds64 = march_lds_bytes(cpt, max_nx, 8), lds32 = march_lds_bytes(cpt, max_nx, 4);
     switch (k) {
-    case K_K1:
-        if (fp32) EQS_DISPATCH(cpt, h, hipLaunchKernelGGL((k1_kernel<float, C, HH, false>), grid, block, lds32, stream, ls));
-        else if (trans) EQS_DISPATCH(cpt, h, hipLaunchKernelGGL((k1_kernel<double, C, HH, true>), grid, block, lds64, stream, ls));
-        else EQS_DISPATCH(cpt, h, hipLaunchKernelGGL((k1_kernel<double, C, HH, false>), grid, block, lds64, stream, ls));
+    case K_K1:  // the scaled operator needs no transpose variant
+        if (fp32) EQS_DISPATCH(cpt, h, hipLaunchKernelGGL((k1_kernel<float, C, HH>), grid, block, lds32, stream, ls));
+        else EQS_DISPATCH(cpt, h, hipLaunchKernelGGL((k1_kernel<double, C, HH>), grid, block, lds64, stream, ls));
         break;
     case K_K2:
-        if (fp32) EQS_DISPATCH(cpt, h, hipLaunchKernelGGL((k2_kernel<float, C, HH, false>), grid, block, lds32, stream, ls));
-        else if (trans) EQS_DISPATCH(cpt, h, hipLaunchKernelGGL((k2_kernel<double, C, HH, true>), grid, block, lds64, stream, ls));
-        else EQS_DISPATCH(cpt, h, hipLaunchKernelGGL((k2_kernel<double, C, HH, false>), grid, block, lds64, stream, ls));
+        if (fp32) EQS_DISPATCH(cpt, h, hipLaunchKernelGGL((k2_kernel<float, C, HH>), grid, block, lds32, stream, ls));
+        else EQS_DISPATCH(cpt, h, hipLaunchKernelGGL((k2_kernel<double, C, HH>), grid, block, lds64, stream, ls));
+        break;
+    case K_SCALE:
+        if (trans) hipLaunchKernelGGL((scale_kernel<true>), fgrid, block, 0, stream, ls);
+        else hipLaunchKernelGGL((scale_kernel<false>), fgrid, block, 0, stream, ls);
+        break;
+    case K_UNSCALE:
+        hipLaunchKernelGGL(unscale_kernel, fgrid, block, 0, stream, ls);
         break;
     case K_K3:
         if (fp32) hipLaunchKernelGGL((k3_kernel<float>), fgrid, block, 0, stream, ls);

@@ -20,7 +20,9 @@ enum Kern {
     K_UPDATE,   // x += d / scale (FP32 forms)
     K_ZERO,     // x = 0 (b = 0, or forced)
     K_GRAD,     // adjoint gradients
-    K_APPLY     // y = A x or A^T x
+    K_APPLY,    // y = A x or A^T x
+    K_SCALE,    // coefficients of A D^-1 (or A^T D^-1), FP64
+    K_UNSCALE   // x = y / a_P (before a recheck or a final report)
 };
 
 // LDS bytes of a march kernel (three plane buffers of Q + 2 nx values)
@@ -28,6 +30,16 @@ size_t march_lds_bytes(int cpt, int max_nx, int elem);
 
 // halo cells per thread per plane (1, 2, 4 or 8), or -1 if nx is too wide
 int halo_slots(int max_nx);
+
+// cells of the largest set the one-block persistent solve takes
+constexpr int kSmallSolveMaxCells = 4096;
+
+// one-block persistent FP64 solve of every set of the launch table (each
+// at most kSmallSolveMaxCells cells): one block per set, one launch
+hipError_t launch_small(const LaunchSets &ls, int max_n, bool trans, hipStream_t stream);
+
+// p[0..n) = v on `stream`
+hipError_t launch_fill(double *p, long n, double v, hipStream_t stream);
 
 // Launch kernel k: march kernels over ntiles blocks (the sum of the sets'
 // tile counts), pointwise kernels over nflat blocks (the sum of their nflat).

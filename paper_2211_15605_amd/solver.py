@@ -93,6 +93,14 @@ class Context:
         keys = ("cpt", "segments", "kc", "chunks", "tiles", "readbacks")
         return dict(zip(keys, v))
 
+    def autotune(self, cache_path=None, iters=6):
+        """Choose every set's launch shape by timing candidates on synthetic systems of the
+        same shapes (see eqsolve_autotune); returns the new layouts."""
+        rc = B.eqsolve_autotune(self.h, cache_path, iters)
+        if rc != 0:
+            raise EqSolveError(rc, "eqsolve_autotune")
+        return [self.layout(s) for s in range(len(self.grids))]
+
     def profile(self, kinds=("k1",), every=1):
         """Time every `every`-th launch of the given kernel kinds with HIP events on this
         context's stream (resets the totals); an empty list turns timing off."""

@@ -63,7 +63,11 @@ def abs_terms(orc, shape, diags, x):
 
 SHAPES = [(16, 16, 16), (33, 17, 9), (97, 31, 5), (1, 1, 7), (5, 1, 1), (1, 300, 2), (130, 3, 40),
           (64, 64, 4), (200, 7, 3)]
-TILINGS = [dict(), dict(EQS_CPT=1, EQS_KC=1), dict(EQS_CPT=4, EQS_KC=3), dict(EQS_CPT=2, EQS_KC=7)]
+# launch shapes of the multi-kernel path (EQS_SMALL=0 keeps tiny grids off the one-block path)
+TILINGS = [dict(EQS_SMALL=0), dict(EQS_SMALL=0, EQS_CPT=1, EQS_KC=1), dict(EQS_SMALL=0, EQS_CPT=2, EQS_KC=3),
+           dict(EQS_SMALL=0, EQS_CPT=2, EQS_KC=7)]
+# both solve paths (the one-block persistent solve takes sets of at most 4096 cells by default)
+PATHS = [dict(), dict(EQS_SMALL=0)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
@@ -113,7 +117,7 @@ def test_fp64_matches_oracle_solution(torch_dev, orc, cfg, shape):
     g, diags, b, xs = manufactured(orc, cfg, grid=W.Grid(*shape))
     xo, oinfo = orc.bicgstab(g.shape, diags, b, tol=1e-13, maxit=5000)
     assert oinfo["status"] == 0
-    for tl in TILINGS[:3]:
+    for tl in [dict()] + TILINGS[:3]:
         ctx = context([g.shape], env=tl)
         x, info = ctx.solve(dev_arrays(torch, dev, diags), dev_arrays(torch, dev, [b])[0], tol=1e-13, maxit=5000)
         xg = host(x)
@@ -134,11 +138,54 @@ def test_fp64_repeatable_bitwise(torch_dev, orc):
         assert np.array_equal(o, outs[0])
 
 
-def test_fp64_status_codes(torch_dev, orc):
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+def test_graph_replay_equals_eager_launches(torch_dev, orc, precision):
+    # captured iteration chunks are replayed many times, with other device work and
+    # synchronisations between calls; every result must equal the eager path's bit for bit
+    torch, dev = torch_dev
+    g, diags, b, _ = manufactured(orc, 2, grid=W.Grid(33, 65, 20))
+    D = dev_arrays(torch, dev, diags)
+    bd = dev_arrays(torch, dev, [b])[0]
+    eager = context([g.shape], precision=precision, env=dict(EQS_GRAPHS=0))
+    ref, rinfo = eager.solve(D, bd, tol=1e-11, maxit=3000)
+    ref = host(ref)
+    graphed = context([g.shape], precision=precision)
+    for rep in range(4):
+        junk = torch.randn(1 << 20, device=dev, dtype=torch.float64).cumsum(0)  # unrelated eager work
+        torch.cuda.synchronize()
+        x, info = graphed.solve(D, bd, tol=1e-11, maxit=3000)
+        assert np.array_equal(host(x), ref), rep
+        assert info == rinfo
+        del junk
+
+
+def test_autotune_and_cache_roundtrip(torch_dev, orc, tmp_path):
+    torch, dev = torch_dev
+    g, diags, b, _ = manufactured(orc, 0, grid=W.Grid(40, 48, 24))
+    D = dev_arrays(torch, dev, diags)
+    bd = dev_arrays(torch, dev, [b])[0]
+    cache = str(tmp_path / "tune.jsonl")
+    ctx = context([g.shape])
+    lay = ctx.autotune(cache_path=cache, iters=4)[0]
+    x, info = ctx.solve(D, bd, tol=1e-10, maxit=2000)
+    assert orc.rel_residual(g.shape, diags, b, host(x)) <= 1e-10
+    lines = open(cache).read().strip().splitlines()
+    assert len(lines) == 1 and '"nx": 40' in lines[0]
+    # a new context picks the tuned shape from the cache
+    ctx2 = context([g.shape], env=dict(EQS_TUNE_CACHE=cache))
+    lay2 = ctx2.layout()
+    for k in ("cpt", "kc", "tiles"):
+        assert lay2[k] == lay[k], (lay, lay2)
+    x2, info2 = ctx2.solve(D, bd, tol=1e-10, maxit=2000)
+    assert np.array_equal(host(x2), host(x))
+
+
+@pytest.mark.parametrize("path", PATHS, ids=["default", "multikernel"])
+def test_fp64_status_codes(torch_dev, orc, path):
     torch, dev = torch_dev
     from paper_2211_15605_amd.solver import EqSolveError
     g, diags, b, xs = manufactured(orc, 0, grid=W.Grid(6, 6, 6))
-    ctx = context([g.shape])
+    ctx = context([g.shape], env=path)
     D = dev_arrays(torch, dev, diags)
     bd, xsd = dev_arrays(torch, dev, [b, xs])
     # maxit too small: computed, not converged
@@ -168,24 +215,26 @@ def test_fp64_status_codes(torch_dev, orc):
         ctx.solve(D, bd, tol=0.0)
 
 
-def test_fp64_diagonal_system_one_half_step(torch_dev, orc):
+@pytest.mark.parametrize("path", PATHS, ids=["default", "multikernel"])
+def test_fp64_diagonal_system_one_half_step(torch_dev, orc, path):
     torch, dev = torch_dev
     g = W.Grid(9, 8, 7)
     rng = np.random.default_rng(6)
     P = rng.uniform(1, 3, g.n)
     diags = [P] + [np.zeros(g.n)] * 6
     b = rng.uniform(-1, 1, g.n)
-    ctx = context([g.shape])
+    ctx = context([g.shape], env=path)
     x, info = ctx.solve(dev_arrays(torch, dev, diags), dev_arrays(torch, dev, [b])[0], tol=1e-12, maxit=10)
     assert info["status"] == 0 and info["iters"] == 1
     np.testing.assert_allclose(host(x), b / P, rtol=4 * EPS, atol=0)
 
 
-def test_fp64_breakdown_integer_system(torch_dev, orc):
+@pytest.mark.parametrize("path", PATHS, ids=["default", "multikernel"])
+def test_fp64_breakdown_integer_system(torch_dev, orc, path):
     torch, dev = torch_dev
     z = np.zeros(2)
     diags = [np.ones(2), np.array([2.0, 0.0]), z, z, z, z, z]
-    ctx = context([(2, 1, 1)])
+    ctx = context([(2, 1, 1)], env=path)
     x, info = ctx.solve(dev_arrays(torch, dev, diags), dev_arrays(torch, dev, [np.ones(2)])[0], tol=1e-10,
                         maxit=10, check=False)
     _, oinfo = orc.bicgstab((2, 1, 1), diags, np.ones(2), tol=1e-10, maxit=10)
@@ -240,7 +289,25 @@ def test_batched_equals_sequential_bitwise(torch_dev, orc, precision):
         assert orc.rel_residual(s[0].shape, s[1], s[2], host(xb[i])) <= 1e-10
 
 
-def test_adjoint_matches_dense_reference(torch_dev, orc):
+def test_batched_tiny_sets_one_launch(torch_dev, orc):
+    # four tiny staggered sets: one block per set, each equal to its own solve
+    torch, dev = torch_dev
+    shapes = [(10, 20, 10), (11, 20, 10), (10, 21, 10), (10, 20, 11)]
+    systems = [manufactured(orc, 2, grid=W.Grid(*sh), set_id=i) for i, sh in enumerate(shapes)]
+    ctx = context(shapes)
+    Ds = [dev_arrays(torch, dev, s[1]) for s in systems]
+    bs = [dev_arrays(torch, dev, [s[2]])[0] for s in systems]
+    xb, infos = ctx.solve_batched(Ds, bs, tol=1e-12, maxit=2000)
+    for i, s in enumerate(systems):
+        xi, info = ctx.solve(Ds[i], bs[i], tol=1e-12, maxit=2000, set_id=i)
+        assert np.array_equal(host(xi), host(xb[i])) and info == infos[i]
+        assert orc.rel_residual(s[0].shape, s[1], s[2], host(xb[i])) <= 1e-12
+        xo, _ = orc.bicgstab(s[0].shape, s[1], s[2], tol=1e-13)
+        assert np.linalg.norm(host(xb[i]) - xo) <= 1e-9 * np.linalg.norm(xo)
+
+
+@pytest.mark.parametrize("path", PATHS, ids=["default", "multikernel"])
+def test_adjoint_matches_dense_reference(torch_dev, orc, path):
     torch, dev = torch_dev
     g = W.Grid(8, 8, 8)
     s = W.make_set(3, 0, grid=g, with_weights=True)
@@ -250,7 +317,7 @@ def test_adjoint_matches_dense_reference(torch_dev, orc):
     x = np.linalg.solve(A, b)
     lam = np.linalg.solve(A.T, w)
     G = orc.grad(g.shape, lam, x)
-    ctx = context([g.shape])
+    ctx = context([g.shape], env=path)
     D = dev_arrays(torch, dev, diags)
     xd, wd = dev_arrays(torch, dev, [x, w])
     gb, gd, info = ctx.adjoint(D, xd, wd, tol=1e-13, maxit=1000)
