@@ -246,14 +246,14 @@ struct Run {
             c->ev_used += 2;
             c->ev_kind.push_back(kind);
             c->ev_pos.push_back(pos);
-            EQS_HIP(hipEventRecord(e0, c->stream));
         }
-        if (launch_kernel(k, ls, ntiles, nflat, c->cpt, max_nx, f32, trans, c->stream, x, y, arg) != hipSuccess) {
+        // a timed launch carries the events itself: they take the kernel's own start and end
+        if (launch_kernel(k, ls, ntiles, nflat, c->cpt, max_nx, f32, trans, c->stream, x, y, arg, e0, e1) !=
+            hipSuccess) {
             (void)hipGetLastError();
             c->broken = true;
             return EQS_ERR_HIP;
         }
-        if (timed) EQS_HIP(hipEventRecord(e1, c->stream));
         return 0;
     }
     int readback() {

@@ -32,6 +32,7 @@
 // overlap, then share that XCD's L2.
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <math.h>
 
 #include "eqs_internal.h"
@@ -1351,58 +1352,68 @@ int halo_slots(int max_nx) {
         }                                                                            \
     } while (0)
 
+// With a start/stop event pair the launch goes through hipExtLaunchKernel, which
+// stamps the events with the dispatch's own start and end times (the kernel's
+// duration alone, as a kernel trace reports it); such launches are never captured.
+#define EQS_LAUNCH(KERN, GRID, BLOCK, LDS, ...)                                                  \
+    do {                                                                                         \
+        if (e0) hipExtLaunchKernelGGL(KERN, GRID, BLOCK, LDS, stream, e0, e1, 0u, __VA_ARGS__); \
+        else hipLaunchKernelGGL(KERN, GRID, BLOCK, LDS, stream, __VA_ARGS__);                   \
+    } while (0)
+
 hipError_t launch_kernel(Kern k, const LaunchSets &ls, int ntiles, int nflat, int cpt, int max_nx, bool fp32,
-                         bool trans, hipStream_t stream, const double *x, double *y, int arg) {
+                         bool trans, hipStream_t stream, const double *x, double *y, int arg, hipEvent_t e0,
+                         hipEvent_t e1) {
     const dim3 grid(ntiles), fgrid(nflat), block(kBlock);
     const int h = halo_slots(max_nx);
     if (h < 0 || (cpt != 1 && cpt != 2)) return hipErrorInvalidValue;
     const size_t lds64 = march_lds_bytes(cpt, max_nx, 8), lds32 = march_lds_bytes(cpt, max_nx, 4);
     switch (k) {
     case K_K1:  // the scaled operator needs no transpose variant
-        if (fp32) EQS_DISPATCH(cpt, h, hipLaunchKernelGGL((k1_kernel<float, C, HH>), grid, block, lds32, stream, ls));
-        else EQS_DISPATCH(cpt, h, hipLaunchKernelGGL((k1_kernel<double, C, HH>), grid, block, lds64, stream, ls));
+        if (fp32) EQS_DISPATCH(cpt, h, EQS_LAUNCH((k1_kernel<float, C, HH>), grid, block, lds32, ls));
+        else EQS_DISPATCH(cpt, h, EQS_LAUNCH((k1_kernel<double, C, HH>), grid, block, lds64, ls));
         break;
     case K_K2:
-        if (fp32) EQS_DISPATCH(cpt, h, hipLaunchKernelGGL((k2_kernel<float, C, HH>), grid, block, lds32, stream, ls));
-        else EQS_DISPATCH(cpt, h, hipLaunchKernelGGL((k2_kernel<double, C, HH>), grid, block, lds64, stream, ls));
+        if (fp32) EQS_DISPATCH(cpt, h, EQS_LAUNCH((k2_kernel<float, C, HH>), grid, block, lds32, ls));
+        else EQS_DISPATCH(cpt, h, EQS_LAUNCH((k2_kernel<double, C, HH>), grid, block, lds64, ls));
         break;
     case K_SCALE:
-        if (trans) hipLaunchKernelGGL((scale_kernel<true>), fgrid, block, 0, stream, ls);
-        else hipLaunchKernelGGL((scale_kernel<false>), fgrid, block, 0, stream, ls);
+        if (trans) EQS_LAUNCH((scale_kernel<true>), fgrid, block, 0, ls);
+        else EQS_LAUNCH((scale_kernel<false>), fgrid, block, 0, ls);
         break;
     case K_UNSCALE:
-        hipLaunchKernelGGL(unscale_kernel, fgrid, block, 0, stream, ls);
+        EQS_LAUNCH(unscale_kernel, fgrid, block, 0, ls);
         break;
     case K_K3:
-        if (fp32) hipLaunchKernelGGL((k3_kernel<float>), fgrid, block, 0, stream, ls);
-        else hipLaunchKernelGGL((k3_kernel<double>), fgrid, block, 0, stream, ls);
+        if (fp32) EQS_LAUNCH((k3_kernel<float>), fgrid, block, 0, ls);
+        else EQS_LAUNCH((k3_kernel<double>), fgrid, block, 0, ls);
         break;
     case K_SETUP:
     case K_RECHECK:
     case K_REPORT: {
         const int mode = k == K_SETUP ? 0 : (k == K_RECHECK ? 1 : 2);
-        if (trans) EQS_DISPATCH(cpt, h, hipLaunchKernelGGL((res_kernel<C, HH, true>), grid, block, lds64, stream, ls, mode));
-        else EQS_DISPATCH(cpt, h, hipLaunchKernelGGL((res_kernel<C, HH, false>), grid, block, lds64, stream, ls, mode));
+        if (trans) EQS_DISPATCH(cpt, h, EQS_LAUNCH((res_kernel<C, HH, true>), grid, block, lds64, ls, mode));
+        else EQS_DISPATCH(cpt, h, EQS_LAUNCH((res_kernel<C, HH, false>), grid, block, lds64, ls, mode));
         break;
     }
     case K_OUTER:
-        EQS_DISPATCH(cpt, h, hipLaunchKernelGGL((outer_kernel<C, HH>), grid, block, lds64, stream, ls));
+        EQS_DISPATCH(cpt, h, EQS_LAUNCH((outer_kernel<C, HH>), grid, block, lds64, ls));
         break;
     case K_CAST:
-        hipLaunchKernelGGL(cast_kernel, fgrid, block, 0, stream, ls);
+        EQS_LAUNCH(cast_kernel, fgrid, block, 0, ls);
         break;
     case K_UPDATE:
-        hipLaunchKernelGGL(update_kernel, fgrid, block, 0, stream, ls);
+        EQS_LAUNCH(update_kernel, fgrid, block, 0, ls);
         break;
     case K_ZERO:
-        hipLaunchKernelGGL(zero_kernel, fgrid, block, 0, stream, ls, arg);
+        EQS_LAUNCH(zero_kernel, fgrid, block, 0, ls, arg);
         break;
     case K_GRAD:
-        hipLaunchKernelGGL(grad_kernel, fgrid, block, 0, stream, ls);
+        EQS_LAUNCH(grad_kernel, fgrid, block, 0, ls);
         break;
     case K_APPLY:
-        if (trans) EQS_DISPATCH(cpt, h, hipLaunchKernelGGL((apply_kernel<C, HH, true>), grid, block, lds64, stream, ls, x, y));
-        else EQS_DISPATCH(cpt, h, hipLaunchKernelGGL((apply_kernel<C, HH, false>), grid, block, lds64, stream, ls, x, y));
+        if (trans) EQS_DISPATCH(cpt, h, EQS_LAUNCH((apply_kernel<C, HH, true>), grid, block, lds64, ls, x, y));
+        else EQS_DISPATCH(cpt, h, EQS_LAUNCH((apply_kernel<C, HH, false>), grid, block, lds64, ls, x, y));
         break;
     }
     return hipGetLastError();

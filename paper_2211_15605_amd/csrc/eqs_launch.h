@@ -43,7 +43,10 @@ hipError_t launch_fill(double *p, long n, double v, hipStream_t stream);
 
 // Launch kernel k: march kernels over ntiles blocks (the sum of the sets'
 // tile counts), pointwise kernels over nflat blocks (the sum of their nflat).
+// A non-null e0/e1 pair receives the kernel's own start and end timestamps
+// (not for use under stream capture).
 hipError_t launch_kernel(Kern k, const LaunchSets &ls, int ntiles, int nflat, int cpt, int max_nx, bool fp32,
-                         bool trans, hipStream_t stream, const double *x, double *y, int arg);
+                         bool trans, hipStream_t stream, const double *x, double *y, int arg,
+                         hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
 }  // namespace eqs
