@@ -32,6 +32,11 @@ HBM_PEAK_GBS = 8000.0
 # column-scaled operator: K1 r, p, v, 6 coefficients, r^ / p, v; K2 r, v, 6 coefficients / t;
 # K3 y, p, r, v, t, r^ / y, r  (29 words per iteration)
 WORDS = {"k1": 12, "k2": 9, "k3": 8}
+# the single-sync step (one launch): reads s, t, p, v of the previous step, y, r^, f and six
+# coefficients; writes y, p, v, s, t (18 words per cell and step)
+WORDS["fused"] = 18
+# algorithmic HBM words per cell-iteration of each iteration scheme (reductions per step -> words)
+STEP_WORDS = {1: 18, 3: 29}
 
 
 def kernel_source_digest():
@@ -42,11 +47,11 @@ def kernel_source_digest():
     return h.hexdigest()
 
 
-def measured_traffic(cfg):
-    """HBM bytes per FP64 K1 launch from the committed rocprofv3 counter record
-    (FETCH_SIZE + WRITE_SIZE, scaled by a 1 GiB copy), or None when the kernel
-    source has changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "k1_fp64_sym128x256x128_traffic.json")
+def measured_traffic(cfg, kern):
+    """HBM bytes per launch of the FP64 iteration kernel `kern` from the committed
+    rocprofv3 counter record (FETCH_SIZE + WRITE_SIZE, scaled by a 1 GiB copy), or
+    None when the kernel source has changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "%s_fp64_sym128x256x128_traffic.json" % kern)
     if cfg != 1 or not os.path.exists(path):
         return None
     rec = json.load(open(path))
@@ -94,9 +99,12 @@ def gpu_leg(args):
 
     for _ in range(args.warmup):
         step(None)
-    # HIP events around every 8th K1 launch of the timed FP64 solves (sampling keeps the
-    # events' own cost out of the measured solve time)
-    c64.profile(["k1"], every=8)
+    # the dominant kernel: the fused step (single-sync iteration) or K1 (three launches per step)
+    syncs = c64.layout()["syncs"]
+    kern = "fused" if syncs == 1 else "k1"
+    # the kernel's own start and end stamps on every 8th launch of the timed FP64 solves
+    # (sampling keeps the timing's own cost out of the measured solve time)
+    c64.profile([kern], every=8)
     rec = []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
@@ -111,30 +119,34 @@ def gpu_leg(args):
     it64 = float(np.mean([r[2]["iters"] for r in rec]))
     it32 = float(np.mean([r[3]["iters"] for r in rec]))
     kstats = {}
-    for k in ("k1",):
+    for k in (kern,):
         cnt, ms = c64.kernel_stats(k)
         if cnt:
             kstats[k] = (cnt, ms)
     # the library counts only launches that did work (not the few enqueued past convergence)
-    k1_cnt, k1_ms = kstats["k1"]
+    k1_cnt, k1_ms = kstats[kern]
     k1_avg_ms = k1_ms / k1_cnt
-    k1_bytes = WORDS["k1"] * 8 * n
+    k1_bytes = WORDS[kern] * 8 * n
     achieved = k1_bytes / (k1_avg_ms * 1e-3) / 1e9
+    sw = STEP_WORDS[syncs]
     err64 = float(torch.max(torch.abs(x64 - xs)))
     err32 = float(torch.max(torch.abs(x32 - xs)))
     res = {
         "value": n * it64 / t64,
         "ms_per_step": 1e3 * t_total / args.steps,
         "fp64": {"time_to_tol_ms": 1e3 * t64, "iters": it64, "rel_res": rec[-1][2]["rel_res"],
-                 "cell_iters_per_s": n * it64 / t64, "model_GBps": n * it64 * 232 / t64 / 1e9,
+                 "cell_iters_per_s": n * it64 / t64, "model_GBps": n * it64 * sw * 8 / t64 / 1e9,
                  "max_abs_err_vs_xstar": err64},
         "fp32_refine": {"time_to_tol_ms": 1e3 * t32, "inner_iters": it32, "outer": rec[-1][3]["outer"],
                         "rel_res": rec[-1][3]["rel_res"], "cell_iters_per_s": n * it32 / t32,
-                        "model_GBps": n * it32 * 116 / t32 / 1e9, "max_abs_err_vs_xstar": err32,
+                        "model_GBps": n * it32 * sw * 4 / t32 / 1e9, "max_abs_err_vs_xstar": err32,
                         "speedup_vs_fp64": t64 / t32},
-        "roofline": {"bound": "hbm", "kernel": "k1_fp64", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.config),
-                     "bytes_per_launch": k1_bytes, "mean_launch_ms": k1_avg_ms, "launches": k1_cnt},
+        "roofline": {"bound": "hbm", "kernel": kern + "_fp64", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(args.config, kern),
+                     "bytes_per_launch": k1_bytes, "words_per_cell": WORDS[kern], "mean_launch_ms": k1_avg_ms,
+                     "launches": k1_cnt},
+        "syncs_per_iteration": syncs,
         "kernels_fp64_ms": {k: {"launches": v[0], "mean_ms": v[1] / v[0]} for k, v in kstats.items()},
         "layout": c64.layout(),
         "cells": n,
@@ -195,7 +207,10 @@ def gpu_leg_batched(args):
 
     for _ in range(args.warmup):
         step(None)
-    c64.profile(["k1"], every=1)
+    syncs = c64.layout()["syncs"]
+    kern = "fused" if syncs == 1 else "k1"
+    sw = STEP_WORDS[syncs]
+    c64.profile([kern], every=1)
     rec = []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
@@ -203,7 +218,7 @@ def gpu_leg_batched(args):
         x64, x32 = step(rec)
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
-    k1_cnt, k1_ms = c64.kernel_stats("k1")
+    k1_cnt, k1_ms = c64.kernel_stats(kern)
     c64.profile([])
     # the same sets one after another (plain FP64, the comparison the batched forms are measured against)
     seq = []
@@ -218,7 +233,7 @@ def gpu_leg_batched(args):
     t32 = float(np.mean([r[1] for r in rec]))
     ci64 = sum(n * inf["iters"] for n, inf in zip(n_all, rec[-1][2]))
     ci32 = sum(n * inf["iters"] for n, inf in zip(n_all, rec[-1][3]))
-    k1_bytes_total = sum(WORDS["k1"] * 8 * n * inf["iters"] for n, inf in zip(n_all, rec[-1][2])) * len(rec)
+    k1_bytes_total = sum(WORDS[kern] * 8 * n * inf["iters"] for n, inf in zip(n_all, rec[-1][2])) * len(rec)
     achieved = k1_bytes_total / (k1_ms * 1e-3) / 1e9
     err64 = max(float(torch.max(torch.abs(x - xs))) for x, xs in zip(x64, xss))
     res = {
@@ -226,19 +241,20 @@ def gpu_leg_batched(args):
         "ms_per_step": 1e3 * t_total / args.steps,
         "fp64": {"time_to_tol_ms": 1e3 * t64, "iters": [i["iters"] for i in rec[-1][2]],
                  "rel_res": [i["rel_res"] for i in rec[-1][2]], "cell_iters_per_s": ci64 / t64,
-                 "model_GBps": ci64 * 232 / t64 / 1e9, "max_abs_err_vs_xstar": err64,
+                 "model_GBps": ci64 * sw * 8 / t64 / 1e9, "max_abs_err_vs_xstar": err64,
                  "sequential_time_to_tol_ms": 1e3 * float(np.mean(seq)),
                  "batched_speedup_vs_sequential": float(np.mean(seq)) / t64},
         "fp32_refine": {"time_to_tol_ms": 1e3 * t32, "inner_iters": [i["iters"] for i in rec[-1][3]],
                         "outer": [i["outer"] for i in rec[-1][3]], "rel_res": [i["rel_res"] for i in rec[-1][3]],
-                        "cell_iters_per_s": ci32 / t32, "model_GBps": ci32 * 116 / t32 / 1e9,
+                        "cell_iters_per_s": ci32 / t32, "model_GBps": ci32 * sw * 4 / t32 / 1e9,
                         "speedup_vs_fp64_batched": t64 / t32,
                         "speedup_vs_fp64_sequential": float(np.mean(seq)) / t32},
-        "roofline": {"bound": "hbm", "kernel": "k1_fp64 (batched launch)", "achieved": achieved,
+        "roofline": {"bound": "hbm", "kernel": kern + "_fp64 (batched launch)", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "bytes": "12 words x 8 B per active cell, summed over sets", "launches": k1_cnt,
-                     "mean_launch_ms": k1_ms / max(k1_cnt, 1)},
-        "kernels_fp64_ms": {"k1": {"launches": k1_cnt, "mean_ms": k1_ms / max(k1_cnt, 1)}},
+                     "bytes": "%d words x 8 B per active cell, summed over sets" % WORDS[kern],
+                     "launches": k1_cnt, "mean_launch_ms": k1_ms / max(k1_cnt, 1)},
+        "syncs_per_iteration": syncs,
+        "kernels_fp64_ms": {kern: {"launches": k1_cnt, "mean_ms": k1_ms / max(k1_cnt, 1)}},
         "layout": [c64.layout(i) for i in range(len(grids))],
         "cells": sum(n_all),
     }

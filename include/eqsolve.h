@@ -149,12 +149,14 @@ int eqsolve_destroy(eqs_ctx *ctx);
 const char *eqsolve_strerror(int code);
 
 /*
- * Diagnostics: the launch layout chosen for set `set` at create time.
- * out6 (host, 6 entries) receives cells per thread, segments per plane,
- * planes per chunk, chunks, tiles, and the number of host state readbacks
- * so far.  Returns EQS_OK or EQS_ERR_ARG.
+ * Diagnostics: the launch layout of set `set` (chosen at create time or by
+ * eqsolve_autotune).  out8 (host, 8 entries) receives cells per thread,
+ * segments per plane, planes per chunk, chunks, tiles, the number of host
+ * state readbacks so far, the grid-wide reductions per BiCGSTAB step of the
+ * iteration in use (1: one fused launch per step; 3: three launches), and the
+ * blocks of the pointwise kernels.  Returns EQS_OK or EQS_ERR_ARG.
  */
-int eqsolve_debug_layout(const eqs_ctx *ctx, int32_t set, int32_t *out6);
+int eqsolve_debug_layout(const eqs_ctx *ctx, int32_t set, int32_t *out8);
 
 /*
  * Diagnostics: every `every`-th launch of a kernel kind whose bit is set in
@@ -168,10 +170,13 @@ int eqsolve_debug_profile(eqs_ctx *ctx, int32_t kind_mask, int32_t every);
 
 /*
  * Diagnostics: launches and total milliseconds recorded for kernel `kind`
- * (for the three BiCGSTAB iteration kernels, only launches that did work:
- * those enqueued past a set's convergence are left out)
+ * (for the BiCGSTAB iteration kernels, only launches that did work: those
+ * enqueued past a set's convergence are left out)
  * (0 setup, 1 recheck, 2 report, 3 K1, 4 K2, 5 K3, 6 cast, 7 outer residual,
- * 8 update, 9 zero, 10 gradient, 11 product) in FP32 (fp32 = 1) or FP64.
+ * 8 update, 9 zero, 10 gradient, 11 product, 12 scaling, 13 unscaling,
+ * 14 fused single-sync step, 15 its set-up product f = M^T r^, 16 forming the
+ * iterate on leaving it) in FP32 (fp32 = 1) or FP64.  Returns EQS_OK or
+ * EQS_ERR_ARG (kind outside 0..31).
  */
 int eqsolve_debug_kernel_stats(const eqs_ctx *ctx, int32_t kind, int32_t fp32, int64_t *count,
                                double *total_ms);

@@ -26,7 +26,8 @@ SYMBOLS = ("eqsolve_create", "eqsolve_solve", "eqsolve_solve_batched", "eqsolve_
            "eqsolve_destroy", "eqsolve_strerror", "eqsolve_autotune", "eqsolve_debug_layout",
            "eqsolve_debug_profile", "eqsolve_debug_kernel_stats")
 KERNEL_KINDS = {"setup": 0, "recheck": 1, "report": 2, "k1": 3, "k2": 4, "k3": 5, "cast": 6, "outer": 7,
-                "update": 8, "zero": 9, "grad": 10, "apply": 11}
+                "update": 8, "zero": 9, "grad": 10, "apply": 11, "scale": 12, "unscale": 13, "fused": 14,
+                "fsetup": 15, "mat": 16}
 
 
 class EqsGrid(ctypes.Structure):
@@ -151,7 +152,7 @@ def eqsolve_destroy(h):
 
 
 def eqsolve_debug_layout(h, set_id):
-    out = (ctypes.c_int32 * 6)()
+    out = (ctypes.c_int32 * 8)()
     rc = load().eqsolve_debug_layout(h, int(set_id), out)
     return rc, list(out)
 

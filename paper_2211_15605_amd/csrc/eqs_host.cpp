@@ -49,8 +49,10 @@ struct SetHost {
     // workspace offsets resolved to pointers
     double *r, *rh, *p[2], *v[2], *t, *y;
     double *as[6];
+    double *s1, *t1, *f;
     float *as32[6];
     float *r32, *rh32, *p32[2], *v32[2], *t32, *d32;
+    float *s1_32, *t1_32, *f32;
     double *partials;
     uint32_t *counter;
     // convergence-rate tracking for chunk sizing
@@ -85,6 +87,9 @@ struct eqs_ctx {
     int precision = 0;
     int cpt = 2;
     int max_nx = 1;
+    // iteration scheme: one fused launch and one reduction per step (true), or
+    // three launches and three reductions per step (false)
+    bool sync1 = true;
     std::vector<SetHost> sets;
     SetDesc *h_desc = nullptr;
     SetDesc *d_desc = nullptr;
@@ -97,8 +102,8 @@ struct eqs_ctx {
     // optional per-launch event timing (diagnostics)
     uint32_t profile_mask = 0;  // bit k: time launches of kernel kind k
     int profile_every = 1;      // time every n-th launch of a timed kind
-    int64_t kseen[2 * 16] = {0};  // launches of each kind since profiling started
-    int kpos[2 * 16] = {0};       // launches of each kind since the last readback
+    int64_t kseen[2 * 32] = {0};  // launches of each kind since profiling started
+    int kpos[2 * 32] = {0};       // launches of each kind since the last readback
     std::vector<int> ev_pos;      // position of each timed launch since the last readback
     // captured iteration chunks: (first set, set count, transpose, fp32) -> graphs of 2^k iterations
     bool use_graphs = true;
@@ -109,8 +114,8 @@ struct eqs_ctx {
     std::vector<hipEvent_t> ev_pool;
     std::vector<int> ev_kind;     // pending (start, stop) pairs: kind per pair
     size_t ev_used = 0;
-    int64_t kcount[2 * 16] = {0};
-    double kms[2 * 16] = {0};
+    int64_t kcount[2 * 32] = {0};
+    double kms[2 * 32] = {0};
 };
 
 namespace {
@@ -184,6 +189,9 @@ void fill_desc(eqs_ctx *c, int s) {
     d.v[1] = h.v[1];
     d.t = h.t;
     d.y = h.y;
+    d.s1 = h.s1;
+    d.t1 = h.t1;
+    d.f = h.f;
     for (int k = 0; k < 6; ++k) d.as[k] = h.as[k];
     for (int k = 0; k < 6; ++k) d.as32[k] = h.as32[k];
     d.r32 = h.r32;
@@ -194,6 +202,9 @@ void fill_desc(eqs_ctx *c, int s) {
     d.v32[1] = h.v32[1];
     d.t32 = h.t32;
     d.d32 = h.d32;
+    d.s1_32 = h.s1_32;
+    d.t1_32 = h.t1_32;
+    d.f32 = h.f32;
     d.partials = h.partials;
     d.counter = h.counter;
     d.st = c->d_state + s;
@@ -281,7 +292,7 @@ struct Run {
             for (size_t i = 0; i < c->ev_kind.size(); ++i) {
                 const int kind = c->ev_kind[i];
                 const int kk = kind / 2;
-                const bool iter_kernel = kk == K_K1 || kk == K_K2 || kk == K_K3;
+                const bool iter_kernel = kk == K_K1 || kk == K_K2 || kk == K_K3 || kk == K_FUSED;
                 if (iter_kernel && c->ev_pos[i] >= worked) continue;
                 float ms = 0.f;
                 EQS_HIP(hipEventElapsedTime(&ms, c->ev_pool[2 * i], c->ev_pool[2 * i + 1]));
@@ -292,7 +303,7 @@ struct Run {
             c->ev_pos.clear();
             c->ev_used = 0;
         }
-        for (int i = 0; i < 2 * 16; ++i) c->kpos[i] = 0;
+        for (int i = 0; i < 2 * 32; ++i) c->kpos[i] = 0;
         return 0;
     }
     // C BiCGSTAB iterations (K1, K2, K3 each): replayed from captured graphs of
@@ -303,12 +314,17 @@ struct Run {
         int rc;
         if (c->profile_mask || !c->use_graphs) {
             for (int i = 0; i < C; ++i) {
+                if (c->sync1) {
+                    if ((rc = L(K_FUSED, nullptr, nullptr, 0, f32))) return rc;
+                    continue;
+                }
                 if ((rc = L(K_K1, nullptr, nullptr, 0, f32))) return rc;
                 if ((rc = L(K_K2, nullptr, nullptr, 0, f32))) return rc;
                 if ((rc = L(K_K3, nullptr, nullptr, 0, f32))) return rc;
             }
             return 0;
         }
+        const int per_iter = c->sync1 ? 1 : 3;
         auto &slots = c->graphs[std::make_tuple(first, count, trans, f32)];
         for (int b = 8; b >= 0; --b) {
             while (C >= (1 << b)) {
@@ -316,10 +332,16 @@ struct Run {
                     if (!c->capture_stream) EQS_HIP(hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
                     EQS_HIP(hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
                     bool ok = true;
-                    for (int i = 0; i < (1 << b) && ok; ++i)
+                    for (int i = 0; i < (1 << b) && ok; ++i) {
+                        if (c->sync1) {
+                            ok = launch_kernel(K_FUSED, ls, ntiles, nflat, c->cpt, max_nx, f32, trans,
+                                               c->capture_stream, nullptr, nullptr, 0) == hipSuccess;
+                            continue;
+                        }
                         for (Kern k : {K_K1, K_K2, K_K3})
                             ok = ok && launch_kernel(k, ls, ntiles, nflat, c->cpt, max_nx, f32, trans,
                                                      c->capture_stream, nullptr, nullptr, 0) == hipSuccess;
+                    }
                     hipGraph_t g = nullptr;
                     const hipError_t e = hipStreamEndCapture(c->capture_stream, &g);
                     if (!ok || e != hipSuccess || !g) {
@@ -339,7 +361,7 @@ struct Run {
                     slots[b] = ex;
                 }
                 EQS_HIP(hipGraphLaunch(slots[b], c->stream));
-                c->launches += 3u << b;
+                c->launches += (uint64_t)per_iter << b;
                 C -= 1 << b;
             }
         }
@@ -407,17 +429,23 @@ int run_fp64(Run &R) {
         }
         return R.readback();
     }
+    const bool s1 = R.c->sync1;
     if ((rc = R.L(K_SCALE))) return rc;  // coefficients of A D^-1 (A^T D^-1), once per solve
     if ((rc = R.L(K_SETUP))) return rc;
+    if (s1 && (rc = R.L(K_FSETUP))) return rc;
     if ((rc = R.readback())) return rc;
     R.reset_rate();
     for (long guard = 0;; ++guard) {
         if (guard > R.guard_limit) { R.c->broken = true; return EQS_ERR_STATE; }
         if (R.all_done()) break;
-        if (R.any([](const SolveState &s) { return s.converged || s.need_report; })) {
+        if (R.any([s1](const SolveState &s) {
+                return !s.done && (s.converged || s.need_report || (s1 && (s.mat || s.need_f)));
+            })) {
+            if (s1 && (rc = R.L(K_MAT))) return rc;  // the iterate of the step being left
             if ((rc = R.L(K_UNSCALE))) return rc;  // x = y / a_P
             if ((rc = R.L(K_RECHECK))) return rc;
             if ((rc = R.L(K_REPORT))) return rc;
+            if (s1 && (rc = R.L(K_FSETUP))) return rc;  // after a restart
             if ((rc = R.readback())) return rc;
             R.reset_rate();
             continue;
@@ -434,16 +462,22 @@ int run_fp64(Run &R) {
 
 int run_fp32(Run &R) {
     int rc;
+    const bool s1 = R.c->sync1;
     if ((rc = R.L(K_CAST))) return rc;
     if ((rc = R.L(K_OUTER))) return rc;
+    if (s1 && (rc = R.L(K_FSETUP, nullptr, nullptr, 0, true))) return rc;
     if ((rc = R.readback())) return rc;
     R.reset_rate();
     for (long guard = 0;; ++guard) {
         if (guard > R.guard_limit) { R.c->broken = true; return EQS_ERR_STATE; }
         if (R.all_done()) break;
-        if (R.any([](const SolveState &s) { return s.inner_done != 0 && !s.done; })) {
+        if (R.any([s1](const SolveState &s) {
+                return !s.done && (s.inner_done != 0 || (s1 && (s.mat || s.need_f)));
+            })) {
+            if (s1 && (rc = R.L(K_MAT, nullptr, nullptr, 0, true))) return rc;
             if ((rc = R.L(K_UPDATE))) return rc;
             if ((rc = R.L(K_OUTER))) return rc;
+            if (s1 && (rc = R.L(K_FSETUP, nullptr, nullptr, 0, true))) return rc;
             if ((rc = R.readback())) return rc;
             R.reset_rate();
             continue;
@@ -604,15 +638,20 @@ double time_iterations(eqs_ctx *c, int s, double *tmp, int iters) {
     } else if (R.L(K_SCALE) || R.L(K_SETUP)) {
         return -1.0;
     }
-    for (int i = 0; i < 2; ++i)
+    if (c->sync1 && R.L(K_FSETUP, nullptr, nullptr, 0, f32)) return -1.0;
+    auto step = [&]() -> int {
+        if (c->sync1) return R.L(K_FUSED, nullptr, nullptr, 0, f32);
         for (Kern k : {K_K1, K_K2, K_K3})
-            if (R.L(k, nullptr, nullptr, 0, f32)) return -1.0;
+            if (int rc = R.L(k, nullptr, nullptr, 0, f32)) return rc;
+        return 0;
+    };
+    for (int i = 0; i < 2; ++i)
+        if (step()) return -1.0;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return -1.0;
     (void)hipEventRecord(e0, c->stream);
     for (int i = 0; i < iters; ++i)
-        for (Kern k : {K_K1, K_K2, K_K3})
-            if (R.L(k, nullptr, nullptr, 0, f32)) return -1.0;
+        if (step()) return -1.0;
     (void)hipEventRecord(e1, c->stream);
     float ms = 0.f;
     const bool ok = hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
@@ -665,6 +704,17 @@ int eqsolve_create(eqs_ctx **out, const eqs_grid *grids, int32_t nsets, int32_t 
     int cpt = env_int("EQS_CPT", 0);
     if (cpt != 1 && cpt != 2) cpt = max_plane >= 4 * kBlock ? 2 : 1;
     while (cpt > 1 && march_lds_bytes(cpt, max_nx, 8) > kMaxLds) cpt /= 2;
+    // single-sync iteration (EQS_SYNC=3 selects the three-launch one) where its
+    // wider planes fit in LDS; it may need the narrower segment
+    c->sync1 = env_int("EQS_SYNC", 1) != 3 && halo_slots(max_nx) > 0 && halo_slots(max_nx) <= 4;
+    if (c->sync1) {
+        int fc = cpt;
+        while (fc > 1 && fused_lds_bytes(fc, max_nx, 8) > kMaxLds) fc /= 2;
+        if (fused_lds_bytes(fc, max_nx, 8) > kMaxLds)
+            c->sync1 = false;
+        else
+            cpt = fc;
+    }
     // nx beyond what one LDS plane buffer or the halo slots cover
     if (march_lds_bytes(cpt, max_nx, 8) > kMaxLds || halo_slots(max_nx) < 0) { delete c; return EQS_ERR_ARG; }
     // a tuning cache (EQS_TUNE_CACHE) entry for every set, with one common cpt, overrides the defaults
@@ -679,6 +729,7 @@ int eqsolve_create(eqs_ctx **out, const eqs_grid *grids, int32_t nsets, int32_t 
         }
         if (tuned_ok) tuned_cpt = tuned[0].cpt;
         if (tuned_ok && march_lds_bytes(tuned_cpt, max_nx, 8) > kMaxLds) tuned_ok = false;
+        if (tuned_ok && c->sync1 && fused_lds_bytes(tuned_cpt, max_nx, 8) > kMaxLds) tuned_ok = false;
         if (tuned_ok) cpt = tuned_cpt;
     }
     c->cpt = cpt;
@@ -697,8 +748,8 @@ int eqsolve_create(eqs_ctx **out, const eqs_grid *grids, int32_t nsets, int32_t 
         choose_tiling(h, cpt);
         if (tuned_ok) set_tiling(h, tuned_cpt, tuned[s].kc, tuned[s].nflat);
         base[s] = bytes;
-        bytes += 14 * align_up((size_t)h.n * 8);   // r, r^, p[2], v[2], t, y, 6 scaled coefficients
-        if (f32) bytes += 14 * align_up((size_t)h.n * 4);  // 6 scaled coefficients, r, r^, p[2], v[2], t, d
+        bytes += 17 * align_up((size_t)h.n * 8);   // r, r^, p[2], v[2], t, y, 6 scaled coefficients, s1, t1, f
+        if (f32) bytes += 17 * align_up((size_t)h.n * 4);  // the same in FP32 (d = the inner iterate)
         bytes += align_up(max_partials(h) * kMaxRed * 8);
         bytes += kAlign;  // counter
     }
@@ -728,6 +779,9 @@ int eqsolve_create(eqs_ctx **out, const eqs_grid *grids, int32_t nsets, int32_t 
         h.t = (double *)take((size_t)h.n * 8);
         h.y = (double *)take((size_t)h.n * 8);
         for (int k = 0; k < 6; ++k) h.as[k] = (double *)take((size_t)h.n * 8);
+        h.s1 = (double *)take((size_t)h.n * 8);
+        h.t1 = (double *)take((size_t)h.n * 8);
+        h.f = (double *)take((size_t)h.n * 8);
         if (f32) {
             for (int k = 0; k < 6; ++k) h.as32[k] = (float *)take((size_t)h.n * 4);
             h.r32 = (float *)take((size_t)h.n * 4);
@@ -738,6 +792,9 @@ int eqsolve_create(eqs_ctx **out, const eqs_grid *grids, int32_t nsets, int32_t 
             h.v32[1] = (float *)take((size_t)h.n * 4);
             h.t32 = (float *)take((size_t)h.n * 4);
             h.d32 = (float *)take((size_t)h.n * 4);
+            h.s1_32 = (float *)take((size_t)h.n * 4);
+            h.t1_32 = (float *)take((size_t)h.n * 4);
+            h.f32 = (float *)take((size_t)h.n * 4);
         }
         h.partials = (double *)take(max_partials(h) * kMaxRed * 8);
         h.counter = (uint32_t *)take(kAlign);
@@ -894,15 +951,17 @@ const char *eqsolve_strerror(int code) {
 }
 
 // introspection used by tests and the benchmark (not part of the solver contract)
-int eqsolve_debug_layout(const eqs_ctx *c, int32_t set, int32_t *out6) {
-    if (!c || set < 0 || set >= c->nsets || !out6) return EQS_ERR_ARG;
+int eqsolve_debug_layout(const eqs_ctx *c, int32_t set, int32_t *out8) {
+    if (!c || set < 0 || set >= c->nsets || !out8) return EQS_ERR_ARG;
     const SetHost &h = c->sets[set];
-    out6[0] = c->cpt;
-    out6[1] = h.S;
-    out6[2] = h.KC;
-    out6[3] = h.NKC;
-    out6[4] = h.ntiles;
-    out6[5] = (int32_t)std::min<uint64_t>(c->readbacks, 0x7fffffff);
+    out8[0] = c->cpt;
+    out8[1] = h.S;
+    out8[2] = h.KC;
+    out8[3] = h.NKC;
+    out8[4] = h.ntiles;
+    out8[5] = (int32_t)std::min<uint64_t>(c->readbacks, 0x7fffffff);
+    out8[6] = c->sync1 ? 1 : 3;
+    out8[7] = h.nflat;
     return EQS_OK;
 }
 
@@ -930,6 +989,7 @@ int eqsolve_autotune(eqs_ctx *c, const char *cache_path, int32_t iters) {
     std::vector<TuneEntry> best(c->nsets), cur(c->nsets);
     for (int cpt = 1; cpt <= 2 && rc == EQS_OK; ++cpt) {
         if (march_lds_bytes(cpt, c->max_nx, 8) > kMaxLds) continue;
+        if (c->sync1 && fused_lds_bytes(cpt, c->max_nx, 8) > kMaxLds) continue;
         c->cpt = cpt;
         clear_graphs(c);
         double total = 0.0;
@@ -996,7 +1056,7 @@ int eqsolve_debug_profile(eqs_ctx *c, int32_t kind_mask, int32_t every) {
 }
 
 int eqsolve_debug_kernel_stats(const eqs_ctx *c, int32_t kind, int32_t fp32, int64_t *count, double *total_ms) {
-    if (!c || kind < 0 || kind >= 16 || !count || !total_ms) return EQS_ERR_ARG;
+    if (!c || kind < 0 || kind >= 32 || !count || !total_ms) return EQS_ERR_ARG;
     const int i = kind * 2 + (fp32 ? 1 : 0);
     *count = c->kcount[i];
     *total_ms = c->kms[i];

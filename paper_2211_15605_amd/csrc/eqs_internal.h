@@ -14,7 +14,7 @@ namespace eqs {
 
 constexpr int kBlock = 256;      // threads per block (4 wave64)
 constexpr int kMaxSets = 8;      // sets per launch table
-constexpr int kMaxRed = 4;       // reduction values per tile
+constexpr int kMaxRed = 10;      // reduction values per tile
 constexpr int kFlatU = 4;        // pointwise kernels: cells per thread per chunk
 constexpr int kFlatChunk = kBlock * kFlatU;
 constexpr int kMaxFlatBlocks = 4096;
@@ -39,6 +39,9 @@ struct SolveState {
     double rr_prev;   // outer residual of the previous refinement step
     double scale;     // power of two applied to the residual cast to FP32
     double upd_inv_scale;  // 1/scale of the inner solve being applied
+    // single-sync iteration: the scalars of the previous step (alpha_prev,
+    // omega, beta) with which the next launch forms r, p and y
+    double alpha_prev, beta;
     int32_t iters;    // BiCGSTAB iterations so far (inner, for the FP32 forms)
     int32_t maxit;
     int32_t active;   // BiCGSTAB iterating
@@ -55,6 +58,12 @@ struct SolveState {
     int32_t zero_rhs;     // b = 0: x must be set to 0
     int32_t mode;
     int32_t outer_pending;  // FP32 forms: first outer residual pending
+    // single-sync iteration
+    int32_t fpar;     // buffer slot (0/1) holding the latest s, t, p, v
+    int32_t need_f;   // f = M^T r^ and sigma_0 pending (after a fresh start)
+    int32_t mat;      // iterate to form before leaving the iteration: 1 y += alpha p;
+                      // 2 y += alpha p + omega s; 3 as 2, plus r = s - omega t, r^ = r (restart)
+    int32_t pad_;
 };
 
 struct SetDesc {
@@ -76,9 +85,13 @@ struct SetDesc {
     // the adjoint, those of A^T D^-1) and y = D x is its iterate.
     double *r, *rh, *p[2], *v[2], *t, *y;
     double *as[6];
+    // single-sync iteration: s and t double-buffered with r (slot 0 of s) and
+    // t (slot 0 of t); f = M^T r^ with M the scaled operator
+    double *s1, *t1, *f;
     // FP32 work (refinement): scaled coefficients, vectors, d32 = inner iterate (scaled)
     float *as32[6];
     float *r32, *rh32, *p32[2], *v32[2], *t32, *d32;
+    float *s1_32, *t1_32, *f32;
     // adjoint: forward solution and gradient outputs (grad_b is the iterate x)
     const double *xf;
     double *g[7];

@@ -154,6 +154,9 @@ __device__ __forceinline__ void start_fresh(SolveState *st, double rr) {
     st->fresh = 1;
     st->half = 0;
     st->active = 1;
+    st->fpar = 0;     // the residual is in slot 0 of s
+    st->need_f = 1;   // single-sync iteration: f = M^T r^ before the first step
+    st->mat = 0;
 }
 
 // stop the BiCGSTAB iteration with a failure code
@@ -184,6 +187,9 @@ struct FinSetup {  // sums: (b,b), (r,r), #bad a_P
     const SetDesc *d;
     __device__ void operator()(SolveState *st, const double *s) const {
         st->mode = d->mode;
+        st->mat = 0;
+        st->need_f = 0;
+        st->fpar = 0;
         st->maxit = d->maxit;
         st->iters = 0;
         st->restarts = 0;
@@ -216,6 +222,7 @@ struct FinSetup {  // sums: (b,b), (r,r), #bad a_P
 struct FinRecheck {  // sums: (b,b), (r,r), #bad
     __device__ void operator()(SolveState *st, const double *s) const {
         st->converged = 0;
+        st->mat = 0;
         const double rr = s[1];
         st->rr_true = rr;
         st->rr = rr;
@@ -231,6 +238,7 @@ struct FinReport {
     __device__ void operator()(SolveState *st, const double *s) const {
         st->rr_true = s[1];
         st->need_report = 0;
+        st->mat = 0;
         st->done = 1;
     }
 };
@@ -281,10 +289,90 @@ struct FinK3 {  // sums: (r^, r), (r, r)
     }
 };
 
+// Single-sync iteration (see fused_kernel).  After a fresh start: sums (f, r^),
+// (r^, r^) with f = M^T r^, so sigma_0 = (r^, M p_0) = (f, r_0) (p_0 = r_0 = r^).
+struct FinFSetup {
+    __device__ void operator()(SolveState *st, const double *s) const {
+        st->need_f = 0;
+        st->mat = 0;
+        st->fpar = 0;
+        st->fresh = 1;
+        const double sg = s[0], rr = s[1];
+        st->rho = rr;
+        st->sigma = sg;
+        if (!isfinite(sg) || !isfinite(rr)) { stop_iter(st, ST_NONFINITE); return; }
+        if (sg == 0.0) {  // breakdown in the first half-step of the iteration about to start
+            st->iters++;
+            stop_iter(st, ST_BREAKDOWN);
+            return;
+        }
+        st->alpha = rr / sg;
+    }
+};
+
+// After launch j of the single-sync iteration: sums (f,p_j), (f,v_j), (f,s_j),
+// (f,t_j), (r^,s_j), (r^,t_j), (t_j,s_j), (t_j,t_j), (r_j,r_j), (s_j,s_j).
+struct FinFused {
+    __device__ void operator()(SolveState *st, const double *s) const {
+        const double fp = s[0], fv = s[1], fs = s[2], ft = s[3], rs = s[4], rt = s[5];
+        const double ts = s[6], tt = s[7], rr = s[8], ss = s[9];
+        st->fpar ^= 1;  // step j's s, t, p, v are in the other slot now
+        if (!st->fresh) {
+            // r_j (formed by this launch) decides convergence; y_j is stored
+            st->rr = rr;
+            if (!isfinite(rr)) { stop_iter(st, ST_NONFINITE); return; }
+            if (sqrt(rr) <= st->lim2) { converge_iter(st); return; }
+        }
+        st->fresh = 0;
+        st->ts = ts;
+        st->tt = tt;
+        st->ss = ss;
+        bool fin = true;
+        for (int i = 0; i < 10; ++i) fin = fin && isfinite(s[i]);
+        if (!fin) { stop_iter(st, ST_NONFINITE); return; }
+        st->iters++;
+        st->alpha_prev = st->alpha;  // alpha_j
+        if (sqrt(ss) <= st->lim2) {  // half-step exit: x = y_j + alpha_j p_j
+            st->mat = 1;
+            converge_iter(st);
+            return;
+        }
+        const double om = tt == 0.0 ? 0.0 : ts / tt;
+        st->omega = om;
+        if (om == 0.0) { st->mat = 2; stop_iter(st, ST_BREAKDOWN); return; }
+        if (st->iters >= st->maxit) {  // y_{j+1} formed, then the true residual decides
+            st->mat = 2;
+            converge_iter(st);
+            return;
+        }
+        const double rho_new = rs - om * rt;  // (r^, r_{j+1}) with r_{j+1} = s_j - omega_j t_j
+        if (!isfinite(rho_new)) { st->mat = 2; stop_iter(st, ST_NONFINITE); return; }
+        if (rho_new == 0.0) {
+            if (st->rho_restarts++ > 0) { st->mat = 2; stop_iter(st, ST_BREAKDOWN); return; }
+            st->restarts++;
+            st->mat = 3;  // y_{j+1}, r_{j+1}, r^ := r_{j+1}, then a fresh start
+            st->need_f = 1;
+            return;
+        }
+        const double beta = (rho_new / st->rho) * (st->alpha_prev / om);
+        // (r^, M p_{j+1}) = (f, p_{j+1}), p_{j+1} = s_j - omega t_j + beta (p_j - omega v_j)
+        const double sg = fs - om * ft + beta * (fp - om * fv);
+        st->sigma = sg;
+        if (!isfinite(sg) || sg == 0.0) { st->mat = 2; stop_iter(st, sg == 0.0 ? ST_BREAKDOWN : ST_NONFINITE); return; }
+        st->beta = beta;
+        st->rho_prev = st->rho;
+        st->rho = rho_new;
+        st->alpha = rho_new / sg;
+    }
+};
+
 struct FinCast {  // sums: (b,b), #bad
     const SetDesc *d;
     __device__ void operator()(SolveState *st, const double *s) const {
         st->mode = d->mode;
+        st->mat = 0;
+        st->need_f = 0;
+        st->fpar = 0;
         st->maxit = d->maxit;
         st->iters = 0;
         st->restarts = 0;
@@ -317,6 +405,7 @@ struct FinOuter {  // sums: (r,r) in FP64, (r32, r32)
     __device__ void operator()(SolveState *st, const double *s) const {
         st->inner_done = 0;
         st->outer_pending = 0;
+        st->mat = 0;
         const double rr = s[0], rr32 = s[1];
         st->rr_true = rr;
         if (!isfinite(rr) || !isfinite(rr32)) { st->status = ST_NONFINITE; st->done = 1; return; }
@@ -538,6 +627,9 @@ struct Vecs<double> {
     __device__ static double *v(const SetDesc &d, int i) { return i ? d.v[1] : d.v[0]; }
     __device__ static double *t(const SetDesc &d) { return d.t; }
     __device__ static double *y(const SetDesc &d) { return d.y; }
+    __device__ static double *s(const SetDesc &d, int i) { return i ? d.s1 : d.r; }
+    __device__ static double *t(const SetDesc &d, int i) { return i ? d.t1 : d.t; }
+    __device__ static double *f(const SetDesc &d) { return d.f; }
 };
 template <>
 struct Vecs<float> {
@@ -548,6 +640,9 @@ struct Vecs<float> {
     __device__ static float *v(const SetDesc &d, int i) { return i ? d.v32[1] : d.v32[0]; }
     __device__ static float *t(const SetDesc &d) { return d.t32; }
     __device__ static float *y(const SetDesc &d) { return d.d32; }
+    __device__ static float *s(const SetDesc &d, int i) { return i ? d.s1_32 : d.r32; }
+    __device__ static float *t(const SetDesc &d, int i) { return i ? d.t1_32 : d.t32; }
+    __device__ static float *f(const SetDesc &d) { return d.f32; }
 };
 
 // the six scaled coefficients of a row, zero where the neighbour is outside
@@ -562,6 +657,22 @@ struct Unit6 {
         s = ld(as[3], idx);
         t = ld(as[4], idx);
         b = ld(as[5], idx);
+        e = nb.e ? e : T(0);
+        w = nb.w ? w : T(0);
+        n = nb.n ? n : T(0);
+        s = nb.s ? s : T(0);
+        t = up ? t : T(0);
+        b = dn ? b : T(0);
+    }
+    // row idx of M^T: the link to neighbour nb is row nb's coefficient towards idx
+    __device__ __forceinline__ void load_transposed(const T *const *as, int idx, int nx, int P, int ncell, Nb nb,
+                                                    bool up, bool dn) {
+        e = ld(as[1], min(idx + 1, ncell - 1));
+        w = ld(as[0], max(idx - 1, 0));
+        n = ld(as[3], min(idx + nx, ncell - 1));
+        s = ld(as[2], max(idx - nx, 0));
+        t = ld(as[5], min(idx + P, ncell - 1));
+        b = ld(as[4], max(idx - P, 0));
         e = nb.e ? e : T(0);
         w = nb.w ? w : T(0);
         n = nb.n ? n : T(0);
@@ -750,6 +861,32 @@ struct PhApply {
     }
 };
 
+// f = M^T r^ (M the scaled operator), (f, r^), (r^, r^): set-up of the single-sync iteration
+template <typename T>
+struct PhFSet {
+    static constexpr int NV = 2;
+    struct Raw { T x; };
+    struct Aux {};
+    struct Pre { Unit6<T> c; };
+    const T *as[6];
+    const T *rh;
+    T *f;
+    int nx, P, ncell;
+    __device__ __forceinline__ Raw load(int idx) const { return Raw{ld(rh, idx)}; }
+    __device__ __forceinline__ T own(const Raw &w, int, Aux &) { return w.x; }
+    __device__ __forceinline__ T halo(const Raw &w) const { return w.x; }
+    __device__ __forceinline__ void pre(int idx, Nb nb, bool up, bool dn, Pre &pr) const {
+        pr.c.load_transposed(as, idx, nx, P, ncell, nb, up, dn);
+    }
+    __device__ __forceinline__ void center(int idx, const Pre &pr, const Aux &, T xc, T xE, T xW, T xN, T xS,
+                                           T xT, T xB, double (&acc)[NV]) {
+        const T fv = pr.c.apply(xc, xE, xW, xN, xS, xT, xB);
+        st(f, idx, fv);
+        acc[0] += (double)fv * (double)xc;
+        acc[1] += (double)xc * (double)xc;
+    }
+};
+
 // ------------------------------------------------------------------ march kernels
 
 template <typename T>
@@ -866,6 +1003,271 @@ __global__ void __launch_bounds__(kBlock) apply_kernel(LaunchSets ls, const doub
     march<double, CPT, H>(ph, geo_of(d), tr.tile, lds_base<double>(), acc);
 }
 
+template <typename T, int CPT, int H>
+__global__ void __launch_bounds__(kBlock) fsetup_kernel(LaunchSets ls) {
+    const TileRef tr = locate<false>(ls);
+    const SetDesc &d = *tr.d;
+    const SolveState *st_ = d.st;
+    if (st_->done || !st_->active || !st_->need_f) return;
+    PhFSet<T> ph;
+    for (int k = 0; k < 6; ++k) ph.as[k] = Vecs<T>::as(d)[k];
+    ph.rh = Vecs<T>::rh(d);
+    ph.f = Vecs<T>::f(d);
+    ph.nx = d.nx;
+    ph.P = d.plane;
+    ph.ncell = d.n;
+    double acc[2] = {0.0, 0.0};
+    march<T, CPT, H>(ph, geo_of(d), tr.tile, lds_base<T>(), acc);
+    reduce_and_finalize<2>(d, tr.tile, d.ntiles, acc, FinFSetup{});
+}
+
+// ------------------------------------------------------------------ single-sync iteration
+//
+// One launch per BiCGSTAB step j on the scaled operator M = A D^-1.  From
+// step j-1's s, t, p, v (slot st->fpar) and scalars it forms, per cell,
+//   r_j = s_{j-1} - omega_{j-1} t_{j-1}
+//   y_j = y_{j-1} + alpha_{j-1} p_{j-1} + omega_{j-1} s_{j-1}
+//   p_j = r_j + beta_{j-1} (p_{j-1} - omega_{j-1} v_{j-1})
+//   v_j = M p_j,   s_j = r_j - alpha_j v_j,   t_j = M s_j
+// (at a fresh start r_0 is the stored residual, p_0 = r_0, y unchanged) and
+// the ten sums of FinFused, from which the finalising block gets omega_j,
+// rho_{j+1} = (r^, s_j) - omega_j (r^, t_j) and sigma_{j+1} = (r^, M p_{j+1})
+// = (f, p_{j+1}) with f = M^T r^, expanded over step j's vectors.  The
+// products and vector updates are those of BiCGSTAB; only the grouping of
+// the dot products differs, so one grid-wide reduction serves a step and
+// the six coefficient arrays are read once for both products.
+//
+// Tile: a segment of Q = 256 CPT cells of a plane (flat in-plane index q0 ..
+// q0+Q-1) times the planes k0 .. k1-1.  t needs s one row (nx cells) and one
+// plane beyond the tile, and s there needs p one more row and plane out, so
+// p is formed on the segment widened by 2 nx cells each side (index e = q -
+// q0 + 2 nx in [0, Q + 4 nx)), v and s on the segment widened by nx, t on
+// the segment itself.  Step kt forms p on plane kt + 2, v and s on plane
+// kt + 1 and t on plane kt; four lead-in steps start the pipeline at k0 - 4.
+// p and s planes rotate through three LDS buffers each.  Each thread owns
+// CPT cells of the segment and H cells of each of two halo rings: the inner
+// ring (the nx cells next to the segment on each side: v and s needed there)
+// and the outer ring (p only).
+template <typename T, int CPT, int H>
+__global__ void __launch_bounds__(kBlock) fused_kernel(LaunchSets ls) {
+    constexpr int Q = kBlock * CPT;
+    const TileRef tr = locate<false>(ls);
+    const SetDesc &d = *tr.d;
+    const SolveState *st_ = d.st;
+    if (!st_->active || st_->need_f) return;
+    const int in = st_->fpar, out = in ^ 1;
+    const bool fresh = st_->fresh != 0;
+    const T al = (T)st_->alpha, ap = (T)st_->alpha_prev, om = (T)st_->omega, be = (T)st_->beta;
+    const T *as[6];
+    for (int k = 0; k < 6; ++k) as[k] = Vecs<T>::as(d)[k];
+    const T *sI = Vecs<T>::s(d, in), *tI = Vecs<T>::t(d, in), *pI = Vecs<T>::p(d, in), *vI = Vecs<T>::v(d, in);
+    T *sO = Vecs<T>::s(d, out), *tO = Vecs<T>::t(d, out), *pO = Vecs<T>::p(d, out), *vO = Vecs<T>::v(d, out);
+    T *yv = Vecs<T>::y(d);
+    const T *fv = Vecs<T>::f(d), *rhv = Vecs<T>::rh(d);
+    const int nx = d.nx, ny = d.ny, nz = d.nz, P = d.plane, S = d.S, KC = d.KC;
+    const int seg = tr.tile % S, chunk = tr.tile / S;
+    const int q0 = seg * Q, k0 = chunk * KC, k1 = min(k0 + KC, nz);
+    const int W = Q + 4 * nx;
+    T *Pb = lds_base<T>();
+    T *Sb = Pb + 3 * W;
+    const int tid = threadIdx.x;
+
+    // own cells
+    int qo[CPT], eo[CPT];
+    bool oko[CPT];
+    Nb nbo[CPT];
+#pragma unroll
+    for (int m = 0; m < CPT; ++m) {
+        const int q = q0 + tid + kBlock * m;
+        qo[m] = min(q, P - 1);
+        eo[m] = 2 * nx + tid + kBlock * m;
+        oko[m] = q < P;
+        const int j = qo[m] / nx, i = qo[m] - j * nx;
+        nbo[m] = Nb{i + 1 < nx, i > 0, j + 1 < ny, j > 0};
+    }
+    // ring cells: slot h covers ring position hh = tid + 256 h < 2 nx
+    int qi[H], ei[H], qr[H], er[H];
+    bool oki[H], okr[H], usei[H], user[H];
+    Nb nbi[H];
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+        const int hh = tid + kBlock * h;
+        const bool use = hh < 2 * nx;
+        // inner ring: e in [nx, 2nx) and [Q + 2nx, Q + 3nx)
+        const int e1 = hh < nx ? nx + hh : Q + nx + hh;
+        const int q1 = q0 - 2 * nx + e1;
+        usei[h] = use;
+        ei[h] = use ? e1 : 0;
+        oki[h] = use && q1 >= 0 && q1 < P;
+        qi[h] = min(max(q1, 0), P - 1);
+        const int j = qi[h] / nx, i = qi[h] - j * nx;
+        nbi[h] = Nb{i + 1 < nx, i > 0, j + 1 < ny, j > 0};
+        // outer ring: e in [0, nx) and [Q + 3nx, Q + 4nx)
+        const int e2 = hh < nx ? hh : Q + 2 * nx + hh;
+        const int q2 = q0 - 2 * nx + e2;
+        user[h] = use;
+        er[h] = use ? e2 : 0;
+        okr[h] = use && q2 >= 0 && q2 < P;
+        qr[h] = min(max(q2, 0), P - 1);
+    }
+
+    // values carried between steps (own cells): f on planes kt+2 / kt+1 / kt,
+    // r^ and the coefficients on plane kt, r on plane kt+1 (also inner ring)
+    T fA[CPT], fB[CPT], fC[CPT], rhC[CPT], rBo[CPT], rBi[H];
+    Unit6<T> cC[CPT];
+#pragma unroll
+    for (int m = 0; m < CPT; ++m) {
+        fA[m] = fB[m] = fC[m] = rhC[m] = rBo[m] = T(0);
+        cC[m] = Unit6<T>{T(0), T(0), T(0), T(0), T(0), T(0)};
+    }
+#pragma unroll
+    for (int h = 0; h < H; ++h) rBi[h] = T(0);
+    double acc[10];
+#pragma unroll
+    for (int i = 0; i < 10; ++i) acc[i] = 0.0;
+
+    int bt = 0, bv = 1, bp = 2;  // LDS slots of planes kt, kt+1, kt+2 (kt-1 shares kt+2's slot)
+    for (int kt = k0 - 4; kt < k1; ++kt) {
+        const int kp = kt + 2, kv = kt + 1;
+        const bool pin = kp >= 0 && kp < nz, pown = kp >= k0 && kp < k1;
+        const bool do2 = kt >= k0 - 2, vin = kv >= 0 && kv < nz, vown = kv >= k0 && kv < k1;
+        const bool do3 = kt >= k0;
+        const int kpb = min(max(kp, 0), nz - 1) * P, kvb = min(max(kv, 0), nz - 1) * P;
+
+        // ---- loads: step j-1 vectors on plane kp, coefficients on plane kv
+        T sIo[CPT], tIo[CPT], pIo[CPT], vIo[CPT], yo[CPT], rhN[CPT];
+        T sIi[H], tIi[H], pIi[H], vIi[H], sIr[H], tIr[H], pIr[H], vIr[H];
+        Unit6<T> cN[CPT], cI[H];
+#pragma unroll
+        for (int m = 0; m < CPT; ++m) {
+            const int i = qo[m] + kpb;
+            sIo[m] = ld(sI, i); tIo[m] = ld(tI, i); pIo[m] = ld(pI, i); vIo[m] = ld(vI, i);
+        }
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+            const int i = qi[h] + kpb, r = qr[h] + kpb;
+            sIi[h] = ld(sI, i); tIi[h] = ld(tI, i); pIi[h] = ld(pI, i); vIi[h] = ld(vI, i);
+            sIr[h] = ld(sI, r); tIr[h] = ld(tI, r); pIr[h] = ld(pI, r); vIr[h] = ld(vI, r);
+        }
+        if (pown) {
+#pragma unroll
+            for (int m = 0; m < CPT; ++m) {
+                yo[m] = ld(yv, qo[m] + kpb);
+                fA[m] = ld(fv, qo[m] + kpb);
+            }
+        }
+        if (do2) {
+            const bool up = kv + 1 < nz, dn = kv > 0;
+#pragma unroll
+            for (int m = 0; m < CPT; ++m) cN[m].load(as, qo[m] + kvb, nbo[m], up, dn);
+#pragma unroll
+            for (int h = 0; h < H; ++h) cI[h].load(as, qi[h] + kvb, nbi[h], up, dn);
+            if (vown) {
+#pragma unroll
+                for (int m = 0; m < CPT; ++m) rhN[m] = ld(rhv, qo[m] + kvb);
+            }
+        }
+
+        // ---- p_j on plane kp (segment + both rings), r_j kept for plane kp
+        T rAo[CPT], rAi[H];
+#pragma unroll
+        for (int m = 0; m < CPT; ++m) {
+            T r = fresh ? sIo[m] : fma(-om, tIo[m], sIo[m]);
+            T pv = fresh ? r : fma(be, fma(-om, vIo[m], pIo[m]), r);
+            const bool ok = pin && oko[m];
+            r = ok ? r : T(0);
+            pv = ok ? pv : T(0);
+            Pb[bp * W + eo[m]] = pv;
+            rAo[m] = r;
+            if (pown && oko[m]) {
+                const int i = qo[m] + kpb;
+                st(pO, i, pv);
+                if (!fresh) st(yv, i, yo[m] + fma(ap, pIo[m], om * sIo[m]));
+                acc[0] += (double)fA[m] * (double)pv;
+                acc[8] += (double)r * (double)r;
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+            T r = fresh ? sIi[h] : fma(-om, tIi[h], sIi[h]);
+            T pv = fresh ? r : fma(be, fma(-om, vIi[h], pIi[h]), r);
+            const bool ok = pin && oki[h];
+            rAi[h] = ok ? r : T(0);
+            if (usei[h]) Pb[bp * W + ei[h]] = ok ? pv : T(0);
+            T r2 = fresh ? sIr[h] : fma(-om, tIr[h], sIr[h]);
+            T pv2 = fresh ? r2 : fma(be, fma(-om, vIr[h], pIr[h]), r2);
+            if (user[h]) Pb[bp * W + er[h]] = (pin && okr[h]) ? pv2 : T(0);
+        }
+        __syncthreads();
+
+        // ---- v_j = M p_j and s_j = r_j - alpha_j v_j on plane kv (segment + inner ring)
+        if (do2) {
+            const T *pc = Pb + bv * W, *pu = Pb + bp * W, *pd = Pb + bt * W;
+#pragma unroll
+            for (int m = 0; m < CPT; ++m) {
+                const int e = eo[m];
+                const T v = cN[m].apply(pc[e], pc[e + 1], pc[e - 1], pc[e + nx], pc[e - nx], pu[e], pd[e]);
+                const bool ok = vin && oko[m];
+                const T sv = ok ? fma(-al, v, rBo[m]) : T(0);
+                Sb[bv * W + e] = sv;
+                if (vown && oko[m]) {
+                    const int i = qo[m] + kvb;
+                    st(vO, i, v);
+                    st(sO, i, sv);
+                    acc[1] += (double)fB[m] * (double)v;
+                    acc[2] += (double)fB[m] * (double)sv;
+                    acc[4] += (double)rhN[m] * (double)sv;
+                    acc[9] += (double)sv * (double)sv;
+                }
+            }
+#pragma unroll
+            for (int h = 0; h < H; ++h) {
+                if (usei[h]) {
+                    const int e = ei[h];
+                    const T v = cI[h].apply(pc[e], pc[e + 1], pc[e - 1], pc[e + nx], pc[e - nx], pu[e], pd[e]);
+                    Sb[bv * W + e] = (vin && oki[h]) ? fma(-al, v, rBi[h]) : T(0);
+                }
+            }
+        }
+        __syncthreads();
+
+        // ---- t_j = M s_j on plane kt (segment)
+        if (do3) {
+            const T *sc = Sb + bt * W, *su = Sb + bv * W, *sd = Sb + bp * W;
+#pragma unroll
+            for (int m = 0; m < CPT; ++m) {
+                if (oko[m]) {
+                    const int e = eo[m];
+                    const T s0 = sc[e];
+                    const T t = cC[m].apply(s0, sc[e + 1], sc[e - 1], sc[e + nx], sc[e - nx], su[e], sd[e]);
+                    st(tO, qo[m] + kt * P, t);
+                    acc[3] += (double)fC[m] * (double)t;
+                    acc[5] += (double)rhC[m] * (double)t;
+                    acc[6] += (double)t * (double)s0;
+                    acc[7] += (double)t * (double)t;
+                }
+            }
+        }
+
+        // ---- rotate
+#pragma unroll
+        for (int m = 0; m < CPT; ++m) {
+            fC[m] = fB[m];
+            fB[m] = fA[m];
+            rhC[m] = rhN[m];
+            cC[m] = cN[m];
+            rBo[m] = rAo[m];
+        }
+#pragma unroll
+        for (int h = 0; h < H; ++h) rBi[h] = rAi[h];
+        const int b0 = bt;
+        bt = bv;
+        bv = bp;
+        bp = b0;
+    }
+    reduce_and_finalize<10>(d, tr.tile, d.ntiles, acc, FinFused{});
+}
+
 // ------------------------------------------------------------------ pointwise kernels
 //
 // Block b of a set takes chunks b, b + nflat, ... of kFlatChunk cells; each
@@ -913,6 +1315,47 @@ __global__ void __launch_bounds__(kBlock) k3_kernel(LaunchSets ls) {
         }
     }
     reduce_and_finalize<2>(d, tr.tile, nflat, acc, FinK3{});
+}
+
+// Leaving the single-sync iteration (st->mat): y += alpha p (1), y += alpha p +
+// omega s (2), and for a restart (3) also r = s - omega t into slot 0 and r^ = r,
+// with step j's vectors (slot st->fpar) and scalars (alpha_prev, omega).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) mat_kernel(LaunchSets ls) {
+    const TileRef tr = locate<true>(ls);
+    const SetDesc &d = *tr.d;
+    const SolveState *st_ = d.st;
+    const int mode = st_->mat;
+    if (!mode) return;
+    const int cur = st_->fpar;
+    const T a = (T)st_->alpha_prev, om = mode == 1 ? T(0) : (T)st_->omega;
+    const T *p = Vecs<T>::p(d, cur), *s = Vecs<T>::s(d, cur), *t = Vecs<T>::t(d, cur);
+    T *y = Vecs<T>::y(d), *r0 = Vecs<T>::s(d, 0), *rh = Vecs<T>::rh(d);
+    const int n = d.n, nflat = d.nflat;
+    for (int ch = tr.tile; ch * kFlatChunk < n; ch += nflat) {
+        const int base = ch * kFlatChunk + (int)threadIdx.x;
+        T Y[kFlatU], Pv[kFlatU], Sv[kFlatU], Tt[kFlatU];
+#pragma unroll
+        for (int u = 0; u < kFlatU; ++u) {
+            const int i = min(base + kBlock * u, n - 1);
+            Y[u] = ld(y, i);
+            Pv[u] = ld(p, i);
+            Sv[u] = ld(s, i);
+            Tt[u] = ld(t, i);
+        }
+#pragma unroll
+        for (int u = 0; u < kFlatU; ++u) {
+            const int i = base + kBlock * u;
+            if (i < n) {
+                st(y, i, mode == 1 ? fma(a, Pv[u], Y[u]) : Y[u] + fma(a, Pv[u], om * Sv[u]));
+                if (mode == 3) {
+                    const T rv = fma(-om, Tt[u], Sv[u]);
+                    st(r0, i, rv);
+                    st(rh, i, rv);
+                }
+            }
+        }
+    }
 }
 
 // coefficients of A D^-1 (TR = false) or A^T D^-1 (TR = true), FP64 (for the
@@ -1335,6 +1778,26 @@ int halo_slots(int max_nx) {
     return need <= 1 ? 1 : need <= 2 ? 2 : need <= 4 ? 4 : need <= 8 ? 8 : -1;
 }
 
+size_t fused_lds_bytes(int cpt, int max_nx, int elem) {
+    return (size_t)6 * (size_t)(kBlock * cpt + 4 * max_nx) * (size_t)elem;
+}
+
+// the single-sync kernel takes 1, 2 or 4 halo slots per ring
+#define EQS_DISPATCH_FUSED(cpt, h, BODY)                                             \
+    do {                                                                             \
+        if ((cpt) == 1) {                                                            \
+            constexpr int C = 1;                                                     \
+            if ((h) == 1) { constexpr int HH = 1; BODY; }                            \
+            else if ((h) == 2) { constexpr int HH = 2; BODY; }                       \
+            else { constexpr int HH = 4; BODY; }                                     \
+        } else {                                                                     \
+            constexpr int C = 2;                                                     \
+            if ((h) == 1) { constexpr int HH = 1; BODY; }                            \
+            else if ((h) == 2) { constexpr int HH = 2; BODY; }                       \
+            else { constexpr int HH = 4; BODY; }                                     \
+        }                                                                            \
+    } while (0)
+
 #define EQS_DISPATCH(cpt, h, BODY)                                                   \
     do {                                                                             \
         if ((cpt) == 1) {                                                            \
@@ -1414,6 +1877,21 @@ hipError_t launch_kernel(Kern k, const LaunchSets &ls, int ntiles, int nflat, in
     case K_APPLY:
         if (trans) EQS_DISPATCH(cpt, h, EQS_LAUNCH((apply_kernel<C, HH, true>), grid, block, lds64, ls, x, y));
         else EQS_DISPATCH(cpt, h, EQS_LAUNCH((apply_kernel<C, HH, false>), grid, block, lds64, ls, x, y));
+        break;
+    case K_FUSED: {  // the scaled operator needs no transpose variant
+        if (h > 4) return hipErrorInvalidValue;
+        const size_t fl = fused_lds_bytes(cpt, max_nx, fp32 ? 4 : 8);
+        if (fp32) EQS_DISPATCH_FUSED(cpt, h, EQS_LAUNCH((fused_kernel<float, C, HH>), grid, block, fl, ls));
+        else EQS_DISPATCH_FUSED(cpt, h, EQS_LAUNCH((fused_kernel<double, C, HH>), grid, block, fl, ls));
+        break;
+    }
+    case K_FSETUP:
+        if (fp32) EQS_DISPATCH(cpt, h, EQS_LAUNCH((fsetup_kernel<float, C, HH>), grid, block, lds32, ls));
+        else EQS_DISPATCH(cpt, h, EQS_LAUNCH((fsetup_kernel<double, C, HH>), grid, block, lds64, ls));
+        break;
+    case K_MAT:
+        if (fp32) EQS_LAUNCH((mat_kernel<float>), fgrid, block, 0, ls);
+        else EQS_LAUNCH((mat_kernel<double>), fgrid, block, 0, ls);
         break;
     }
     return hipGetLastError();

@@ -22,8 +22,14 @@ enum Kern {
     K_GRAD,     // adjoint gradients
     K_APPLY,    // y = A x or A^T x
     K_SCALE,    // coefficients of A D^-1 (or A^T D^-1), FP64
-    K_UNSCALE   // x = y / a_P (before a recheck or a final report)
+    K_UNSCALE,  // x = y / a_P (before a recheck or a final report)
+    K_FUSED,    // single-sync iteration: both products and all ten dot products in one launch
+    K_FSETUP,   // f = M^T r^, (f, r^), (r^, r^) after a fresh start (single-sync iteration)
+    K_MAT       // form the iterate (and a restart residual) on leaving the single-sync iteration
 };
+
+// LDS bytes of the single-sync kernel (p and s, three planes each of Q + 4 nx values)
+size_t fused_lds_bytes(int cpt, int max_nx, int elem);
 
 // LDS bytes of a march kernel (three plane buffers of Q + 2 nx values)
 size_t march_lds_bytes(int cpt, int max_nx, int elem);

@@ -90,7 +90,7 @@ class Context:
 
     def layout(self, set_id=0):
         rc, v = B.eqsolve_debug_layout(self.h, set_id)
-        keys = ("cpt", "segments", "kc", "chunks", "tiles", "readbacks")
+        keys = ("cpt", "segments", "kc", "chunks", "tiles", "readbacks", "syncs", "flat_blocks")
         return dict(zip(keys, v))
 
     def autotune(self, cache_path=None, iters=6):

@@ -66,8 +66,13 @@ SHAPES = [(16, 16, 16), (33, 17, 9), (97, 31, 5), (1, 1, 7), (5, 1, 1), (1, 300,
 # launch shapes of the multi-kernel path (EQS_SMALL=0 keeps tiny grids off the one-block path)
 TILINGS = [dict(EQS_SMALL=0), dict(EQS_SMALL=0, EQS_CPT=1, EQS_KC=1), dict(EQS_SMALL=0, EQS_CPT=2, EQS_KC=3),
            dict(EQS_SMALL=0, EQS_CPT=2, EQS_KC=7)]
-# both solve paths (the one-block persistent solve takes sets of at most 4096 cells by default)
-PATHS = [dict(), dict(EQS_SMALL=0)]
+# solve paths: the one-block persistent solve (sets of at most 4096 cells, by default), the
+# single-sync march iteration (one launch per step) and the three-launch iteration
+PATHS = [dict(), dict(EQS_SMALL=0), dict(EQS_SMALL=0, EQS_SYNC=3)]
+PATH_IDS = ["small", "sync1", "sync3"]
+# the two march iterations on sets above the one-block size
+SCHEMES = [dict(), dict(EQS_SYNC=3)]
+SCHEME_IDS = ["sync1", "sync3"]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
@@ -94,10 +99,11 @@ def manufactured(orc, cfg, grid=None, recipe=None, set_id=0):
     return g, s["diags"], b, s["x_star"]
 
 
-def test_fp64_config0_residual_and_iterations(torch_dev, orc):
+@pytest.mark.parametrize("path", PATHS, ids=PATH_IDS)
+def test_fp64_config0_residual_and_iterations(torch_dev, orc, path):
     torch, dev = torch_dev
     g, diags, b, xs = manufactured(orc, 0)
-    ctx = context([g.shape])
+    ctx = context([g.shape], env=path)
     x, info = ctx.solve(dev_arrays(torch, dev, diags), dev_arrays(torch, dev, [b])[0], tol=1e-10, maxit=1000)
     xg = host(x)
     assert info["status"] == 0
@@ -117,7 +123,7 @@ def test_fp64_matches_oracle_solution(torch_dev, orc, cfg, shape):
     g, diags, b, xs = manufactured(orc, cfg, grid=W.Grid(*shape))
     xo, oinfo = orc.bicgstab(g.shape, diags, b, tol=1e-13, maxit=5000)
     assert oinfo["status"] == 0
-    for tl in [dict()] + TILINGS[:3]:
+    for tl in [dict(), dict(EQS_SYNC=3)] + TILINGS[:3] + [dict(TILINGS[2], EQS_SYNC=3)]:
         ctx = context([g.shape], env=tl)
         x, info = ctx.solve(dev_arrays(torch, dev, diags), dev_arrays(torch, dev, [b])[0], tol=1e-13, maxit=5000)
         xg = host(x)
@@ -138,18 +144,19 @@ def test_fp64_repeatable_bitwise(torch_dev, orc):
         assert np.array_equal(o, outs[0])
 
 
+@pytest.mark.parametrize("scheme", SCHEMES, ids=SCHEME_IDS)
 @pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
-def test_graph_replay_equals_eager_launches(torch_dev, orc, precision):
+def test_graph_replay_equals_eager_launches(torch_dev, orc, precision, scheme):
     # captured iteration chunks are replayed many times, with other device work and
     # synchronisations between calls; every result must equal the eager path's bit for bit
     torch, dev = torch_dev
     g, diags, b, _ = manufactured(orc, 2, grid=W.Grid(33, 65, 20))
     D = dev_arrays(torch, dev, diags)
     bd = dev_arrays(torch, dev, [b])[0]
-    eager = context([g.shape], precision=precision, env=dict(EQS_GRAPHS=0))
+    eager = context([g.shape], precision=precision, env=dict(scheme, EQS_GRAPHS=0))
     ref, rinfo = eager.solve(D, bd, tol=1e-11, maxit=3000)
     ref = host(ref)
-    graphed = context([g.shape], precision=precision)
+    graphed = context([g.shape], precision=precision, env=scheme)
     for rep in range(4):
         junk = torch.randn(1 << 20, device=dev, dtype=torch.float64).cumsum(0)  # unrelated eager work
         torch.cuda.synchronize()
@@ -180,7 +187,7 @@ def test_autotune_and_cache_roundtrip(torch_dev, orc, tmp_path):
     assert np.array_equal(host(x2), host(x))
 
 
-@pytest.mark.parametrize("path", PATHS, ids=["default", "multikernel"])
+@pytest.mark.parametrize("path", PATHS, ids=PATH_IDS)
 def test_fp64_status_codes(torch_dev, orc, path):
     torch, dev = torch_dev
     from paper_2211_15605_amd.solver import EqSolveError
@@ -215,7 +222,7 @@ def test_fp64_status_codes(torch_dev, orc, path):
         ctx.solve(D, bd, tol=0.0)
 
 
-@pytest.mark.parametrize("path", PATHS, ids=["default", "multikernel"])
+@pytest.mark.parametrize("path", PATHS, ids=PATH_IDS)
 def test_fp64_diagonal_system_one_half_step(torch_dev, orc, path):
     torch, dev = torch_dev
     g = W.Grid(9, 8, 7)
@@ -229,7 +236,7 @@ def test_fp64_diagonal_system_one_half_step(torch_dev, orc, path):
     np.testing.assert_allclose(host(x), b / P, rtol=4 * EPS, atol=0)
 
 
-@pytest.mark.parametrize("path", PATHS, ids=["default", "multikernel"])
+@pytest.mark.parametrize("path", PATHS, ids=PATH_IDS)
 def test_fp64_breakdown_integer_system(torch_dev, orc, path):
     torch, dev = torch_dev
     z = np.zeros(2)
@@ -241,11 +248,12 @@ def test_fp64_breakdown_integer_system(torch_dev, orc, path):
     assert info["status"] == 2 == oinfo["status"] and info["iters"] == 1 == oinfo["iters"]
 
 
+@pytest.mark.parametrize("scheme", SCHEMES, ids=SCHEME_IDS)
 @pytest.mark.parametrize("cfg,shape", [(0, (16, 16, 16)), (1, (32, 64, 32)), (2, (49, 97, 23))])
-def test_fp32_refine_reaches_fp64_tolerance(torch_dev, orc, cfg, shape):
+def test_fp32_refine_reaches_fp64_tolerance(torch_dev, orc, cfg, shape, scheme):
     torch, dev = torch_dev
     g, diags, b, xs = manufactured(orc, cfg, grid=W.Grid(*shape))
-    ctx = context([g.shape], precision="fp32_refine")
+    ctx = context([g.shape], precision="fp32_refine", env=scheme)
     x, info = ctx.solve(dev_arrays(torch, dev, diags), dev_arrays(torch, dev, [b])[0], tol=1e-10, maxit=20000)
     assert info["status"] == 0, info
     assert info["outer"] >= 2
@@ -254,10 +262,11 @@ def test_fp32_refine_reaches_fp64_tolerance(torch_dev, orc, cfg, shape):
     assert abs(rel - info["rel_res"]) <= 1e-3 * rel
 
 
-def test_fp32_pure_residual(torch_dev, orc):
+@pytest.mark.parametrize("scheme", SCHEMES, ids=SCHEME_IDS)
+def test_fp32_pure_residual(torch_dev, orc, scheme):
     torch, dev = torch_dev
     g, diags, b, xs = manufactured(orc, 0)
-    ctx = context([g.shape], precision="fp32")
+    ctx = context([g.shape], precision="fp32", env=scheme)
     x, info = ctx.solve(dev_arrays(torch, dev, diags), dev_arrays(torch, dev, [b])[0], tol=1e-5, maxit=2000)
     assert info["status"] == 0, info
     assert orc.rel_residual(g.shape, diags, b, host(x)) <= 1e-5
@@ -274,11 +283,12 @@ def test_fp32_pure_residual(torch_dev, orc):
 STAGGERED_SMALL = [(24, 96, 24), (25, 96, 24), (24, 97, 24), (24, 96, 25)]
 
 
+@pytest.mark.parametrize("scheme", SCHEMES, ids=SCHEME_IDS)
 @pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
-def test_batched_equals_sequential_bitwise(torch_dev, orc, precision):
+def test_batched_equals_sequential_bitwise(torch_dev, orc, precision, scheme):
     torch, dev = torch_dev
     systems = [manufactured(orc, 2, grid=W.Grid(*s), set_id=i) for i, s in enumerate(STAGGERED_SMALL)]
-    ctx = context(STAGGERED_SMALL, precision=precision)
+    ctx = context(STAGGERED_SMALL, precision=precision, env=scheme)
     Ds = [dev_arrays(torch, dev, s[1]) for s in systems]
     bs = [dev_arrays(torch, dev, [s[2]])[0] for s in systems]
     xb, infos = ctx.solve_batched(Ds, bs, tol=1e-10, maxit=2000)
@@ -306,7 +316,7 @@ def test_batched_tiny_sets_one_launch(torch_dev, orc):
         assert np.linalg.norm(host(xb[i]) - xo) <= 1e-9 * np.linalg.norm(xo)
 
 
-@pytest.mark.parametrize("path", PATHS, ids=["default", "multikernel"])
+@pytest.mark.parametrize("path", PATHS, ids=PATH_IDS)
 def test_adjoint_matches_dense_reference(torch_dev, orc, path):
     torch, dev = torch_dev
     g = W.Grid(8, 8, 8)
@@ -327,7 +337,8 @@ def test_adjoint_matches_dense_reference(torch_dev, orc, path):
         np.testing.assert_allclose(host(gd[k]), G[k], rtol=0, atol=1e-10 * np.max(np.abs(G[k])) + 1e-300)
 
 
-def test_adjoint_config3_matches_oracle(torch_dev, orc):
+@pytest.mark.parametrize("scheme", SCHEMES, ids=SCHEME_IDS)
+def test_adjoint_config3_matches_oracle(torch_dev, orc, scheme):
     torch, dev = torch_dev
     g = W.Grid(64, 64, 64)
     s = W.make_set(3, 0, grid=g, with_weights=True)
@@ -337,7 +348,7 @@ def test_adjoint_config3_matches_oracle(torch_dev, orc):
     lo, linfo = orc.bicgstab(g.shape, diags, w, tol=1e-13, maxit=2000, transpose=True)
     assert linfo["status"] == 0
     Go = orc.grad(g.shape, lo, xo)
-    ctx = context([g.shape])
+    ctx = context([g.shape], env=scheme)
     D = dev_arrays(torch, dev, diags)
     xd, wd = dev_arrays(torch, dev, [xo, w])
     gb, gd, info = ctx.adjoint(D, xd, wd, tol=1e-13, maxit=2000)
@@ -371,11 +382,12 @@ def test_autograd_function_backward(torch_dev, orc):
 
 # ---------------------------------------------------------------- full-size workloads (as benchmarked)
 
+@pytest.mark.parametrize("scheme", SCHEMES, ids=SCHEME_IDS)
 @pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
-def test_config1_full_size_residual(torch_dev, orc, precision):
+def test_config1_full_size_residual(torch_dev, orc, precision, scheme):
     torch, dev = torch_dev
     g, diags, b, xs = manufactured(orc, 1)
-    ctx = context([g.shape], precision=precision)
+    ctx = context([g.shape], precision=precision, env=scheme)
     x, info = ctx.solve(dev_arrays(torch, dev, diags), dev_arrays(torch, dev, [b])[0], tol=1e-10, maxit=20000)
     print("config1", precision, info, ctx.layout(), flush=True)
     assert info["status"] == 0
