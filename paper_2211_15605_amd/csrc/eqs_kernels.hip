@@ -1042,12 +1042,27 @@ __global__ void __launch_bounds__(kBlock) fsetup_kernel(LaunchSets ls) {
 // plane beyond the tile, and s there needs p one more row and plane out, so
 // p is formed on the segment widened by 2 nx cells each side (index e = q -
 // q0 + 2 nx in [0, Q + 4 nx)), v and s on the segment widened by nx, t on
-// the segment itself.  Step kt forms p on plane kt + 2, v and s on plane
-// kt + 1 and t on plane kt; four lead-in steps start the pipeline at k0 - 4.
+// the segment itself.  Step kt forms p on plane kt + 2d, v and s on plane
+// kt + d and t on plane kt, with d = +1 (upward march) or -1 (downward); four
+// lead-in steps start the pipeline two planes outside the chunk.  Tiles are
+// numbered chunk-fastest, so the chunks of a column of segments are
+// neighbours in the launch (the same XCD: see xcd_remap), and odd chunks march
+// downward: two chunks that share a boundary then read the planes on either
+// side of it at the same time, and the second read finds them in L2.
 // p and s planes rotate through three LDS buffers each.  Each thread owns
 // CPT cells of the segment and H cells of each of two halo rings: the inner
 // ring (the nx cells next to the segment on each side: v and s needed there)
 // and the outer ring (p only).
+// x where c holds, else +0, as a bitwise mask: a use of x that does not depend on
+// c, so the compiler cannot move x's loads under a per-lane branch (whose join
+// would wait for every load in flight), and a NaN or Inf in x never leaks out
+__device__ __forceinline__ double keep_if(bool c, double x) {
+    return __longlong_as_double(__double_as_longlong(x) & (c ? ~0ll : 0ll));
+}
+__device__ __forceinline__ float keep_if(bool c, float x) {
+    return __int_as_float(__float_as_int(x) & (c ? ~0 : 0));
+}
+
 template <typename T, int CPT, int H>
 __global__ void __launch_bounds__(kBlock) fused_kernel(LaunchSets ls) {
     constexpr int Q = kBlock * CPT;
@@ -1064,12 +1079,15 @@ __global__ void __launch_bounds__(kBlock) fused_kernel(LaunchSets ls) {
     T *sO = Vecs<T>::s(d, out), *tO = Vecs<T>::t(d, out), *pO = Vecs<T>::p(d, out), *vO = Vecs<T>::v(d, out);
     T *yv = Vecs<T>::y(d);
     const T *fv = Vecs<T>::f(d), *rhv = Vecs<T>::rh(d);
-    const int nx = d.nx, ny = d.ny, nz = d.nz, P = d.plane, S = d.S, KC = d.KC;
-    const int seg = tr.tile % S, chunk = tr.tile / S;
+    const int nx = d.nx, ny = d.ny, nz = d.nz, P = d.plane, KC = d.KC, NKC = d.NKC;
+    const int chunk = tr.tile % NKC, seg = tr.tile / NKC;
     const int q0 = seg * Q, k0 = chunk * KC, k1 = min(k0 + KC, nz);
+    const bool down = (chunk & 1) != 0;
+    const int dk = down ? -1 : 1;
     const int W = Q + 4 * nx;
     T *Pb = lds_base<T>();
     T *Sb = Pb + 3 * W;
+    T *pad = Sb + 3 * W;  // one cell per thread: the target of unused ring slots
     const int tid = threadIdx.x;
 
     // own cells
@@ -1085,9 +1103,11 @@ __global__ void __launch_bounds__(kBlock) fused_kernel(LaunchSets ls) {
         const int j = qo[m] / nx, i = qo[m] - j * nx;
         nbo[m] = Nb{i + 1 < nx, i > 0, j + 1 < ny, j > 0};
     }
-    // ring cells: slot h covers ring position hh = tid + 256 h < 2 nx
-    int qi[H], ei[H], qr[H], er[H];
-    bool oki[H], okr[H], usei[H], user[H];
+    // ring cells: slot h covers ring position hh = tid + 256 h < 2 nx; an unused
+    // slot writes its (ignored) values to the thread's pad cell
+    int qi[H], qr[H];
+    int ei[H], er[H];   // LDS offsets within a plane buffer, -1 for an unused slot
+    bool oki[H], okr[H];
     Nb nbi[H];
 #pragma unroll
     for (int h = 0; h < H; ++h) {
@@ -1096,8 +1116,7 @@ __global__ void __launch_bounds__(kBlock) fused_kernel(LaunchSets ls) {
         // inner ring: e in [nx, 2nx) and [Q + 2nx, Q + 3nx)
         const int e1 = hh < nx ? nx + hh : Q + nx + hh;
         const int q1 = q0 - 2 * nx + e1;
-        usei[h] = use;
-        ei[h] = use ? e1 : 0;
+        ei[h] = use ? e1 : -1;
         oki[h] = use && q1 >= 0 && q1 < P;
         qi[h] = min(max(q1, 0), P - 1);
         const int j = qi[h] / nx, i = qi[h] - j * nx;
@@ -1105,14 +1124,13 @@ __global__ void __launch_bounds__(kBlock) fused_kernel(LaunchSets ls) {
         // outer ring: e in [0, nx) and [Q + 3nx, Q + 4nx)
         const int e2 = hh < nx ? hh : Q + 2 * nx + hh;
         const int q2 = q0 - 2 * nx + e2;
-        user[h] = use;
-        er[h] = use ? e2 : 0;
+        er[h] = use ? e2 : -1;
         okr[h] = use && q2 >= 0 && q2 < P;
         qr[h] = min(max(q2, 0), P - 1);
     }
 
-    // values carried between steps (own cells): f on planes kt+2 / kt+1 / kt,
-    // r^ and the coefficients on plane kt, r on plane kt+1 (also inner ring)
+    // values carried between steps (own cells): f on planes kt+2d / kt+d / kt,
+    // r^ and the coefficients on plane kt, r on plane kt+d (also inner ring)
     T fA[CPT], fB[CPT], fC[CPT], rhC[CPT], rBo[CPT], rBi[H];
     Unit6<T> cC[CPT];
 #pragma unroll
@@ -1125,127 +1143,140 @@ __global__ void __launch_bounds__(kBlock) fused_kernel(LaunchSets ls) {
     double acc[10];
 #pragma unroll
     for (int i = 0; i < 10; ++i) acc[i] = 0.0;
+    // At a fresh start r = s (the stored residual) and p = r: the terms of step
+    // j-1 are masked off bitwise (their buffers may hold anything) and their
+    // scalars zeroed, so no branch depends on `fresh` either.
+    const T omf = fresh ? T(0) : om, bef = fresh ? T(0) : be;
+    const bool cont = !fresh;
 
-    int bt = 0, bv = 1, bp = 2;  // LDS slots of planes kt, kt+1, kt+2 (kt-1 shares kt+2's slot)
-    for (int kt = k0 - 4; kt < k1; ++kt) {
-        const int kp = kt + 2, kv = kt + 1;
+    int bt = 0, bv = 1, bp = 2;  // LDS slots of planes kt, kt+d, kt+2d (kt-d shares kt+2d's slot)
+    const int nsteps = k1 - k0 + 4;
+    for (int it = 0; it < nsteps; ++it) {
+        const int kt = down ? k1 + 3 - it : k0 - 4 + it;
+        const int kp = kt + 2 * dk, kv = kt + dk;
         const bool pin = kp >= 0 && kp < nz, pown = kp >= k0 && kp < k1;
-        const bool do2 = kt >= k0 - 2, vin = kv >= 0 && kv < nz, vown = kv >= k0 && kv < k1;
-        const bool do3 = kt >= k0;
+        const bool do2 = it >= 2, vin = kv >= 0 && kv < nz, vown = kv >= k0 && kv < k1;
+        const bool do3 = it >= 4;
         const int kpb = min(max(kp, 0), nz - 1) * P, kvb = min(max(kv, 0), nz - 1) * P;
 
-        // ---- loads: step j-1 vectors on plane kp, coefficients on plane kv
+        // ---- loads: step j-1 vectors on plane kp, coefficients on plane kv.
+        // Every load is unconditional, at a plane index clamped into the range
+        // where it is used; what a step outside that range loads is read again
+        // when the range is reached.
         T sIo[CPT], tIo[CPT], pIo[CPT], vIo[CPT], yo[CPT], rhN[CPT];
         T sIi[H], tIi[H], pIi[H], vIi[H], sIr[H], tIr[H], pIr[H], vIr[H];
         Unit6<T> cN[CPT], cI[H];
-#pragma unroll
-        for (int m = 0; m < CPT; ++m) {
-            const int i = qo[m] + kpb;
-            sIo[m] = ld(sI, i); tIo[m] = ld(tI, i); pIo[m] = ld(pI, i); vIo[m] = ld(vI, i);
-        }
-#pragma unroll
-        for (int h = 0; h < H; ++h) {
-            const int i = qi[h] + kpb, r = qr[h] + kpb;
-            sIi[h] = ld(sI, i); tIi[h] = ld(tI, i); pIi[h] = ld(pI, i); vIi[h] = ld(vI, i);
-            sIr[h] = ld(sI, r); tIr[h] = ld(tI, r); pIr[h] = ld(pI, r); vIr[h] = ld(vI, r);
-        }
-        if (pown) {
-#pragma unroll
-            for (int m = 0; m < CPT; ++m) {
-                yo[m] = ld(yv, qo[m] + kpb);
-                fA[m] = ld(fv, qo[m] + kpb);
-            }
-        }
-        if (do2) {
+        {
+            const int kyb = min(max(kp, k0), k1 - 1) * P;  // y, f: own planes
+            const int krb = min(max(kv, k0), k1 - 1) * P;  // r^: own planes
+            const int kcb = min(max(min(max(kv, k0 - 1), k1), 0), nz - 1) * P;  // coefficients: k0-1 .. k1
             const bool up = kv + 1 < nz, dn = kv > 0;
 #pragma unroll
-            for (int m = 0; m < CPT; ++m) cN[m].load(as, qo[m] + kvb, nbo[m], up, dn);
-#pragma unroll
-            for (int h = 0; h < H; ++h) cI[h].load(as, qi[h] + kvb, nbi[h], up, dn);
-            if (vown) {
-#pragma unroll
-                for (int m = 0; m < CPT; ++m) rhN[m] = ld(rhv, qo[m] + kvb);
+            for (int m = 0; m < CPT; ++m) {
+                const int i = qo[m] + kpb;
+                sIo[m] = ld(sI, i); tIo[m] = ld(tI, i); pIo[m] = ld(pI, i); vIo[m] = ld(vI, i);
+                yo[m] = ld(yv, qo[m] + kyb);
+                fA[m] = ld(fv, qo[m] + kyb);
             }
+#pragma unroll
+            for (int h = 0; h < H; ++h) {
+                const int i = qi[h] + kpb, r = qr[h] + kpb;
+                sIi[h] = ld(sI, i); tIi[h] = ld(tI, i); pIi[h] = ld(pI, i); vIi[h] = ld(vI, i);
+                sIr[h] = ld(sI, r); tIr[h] = ld(tI, r); pIr[h] = ld(pI, r); vIr[h] = ld(vI, r);
+            }
+#pragma unroll
+            for (int m = 0; m < CPT; ++m) {
+                cN[m].load(as, qo[m] + kcb, nbo[m], up, dn);
+                rhN[m] = ld(rhv, qo[m] + krb);
+            }
+#pragma unroll
+            for (int h = 0; h < H; ++h) cI[h].load(as, qi[h] + kcb, nbi[h], up, dn);
         }
 
         // ---- p_j on plane kp (segment + both rings), r_j kept for plane kp
         T rAo[CPT], rAi[H];
+        T *pw = Pb + bp * W;
 #pragma unroll
         for (int m = 0; m < CPT; ++m) {
-            T r = fresh ? sIo[m] : fma(-om, tIo[m], sIo[m]);
-            T pv = fresh ? r : fma(be, fma(-om, vIo[m], pIo[m]), r);
             const bool ok = pin && oko[m];
-            r = ok ? r : T(0);
-            pv = ok ? pv : T(0);
-            Pb[bp * W + eo[m]] = pv;
+            const T r = keep_if(ok, fma(-omf, keep_if(cont, tIo[m]), sIo[m]));
+            const T pv = keep_if(ok, fma(bef, keep_if(cont, fma(-om, vIo[m], pIo[m])), r));
+            pw[eo[m]] = pv;
             rAo[m] = r;
-            if (pown && oko[m]) {
+            const bool own = pown && oko[m];
+            const T yn = yo[m] + fma(ap, pIo[m], om * sIo[m]);
+            asm volatile("" ::"v"(yn));  // formed on every lane, before the branch (no sunk loads)
+            if (own) {
                 const int i = qo[m] + kpb;
                 st(pO, i, pv);
-                if (!fresh) st(yv, i, yo[m] + fma(ap, pIo[m], om * sIo[m]));
-                acc[0] += (double)fA[m] * (double)pv;
-                acc[8] += (double)r * (double)r;
+                if (!fresh) st(yv, i, yn);
             }
+            acc[0] += (double)keep_if(own, fA[m]) * (double)pv;
+            acc[8] += (double)keep_if(own, r) * (double)r;
         }
 #pragma unroll
         for (int h = 0; h < H; ++h) {
-            T r = fresh ? sIi[h] : fma(-om, tIi[h], sIi[h]);
-            T pv = fresh ? r : fma(be, fma(-om, vIi[h], pIi[h]), r);
             const bool ok = pin && oki[h];
-            rAi[h] = ok ? r : T(0);
-            if (usei[h]) Pb[bp * W + ei[h]] = ok ? pv : T(0);
-            T r2 = fresh ? sIr[h] : fma(-om, tIr[h], sIr[h]);
-            T pv2 = fresh ? r2 : fma(be, fma(-om, vIr[h], pIr[h]), r2);
-            if (user[h]) Pb[bp * W + er[h]] = (pin && okr[h]) ? pv2 : T(0);
+            const T r = keep_if(ok, fma(-omf, keep_if(cont, tIi[h]), sIi[h]));
+            const T pv = keep_if(ok, fma(bef, keep_if(cont, fma(-om, vIi[h], pIi[h])), r));
+            rAi[h] = r;
+            (ei[h] >= 0 ? pw[ei[h]] : pad[tid]) = pv;
+            const bool ok2 = pin && okr[h];
+            const T r2 = keep_if(ok2, fma(-omf, keep_if(cont, tIr[h]), sIr[h]));
+            const T pv2 = keep_if(ok2, fma(bef, keep_if(cont, fma(-om, vIr[h], pIr[h])), r2));
+            (er[h] >= 0 ? pw[er[h]] : pad[tid]) = pv2;
         }
         __syncthreads();
 
         // ---- v_j = M p_j and s_j = r_j - alpha_j v_j on plane kv (segment + inner ring)
         if (do2) {
-            const T *pc = Pb + bv * W, *pu = Pb + bp * W, *pd = Pb + bt * W;
+            // plane kv's neighbours: kv + d = kp, kv - d = kt
+            const T *pc = Pb + bv * W, *pu = Pb + (down ? bt : bp) * W, *pd = Pb + (down ? bp : bt) * W;
+            T *sw = Sb + bv * W;
 #pragma unroll
             for (int m = 0; m < CPT; ++m) {
                 const int e = eo[m];
                 const T v = cN[m].apply(pc[e], pc[e + 1], pc[e - 1], pc[e + nx], pc[e - nx], pu[e], pd[e]);
                 const bool ok = vin && oko[m];
-                const T sv = ok ? fma(-al, v, rBo[m]) : T(0);
-                Sb[bv * W + e] = sv;
-                if (vown && oko[m]) {
+                const T sv = keep_if(ok, fma(-al, v, rBo[m]));
+                sw[e] = sv;
+                const bool own = vown && oko[m];
+                if (own) {
                     const int i = qo[m] + kvb;
                     st(vO, i, v);
                     st(sO, i, sv);
-                    acc[1] += (double)fB[m] * (double)v;
-                    acc[2] += (double)fB[m] * (double)sv;
-                    acc[4] += (double)rhN[m] * (double)sv;
-                    acc[9] += (double)sv * (double)sv;
                 }
+                const T vk = keep_if(own, v), sk = keep_if(own, sv);
+                acc[1] += (double)fB[m] * (double)vk;
+                acc[2] += (double)fB[m] * (double)sk;
+                acc[4] += (double)keep_if(own, rhN[m]) * (double)sk;
+                acc[9] += (double)sk * (double)sk;
             }
 #pragma unroll
             for (int h = 0; h < H; ++h) {
-                if (usei[h]) {
-                    const int e = ei[h];
-                    const T v = cI[h].apply(pc[e], pc[e + 1], pc[e - 1], pc[e + nx], pc[e - nx], pu[e], pd[e]);
-                    Sb[bv * W + e] = (vin && oki[h]) ? fma(-al, v, rBi[h]) : T(0);
-                }
+                const int e = ei[h] >= 0 ? ei[h] : 2 * nx;  // an unused slot reads a valid cell, writes its pad
+                const T v = cI[h].apply(pc[e], pc[e + 1], pc[e - 1], pc[e + nx], pc[e - nx], pu[e], pd[e]);
+                const T sv = keep_if(vin && oki[h], fma(-al, v, rBi[h]));
+                (ei[h] >= 0 ? sw[e] : pad[tid]) = sv;
             }
         }
         __syncthreads();
 
         // ---- t_j = M s_j on plane kt (segment)
         if (do3) {
-            const T *sc = Sb + bt * W, *su = Sb + bv * W, *sd = Sb + bp * W;
+            // plane kt's neighbours: kt + d = kv, kt - d (slot of kt + 2d)
+            const T *sc = Sb + bt * W, *su = Sb + (down ? bp : bv) * W, *sd = Sb + (down ? bv : bp) * W;
 #pragma unroll
             for (int m = 0; m < CPT; ++m) {
-                if (oko[m]) {
-                    const int e = eo[m];
-                    const T s0 = sc[e];
-                    const T t = cC[m].apply(s0, sc[e + 1], sc[e - 1], sc[e + nx], sc[e - nx], su[e], sd[e]);
-                    st(tO, qo[m] + kt * P, t);
-                    acc[3] += (double)fC[m] * (double)t;
-                    acc[5] += (double)rhC[m] * (double)t;
-                    acc[6] += (double)t * (double)s0;
-                    acc[7] += (double)t * (double)t;
-                }
+                const int e = eo[m];
+                const T s0 = sc[e];
+                const T t = cC[m].apply(s0, sc[e + 1], sc[e - 1], sc[e + nx], sc[e - nx], su[e], sd[e]);
+                if (oko[m]) st(tO, qo[m] + kt * P, t);
+                const T tk = keep_if(oko[m], t);
+                acc[3] += (double)fC[m] * (double)tk;
+                acc[5] += (double)rhC[m] * (double)tk;
+                acc[6] += (double)tk * (double)s0;
+                acc[7] += (double)tk * (double)tk;
             }
         }
 
@@ -1779,7 +1810,8 @@ int halo_slots(int max_nx) {
 }
 
 size_t fused_lds_bytes(int cpt, int max_nx, int elem) {
-    return (size_t)6 * (size_t)(kBlock * cpt + 4 * max_nx) * (size_t)elem;
+    // p and s: three planes each; plus one pad cell per thread
+    return ((size_t)6 * (size_t)(kBlock * cpt + 4 * max_nx) + kBlock) * (size_t)elem;
 }
 
 // the single-sync kernel takes 1, 2 or 4 halo slots per ring
