@@ -1080,9 +1080,15 @@ __global__ void __launch_bounds__(kBlock) fused_kernel(LaunchSets ls) {
     T *yv = Vecs<T>::y(d);
     const T *fv = Vecs<T>::f(d), *rhv = Vecs<T>::rh(d);
     const int nx = d.nx, ny = d.ny, nz = d.nz, P = d.plane, KC = d.KC, NKC = d.NKC;
-    const int chunk = tr.tile % NKC, seg = tr.tile / NKC;
+    // every other step runs the tiles in reverse order and each march in the
+    // opposite direction, so a step starts on the planes the previous one
+    // touched last (still in the MALL, the memory-side cache) and ends on those
+    // the next step will start from
+    const bool flip = in != 0;
+    const int tl = flip ? d.ntiles - 1 - tr.tile : tr.tile;
+    const int chunk = tl % NKC, seg = tl / NKC;
     const int q0 = seg * Q, k0 = chunk * KC, k1 = min(k0 + KC, nz);
-    const bool down = (chunk & 1) != 0;
+    const bool down = ((chunk & 1) != 0) != flip;
     const int dk = down ? -1 : 1;
     const int W = Q + 4 * nx;
     T *Pb = lds_base<T>();
