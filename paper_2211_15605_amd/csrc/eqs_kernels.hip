@@ -1592,7 +1592,7 @@ __global__ void __launch_bounds__(kBlock) grad_kernel(LaunchSets ls) {
 
 // ------------------------------------------------------------------ one-block persistent solve (tiny sets)
 //
-// For a set of at most kSmallThreads * 8 cells, one 512-thread block runs the
+// For a set of at most kSmallThreads * 4 cells, one 512-thread block runs the
 // whole FP64 solve in a single launch: every cell's coefficients and vectors
 // live in registers (cell c = tid + kSmallThreads * m), the stencil operand is
 // exchanged through LDS, and the scalar updates are the same state-machine
@@ -1600,7 +1600,7 @@ __global__ void __launch_bounds__(kBlock) grad_kernel(LaunchSets ls) {
 // independent blocks of one launch.
 
 constexpr int kSmallThreads = 512;  // 2 waves per SIMD: up to 256 VGPRs per lane for the register-resident vectors
-constexpr int kSmallMaxCells = kSmallThreads * 8;
+constexpr int kSmallMaxCells = kSmallThreads * 4;
 
 template <int NV>
 __device__ __forceinline__ void small_block_sum(double (&v)[NV], double *red) {
@@ -1791,12 +1791,9 @@ hipError_t launch_small(const LaunchSets &ls, int max_n, bool trans, hipStream_t
     } else if (cpc == 2) {
         if (trans) hipLaunchKernelGGL((small_kernel<2, true>), grid, block, 0, stream, ls);
         else hipLaunchKernelGGL((small_kernel<2, false>), grid, block, 0, stream, ls);
-    } else if (cpc <= 4) {
+    } else {
         if (trans) hipLaunchKernelGGL((small_kernel<4, true>), grid, block, 0, stream, ls);
         else hipLaunchKernelGGL((small_kernel<4, false>), grid, block, 0, stream, ls);
-    } else {
-        if (trans) hipLaunchKernelGGL((small_kernel<8, true>), grid, block, 0, stream, ls);
-        else hipLaunchKernelGGL((small_kernel<8, false>), grid, block, 0, stream, ls);
     }
     return hipGetLastError();
 }

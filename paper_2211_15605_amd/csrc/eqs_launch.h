@@ -38,7 +38,7 @@ size_t march_lds_bytes(int cpt, int max_nx, int elem);
 int halo_slots(int max_nx);
 
 // cells of the largest set the one-block persistent solve takes
-constexpr int kSmallSolveMaxCells = 4096;
+constexpr int kSmallSolveMaxCells = 2048;
 
 // one-block persistent FP64 solve of every set of the launch table (each
 // at most kSmallSolveMaxCells cells): one block per set, one launch

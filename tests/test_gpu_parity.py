@@ -66,7 +66,7 @@ SHAPES = [(16, 16, 16), (33, 17, 9), (97, 31, 5), (1, 1, 7), (5, 1, 1), (1, 300,
 # launch shapes of the multi-kernel path (EQS_SMALL=0 keeps tiny grids off the one-block path)
 TILINGS = [dict(EQS_SMALL=0), dict(EQS_SMALL=0, EQS_CPT=1, EQS_KC=1), dict(EQS_SMALL=0, EQS_CPT=2, EQS_KC=3),
            dict(EQS_SMALL=0, EQS_CPT=2, EQS_KC=7)]
-# solve paths: the one-block persistent solve (sets of at most 4096 cells, by default), the
+# solve paths: the one-block persistent solve (sets of at most 2048 cells, by default), the
 # single-sync march iteration (one launch per step) and the three-launch iteration
 PATHS = [dict(), dict(EQS_SMALL=0), dict(EQS_SMALL=0, EQS_SYNC=3)]
 PATH_IDS = ["small", "sync1", "sync3"]
@@ -114,6 +114,28 @@ def test_fp64_config0_residual_and_iterations(torch_dev, orc, path):
     # rounding differs, so iteration counts may differ slightly (parity unpinned)
     assert abs(info["iters"] - oinfo["iters"]) <= 3, (info, oinfo)
     assert np.max(np.abs(xg - xs)) <= orc.forward_error_certificate(g.shape, diags, b, xg) * (1 + 1e-6)
+
+
+@pytest.mark.parametrize("shape", [(12, 12, 12), (16, 8, 16), (1, 2048, 1), (1, 64, 32), (1, 1, 2049)])
+def test_fp64_one_block_path_sizes(torch_dev, orc, shape):
+    # the one-block solve up to its 2048-cell limit (and one cell past it, on the march path):
+    # the same solution as the oracle, and the same as the march path's
+    torch, dev = torch_dev
+    g, diags, b, xs = manufactured(orc, 0, grid=W.Grid(*shape))
+    xo, oinfo = orc.bicgstab(g.shape, diags, b, tol=1e-13, maxit=5000)
+    D = dev_arrays(torch, dev, diags)
+    bd = dev_arrays(torch, dev, [b])[0]
+    out = []
+    for env in (dict(), dict(EQS_SMALL=0)):
+        ctx = context([g.shape], env=env)
+        x, info = ctx.solve(D, bd, tol=1e-13, maxit=5000)
+        xg = host(x)
+        assert info["status"] == 0, (env, info)
+        assert orc.rel_residual(g.shape, diags, b, xg) <= 1e-13
+        assert np.linalg.norm(xg - xo) <= 1e-10 * np.linalg.norm(xo), env
+        out.append(xg)
+        ctx.close()
+    assert np.linalg.norm(out[0] - out[1]) <= 1e-10 * np.linalg.norm(xo)
 
 
 @pytest.mark.parametrize("cfg,shape", [(0, (16, 16, 16)), (0, (37, 23, 11)), (3, (64, 64, 64)),
@@ -302,7 +324,7 @@ def test_batched_equals_sequential_bitwise(torch_dev, orc, precision, scheme):
 def test_batched_tiny_sets_one_launch(torch_dev, orc):
     # four tiny staggered sets: one block per set, each equal to its own solve
     torch, dev = torch_dev
-    shapes = [(10, 20, 10), (11, 20, 10), (10, 21, 10), (10, 20, 11)]
+    shapes = [(8, 16, 8), (9, 16, 8), (8, 17, 8), (8, 16, 9)]
     systems = [manufactured(orc, 2, grid=W.Grid(*sh), set_id=i) for i, sh in enumerate(shapes)]
     ctx = context(shapes)
     Ds = [dev_arrays(torch, dev, s[1]) for s in systems]
