@@ -82,7 +82,11 @@ typedef struct {
  * of one time step, e.g. p', u, v, w on their staggered grids).  Allocates
  * all device workspace for `precision` once (no allocation happens in the
  * solve calls).  hip_stream is a hipStream_t (NULL = the default stream).
- * Grids need 1 <= nx, ny, nz and nx*ny*nz < 2^31.
+ * Grids need 1 <= nx <= 1024 (a stencil pass stages one row of nx cells on
+ * each side of a plane segment in LDS), 1 <= ny, nz and nx*ny*nz < 2^31;
+ * 1 <= nsets <= 8.  Returns EQS_OK, EQS_ERR_ARG (grids, nsets, precision),
+ * EQS_ERR_NOMEM or EQS_ERR_HIP; *ctx is NULL unless EQS_OK.  The argument
+ * checks come before any HIP call.
  */
 int eqsolve_create(eqs_ctx **ctx, const eqs_grid *grids, int32_t nsets, int32_t precision,
                    void *hip_stream);

@@ -79,6 +79,19 @@ def _diag_ptrs(diags):
     return arrs, ctypes.cast(ptrs, ctypes.POINTER(ctypes.c_void_p))
 
 
+class OrcMgParams(ctypes.Structure):
+    _fields_ = [
+        ("omega", ctypes.c_double),
+        ("gamma", ctypes.c_double),
+        ("coarse_sweeps", ctypes.c_int32),
+        ("coarse_cells", ctypes.c_int32),
+    ]
+
+
+def mg_params(omega=0.8, gamma=1.0, coarse_sweeps=30, coarse_cells=512):
+    return OrcMgParams(float(omega), float(gamma), int(coarse_sweeps), int(coarse_cells))
+
+
 class Oracle:
     """The oracle's functions bound to one compiled copy of orc.c."""
 
@@ -94,6 +107,16 @@ class Oracle:
                                                         ctypes.c_int, ctypes.POINTER(OrcInfo),
                                                         ctypes.c_void_p]
         L.orc_bicgstab.restype = ctypes.c_int
+        L.orc_bicgstab_mg.argtypes = [ctypes.c_int] * 3 + [dpp, ctypes.c_void_p, ctypes.c_void_p,
+                                                           ctypes.c_double, ctypes.c_int,
+                                                           ctypes.POINTER(OrcMgParams), ctypes.POINTER(OrcInfo),
+                                                           ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)]
+        L.orc_bicgstab_mg.restype = ctypes.c_int
+        L.orc_mg_coarsen.argtypes = [ctypes.c_int] * 3 + [dpp, ctypes.POINTER(ctypes.c_int), dpp]
+        L.orc_mg_coarsen.restype = ctypes.c_int
+        L.orc_mg_apply.argtypes = [ctypes.c_int] * 3 + [dpp, ctypes.POINTER(OrcMgParams), ctypes.c_void_p,
+                                                        ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)]
+        L.orc_mg_apply.restype = ctypes.c_int
         L.orc_grad.argtypes = [ctypes.c_int] * 3 + [ctypes.c_void_p, ctypes.c_void_p, dpp]
         L.orc_grad.restype = None
         L.orc_set_threads.argtypes = [ctypes.c_int]
@@ -140,6 +163,53 @@ class Oracle:
         d = info.as_dict()
         if history:
             return x, d, hist[: max(d["iters"], 0)]
+        return x, d
+
+    def mg_coarsen(self, shape, diags):
+        """Galerkin coarse operator (P^T A P, piecewise-constant P over 2x2x2 aggregates).
+        Returns (coarse shape, 7 coarse diagonals)."""
+        nx, ny, nz = shape
+        keep, dp = _diag_ptrs(diags)
+        cshape = ((nx + 1) // 2, (ny + 1) // 2, (nz + 1) // 2)
+        nc = cshape[0] * cshape[1] * cshape[2]
+        out = [np.empty(nc) for _ in range(7)]
+        op = ctypes.cast((ctypes.c_void_p * 7)(*[o.ctypes.data for o in out]), ctypes.POINTER(ctypes.c_void_p))
+        dims = (ctypes.c_int * 3)()
+        rc = self.L.orc_mg_coarsen(nx, ny, nz, dp, dims, op)
+        assert rc == 0 and tuple(dims) == cshape
+        return cshape, out
+
+    def mg_apply(self, shape, diags, r, params=None):
+        """z = B^{-1} r, one V-cycle; returns (z, number of levels)."""
+        nx, ny, nz = shape
+        keep, dp = _diag_ptrs(diags)
+        r = _f64(r).ravel()
+        z = np.empty_like(r)
+        prm = params if params is not None else mg_params()
+        lv = ctypes.c_int(0)
+        rc = self.L.orc_mg_apply(nx, ny, nz, dp, ctypes.byref(prm), _ptr(r), _ptr(z), ctypes.byref(lv))
+        assert rc == 0, rc
+        return z, lv.value
+
+    def bicgstab_mg(self, shape, diags, b, x0=None, tol=1e-10, maxit=1000, params=None, history=False):
+        """BiCGSTAB with the multigrid V-cycle as right preconditioner.
+        Returns (x, info[, history]); info also carries the number of levels."""
+        nx, ny, nz = shape
+        n = nx * ny * nz
+        keep, dp = _diag_ptrs(diags)
+        b = _f64(b).ravel()
+        x = np.zeros(n) if x0 is None else _f64(x0).ravel().copy()
+        assert b.size == n and x.size == n and all(a.size == n for a in keep)
+        info = OrcInfo()
+        prm = params if params is not None else mg_params()
+        hist = np.full(max(int(maxit), 1), np.nan) if history else None
+        lv = ctypes.c_int(0)
+        self.L.orc_bicgstab_mg(nx, ny, nz, dp, _ptr(b), _ptr(x), float(tol), int(maxit), ctypes.byref(prm),
+                               ctypes.byref(info), _ptr(hist) if history else None, ctypes.byref(lv))
+        d = info.as_dict()
+        d["levels"] = lv.value
+        if history:
+            return x, d, hist[: d["iters"]]
         return x, d
 
     def grad(self, shape, lam, x):

@@ -33,6 +33,12 @@
  * Dot products are summed in fixed 4096-element chunks, then the chunk sums
  * in index order, so every result is independent of the OpenMP thread count.
  *
+ * Addition beyond the paper (its solver is unpreconditioned or Jacobi): an
+ * aggregation multigrid V-cycle as a second right preconditioner, aimed at
+ * the pressure-correction system, whose Jacobi iteration count grows with
+ * the grid (Sec. 3.1 notes the pressure equation needs many more iterations
+ * than momentum).  Its definition is below (orc_mg_*).
+ *
  * Every function here is pinned by tests that do not retype it: closed-form
  * eigenpairs of constant-coefficient tridiagonal-Toeplitz Kronecker sums, the
  * adjoint identity, row-sum invariants, dense LU, banded LU, exact finite
@@ -158,11 +164,190 @@ static double residual(int nx, int ny, int nz, const double *const *a, int trans
     return orc_dot(n, r, r);
 }
 
-/* w = M^{-1} u with M = diag(a_P) or M = I */
-static void precond(long n, const double *ap, int jacobi, const double *u, double *w)
+/* ---------------------------------------------------------------- multigrid
+ *
+ * Aggregation multigrid V-cycle B^{-1}, used as a right preconditioner.
+ *
+ * Levels: level 0 is the system as passed; level l+1 has dimensions
+ * ((nx+1)/2, (ny+1)/2, (nz+1)/2) (a dimension of 1 stays 1) and aggregates
+ * the fine cells (i, j, k) with (i/2, j/2, k/2) equal.  Coarsening stops at
+ * a level of at most coarse_cells cells (or 1 x 1 x 1).
+ *
+ * Interpolation P is piecewise constant (a coarse value copied to every
+ * cell of its aggregate), restriction is R = P^T (sum over the aggregate)
+ * and the coarse operator is the Galerkin product P^T A P, which is again a
+ * 7-point operator in the same Patankar form:
+ *   coarse a_P(C)  = sum over c in C of a_P(c), minus a_nb(c) for every link
+ *                    from c to a neighbour inside C;
+ *   coarse a_nb(C) = sum of a_nb(c) over the links from c in C to cells of
+ *                    the neighbouring aggregate in direction nb.
+ *
+ * V-cycle at level l on right-hand side r (D = diag(a_P), weight omega):
+ *   coarsest level: z = 0, then coarse_sweeps times z += omega D^{-1} (r - A z);
+ *   otherwise:      z1 = omega D^{-1} r
+ *                   e  = V-cycle at level l+1 on R (r - A z1)
+ *                   z2 = z1 + gamma P e
+ *                   z  = z2 + omega D^{-1} (r - A z2)
+ * A fixed number of sweeps everywhere makes B^{-1} a fixed linear map, as
+ * BiCGSTAB's preconditioner must be.
+ */
+typedef struct {
+    double omega;       /* damped-Jacobi weight */
+    double gamma;       /* scale of the coarse correction */
+    int32_t coarse_sweeps;
+    int32_t coarse_cells;
+} orc_mg_params;
+
+#define ORC_MG_MAX_LEVELS 24
+
+typedef struct {
+    int nlev;
+    int dims[ORC_MG_MAX_LEVELS][3];
+    double *coef[ORC_MG_MAX_LEVELS][7];  /* level 0 points at the caller's arrays */
+    double *work;                          /* per level: q, z1, rc, e (largest level size) */
+    orc_mg_params prm;
+} orc_mg;
+
+/* Galerkin coarse operator of one level (see above); returns 0, or ORC_BAD_ARG */
+int orc_mg_coarsen(int nx, int ny, int nz, const double *const *a, int *cdims, double *const *ac)
 {
+    if (nx < 1 || ny < 1 || nz < 1 || !a || !cdims || !ac) return ORC_BAD_ARG;
+    const int cx = (nx + 1) / 2, cy = (ny + 1) / 2, cz = (nz + 1) / 2;
+    cdims[0] = cx;
+    cdims[1] = cy;
+    cdims[2] = cz;
+    const long nc = (long)cx * cy * cz;
+    for (int q = 0; q < 7; q++) memset(ac[q], 0, (size_t)nc * sizeof(double));
+    for (int k = 0; k < nz; k++)
+        for (int j = 0; j < ny; j++)
+            for (int i = 0; i < nx; i++) {
+                const long c = i + (long)nx * (j + (long)ny * k);
+                const long C = i / 2 + (long)cx * (j / 2 + (long)cy * (k / 2));
+                ac[SLOT_P][C] += a[SLOT_P][c];
+                /* each link: direction slot, neighbour (i2, j2, k2) */
+                const int nbi[6] = {i + 1, i - 1, i, i, i, i};
+                const int nbj[6] = {j, j, j + 1, j - 1, j, j};
+                const int nbk[6] = {k, k, k, k, k + 1, k - 1};
+                for (int d = 0; d < 6; d++) {
+                    const int i2 = nbi[d], j2 = nbj[d], k2 = nbk[d];
+                    if (i2 < 0 || i2 >= nx || j2 < 0 || j2 >= ny || k2 < 0 || k2 >= nz) continue;
+                    const double coef = a[SLOT_E + d][c];
+                    if (i2 / 2 == i / 2 && j2 / 2 == j / 2 && k2 / 2 == k / 2)
+                        ac[SLOT_P][C] -= coef;        /* link inside the aggregate */
+                    else
+                        ac[SLOT_E + d][C] += coef;    /* link to the neighbouring aggregate */
+                }
+            }
+    return 0;
+}
+
+static void mg_free(orc_mg *m)
+{
+    for (int l = 1; l < m->nlev; l++)
+        free(m->coef[l][0]);
+    free(m->work);
+}
+
+static int mg_build(orc_mg *m, int nx, int ny, int nz, const double *const *a, const orc_mg_params *prm)
+{
+    memset(m, 0, sizeof(*m));
+    m->prm = *prm;
+    m->nlev = 1;
+    m->dims[0][0] = nx;
+    m->dims[0][1] = ny;
+    m->dims[0][2] = nz;
+    for (int q = 0; q < 7; q++) m->coef[0][q] = (double *)a[q];
+    for (;;) {
+        const int l = m->nlev - 1;
+        const int *dm = m->dims[l];
+        const long n = (long)dm[0] * dm[1] * dm[2];
+        if (n <= prm->coarse_cells || n == 1 || m->nlev == ORC_MG_MAX_LEVELS) break;
+        const long nc = (long)((dm[0] + 1) / 2) * ((dm[1] + 1) / 2) * ((dm[2] + 1) / 2);
+        double *blk = (double *)malloc((size_t)nc * 7 * sizeof(double));
+        if (!blk) { mg_free(m); return ORC_NOMEM; }
+        for (int q = 0; q < 7; q++) m->coef[l + 1][q] = blk + q * nc;
+        orc_mg_coarsen(dm[0], dm[1], dm[2], (const double *const *)m->coef[l], m->dims[l + 1], m->coef[l + 1]);
+        m->nlev++;
+    }
+    long tot = 0;
+    for (int l = 0; l < m->nlev; l++) tot += 4L * m->dims[l][0] * m->dims[l][1] * m->dims[l][2];
+    m->work = (double *)malloc((size_t)tot * sizeof(double));
+    if (!m->work) { mg_free(m); return ORC_NOMEM; }
+    return 0;
+}
+
+static void mg_vcycle(const orc_mg *m, int l, double *wk, const double *r, double *z)
+{
+    const int nx = m->dims[l][0], ny = m->dims[l][1], nz = m->dims[l][2];
+    const long n = (long)nx * ny * nz;
+    const double *const *a = (const double *const *)m->coef[l];
+    const double *ap = a[SLOT_P];
+    const double w = m->prm.omega;
+    double *q = wk, *z1 = wk + n;
+    if (l == m->nlev - 1) {
+        for (long c = 0; c < n; c++) z[c] = 0.0;
+        for (int it = 0; it < m->prm.coarse_sweeps; it++) {
+            orc_apply(nx, ny, nz, a, z, q, 0);
+            for (long c = 0; c < n; c++) z[c] += w * (r[c] - q[c]) / ap[c];
+        }
+        return;
+    }
+    const int cx = m->dims[l + 1][0], cy = m->dims[l + 1][1];
+    const long nc = (long)cx * cy * m->dims[l + 1][2];
+    double *rc = wk + 2 * n, *e = rc + nc, *wk_next = e + nc;
+    for (long c = 0; c < n; c++) z1[c] = w * r[c] / ap[c];
+    orc_apply(nx, ny, nz, a, z1, q, 0);
+    for (long C = 0; C < nc; C++) rc[C] = 0.0;
+    for (int k = 0; k < nz; k++)
+        for (int j = 0; j < ny; j++)
+            for (int i = 0; i < nx; i++) {
+                const long c = i + (long)nx * (j + (long)ny * k);
+                rc[i / 2 + (long)cx * (j / 2 + (long)cy * (k / 2))] += r[c] - q[c];
+            }
+    mg_vcycle(m, l + 1, wk_next, rc, e);
+    for (int k = 0; k < nz; k++)
+        for (int j = 0; j < ny; j++)
+            for (int i = 0; i < nx; i++) {
+                const long c = i + (long)nx * (j + (long)ny * k);
+                z1[c] += m->prm.gamma * e[i / 2 + (long)cx * (j / 2 + (long)cy * (k / 2))];
+            }
+    orc_apply(nx, ny, nz, a, z1, q, 0);
+    for (long c = 0; c < n; c++) z[c] = z1[c] + w * (r[c] - q[c]) / ap[c];
+}
+
+/* z = B^{-1} r: one V-cycle of the hierarchy built for this system.  levels, if
+ * not NULL, receives the number of levels. */
+int orc_mg_apply(int nx, int ny, int nz, const double *const *a, const orc_mg_params *prm, const double *r,
+                 double *z, int *levels)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || !a || !prm || !r || !z || prm->coarse_sweeps < 1 || prm->coarse_cells < 1)
+        return ORC_BAD_ARG;
+    orc_mg m;
+    int rc = mg_build(&m, nx, ny, nz, a, prm);
+    if (rc) return rc;
+    /* the work layout of a level holds the next level's after its own q, z1, rc, e */
+    mg_vcycle(&m, 0, m.work, r, z);
+    if (levels) *levels = m.nlev;
+    mg_free(&m);
+    return 0;
+}
+
+/* the preconditioner of the BiCGSTAB below */
+typedef struct {
+    int kind;             /* 0: M = I, 1: Jacobi, 2: multigrid */
+    const double *ap;
+    const orc_mg *mg;
+} orc_pc;
+
+/* w = M^{-1} u */
+static void precond(long n, const orc_pc *pc, const double *u, double *w)
+{
+    if (pc->kind == 2) {
+        mg_vcycle(pc->mg, 0, pc->mg->work, u, w);
+        return;
+    }
 #pragma omp parallel for schedule(static)
-    for (long c = 0; c < n; c++) w[c] = jacobi ? u[c] / ap[c] : u[c];
+    for (long c = 0; c < n; c++) w[c] = pc->kind == 1 ? u[c] / pc->ap[c] : u[c];
 }
 
 static int all_finite(long n, const double *u)
@@ -196,9 +381,43 @@ static int all_finite(long n, const double *u)
  * x holds x0 on entry and the last iterate on return.  hist, if not NULL,
  * receives ||r||_2 / ||b||_2 after every iteration (maxit entries).
  */
+static int bicgstab_core(int nx, int ny, int nz, const double *const *a, const double *b, double *x, double tol,
+                         int maxit, orc_pc *pc, int transpose, orc_info *info, double *hist);
+
 int orc_bicgstab(int nx, int ny, int nz, const double *const *a, const double *b,
                  double *x, double tol, int maxit, int jacobi, int transpose,
                  orc_info *info, double *hist)
+{
+    orc_pc pc = {jacobi ? 1 : 0, a ? a[SLOT_P] : NULL, NULL};
+    return bicgstab_core(nx, ny, nz, a, b, x, tol, maxit, &pc, transpose, info, hist);
+}
+
+/* The same BiCGSTAB with the multigrid V-cycle (orc_mg_params) as the right
+ * preconditioner; the hierarchy is built once, from the system's diagonals.
+ * levels, if not NULL, receives the number of levels. */
+int orc_bicgstab_mg(int nx, int ny, int nz, const double *const *a, const double *b, double *x, double tol,
+                    int maxit, const orc_mg_params *prm, orc_info *info, double *hist, int *levels)
+{
+    orc_info loc;
+    if (!info) info = &loc;
+    memset(info, 0, sizeof(*info));
+    if (nx < 1 || ny < 1 || nz < 1 || !a || !prm || prm->coarse_sweeps < 1 || prm->coarse_cells < 1) {
+        info->status = ORC_BAD_ARG;
+        return info->status;
+    }
+    for (int q = 0; q < 7; q++)
+        if (!a[q]) { info->status = ORC_BAD_ARG; return info->status; }
+    orc_mg m;
+    if (mg_build(&m, nx, ny, nz, a, prm)) { info->status = ORC_NOMEM; return info->status; }
+    if (levels) *levels = m.nlev;
+    orc_pc pc = {2, a[SLOT_P], &m};
+    int st = bicgstab_core(nx, ny, nz, a, b, x, tol, maxit, &pc, 0, info, hist);
+    mg_free(&m);
+    return st;
+}
+
+static int bicgstab_core(int nx, int ny, int nz, const double *const *a, const double *b, double *x, double tol,
+                         int maxit, orc_pc *pc, int transpose, orc_info *info, double *hist)
 {
     orc_info loc;
     if (!info) info = &loc;
@@ -210,7 +429,7 @@ int orc_bicgstab(int nx, int ny, int nz, const double *const *a, const double *b
     for (int q = 0; q < 7; q++)
         if (!a[q]) { info->status = ORC_BAD_ARG; return info->status; }
     long n = (long)nx * ny * nz;
-    if (jacobi) {
+    if (pc->kind != 0) {
         for (long c = 0; c < n; c++)
             if (a[SLOT_P][c] == 0.0 || !isfinite(a[SLOT_P][c])) {
                 info->status = ORC_BAD_ARG;
@@ -283,7 +502,7 @@ int orc_bicgstab(int nx, int ny, int nz, const double *const *a, const double *b
         double beta = (rho / rho_prev) * (alpha / omega);
 #pragma omp parallel for schedule(static)
         for (long c = 0; c < n; c++) p[c] = r[c] + beta * (p[c] - omega * v[c]);
-        precond(n, a[SLOT_P], jacobi, p, ph);
+        precond(n, pc, p, ph);
         orc_apply(nx, ny, nz, a, ph, v, transpose);
         iters++;
 
@@ -305,7 +524,7 @@ int orc_bicgstab(int nx, int ny, int nz, const double *const *a, const double *b
             goto recheck;
         }
 
-        precond(n, a[SLOT_P], jacobi, s, sh);
+        precond(n, pc, s, sh);
         orc_apply(nx, ny, nz, a, sh, t, transpose);
         double ts = orc_dot(n, t, s);
         double tt = orc_dot(n, t, t);

@@ -129,8 +129,11 @@ namespace {
         }                                             \
     } while (0)
 
+// widest row a stencil pass stages (one row on each side of a segment, in LDS)
+constexpr int kMaxNx = 1024;
+
 bool grid_ok(const eqs_grid &g) {
-    if (g.nx < 1 || g.ny < 1 || g.nz < 1) return false;
+    if (g.nx < 1 || g.ny < 1 || g.nz < 1 || g.nx > kMaxNx) return false;
     const long long n = (long long)g.nx * g.ny * g.nz;
     return n < (1ll << 31) - (1ll << 20);
 }

@@ -46,6 +46,10 @@ def test_library_argument_errors_without_device():
     assert rc == B.EQS_ERR_ARG
     rc, h = B.eqsolve_create([(4, -1, 4)], 0, None)
     assert rc == B.EQS_ERR_ARG
+    rc, h = B.eqsolve_create([(1025, 2, 2)], 0, None)  # rows wider than a stencil pass stages
+    assert rc == B.EQS_ERR_ARG
+    rc, h = B.eqsolve_create([(4, 4, 4)] * 9, 0, None)  # more sets than one launch table takes
+    assert rc == B.EQS_ERR_ARG
     assert B.load().eqsolve_autotune(None, None, 4) == B.EQS_ERR_STATE
     assert B.eqsolve_debug_layout(None, 0)[0] == B.EQS_ERR_ARG
     assert B.strerror(B.EQS_BREAKDOWN).startswith("BiCGSTAB breakdown")

@@ -23,7 +23,8 @@ MUTANTS = [
     ("dot_squares_u", "s += u[c] * v[c];", "s += u[c] * u[c];"),
     ("omega_sign_in_x", "x[c] += alpha * ph[c] + omega * sh[c];", "x[c] += alpha * ph[c] - omega * sh[c];"),
     ("beta_inverted", "(rho / rho_prev) * (alpha / omega)", "(rho / rho_prev) * (omega / alpha)"),
-    ("precond_multiplies", "w[c] = jacobi ? u[c] / ap[c] : u[c];", "w[c] = jacobi ? u[c] * ap[c] : u[c];"),
+    ("precond_multiplies", "w[c] = pc->kind == 1 ? u[c] / pc->ap[c] : u[c];",
+     "w[c] = pc->kind == 1 ? u[c] * pc->ap[c] : u[c];"),
     ("half_step_unpreconditioned", "for (long c = 0; c < n; c++) x[c] += alpha * ph[c];",
      "for (long c = 0; c < n; c++) x[c] += alpha * p[c];"),
     ("residual_sign", "r[c] = b[c] - r[c];", "r[c] = r[c] - b[c];"),
@@ -34,6 +35,13 @@ MUTANTS = [
      "g[SLOT_T][c] = k + 1 < nz ? l * x[c + sy] : 0.0;"),
     ("r_update_uses_plus", "r[c] = s[c] - omega * t[c];", "r[c] = s[c] + omega * t[c];"),
     ("sigma_uses_r", "double sigma = orc_dot(n, rh, v);", "double sigma = orc_dot(n, r, v);"),
+    ("mg_internal_link_added", "ac[SLOT_P][C] -= coef;", "ac[SLOT_P][C] += coef;"),
+    ("mg_link_to_opposite_slot", "ac[SLOT_E + d][C] += coef;", "ac[SLOT_E + (d ^ 1)][C] += coef;"),
+    ("mg_restricts_r_not_residual", "rc[i / 2 + (long)cx * (j / 2 + (long)cy * (k / 2))] += r[c] - q[c];",
+     "rc[i / 2 + (long)cx * (j / 2 + (long)cy * (k / 2))] += r[c];"),
+    ("mg_post_smooth_sign", "z[c] = z1[c] + w * (r[c] - q[c]) / ap[c];", "z[c] = z1[c] - w * (r[c] - q[c]) / ap[c];"),
+    ("mg_prolongs_to_wrong_aggregate", "z1[c] += m->prm.gamma * e[i / 2 + (long)cx * (j / 2 + (long)cy * (k / 2))];",
+     "z1[c] += m->prm.gamma * e[i / 2 + (long)cx * (j / 2 + (long)cy * (k / 4))];"),
 ]
 
 # the pins run against each mutant (cheap ones; each returns normally or raises)
@@ -50,6 +58,10 @@ BATTERY = [
     lambda o: pins.test_bicgstab_one_dimensional_matches_banded_lu(o),
     lambda o: pins.test_bicgstab_transpose_matches_dense_lu(o),
     lambda o: pins.test_grad_matches_finite_differences_of_dense_solve(o),
+    lambda o: pins.test_mg_coarse_operator_is_galerkin_product(o, (5, 3, 4)),
+    lambda o: pins.test_mg_vcycle_transpose_identity(o, "cd"),
+    lambda o: pins.test_mg_vcycle_transpose_identity(o, "sym"),
+    lambda o: pins.test_mg_bicgstab_matches_dense_lu(o),
 ]
 
 

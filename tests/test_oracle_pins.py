@@ -372,3 +372,108 @@ def test_bicgstab_transpose_matches_dense_lu(orc):
     lam, info = orc.bicgstab(g.shape, s["diags"], s["w"], tol=1e-13, maxit=1000, transpose=True)
     assert info["status"] == 0
     np.testing.assert_allclose(lam, np.linalg.solve(A.T, s["w"]), rtol=0, atol=1e-10)
+
+
+# ---------------------------------------------------------------- multigrid preconditioner
+# (an addition beyond the paper's method: aggregation multigrid as the right preconditioner)
+
+def _aggregation_matrix(shape):
+    """Piecewise-constant interpolation from the aggregate definition: fine cell (i, j, k)
+    belongs to coarse cell (i // 2, j // 2, k // 2) of the ((nx+1)//2, (ny+1)//2, (nz+1)//2) grid."""
+    nx, ny, nz = shape
+    cx, cy, cz = (nx + 1) // 2, (ny + 1) // 2, (nz + 1) // 2
+    P = np.zeros((nx * ny * nz, cx * cy * cz))
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                P[i + nx * (j + ny * k), i // 2 + cx * (j // 2 + cy * (k // 2))] = 1.0
+    return P
+
+
+def _transposed_diagonals(shape, diags):
+    """Diagonals of A^T in the same Patankar form: row c of A^T links to c+1 with A's
+    coefficient from c+1 towards c (a_W[c+1]), and so on; a_P is shared."""
+    nx, ny, nz = shape
+    P_, E, Wd, N, S, T, B = [np.asarray(d, dtype=np.float64).reshape(nz, ny, nx) for d in diags]
+    out = [P_.copy()] + [np.zeros_like(P_) for _ in range(6)]
+    out[1][:, :, :-1] = Wd[:, :, 1:]
+    out[2][:, :, 1:] = E[:, :, :-1]
+    out[3][:, :-1, :] = S[:, 1:, :]
+    out[4][:, 1:, :] = N[:, :-1, :]
+    out[5][:-1, :, :] = B[1:, :, :]
+    out[6][1:, :, :] = T[:-1, :, :]
+    return [o.ravel() for o in out]
+
+
+@pytest.mark.parametrize("shape", [(5, 3, 4), (4, 4, 4), (1, 6, 3), (7, 1, 1), (3, 5, 1), (2, 2, 2)])
+def test_mg_coarse_operator_is_galerkin_product(orc, shape):
+    g = W.Grid(*shape)
+    diags = W.random_general(g, seed=31)
+    A = orc.dense(shape, diags)
+    Pm = _aggregation_matrix(shape)
+    cshape, cd = orc.mg_coarsen(shape, diags)
+    Ac = orc.dense(cshape, cd)
+    ref = Pm.T @ A @ Pm
+    assert np.max(np.abs(Ac - ref)) <= 1e-13 * np.max(np.abs(A))
+
+
+def _mg_params(levels_small=True):
+    from oracle import oracle as O
+    return O.mg_params(omega=0.8, gamma=1.6, coarse_sweeps=5, coarse_cells=16 if levels_small else 512)
+
+
+@pytest.mark.parametrize("recipe", ["cd", "sym"])
+def test_mg_vcycle_transpose_identity(orc, recipe):
+    # with R = P^T and Galerkin coarse operators, the V-cycle built for A^T is the
+    # transpose of the one built for A: (u, B_A^{-1} v) = (B_{A^T}^{-1} u, v); for a
+    # symmetric system that is the symmetry of B^{-1}
+    shape = (11, 9, 7)
+    g = W.Grid(*shape)
+    diags = W.coefficients(g, recipe, W.rng_for(0, 5))
+    dT = _transposed_diagonals(shape, diags)
+    A = orc.dense((5, 4, 3), W.random_general(W.Grid(5, 4, 3), seed=2))
+    AT = orc.dense((5, 4, 3), _transposed_diagonals((5, 4, 3), W.random_general(W.Grid(5, 4, 3), seed=2)))
+    assert np.array_equal(A.T, AT)  # the helper itself is right
+    rng = np.random.default_rng(7)
+    u, v = rng.standard_normal(g.n), rng.standard_normal(g.n)
+    zA, lev = orc.mg_apply(shape, diags, v, _mg_params())
+    zT, _ = orc.mg_apply(shape, dT, u, _mg_params())
+    assert lev >= 3
+    lhs, rhs = float(u @ zA), float(zT @ v)
+    assert abs(lhs - rhs) <= 1e-12 * np.linalg.norm(u) * np.linalg.norm(zA)
+
+
+def test_mg_vcycle_exact_on_diagonal_system_with_unit_weight(orc):
+    from oracle import oracle as O
+    g = W.Grid(9, 6, 5)
+    rng = np.random.default_rng(3)
+    ap = rng.uniform(1, 3, g.n)
+    diags = [ap] + [np.zeros(g.n)] * 6
+    r = rng.uniform(-1, 1, g.n)
+    z, lev = orc.mg_apply(g.shape, diags, r, O.mg_params(omega=1.0, gamma=1.6, coarse_sweeps=3, coarse_cells=8))
+    assert lev >= 3
+    np.testing.assert_allclose(z, r / ap, rtol=4 * np.finfo(float).eps, atol=0)
+
+
+def test_mg_bicgstab_matches_dense_lu(orc):
+    g = W.Grid(8, 8, 8)
+    s = W.make_set(0, 0, grid=g)
+    A = orc.dense(g.shape, s["diags"])
+    b = A @ s["x_star"]
+    xd = np.linalg.solve(A, b)
+    x, info = orc.bicgstab_mg(g.shape, s["diags"], b, tol=1e-13, maxit=200, params=_mg_params())
+    assert info["status"] == 0 and info["levels"] >= 2
+    assert np.linalg.norm(x - xd) <= 1e-10 * np.linalg.norm(xd)
+
+
+@pytest.mark.parametrize("cfg,shape", [(1, (16, 32, 16)), (0, (16, 16, 16))])
+def test_mg_bicgstab_residual_invariant_and_iterations(orc, cfg, shape):
+    from oracle import oracle as O
+    g = W.Grid(*shape)
+    s = W.make_set(cfg, 0, grid=g)
+    b = orc.apply(g.shape, s["diags"], s["x_star"])
+    x, info = orc.bicgstab_mg(g.shape, s["diags"], b, tol=1e-10, maxit=500, params=O.mg_params())
+    assert info["status"] == 0
+    assert orc.rel_residual(g.shape, s["diags"], b, x) <= 1e-10
+    _, jinfo = orc.bicgstab(g.shape, s["diags"], b, tol=1e-10, maxit=2000)
+    assert 4 * info["iters"] <= jinfo["iters"], (info, jinfo)
