@@ -149,6 +149,47 @@ int eqsolve_autotune(eqs_ctx *ctx, const char *cache_path, int32_t iters);
 /* Release the context and its workspace (NULL is allowed). */
 int eqsolve_destroy(eqs_ctx *ctx);
 
+/* Preconditioners of the FP64 forward solves. */
+enum { EQS_PRECOND_JACOBI = 0, EQS_PRECOND_MG = 1 };
+
+/* Parameters of the multigrid V-cycle (see eqsolve_set_preconditioner). */
+typedef struct {
+    double omega;          /* damped-Jacobi weight, in (0, 2); default 0.8 */
+    double gamma;          /* scale of the coarse correction, in (0, 4]; default 1 */
+    int32_t coarse_sweeps; /* damped-Jacobi sweeps on the coarsest level, >= 1; default 30 */
+    int32_t coarse_cells;  /* coarsen until a level has at most this many cells, 1..2048; default 512 */
+} eqs_mg_params;
+
+/*
+ * Choose the right preconditioner of the forward solves of an EQS_FP64
+ * context (eqsolve_solve and eqsolve_solve_batched; the adjoint keeps
+ * Jacobi).  EQS_PRECOND_JACOBI is the default.  EQS_PRECOND_MG is an
+ * aggregation multigrid V-cycle, an addition to the paper's method aimed at
+ * the pressure-correction system, whose Jacobi iteration count grows with
+ * the grid: levels of 2 x 2 x 2 aggregates (dimensions halved, rounding up)
+ * down to at most coarse_cells cells, piecewise-constant interpolation,
+ * restriction by summing an aggregate, Galerkin coarse operators (again
+ * 7-point), one damped-Jacobi step before and after the coarse correction
+ * (scaled by gamma) and coarse_sweeps damped-Jacobi sweeps on the coarsest
+ * level.  With it a set is iterated on its own (a batched call solves its
+ * sets one after another), on the original A, with x updated in place.
+ * params NULL selects the defaults.  Allocates the level hierarchy (about
+ * 1.3 words per cell) here, not in the solves.  Returns EQS_OK, EQS_ERR_ARG
+ * (kind, params, or a context that is not EQS_FP64), EQS_ERR_NOMEM,
+ * EQS_ERR_HIP or EQS_ERR_STATE.
+ */
+int eqsolve_set_preconditioner(eqs_ctx *ctx, int32_t kind, const eqs_mg_params *params);
+
+/*
+ * Diagnostics: z = B^-1 r, one V-cycle of the multigrid preconditioner of set
+ * `set`, built from the diagonals diag (device arrays as in eqsolve_solve;
+ * r and z device arrays of the set's size, z not aliasing r).  *levels (host,
+ * may be NULL) receives the number of levels.  Returns EQS_OK, EQS_ERR_ARG
+ * (multigrid not selected, bad pointers), EQS_ERR_HIP or EQS_ERR_STATE.
+ */
+int eqsolve_debug_precond(eqs_ctx *ctx, int32_t set, const double *const diag[7], const double *r, double *z,
+                          int32_t *levels);
+
 /* Static description of a result code. */
 const char *eqsolve_strerror(int code);
 

@@ -24,7 +24,8 @@ PRECISIONS = {"fp64": EQS_FP64, "fp32_refine": EQS_FP32_REFINE, "fp32": EQS_FP32
 # symbols declared in include/eqsolve.h
 SYMBOLS = ("eqsolve_create", "eqsolve_solve", "eqsolve_solve_batched", "eqsolve_adjoint", "eqsolve_apply",
            "eqsolve_destroy", "eqsolve_strerror", "eqsolve_autotune", "eqsolve_debug_layout",
-           "eqsolve_debug_profile", "eqsolve_debug_kernel_stats")
+           "eqsolve_debug_profile", "eqsolve_debug_kernel_stats", "eqsolve_set_preconditioner",
+           "eqsolve_debug_precond")
 KERNEL_KINDS = {"setup": 0, "recheck": 1, "report": 2, "k1": 3, "k2": 4, "k3": 5, "cast": 6, "outer": 7,
                 "update": 8, "zero": 9, "grad": 10, "apply": 11, "scale": 12, "unscale": 13, "fused": 14,
                 "fsetup": 15, "mat": 16}
@@ -32,6 +33,14 @@ KERNEL_KINDS = {"setup": 0, "recheck": 1, "report": 2, "k1": 3, "k2": 4, "k3": 5
 
 class EqsGrid(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32)]
+
+
+EQS_PRECOND_JACOBI, EQS_PRECOND_MG = 0, 1
+
+
+class EqsMgParams(ctypes.Structure):
+    _fields_ = [("omega", ctypes.c_double), ("gamma", ctypes.c_double), ("coarse_sweeps", ctypes.c_int32),
+                ("coarse_cells", ctypes.c_int32)]
 
 
 class EqsInfo(ctypes.Structure):
@@ -85,6 +94,10 @@ def load(path: str | None = None):
         L.eqsolve_debug_kernel_stats.argtypes = [VP, ctypes.c_int32, ctypes.c_int32,
                                                  ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]
         L.eqsolve_debug_kernel_stats.restype = ctypes.c_int
+        L.eqsolve_set_preconditioner.argtypes = [VP, ctypes.c_int32, ctypes.POINTER(EqsMgParams)]
+        L.eqsolve_set_preconditioner.restype = ctypes.c_int
+        L.eqsolve_debug_precond.argtypes = [VP, ctypes.c_int32, VPP, VP, VP, ctypes.POINTER(ctypes.c_int32)]
+        L.eqsolve_debug_precond.restype = ctypes.c_int
         if path is None:
             _lib = L
         return L
@@ -149,6 +162,22 @@ def eqsolve_apply(h, set_id, diag_ptrs, x_ptr, y_ptr, transpose):
 
 def eqsolve_destroy(h):
     return load().eqsolve_destroy(h)
+
+
+def eqsolve_set_preconditioner(h, kind, params=None):
+    """params: None (defaults) or a dict with omega, gamma, coarse_sweeps, coarse_cells."""
+    prm = None
+    if params is not None:
+        prm = EqsMgParams(float(params.get("omega", 0.8)), float(params.get("gamma", 1.0)),
+                          int(params.get("coarse_sweeps", 30)), int(params.get("coarse_cells", 512)))
+    return load().eqsolve_set_preconditioner(h, int(kind), ctypes.byref(prm) if prm is not None else None)
+
+
+def eqsolve_debug_precond(h, set_id, diag_ptrs, r_ptr, z_ptr):
+    dp, keep = ptr_array(diag_ptrs)
+    lv = ctypes.c_int32(0)
+    rc = load().eqsolve_debug_precond(h, int(set_id), dp, VP(r_ptr), VP(z_ptr), ctypes.byref(lv))
+    return rc, lv.value
 
 
 def eqsolve_debug_layout(h, set_id):

@@ -116,6 +116,13 @@ struct eqs_ctx {
     size_t ev_used = 0;
     int64_t kcount[2 * 32] = {0};
     double kms[2 * 32] = {0};
+    // multigrid preconditioner of the FP64 forward solves (eqsolve_set_preconditioner)
+    int precond = 0;                        // EQS_PRECOND_*
+    MgParams mgp{0.8, 1.0, 30, 512};
+    std::vector<std::vector<MgLevel>> mg;   // per set: the level table (host copy)
+    MgLevel *d_mg = nullptr;                // device: nsets x kMgMaxLevels
+    void *mg_ws = nullptr;
+    std::map<int, std::array<hipGraphExec_t, 4>> graphs_mg;  // per set: 2^k preconditioned iterations
 };
 
 namespace {
@@ -418,8 +425,19 @@ struct Run {
     }
 };
 
+int run_fp64_mg(Run &R);
+Run make_run(eqs_ctx *c, int first, int count, bool trans);
+
 int run_fp64(Run &R) {
     int rc;
+    // forward FP64 solves with the multigrid preconditioner: one set at a time
+    if (R.c->precond == EQS_PRECOND_MG && !R.trans) {
+        for (int i = 0; i < R.count; ++i) {
+            Run Q = make_run(R.c, R.first + i, 1, false);
+            if ((rc = run_fp64_mg(Q))) return rc;
+        }
+        return 0;
+    }
     // tiny sets: the whole solve in one launch, one block per set
     int max_n = 0;
     for (int i = 0; i < R.count; ++i) max_n = std::max(max_n, R.c->sets[R.first + i].n);
@@ -610,6 +628,132 @@ void clear_graphs(eqs_ctx *c) {
         for (hipGraphExec_t ex : kv.second)
             if (ex) (void)hipGraphExecDestroy(ex);
     c->graphs.clear();
+    for (auto &kv : c->graphs_mg)
+        for (hipGraphExec_t ex : kv.second)
+            if (ex) (void)hipGraphExecDestroy(ex);
+    c->graphs_mg.clear();
+}
+
+// ------------------------------------------------------------------ multigrid-preconditioned iteration
+
+// z = B^-1 r for set s (one V-cycle); gated launches do nothing once the set stops iterating
+hipError_t mg_vcycle(eqs_ctx *c, int s, const double *r, double *z, bool gated, hipStream_t stream) {
+    const std::vector<MgLevel> &L = c->mg[s];
+    const int nl = (int)L.size();
+    const SetDesc *dd = c->d_desc + s;
+    const MgLevel *lev = c->d_mg + (size_t)s * kMgMaxLevels;
+    hipError_t e = hipSuccess;
+    for (int l = 0; l + 1 < nl && e == hipSuccess; ++l)
+        e = launch_mg_restrict(dd, lev, l, L[l + 1].n, l == 0 ? r : L[l].r, c->mgp, gated, stream);
+    if (e == hipSuccess)
+        e = launch_mg_coarsest(dd, lev, nl - 1, L[nl - 1].n, nl == 1 ? r : L[nl - 1].r, nl == 1 ? z : L[nl - 1].z,
+                               c->mgp, gated, stream);
+    for (int l = nl - 2; l >= 0 && e == hipSuccess; --l)
+        e = launch_mg_prolong(dd, lev, l, L[l].n, l == 0 ? r : L[l].r, l == 0 ? z : L[l].z, c->mgp, gated, stream);
+    c->launches += 2 * nl - 1;
+    return e;
+}
+
+// the Galerkin operators of every coarse level of set s, from the diagonals in its table entry
+hipError_t mg_coarsen_all(eqs_ctx *c, int s) {
+    const std::vector<MgLevel> &L = c->mg[s];
+    hipError_t e = hipSuccess;
+    for (int l = 0; l + 1 < (int)L.size() && e == hipSuccess; ++l)
+        e = launch_mg_coarsen(c->d_desc + s, c->d_mg + (size_t)s * kMgMaxLevels, l, L[l + 1].n, c->stream);
+    return e;
+}
+
+// one preconditioned BiCGSTAB iteration of the run's (single) set on `stream`
+hipError_t mg_iteration(Run &R, hipStream_t stream) {
+    eqs_ctx *c = R.c;
+    const SetHost &h = c->sets[R.first];
+    auto K = [&](Kern k) {
+        c->launches++;
+        return launch_kernel(k, R.ls, R.ntiles, R.nflat, c->cpt, R.max_nx, false, false, stream, nullptr, nullptr, 0);
+    };
+    hipError_t e = K(K_PC_P);
+    if (e == hipSuccess) e = mg_vcycle(c, R.first, h.p[0], h.p[1], true, stream);  // p^ = B^-1 p
+    if (e == hipSuccess) e = K(K_PC_V);
+    if (e == hipSuccess) e = K(K_PC_S);
+    if (e == hipSuccess) e = mg_vcycle(c, R.first, h.s1, h.v[1], true, stream);    // s^ = B^-1 s
+    if (e == hipSuccess) e = K(K_PC_T);
+    if (e == hipSuccess) e = K(K_PC_X);
+    return e;
+}
+
+// C iterations: replayed from captured graphs of 1, 2, 4 or 8 iterations (launched one
+// by one when graphs are off)
+int mg_iterate(Run &R, int C) {
+    eqs_ctx *c = R.c;
+    if (!c->use_graphs) {
+        for (int i = 0; i < C; ++i)
+            if (mg_iteration(R, c->stream) != hipSuccess) {
+                (void)hipGetLastError();
+                c->broken = true;
+                return EQS_ERR_HIP;
+            }
+        return 0;
+    }
+    auto &slots = c->graphs_mg[R.first];
+    for (int b = 3; b >= 0; --b) {
+        while (C >= (1 << b)) {
+            if (!slots[b]) {
+                if (!c->capture_stream) EQS_HIP(hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
+                EQS_HIP(hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
+                bool ok = true;
+                const uint64_t before = c->launches;
+                for (int i = 0; i < (1 << b) && ok; ++i) ok = mg_iteration(R, c->capture_stream) == hipSuccess;
+                c->launches = before;
+                hipGraph_t g = nullptr;
+                const hipError_t e = hipStreamEndCapture(c->capture_stream, &g);
+                hipGraphExec_t ex = nullptr;
+                const hipError_t ei = (ok && e == hipSuccess && g) ? hipGraphInstantiate(&ex, g, nullptr, nullptr, 0)
+                                                                   : hipErrorUnknown;
+                if (g) (void)hipGraphDestroy(g);
+                if (ei != hipSuccess) {
+                    (void)hipGetLastError();
+                    c->broken = true;
+                    return EQS_ERR_HIP;
+                }
+                slots[b] = ex;
+            }
+            EQS_HIP(hipGraphLaunch(slots[b], c->stream));
+            c->launches += (uint64_t)(5 + 2 * (2 * (int)c->mg[R.first].size() - 1)) << b;
+            C -= 1 << b;
+        }
+    }
+    return 0;
+}
+
+int run_fp64_mg(Run &R) {
+    int rc;
+    if (mg_coarsen_all(R.c, R.first) != hipSuccess) {
+        (void)hipGetLastError();
+        R.c->broken = true;
+        return EQS_ERR_HIP;
+    }
+    R.c->launches += R.c->mg[R.first].size() - 1;
+    if ((rc = R.L(K_SETUP))) return rc;
+    if ((rc = R.readback())) return rc;
+    R.reset_rate();
+    for (long guard = 0;; ++guard) {
+        if (guard > R.guard_limit) { R.c->broken = true; return EQS_ERR_STATE; }
+        if (R.all_done()) break;
+        if (R.any([](const SolveState &s) { return s.converged || s.need_report; })) {
+            if ((rc = R.L(K_RECHECK))) return rc;  // x is updated in place: no unscaling
+            if ((rc = R.L(K_REPORT))) return rc;
+            if ((rc = R.readback())) return rc;
+            R.reset_rate();
+            continue;
+        }
+        const int C = std::min(R.chunk(), 15);
+        if (C <= 0) { R.c->broken = true; return EQS_ERR_STATE; }
+        if ((rc = mg_iterate(R, C))) return rc;
+        if ((rc = R.readback())) return rc;
+    }
+    if (R.any([](const SolveState &s) { return s.zero_rhs != 0; }))
+        if ((rc = R.L(K_ZERO, nullptr, nullptr, 0))) return rc;
+    return 0;
 }
 
 // Mean time of one BiCGSTAB iteration (K1 + K2 + K3) of set s under its
@@ -818,11 +962,111 @@ int eqsolve_create(eqs_ctx **out, const eqs_grid *grids, int32_t nsets, int32_t 
     return EQS_OK;
 }
 
+int eqsolve_set_preconditioner(eqs_ctx *c, int32_t kind, const eqs_mg_params *prm) {
+    if (!c || c->broken) return EQS_ERR_STATE;
+    if (kind == EQS_PRECOND_JACOBI) {
+        c->precond = EQS_PRECOND_JACOBI;
+        return EQS_OK;
+    }
+    if (kind != EQS_PRECOND_MG || c->precision != EQS_FP64) return EQS_ERR_ARG;
+    MgParams p{0.8, 1.0, 30, 512};
+    if (prm) p = MgParams{prm->omega, prm->gamma, prm->coarse_sweeps, prm->coarse_cells};
+    if (!(p.omega > 0.0 && p.omega < 2.0) || !(p.gamma > 0.0 && p.gamma <= 4.0) || p.coarse_sweeps < 1 ||
+        p.coarse_sweeps > 100000 || p.coarse_cells < 1 || p.coarse_cells > kMgCoarsestMax)
+        return EQS_ERR_ARG;
+    // levels: halve every dimension (rounding up) until at most coarse_cells cells remain
+    std::vector<std::vector<MgLevel>> mg(c->nsets);
+    size_t bytes = 0;
+    for (int s = 0; s < c->nsets; ++s) {
+        const eqs_grid &g = c->sets[s].g;
+        MgLevel l0{};
+        l0.nx = g.nx;
+        l0.ny = g.ny;
+        l0.nz = g.nz;
+        l0.n = c->sets[s].n;
+        mg[s].push_back(l0);
+        while (mg[s].back().n > p.coarse_cells && mg[s].back().n > 1 && (int)mg[s].size() < kMgMaxLevels) {
+            const MgLevel &f = mg[s].back();
+            MgLevel q{};
+            q.nx = (f.nx + 1) / 2;
+            q.ny = (f.ny + 1) / 2;
+            q.nz = (f.nz + 1) / 2;
+            q.n = q.nx * q.ny * q.nz;
+            mg[s].push_back(q);
+            bytes += 9 * align_up((size_t)q.n * 8);
+        }
+        if (mg[s].back().n > kMgCoarsestMax) return EQS_ERR_ARG;
+    }
+    void *ws = nullptr;
+    if (bytes && hipMalloc(&ws, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return EQS_ERR_NOMEM;
+    }
+    if (!c->d_mg && hipMalloc((void **)&c->d_mg, sizeof(MgLevel) * kMgMaxLevels * c->nsets) != hipSuccess) {
+        (void)hipGetLastError();
+        if (ws) (void)hipFree(ws);
+        return EQS_ERR_NOMEM;
+    }
+    char *q = (char *)ws;
+    std::vector<MgLevel> table((size_t)kMgMaxLevels * c->nsets);
+    for (int s = 0; s < c->nsets; ++s)
+        for (size_t l = 0; l < mg[s].size(); ++l) {
+            MgLevel &L = mg[s][l];
+            if (l > 0) {
+                for (int k = 0; k < 7; ++k) {
+                    L.a[k] = (double *)q;
+                    q += align_up((size_t)L.n * 8);
+                }
+                L.r = (double *)q;
+                q += align_up((size_t)L.n * 8);
+                L.z = (double *)q;
+                q += align_up((size_t)L.n * 8);
+            }
+            table[(size_t)s * kMgMaxLevels + l] = L;
+        }
+    if (hipMemcpyAsync(c->d_mg, table.data(), sizeof(MgLevel) * table.size(), hipMemcpyHostToDevice, c->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+        (void)hipGetLastError();
+        if (ws) (void)hipFree(ws);
+        c->broken = true;
+        return EQS_ERR_HIP;
+    }
+    clear_graphs(c);
+    if (c->mg_ws) (void)hipFree(c->mg_ws);
+    c->mg_ws = ws;
+    c->mg = std::move(mg);
+    c->mgp = p;
+    c->precond = EQS_PRECOND_MG;
+    return EQS_OK;
+}
+
+int eqsolve_debug_precond(eqs_ctx *c, int32_t set, const double *const diag[7], const double *r, double *z,
+                          int32_t *levels) {
+    if (!c || c->broken) return EQS_ERR_STATE;
+    if (c->precond != EQS_PRECOND_MG || set < 0 || set >= c->nsets || !diag_ok(diag) || !r || !z || r == z)
+        return EQS_ERR_ARG;
+    SetDesc &d = c->h_desc[set];
+    for (int k = 0; k < 7; ++k) d.a[k] = diag[k];
+    int rc = upload_desc(c, set, 1);
+    if (rc) return rc;
+    if (mg_coarsen_all(c, set) != hipSuccess || mg_vcycle(c, set, r, z, false, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+        (void)hipGetLastError();
+        c->broken = true;
+        return EQS_ERR_HIP;
+    }
+    if (levels) *levels = (int32_t)c->mg[set].size();
+    return EQS_OK;
+}
+
 int eqsolve_destroy(eqs_ctx *c) {
     if (!c) return EQS_OK;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     clear_graphs(c);
+    if (c->mg_ws) (void)hipFree(c->mg_ws);
+    if (c->d_mg) (void)hipFree(c->d_mg);
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     if (c->ws) (void)hipFree(c->ws);
     if (c->d_desc) (void)hipFree(c->d_desc);

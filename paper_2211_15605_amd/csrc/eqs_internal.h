@@ -101,6 +101,23 @@ struct SetDesc {
     SolveState *st;
 };
 
+// One level of a set's multigrid hierarchy (the aggregation V-cycle used as
+// the right preconditioner of the FP64 solve).  Level 0 is the system itself
+// (its coefficients are the caller's arrays in the set table); level l + 1
+// aggregates 2 x 2 x 2 cells of level l.
+constexpr int kMgMaxLevels = 16;
+struct MgLevel {
+    int32_t nx, ny, nz, n;
+    double *a[7];   // Galerkin coefficients (levels >= 1)
+    double *r, *z;  // right-hand side and result of the level's V-cycle (levels >= 1)
+};
+struct MgParams {
+    double omega;         // damped-Jacobi weight
+    double gamma;         // scale of the coarse correction
+    int32_t coarse_sweeps;
+    int32_t coarse_cells;
+};
+
 // blocks of one launch -> (set, tile); set s owns logical tiles [tile_begin[s], tile_begin[s+1])
 // (pointwise kernels use flat_begin over the sets' nflat blocks instead)
 struct LaunchSets {

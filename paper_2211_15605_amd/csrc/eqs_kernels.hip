@@ -35,6 +35,8 @@
 #include <hip/hip_ext.h>
 #include <math.h>
 
+#include <algorithm>
+
 #include "eqs_internal.h"
 #include "eqs_launch.h"
 
@@ -1779,6 +1781,308 @@ __global__ void __launch_bounds__(kBlock) fill_kernel(double *p, long n, double 
     for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) p[i] = v;
 }
 
+// ------------------------------------------------------------------ multigrid preconditioner
+//
+// Aggregation V-cycle B^{-1} (right preconditioner of the FP64 solve).  Level
+// l + 1 aggregates the cells (i, j, k) of level l with equal (i/2, j/2, k/2);
+// interpolation is piecewise constant, restriction its transpose (the sum
+// over an aggregate), the coarse operators are the Galerkin products (again
+// 7-point).  V-cycle on level l with right-hand side r, D = diag(a_P):
+//   coarsest level: z = 0, then coarse_sweeps times z += omega D^-1 (r - A z)
+//   otherwise:      z1 = omega D^-1 r; e = V-cycle(l+1, R (r - A z1));
+//                   z2 = z1 + gamma P e;  z = z2 + omega D^-1 (r - A z2)
+// The kernels take the operations in that order, with FMA contraction off,
+// and sum an aggregate's cells in index order, so the V-cycle equals a plain
+// sequential evaluation of the definition to the last bit.
+
+__device__ __forceinline__ const double *mg_coef(const SetDesc *d, const MgLevel &L, int l, int q) {
+    return l == 0 ? d->a[q] : L.a[q];
+}
+
+// row c = (i, j, k) of A applied to x: a_P x_c, then minus each present
+// neighbour's term in the order E, W, N, S, T, B; xat(cell, i, j, k) gives x
+template <class F>
+__device__ __forceinline__ double mg_row(const double *const *a, int nx, int ny, int nz, int i, int j, int k, int c,
+                                         F xat) {
+#pragma clang fp contract(off)
+    const int P = nx * ny;
+    double acc = ld(a[0], c) * xat(c, i, j, k);
+    if (i + 1 < nx) acc -= ld(a[1], c) * xat(c + 1, i + 1, j, k);
+    if (i > 0) acc -= ld(a[2], c) * xat(c - 1, i - 1, j, k);
+    if (j + 1 < ny) acc -= ld(a[3], c) * xat(c + nx, i, j + 1, k);
+    if (j > 0) acc -= ld(a[4], c) * xat(c - nx, i, j - 1, k);
+    if (k + 1 < nz) acc -= ld(a[5], c) * xat(c + P, i, j, k + 1);
+    if (k > 0) acc -= ld(a[6], c) * xat(c - P, i, j, k - 1);
+    return acc;
+}
+
+// Galerkin coarse operator of level l + 1, one thread per coarse cell
+__global__ void __launch_bounds__(kBlock) mg_coarsen_kernel(const SetDesc *d, const MgLevel *lev, int l) {
+#pragma clang fp contract(off)
+    const MgLevel F = lev[l], C = lev[l + 1];
+    const double *a[7];
+    for (int q = 0; q < 7; ++q) a[q] = mg_coef(d, F, l, q);
+    const int nx = F.nx, ny = F.ny, nz = F.nz, cx = C.nx, cy = C.ny;
+    for (int cc = blockIdx.x * kBlock + threadIdx.x; cc < C.n; cc += gridDim.x * kBlock) {
+        const int I = cc % cx, t = cc / cx, J = t % cy, K = t / cy;
+        double acc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int k = 2 * K; k < min(2 * K + 2, nz); ++k)
+            for (int j = 2 * J; j < min(2 * J + 2, ny); ++j)
+                for (int i = 2 * I; i < min(2 * I + 2, nx); ++i) {
+                    const int c = i + nx * (j + ny * k);
+                    acc[0] += ld(a[0], c);
+                    const int ni[6] = {i + 1, i - 1, i, i, i, i};
+                    const int nj[6] = {j, j, j + 1, j - 1, j, j};
+                    const int nk[6] = {k, k, k, k, k + 1, k - 1};
+                    for (int dd = 0; dd < 6; ++dd) {
+                        if (ni[dd] < 0 || ni[dd] >= nx || nj[dd] < 0 || nj[dd] >= ny || nk[dd] < 0 || nk[dd] >= nz)
+                            continue;
+                        const double coef = ld(a[1 + dd], c);
+                        if (ni[dd] / 2 == I && nj[dd] / 2 == J && nk[dd] / 2 == K)
+                            acc[0] -= coef;  // link inside the aggregate
+                        else
+                            acc[1 + dd] += coef;
+                    }
+                }
+        for (int q = 0; q < 7; ++q) st(C.a[q], cc, acc[q]);
+    }
+}
+
+// R (r - A z1) with z1 = omega D^-1 r, into level l + 1's right-hand side
+__global__ void __launch_bounds__(kBlock) mg_restrict_kernel(const SetDesc *d, const MgLevel *lev, int l,
+                                                             const double *rin, MgParams prm, int gated) {
+#pragma clang fp contract(off)
+    if (gated && !d->st->active) return;
+    const MgLevel F = lev[l], C = lev[l + 1];
+    const double *a[7];
+    for (int q = 0; q < 7; ++q) a[q] = mg_coef(d, F, l, q);
+    const int nx = F.nx, ny = F.ny, nz = F.nz, cx = C.nx, cy = C.ny;
+    const double w = prm.omega;
+    const double *ap = a[0];
+    auto z1 = [&](int x, int, int, int) { return w * ld(rin, x) / ld(ap, x); };
+    for (int cc = blockIdx.x * kBlock + threadIdx.x; cc < C.n; cc += gridDim.x * kBlock) {
+        const int I = cc % cx, t = cc / cx, J = t % cy, K = t / cy;
+        double sum = 0.0;
+        for (int k = 2 * K; k < min(2 * K + 2, nz); ++k)
+            for (int j = 2 * J; j < min(2 * J + 2, ny); ++j)
+                for (int i = 2 * I; i < min(2 * I + 2, nx); ++i) {
+                    const int c = i + nx * (j + ny * k);
+                    const double q = mg_row(a, nx, ny, nz, i, j, k, c, z1);
+                    sum += ld(rin, c) - q;
+                }
+        st(C.r, cc, sum);
+    }
+}
+
+// z = z2 + omega D^-1 (r - A z2) with z2 = omega D^-1 r + gamma P e, e = level l + 1's result
+__global__ void __launch_bounds__(kBlock) mg_prolong_kernel(const SetDesc *d, const MgLevel *lev, int l,
+                                                            const double *rin, double *zout, MgParams prm,
+                                                            int gated) {
+#pragma clang fp contract(off)
+    if (gated && !d->st->active) return;
+    const MgLevel F = lev[l], C = lev[l + 1];
+    const double *a[7];
+    for (int q = 0; q < 7; ++q) a[q] = mg_coef(d, F, l, q);
+    const int nx = F.nx, ny = F.ny, nz = F.nz, cx = C.nx, cy = C.ny;
+    const double w = prm.omega, gm = prm.gamma;
+    const double *ap = a[0], *e = C.z;
+    auto z2 = [&](int x, int i, int j, int k) {
+        return w * ld(rin, x) / ld(ap, x) + gm * ld(e, i / 2 + cx * (j / 2 + cy * (k / 2)));
+    };
+    for (int c = blockIdx.x * kBlock + threadIdx.x; c < F.n; c += gridDim.x * kBlock) {
+        const int i = c % nx, t = c / nx, j = t % ny, k = t / ny;
+        const double q = mg_row(a, nx, ny, nz, i, j, k, c, z2);
+        st(zout, c, z2(c, i, j, k) + w * (ld(rin, c) - q) / ld(ap, c));
+    }
+}
+
+// coarsest level: coarse_sweeps damped-Jacobi sweeps from zero in one block
+constexpr int kMgCoarseThreads = 1024;
+__global__ void __launch_bounds__(kMgCoarseThreads) mg_coarsest_kernel(const SetDesc *d, const MgLevel *lev, int l,
+                                                                       const double *rin, double *zout,
+                                                                       MgParams prm, int gated) {
+#pragma clang fp contract(off)
+    if (gated && !d->st->active) return;
+    __shared__ double zb[2][kMgCoarsestMax];
+    const MgLevel F = lev[l];
+    const double *a[7];
+    for (int q = 0; q < 7; ++q) a[q] = mg_coef(d, F, l, q);
+    const int nx = F.nx, ny = F.ny, nz = F.nz, n = F.n;
+    const double w = prm.omega;
+    for (int c = threadIdx.x; c < n; c += kMgCoarseThreads) zb[0][c] = 0.0;
+    __syncthreads();
+    int cur = 0;
+    for (int it = 0; it < prm.coarse_sweeps; ++it) {
+        const double *zc = zb[cur];
+        auto zat = [&](int x, int, int, int) { return zc[x]; };
+        for (int c = threadIdx.x; c < n; c += kMgCoarseThreads) {
+            const int i = c % nx, t = c / nx, j = t % ny, k = t / ny;
+            const double q = mg_row(a, nx, ny, nz, i, j, k, c, zat);
+            zb[cur ^ 1][c] = zc[c] + w * (ld(rin, c) - q) / ld(a[0], c);
+        }
+        __syncthreads();
+        cur ^= 1;
+    }
+    for (int c = threadIdx.x; c < n; c += kMgCoarseThreads) st(zout, c, zb[cur][c]);
+}
+
+// ---- BiCGSTAB with the V-cycle as right preconditioner (FP64, original A, x updated in place).
+// Buffers: p = p[0], v = v[0], p^ = p[1], s = s1, s^ = v[1], t, r, r^; the finalisers are
+// those of the three-launch iteration (FinK1: alpha; FinK2: omega and the half-step exit;
+// FinK3: convergence, rho and restarts).
+
+// p = r + beta (p - omega v); at a fresh start p = r and r^ = r
+__global__ void __launch_bounds__(kBlock) pc_p_kernel(LaunchSets ls) {
+    const TileRef tr = locate<true>(ls);
+    const SetDesc &d = *tr.d;
+    const SolveState *st_ = d.st;
+    if (!st_->active) return;
+    const bool fresh = st_->fresh != 0;
+    const double beta = (st_->rho / st_->rho_prev) * (st_->alpha / st_->omega), om = st_->omega;
+    const double *r = d.r, *v = d.v[0];
+    double *p = d.p[0], *rh = d.rh;
+    const int n = d.n, nflat = d.nflat;
+    for (int ch = tr.tile; ch * kFlatChunk < n; ch += nflat) {
+        const int base = ch * kFlatChunk + (int)threadIdx.x;
+        double R[kFlatU], Pv[kFlatU], V[kFlatU];
+#pragma unroll
+        for (int u = 0; u < kFlatU; ++u) {
+            const int i = min(base + kBlock * u, n - 1);
+            R[u] = ld(r, i);
+            Pv[u] = ld(p, i);
+            V[u] = ld(v, i);
+        }
+#pragma unroll
+        for (int u = 0; u < kFlatU; ++u) {
+            const int i = base + kBlock * u;
+            if (i < n) {
+                st(p, i, fresh ? R[u] : fma(beta, fma(-om, V[u], Pv[u]), R[u]));
+                if (fresh) st(rh, i, R[u]);
+            }
+        }
+    }
+}
+
+// stencil operand x at a cell for the products of the preconditioned iteration
+struct PhPc {
+    static constexpr int NV = 3;
+    using Raw = RawX;
+    struct Aux {};
+    struct Pre { Coef6<double, false> c; double ap, w; };
+    const double *a[7];
+    const double *x, *wv;  // operand; second vector of the sums ((r^) for v, (s) for t)
+    double *y;
+    int nx, P, ncell;
+    bool tstep;            // false: v = A p^, sum (r^, v); true: t = A s^, sums (t,s), (t,t), (s,s)
+    __device__ __forceinline__ Raw load(int idx) const { return Raw{ld(x, idx)}; }
+    __device__ __forceinline__ double own(const Raw &w, int, Aux &) { return w.x; }
+    __device__ __forceinline__ double halo(const Raw &w) const { return w.x; }
+    __device__ __forceinline__ void pre(int idx, Nb nb, bool up, bool dn, Pre &pr) const {
+        pr.c.load(a, idx, nx, P, ncell, nb, up, dn);
+        pr.ap = ld(a[0], idx);
+        pr.w = ld(wv, idx);
+    }
+    __device__ __forceinline__ void center(int idx, const Pre &pr, const Aux &, double xc, double xE, double xW,
+                                           double xN, double xS, double xT, double xB, double (&acc)[NV]) {
+        const double yv = pr.c.apply(pr.ap, xc, xE, xW, xN, xS, xT, xB);
+        st(y, idx, yv);
+        if (!tstep) {
+            acc[0] += pr.w * yv;
+        } else {
+            acc[0] += yv * pr.w;
+            acc[1] += yv * yv;
+            acc[2] += pr.w * pr.w;
+        }
+    }
+};
+
+template <int CPT, int H>
+__global__ void __launch_bounds__(kBlock) pc_prod_kernel(LaunchSets ls, int tstep) {
+    const TileRef tr = locate<false>(ls);
+    const SetDesc &d = *tr.d;
+    const SolveState *st_ = d.st;
+    if (!st_->active) return;
+    PhPc ph;
+    for (int k = 0; k < 7; ++k) ph.a[k] = d.a[k];
+    ph.tstep = tstep != 0;
+    ph.x = ph.tstep ? d.v[1] : d.p[1];
+    ph.wv = ph.tstep ? d.s1 : d.rh;
+    ph.y = ph.tstep ? d.t : d.v[0];
+    ph.nx = d.nx;
+    ph.P = d.plane;
+    ph.ncell = d.n;
+    double acc[3] = {0.0, 0.0, 0.0};
+    march<double, CPT, H>(ph, geo_of(d), tr.tile, lds_base<double>(), acc);
+    if (ph.tstep) {
+        reduce_and_finalize<3>(d, tr.tile, d.ntiles, acc, FinK2{});
+    } else {
+        double sig[1] = {acc[0]};
+        reduce_and_finalize<1>(d, tr.tile, d.ntiles, sig, FinK1{});
+    }
+}
+
+// s = r - alpha v
+__global__ void __launch_bounds__(kBlock) pc_s_kernel(LaunchSets ls) {
+    const TileRef tr = locate<true>(ls);
+    const SetDesc &d = *tr.d;
+    const SolveState *st_ = d.st;
+    if (!st_->active) return;
+    const double al = st_->alpha;
+    const double *r = d.r, *v = d.v[0];
+    double *s = d.s1;
+    const int n = d.n, nflat = d.nflat;
+    for (int ch = tr.tile; ch * kFlatChunk < n; ch += nflat) {
+        const int base = ch * kFlatChunk + (int)threadIdx.x;
+        double R[kFlatU], V[kFlatU];
+#pragma unroll
+        for (int u = 0; u < kFlatU; ++u) {
+            const int i = min(base + kBlock * u, n - 1);
+            R[u] = ld(r, i);
+            V[u] = ld(v, i);
+        }
+#pragma unroll
+        for (int u = 0; u < kFlatU; ++u) {
+            const int i = base + kBlock * u;
+            if (i < n) st(s, i, fma(-al, V[u], R[u]));
+        }
+    }
+}
+
+// x += alpha p^ + omega s^; r = s - omega t; (r^, r), (r, r)
+__global__ void __launch_bounds__(kBlock) pc_x_kernel(LaunchSets ls) {
+    const TileRef tr = locate<true>(ls);
+    const SetDesc &d = *tr.d;
+    const SolveState *st_ = d.st;
+    if (!st_->active) return;
+    const double al = st_->alpha, om = st_->omega;
+    const double *ph = d.p[1], *sh = d.v[1], *s = d.s1, *t = d.t, *rh = d.rh;
+    double *x = d.x, *r = d.r;
+    const int n = d.n, nflat = d.nflat;
+    double acc[2] = {0.0, 0.0};
+    for (int ch = tr.tile; ch * kFlatChunk < n; ch += nflat) {
+        const int base = ch * kFlatChunk + (int)threadIdx.x;
+        double X[kFlatU], PH[kFlatU], SH[kFlatU], S[kFlatU], Tt[kFlatU], RH[kFlatU];
+#pragma unroll
+        for (int u = 0; u < kFlatU; ++u) {
+            const int i = min(base + kBlock * u, n - 1);
+            X[u] = ld(x, i); PH[u] = ld(ph, i); SH[u] = ld(sh, i);
+            S[u] = ld(s, i); Tt[u] = ld(t, i); RH[u] = ld(rh, i);
+        }
+#pragma unroll
+        for (int u = 0; u < kFlatU; ++u) {
+            const int i = base + kBlock * u;
+            if (i < n) {
+                st(x, i, X[u] + fma(al, PH[u], om * SH[u]));
+                const double rn = fma(-om, Tt[u], S[u]);
+                st(r, i, rn);
+                acc[0] += RH[u] * rn;
+                acc[1] += rn * rn;
+            }
+        }
+    }
+    reduce_and_finalize<2>(d, tr.tile, nflat, acc, FinK3{});
+}
+
 // ------------------------------------------------------------------ host launchers
 
 hipError_t launch_small(const LaunchSets &ls, int max_n, bool trans, hipStream_t stream) {
@@ -1795,6 +2099,34 @@ hipError_t launch_small(const LaunchSets &ls, int max_n, bool trans, hipStream_t
         if (trans) hipLaunchKernelGGL((small_kernel<4, true>), grid, block, 0, stream, ls);
         else hipLaunchKernelGGL((small_kernel<4, false>), grid, block, 0, stream, ls);
     }
+    return hipGetLastError();
+}
+
+static dim3 mg_grid(int n) { return dim3((unsigned)std::max(1, std::min((n + kBlock - 1) / kBlock, 8192))); }
+
+hipError_t launch_mg_coarsen(const SetDesc *d, const MgLevel *lev, int l, int nc, hipStream_t stream) {
+    hipLaunchKernelGGL(mg_coarsen_kernel, mg_grid(nc), dim3(kBlock), 0, stream, d, lev, l);
+    return hipGetLastError();
+}
+
+hipError_t launch_mg_restrict(const SetDesc *d, const MgLevel *lev, int l, int nc, const double *rin, MgParams prm,
+                              bool gated, hipStream_t stream) {
+    hipLaunchKernelGGL(mg_restrict_kernel, mg_grid(nc), dim3(kBlock), 0, stream, d, lev, l, rin, prm, gated ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_mg_coarsest(const SetDesc *d, const MgLevel *lev, int l, int n, const double *rin, double *zout,
+                              MgParams prm, bool gated, hipStream_t stream) {
+    if (n > kMgCoarsestMax) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(mg_coarsest_kernel, dim3(1), dim3(kMgCoarseThreads), 0, stream, d, lev, l, rin, zout, prm,
+                       gated ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_mg_prolong(const SetDesc *d, const MgLevel *lev, int l, int n, const double *rin, double *zout,
+                             MgParams prm, bool gated, hipStream_t stream) {
+    hipLaunchKernelGGL(mg_prolong_kernel, mg_grid(n), dim3(kBlock), 0, stream, d, lev, l, rin, zout, prm,
+                       gated ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -1928,6 +2260,21 @@ hipError_t launch_kernel(Kern k, const LaunchSets &ls, int ntiles, int nflat, in
         if (fp32) EQS_LAUNCH((mat_kernel<float>), fgrid, block, 0, ls);
         else EQS_LAUNCH((mat_kernel<double>), fgrid, block, 0, ls);
         break;
+    case K_PC_P:
+        EQS_LAUNCH(pc_p_kernel, fgrid, block, 0, ls);
+        break;
+    case K_PC_V:
+    case K_PC_T:
+        EQS_DISPATCH(cpt, h, EQS_LAUNCH((pc_prod_kernel<C, HH>), grid, block, lds64, ls, k == K_PC_T ? 1 : 0));
+        break;
+    case K_PC_S:
+        EQS_LAUNCH(pc_s_kernel, fgrid, block, 0, ls);
+        break;
+    case K_PC_X:
+        EQS_LAUNCH(pc_x_kernel, fgrid, block, 0, ls);
+        break;
+    default:
+        return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }

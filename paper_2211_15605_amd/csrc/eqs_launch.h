@@ -25,8 +25,27 @@ enum Kern {
     K_UNSCALE,  // x = y / a_P (before a recheck or a final report)
     K_FUSED,    // single-sync iteration: both products and all ten dot products in one launch
     K_FSETUP,   // f = M^T r^, (f, r^), (r^, r^) after a fresh start (single-sync iteration)
-    K_MAT       // form the iterate (and a restart residual) on leaving the single-sync iteration
+    K_MAT,      // form the iterate (and a restart residual) on leaving the single-sync iteration
+    K_PC_P,     // multigrid-preconditioned iteration: p = r + beta (p - omega v)
+    K_PC_V,     // v = A p^, (r^, v)
+    K_PC_S,     // s = r - alpha v
+    K_PC_T,     // t = A s^, (t,s), (t,t), (s,s)
+    K_PC_X,     // x += alpha p^ + omega s^, r = s - omega t, (r^, r), (r, r)
+    K_MG        // one V-cycle level step (restriction, coarsest sweeps or prolongation + smoothing)
 };
+
+// multigrid kernels of set `set` (d: its device table entry, lev: its device level table)
+hipError_t launch_mg_coarsen(const SetDesc *d, const MgLevel *lev, int l, int nc, hipStream_t stream);
+// V-cycle: restriction from level l to l+1 (nc = cells of level l+1); rin = level l's right-hand side
+hipError_t launch_mg_restrict(const SetDesc *d, const MgLevel *lev, int l, int nc, const double *rin, MgParams prm,
+                              bool gated, hipStream_t stream);
+// coarsest level l (n cells, at most kMgCoarsestMax): coarse_sweeps damped-Jacobi sweeps from zero
+constexpr int kMgCoarsestMax = 2048;
+hipError_t launch_mg_coarsest(const SetDesc *d, const MgLevel *lev, int l, int n, const double *rin, double *zout,
+                              MgParams prm, bool gated, hipStream_t stream);
+// prolongation of level l+1's result and one smoothing sweep on level l (n = cells of level l)
+hipError_t launch_mg_prolong(const SetDesc *d, const MgLevel *lev, int l, int n, const double *rin, double *zout,
+                             MgParams prm, bool gated, hipStream_t stream);
 
 // LDS bytes of the single-sync kernel (p and s, three planes each of Q + 4 nx values)
 size_t fused_lds_bytes(int cpt, int max_nx, int elem);

@@ -93,6 +93,29 @@ class Context:
         keys = ("cpt", "segments", "kc", "chunks", "tiles", "readbacks", "syncs", "flat_blocks")
         return dict(zip(keys, v))
 
+    def set_preconditioner(self, kind="jacobi", **params):
+        """'jacobi' (default) or 'mg' (aggregation multigrid V-cycle, FP64 contexts; params:
+        omega, gamma, coarse_sweeps, coarse_cells).  See eqsolve_set_preconditioner."""
+        k = {"jacobi": B.EQS_PRECOND_JACOBI, "mg": B.EQS_PRECOND_MG}.get(kind)
+        if k is None:
+            raise ValueError("preconditioner must be 'jacobi' or 'mg'")
+        rc = B.eqsolve_set_preconditioner(self.h, k, params or None)
+        if rc != 0:
+            raise EqSolveError(rc, "eqsolve_set_preconditioner")
+
+    def precond_apply(self, diags, r, set_id=0, out=None):
+        """z = B^-1 r, one V-cycle of the multigrid preconditioner (diagnostics); returns (z, levels)."""
+        import torch
+        n = self.n(set_id)
+        dp = self._diag_ptrs(diags, n)
+        rp = _check_vec(r, n, "r", self.device)
+        z = out if out is not None else torch.empty_like(r)
+        zp = _check_vec(z, n, "z", self.device)
+        rc, levels = B.eqsolve_debug_precond(self.h, set_id, dp, rp, zp)
+        if rc != 0:
+            raise EqSolveError(rc, "eqsolve_debug_precond")
+        return z, levels
+
     def autotune(self, cache_path=None, iters=6):
         """Choose every set's launch shape by timing candidates on synthetic systems of the
         same shapes (see eqsolve_autotune); returns the new layouts."""

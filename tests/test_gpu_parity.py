@@ -417,3 +417,96 @@ def test_config1_full_size_residual(torch_dev, orc, precision, scheme):
     rel = orc.rel_residual(g.shape, diags, b, xg)
     assert rel <= 1e-10
     assert np.max(np.abs(xg - xs)) <= orc.forward_error_certificate(g.shape, diags, b, xg) * (1 + 1e-6)
+
+
+# ---------------------------------------------------------------- multigrid preconditioner
+
+MG_SMALL = dict(omega=0.8, gamma=1.6, coarse_sweeps=7, coarse_cells=16)
+
+
+@pytest.mark.parametrize("cfg,shape", [(0, (20, 17, 9)), (1, (33, 64, 17)), (0, (5, 1, 1)), (2, (1, 40, 3)),
+                                       (1, (16, 16, 16))])
+def test_mg_vcycle_matches_oracle(torch_dev, orc, cfg, shape):
+    # the V-cycle takes the definition's operations in its order with no FMA contraction:
+    # the same bits as the oracle's plain evaluation
+    from oracle import oracle as O
+    torch, dev = torch_dev
+    g = W.Grid(*shape)
+    diags = W.make_set(cfg, 0, grid=g)["diags"]
+    r = np.random.default_rng(11).standard_normal(g.n)
+    zo, lo = orc.mg_apply(g.shape, diags, r, O.mg_params(**MG_SMALL))
+    ctx = context([g.shape])
+    ctx.set_preconditioner("mg", **MG_SMALL)
+    z, lev = ctx.precond_apply(dev_arrays(torch, dev, diags), dev_arrays(torch, dev, [r])[0])
+    zg = host(z)
+    assert lev == lo
+    err = np.max(np.abs(zg - zo)) / np.max(np.abs(zo))
+    print("mg vcycle", shape, "levels", lev, "bitwise", np.array_equal(zg, zo), "max rel diff %.2e" % err, flush=True)
+    assert np.array_equal(zg, zo)
+
+
+@pytest.mark.parametrize("cfg,shape,gamma", [(1, (32, 64, 32), 1.6), (0, (20, 30, 15), 1.0), (2, (25, 48, 24), 1.0)])
+def test_mg_solve_matches_oracle(torch_dev, orc, cfg, shape, gamma):
+    from oracle import oracle as O
+    torch, dev = torch_dev
+    g, diags, b, xs = manufactured(orc, cfg, grid=W.Grid(*shape))
+    prm = dict(omega=0.8, gamma=gamma, coarse_sweeps=30, coarse_cells=512)
+    xo, oinfo = orc.bicgstab_mg(g.shape, diags, b, tol=1e-12, maxit=500, params=O.mg_params(**prm))
+    assert oinfo["status"] == 0
+    ctx = context([g.shape])
+    ctx.set_preconditioner("mg", **prm)
+    x, info = ctx.solve(dev_arrays(torch, dev, diags), dev_arrays(torch, dev, [b])[0], tol=1e-12, maxit=500)
+    xg = host(x)
+    print("mg solve", shape, "gpu", info, "oracle", oinfo, flush=True)
+    assert info["status"] == 0
+    assert orc.rel_residual(g.shape, diags, b, xg) <= 1e-12
+    assert abs(info["iters"] - oinfo["iters"]) <= 2
+    assert np.max(np.abs(xg - xs)) <= orc.forward_error_certificate(g.shape, diags, b, xg) * (1 + 1e-6)
+    if cfg != 1:  # well-conditioned systems: the two solutions agree to 1e-10
+        assert np.linalg.norm(xg - xo) <= 1e-10 * np.linalg.norm(xo)
+
+
+def test_mg_batched_equals_sequential_and_statuses(torch_dev, orc):
+    torch, dev = torch_dev
+    systems = [manufactured(orc, 2, grid=W.Grid(*s), set_id=i) for i, s in enumerate(STAGGERED_SMALL)]
+    ctx = context(STAGGERED_SMALL)
+    ctx.set_preconditioner("mg")
+    Ds = [dev_arrays(torch, dev, s[1]) for s in systems]
+    bs = [dev_arrays(torch, dev, [s[2]])[0] for s in systems]
+    xb, infos = ctx.solve_batched(Ds, bs, tol=1e-10, maxit=500)
+    for i, s in enumerate(systems):
+        xi, info = ctx.solve(Ds[i], bs[i], tol=1e-10, maxit=500, set_id=i)
+        assert np.array_equal(host(xi), host(xb[i])) and info == infos[i]
+        assert orc.rel_residual(s[0].shape, s[1], s[2], host(xb[i])) <= 1e-10
+    # maxit too small: computed, not converged; exact initial guess: no iteration; b = 0: x = 0
+    g, diags, b, xs = systems[0]
+    x, info = ctx.solve(Ds[0], bs[0], tol=1e-13, maxit=1, check=False)
+    assert info["status"] == 1 and info["iters"] == 1
+    assert abs(info["rel_res"] - orc.rel_residual(g.shape, diags, b, host(x))) <= 1e-8 * info["rel_res"]
+    x, info = ctx.solve(Ds[0], bs[0], x=dev_arrays(torch, dev, [xs])[0], tol=1e-10)
+    assert info["iters"] == 0 and np.array_equal(host(x), xs)
+    x, info = ctx.solve(Ds[0], torch.zeros_like(bs[0]), x=torch.ones_like(bs[0]), tol=1e-10)
+    assert info["status"] == 0 and not np.any(host(x))
+
+
+def test_mg_needs_an_fp64_context(torch_dev):
+    from paper_2211_15605_amd.solver import EqSolveError
+    ctx = context([(8, 8, 8)], precision="fp32_refine")
+    with pytest.raises(EqSolveError):
+        ctx.set_preconditioner("mg")
+    ctx = context([(8, 8, 8)])
+    with pytest.raises(EqSolveError):
+        ctx.set_preconditioner("mg", coarse_cells=4096)  # beyond the one-block coarsest solve
+
+
+def test_mg_config1_full_size(torch_dev, orc):
+    torch, dev = torch_dev
+    g, diags, b, xs = manufactured(orc, 1)
+    ctx = context([g.shape])
+    ctx.set_preconditioner("mg", gamma=1.6)
+    x, info = ctx.solve(dev_arrays(torch, dev, diags), dev_arrays(torch, dev, [b])[0], tol=1e-10, maxit=500)
+    print("config1 mg", info, flush=True)
+    assert info["status"] == 0 and info["iters"] <= 40
+    xg = host(x)
+    assert orc.rel_residual(g.shape, diags, b, xg) <= 1e-10
+    assert np.max(np.abs(xg - xs)) <= orc.forward_error_certificate(g.shape, diags, b, xg) * (1 + 1e-6)
