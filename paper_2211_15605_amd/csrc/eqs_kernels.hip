@@ -1848,7 +1848,10 @@ __global__ void __launch_bounds__(kBlock) mg_coarsen_kernel(const SetDesc *d, co
     }
 }
 
-// R (r - A z1) with z1 = omega D^-1 r, into level l + 1's right-hand side
+// R (r - A z1) with z1 = omega D^-1 r, into level l + 1's right-hand side.
+// Eight consecutive lanes take the eight cells of one aggregate (lane bits:
+// i, j, k offsets), so a wave reads rows of 16 consecutive cells; lane 0 of
+// the group sums the group's values in cell-index order (the definition's).
 __global__ void __launch_bounds__(kBlock) mg_restrict_kernel(const SetDesc *d, const MgLevel *lev, int l,
                                                              const double *rin, MgParams prm, int gated) {
 #pragma clang fp contract(off)
@@ -1860,17 +1863,35 @@ __global__ void __launch_bounds__(kBlock) mg_restrict_kernel(const SetDesc *d, c
     const double w = prm.omega;
     const double *ap = a[0];
     auto z1 = [&](int x, int, int, int) { return w * ld(rin, x) / ld(ap, x); };
-    for (int cc = blockIdx.x * kBlock + threadIdx.x; cc < C.n; cc += gridDim.x * kBlock) {
-        const int I = cc % cx, t = cc / cx, J = t % cy, K = t / cy;
-        double sum = 0.0;
-        for (int k = 2 * K; k < min(2 * K + 2, nz); ++k)
-            for (int j = 2 * J; j < min(2 * J + 2, ny); ++j)
-                for (int i = 2 * I; i < min(2 * I + 2, nx); ++i) {
-                    const int c = i + nx * (j + ny * k);
-                    const double q = mg_row(a, nx, ny, nz, i, j, k, c, z1);
-                    sum += ld(rin, c) - q;
-                }
-        st(C.r, cc, sum);
+    const int g8 = threadIdx.x & 7, di = g8 & 1, dj = (g8 >> 1) & 1, dk = g8 >> 2;
+    const int stride = (int)(gridDim.x * kBlock) >> 3;
+    // the loop bound is uniform over a wave (the shuffles need every lane of a group)
+    for (int w0 = (int)(blockIdx.x * kBlock + (threadIdx.x & ~63)) >> 3; w0 < C.n; w0 += stride) {
+        const int cc = w0 + (int)((threadIdx.x & 63) >> 3);
+        const bool inC = cc < C.n;
+        const int ccl = min(cc, C.n - 1);
+        const int I = ccl % cx, t = ccl / cx, J = t % cy, K = t / cy;
+        const int i = 2 * I + di, j = 2 * J + dj, k = 2 * K + dk;
+        const bool ok = inC && i < nx && j < ny && k < nz;
+        double q = 0.0;
+        if (ok) {
+            const int c = i + nx * (j + ny * k);
+            q = ld(rin, c) - mg_row(a, nx, ny, nz, i, j, k, c, z1);
+        }
+        double qs[8];
+        int oks[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            qs[m] = __shfl(q, m, 8);
+            oks[m] = __shfl(ok ? 1 : 0, m, 8);
+        }
+        if (g8 == 0 && inC) {
+            double sum = 0.0;
+#pragma unroll
+            for (int m = 0; m < 8; ++m)
+                if (oks[m]) sum += qs[m];
+            st(C.r, cc, sum);
+        }
     }
 }
 
@@ -1896,8 +1917,10 @@ __global__ void __launch_bounds__(kBlock) mg_prolong_kernel(const SetDesc *d, co
     }
 }
 
-// coarsest level: coarse_sweeps damped-Jacobi sweeps from zero in one block
+// coarsest level: coarse_sweeps damped-Jacobi sweeps from zero in one block;
+// a thread keeps its cells' coefficients and right-hand side in registers
 constexpr int kMgCoarseThreads = 1024;
+constexpr int kMgCoarseCells = kMgCoarsestMax / kMgCoarseThreads;
 __global__ void __launch_bounds__(kMgCoarseThreads) mg_coarsest_kernel(const SetDesc *d, const MgLevel *lev, int l,
                                                                        const double *rin, double *zout,
                                                                        MgParams prm, int gated) {
@@ -1907,23 +1930,49 @@ __global__ void __launch_bounds__(kMgCoarseThreads) mg_coarsest_kernel(const Set
     const MgLevel F = lev[l];
     const double *a[7];
     for (int q = 0; q < 7; ++q) a[q] = mg_coef(d, F, l, q);
-    const int nx = F.nx, ny = F.ny, nz = F.nz, n = F.n;
+    const int nx = F.nx, ny = F.ny, nz = F.nz, n = F.n, P = nx * ny;
     const double w = prm.omega;
-    for (int c = threadIdx.x; c < n; c += kMgCoarseThreads) zb[0][c] = 0.0;
+    double co[kMgCoarseCells][7], rr[kMgCoarseCells];
+    int cell[kMgCoarseCells];
+    bool has[kMgCoarseCells][6];
+#pragma unroll
+    for (int m = 0; m < kMgCoarseCells; ++m) {
+        const int c = threadIdx.x + kMgCoarseThreads * m;
+        cell[m] = c;
+        const int cl = min(c, n - 1);
+        const int i = cl % nx, t = cl / nx, j = t % ny, k = t / ny;
+        has[m][0] = i + 1 < nx;
+        has[m][1] = i > 0;
+        has[m][2] = j + 1 < ny;
+        has[m][3] = j > 0;
+        has[m][4] = k + 1 < nz;
+        has[m][5] = k > 0;
+        for (int q = 0; q < 7; ++q) co[m][q] = ld(a[q], cl);
+        rr[m] = ld(rin, cl);
+        if (c < n) zb[0][c] = 0.0;
+    }
     __syncthreads();
+    const int off[6] = {1, -1, nx, -nx, P, -P};
     int cur = 0;
     for (int it = 0; it < prm.coarse_sweeps; ++it) {
         const double *zc = zb[cur];
-        auto zat = [&](int x, int, int, int) { return zc[x]; };
-        for (int c = threadIdx.x; c < n; c += kMgCoarseThreads) {
-            const int i = c % nx, t = c / nx, j = t % ny, k = t / ny;
-            const double q = mg_row(a, nx, ny, nz, i, j, k, c, zat);
-            zb[cur ^ 1][c] = zc[c] + w * (ld(rin, c) - q) / ld(a[0], c);
+#pragma unroll
+        for (int m = 0; m < kMgCoarseCells; ++m) {
+            const int c = cell[m];
+            if (c < n) {
+                double acc = co[m][0] * zc[c];  // a_P z, then E, W, N, S, T, B in order
+#pragma unroll
+                for (int q = 0; q < 6; ++q)
+                    if (has[m][q]) acc -= co[m][1 + q] * zc[c + off[q]];
+                zb[cur ^ 1][c] = zc[c] + w * (rr[m] - acc) / co[m][0];
+            }
         }
         __syncthreads();
         cur ^= 1;
     }
-    for (int c = threadIdx.x; c < n; c += kMgCoarseThreads) st(zout, c, zb[cur][c]);
+#pragma unroll
+    for (int m = 0; m < kMgCoarseCells; ++m)
+        if (cell[m] < n) st(zout, cell[m], zb[cur][cell[m]]);
 }
 
 // ---- BiCGSTAB with the V-cycle as right preconditioner (FP64, original A, x updated in place).
@@ -2111,7 +2160,9 @@ hipError_t launch_mg_coarsen(const SetDesc *d, const MgLevel *lev, int l, int nc
 
 hipError_t launch_mg_restrict(const SetDesc *d, const MgLevel *lev, int l, int nc, const double *rin, MgParams prm,
                               bool gated, hipStream_t stream) {
-    hipLaunchKernelGGL(mg_restrict_kernel, mg_grid(nc), dim3(kBlock), 0, stream, d, lev, l, rin, prm, gated ? 1 : 0);
+    // eight lanes per coarse cell
+    hipLaunchKernelGGL(mg_restrict_kernel, mg_grid(8 * nc), dim3(kBlock), 0, stream, d, lev, l, rin, prm,
+                       gated ? 1 : 0);
     return hipGetLastError();
 }
 
