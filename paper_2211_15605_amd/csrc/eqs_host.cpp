@@ -636,21 +636,33 @@ void clear_graphs(eqs_ctx *c) {
 
 // ------------------------------------------------------------------ multigrid-preconditioned iteration
 
-// z = B^-1 r for set s (one V-cycle); gated launches do nothing once the set stops iterating
-hipError_t mg_vcycle(eqs_ctx *c, int s, const double *r, double *z, bool gated, hipStream_t stream) {
+// z = B^-1 r for the run's (single) set: one V-cycle; gated launches do nothing once the
+// set stops iterating.  The finest level goes through the k-march on the set's tiles
+// (its per-cell residual in the set's y buffer, unused by this iteration); the coarser
+// levels through per-cell kernels.
+hipError_t mg_vcycle(const Run &R, const double *r, double *z, bool gated, hipStream_t stream) {
+    eqs_ctx *c = R.c;
+    const int s = R.first;
     const std::vector<MgLevel> &L = c->mg[s];
     const int nl = (int)L.size();
     const SetDesc *dd = c->d_desc + s;
     const MgLevel *lev = c->d_mg + (size_t)s * kMgMaxLevels;
+    double *res = c->sets[s].y;
     hipError_t e = hipSuccess;
-    for (int l = 0; l + 1 < nl && e == hipSuccess; ++l)
-        e = launch_mg_restrict(dd, lev, l, L[l + 1].n, l == 0 ? r : L[l].r, c->mgp, gated, stream);
+    if (nl > 1) {
+        e = launch_mg_fine(R.ls, R.ntiles, c->cpt, R.max_nx, lev, r, res, nullptr, c->mgp, gated, stream);
+        if (e == hipSuccess) e = launch_mg_aggregate(dd, lev, L[1].n, res, gated, stream);
+    }
+    for (int l = 1; l + 1 < nl && e == hipSuccess; ++l)
+        e = launch_mg_restrict(dd, lev, l, L[l + 1].n, L[l].r, c->mgp, gated, stream);
     if (e == hipSuccess)
         e = launch_mg_coarsest(dd, lev, nl - 1, L[nl - 1].n, nl == 1 ? r : L[nl - 1].r, nl == 1 ? z : L[nl - 1].z,
                                c->mgp, gated, stream);
-    for (int l = nl - 2; l >= 0 && e == hipSuccess; --l)
-        e = launch_mg_prolong(dd, lev, l, L[l].n, l == 0 ? r : L[l].r, l == 0 ? z : L[l].z, c->mgp, gated, stream);
-    c->launches += 2 * nl - 1;
+    for (int l = nl - 2; l >= 1 && e == hipSuccess; --l)
+        e = launch_mg_prolong(dd, lev, l, L[l].n, L[l].r, L[l].z, c->mgp, gated, stream);
+    if (nl > 1 && e == hipSuccess)
+        e = launch_mg_fine(R.ls, R.ntiles, c->cpt, R.max_nx, lev, r, nullptr, z, c->mgp, gated, stream);
+    c->launches += 2 * nl;
     return e;
 }
 
@@ -672,10 +684,10 @@ hipError_t mg_iteration(Run &R, hipStream_t stream) {
         return launch_kernel(k, R.ls, R.ntiles, R.nflat, c->cpt, R.max_nx, false, false, stream, nullptr, nullptr, 0);
     };
     hipError_t e = K(K_PC_P);
-    if (e == hipSuccess) e = mg_vcycle(c, R.first, h.p[0], h.p[1], true, stream);  // p^ = B^-1 p
+    if (e == hipSuccess) e = mg_vcycle(R, h.p[0], h.p[1], true, stream);  // p^ = B^-1 p
     if (e == hipSuccess) e = K(K_PC_V);
     if (e == hipSuccess) e = K(K_PC_S);
-    if (e == hipSuccess) e = mg_vcycle(c, R.first, h.s1, h.v[1], true, stream);    // s^ = B^-1 s
+    if (e == hipSuccess) e = mg_vcycle(R, h.s1, h.v[1], true, stream);    // s^ = B^-1 s
     if (e == hipSuccess) e = K(K_PC_T);
     if (e == hipSuccess) e = K(K_PC_X);
     return e;
@@ -718,7 +730,7 @@ int mg_iterate(Run &R, int C) {
                 slots[b] = ex;
             }
             EQS_HIP(hipGraphLaunch(slots[b], c->stream));
-            c->launches += (uint64_t)(5 + 2 * (2 * (int)c->mg[R.first].size() - 1)) << b;
+            c->launches += (uint64_t)(5 + 2 * (2 * (int)c->mg[R.first].size())) << b;
             C -= 1 << b;
         }
     }
@@ -1050,7 +1062,8 @@ int eqsolve_debug_precond(eqs_ctx *c, int32_t set, const double *const diag[7], 
     for (int k = 0; k < 7; ++k) d.a[k] = diag[k];
     int rc = upload_desc(c, set, 1);
     if (rc) return rc;
-    if (mg_coarsen_all(c, set) != hipSuccess || mg_vcycle(c, set, r, z, false, c->stream) != hipSuccess ||
+    const Run R = make_run(c, set, 1, false);
+    if (mg_coarsen_all(c, set) != hipSuccess || mg_vcycle(R, r, z, false, c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess) {
         (void)hipGetLastError();
         c->broken = true;

@@ -493,7 +493,8 @@ __device__ __forceinline__ Geo geo_of(const SetDesc &d) {
 }
 //
 // A phase Ph supplies:
-//   Raw  load(idx)                 raw inputs of the stencil operand at a cell
+//   Raw  load(idx, q, k)           raw inputs of the stencil operand at cell idx
+//                                  (in-plane index q, plane k)
 //   T    own(raw, idx, Aux&)       operand value of an own cell (+ its stores)
 //   T    halo(raw)                 operand value of any other cell (no stores)
 //   void pre(idx, nb, up, dn, Pre&)  loads for the centre pass of an own cell
@@ -512,7 +513,7 @@ __device__ __forceinline__ void ext_plane(Ph &ph, const Geo &d, int k, T *buf, c
     int he[H];
     bool hv[H];
 #pragma unroll
-    for (int m = 0; m < CPT; ++m) ro[m] = ph.load(min(qo[m], P - 1) + kb);
+    for (int m = 0; m < CPT; ++m) ro[m] = ph.load(min(qo[m], P - 1) + kb, min(qo[m], P - 1), k);
 #pragma unroll
     for (int hh = 0; hh < H; ++hh) {
         const int h = (int)threadIdx.x + kBlock * hh;
@@ -520,7 +521,7 @@ __device__ __forceinline__ void ext_plane(Ph &ph, const Geo &d, int k, T *buf, c
         const int q = q0 - nx + e;
         he[hh] = h < 2 * nx ? e : -1;
         hv[hh] = h < 2 * nx && q >= 0 && q < P;
-        rh[hh] = ph.load(min(max(q, 0), P - 1) + kb);
+        rh[hh] = ph.load(min(max(q, 0), P - 1) + kb, min(max(q, 0), P - 1), k);
     }
 #pragma unroll
     for (int m = 0; m < CPT; ++m) {
@@ -563,7 +564,7 @@ __device__ __forceinline__ void march(Ph &ph, const Geo &d, int tile, T *lds, do
     {
         typename Ph::Raw rb[CPT];
 #pragma unroll
-        for (int m = 0; m < CPT; ++m) rb[m] = ph.load(min(qo[m], P - 1) + max(k0 - 1, 0) * P);
+        for (int m = 0; m < CPT; ++m) rb[m] = ph.load(min(qo[m], P - 1) + max(k0 - 1, 0) * P, min(qo[m], P - 1), max(k0 - 1, 0));
 #pragma unroll
         for (int m = 0; m < CPT; ++m) vm[m] = (k0 > 0 && ok[m]) ? ph.halo(rb[m]) : T(0);
     }
@@ -580,7 +581,8 @@ __device__ __forceinline__ void march(Ph &ph, const Geo &d, int tile, T *lds, do
         } else {
             typename Ph::Raw rb[CPT];
 #pragma unroll
-            for (int m = 0; m < CPT; ++m) rb[m] = ph.load(min(qo[m], P - 1) + min(k + 1, nz - 1) * P);
+            for (int m = 0; m < CPT; ++m)
+                rb[m] = ph.load(min(qo[m], P - 1) + min(k + 1, nz - 1) * P, min(qo[m], P - 1), min(k + 1, nz - 1));
 #pragma unroll
             for (int m = 0; m < CPT; ++m) vp[m] = (up && ok[m]) ? ph.halo(rb[m]) : T(0);
         }
@@ -706,7 +708,7 @@ struct PhK1 {
     T *pnew, *vnew, *rhw;
     T beta, omega;
     bool fresh;
-    __device__ __forceinline__ Raw load(int idx) const {
+    __device__ __forceinline__ Raw load(int idx, int, int) const {
         Raw w;
         w.r = ld(r, idx);
         w.p = ld(pold, idx);
@@ -746,7 +748,7 @@ struct PhK2 {
     const T *r, *v;
     T *tout;
     T alpha;
-    __device__ __forceinline__ Raw load(int idx) const {
+    __device__ __forceinline__ Raw load(int idx, int, int) const {
         Raw w;
         w.r = ld(r, idx);
         w.v = ld(v, idx);
@@ -785,7 +787,7 @@ struct PhRes {
     double *r, *rh, *y;
     int nx, P, ncell;
     bool write;
-    __device__ __forceinline__ Raw load(int idx) const { return Raw{ld(x, idx)}; }
+    __device__ __forceinline__ Raw load(int idx, int, int) const { return Raw{ld(x, idx)}; }
     __device__ __forceinline__ double own(const Raw &w, int, Aux &) { return w.x; }
     __device__ __forceinline__ double halo(const Raw &w) const { return w.x; }
     __device__ __forceinline__ void pre(int idx, Nb nb, bool up, bool dn, Pre &pr) const {
@@ -819,7 +821,7 @@ struct PhOuter {
     float *r32, *rh32, *d32;
     double scale;
     int nx, P, ncell;
-    __device__ __forceinline__ Raw load(int idx) const { return Raw{ld(x, idx)}; }
+    __device__ __forceinline__ Raw load(int idx, int, int) const { return Raw{ld(x, idx)}; }
     __device__ __forceinline__ double own(const Raw &w, int, Aux &) { return w.x; }
     __device__ __forceinline__ double halo(const Raw &w) const { return w.x; }
     __device__ __forceinline__ void pre(int idx, Nb nb, bool up, bool dn, Pre &pr) const {
@@ -850,7 +852,7 @@ struct PhApply {
     const double *x;
     double *y;
     int nx, P, ncell;
-    __device__ __forceinline__ Raw load(int idx) const { return Raw{ld(x, idx)}; }
+    __device__ __forceinline__ Raw load(int idx, int, int) const { return Raw{ld(x, idx)}; }
     __device__ __forceinline__ double own(const Raw &w, int, Aux &) { return w.x; }
     __device__ __forceinline__ double halo(const Raw &w) const { return w.x; }
     __device__ __forceinline__ void pre(int idx, Nb nb, bool up, bool dn, Pre &pr) const {
@@ -874,7 +876,7 @@ struct PhFSet {
     const T *rh;
     T *f;
     int nx, P, ncell;
-    __device__ __forceinline__ Raw load(int idx) const { return Raw{ld(rh, idx)}; }
+    __device__ __forceinline__ Raw load(int idx, int, int) const { return Raw{ld(rh, idx)}; }
     __device__ __forceinline__ T own(const Raw &w, int, Aux &) { return w.x; }
     __device__ __forceinline__ T halo(const Raw &w) const { return w.x; }
     __device__ __forceinline__ void pre(int idx, Nb nb, bool up, bool dn, Pre &pr) const {
@@ -1975,6 +1977,168 @@ __global__ void __launch_bounds__(kMgCoarseThreads) mg_coarsest_kernel(const Set
         if (cell[m] < n) st(zout, cell[m], zb[cur][cell[m]]);
 }
 
+// ---- finest level through the k-march (operands staged in LDS like the
+// iteration's stencil passes): the residual of the pre-smoothed iterate, and
+// the prolongation with its smoothing step.  Same operations and order as the
+// per-cell kernels above (an absent neighbour's coefficient is zero, so its
+// term subtracts an exact zero).
+
+// q = r - A z1 with z1 = omega D^-1 r, per cell (summed over aggregates by mg_aggregate_kernel)
+struct PhMgResid {
+    static constexpr int NV = 1;
+    struct Raw { double r, ap; };
+    struct Aux { double r, ap; };
+    struct Pre { Coef6<double, false> c; };
+    const double *a[7];
+    const double *rin;
+    double *res;
+    double w;
+    int nx, P, ncell;
+    __device__ __forceinline__ Raw load(int idx, int, int) const { return Raw{ld(rin, idx), ld(a[0], idx)}; }
+    __device__ __forceinline__ double zval(const Raw &v) const {
+#pragma clang fp contract(off)
+        return w * v.r / v.ap;
+    }
+    __device__ __forceinline__ double own(const Raw &v, int, Aux &ax) {
+        ax.r = v.r;
+        ax.ap = v.ap;
+        return zval(v);
+    }
+    __device__ __forceinline__ double halo(const Raw &v) const { return zval(v); }
+    __device__ __forceinline__ void pre(int idx, Nb nb, bool up, bool dn, Pre &pr) const {
+        pr.c.load(a, idx, nx, P, ncell, nb, up, dn);
+    }
+    __device__ __forceinline__ void center(int idx, const Pre &pr, const Aux &ax, double xc, double xE, double xW,
+                                           double xN, double xS, double xT, double xB, double (&)[NV]) {
+#pragma clang fp contract(off)
+        double q = ax.ap * xc;
+        q -= pr.c.e * xE;
+        q -= pr.c.w * xW;
+        q -= pr.c.n * xN;
+        q -= pr.c.s * xS;
+        q -= pr.c.t * xT;
+        q -= pr.c.b * xB;
+        st(res, idx, ax.r - q);
+    }
+};
+
+// z = z2 + omega D^-1 (r - A z2) with z2 = omega D^-1 r + gamma e(aggregate)
+struct PhMgProlong {
+    static constexpr int NV = 1;
+    struct Raw { double r, ap, e; };
+    struct Aux { double r, ap; };
+    struct Pre { Coef6<double, false> c; };
+    const double *a[7];
+    const double *rin, *e;
+    double *zout;
+    double w, g;
+    int nx, P, ncell, cx, cy;
+    __device__ __forceinline__ Raw load(int idx, int q, int k) const {
+        const int j = q / nx, i = q - j * nx;
+        return Raw{ld(rin, idx), ld(a[0], idx), ld(e, (i >> 1) + cx * ((j >> 1) + cy * (k >> 1)))};
+    }
+    __device__ __forceinline__ double zval(const Raw &v) const {
+#pragma clang fp contract(off)
+        return w * v.r / v.ap + g * v.e;
+    }
+    __device__ __forceinline__ double own(const Raw &v, int, Aux &ax) {
+        ax.r = v.r;
+        ax.ap = v.ap;
+        return zval(v);
+    }
+    __device__ __forceinline__ double halo(const Raw &v) const { return zval(v); }
+    __device__ __forceinline__ void pre(int idx, Nb nb, bool up, bool dn, Pre &pr) const {
+        pr.c.load(a, idx, nx, P, ncell, nb, up, dn);
+    }
+    __device__ __forceinline__ void center(int idx, const Pre &pr, const Aux &ax, double xc, double xE, double xW,
+                                           double xN, double xS, double xT, double xB, double (&)[NV]) {
+#pragma clang fp contract(off)
+        double q = ax.ap * xc;
+        q -= pr.c.e * xE;
+        q -= pr.c.w * xW;
+        q -= pr.c.n * xN;
+        q -= pr.c.s * xS;
+        q -= pr.c.t * xT;
+        q -= pr.c.b * xB;
+        st(zout, idx, xc + w * (ax.r - q) / ax.ap);
+    }
+};
+
+template <int CPT, int H>
+__global__ void __launch_bounds__(kBlock) mg_resid0_kernel(LaunchSets ls, const double *rin, double *res,
+                                                           MgParams prm, int gated) {
+    const TileRef tr = locate<false>(ls);
+    const SetDesc &d = *tr.d;
+    if (gated && !d.st->active) return;
+    PhMgResid ph;
+    for (int k = 0; k < 7; ++k) ph.a[k] = d.a[k];
+    ph.rin = rin;
+    ph.res = res;
+    ph.w = prm.omega;
+    ph.nx = d.nx;
+    ph.P = d.plane;
+    ph.ncell = d.n;
+    double acc[1] = {0.0};
+    march<double, CPT, H>(ph, geo_of(d), tr.tile, lds_base<double>(), acc);
+}
+
+template <int CPT, int H>
+__global__ void __launch_bounds__(kBlock) mg_prolong0_kernel(LaunchSets ls, const MgLevel *lev, const double *rin,
+                                                             double *zout, MgParams prm, int gated) {
+    const TileRef tr = locate<false>(ls);
+    const SetDesc &d = *tr.d;
+    if (gated && !d.st->active) return;
+    PhMgProlong ph;
+    for (int k = 0; k < 7; ++k) ph.a[k] = d.a[k];
+    ph.rin = rin;
+    ph.e = lev[1].z;
+    ph.zout = zout;
+    ph.w = prm.omega;
+    ph.g = prm.gamma;
+    ph.nx = d.nx;
+    ph.P = d.plane;
+    ph.ncell = d.n;
+    ph.cx = lev[1].nx;
+    ph.cy = lev[1].ny;
+    double acc[1] = {0.0};
+    march<double, CPT, H>(ph, geo_of(d), tr.tile, lds_base<double>(), acc);
+}
+
+// level 1's right-hand side: the sum of res over each aggregate of level 0, in
+// cell-index order (eight lanes per aggregate, as in mg_restrict_kernel)
+__global__ void __launch_bounds__(kBlock) mg_aggregate_kernel(const SetDesc *d, const MgLevel *lev, const double *res,
+                                                              int gated) {
+#pragma clang fp contract(off)
+    if (gated && !d->st->active) return;
+    const MgLevel F = lev[0], C = lev[1];
+    const int nx = F.nx, ny = F.ny, nz = F.nz, cx = C.nx, cy = C.ny;
+    const int g8 = threadIdx.x & 7, di = g8 & 1, dj = (g8 >> 1) & 1, dk = g8 >> 2;
+    const int stride = (int)(gridDim.x * kBlock) >> 3;
+    for (int w0 = (int)(blockIdx.x * kBlock + (threadIdx.x & ~63)) >> 3; w0 < C.n; w0 += stride) {
+        const int cc = w0 + (int)((threadIdx.x & 63) >> 3);
+        const bool inC = cc < C.n;
+        const int ccl = min(cc, C.n - 1);
+        const int I = ccl % cx, t = ccl / cx, J = t % cy, K = t / cy;
+        const int i = 2 * I + di, j = 2 * J + dj, k = 2 * K + dk;
+        const bool ok = inC && i < nx && j < ny && k < nz;
+        const double q = ok ? ld(res, i + nx * (j + ny * k)) : 0.0;
+        double qs[8];
+        int oks[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            qs[m] = __shfl(q, m, 8);
+            oks[m] = __shfl(ok ? 1 : 0, m, 8);
+        }
+        if (g8 == 0 && inC) {
+            double sum = 0.0;
+#pragma unroll
+            for (int m = 0; m < 8; ++m)
+                if (oks[m]) sum += qs[m];
+            st(C.r, cc, sum);
+        }
+    }
+}
+
 // ---- BiCGSTAB with the V-cycle as right preconditioner (FP64, original A, x updated in place).
 // Buffers: p = p[0], v = v[0], p^ = p[1], s = s1, s^ = v[1], t, r, r^; the finalisers are
 // those of the three-launch iteration (FinK1: alpha; FinK2: omega and the half-step exit;
@@ -2023,7 +2187,7 @@ struct PhPc {
     double *y;
     int nx, P, ncell;
     bool tstep;            // false: v = A p^, sum (r^, v); true: t = A s^, sums (t,s), (t,t), (s,s)
-    __device__ __forceinline__ Raw load(int idx) const { return Raw{ld(x, idx)}; }
+    __device__ __forceinline__ Raw load(int idx, int, int) const { return Raw{ld(x, idx)}; }
     __device__ __forceinline__ double own(const Raw &w, int, Aux &) { return w.x; }
     __device__ __forceinline__ double halo(const Raw &w) const { return w.x; }
     __device__ __forceinline__ void pre(int idx, Nb nb, bool up, bool dn, Pre &pr) const {
@@ -2241,6 +2405,27 @@ size_t fused_lds_bytes(int cpt, int max_nx, int elem) {
         if (e0) hipExtLaunchKernelGGL(KERN, GRID, BLOCK, LDS, stream, e0, e1, 0u, __VA_ARGS__); \
         else hipLaunchKernelGGL(KERN, GRID, BLOCK, LDS, stream, __VA_ARGS__);                   \
     } while (0)
+
+hipError_t launch_mg_fine(const LaunchSets &ls, int ntiles, int cpt, int max_nx, const MgLevel *lev, const double *rin,
+                          double *res, double *zout, MgParams prm, bool gated, hipStream_t stream) {
+    const dim3 grid(ntiles), block(kBlock);
+    const int h = halo_slots(max_nx);
+    if (h < 0 || (cpt != 1 && cpt != 2)) return hipErrorInvalidValue;
+    const size_t lds64 = march_lds_bytes(cpt, max_nx, 8);
+    if (res)
+        EQS_DISPATCH(cpt, h, hipLaunchKernelGGL((mg_resid0_kernel<C, HH>), grid, block, lds64, stream, ls, rin, res,
+                                                prm, gated ? 1 : 0));
+    else
+        EQS_DISPATCH(cpt, h, hipLaunchKernelGGL((mg_prolong0_kernel<C, HH>), grid, block, lds64, stream, ls, lev, rin,
+                                                zout, prm, gated ? 1 : 0));
+    return hipGetLastError();
+}
+
+hipError_t launch_mg_aggregate(const SetDesc *d, const MgLevel *lev, int nc, const double *res, bool gated,
+                               hipStream_t stream) {
+    hipLaunchKernelGGL(mg_aggregate_kernel, mg_grid(8 * nc), dim3(kBlock), 0, stream, d, lev, res, gated ? 1 : 0);
+    return hipGetLastError();
+}
 
 hipError_t launch_kernel(Kern k, const LaunchSets &ls, int ntiles, int nflat, int cpt, int max_nx, bool fp32,
                          bool trans, hipStream_t stream, const double *x, double *y, int arg, hipEvent_t e0,

@@ -43,6 +43,13 @@ hipError_t launch_mg_restrict(const SetDesc *d, const MgLevel *lev, int l, int n
 constexpr int kMgCoarsestMax = 2048;
 hipError_t launch_mg_coarsest(const SetDesc *d, const MgLevel *lev, int l, int n, const double *rin, double *zout,
                               MgParams prm, bool gated, hipStream_t stream);
+// finest level through the k-march (the set's tiles): res != NULL: res = r - A z1 per cell;
+// res == NULL: zout = prolongation of level 1's result + one smoothing step
+hipError_t launch_mg_fine(const LaunchSets &ls, int ntiles, int cpt, int max_nx, const MgLevel *lev, const double *rin,
+                          double *res, double *zout, MgParams prm, bool gated, hipStream_t stream);
+// level 1's right-hand side from the per-cell residual of level 0 (nc = cells of level 1)
+hipError_t launch_mg_aggregate(const SetDesc *d, const MgLevel *lev, int nc, const double *res, bool gated,
+                               hipStream_t stream);
 // prolongation of level l+1's result and one smoothing sweep on level l (n = cells of level l)
 hipError_t launch_mg_prolong(const SetDesc *d, const MgLevel *lev, int l, int n, const double *rin, double *zout,
                              MgParams prm, bool gated, hipStream_t stream);
