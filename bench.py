@@ -113,10 +113,10 @@ def gpu_leg(args):
         x64 = torch.zeros_like(b)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        x64, i64 = c64.solve(D, b, x64, tol=tol, maxit=maxit)
+        x64, i64 = c64.solve(D, b, x64, tol=tol, maxit=maxit, check=False)
         t1 = time.perf_counter()
         x32 = torch.zeros_like(b)
-        x32, i32 = c32.solve(D, b, x32, tol=tol, maxit=maxit)
+        x32, i32 = c32.solve(D, b, x32, tol=tol, maxit=maxit, check=False)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         if rec is not None:
@@ -158,18 +158,20 @@ def gpu_leg(args):
     err64 = float(torch.max(torch.abs(x64 - xs)))
     err32 = float(torch.max(torch.abs(x32 - xs)))
     tmg, (xmg, img), mgp = time_mg(Context, [g.shape], lambda cm: cm.solve(D, b, torch.zeros_like(b), tol=tol,
-                                                                           maxit=maxit), args.config)
+                                                                           maxit=maxit, check=False), args.config)
     res = {
         "value": n * it64 / t64,
         "ms_per_step": 1e3 * t_total / args.steps,
-        "fp64": {"time_to_tol_ms": 1e3 * t64, "iters": it64, "rel_res": rec[-1][2]["rel_res"],
+        "fp64": {"time_to_tol_ms": 1e3 * t64, "iters": it64, "status": rec[-1][2]["status"], "rel_res": rec[-1][2]["rel_res"],
                  "cell_iters_per_s": n * it64 / t64, "model_GBps": n * it64 * sw * 8 / t64 / 1e9,
                  "max_abs_err_vs_xstar": err64},
         "fp32_refine": {"time_to_tol_ms": 1e3 * t32, "inner_iters": it32, "outer": rec[-1][3]["outer"],
+                        "status": rec[-1][3]["status"],
                         "rel_res": rec[-1][3]["rel_res"], "cell_iters_per_s": n * it32 / t32,
                         "model_GBps": n * it32 * sw * 4 / t32 / 1e9, "max_abs_err_vs_xstar": err32,
                         "speedup_vs_fp64": t64 / t32},
-        "fp64_multigrid": {"time_to_tol_ms": 1e3 * tmg, "iters": img["iters"], "rel_res": img["rel_res"],
+        "fp64_multigrid": {"time_to_tol_ms": 1e3 * tmg, "iters": img["iters"], "status": img["status"],
+                           "rel_res": img["rel_res"],
                            "max_abs_err_vs_xstar": float(torch.max(torch.abs(xmg - xs))),
                            "speedup_vs_fp64_jacobi": t64 / tmg, "params": mgp},
         "roofline": {"bound": "hbm", "kernel": kern + "_fp64", "achieved": achieved, "peak": HBM_PEAK_GBS,
@@ -227,9 +229,9 @@ def gpu_leg_batched(args):
     def step(rec):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        x64, i64 = c64.solve_batched(Ds, bs, tol=tol, maxit=maxit)
+        x64, i64 = c64.solve_batched(Ds, bs, tol=tol, maxit=maxit, check=False)
         t1 = time.perf_counter()
-        x32, i32 = c32.solve_batched(Ds, bs, tol=tol, maxit=maxit)
+        x32, i32 = c32.solve_batched(Ds, bs, tol=tol, maxit=maxit, check=False)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         if rec is not None:
@@ -257,7 +259,7 @@ def gpu_leg_batched(args):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for i in range(len(grids)):
-            c64.solve(Ds[i], bs[i], tol=tol, maxit=maxit, set_id=i)
+            c64.solve(Ds[i], bs[i], tol=tol, maxit=maxit, set_id=i, check=False)
         torch.cuda.synchronize()
         seq.append(time.perf_counter() - t0)
     t64 = float(np.mean([r[0] for r in rec]))
@@ -267,22 +269,25 @@ def gpu_leg_batched(args):
     k1_bytes_total = sum(WORDS[kern] * 8 * n * inf["iters"] for n, inf in zip(n_all, rec[-1][2])) * len(rec)
     achieved = k1_bytes_total / (k1_ms * 1e-3) / 1e9
     err64 = max(float(torch.max(torch.abs(x - xs))) for x, xs in zip(x64, xss))
-    tmg, (xmg, img), mgp = time_mg(Context, grids, lambda cm: cm.solve_batched(Ds, bs, tol=tol, maxit=maxit),
+    tmg, (xmg, img), mgp = time_mg(Context, grids, lambda cm: cm.solve_batched(Ds, bs, tol=tol, maxit=maxit, check=False),
                                    args.config, reps=2)
     res = {
         "value": ci64 / t64,
         "ms_per_step": 1e3 * t_total / args.steps,
         "fp64": {"time_to_tol_ms": 1e3 * t64, "iters": [i["iters"] for i in rec[-1][2]],
+                 "status": [i["status"] for i in rec[-1][2]],
                  "rel_res": [i["rel_res"] for i in rec[-1][2]], "cell_iters_per_s": ci64 / t64,
                  "model_GBps": ci64 * sw * 8 / t64 / 1e9, "max_abs_err_vs_xstar": err64,
                  "sequential_time_to_tol_ms": 1e3 * float(np.mean(seq)),
                  "batched_speedup_vs_sequential": float(np.mean(seq)) / t64},
         "fp32_refine": {"time_to_tol_ms": 1e3 * t32, "inner_iters": [i["iters"] for i in rec[-1][3]],
+                        "status": [i["status"] for i in rec[-1][3]],
                         "outer": [i["outer"] for i in rec[-1][3]], "rel_res": [i["rel_res"] for i in rec[-1][3]],
                         "cell_iters_per_s": ci32 / t32, "model_GBps": ci32 * sw * 4 / t32 / 1e9,
                         "speedup_vs_fp64_batched": t64 / t32,
                         "speedup_vs_fp64_sequential": float(np.mean(seq)) / t32},
         "fp64_multigrid": {"time_to_tol_ms": 1e3 * tmg, "iters": [i["iters"] for i in img],
+                           "status": [i["status"] for i in img],
                            "rel_res": [i["rel_res"] for i in img],
                            "max_abs_err_vs_xstar": max(float(torch.max(torch.abs(x - xs))) for x, xs in zip(xmg, xss)),
                            "speedup_vs_fp64_jacobi_batched": t64 / tmg, "params": mgp},

@@ -14,7 +14,7 @@ namespace eqs {
 
 constexpr int kBlock = 256;      // threads per block (4 wave64)
 constexpr int kMaxSets = 8;      // sets per launch table
-constexpr int kMaxRed = 10;      // reduction values per tile
+constexpr int kMaxRed = 11;      // reduction values per tile
 constexpr int kFlatU = 4;        // pointwise kernels: cells per thread per chunk
 constexpr int kFlatChunk = kBlock * kFlatU;
 constexpr int kMaxFlatBlocks = 4096;
@@ -62,8 +62,9 @@ struct SolveState {
     int32_t fpar;     // buffer slot (0/1) holding the latest s, t, p, v
     int32_t need_f;   // f = M^T r^ and sigma_0 pending (after a fresh start)
     int32_t mat;      // iterate to form before leaving the iteration: 1 y += alpha p;
-                      // 2 y += alpha p + omega s; 3 as 2, plus r = s - omega t, r^ = r (restart)
-    int32_t pad_;
+                      // 2 y += alpha p + omega s; 3 as 2, plus r = s - omega t, r^ = r (restart);
+                      // 4 no y change, r = s + alpha v, r^ = r (restart at the current iterate)
+    int32_t weak_outer;  // consecutive refinement steps that reduced ||r|| by less than 2x
 };
 
 struct SetDesc {

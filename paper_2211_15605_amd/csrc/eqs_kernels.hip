@@ -313,7 +313,7 @@ struct FinFSetup {
 };
 
 // After launch j of the single-sync iteration: sums (f,p_j), (f,v_j), (f,s_j),
-// (f,t_j), (r^,s_j), (r^,t_j), (t_j,s_j), (t_j,t_j), (r_j,r_j), (s_j,s_j).
+// (f,t_j), (r^,s_j), (r^,t_j), (t_j,s_j), (t_j,t_j), (r_j,r_j), (s_j,s_j), (r^,v_j).
 struct FinFused {
     __device__ void operator()(SolveState *st, const double *s) const {
         const double fp = s[0], fv = s[1], fs = s[2], ft = s[3], rs = s[4], rt = s[5];
@@ -330,8 +330,20 @@ struct FinFused {
         st->tt = tt;
         st->ss = ss;
         bool fin = true;
-        for (int i = 0; i < 10; ++i) fin = fin && isfinite(s[i]);
+        for (int i = 0; i < 11; ++i) fin = fin && isfinite(s[i]);
         if (!fin) { stop_iter(st, ST_NONFINITE); return; }
+        // alpha_j came from sigma_j expanded over the previous step's vectors; (r^, v_j) taken
+        // directly must agree with it.  Where the expansion's terms cancel (in FP32 above all),
+        // they can part, and a step with the wrong alpha derails the iteration: start afresh
+        // from the current iterate instead (r_j = s_j + alpha_j v_j, r^ = r_j).
+        const double sd = s[10];
+        if (fabs(sd - st->sigma) > 1e-3 * fabs(sd)) {
+            if (st->restarts >= 32) { stop_iter(st, ST_BREAKDOWN); return; }
+            st->restarts++;
+            st->mat = 4;
+            st->need_f = 1;
+            return;
+        }
         st->iters++;
         st->alpha_prev = st->alpha;  // alpha_j
         if (sqrt(ss) <= st->lim2) {  // half-step exit: x = y_j + alpha_j p_j
@@ -372,6 +384,7 @@ struct FinCast {  // sums: (b,b), #bad
     const SetDesc *d;
     __device__ void operator()(SolveState *st, const double *s) const {
         st->mode = d->mode;
+        st->weak_outer = 0;
         st->mat = 0;
         st->need_f = 0;
         st->fpar = 0;
@@ -413,7 +426,14 @@ struct FinOuter {  // sums: (r,r) in FP64, (r32, r32)
         if (!isfinite(rr) || !isfinite(rr32)) { st->status = ST_NONFINITE; st->done = 1; return; }
         if (sqrt(rr) <= st->lim2_outer) { st->status = ST_OK; st->done = 1; return; }
         if (st->mode == MODE_FP32 && st->outer >= 1) { st->status = ST_NOT_CONVERGED; st->done = 1; return; }
-        if (st->outer >= 1 && rr > 0.25 * st->rr_prev) { st->status = ST_NOT_CONVERGED; st->done = 1; return; }
+        // a refinement step should cut ||r|| at least in half; an inner FP32 solve can fail
+        // to (rounding), and the next step starts afresh from the new residual, so only
+        // three such steps in a row stop the solve
+        if (st->outer >= 1 && rr > 0.25 * st->rr_prev) {
+            if (++st->weak_outer >= 3) { st->status = ST_NOT_CONVERGED; st->done = 1; return; }
+        } else {
+            st->weak_outer = 0;
+        }
         if (st->iters >= st->maxit) { st->status = ST_NOT_CONVERGED; st->done = 1; return; }
         if (rr32 == 0.0) { st->status = ST_NOT_CONVERGED; st->done = 1; return; }  // residual below FP32 range
         st->bb = rr32;
@@ -1150,9 +1170,9 @@ __global__ void __launch_bounds__(kBlock) fused_kernel(LaunchSets ls) {
     }
 #pragma unroll
     for (int h = 0; h < H; ++h) rBi[h] = T(0);
-    double acc[10];
+    double acc[11];
 #pragma unroll
-    for (int i = 0; i < 10; ++i) acc[i] = 0.0;
+    for (int i = 0; i < 11; ++i) acc[i] = 0.0;
     // At a fresh start r = s (the stored residual) and p = r: the terms of step
     // j-1 are masked off bitwise (their buffers may hold anything) and their
     // scalars zeroed, so no branch depends on `fresh` either.
@@ -1261,6 +1281,7 @@ __global__ void __launch_bounds__(kBlock) fused_kernel(LaunchSets ls) {
                 acc[2] += (double)fB[m] * (double)sk;
                 acc[4] += (double)keep_if(own, rhN[m]) * (double)sk;
                 acc[9] += (double)sk * (double)sk;
+                acc[10] += (double)keep_if(own, rhN[m]) * (double)vk;  // sigma_j taken directly
             }
 #pragma unroll
             for (int h = 0; h < H; ++h) {
@@ -1306,7 +1327,7 @@ __global__ void __launch_bounds__(kBlock) fused_kernel(LaunchSets ls) {
         bv = bp;
         bp = b0;
     }
-    reduce_and_finalize<10>(d, tr.tile, d.ntiles, acc, FinFused{});
+    reduce_and_finalize<11>(d, tr.tile, d.ntiles, acc, FinFused{});
 }
 
 // ------------------------------------------------------------------ pointwise kernels
@@ -1369,6 +1390,32 @@ __global__ void __launch_bounds__(kBlock) mat_kernel(LaunchSets ls) {
     const int mode = st_->mat;
     if (!mode) return;
     const int cur = st_->fpar;
+    if (mode == 4) {  // restart at the current iterate: r = s + alpha v into slot 0, r^ = r
+        const T al = (T)st_->alpha;
+        const T *s = Vecs<T>::s(d, cur), *v = Vecs<T>::v(d, cur);
+        T *r0 = Vecs<T>::s(d, 0), *rh = Vecs<T>::rh(d);
+        const int n = d.n, nflat = d.nflat;
+        for (int ch = tr.tile; ch * kFlatChunk < n; ch += nflat) {
+            const int base = ch * kFlatChunk + (int)threadIdx.x;
+            T Sv[kFlatU], V[kFlatU];
+#pragma unroll
+            for (int u = 0; u < kFlatU; ++u) {
+                const int i = min(base + kBlock * u, n - 1);
+                Sv[u] = ld(s, i);
+                V[u] = ld(v, i);
+            }
+#pragma unroll
+            for (int u = 0; u < kFlatU; ++u) {
+                const int i = base + kBlock * u;
+                if (i < n) {
+                    const T rv = fma(al, V[u], Sv[u]);
+                    st(r0, i, rv);
+                    st(rh, i, rv);
+                }
+            }
+        }
+        return;
+    }
     const T a = (T)st_->alpha_prev, om = mode == 1 ? T(0) : (T)st_->omega;
     const T *p = Vecs<T>::p(d, cur), *s = Vecs<T>::s(d, cur), *t = Vecs<T>::t(d, cur);
     T *y = Vecs<T>::y(d), *r0 = Vecs<T>::s(d, 0), *rh = Vecs<T>::rh(d);

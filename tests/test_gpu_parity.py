@@ -404,7 +404,10 @@ def test_autograd_function_backward(torch_dev, orc):
 
 # ---------------------------------------------------------------- full-size workloads (as benchmarked)
 
-@pytest.mark.parametrize("scheme", SCHEMES, ids=SCHEME_IDS)
+# (the last: a launch layout on which the FP32 single-sync inner iteration once derailed, the
+# regression case of the direct-sigma check and of the refinement's weak-step allowance)
+@pytest.mark.parametrize("scheme", SCHEMES + [dict(EQS_CPT=2, EQS_KC=16, EQS_FLAT_MAX=256)],
+                         ids=SCHEME_IDS + ["sync1_kc16_flat256"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
 def test_config1_full_size_residual(torch_dev, orc, precision, scheme):
     torch, dev = torch_dev
