@@ -78,6 +78,11 @@ double env_double(const char *name, double dflt) {
 // taking a few more outer steps minimises the total inner iterations.
 double inner_tol() { return env_double("EQS_TOL_INNER", 3e-3); }
 
+// Single-sync iteration: the relative gap between sigma taken directly and the
+// expanded sigma a step ran with, above which the iteration starts afresh
+// (FP64, FP32).
+double sigma_tol(bool fp32) { return fp32 ? env_double("EQS_SIGMA_TOL32", 1e-2) : env_double("EQS_SIGMA_TOL", 1e-3); }
+
 }  // namespace
 
 struct eqs_ctx {
@@ -218,6 +223,8 @@ void fill_desc(eqs_ctx *c, int s) {
     d.partials = h.partials;
     d.counter = h.counter;
     d.st = c->d_state + s;
+    d.sigma_tol[0] = sigma_tol(false);
+    d.sigma_tol[1] = sigma_tol(true);
 }
 
 LaunchSets launch_table(eqs_ctx *c, int first, int count, int *total, int *total_flat) {

@@ -75,6 +75,8 @@ struct SetDesc {
     int32_t nflat;
     int32_t mode;
     double tol, tol_inner;
+    double sigma_tol[2];  // single-sync iteration: largest relative gap between sigma taken
+                          // directly and the expanded one it ran with, FP64 [0] and FP32 [1]
     int32_t maxit, pad;
     // caller arrays
     const double *a[7];

@@ -315,6 +315,7 @@ struct FinFSetup {
 // After launch j of the single-sync iteration: sums (f,p_j), (f,v_j), (f,s_j),
 // (f,t_j), (r^,s_j), (r^,t_j), (t_j,s_j), (t_j,t_j), (r_j,r_j), (s_j,s_j), (r^,v_j).
 struct FinFused {
+    double sig_tol;
     __device__ void operator()(SolveState *st, const double *s) const {
         const double fp = s[0], fv = s[1], fs = s[2], ft = s[3], rs = s[4], rt = s[5];
         const double ts = s[6], tt = s[7], rr = s[8], ss = s[9];
@@ -337,7 +338,7 @@ struct FinFused {
         // they can part, and a step with the wrong alpha derails the iteration: start afresh
         // from the current iterate instead (r_j = s_j + alpha_j v_j, r^ = r_j).
         const double sd = s[10];
-        if (fabs(sd - st->sigma) > 1e-3 * fabs(sd)) {
+        if (fabs(sd - st->sigma) > sig_tol * fabs(sd)) {
             if (st->restarts >= 32) { stop_iter(st, ST_BREAKDOWN); return; }
             st->restarts++;
             st->mat = 4;
@@ -1327,7 +1328,7 @@ __global__ void __launch_bounds__(kBlock) fused_kernel(LaunchSets ls) {
         bv = bp;
         bp = b0;
     }
-    reduce_and_finalize<11>(d, tr.tile, d.ntiles, acc, FinFused{});
+    reduce_and_finalize<11>(d, tr.tile, d.ntiles, acc, FinFused{d.sigma_tol[sizeof(T) == 4 ? 1 : 0]});
 }
 
 // ------------------------------------------------------------------ pointwise kernels
