@@ -25,7 +25,9 @@ PRECISIONS = {"fp64": EQS_FP64, "fp32_refine": EQS_FP32_REFINE, "fp32": EQS_FP32
 SYMBOLS = ("eqsolve_create", "eqsolve_solve", "eqsolve_solve_batched", "eqsolve_adjoint", "eqsolve_apply",
            "eqsolve_destroy", "eqsolve_strerror", "eqsolve_autotune", "eqsolve_debug_layout",
            "eqsolve_debug_profile", "eqsolve_debug_kernel_stats", "eqsolve_set_preconditioner",
-           "eqsolve_debug_precond")
+           "eqsolve_debug_precond",
+           "eqsimple_create", "eqsimple_form_momentum", "eqsimple_form_pressure", "eqsimple_correct",
+           "eqsimple_iterate", "eqsimple_set_pressure_preconditioner", "eqsimple_destroy")
 KERNEL_KINDS = {"setup": 0, "recheck": 1, "report": 2, "k1": 3, "k2": 4, "k3": 5, "cast": 6, "outer": 7,
                 "update": 8, "zero": 9, "grad": 10, "apply": 11, "scale": 12, "unscale": 13, "fused": 14,
                 "fsetup": 15, "mat": 16}
@@ -41,6 +43,23 @@ EQS_PRECOND_JACOBI, EQS_PRECOND_MG = 0, 1
 class EqsMgParams(ctypes.Structure):
     _fields_ = [("omega", ctypes.c_double), ("gamma", ctypes.c_double), ("coarse_sweeps", ctypes.c_int32),
                 ("coarse_cells", ctypes.c_int32)]
+
+
+BOX_FIELDS = ("nx", "ny", "nz", "hx", "hy", "hz", "rho", "mu", "dt", "gy", "v_in", "alpha_u", "alpha_p")
+
+
+class EqsBox(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32), ("pad", ctypes.c_int32)] + \
+               [(f, ctypes.c_double) for f in BOX_FIELDS[3:]]
+
+
+class EqsSimpleInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32 * 4), ("pad", ctypes.c_int32),
+                ("mom_residual", ctypes.c_double * 3), ("mass_residual", ctypes.c_double)]
+
+    def as_dict(self):
+        return {"status": self.status, "iters": dict(zip(("p", "u", "v", "w"), list(self.iters))),
+                "mom_residual": list(self.mom_residual), "mass_residual": self.mass_residual}
 
 
 class EqsInfo(ctypes.Structure):
@@ -98,6 +117,18 @@ def load(path: str | None = None):
         L.eqsolve_set_preconditioner.restype = ctypes.c_int
         L.eqsolve_debug_precond.argtypes = [VP, ctypes.c_int32, VPP, VP, VP, ctypes.POINTER(ctypes.c_int32)]
         L.eqsolve_debug_precond.restype = ctypes.c_int
+        D3 = ctypes.POINTER(ctypes.c_double)
+        L.eqsimple_create.argtypes = [ctypes.POINTER(VP), ctypes.POINTER(EqsBox), ctypes.c_int32, VP]
+        L.eqsimple_form_momentum.argtypes = [VP, VPP, VP, VPP, VPP, VPP, VPP, D3]
+        L.eqsimple_form_pressure.argtypes = [VP, VPP, VPP, VPP, VP, D3]
+        L.eqsimple_correct.argtypes = [VP, VPP, VP, VPP, VP]
+        L.eqsimple_iterate.argtypes = [VP, VPP, VP, VPP, ctypes.c_int32, D3, ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(EqsSimpleInfo)]
+        L.eqsimple_set_pressure_preconditioner.argtypes = [VP, ctypes.c_int32, ctypes.POINTER(EqsMgParams)]
+        L.eqsimple_destroy.argtypes = [VP]
+        for f in ("eqsimple_create", "eqsimple_form_momentum", "eqsimple_form_pressure", "eqsimple_correct",
+                  "eqsimple_iterate", "eqsimple_set_pressure_preconditioner", "eqsimple_destroy"):
+            getattr(L, f).restype = ctypes.c_int
         if path is None:
             _lib = L
         return L
@@ -199,3 +230,69 @@ def eqsolve_debug_kernel_stats(h, kind, fp32):
 
 def eqsolve_autotune(h, cache_path=None, iters=6):
     return load().eqsolve_autotune(h, cache_path.encode() if cache_path else None, int(iters))
+
+
+# ---------------------------------------------------------------- SIMPLE box (include/eqsimple.h)
+
+def make_box(box):
+    """EqsBox from a mapping or an object with the BOX_FIELDS attributes."""
+    get = (lambda k: box[k]) if isinstance(box, dict) else (lambda k: getattr(box, k))
+    b = EqsBox()
+    for f in BOX_FIELDS:
+        setattr(b, f, int(get(f)) if f in ("nx", "ny", "nz") else float(get(f)))
+    return b
+
+
+def eqsimple_create(box, precision, stream):
+    h = VP()
+    b = make_box(box)
+    rc = load().eqsimple_create(ctypes.byref(h), ctypes.byref(b), int(precision), VP(stream or 0))
+    return rc, h
+
+
+def eqsimple_form_momentum(h, vel, p, old, diag21, b3, d3, want_norms=True):
+    vp, k1 = ptr_array(vel)
+    op, k2 = ptr_array(old)
+    dp, k3 = ptr_array(diag21)
+    bp, k4 = ptr_array(b3)
+    ddp, k5 = ptr_array(d3)
+    res = (ctypes.c_double * 3)()
+    rc = load().eqsimple_form_momentum(h, vp, VP(p), op, dp, bp, ddp, res if want_norms else None)
+    return rc, list(res)
+
+
+def eqsimple_form_pressure(h, d3, vel, diag7, b, want_norm=True):
+    ddp, k1 = ptr_array(d3)
+    vp, k2 = ptr_array(vel)
+    dp, k3 = ptr_array(diag7)
+    m = ctypes.c_double(0.0)
+    rc = load().eqsimple_form_pressure(h, ddp, vp, dp, VP(b), ctypes.byref(m) if want_norm else None)
+    return rc, m.value
+
+
+def eqsimple_correct(h, d3, pp, vel, p):
+    ddp, k1 = ptr_array(d3)
+    vp, k2 = ptr_array(vel)
+    return load().eqsimple_correct(h, ddp, VP(pp), vp, VP(p))
+
+
+def eqsimple_iterate(h, vel, p, old, niter, tol2, maxit2):
+    vp, k1 = ptr_array(vel)
+    op, k2 = ptr_array(old)
+    t = (ctypes.c_double * 2)(*map(float, tol2))
+    m = (ctypes.c_int32 * 2)(*map(int, maxit2))
+    info = EqsSimpleInfo()
+    rc = load().eqsimple_iterate(h, vp, VP(p), op, int(niter), t, m, ctypes.byref(info))
+    return rc, info
+
+
+def eqsimple_set_pressure_preconditioner(h, kind, params=None):
+    prm = None
+    if params is not None:
+        prm = EqsMgParams(float(params.get("omega", 0.8)), float(params.get("gamma", 1.0)),
+                          int(params.get("coarse_sweeps", 30)), int(params.get("coarse_cells", 512)))
+    return load().eqsimple_set_pressure_preconditioner(h, int(kind), ctypes.byref(prm) if prm is not None else None)
+
+
+def eqsimple_destroy(h):
+    return load().eqsimple_destroy(h)

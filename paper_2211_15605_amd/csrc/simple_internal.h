@@ -1,0 +1,53 @@
+// simple_internal.h -- launch arguments shared by the SIMPLE-stage kernels and
+// their host driver.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+namespace eqsim {
+
+constexpr int kThreads = 256;   // threads per block; one cell per thread
+constexpr int kXcds = 8;        // blocks go round-robin to the XCDs of the chip
+
+struct BoxK {
+    int32_t nx, ny, nz, pad;
+    double hx, hy, hz, rho, mu, dt, gy, v_in, alpha_u, alpha_p;
+};
+
+// logical blocks [0, nb[0]) form u, [nb[0], nb[0]+nb[1]) v, the rest w
+struct MomArgs {
+    BoxK bx;
+    const double *u, *v, *w, *p, *u0, *v0, *w0;
+    double *a[3][7];
+    double *b[3], *d[3];
+    double *partials;   // per logical block: sum of squared row residuals
+    int32_t nb[3];
+};
+
+struct PresArgs {
+    BoxK bx;
+    const double *du, *dv, *dw, *u, *v, *w;
+    double *a[7];
+    double *b;
+    double *partials;   // per block: sum of b'^2
+};
+
+// logical blocks over u, v, w, p in that order
+struct CorrArgs {
+    BoxK bx;
+    const double *du, *dv, *dw, *pp;
+    double *u, *v, *w, *p;
+    int32_t nb[4];
+};
+
+inline int blocks_for(long n) { return (int)((n + kThreads - 1) / kThreads); }
+
+hipError_t launch_form_momentum(const MomArgs &a, hipStream_t s);
+hipError_t launch_form_pressure(const PresArgs &a, int nblocks, hipStream_t s);
+hipError_t launch_correct(const CorrArgs &a, hipStream_t s);
+// out[q] = sum of partials[begin[q] .. begin[q+1]) in a fixed order, q < nq
+hipError_t launch_sum_ranges(const double *partials, const int32_t *begin_host, int nq, double *out, hipStream_t s);
+hipError_t launch_zero(double *p, long n, hipStream_t s);
+
+}  // namespace eqsim

@@ -142,3 +142,57 @@ def random_general(grid: Grid, seed: int, diag_shift: float = 0.5):
     inside[4][-1, :, :] = 0; inside[5][0, :, :] = 0
     P = sum(a * m for a, m in zip(nb, inside)) + diag_shift
     return [P.ravel()] + [a.ravel() for a in nb]
+
+
+# ---------------------------------------------------------------- SIMPLE box states
+#
+# The gas-only bed box: the verification case of Sec. 3 (gas properties,
+# gravity along -y, inlet at the bottom, outlet at the top, vertical walls)
+# on the pressure grid of the four-set time step above (p' 96x384x96; the
+# u, v, w grids of that step are exactly its staggered faces), with cubic
+# cells of 1.25 mm (a 12 cm x 48 cm x 12 cm column).  Small boxes of the same
+# recipe serve the parity tests.
+
+BED = dict(nx=96, ny=384, nz=96, hx=1.25e-3, hy=1.25e-3, hz=1.25e-3, rho=1.093, mu=1.9e-5, dt=1e-3,
+           gy=-9.81, v_in=0.5, alpha_u=0.5, alpha_p=0.8)
+
+
+def bed_box(nx=None, ny=None, nz=None, **kw):
+    """The bed recipe, optionally with other cell counts (same cell size) or parameters."""
+    b = dict(BED)
+    for k, v in (("nx", nx), ("ny", ny), ("nz", nz)):
+        if v is not None:
+            b[k] = int(v)
+    b.update(kw)
+    return b
+
+
+def box_state(box, seed: int, noise: float = 0.05, old: str = "same"):
+    """Seeded initial fields, numpy FP64 [k, j, i] arrays: plug flow (v = v_in,
+    u = w = 0) and a pressure that falls by rho |g| hy per row towards 0 above
+    the top, each perturbed by uniform noise of relative size `noise` (velocity
+    noise scaled by v_in, pressure noise by rho |g| hy).  old = "same": the
+    old-time velocities equal these; "draw": drawn the same way, afterwards.
+    Draw order: u, v, w, p, then u0, v0, w0."""
+    nx, ny, nz = int(box["nx"]), int(box["ny"]), int(box["nz"])
+    rng = np.random.default_rng(np.random.SeedSequence([2211, 15605, 1000, int(seed)]))
+    vin = float(box["v_in"])
+    dp = float(box["rho"]) * abs(float(box["gy"])) * float(box["hy"])
+    shp = dict(u=(nz, ny, nx + 1), v=(nz, ny + 1, nx), w=(nz + 1, ny, nx), p=(nz, ny, nx))
+
+    def velocities():
+        u = noise * vin * rng.uniform(-1, 1, shp["u"])
+        v = vin * (1.0 + noise * rng.uniform(-1, 1, shp["v"]))
+        w = noise * vin * rng.uniform(-1, 1, shp["w"])
+        return u, v, w
+
+    u, v, w = velocities()
+    j = np.arange(ny, dtype=np.float64)
+    p = (ny - j)[None, :, None] * dp + noise * dp * rng.uniform(-1, 1, shp["p"])
+    st = dict(u=u, v=v, w=w, p=p)
+    if old == "same":
+        st.update(u0=u.copy(), v0=v.copy(), w0=w.copy())
+    else:
+        u0, v0, w0 = velocities()
+        st.update(u0=u0, v0=v0, w0=w0)
+    return st

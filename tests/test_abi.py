@@ -6,14 +6,16 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "eqsolve.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("eqsolve.h", "eqsimple.h")]
 LIB = os.path.join(ROOT, "paper_2211_15605_amd", "libeqsolve.so")
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(eqsolve_\w+)\s*\(", text)))
+    names = set()
+    for h in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(eqs(?:olve|imple)_\w+)\s*\(", text))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -41,7 +43,7 @@ def test_binding_symbol_list_matches_header():
     spec = importlib.util.spec_from_file_location("b", os.path.join(ROOT, "paper_2211_15605_amd", "binding.py"))
     src = open(spec.origin).read()
     m = re.search(r"SYMBOLS = \((.*?)\)", src, re.S)
-    listed = sorted(re.findall(r'"(eqsolve_\w+)"', m.group(1)))
+    listed = sorted(re.findall(r'"(eqs(?:olve|imple)_\w+)"', m.group(1)))
     assert listed == declared_functions()
 
 

@@ -53,3 +53,23 @@ def test_library_argument_errors_without_device():
     assert B.load().eqsolve_autotune(None, None, 4) == B.EQS_ERR_STATE
     assert B.eqsolve_debug_layout(None, 0)[0] == B.EQS_ERR_ARG
     assert B.strerror(B.EQS_BREAKDOWN).startswith("BiCGSTAB breakdown")
+
+
+def test_simple_box_argument_errors_without_device():
+    """eqsimple_create rejects bad boxes and precisions before any HIP call;
+    the stage calls reject a missing context."""
+    from paper_2211_15605_amd import binding as B
+    from paper_2211_15605_amd import workloads as W
+    for bad in (dict(nx=0), dict(nx=1024), dict(ny=0), dict(hx=0.0), dict(hz=float("inf")), dict(rho=-1.0),
+                dict(mu=-1e-5), dict(mu=float("nan")), dict(dt=0.0), dict(alpha_u=0.0), dict(alpha_u=1.01),
+                dict(alpha_p=2.0), dict(gy=float("nan")), dict(v_in=float("inf"))):
+        box = W.bed_box(4, 4, 4)
+        box.update(bad)
+        rc, h = B.eqsimple_create(box, B.EQS_FP64, None)
+        assert rc == B.EQS_ERR_ARG and not h.value, bad
+    rc, h = B.eqsimple_create(W.bed_box(4, 4, 4), 7, None)
+    assert rc == B.EQS_ERR_ARG
+    L = B.load()
+    assert L.eqsimple_form_momentum(None, None, None, None, None, None, None, None) == B.EQS_ERR_STATE
+    assert L.eqsimple_iterate(None, None, None, None, 1, None, None, None) == B.EQS_ERR_STATE
+    assert L.eqsimple_destroy(None) == B.EQS_OK
