@@ -86,6 +86,82 @@ def time_mg(Context, grids, solve, cfg, reps=3):
     return float(np.min(ts)), out, prm
 
 
+def time_simple(iters=8, warm=2):
+    """SIMPLE iterations of one time step on the gas-only bed box (96 x 384 x 96 pressure cells:
+    the p', u, v, w grids of the four-set time step), outside the timed steps: milliseconds per
+    SIMPLE iteration with Jacobi and with multigrid p' solves, and the stage kernels' times."""
+    import numpy as np
+    import torch
+
+    from paper_2211_15605_amd import workloads as W
+    from paper_2211_15605_amd.simple import SimpleBox
+
+    dev = torch.device("cuda", 0)
+    box = W.bed_box()
+    st = W.box_state(box, seed=0, noise=0.05)
+    comps = ("u", "v", "w")
+    tol, maxit = (1e-5, 1e-6), (100, 2000)
+    out = {"box": "%dx%dx%d pressure cells, h = %g m, dt = %g s, v_in = %g m/s" % (
+        box["nx"], box["ny"], box["nz"], box["hx"], box["dt"], box["v_in"]),
+        "tol": {"momentum": tol[0], "pressure": tol[1]}, "iterations_timed": iters}
+    for kind in ("jacobi", "mg"):
+        f = {k: torch.from_numpy(v).to(dev) for k, v in st.items()}
+        vel, old = [f[c] for c in comps], [f[c + "0"] for c in comps]
+        sb = SimpleBox(box)
+        if kind == "mg":
+            sb.set_pressure_preconditioner("mg", gamma=1.6, coarse_cells=2048)
+        first = sb.iterate(vel, f["p"], old, niter=1, tol=tol, maxit=maxit)
+        if warm > 1:
+            sb.iterate(vel, f["p"], old, niter=warm - 1, tol=tol, maxit=maxit)
+        ts, infos = [], []
+        for _ in range(iters):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            infos.append(sb.iterate(vel, f["p"], old, niter=1, tol=tol, maxit=maxit))
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        out[kind] = {"ms_per_simple_iteration": 1e3 * float(np.mean(ts)),
+                     "solver_iters_last": infos[-1]["iters"], "status_worst": max(i["status"] for i in infos),
+                     "mass_residual_first_last": [first["mass_residual"], infos[-1]["mass_residual"]]}
+        if kind == "mg":
+            # stage kernels on the current state, each enqueued `reps` times back to back between
+            # two events on the library's stream (torch's current stream), outputs preallocated
+            reps = 10
+            mo = sb.momentum_outputs()
+            po = sb.pressure_outputs()
+            d = mo[2]
+            pp = torch.zeros_like(f["p"])
+            vc = [v.clone() for v in vel]
+            pc = f["p"].clone()
+            sb.form_momentum(vel, f["p"], old, out=mo)
+            sb.form_pressure(d, vel, out=po)
+            calls = {"form_momentum": lambda: sb.form_momentum(vel, f["p"], old, out=mo, norms=False),
+                     "form_pressure": lambda: sb.form_pressure(d, vel, out=po, norms=False),
+                     "correct": lambda: sb.correct(d, pp, vc, pc)}
+            nu, nv, nw, npc = (int(np.prod(sb.shapes[c])) for c in ("u", "v", "w", "p"))
+            # algorithmic bytes: every input field read once, every output written once
+            by = {"form_momentum": 8 * (2 * (nu + nv + nw) + npc + 9 * (nu + nv + nw)),
+                  "form_pressure": 8 * (2 * (nu + nv + nw) + 8 * npc),
+                  "correct": 8 * (3 * (nu + nv + nw) + 3 * npc)}
+            for name, fn in calls.items():
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                torch.cuda.synchronize()
+                e0.record()
+                for _ in range(reps):
+                    fn()
+                e1.record()
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / reps
+                out["stage_" + name] = {"ms": ms, "algorithmic_MB": by[name] / 1e6,
+                                        "GBps": by[name] / (ms * 1e-3) / 1e9}
+            del mo, po
+            del d, pp, vc, pc
+        sb.close()
+        del f, vel, old
+    out["mg_speedup_per_iteration"] = out["jacobi"]["ms_per_simple_iteration"] / out["mg"]["ms_per_simple_iteration"]
+    return out
+
+
 def gpu_leg(args):
     import numpy as np
     import torch
@@ -337,6 +413,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-tune", action="store_true", help="use the default launch shapes (no autotuning)")
+    ap.add_argument("--no-simple", action="store_true", help="skip the SIMPLE-iteration section")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the timed steps, copy 1 GiB three times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -350,6 +427,7 @@ def main():
     g = cfg["grids"][0]
     batched = len(cfg["grids"]) > 1
     r = gpu_leg_batched(args) if batched else gpu_leg(args)
+    simple = None if args.no_simple else time_simple()
     cpu = None if args.no_cpu_baseline else cpu_leg(args)
     line = {
         "metric": METRIC,
@@ -377,6 +455,7 @@ def main():
         "fp32_refine": r["fp32_refine"],
         "fp64_multigrid": r["fp64_multigrid"],
         "kernels_fp64_ms": r["kernels_fp64_ms"],
+        "simple_bed": simple,
     }
     print(json.dumps(line))
 

@@ -48,38 +48,52 @@ class SimpleBox:
     def zeros(self, comp):
         return torch.zeros(self.shapes[comp], dtype=torch.float64, device=self.device)
 
+    def empty(self, comp):
+        return torch.empty(self.shapes[comp], dtype=torch.float64, device=self.device)
+
+    def momentum_outputs(self):
+        """Output buffers of form_momentum (every value is written by the kernel)."""
+        comps = ("u", "v", "w")
+        return ([[self.empty(c) for _ in range(7)] for c in comps], [self.empty(c) for c in comps],
+                [self.empty(c) for c in comps])
+
+    def pressure_outputs(self):
+        return [self.empty("p") for _ in range(7)], self.empty("p")
+
     def _call(self, rc, what):
         if rc < 0:
             raise EqSolveError(rc, what)
         return rc
 
     # ------------------------------------------------------------ stages
-    def form_momentum(self, vel, p, old):
-        """(diags [3][7], b [3], d [3], res2 [3]) of the u, v, w systems."""
+    def form_momentum(self, vel, p, old, out=None, norms=True):
+        """(diags [3][7], b [3], d [3], res2 [3]) of the u, v, w systems.  out: buffers from
+        momentum_outputs() to reuse; norms=False only enqueues the work (res2 is None)."""
         comps = ("u", "v", "w")
         vp = self._ptrs(vel, comps)
         pp = self._ptrs([p], ["p"])[0]
         op = self._ptrs(old, comps)
-        diags = [[self.zeros(c) for _ in range(7)] for c in comps]
-        b = [self.zeros(c) for c in comps]
-        d = [self.zeros(c) for c in comps]
+        diags, b, d = out if out is not None else self.momentum_outputs()
+        dptr = [_check_vec(t, self.n[c], "diag", self.device) for s, c in zip(diags, comps) for t in s]
+        bptr = self._ptrs(b, comps)
+        ddptr = self._ptrs(d, comps)
         with torch.cuda.device(self.device):
-            rc, res2 = B.eqsimple_form_momentum(self._h, vp, pp, op, [t.data_ptr() for s in diags for t in s],
-                                                [t.data_ptr() for t in b], [t.data_ptr() for t in d])
+            rc, res2 = B.eqsimple_form_momentum(self._h, vp, pp, op, dptr, bptr, ddptr, want_norms=norms)
         self._call(rc, "eqsimple_form_momentum")
-        return diags, b, d, res2
+        return diags, b, d, (res2 if norms else None)
 
-    def form_pressure(self, d, vel):
-        """(diags [7], b, mass2) of the p' system."""
+    def form_pressure(self, d, vel, out=None, norms=True):
+        """(diags [7], b, mass2) of the p' system (out, norms as for form_momentum)."""
         comps = ("u", "v", "w")
         dp = self._ptrs(d, comps)
         vp = self._ptrs(vel, comps)
-        diags = [self.zeros("p") for _ in range(7)]
-        b = self.zeros("p")
+        diags, b = out if out is not None else self.pressure_outputs()
+        dptr = self._ptrs(diags, ["p"] * 7)
+        bptr = self._ptrs([b], ["p"])[0]
         with torch.cuda.device(self.device):
-            rc, m2 = B.eqsimple_form_pressure(self._h, dp, vp, [t.data_ptr() for t in diags], b.data_ptr())
+            rc, m2 = B.eqsimple_form_pressure(self._h, dp, vp, dptr, bptr, want_norm=norms)
         self._call(rc, "eqsimple_form_pressure")
-        return diags, b, m2
+        return diags, b, (m2 if norms else None)
 
     def correct(self, d, pp, vel, p):
         """In place on vel (u, v, w) and p."""
