@@ -162,6 +162,37 @@ def time_simple(iters=8, warm=2):
     return out
 
 
+def time_latency(runs=10, warm=3):
+    """The small convection-diffusion system (16^3 cells, tol 1e-10), latency-bound: median
+    microseconds per FP64 solve from x0 = 0 (outside the timed steps)."""
+    import numpy as np
+    import torch
+
+    from paper_2211_15605_amd import workloads as W
+    from paper_2211_15605_amd.solver import Context
+
+    dev = torch.device("cuda", 0)
+    cfg = W.CONFIGS[0]
+    s = W.make_set(0, 0)
+    g = s["grid"]
+    D = [torch.from_numpy(d).to(dev) for d in s["diags"]]
+    ctx = Context([g.shape], precision="fp64")
+    b = ctx.apply(D, torch.from_numpy(s["x_star"]).to(dev))
+    ts, info = [], None
+    for r in range(warm + runs):
+        x = torch.zeros_like(b)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, info = ctx.solve(D, b, x, tol=cfg["tol"], maxit=cfg["maxit"], check=False)
+        torch.cuda.synchronize()
+        if r >= warm:
+            ts.append(time.perf_counter() - t0)
+    ctx.close()
+    us = 1e6 * float(np.median(ts))
+    return {"workload": "cd16: 16x16x16 convection-diffusion, tol 1e-10, FP64", "us_per_solve": us,
+            "iters": info["iters"], "us_per_iteration": us / max(info["iters"], 1), "status": info["status"]}
+
+
 def gpu_leg(args):
     import numpy as np
     import torch
@@ -413,7 +444,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-tune", action="store_true", help="use the default launch shapes (no autotuning)")
-    ap.add_argument("--no-simple", action="store_true", help="skip the SIMPLE-iteration section")
+    ap.add_argument("--no-simple", action="store_true", help="skip the SIMPLE-iteration and latency sections")
+    ap.add_argument("--only-simple", action="store_true",
+                    help="run only the SIMPLE-iteration section and print it as the JSON line (for profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the timed steps, copy 1 GiB three times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -423,11 +456,15 @@ def main():
         sys.exit(2)
     from paper_2211_15605_amd import workloads as W
 
+    if args.only_simple:
+        print(json.dumps({"simple_bed": time_simple()}))
+        return
     cfg = W.CONFIGS[args.config]
     g = cfg["grids"][0]
     batched = len(cfg["grids"]) > 1
     r = gpu_leg_batched(args) if batched else gpu_leg(args)
     simple = None if args.no_simple else time_simple()
+    latency = None if args.no_simple else time_latency()
     cpu = None if args.no_cpu_baseline else cpu_leg(args)
     line = {
         "metric": METRIC,
@@ -456,6 +493,7 @@ def main():
         "fp64_multigrid": r["fp64_multigrid"],
         "kernels_fp64_ms": r["kernels_fp64_ms"],
         "simple_bed": simple,
+        "latency_cd16": latency,
     }
     print(json.dumps(line))
 

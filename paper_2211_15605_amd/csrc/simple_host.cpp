@@ -24,6 +24,9 @@
 
 using namespace eqsim;
 
+// the uniform values of BoxK are formed exactly as the kernels would form them
+#pragma clang fp contract(off)
+
 struct eqsimple_ctx {
     eqs_box box{};
     BoxK bk{};
@@ -75,6 +78,19 @@ BoxK to_k(const eqs_box &b) {
     k.v_in = b.v_in;
     k.alpha_u = b.alpha_u;
     k.alpha_p = b.alpha_p;
+    k.Ax = b.hy * b.hz;
+    k.Ay = b.hx * b.hz;
+    k.Az = b.hx * b.hy;
+    k.V = b.hx * b.hy * b.hz;
+    k.aP0 = b.rho * k.V / b.dt;
+    k.De = b.mu * k.Ax / b.hx;
+    k.Dn = b.mu * k.Ay / b.hy;
+    k.Dt = b.mu * k.Az / b.hz;
+    k.rAx = b.rho * k.Ax;
+    k.rAy = b.rho * k.Ay;
+    k.rAz = b.rho * k.Az;
+    k.rgV = b.rho * b.gy * k.V;
+    k.oma = 1.0 - b.alpha_u;
     return k;
 }
 

@@ -13,6 +13,10 @@ constexpr int kXcds = 8;        // blocks go round-robin to the XCDs of the chip
 struct BoxK {
     int32_t nx, ny, nz, pad;
     double hx, hy, hz, rho, mu, dt, gy, v_in, alpha_u, alpha_p;
+    // uniform values, formed once on the host in the kernels' own operation order:
+    // face areas, cell volume, rho V / dt, diffusion conductances mu A / h, rho A,
+    // rho g_y V, 1 - alpha_u
+    double Ax, Ay, Az, V, aP0, De, Dn, Dt, rAx, rAy, rAz, rgV, oma;
 };
 
 // logical blocks [0, nb[0]) form u, [nb[0], nb[0]+nb[1]) v, the rest w

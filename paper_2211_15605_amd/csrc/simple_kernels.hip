@@ -47,15 +47,12 @@ __device__ double block_sum(double v) {
     return s;
 }
 
+// the box's uniform values (formed on the host)
 struct Geo {
-    double Ax, Ay, Az, V, aP0;
-    __device__ explicit Geo(const BoxK &b) {
-        Ax = b.hy * b.hz;
-        Ay = b.hx * b.hz;
-        Az = b.hx * b.hy;
-        V = b.hx * b.hy * b.hz;
-        aP0 = b.rho * V / b.dt;
-    }
+    double Ax, Ay, Az, aP0, De, Dn, Dt, rAx, rAy, rAz, rgV, oma;
+    __device__ explicit Geo(const BoxK &b)
+        : Ax(b.Ax), Ay(b.Ay), Az(b.Az), aP0(b.aP0), De(b.De), Dn(b.Dn), Dt(b.Dt), rAx(b.rAx), rAy(b.rAy),
+          rAz(b.rAz), rgV(b.rgV), oma(b.oma) {}
 };
 
 // a row: coefficients P,E,W,N,S,T,B, right-hand side, d
@@ -84,7 +81,7 @@ __device__ __forceinline__ void finish(const BoxK &bx, const Geo &g, double aE, 
     r.a[4] = aS;
     r.a[5] = aT;
     r.a[6] = aB;
-    r.b = src + (1.0 - bx.alpha_u) * aPr * xs;
+    r.b = src + g.oma * aPr * xs;
     r.d = area * (1.0 / aPr);
 }
 
@@ -106,15 +103,14 @@ __device__ void form_u(const MomArgs &A, const Geo &g, const Idx &X, int i, int 
         return;
     }
     const double *u = A.u, *v = A.v, *w = A.w, *p = A.p;
-    const double rh = bx.rho;
     const int c = X.u(i, j, k);
-    const double Fe = rh * g.Ax * (u[c] + u[c + 1]) / 2;
-    const double Fw = rh * g.Ax * (u[c - 1] + u[c]) / 2;
-    const double Fn = rh * g.Ay * (v[X.v(i - 1, j + 1, k)] + v[X.v(i, j + 1, k)]) / 2;
-    const double Fs = rh * g.Ay * (v[X.v(i - 1, j, k)] + v[X.v(i, j, k)]) / 2;
-    const double Ft = rh * g.Az * (w[X.w(i - 1, j, k + 1)] + w[X.w(i, j, k + 1)]) / 2;
-    const double Fb = rh * g.Az * (w[X.w(i - 1, j, k)] + w[X.w(i, j, k)]) / 2;
-    const double De = bx.mu * g.Ax / bx.hx, Dn = bx.mu * g.Ay / bx.hy, Dt = bx.mu * g.Az / bx.hz;
+    const double Fe = g.rAx * (u[c] + u[c + 1]) / 2;
+    const double Fw = g.rAx * (u[c - 1] + u[c]) / 2;
+    const double Fn = g.rAy * (v[X.v(i - 1, j + 1, k)] + v[X.v(i, j + 1, k)]) / 2;
+    const double Fs = g.rAy * (v[X.v(i - 1, j, k)] + v[X.v(i, j, k)]) / 2;
+    const double Ft = g.rAz * (w[X.w(i - 1, j, k + 1)] + w[X.w(i, j, k + 1)]) / 2;
+    const double Fb = g.rAz * (w[X.w(i - 1, j, k)] + w[X.w(i, j, k)]) / 2;
+    const double De = g.De, Dn = g.Dn, Dt = g.Dt;
     double bnd = 0.0, aS = 0.0, aT = 0.0, aB = 0.0;
     const double aE = De + pos(-Fe);
     const double aW = De + pos(Fw);
@@ -125,7 +121,7 @@ __device__ void form_u(const MomArgs &A, const Geo &g, const Idx &X, int i, int 
     else bnd = bnd + 2 * Dt + pos(-Ft);                     // wall z = Lz
     if (k > 0) aB = Dt + pos(Fb);
     else bnd = bnd + 2 * Dt + pos(Fb);                      // wall z = 0
-    const double src = rh * g.V / bx.dt * A.u0[c] + (p[X.p(i - 1, j, k)] - p[X.p(i, j, k)]) * g.Ax;
+    const double src = g.aP0 * A.u0[c] + (p[X.p(i - 1, j, k)] - p[X.p(i, j, k)]) * g.Ax;
     finish(bx, g, aE, aW, aN, aS, aT, aB, bnd, src, u[c], g.Ax, r);
 }
 
@@ -138,17 +134,16 @@ __device__ void form_v(const MomArgs &A, const Geo &g, const Idx &X, int i, int 
         return;
     }
     const double *u = A.u, *v = A.v, *w = A.w, *p = A.p;
-    const double rh = bx.rho;
     const int c = X.v(i, j, k);
     const int jl = j - 1, jh = j < ny ? j : ny - 1;
     const double vn = v[j < ny ? c + nx : c];   // (every load in bounds)
-    const double Fn = rh * g.Ay * (j < ny ? (v[c] + vn) / 2 : v[c]);
-    const double Fs = rh * g.Ay * (v[c - nx] + v[c]) / 2;
-    const double Fe = rh * g.Ax * (u[X.u(i + 1, jl, k)] + u[X.u(i + 1, jh, k)]) / 2;
-    const double Fw = rh * g.Ax * (u[X.u(i, jl, k)] + u[X.u(i, jh, k)]) / 2;
-    const double Ft = rh * g.Az * (w[X.w(i, jl, k + 1)] + w[X.w(i, jh, k + 1)]) / 2;
-    const double Fb = rh * g.Az * (w[X.w(i, jl, k)] + w[X.w(i, jh, k)]) / 2;
-    const double De = bx.mu * g.Ax / bx.hx, Dn = bx.mu * g.Ay / bx.hy, Dt = bx.mu * g.Az / bx.hz;
+    const double Fn = g.rAy * (j < ny ? (v[c] + vn) / 2 : v[c]);
+    const double Fs = g.rAy * (v[c - nx] + v[c]) / 2;
+    const double Fe = g.rAx * (u[X.u(i + 1, jl, k)] + u[X.u(i + 1, jh, k)]) / 2;
+    const double Fw = g.rAx * (u[X.u(i, jl, k)] + u[X.u(i, jh, k)]) / 2;
+    const double Ft = g.rAz * (w[X.w(i, jl, k + 1)] + w[X.w(i, jh, k + 1)]) / 2;
+    const double Fb = g.rAz * (w[X.w(i, jl, k)] + w[X.w(i, jh, k)]) / 2;
+    const double De = g.De, Dn = g.Dn, Dt = g.Dt;
     double bnd = 0.0, aE = 0.0, aW = 0.0, aT = 0.0, aB = 0.0;
     if (i + 1 < nx) aE = De + pos(-Fe);
     else bnd = bnd + 2 * De + pos(-Fe);
@@ -162,7 +157,7 @@ __device__ void form_v(const MomArgs &A, const Geo &g, const Idx &X, int i, int 
     else bnd = bnd + 2 * Dt + pos(Fb);
     const double p_hi = p[X.p(i, jh, k)];
     const double p_above = j < ny ? p_hi : 0.0;
-    const double src = rh * g.V / bx.dt * A.v0[c] + (p[X.p(i, j - 1, k)] - p_above) * g.Ay + rh * bx.gy * g.V;
+    const double src = g.aP0 * A.v0[c] + (p[X.p(i, j - 1, k)] - p_above) * g.Ay + g.rgV;
     finish(bx, g, aE, aW, aN, aS, aT, aB, bnd, src, v[c], g.Ay, r);
 }
 
@@ -175,15 +170,14 @@ __device__ void form_w(const MomArgs &A, const Geo &g, const Idx &X, int i, int 
         return;
     }
     const double *u = A.u, *v = A.v, *w = A.w, *p = A.p;
-    const double rh = bx.rho;
     const int c = X.w(i, j, k), P = nx * ny;
-    const double Ft = rh * g.Az * (w[c] + w[c + P]) / 2;
-    const double Fb = rh * g.Az * (w[c - P] + w[c]) / 2;
-    const double Fe = rh * g.Ax * (u[X.u(i + 1, j, k - 1)] + u[X.u(i + 1, j, k)]) / 2;
-    const double Fw = rh * g.Ax * (u[X.u(i, j, k - 1)] + u[X.u(i, j, k)]) / 2;
-    const double Fn = rh * g.Ay * (v[X.v(i, j + 1, k - 1)] + v[X.v(i, j + 1, k)]) / 2;
-    const double Fs = rh * g.Ay * (v[X.v(i, j, k - 1)] + v[X.v(i, j, k)]) / 2;
-    const double De = bx.mu * g.Ax / bx.hx, Dn = bx.mu * g.Ay / bx.hy, Dt = bx.mu * g.Az / bx.hz;
+    const double Ft = g.rAz * (w[c] + w[c + P]) / 2;
+    const double Fb = g.rAz * (w[c - P] + w[c]) / 2;
+    const double Fe = g.rAx * (u[X.u(i + 1, j, k - 1)] + u[X.u(i + 1, j, k)]) / 2;
+    const double Fw = g.rAx * (u[X.u(i, j, k - 1)] + u[X.u(i, j, k)]) / 2;
+    const double Fn = g.rAy * (v[X.v(i, j + 1, k - 1)] + v[X.v(i, j + 1, k)]) / 2;
+    const double Fs = g.rAy * (v[X.v(i, j, k - 1)] + v[X.v(i, j, k)]) / 2;
+    const double De = g.De, Dn = g.Dn, Dt = g.Dt;
     double bnd = 0.0, aE = 0.0, aW = 0.0, aS = 0.0;
     if (i + 1 < nx) aE = De + pos(-Fe);
     else bnd = bnd + 2 * De + pos(-Fe);
@@ -194,7 +188,7 @@ __device__ void form_w(const MomArgs &A, const Geo &g, const Idx &X, int i, int 
     else bnd = bnd + 2 * Dn + pos(Fs);
     const double aT = Dt + pos(-Ft);
     const double aB = Dt + pos(Fb);
-    const double src = rh * g.V / bx.dt * A.w0[c] + (p[X.p(i, j, k - 1)] - p[X.p(i, j, k)]) * g.Az;
+    const double src = g.aP0 * A.w0[c] + (p[X.p(i, j, k - 1)] - p[X.p(i, j, k)]) * g.Az;
     finish(bx, g, aE, aW, aN, aS, aT, aB, bnd, src, w[c], g.Az, r);
 }
 
@@ -251,13 +245,13 @@ __global__ void __launch_bounds__(kThreads) form_pressure_kernel(PresArgs A, int
     if (c < n) {
         const int i = c % nx, q = c / nx, j = q % ny, k = q / ny;
         const double rh = bx.rho;
-        const double aE = i + 1 < nx ? rh * g.Ax * A.du[X.u(i + 1, j, k)] : 0.0;
-        const double aW = i > 0 ? rh * g.Ax * A.du[X.u(i, j, k)] : 0.0;
-        const double aN = j + 1 < ny ? rh * g.Ay * A.dv[X.v(i, j + 1, k)] : 0.0;
-        const double out = j + 1 == ny ? rh * g.Ay * A.dv[X.v(i, j + 1, k)] : 0.0;
-        const double aS = j > 0 ? rh * g.Ay * A.dv[X.v(i, j, k)] : 0.0;
-        const double aT = k + 1 < nz ? rh * g.Az * A.dw[X.w(i, j, k + 1)] : 0.0;
-        const double aB = k > 0 ? rh * g.Az * A.dw[X.w(i, j, k)] : 0.0;
+        const double aE = i + 1 < nx ? g.rAx * A.du[X.u(i + 1, j, k)] : 0.0;
+        const double aW = i > 0 ? g.rAx * A.du[X.u(i, j, k)] : 0.0;
+        const double aN = j + 1 < ny ? g.rAy * A.dv[X.v(i, j + 1, k)] : 0.0;
+        const double out = j + 1 == ny ? g.rAy * A.dv[X.v(i, j + 1, k)] : 0.0;
+        const double aS = j > 0 ? g.rAy * A.dv[X.v(i, j, k)] : 0.0;
+        const double aT = k + 1 < nz ? g.rAz * A.dw[X.w(i, j, k + 1)] : 0.0;
+        const double aB = k > 0 ? g.rAz * A.dw[X.w(i, j, k)] : 0.0;
         const double aP = aE + aW + aN + aS + aT + aB + out;
         const double b = rh * ((A.u[X.u(i, j, k)] - A.u[X.u(i + 1, j, k)]) * g.Ax +
                                (A.v[X.v(i, j, k)] - A.v[X.v(i, j + 1, k)]) * g.Ay +
