@@ -422,6 +422,41 @@ def test_config1_full_size_residual(torch_dev, orc, precision, scheme):
     assert np.max(np.abs(xg - xs)) <= orc.forward_error_certificate(g.shape, diags, b, xg) * (1 + 1e-6)
 
 
+def _batched_full_size(torch, dev, orc, cfg, precisions, env=None):
+    """Every set of workload cfg at full size, solved in one batched call to 1e-10 per precision;
+    the oracle recomputes each set's residual and bounds its forward error."""
+    systems = []
+    for i in range(len(W.CONFIGS[cfg]["grids"])):
+        systems.append(manufactured(orc, cfg, set_id=i))
+        print("config%d set %d generated" % (cfg, i), flush=True)
+    grids = [s[0].shape for s in systems]
+    Ds = [dev_arrays(torch, dev, s[1]) for s in systems]
+    bs = [dev_arrays(torch, dev, [s[2]])[0] for s in systems]
+    for precision in precisions:
+        ctx = context(grids, precision=precision, env=env)
+        xb, infos = ctx.solve_batched(Ds, bs, tol=1e-10, maxit=W.CONFIGS[cfg]["maxit"])
+        print("config%d batched %s" % (cfg, precision), infos, flush=True)
+        for i, (g, diags, b, xs) in enumerate(systems):
+            assert infos[i]["status"] == 0, (precision, i, infos[i])
+            xg = host(xb[i])
+            assert orc.rel_residual(g.shape, diags, b, xg) <= 1e-10, (precision, i)
+            assert np.max(np.abs(xg - xs)) <= orc.forward_error_certificate(g.shape, diags, b, xg) * (1 + 1e-6)
+        ctx.close()
+        del xb
+
+
+def test_config2_full_size_batched(torch_dev, orc):
+    """The four staggered sets of a time step (96-97 x 384-385 x 96-97), FP64 and FP32 + refinement."""
+    torch, dev = torch_dev
+    _batched_full_size(torch, dev, orc, 2, ["fp64", "fp32_refine"])
+
+
+def test_config4_full_size_batched(torch_dev, orc):
+    """The large tall bed: four 192 x 768 x 192 sets (113 M cells) in one call, FP32 + refinement and FP64."""
+    torch, dev = torch_dev
+    _batched_full_size(torch, dev, orc, 4, ["fp32_refine", "fp64"])
+
+
 # ---------------------------------------------------------------- multigrid preconditioner
 
 MG_SMALL = dict(omega=0.8, gamma=1.6, coarse_sweeps=7, coarse_cells=16)
