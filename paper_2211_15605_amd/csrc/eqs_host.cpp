@@ -676,7 +676,7 @@ hipError_t mg_vcycle(const Run &R, const double *r, double *z, bool gated, hipSt
 // the Galerkin operators of every coarse level of set s, from the diagonals in its table entry
 hipError_t mg_coarsen_all(eqs_ctx *c, int s) {
     const std::vector<MgLevel> &L = c->mg[s];
-    hipError_t e = hipSuccess;
+    hipError_t e = launch_mg_round0(c->d_desc + s, c->d_mg + (size_t)s * kMgMaxLevels, L[0].n, c->stream);
     for (int l = 0; l + 1 < (int)L.size() && e == hipSuccess; ++l)
         e = launch_mg_coarsen(c->d_desc + s, c->d_mg + (size_t)s * kMgMaxLevels, l, L[l + 1].n, c->stream);
     return e;
@@ -751,7 +751,7 @@ int run_fp64_mg(Run &R) {
         R.c->broken = true;
         return EQS_ERR_HIP;
     }
-    R.c->launches += R.c->mg[R.first].size() - 1;
+    R.c->launches += R.c->mg[R.first].size();
     if ((rc = R.L(K_SETUP))) return rc;
     if ((rc = R.readback())) return rc;
     R.reset_rate();
@@ -1004,6 +1004,7 @@ int eqsolve_set_preconditioner(eqs_ctx *c, int32_t kind, const eqs_mg_params *pr
         l0.nz = g.nz;
         l0.n = c->sets[s].n;
         mg[s].push_back(l0);
+        bytes += 7 * align_up((size_t)l0.n * 4);   // level 0's FP32 coefficients
         while (mg[s].back().n > p.coarse_cells && mg[s].back().n > 1 && (int)mg[s].size() < kMgMaxLevels) {
             const MgLevel &f = mg[s].back();
             MgLevel q{};
@@ -1031,7 +1032,12 @@ int eqsolve_set_preconditioner(eqs_ctx *c, int32_t kind, const eqs_mg_params *pr
     for (int s = 0; s < c->nsets; ++s)
         for (size_t l = 0; l < mg[s].size(); ++l) {
             MgLevel &L = mg[s][l];
-            if (l > 0) {
+            if (l == 0) {
+                for (int k = 0; k < 7; ++k) {
+                    L.a32[k] = (float *)q;
+                    q += align_up((size_t)L.n * 4);
+                }
+            } else {
                 for (int k = 0; k < 7; ++k) {
                     L.a[k] = (double *)q;
                     q += align_up((size_t)L.n * 8);

@@ -113,6 +113,8 @@ struct MgLevel {
     int32_t nx, ny, nz, n;
     double *a[7];   // Galerkin coefficients (levels >= 1)
     double *r, *z;  // right-hand side and result of the level's V-cycle (levels >= 1)
+    float *a32[7];  // level 0: the system's coefficients rounded to FP32, the operator the
+                    // V-cycle takes on that level (and coarsens from); arithmetic stays FP64
 };
 struct MgParams {
     double omega;         // damped-Jacobi weight

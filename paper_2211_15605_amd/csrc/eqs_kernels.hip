@@ -1845,33 +1845,59 @@ __global__ void __launch_bounds__(kBlock) fill_kernel(double *p, long n, double 
 // and sum an aggregate's cells in index order, so the V-cycle equals a plain
 // sequential evaluation of the definition to the last bit.
 
-__device__ __forceinline__ const double *mg_coef(const SetDesc *d, const MgLevel &L, int l, int q) {
-    return l == 0 ? d->a[q] : L.a[q];
+// the coefficients of level l as the V-cycle sees them: level 0 from its FP32 copy
+// (widened exactly to FP64), coarser levels from their FP64 Galerkin arrays
+struct LevCoef {
+    const double *d[7];
+    const float *f[7];
+    bool f32;
+    __device__ __forceinline__ double operator()(int q, int c) const {
+        return f32 ? (double)ld(f[q], c) : ld(d[q], c);
+    }
+};
+
+__device__ __forceinline__ LevCoef mg_coef(const MgLevel &L, int l) {
+    LevCoef k;
+    k.f32 = l == 0;
+    for (int q = 0; q < 7; ++q) {
+        k.d[q] = L.a[q];
+        k.f[q] = L.a32[q];
+    }
+    return k;
 }
 
 // row c = (i, j, k) of A applied to x: a_P x_c, then minus each present
 // neighbour's term in the order E, W, N, S, T, B; xat(cell, i, j, k) gives x
 template <class F>
-__device__ __forceinline__ double mg_row(const double *const *a, int nx, int ny, int nz, int i, int j, int k, int c,
+__device__ __forceinline__ double mg_row(const LevCoef &a, int nx, int ny, int nz, int i, int j, int k, int c,
                                          F xat) {
 #pragma clang fp contract(off)
     const int P = nx * ny;
-    double acc = ld(a[0], c) * xat(c, i, j, k);
-    if (i + 1 < nx) acc -= ld(a[1], c) * xat(c + 1, i + 1, j, k);
-    if (i > 0) acc -= ld(a[2], c) * xat(c - 1, i - 1, j, k);
-    if (j + 1 < ny) acc -= ld(a[3], c) * xat(c + nx, i, j + 1, k);
-    if (j > 0) acc -= ld(a[4], c) * xat(c - nx, i, j - 1, k);
-    if (k + 1 < nz) acc -= ld(a[5], c) * xat(c + P, i, j, k + 1);
-    if (k > 0) acc -= ld(a[6], c) * xat(c - P, i, j, k - 1);
+    double acc = a(0, c) * xat(c, i, j, k);
+    if (i + 1 < nx) acc -= a(1, c) * xat(c + 1, i + 1, j, k);
+    if (i > 0) acc -= a(2, c) * xat(c - 1, i - 1, j, k);
+    if (j + 1 < ny) acc -= a(3, c) * xat(c + nx, i, j + 1, k);
+    if (j > 0) acc -= a(4, c) * xat(c - nx, i, j - 1, k);
+    if (k + 1 < nz) acc -= a(5, c) * xat(c + P, i, j, k + 1);
+    if (k > 0) acc -= a(6, c) * xat(c - P, i, j, k - 1);
     return acc;
+}
+
+// level 0's FP32 copy of the set's coefficients (round to nearest), once per solve
+__global__ void __launch_bounds__(kBlock) mg_round0_kernel(const SetDesc *d, const MgLevel *lev) {
+    const MgLevel F = lev[0];
+    const double *a[7];
+    for (int q = 0; q < 7; ++q) a[q] = d->a[q];
+    for (int c = blockIdx.x * kBlock + threadIdx.x; c < F.n; c += gridDim.x * kBlock)
+#pragma unroll
+        for (int q = 0; q < 7; ++q) st(F.a32[q], c, (float)ld(a[q], c));
 }
 
 // Galerkin coarse operator of level l + 1, one thread per coarse cell
 __global__ void __launch_bounds__(kBlock) mg_coarsen_kernel(const SetDesc *d, const MgLevel *lev, int l) {
 #pragma clang fp contract(off)
     const MgLevel F = lev[l], C = lev[l + 1];
-    const double *a[7];
-    for (int q = 0; q < 7; ++q) a[q] = mg_coef(d, F, l, q);
+    const LevCoef a = mg_coef(F, l);
     const int nx = F.nx, ny = F.ny, nz = F.nz, cx = C.nx, cy = C.ny;
     for (int cc = blockIdx.x * kBlock + threadIdx.x; cc < C.n; cc += gridDim.x * kBlock) {
         const int I = cc % cx, t = cc / cx, J = t % cy, K = t / cy;
@@ -1880,14 +1906,14 @@ __global__ void __launch_bounds__(kBlock) mg_coarsen_kernel(const SetDesc *d, co
             for (int j = 2 * J; j < min(2 * J + 2, ny); ++j)
                 for (int i = 2 * I; i < min(2 * I + 2, nx); ++i) {
                     const int c = i + nx * (j + ny * k);
-                    acc[0] += ld(a[0], c);
+                    acc[0] += a(0, c);
                     const int ni[6] = {i + 1, i - 1, i, i, i, i};
                     const int nj[6] = {j, j, j + 1, j - 1, j, j};
                     const int nk[6] = {k, k, k, k, k + 1, k - 1};
                     for (int dd = 0; dd < 6; ++dd) {
                         if (ni[dd] < 0 || ni[dd] >= nx || nj[dd] < 0 || nj[dd] >= ny || nk[dd] < 0 || nk[dd] >= nz)
                             continue;
-                        const double coef = ld(a[1 + dd], c);
+                        const double coef = a(1 + dd, c);
                         if (ni[dd] / 2 == I && nj[dd] / 2 == J && nk[dd] / 2 == K)
                             acc[0] -= coef;  // link inside the aggregate
                         else
@@ -1907,12 +1933,10 @@ __global__ void __launch_bounds__(kBlock) mg_restrict_kernel(const SetDesc *d, c
 #pragma clang fp contract(off)
     if (gated && !d->st->active) return;
     const MgLevel F = lev[l], C = lev[l + 1];
-    const double *a[7];
-    for (int q = 0; q < 7; ++q) a[q] = mg_coef(d, F, l, q);
+    const LevCoef a = mg_coef(F, l);
     const int nx = F.nx, ny = F.ny, nz = F.nz, cx = C.nx, cy = C.ny;
     const double w = prm.omega;
-    const double *ap = a[0];
-    auto z1 = [&](int x, int, int, int) { return w * ld(rin, x) / ld(ap, x); };
+    auto z1 = [&](int x, int, int, int) { return w * ld(rin, x) / a(0, x); };
     const int g8 = threadIdx.x & 7, di = g8 & 1, dj = (g8 >> 1) & 1, dk = g8 >> 2;
     const int stride = (int)(gridDim.x * kBlock) >> 3;
     // the loop bound is uniform over a wave (the shuffles need every lane of a group)
@@ -1952,18 +1976,17 @@ __global__ void __launch_bounds__(kBlock) mg_prolong_kernel(const SetDesc *d, co
 #pragma clang fp contract(off)
     if (gated && !d->st->active) return;
     const MgLevel F = lev[l], C = lev[l + 1];
-    const double *a[7];
-    for (int q = 0; q < 7; ++q) a[q] = mg_coef(d, F, l, q);
+    const LevCoef a = mg_coef(F, l);
     const int nx = F.nx, ny = F.ny, nz = F.nz, cx = C.nx, cy = C.ny;
     const double w = prm.omega, gm = prm.gamma;
-    const double *ap = a[0], *e = C.z;
+    const double *e = C.z;
     auto z2 = [&](int x, int i, int j, int k) {
-        return w * ld(rin, x) / ld(ap, x) + gm * ld(e, i / 2 + cx * (j / 2 + cy * (k / 2)));
+        return w * ld(rin, x) / a(0, x) + gm * ld(e, i / 2 + cx * (j / 2 + cy * (k / 2)));
     };
     for (int c = blockIdx.x * kBlock + threadIdx.x; c < F.n; c += gridDim.x * kBlock) {
         const int i = c % nx, t = c / nx, j = t % ny, k = t / ny;
         const double q = mg_row(a, nx, ny, nz, i, j, k, c, z2);
-        st(zout, c, z2(c, i, j, k) + w * (ld(rin, c) - q) / ld(ap, c));
+        st(zout, c, z2(c, i, j, k) + w * (ld(rin, c) - q) / a(0, c));
     }
 }
 
@@ -1978,8 +2001,7 @@ __global__ void __launch_bounds__(kMgCoarseThreads) mg_coarsest_kernel(const Set
     if (gated && !d->st->active) return;
     __shared__ double zb[2][kMgCoarsestMax];
     const MgLevel F = lev[l];
-    const double *a[7];
-    for (int q = 0; q < 7; ++q) a[q] = mg_coef(d, F, l, q);
+    const LevCoef a = mg_coef(F, l);
     const int nx = F.nx, ny = F.ny, nz = F.nz, n = F.n, P = nx * ny;
     const double w = prm.omega;
     double co[kMgCoarseCells][7], rr[kMgCoarseCells];
@@ -1997,7 +2019,7 @@ __global__ void __launch_bounds__(kMgCoarseThreads) mg_coarsest_kernel(const Set
         has[m][3] = j > 0;
         has[m][4] = k + 1 < nz;
         has[m][5] = k > 0;
-        for (int q = 0; q < 7; ++q) co[m][q] = ld(a[q], cl);
+        for (int q = 0; q < 7; ++q) co[m][q] = a(q, cl);
         rr[m] = ld(rin, cl);
         if (c < n) zb[0][c] = 0.0;
     }
@@ -2036,8 +2058,8 @@ struct PhMgResid {
     static constexpr int NV = 1;
     struct Raw { double r, ap; };
     struct Aux { double r, ap; };
-    struct Pre { Coef6<double, false> c; };
-    const double *a[7];
+    struct Pre { Coef6<float, false> c; };  // level 0's FP32 coefficients, widened in use
+    const float *a[7];
     const double *rin;
     double *res;
     double w;
@@ -2075,8 +2097,8 @@ struct PhMgProlong {
     static constexpr int NV = 1;
     struct Raw { double r, ap, e; };
     struct Aux { double r, ap; };
-    struct Pre { Coef6<double, false> c; };
-    const double *a[7];
+    struct Pre { Coef6<float, false> c; };  // level 0's FP32 coefficients, widened in use
+    const float *a[7];
     const double *rin, *e;
     double *zout;
     double w, g;
@@ -2113,13 +2135,13 @@ struct PhMgProlong {
 };
 
 template <int CPT, int H>
-__global__ void __launch_bounds__(kBlock) mg_resid0_kernel(LaunchSets ls, const double *rin, double *res,
-                                                           MgParams prm, int gated) {
+__global__ void __launch_bounds__(kBlock) mg_resid0_kernel(LaunchSets ls, const MgLevel *lev, const double *rin,
+                                                           double *res, MgParams prm, int gated) {
     const TileRef tr = locate<false>(ls);
     const SetDesc &d = *tr.d;
     if (gated && !d.st->active) return;
     PhMgResid ph;
-    for (int k = 0; k < 7; ++k) ph.a[k] = d.a[k];
+    for (int k = 0; k < 7; ++k) ph.a[k] = lev[0].a32[k];
     ph.rin = rin;
     ph.res = res;
     ph.w = prm.omega;
@@ -2137,7 +2159,7 @@ __global__ void __launch_bounds__(kBlock) mg_prolong0_kernel(LaunchSets ls, cons
     const SetDesc &d = *tr.d;
     if (gated && !d.st->active) return;
     PhMgProlong ph;
-    for (int k = 0; k < 7; ++k) ph.a[k] = d.a[k];
+    for (int k = 0; k < 7; ++k) ph.a[k] = lev[0].a32[k];
     ph.rin = rin;
     ph.e = lev[1].z;
     ph.zout = zout;
@@ -2365,6 +2387,11 @@ hipError_t launch_small(const LaunchSets &ls, int max_n, bool trans, hipStream_t
 
 static dim3 mg_grid(int n) { return dim3((unsigned)std::max(1, std::min((n + kBlock - 1) / kBlock, 8192))); }
 
+hipError_t launch_mg_round0(const SetDesc *d, const MgLevel *lev, int n, hipStream_t stream) {
+    hipLaunchKernelGGL(mg_round0_kernel, mg_grid(n), dim3(kBlock), 0, stream, d, lev);
+    return hipGetLastError();
+}
+
 hipError_t launch_mg_coarsen(const SetDesc *d, const MgLevel *lev, int l, int nc, hipStream_t stream) {
     hipLaunchKernelGGL(mg_coarsen_kernel, mg_grid(nc), dim3(kBlock), 0, stream, d, lev, l);
     return hipGetLastError();
@@ -2461,8 +2488,8 @@ hipError_t launch_mg_fine(const LaunchSets &ls, int ntiles, int cpt, int max_nx,
     if (h < 0 || (cpt != 1 && cpt != 2)) return hipErrorInvalidValue;
     const size_t lds64 = march_lds_bytes(cpt, max_nx, 8);
     if (res)
-        EQS_DISPATCH(cpt, h, hipLaunchKernelGGL((mg_resid0_kernel<C, HH>), grid, block, lds64, stream, ls, rin, res,
-                                                prm, gated ? 1 : 0));
+        EQS_DISPATCH(cpt, h, hipLaunchKernelGGL((mg_resid0_kernel<C, HH>), grid, block, lds64, stream, ls, lev, rin,
+                                                res, prm, gated ? 1 : 0));
     else
         EQS_DISPATCH(cpt, h, hipLaunchKernelGGL((mg_prolong0_kernel<C, HH>), grid, block, lds64, stream, ls, lev, rin,
                                                 zout, prm, gated ? 1 : 0));

@@ -465,14 +465,16 @@ MG_SMALL = dict(omega=0.8, gamma=1.6, coarse_sweeps=7, coarse_cells=16)
 @pytest.mark.parametrize("cfg,shape", [(0, (20, 17, 9)), (1, (33, 64, 17)), (0, (5, 1, 1)), (2, (1, 40, 3)),
                                        (1, (16, 16, 16))])
 def test_mg_vcycle_matches_oracle(torch_dev, orc, cfg, shape):
-    # the V-cycle takes the definition's operations in its order with no FMA contraction:
-    # the same bits as the oracle's plain evaluation
+    # the V-cycle takes the definition's operations in its order with no FMA contraction, on the
+    # system's coefficients rounded to FP32 (its level-0 operator): the same bits as the oracle's
+    # plain evaluation of the V-cycle of that operator
     from oracle import oracle as O
     torch, dev = torch_dev
     g = W.Grid(*shape)
     diags = W.make_set(cfg, 0, grid=g)["diags"]
     r = np.random.default_rng(11).standard_normal(g.n)
-    zo, lo = orc.mg_apply(g.shape, diags, r, O.mg_params(**MG_SMALL))
+    rounded = [d.astype(np.float32).astype(np.float64) for d in diags]
+    zo, lo = orc.mg_apply(g.shape, rounded, r, O.mg_params(**MG_SMALL))
     ctx = context([g.shape])
     ctx.set_preconditioner("mg", **MG_SMALL)
     z, lev = ctx.precond_apply(dev_arrays(torch, dev, diags), dev_arrays(torch, dev, [r])[0])
