@@ -306,7 +306,7 @@ def gpu_leg(args):
 
 
 def gpu_leg_batched(args):
-    """All equation sets of the workload in one call (configs 2 and 4)."""
+    """All equation sets of the workload in one call (the four-set time step, the large tall bed)."""
     import numpy as np
     import torch
 
