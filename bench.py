@@ -159,6 +159,20 @@ def time_simple(iters=8, warm=2):
                                         "GBps": by[name] / (ms * 1e-3) / 1e9}
             del mo, po
             del d, pp, vc, pc
+            # whole time steps (one call each): from the initial fields, SIMPLE iterations until the
+            # mass imbalance has fallen by 1e-4, at most 50
+            g = {k: torch.from_numpy(v).to(dev) for k, v in st.items()}
+            vg = [g[c] for c in comps]
+            steps = []
+            for _ in range(2):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                si = sb.time_step(vg, g["p"], max_iter=50, mass_tol=1e-4, tol=tol, maxit=maxit)
+                torch.cuda.synchronize()
+                steps.append({"ms": 1e3 * (time.perf_counter() - t0), "simple_iters": si["simple_iters"],
+                              "status": si["status"], "mass_residual_last": si["mass_residual"]})
+            out["time_steps_mg"] = steps
+            del g, vg
         sb.close()
         del f, vel, old
     out["mg_speedup_per_iteration"] = out["jacobi"]["ms_per_simple_iteration"] / out["mg"]["ms_per_simple_iteration"]

@@ -63,9 +63,9 @@ typedef struct {
 } eqs_box;
 
 typedef struct {
-    int32_t status;          /* worst EQS_* status (>= 0) of the last SIMPLE iteration's solves */
-    int32_t iters[4];        /* BiCGSTAB iterations of those solves: p', u, v, w */
-    int32_t pad;
+    int32_t status;          /* worst EQS_* status (>= 0) of the call's solves */
+    int32_t iters[4];        /* BiCGSTAB iterations of the last SIMPLE iteration's solves: p', u, v, w */
+    int32_t simple_iters;    /* SIMPLE iterations the call ran */
     double mom_residual[3];  /* ||b - A x*||_2 of the u, v, w rows at the incoming iterate x* */
     double mass_residual;    /* ||b'||_2: mass imbalance of the predicted velocities (kg/s) */
 } eqs_simple_info;
@@ -74,7 +74,8 @@ typedef struct {
  * Create a context for one box: two solver contexts on `hip_stream` (the
  * three momentum grids, in `precision`, one EQS_* precision of eqsolve.h;
  * the p' grid in FP64) and the work arrays of one SIMPLE iteration (8 FP64
- * arrays per system, 3 d arrays, p', partial sums).  Returns EQS_OK,
+ * arrays per system, 3 d arrays, p', partial sums) and of a time step (the
+ * 3 old-time velocity fields).  Returns EQS_OK,
  * EQS_ERR_ARG (box values out of range, precision), EQS_ERR_NOMEM or
  * EQS_ERR_HIP; *ctx is NULL unless EQS_OK.
  */
@@ -127,6 +128,19 @@ int eqsimple_correct(eqsimple_ctx *ctx, const double *const d[3], const double *
  */
 int eqsimple_iterate(eqsimple_ctx *ctx, double *const vel[3], double *p, const double *const old[3],
                      int32_t niter, const double tol[2], const int32_t maxit[2], eqs_simple_info *info);
+
+/*
+ * One time step in one call (the paper's one call into the device graph per
+ * time step, Sec. 2.2.2): the current velocities vel[3] become the old-time
+ * fields (copied into the context), then SIMPLE iterations as in
+ * eqsimple_iterate run in place on vel[3] and p, at most max_iter, stopping
+ * after the first iteration whose mass imbalance ||b'|| is at most mass_tol
+ * times the first iteration's (mass_tol = 0: all max_iter).  info reports the
+ * SIMPLE iterations run.  Returns as eqsimple_iterate; EQS_ERR_ARG also for
+ * max_iter < 1 or mass_tol outside [0, 1).
+ */
+int eqsimple_step(eqsimple_ctx *ctx, double *const vel[3], double *p, int32_t max_iter, double mass_tol,
+                  const double tol[2], const int32_t maxit[2], eqs_simple_info *info);
 
 /*
  * Preconditioner of the p' solves (eqsolve_set_preconditioner on the

@@ -27,7 +27,7 @@ SYMBOLS = ("eqsolve_create", "eqsolve_solve", "eqsolve_solve_batched", "eqsolve_
            "eqsolve_debug_profile", "eqsolve_debug_kernel_stats", "eqsolve_set_preconditioner",
            "eqsolve_debug_precond",
            "eqsimple_create", "eqsimple_form_momentum", "eqsimple_form_pressure", "eqsimple_correct",
-           "eqsimple_iterate", "eqsimple_set_pressure_preconditioner", "eqsimple_destroy")
+           "eqsimple_iterate", "eqsimple_step", "eqsimple_set_pressure_preconditioner", "eqsimple_destroy")
 KERNEL_KINDS = {"setup": 0, "recheck": 1, "report": 2, "k1": 3, "k2": 4, "k3": 5, "cast": 6, "outer": 7,
                 "update": 8, "zero": 9, "grad": 10, "apply": 11, "scale": 12, "unscale": 13, "fused": 14,
                 "fsetup": 15, "mat": 16}
@@ -54,12 +54,13 @@ class EqsBox(ctypes.Structure):
 
 
 class EqsSimpleInfo(ctypes.Structure):
-    _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32 * 4), ("pad", ctypes.c_int32),
+    _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32 * 4), ("simple_iters", ctypes.c_int32),
                 ("mom_residual", ctypes.c_double * 3), ("mass_residual", ctypes.c_double)]
 
     def as_dict(self):
         return {"status": self.status, "iters": dict(zip(("p", "u", "v", "w"), list(self.iters))),
-                "mom_residual": list(self.mom_residual), "mass_residual": self.mass_residual}
+                "simple_iters": self.simple_iters, "mom_residual": list(self.mom_residual),
+                "mass_residual": self.mass_residual}
 
 
 class EqsInfo(ctypes.Structure):
@@ -124,10 +125,12 @@ def load(path: str | None = None):
         L.eqsimple_correct.argtypes = [VP, VPP, VP, VPP, VP]
         L.eqsimple_iterate.argtypes = [VP, VPP, VP, VPP, ctypes.c_int32, D3, ctypes.POINTER(ctypes.c_int32),
                                        ctypes.POINTER(EqsSimpleInfo)]
+        L.eqsimple_step.argtypes = [VP, VPP, VP, ctypes.c_int32, ctypes.c_double, D3, ctypes.POINTER(ctypes.c_int32),
+                                    ctypes.POINTER(EqsSimpleInfo)]
         L.eqsimple_set_pressure_preconditioner.argtypes = [VP, ctypes.c_int32, ctypes.POINTER(EqsMgParams)]
         L.eqsimple_destroy.argtypes = [VP]
         for f in ("eqsimple_create", "eqsimple_form_momentum", "eqsimple_form_pressure", "eqsimple_correct",
-                  "eqsimple_iterate", "eqsimple_set_pressure_preconditioner", "eqsimple_destroy"):
+                  "eqsimple_iterate", "eqsimple_step", "eqsimple_set_pressure_preconditioner", "eqsimple_destroy"):
             getattr(L, f).restype = ctypes.c_int
         if path is None:
             _lib = L
@@ -283,6 +286,15 @@ def eqsimple_iterate(h, vel, p, old, niter, tol2, maxit2):
     m = (ctypes.c_int32 * 2)(*map(int, maxit2))
     info = EqsSimpleInfo()
     rc = load().eqsimple_iterate(h, vp, VP(p), op, int(niter), t, m, ctypes.byref(info))
+    return rc, info
+
+
+def eqsimple_step(h, vel, p, max_iter, mass_tol, tol2, maxit2):
+    vp, k1 = ptr_array(vel)
+    t = (ctypes.c_double * 2)(*map(float, tol2))
+    m = (ctypes.c_int32 * 2)(*map(int, maxit2))
+    info = EqsSimpleInfo()
+    rc = load().eqsimple_step(h, vp, VP(p), int(max_iter), float(mass_tol), t, m, ctypes.byref(info))
     return rc, info
 
 

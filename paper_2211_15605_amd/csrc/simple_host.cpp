@@ -41,6 +41,7 @@ struct eqsimple_ctx {
     double *b[4] = {};
     double *d[3] = {};
     double *pp = nullptr;
+    double *old[3] = {};        // old-time velocities of eqsimple_step
     double *partials = nullptr;
     double *sums = nullptr;     // 4 device doubles
     double *sums_host = nullptr;  // pinned
@@ -179,6 +180,73 @@ hipError_t read_sums(eqsimple_ctx *c) {
     return hipStreamSynchronize(c->stream);
 }
 
+// up to niter SIMPLE iterations; with mass_tol > 0 they stop once the mass imbalance of an
+// iteration's predicted velocities is at most mass_tol times the first iteration's
+int run_iterations(eqsimple_ctx *c, double *const vel[3], double *p, const double *const old[3], int32_t niter,
+                   double mass_tol, const double tol[2], const int32_t maxit[2], eqs_simple_info *info) {
+    int rc;
+    double *diag_m[21];
+    double *bm[3];
+    for (int s = 0; s < 3; ++s) {
+        for (int q = 0; q < 7; ++q) diag_m[7 * s + q] = c->a[s][q];
+        bm[s] = c->b[s];
+    }
+    const double *const *vel_c = (const double *const *)vel;
+    const double *diag_sets[3][7];
+    const double *const *diag_ptrs[3];
+    const double *b_sets[3];
+    for (int s = 0; s < 3; ++s) {
+        for (int q = 0; q < 7; ++q) diag_sets[s][q] = c->a[s][q];
+        diag_ptrs[s] = diag_sets[s];
+        b_sets[s] = c->b[s];
+    }
+    const double tols[3] = {tol[0], tol[0], tol[0]};
+    const int32_t maxits[3] = {maxit[0], maxit[0], maxit[0]};
+    const double *diag_p[7];
+    for (int q = 0; q < 7; ++q) diag_p[q] = c->a[3][q];
+    eqs_info mi[3], pi{};
+    int worst = EQS_OK, done = 0;
+    double mass0 = -1.0;
+    for (int it = 0; it < niter; ++it) {
+        if (enqueue_form_momentum(c, vel_c, p, old, diag_m, bm, c->d) != hipSuccess) return hip_fail(c);
+        rc = eqsolve_solve_batched(c->mom, diag_ptrs, b_sets, vel, tols, maxits, mi);
+        if (rc < 0) return rc;
+        if (enqueue_form_pressure(c, c->d, vel_c, c->a[3], c->b[3]) != hipSuccess) return hip_fail(c);
+        if (launch_zero(c->pp, c->n[3], c->stream) != hipSuccess) return hip_fail(c);
+        rc = eqsolve_solve(c->prs, 0, diag_p, c->b[3], c->pp, tol[1], maxit[1], &pi);
+        if (rc < 0) return rc;
+        if (enqueue_correct(c, c->d, c->pp, vel, p) != hipSuccess) return hip_fail(c);
+        worst = std::max({worst, pi.status, mi[0].status, mi[1].status, mi[2].status});
+        ++done;
+        if (mass_tol > 0) {
+            if (read_sums(c) != hipSuccess) return hip_fail(c);
+            const double m = sqrt(c->sums_host[3]);
+            if (mass0 < 0) mass0 = m;
+            if (m <= mass_tol * mass0) break;
+        }
+    }
+    if (read_sums(c) != hipSuccess) return hip_fail(c);
+    if (info) {
+        memset(info, 0, sizeof(*info));
+        info->status = worst;
+        info->simple_iters = done;
+        info->iters[0] = pi.iters;
+        for (int s = 0; s < 3; ++s) {
+            info->iters[1 + s] = mi[s].iters;
+            info->mom_residual[s] = sqrt(c->sums_host[s]);
+        }
+        info->mass_residual = sqrt(c->sums_host[3]);
+    }
+    return EQS_OK;
+}
+
+bool solve_args_ok(const double tol[2], const int32_t maxit[2]) {
+    if (!tol || !maxit) return false;
+    for (int q = 0; q < 2; ++q)
+        if (!(tol[q] > 0 && tol[q] < 1) || maxit[q] < 1) return false;
+    return true;
+}
+
 }  // namespace
 
 extern "C" {
@@ -217,7 +285,7 @@ int eqsimple_create(eqsimple_ctx **out, const eqs_box *box, int32_t precision, v
     auto up = [](long v) { return (v + 31) / 32 * 32; };
     long total = 0;
     for (int s = 0; s < 4; ++s) total += 8 * up(c->n[s]);
-    for (int s = 0; s < 3; ++s) total += up(c->n[s]);
+    for (int s = 0; s < 3; ++s) total += 2 * up(c->n[s]);   // d, old-time velocity
     total += up(c->n[3]);
     const long nparts = (long)c->nb[0] + c->nb[1] + c->nb[2] + c->nb[3];
     total += up(nparts) + 32;
@@ -239,6 +307,8 @@ int eqsimple_create(eqsimple_ctx **out, const eqs_box *box, int32_t precision, v
     }
     for (int s = 0; s < 3; ++s) {
         c->d[s] = q;
+        q += up(c->n[s]);
+        c->old[s] = q;
         q += up(c->n[s]);
     }
     c->pp = q;
@@ -308,54 +378,24 @@ int eqsimple_iterate(eqsimple_ctx *c, double *const vel[3], double *p, const dou
                      const double tol[2], const int32_t maxit[2], eqs_simple_info *info) {
     int rc = usable(c);
     if (rc != EQS_OK) return rc;
-    if (!all_set(vel, 3) || !p || !all_set(old, 3) || !tol || !maxit || niter < 1) return EQS_ERR_ARG;
-    for (int q = 0; q < 2; ++q)
-        if (!(tol[q] > 0 && tol[q] < 1) || maxit[q] < 1) return EQS_ERR_ARG;
+    if (!all_set(vel, 3) || !p || !all_set(old, 3) || niter < 1 || !solve_args_ok(tol, maxit)) return EQS_ERR_ARG;
     if (hipSetDevice(c->device) != hipSuccess) return hip_fail(c);
-    double *diag_m[21];
-    double *bm[3];
-    for (int s = 0; s < 3; ++s) {
-        for (int q = 0; q < 7; ++q) diag_m[7 * s + q] = c->a[s][q];
-        bm[s] = c->b[s];
-    }
-    const double *const *vel_c = (const double *const *)vel;
-    const double *diag_sets[3][7];
-    const double *const *diag_ptrs[3];
-    const double *b_sets[3];
-    for (int s = 0; s < 3; ++s) {
-        for (int q = 0; q < 7; ++q) diag_sets[s][q] = c->a[s][q];
-        diag_ptrs[s] = diag_sets[s];
-        b_sets[s] = c->b[s];
-    }
-    const double tols[3] = {tol[0], tol[0], tol[0]};
-    const int32_t maxits[3] = {maxit[0], maxit[0], maxit[0]};
-    const double *diag_p[7];
-    for (int q = 0; q < 7; ++q) diag_p[q] = c->a[3][q];
-    eqs_info mi[3], pi{};
-    int worst = EQS_OK;
-    for (int it = 0; it < niter; ++it) {
-        if (enqueue_form_momentum(c, vel_c, p, old, diag_m, bm, c->d) != hipSuccess) return hip_fail(c);
-        rc = eqsolve_solve_batched(c->mom, diag_ptrs, b_sets, vel, tols, maxits, mi);
-        if (rc < 0) return rc;
-        if (enqueue_form_pressure(c, c->d, vel_c, c->a[3], c->b[3]) != hipSuccess) return hip_fail(c);
-        if (launch_zero(c->pp, c->n[3], c->stream) != hipSuccess) return hip_fail(c);
-        rc = eqsolve_solve(c->prs, 0, diag_p, c->b[3], c->pp, tol[1], maxit[1], &pi);
-        if (rc < 0) return rc;
-        if (enqueue_correct(c, c->d, c->pp, vel, p) != hipSuccess) return hip_fail(c);
-        worst = std::max({pi.status, mi[0].status, mi[1].status, mi[2].status});
-    }
-    if (read_sums(c) != hipSuccess) return hip_fail(c);
-    if (info) {
-        memset(info, 0, sizeof(*info));
-        info->status = worst;
-        info->iters[0] = pi.iters;
-        for (int s = 0; s < 3; ++s) {
-            info->iters[1 + s] = mi[s].iters;
-            info->mom_residual[s] = sqrt(c->sums_host[s]);
-        }
-        info->mass_residual = sqrt(c->sums_host[3]);
-    }
-    return EQS_OK;
+    return run_iterations(c, vel, p, old, niter, 0.0, tol, maxit, info);
+}
+
+int eqsimple_step(eqsimple_ctx *c, double *const vel[3], double *p, int32_t max_iter, double mass_tol,
+                  const double tol[2], const int32_t maxit[2], eqs_simple_info *info) {
+    int rc = usable(c);
+    if (rc != EQS_OK) return rc;
+    if (!all_set(vel, 3) || !p || max_iter < 1 || !(mass_tol >= 0 && mass_tol < 1) || !solve_args_ok(tol, maxit))
+        return EQS_ERR_ARG;
+    if (hipSetDevice(c->device) != hipSuccess) return hip_fail(c);
+    for (int s = 0; s < 3; ++s)
+        if (hipMemcpyAsync(c->old[s], vel[s], c->n[s] * sizeof(double), hipMemcpyDeviceToDevice, c->stream) !=
+            hipSuccess)
+            return hip_fail(c);
+    const double *old_c[3] = {c->old[0], c->old[1], c->old[2]};
+    return run_iterations(c, vel, p, old_c, max_iter, mass_tol, tol, maxit, info);
 }
 
 int eqsimple_set_pressure_preconditioner(eqsimple_ctx *c, int32_t kind, const eqs_mg_params *params) {

@@ -119,6 +119,20 @@ class SimpleBox:
         self._call(rc, "eqsimple_iterate")
         return info.as_dict()
 
+    def time_step(self, vel, p, max_iter=30, mass_tol=1e-3, tol=(1e-6, 1e-6), maxit=(100, 5000)):
+        """One time step in place on vel and p: the current velocities become the old-time
+        fields, then SIMPLE iterations until the mass imbalance falls to mass_tol times the
+        first iteration's (at most max_iter); returns the info of the call."""
+        comps = ("u", "v", "w")
+        vp = self._ptrs(vel, comps)
+        p_ = self._ptrs([p], ["p"])[0]
+        if int(max_iter) < 1 or not (0.0 <= float(mass_tol) < 1.0):
+            raise ValueError("max_iter must be >= 1 and mass_tol in [0, 1)")
+        with torch.cuda.device(self.device):
+            rc, info = B.eqsimple_step(self._h, vp, p_, max_iter, mass_tol, tol, maxit)
+        self._call(rc, "eqsimple_step")
+        return info.as_dict()
+
     def set_pressure_preconditioner(self, kind: str = "mg", **params):
         k = {"jacobi": B.EQS_PRECOND_JACOBI, "mg": B.EQS_PRECOND_MG}[kind]
         with torch.cuda.device(self.device):

@@ -200,3 +200,44 @@ def test_bad_boxes_rejected(tdev):
         box.update(bad)
         with pytest.raises(EqSolveError):
             simple_box(box)
+
+
+def test_time_step_equals_copy_then_iterations(tdev):
+    """eqsimple_step: the velocities become the old-time fields, then SIMPLE iterations; it equals
+    a copy followed by eqsimple_iterate bit for bit, and stops at the first iteration whose mass
+    imbalance has fallen to mass_tol times the first one's."""
+    torch, dev = tdev
+    box = W.bed_box(10, 20, 8)
+    st = W.box_state(box, seed=21, noise=0.2, old="draw")
+    tol, maxit = (1e-10, 1e-10), (500, 2000)
+    fa = dev_state(torch, dev, st)
+    sa = simple_box(box)
+    va = [fa[c] for c in COMPS]
+    info = sa.time_step(va, fa["p"], max_iter=3, mass_tol=0.0, tol=tol, maxit=maxit)
+    assert info["simple_iters"] == 3 and info["status"] == 0, info
+    fb = dev_state(torch, dev, st)
+    sb = simple_box(box)
+    vb = [fb[c] for c in COMPS]
+    old = [v.clone() for v in vb]
+    ib = sb.iterate(vb, fb["p"], old, niter=3, tol=tol, maxit=maxit)
+    assert ib["simple_iters"] == 3
+    for x, y in zip(va + [fa["p"]], vb + [fb["p"]]):
+        assert torch.equal(x, y)
+    # early stop
+    fc = dev_state(torch, dev, st)
+    vc = [fc[c] for c in COMPS]
+    ic = sa.time_step(vc, fc["p"], max_iter=50, mass_tol=1e-2, tol=tol, maxit=maxit)
+    fd = dev_state(torch, dev, st)
+    vd = [fd[c] for c in COMPS]
+    old = [v.clone() for v in vd]
+    masses = []
+    for k in range(50):
+        masses.append(sb.iterate(vd, fd["p"], old, niter=1, tol=tol, maxit=maxit)["mass_residual"])
+        if masses[-1] <= 1e-2 * masses[0]:
+            break
+    print("time step", ic, "masses", masses, flush=True)
+    assert ic["simple_iters"] == len(masses) < 50
+    for x, y in zip(vc + [fc["p"]], vd + [fd["p"]]):
+        assert torch.equal(x, y)
+    sa.close()
+    sb.close()
