@@ -179,6 +179,55 @@ def time_simple(iters=8, warm=2):
     return out
 
 
+def time_batching(runs=5, warm=2):
+    """The four staggered grids of a time step at reduced scales (the grids of the 96 x 384 x 96
+    step divided by 4 and by 8 along each axis, as the pressure grid divides), convection-diffusion,
+    tol 1e-10: one batched call against the four sets solved one after another, FP64 and FP32 +
+    refinement (median milliseconds; outside the timed steps)."""
+    import numpy as np
+    import torch
+
+    from paper_2211_15605_amd import workloads as W
+    from paper_2211_15605_amd.solver import Context
+
+    dev = torch.device("cuda", 0)
+    out = []
+    for div in (4, 8):
+        nx, ny, nz = 96 // div, 384 // div, 96 // div
+        grids = [W.Grid(nx, ny, nz), W.Grid(nx + 1, ny, nz), W.Grid(nx, ny + 1, nz), W.Grid(nx, ny, nz + 1)]
+        sets = [W.make_set(2, i, grid=g) for i, g in enumerate(grids)]
+        Ds = [[torch.from_numpy(d).to(dev) for d in s_["diags"]] for s_ in sets]
+        row = {"grids": ["%dx%dx%d" % g.shape for g in grids], "cells": int(sum(g.n for g in grids))}
+        for prec in ("fp64", "fp32_refine"):
+            ctx = Context([g.shape for g in grids], precision=prec)
+            c64 = Context([g.shape for g in grids], precision="fp64")
+            bs = [c64.apply(D, torch.from_numpy(s_["x_star"]).to(dev), set_id=i) for i, (D, s_) in
+                  enumerate(zip(Ds, sets))]
+            c64.close()
+            tb, tq, st = [], [], []
+            for r in range(warm + runs):
+                xs = [torch.zeros_like(b) for b in bs]
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, infos = ctx.solve_batched(Ds, bs, xs, tol=1e-10, maxit=1000, check=False)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                for i in range(4):
+                    x = torch.zeros_like(bs[i])
+                    ctx.solve(Ds[i], bs[i], x, tol=1e-10, maxit=1000, set_id=i, check=False)
+                torch.cuda.synchronize()
+                t2 = time.perf_counter()
+                if r >= warm:
+                    tb.append(t1 - t0)
+                    tq.append(t2 - t1)
+                    st.append(max(i["status"] for i in infos))
+            ctx.close()
+            row[prec] = {"batched_ms": 1e3 * float(np.median(tb)), "sequential_ms": 1e3 * float(np.median(tq)),
+                         "speedup": float(np.median(tq) / np.median(tb)), "status_worst": max(st)}
+        out.append(row)
+    return out
+
+
 def time_latency(runs=10, warm=3):
     """The small convection-diffusion system (16^3 cells, tol 1e-10), latency-bound: median
     microseconds per FP64 solve from x0 = 0 (outside the timed steps)."""
@@ -472,7 +521,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-tune", action="store_true", help="use the default launch shapes (no autotuning)")
-    ap.add_argument("--no-simple", action="store_true", help="skip the SIMPLE-iteration and latency sections")
+    ap.add_argument("--no-simple", action="store_true",
+                    help="skip the SIMPLE-iteration, latency and small-batch sections")
     ap.add_argument("--only-simple", action="store_true",
                     help="run only the SIMPLE-iteration section and print it as the JSON line (for profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -493,6 +543,7 @@ def main():
     r = gpu_leg_batched(args) if batched else gpu_leg(args)
     simple = None if args.no_simple else time_simple()
     latency = None if args.no_simple else time_latency()
+    batching = None if args.no_simple else time_batching()
     cpu = None if args.no_cpu_baseline else cpu_leg(args)
     line = {
         "metric": METRIC,
@@ -522,6 +573,7 @@ def main():
         "kernels_fp64_ms": r["kernels_fp64_ms"],
         "simple_bed": simple,
         "latency_cd16": latency,
+        "batching_small": batching,
     }
     print(json.dumps(line))
 
