@@ -241,3 +241,62 @@ def test_time_step_equals_copy_then_iterations(tdev):
         assert torch.equal(x, y)
     sa.close()
     sb.close()
+
+
+def test_widest_box_iteration_matches_oracle(tdev):
+    """nx = 1023 (a 1024-wide u grid, the solver's widest row): one SIMPLE iteration vs the oracle."""
+    torch, dev = tdev
+    box = W.bed_box(1023, 3, 2)
+    st = W.box_state(box, seed=5, noise=0.3, old="draw")
+    d_st = dev_state(torch, dev, st)
+    sb = simple_box(box)
+    vel = [d_st[c] for c in COMPS]
+    info = sb.iterate(vel, d_st["p"], [d_st[c + "0"] for c in COMPS], niter=1, tol=(1e-13, 1e-13),
+                      maxit=(2000, 20000))
+    new, _ = S().simple_iteration(obox(box), st)
+    assert info["status"] == 0, info
+    for c, t in zip(COMPS + ("p",), vel + [d_st["p"]]):
+        assert np.abs(host(t) - new[c]).max() <= 1e-9 * np.abs(new[c]).max(), c
+    sb.close()
+
+
+def test_fp32_refined_momentum_solves_give_the_same_iteration(tdev):
+    """Momentum solves in FP32 with FP64 refinement (to the same tolerance) leave the SIMPLE
+    iteration unchanged to that tolerance."""
+    torch, dev = tdev
+    box = W.bed_box(16, 40, 12, mu=0.05, dt=0.01)
+    st = W.box_state(box, seed=9, noise=0.3, old="draw")
+    res = []
+    for prec in ("fp64", "fp32_refine"):
+        d_st = dev_state(torch, dev, st)
+        sb = simple_box(box, precision=prec)
+        vel = [d_st[c] for c in COMPS]
+        info = sb.iterate(vel, d_st["p"], [d_st[c + "0"] for c in COMPS], niter=2, tol=(1e-11, 1e-11),
+                          maxit=(2000, 5000))
+        assert info["status"] == 0, (prec, info)
+        res.append([host(t) for t in vel + [d_st["p"]]])
+        sb.close()
+    for a, b in zip(*res):
+        assert np.abs(a - b).max() <= 1e-8 * np.abs(b).max()
+
+
+def test_two_time_steps_match_oracle(tdev):
+    """Two time steps of three SIMPLE iterations each (old-time fields taken from the previous
+    step) against the oracle run the same way."""
+    torch, dev = tdev
+    box = W.bed_box(5, 12, 4, mu=0.02, dt=0.005)
+    st = W.box_state(box, seed=13, noise=0.3)
+    d_st = dev_state(torch, dev, st)
+    sb = simple_box(box)
+    vel = [d_st[c] for c in COMPS]
+    ob = obox(box)
+    ost = dict(st)
+    for step in range(2):
+        info = sb.time_step(vel, d_st["p"], max_iter=3, mass_tol=0.0, tol=(1e-13, 1e-13), maxit=(2000, 5000))
+        assert info["status"] == 0 and info["simple_iters"] == 3, info
+        ost = dict(ost, u0=ost["u"].copy(), v0=ost["v"].copy(), w0=ost["w"].copy())
+        for _ in range(3):
+            ost, _ = S().simple_iteration(ob, ost)
+        for c, t in zip(COMPS + ("p",), vel + [d_st["p"]]):
+            assert np.abs(host(t) - ost[c]).max() <= 1e-9 * np.abs(ost[c]).max(), (step, c)
+    sb.close()
