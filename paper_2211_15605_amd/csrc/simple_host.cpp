@@ -281,7 +281,8 @@ int eqsimple_create(eqsimple_ctx **out, const eqs_box *box, int32_t precision, v
         delete c;
         return rc;
     }
-    // 8 arrays per system, d of u, v, w, p', partials, sums (each rounded up to 32 doubles)
+    // 8 arrays per system; d and the old-time velocity of u, v, w; p'; partials; sums
+    // (each rounded up to 32 doubles)
     auto up = [](long v) { return (v + 31) / 32 * 32; };
     long total = 0;
     for (int s = 0; s < 4; ++s) total += 8 * up(c->n[s]);
@@ -317,16 +318,16 @@ int eqsimple_create(eqsimple_ctx **out, const eqs_box *box, int32_t precision, v
     q += up(nparts);
     c->sums = q;
     q += 32;
-    if (q - c->pool != total) {   // the layout above must cover the allocation exactly
-        hipFree(c->pool);
+    if (q - c->pool != total) {   // the layout above covers the allocation exactly (internal check)
+        (void)hipFree(c->pool);
         eqsolve_destroy(c->mom);
         eqsolve_destroy(c->prs);
         delete c;
-        return EQS_ERR_NOMEM;
+        return EQS_ERR_STATE;
     }
     if (hipHostMalloc((void **)&c->sums_host, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
-        hipFree(c->pool);
+        (void)hipFree(c->pool);
         eqsolve_destroy(c->mom);
         eqsolve_destroy(c->prs);
         delete c;
