@@ -35,7 +35,9 @@ struct eqsimple_ctx {
     bool broken = false;
     eqs_ctx *mom = nullptr, *prs = nullptr;
     long n[4] = {0, 0, 0, 0};   // cells of u, v, w, p'
-    int nb[4] = {0, 0, 0, 0};   // blocks of u, v, w, p'
+    int nb[4] = {0, 0, 0, 0};   // blocks of u, v, w, p' at one cell per thread (correction)
+    int nf[4] = {0, 0, 0, 0};   // blocks of the formation kernels
+    int cpb[4] = {0, 0, 0, 0};  // their cells per block
     double *pool = nullptr;     // every work array below, one allocation
     double *a[4][7] = {};       // diagonals: u, v, w, p'
     double *b[4] = {};
@@ -129,12 +131,13 @@ hipError_t enqueue_form_momentum(eqsimple_ctx *c, const double *const vel[3], co
         for (int q = 0; q < 7; ++q) A.a[s][q] = diag[7 * s + q];
         A.b[s] = b[s];
         A.d[s] = d[s];
-        A.nb[s] = c->nb[s];
+        A.nb[s] = c->nf[s];
+        A.cpb[s] = c->cpb[s];
     }
     A.partials = c->partials;
     hipError_t e = launch_form_momentum(A, c->stream);
     if (e != hipSuccess) return e;
-    const int32_t begin[4] = {0, c->nb[0], c->nb[0] + c->nb[1], c->nb[0] + c->nb[1] + c->nb[2]};
+    const int32_t begin[4] = {0, c->nf[0], c->nf[0] + c->nf[1], c->nf[0] + c->nf[1] + c->nf[2]};
     return launch_sum_ranges(c->partials, begin, 3, c->sums, c->stream);
 }
 
@@ -151,9 +154,10 @@ hipError_t enqueue_form_pressure(eqsimple_ctx *c, const double *const d[3], cons
     for (int q = 0; q < 7; ++q) A.a[q] = diag[q];
     A.b = b;
     A.partials = c->partials;
-    hipError_t e = launch_form_pressure(A, c->nb[3], c->stream);
+    A.cpb = c->cpb[3];
+    hipError_t e = launch_form_pressure(A, c->nf[3], c->stream);
     if (e != hipSuccess) return e;
-    const int32_t begin[2] = {0, c->nb[3]};
+    const int32_t begin[2] = {0, c->nf[3]};
     return launch_sum_ranges(c->partials, begin, 1, c->sums + 3, c->stream);
 }
 
@@ -269,7 +273,11 @@ int eqsimple_create(eqsimple_ctx **out, const eqs_box *box, int32_t precision, v
     c->n[1] = nx * (ny + 1) * nz;
     c->n[2] = nx * ny * (nz + 1);
     c->n[3] = nx * ny * nz;
-    for (int s = 0; s < 4; ++s) c->nb[s] = blocks_for(c->n[s]);
+    for (int s = 0; s < 4; ++s) {
+        c->nb[s] = blocks_for(c->n[s]);
+        c->nf[s] = form_blocks(c->n[s]);
+        c->cpb[s] = form_cells_per_block(c->n[s]);
+    }
     const eqs_grid mg[3] = {{box->nx + 1, box->ny, box->nz}, {box->nx, box->ny + 1, box->nz},
                             {box->nx, box->ny, box->nz + 1}};
     const eqs_grid pg = {box->nx, box->ny, box->nz};
@@ -288,7 +296,7 @@ int eqsimple_create(eqsimple_ctx **out, const eqs_box *box, int32_t precision, v
     for (int s = 0; s < 4; ++s) total += 8 * up(c->n[s]);
     for (int s = 0; s < 3; ++s) total += 2 * up(c->n[s]);   // d, old-time velocity
     total += up(c->n[3]);
-    const long nparts = (long)c->nb[0] + c->nb[1] + c->nb[2] + c->nb[3];
+    const long nparts = std::max((long)c->nf[0] + c->nf[1] + c->nf[2], (long)c->nf[3]);
     total += up(nparts) + 32;
     if (hipMalloc((void **)&c->pool, total * sizeof(double)) != hipSuccess) {
         (void)hipGetLastError();

@@ -19,14 +19,15 @@ struct BoxK {
     double Ax, Ay, Az, V, aP0, De, Dn, Dt, rAx, rAy, rAz, rgV, oma;
 };
 
-// logical blocks [0, nb[0]) form u, [nb[0], nb[0]+nb[1]) v, the rest w
+// logical blocks [0, nb[0]) form u, [nb[0], nb[0]+nb[1]) v, the rest w; block q of a grid
+// forms the contiguous cells [q cpb, (q + 1) cpb) of it, 256 at a time
 struct MomArgs {
     BoxK bx;
     const double *u, *v, *w, *p, *u0, *v0, *w0;
     double *a[3][7];
     double *b[3], *d[3];
     double *partials;   // per logical block: sum of squared row residuals
-    int32_t nb[3];
+    int32_t nb[3], cpb[3];
 };
 
 struct PresArgs {
@@ -35,7 +36,22 @@ struct PresArgs {
     double *a[7];
     double *b;
     double *partials;   // per block: sum of b'^2
+    int32_t cpb;        // cells per block (contiguous)
 };
+
+// the formation kernels' blocks per grid: at most kFormBlocks, each over a contiguous run of
+// cells (a multiple of kThreads).  Measured on the 96 x 384 x 96 bed, one cell per thread (the
+// cap above any grid here) forms fastest: runs of 4 or 14 cells per thread took 349 and 344 us
+// for the momentum rows against 330 us; the final sum of the ~42k block partials takes ~6 us.
+constexpr int kFormBlocks = 1 << 22;
+inline int form_cells_per_block(long n) {
+    const long per = (n + kFormBlocks - 1) / kFormBlocks;
+    return (int)((per + kThreads - 1) / kThreads * kThreads);
+}
+inline int form_blocks(long n) {
+    const long cpb = form_cells_per_block(n);
+    return (int)((n + cpb - 1) / cpb);
+}
 
 // logical blocks over u, v, w, p in that order
 struct CorrArgs {

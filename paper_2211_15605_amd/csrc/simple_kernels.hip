@@ -201,11 +201,14 @@ __global__ void __launch_bounds__(kThreads) form_momentum_kernel(MomArgs A) {
     const BoxK &bx = A.bx;
     const int NX = bx.nx + (comp == 0), NY = bx.ny + (comp == 1), NZ = bx.nz + (comp == 2);
     const int n = NX * NY * NZ;
-    const int c = (lb - first) * kThreads + (int)threadIdx.x;
+    const int cpb = A.cpb[comp];
+    const int base = (lb - first) * cpb;
     const Geo g(bx);
     const Idx X{bx.nx, bx.ny, bx.nz};
     double res2 = 0.0;
-    if (c < n) {
+    for (int off = 0; off < cpb; off += kThreads) {
+        const int c = base + off + (int)threadIdx.x;
+        if (c >= n) break;
         const int i = c % NX, q = c / NX, j = q % NY, k = q / NY;
         Row r;
         if (comp == 0) form_u(A, g, X, i, j, k, r);
@@ -226,7 +229,7 @@ __global__ void __launch_bounds__(kThreads) form_momentum_kernel(MomArgs A) {
         if (k + 1 < NZ) ax -= r.a[5] * x[c + PL];
         if (k > 0) ax -= r.a[6] * x[c - PL];
         const double e = r.b - ax;
-        res2 = e * e;
+        res2 += e * e;
     }
     const double s = block_sum(res2);
     if (threadIdx.x == 0) A.partials[lb] = s;
@@ -238,11 +241,12 @@ __global__ void __launch_bounds__(kThreads) form_pressure_kernel(PresArgs A, int
     const BoxK &bx = A.bx;
     const int nx = bx.nx, ny = bx.ny, nz = bx.nz;
     const int n = nx * ny * nz;
-    const int c = lb * kThreads + (int)threadIdx.x;
     const Geo g(bx);
     const Idx X{nx, ny, nz};
     double b2 = 0.0;
-    if (c < n) {
+    for (int off = 0; off < A.cpb; off += kThreads) {
+        const int c = lb * A.cpb + off + (int)threadIdx.x;
+        if (c >= n) break;
         const int i = c % nx, q = c / nx, j = q % ny, k = q / ny;
         const double rh = bx.rho;
         const double aE = i + 1 < nx ? g.rAx * A.du[X.u(i + 1, j, k)] : 0.0;
@@ -264,7 +268,7 @@ __global__ void __launch_bounds__(kThreads) form_pressure_kernel(PresArgs A, int
         A.a[5][c] = aT;
         A.a[6][c] = aB;
         A.b[c] = b;
-        b2 = b * b;
+        b2 += b * b;
     }
     const double s = block_sum(b2);
     if (threadIdx.x == 0) A.partials[lb] = s;
@@ -303,12 +307,23 @@ struct Ranges {
     int32_t begin[5];
 };
 
-__global__ void __launch_bounds__(kThreads) sum_ranges_kernel(const double *partials, Ranges R, int nq, double *out) {
+// one block of kSumThreads: strided partial sums per thread, then a fixed-order tree
+constexpr int kSumThreads = 1024;
+__global__ void __launch_bounds__(kSumThreads) sum_ranges_kernel(const double *partials, Ranges R, int nq,
+                                                                 double *out) {
+    __shared__ double part[kSumThreads / 64];
     for (int q = 0; q < nq; ++q) {
         double s = 0.0;
-        for (int t = R.begin[q] + (int)threadIdx.x; t < R.begin[q + 1]; t += kThreads) s += partials[t];
-        s = block_sum(s);
-        if (threadIdx.x == 0) out[q] = s;
+        for (int t = R.begin[q] + (int)threadIdx.x; t < R.begin[q + 1]; t += kSumThreads) s += partials[t];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+        if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int w = 0; w < kSumThreads / 64; ++w) t += part[w];
+            out[q] = t;
+        }
         __syncthreads();
     }
 }
@@ -341,7 +356,7 @@ hipError_t launch_correct(const CorrArgs &a, hipStream_t s) {
 hipError_t launch_sum_ranges(const double *partials, const int32_t *begin_host, int nq, double *out, hipStream_t s) {
     Ranges R{};
     for (int q = 0; q <= nq && q < 5; ++q) R.begin[q] = begin_host[q];
-    hipLaunchKernelGGL(sum_ranges_kernel, dim3(1), dim3(kThreads), 0, s, partials, R, nq, out);
+    hipLaunchKernelGGL(sum_ranges_kernel, dim3(1), dim3(kSumThreads), 0, s, partials, R, nq, out);
     return hipGetLastError();
 }
 
