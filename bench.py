@@ -228,6 +228,43 @@ def time_batching(runs=5, warm=2):
     return out
 
 
+def time_adjoint(runs=5, warm=2):
+    """The adjoint workload (64^3 convection-diffusion, loss sum(w x), tol 1e-10, FP64): median
+    milliseconds of the forward solve and of the adjoint call (A^T solve + the 7 coefficient
+    gradients), outside the timed steps."""
+    import numpy as np
+    import torch
+
+    from paper_2211_15605_amd import workloads as W
+    from paper_2211_15605_amd.solver import Context
+
+    dev = torch.device("cuda", 0)
+    s = W.make_set(3, 0, with_weights=True)
+    g = s["grid"]
+    D = [torch.from_numpy(d).to(dev) for d in s["diags"]]
+    w = torch.from_numpy(s["w"]).to(dev)
+    ctx = Context([g.shape], precision="fp64")
+    b = ctx.apply(D, torch.from_numpy(s["x_star"]).to(dev))
+    tf, ta = [], []
+    for r in range(warm + runs):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, fi = ctx.solve(D, b, torch.zeros_like(b), tol=1e-10, maxit=1000, check=False)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        gb, gd, ai = ctx.adjoint(D, x, w, tol=1e-10, maxit=1000, check=False)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if r >= warm:
+            tf.append(t1 - t0)
+            ta.append(t2 - t1)
+    ctx.close()
+    return {"workload": "adjoint64: 64x64x64 convection-diffusion, L = sum(w x), tol 1e-10, FP64",
+            "forward_ms": 1e3 * float(np.median(tf)), "forward_iters": fi["iters"],
+            "adjoint_ms": 1e3 * float(np.median(ta)), "adjoint_iters": ai["iters"],
+            "status": max(fi["status"], ai["status"])}
+
+
 def time_latency(runs=10, warm=3):
     """The small convection-diffusion system (16^3 cells, tol 1e-10), latency-bound: median
     microseconds per FP64 solve from x0 = 0 (outside the timed steps)."""
@@ -522,7 +559,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-tune", action="store_true", help="use the default launch shapes (no autotuning)")
     ap.add_argument("--no-simple", action="store_true",
-                    help="skip the SIMPLE-iteration, latency and small-batch sections")
+                    help="skip the SIMPLE-iteration, latency, small-batch and adjoint sections")
     ap.add_argument("--only-simple", action="store_true",
                     help="run only the SIMPLE-iteration section and print it as the JSON line (for profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -544,6 +581,7 @@ def main():
     simple = None if args.no_simple else time_simple()
     latency = None if args.no_simple else time_latency()
     batching = None if args.no_simple else time_batching()
+    adjoint = None if args.no_simple else time_adjoint()
     cpu = None if args.no_cpu_baseline else cpu_leg(args)
     line = {
         "metric": METRIC,
@@ -574,6 +612,7 @@ def main():
         "simple_bed": simple,
         "latency_cd16": latency,
         "batching_small": batching,
+        "adjoint64": adjoint,
     }
     print(json.dumps(line))
 
