@@ -173,8 +173,16 @@ typedef struct {
  * (scaled by gamma) and coarse_sweeps damped-Jacobi sweeps on the coarsest
  * level.  With it a set is iterated on its own (a batched call solves its
  * sets one after another), on the original A, with x updated in place.
+ * The finest level's operator is the system's with its coefficients rounded
+ * to FP32 (arithmetic stays FP64); when a call's matrix is exactly symmetric
+ * (a_W(c) = a_E(c-1), a_S(c) = a_N(c-nx), a_B(c) = a_T(c-P), checked per
+ * call) its finest-level passes read W, S, B from the E, N, T arrays.
+ * Selecting multigrid also re-tiles the context's sets to at most 8 planes
+ * per chunk (the fine-level passes need more blocks than the Jacobi step;
+ * $EQS_MG_KC overrides); selecting Jacobi again restores the tuned tiling.
  * params NULL selects the defaults.  Allocates the level hierarchy (about
- * 1.3 words per cell) here, not in the solves.  Returns EQS_OK, EQS_ERR_ARG
+ * 1.3 words per cell, plus 7 FP32 words per finest cell) here, not in the
+ * solves.  Returns EQS_OK, EQS_ERR_ARG
  * (kind, params, or a context that is not EQS_FP64), EQS_ERR_NOMEM,
  * EQS_ERR_HIP or EQS_ERR_STATE.
  */

@@ -57,6 +57,7 @@ struct SetHost {
     uint32_t *counter;
     // convergence-rate tracking for chunk sizing
     int last_iters;
+    int kc_jacobi;   // planes per chunk of the Jacobi iteration (tuned); 0 until first re-tiling
     double last_log_rr;
 };
 
@@ -676,7 +677,9 @@ hipError_t mg_vcycle(const Run &R, const double *r, double *z, bool gated, hipSt
 // the Galerkin operators of every coarse level of set s, from the diagonals in its table entry
 hipError_t mg_coarsen_all(eqs_ctx *c, int s) {
     const std::vector<MgLevel> &L = c->mg[s];
-    hipError_t e = launch_mg_round0(c->d_desc + s, c->d_mg + (size_t)s * kMgMaxLevels, L[0].n, c->stream);
+    // exact symmetry of this call's matrix (EQS_MG_SYM=0: never assumed)
+    hipError_t e = launch_mg_symcheck(c->d_desc + s, L[0].n, env_int("EQS_MG_SYM", 1) != 0, c->stream);
+    if (e == hipSuccess) e = launch_mg_round0(c->d_desc + s, c->d_mg + (size_t)s * kMgMaxLevels, L[0].n, c->stream);
     for (int l = 0; l + 1 < (int)L.size() && e == hipSuccess; ++l)
         e = launch_mg_coarsen(c->d_desc + s, c->d_mg + (size_t)s * kMgMaxLevels, l, L[l + 1].n, c->stream);
     return e;
@@ -829,12 +832,32 @@ double time_iterations(eqs_ctx *c, int s, double *tmp, int iters) {
     return 1e3 * ms / iters;
 }
 
+// planes per chunk of a multigrid-preconditioned solve: its fine-level passes stream few
+// operands per step, so they need more blocks in flight than the fused Jacobi step (measured on
+// the 128x256x128 pressure-like system, 2 cells per thread: 32 planes 12.3 ms per solve, 16 planes
+// 10.5, 8 planes 9.7, 4 planes 9.9)
+int mg_kc() { return std::max(1, env_int("EQS_MG_KC", 8)); }
+
+// the tiling for the selected preconditioner: the Jacobi iteration's own depth, or at most
+// mg_kc() planes per chunk under multigrid
+void retile_for_precond(eqs_ctx *c) {
+    for (int s = 0; s < c->nsets; ++s) {
+        SetHost &h = c->sets[s];
+        if (h.kc_jacobi <= 0) h.kc_jacobi = h.KC;
+        const int kc = c->precond == EQS_PRECOND_MG ? std::min(mg_kc(), h.kc_jacobi) : h.kc_jacobi;
+        set_tiling(h, c->cpt, kc, h.nflat);
+        fill_desc(c, s);
+    }
+}
+
 int apply_tuning(eqs_ctx *c, int cpt, const std::vector<TuneEntry> &e) {
     c->cpt = cpt;
     for (int s = 0; s < c->nsets; ++s) {
         set_tiling(c->sets[s], cpt, e[s].kc, e[s].nflat);
+        c->sets[s].kc_jacobi = c->sets[s].KC;
         fill_desc(c, s);
     }
+    retile_for_precond(c);
     clear_graphs(c);
     return upload_desc(c, 0, c->nsets);
 }
@@ -984,8 +1007,12 @@ int eqsolve_create(eqs_ctx **out, const eqs_grid *grids, int32_t nsets, int32_t 
 int eqsolve_set_preconditioner(eqs_ctx *c, int32_t kind, const eqs_mg_params *prm) {
     if (!c || c->broken) return EQS_ERR_STATE;
     if (kind == EQS_PRECOND_JACOBI) {
+        const bool was_mg = c->precond == EQS_PRECOND_MG;
         c->precond = EQS_PRECOND_JACOBI;
-        return EQS_OK;
+        if (!was_mg) return EQS_OK;
+        retile_for_precond(c);
+        clear_graphs(c);
+        return upload_desc(c, 0, c->nsets);
     }
     if (kind != EQS_PRECOND_MG || c->precision != EQS_FP64) return EQS_ERR_ARG;
     MgParams p{0.8, 1.0, 30, 512};
@@ -1063,7 +1090,9 @@ int eqsolve_set_preconditioner(eqs_ctx *c, int32_t kind, const eqs_mg_params *pr
     c->mg = std::move(mg);
     c->mgp = p;
     c->precond = EQS_PRECOND_MG;
-    return EQS_OK;
+    retile_for_precond(c);
+    clear_graphs(c);
+    return upload_desc(c, 0, c->nsets);
 }
 
 int eqsolve_debug_precond(eqs_ctx *c, int32_t set, const double *const diag[7], const double *r, double *z,

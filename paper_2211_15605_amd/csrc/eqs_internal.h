@@ -65,6 +65,8 @@ struct SolveState {
                       // 2 y += alpha p + omega s; 3 as 2, plus r = s - omega t, r^ = r (restart);
                       // 4 no y change, r = s + alpha v, r^ = r (restart at the current iterate)
     int32_t weak_outer;  // consecutive refinement steps that reduced ||r|| by less than 2x
+    int32_t sym;      // multigrid iteration: the matrix is exactly symmetric (checked per solve), so
+                      // its finest-level passes read a_W, a_S, a_B as a_E, a_N, a_T of the neighbour
 };
 
 struct SetDesc {

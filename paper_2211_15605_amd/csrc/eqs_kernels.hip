@@ -500,6 +500,29 @@ struct Coef6 {
     }
 };
 
+// a row's six neighbour coefficients; with sym (an exactly symmetric matrix) the W, S and B terms
+// are read from the E, N and T arrays at the neighbouring cell, a_W(c) = a_E(c-1) and so on, so a
+// pass streams four coefficient arrays instead of seven.  Sources and indices are selected, not
+// branched on, so every load stays unconditional.
+template <typename T>
+__device__ __forceinline__ void load_row6(Coef6<T, false> &c, const T *const *a, int idx, int nx, int P, Nb nb,
+                                          bool up, bool dn, bool sym) {
+    const T *wp = sym ? a[1] : a[2], *sp = sym ? a[3] : a[4], *bp = sym ? a[5] : a[6];
+    const int wi = sym ? max(idx - 1, 0) : idx, si = sym ? max(idx - nx, 0) : idx, bi = sym ? max(idx - P, 0) : idx;
+    c.e = ld(a[1], idx);
+    c.w = ld(wp, wi);
+    c.n = ld(a[3], idx);
+    c.s = ld(sp, si);
+    c.t = ld(a[5], idx);
+    c.b = ld(bp, bi);
+    c.e = nb.e ? c.e : T(0);
+    c.w = nb.w ? c.w : T(0);
+    c.n = nb.n ? c.n : T(0);
+    c.s = nb.s ? c.s : T(0);
+    c.t = up ? c.t : T(0);
+    c.b = dn ? c.b : T(0);
+}
+
 // ------------------------------------------------------------------ march skeleton
 //
 // Geometry and pointers are copied into registers at kernel entry: the set
@@ -1883,6 +1906,26 @@ __device__ __forceinline__ double mg_row(const LevCoef &a, int nx, int ny, int n
     return acc;
 }
 
+// exact symmetry of the set's matrix, once per solve: st->sym = on, then cleared by any block
+// that finds a pair inside the grid with a_W(c) != a_E(c-1), a_S(c) != a_N(c-nx) or
+// a_B(c) != a_T(c-P) (coefficients pointing out of the grid are never used)
+__global__ void mg_symflag_kernel(const SetDesc *d, int on) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) d->st->sym = on;
+}
+
+__global__ void __launch_bounds__(kBlock) mg_symcheck_kernel(const SetDesc *d) {
+    const int nx = d->nx, n = d->n, P = d->plane;
+    const double *E = d->a[1], *W = d->a[2], *N = d->a[3], *S = d->a[4], *T = d->a[5], *B = d->a[6];
+    int bad = 0;
+    for (int c = blockIdx.x * kBlock + threadIdx.x; c < n; c += gridDim.x * kBlock) {
+        const int k = c / P, q = c - k * P, j = q / nx, i = q - j * nx;
+        if (i > 0 && ld(W, c) != ld(E, c - 1)) bad = 1;
+        if (j > 0 && ld(S, c) != ld(N, c - nx)) bad = 1;
+        if (k > 0 && ld(B, c) != ld(T, c - P)) bad = 1;
+    }
+    if (__syncthreads_or(bad) && threadIdx.x == 0) atomicAnd(&d->st->sym, 0);
+}
+
 // level 0's FP32 copy of the set's coefficients (round to nearest), once per solve
 __global__ void __launch_bounds__(kBlock) mg_round0_kernel(const SetDesc *d, const MgLevel *lev) {
     const MgLevel F = lev[0];
@@ -2063,6 +2106,7 @@ struct PhMgResid {
     const double *rin;
     double *res;
     double w;
+    bool sym;
     int nx, P, ncell;
     __device__ __forceinline__ Raw load(int idx, int, int) const { return Raw{ld(rin, idx), ld(a[0], idx)}; }
     __device__ __forceinline__ double zval(const Raw &v) const {
@@ -2076,7 +2120,7 @@ struct PhMgResid {
     }
     __device__ __forceinline__ double halo(const Raw &v) const { return zval(v); }
     __device__ __forceinline__ void pre(int idx, Nb nb, bool up, bool dn, Pre &pr) const {
-        pr.c.load(a, idx, nx, P, ncell, nb, up, dn);
+        load_row6(pr.c, a, idx, nx, P, nb, up, dn, sym);
     }
     __device__ __forceinline__ void center(int idx, const Pre &pr, const Aux &ax, double xc, double xE, double xW,
                                            double xN, double xS, double xT, double xB, double (&)[NV]) {
@@ -2102,6 +2146,7 @@ struct PhMgProlong {
     const double *rin, *e;
     double *zout;
     double w, g;
+    bool sym;
     int nx, P, ncell, cx, cy;
     __device__ __forceinline__ Raw load(int idx, int q, int k) const {
         const int j = q / nx, i = q - j * nx;
@@ -2118,7 +2163,7 @@ struct PhMgProlong {
     }
     __device__ __forceinline__ double halo(const Raw &v) const { return zval(v); }
     __device__ __forceinline__ void pre(int idx, Nb nb, bool up, bool dn, Pre &pr) const {
-        pr.c.load(a, idx, nx, P, ncell, nb, up, dn);
+        load_row6(pr.c, a, idx, nx, P, nb, up, dn, sym);
     }
     __device__ __forceinline__ void center(int idx, const Pre &pr, const Aux &ax, double xc, double xE, double xW,
                                            double xN, double xS, double xT, double xB, double (&)[NV]) {
@@ -2142,6 +2187,7 @@ __global__ void __launch_bounds__(kBlock) mg_resid0_kernel(LaunchSets ls, const 
     if (gated && !d.st->active) return;
     PhMgResid ph;
     for (int k = 0; k < 7; ++k) ph.a[k] = lev[0].a32[k];
+    ph.sym = d.st->sym != 0;
     ph.rin = rin;
     ph.res = res;
     ph.w = prm.omega;
@@ -2160,6 +2206,7 @@ __global__ void __launch_bounds__(kBlock) mg_prolong0_kernel(LaunchSets ls, cons
     if (gated && !d.st->active) return;
     PhMgProlong ph;
     for (int k = 0; k < 7; ++k) ph.a[k] = lev[0].a32[k];
+    ph.sym = d.st->sym != 0;
     ph.rin = rin;
     ph.e = lev[1].z;
     ph.zout = zout;
@@ -2256,12 +2303,13 @@ struct PhPc {
     const double *x, *wv;  // operand; second vector of the sums ((r^) for v, (s) for t)
     double *y;
     int nx, P, ncell;
-    bool tstep;            // false: v = A p^, sum (r^, v); true: t = A s^, sums (t,s), (t,t), (s,s)
+    bool tstep;
+    bool sym;              // exactly symmetric matrix: W, S, B read as E, N, T of the neighbour            // false: v = A p^, sum (r^, v); true: t = A s^, sums (t,s), (t,t), (s,s)
     __device__ __forceinline__ Raw load(int idx, int, int) const { return Raw{ld(x, idx)}; }
     __device__ __forceinline__ double own(const Raw &w, int, Aux &) { return w.x; }
     __device__ __forceinline__ double halo(const Raw &w) const { return w.x; }
     __device__ __forceinline__ void pre(int idx, Nb nb, bool up, bool dn, Pre &pr) const {
-        pr.c.load(a, idx, nx, P, ncell, nb, up, dn);
+        load_row6(pr.c, a, idx, nx, P, nb, up, dn, sym);
         pr.ap = ld(a[0], idx);
         pr.w = ld(wv, idx);
     }
@@ -2288,6 +2336,7 @@ __global__ void __launch_bounds__(kBlock) pc_prod_kernel(LaunchSets ls, int tste
     PhPc ph;
     for (int k = 0; k < 7; ++k) ph.a[k] = d.a[k];
     ph.tstep = tstep != 0;
+    ph.sym = st_->sym != 0;
     ph.x = ph.tstep ? d.v[1] : d.p[1];
     ph.wv = ph.tstep ? d.s1 : d.rh;
     ph.y = ph.tstep ? d.t : d.v[0];
@@ -2386,6 +2435,14 @@ hipError_t launch_small(const LaunchSets &ls, int max_n, bool trans, hipStream_t
 }
 
 static dim3 mg_grid(int n) { return dim3((unsigned)std::max(1, std::min((n + kBlock - 1) / kBlock, 8192))); }
+
+hipError_t launch_mg_symcheck(const SetDesc *d, int n, int on, hipStream_t stream) {
+    hipLaunchKernelGGL(mg_symflag_kernel, dim3(1), dim3(64), 0, stream, d, on);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !on) return e;
+    hipLaunchKernelGGL(mg_symcheck_kernel, mg_grid(n), dim3(kBlock), 0, stream, d);
+    return hipGetLastError();
+}
 
 hipError_t launch_mg_round0(const SetDesc *d, const MgLevel *lev, int n, hipStream_t stream) {
     hipLaunchKernelGGL(mg_round0_kernel, mg_grid(n), dim3(kBlock), 0, stream, d, lev);

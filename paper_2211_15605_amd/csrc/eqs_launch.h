@@ -35,6 +35,7 @@ enum Kern {
 };
 
 // multigrid kernels of set `set` (d: its device table entry, lev: its device level table)
+hipError_t launch_mg_symcheck(const SetDesc *d, int n, int on, hipStream_t stream);
 hipError_t launch_mg_round0(const SetDesc *d, const MgLevel *lev, int n, hipStream_t stream);
 hipError_t launch_mg_coarsen(const SetDesc *d, const MgLevel *lev, int l, int nc, hipStream_t stream);
 // V-cycle: restriction from level l to l+1 (nc = cells of level l+1); rin = level l's right-hand side

@@ -550,3 +550,61 @@ def test_mg_config1_full_size(torch_dev, orc):
     xg = host(x)
     assert orc.rel_residual(g.shape, diags, b, xg) <= 1e-10
     assert np.max(np.abs(xg - xs)) <= orc.forward_error_certificate(g.shape, diags, b, xg) * (1 + 1e-6)
+
+
+def _mg_solve_with_sym(torch, dev, g, diags, b, sym_env):
+    old = os.environ.get("EQS_MG_SYM")
+    os.environ["EQS_MG_SYM"] = sym_env
+    try:
+        ctx = context([g.shape])
+        ctx.set_preconditioner("mg", gamma=1.6, coarse_cells=64)
+        x, info = ctx.solve(dev_arrays(torch, dev, diags), dev_arrays(torch, dev, [b])[0], tol=1e-11, maxit=500)
+        return host(x), info
+    finally:
+        if old is None:
+            os.environ.pop("EQS_MG_SYM", None)
+        else:
+            os.environ["EQS_MG_SYM"] = old
+
+
+def test_mg_symmetric_reads_are_exact_and_detected(torch_dev, orc):
+    """An exactly symmetric matrix (the pressure-like recipe) lets the multigrid iteration read
+    a_W, a_S, a_B as a_E, a_N, a_T of the neighbour: the same values, so the same bits as with that
+    off.  One perturbed coefficient makes the matrix non-symmetric: the check must see it (else the
+    iteration would run on another operator and the true residual would not meet tol)."""
+    torch, dev = torch_dev
+    g, diags, b, xs = manufactured(orc, 1, grid=W.Grid(24, 40, 20))
+    x1, i1 = _mg_solve_with_sym(torch, dev, g, diags, b, "1")
+    x0, i0 = _mg_solve_with_sym(torch, dev, g, diags, b, "0")
+    assert i1 == i0 and np.array_equal(x1, x0)
+    assert orc.rel_residual(g.shape, diags, b, x1) <= 1e-11
+    pert = [d.copy() for d in diags]
+    c = 5 + g.nx * (7 + g.ny * 9)           # an interior cell
+    pert[2][c] *= 1.001                     # a_W(c) != a_E(c - 1)
+    bp = orc.apply(g.shape, pert, xs)
+    x1, i1 = _mg_solve_with_sym(torch, dev, g, pert, bp, "1")
+    x0, i0 = _mg_solve_with_sym(torch, dev, g, pert, bp, "0")
+    assert i1["status"] == 0 and i1 == i0 and np.array_equal(x1, x0)
+    assert orc.rel_residual(g.shape, pert, bp, x1) <= 1e-11
+
+
+def test_preconditioner_switch_restores_the_jacobi_tiling(torch_dev, orc):
+    """Selecting multigrid re-tiles the sets (fewer planes per chunk for its fine-level passes);
+    going back to Jacobi restores the Jacobi iteration's own tiling, so its solves repeat bit for
+    bit (same tiles, same reduction order)."""
+    torch, dev = torch_dev
+    g, diags, b, xs = manufactured(orc, 1, grid=W.Grid(40, 64, 48))
+    ctx = context([g.shape], env=dict(EQS_KC=16))
+    D = dev_arrays(torch, dev, diags)
+    bd = dev_arrays(torch, dev, [b])[0]
+    lay0 = ctx.layout()
+    x0, i0 = ctx.solve(D, bd, tol=1e-10, maxit=2000)
+    ctx.set_preconditioner("mg")
+    lay_mg = ctx.layout()
+    assert lay_mg["kc"] == 8 and lay_mg["cpt"] == lay0["cpt"], (lay0, lay_mg)
+    xm, im = ctx.solve(D, bd, tol=1e-10, maxit=500)
+    assert orc.rel_residual(g.shape, diags, b, host(xm)) <= 1e-10
+    ctx.set_preconditioner("jacobi")
+    assert ctx.layout()["kc"] == lay0["kc"] == 16
+    x1, i1 = ctx.solve(D, bd, tol=1e-10, maxit=2000)
+    assert i1 == i0 and np.array_equal(host(x1), host(x0))
