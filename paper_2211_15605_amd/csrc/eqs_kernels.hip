@@ -2222,37 +2222,20 @@ __global__ void __launch_bounds__(kBlock) mg_prolong0_kernel(LaunchSets ls, cons
 }
 
 // level 1's right-hand side: the sum of res over each aggregate of level 0, in
-// cell-index order (eight lanes per aggregate, as in mg_restrict_kernel)
+// cell-index order (i fastest, then j, then k), one thread per aggregate
 __global__ void __launch_bounds__(kBlock) mg_aggregate_kernel(const SetDesc *d, const MgLevel *lev, const double *res,
                                                               int gated) {
 #pragma clang fp contract(off)
     if (gated && !d->st->active) return;
     const MgLevel F = lev[0], C = lev[1];
     const int nx = F.nx, ny = F.ny, nz = F.nz, cx = C.nx, cy = C.ny;
-    const int g8 = threadIdx.x & 7, di = g8 & 1, dj = (g8 >> 1) & 1, dk = g8 >> 2;
-    const int stride = (int)(gridDim.x * kBlock) >> 3;
-    for (int w0 = (int)(blockIdx.x * kBlock + (threadIdx.x & ~63)) >> 3; w0 < C.n; w0 += stride) {
-        const int cc = w0 + (int)((threadIdx.x & 63) >> 3);
-        const bool inC = cc < C.n;
-        const int ccl = min(cc, C.n - 1);
-        const int I = ccl % cx, t = ccl / cx, J = t % cy, K = t / cy;
-        const int i = 2 * I + di, j = 2 * J + dj, k = 2 * K + dk;
-        const bool ok = inC && i < nx && j < ny && k < nz;
-        const double q = ok ? ld(res, i + nx * (j + ny * k)) : 0.0;
-        double qs[8];
-        int oks[8];
-#pragma unroll
-        for (int m = 0; m < 8; ++m) {
-            qs[m] = __shfl(q, m, 8);
-            oks[m] = __shfl(ok ? 1 : 0, m, 8);
-        }
-        if (g8 == 0 && inC) {
-            double sum = 0.0;
-#pragma unroll
-            for (int m = 0; m < 8; ++m)
-                if (oks[m]) sum += qs[m];
-            st(C.r, cc, sum);
-        }
+    for (int cc = blockIdx.x * kBlock + threadIdx.x; cc < C.n; cc += gridDim.x * kBlock) {
+        const int I = cc % cx, t = cc / cx, J = t % cy, K = t / cy;
+        double sum = 0.0;
+        for (int k = 2 * K; k < min(2 * K + 2, nz); ++k)
+            for (int j = 2 * J; j < min(2 * J + 2, ny); ++j)
+                for (int i = 2 * I; i < min(2 * I + 2, nx); ++i) sum += ld(res, i + nx * (j + ny * k));
+        st(C.r, cc, sum);
     }
 }
 
@@ -2555,7 +2538,7 @@ hipError_t launch_mg_fine(const LaunchSets &ls, int ntiles, int cpt, int max_nx,
 
 hipError_t launch_mg_aggregate(const SetDesc *d, const MgLevel *lev, int nc, const double *res, bool gated,
                                hipStream_t stream) {
-    hipLaunchKernelGGL(mg_aggregate_kernel, mg_grid(8 * nc), dim3(kBlock), 0, stream, d, lev, res, gated ? 1 : 0);
+    hipLaunchKernelGGL(mg_aggregate_kernel, mg_grid(nc), dim3(kBlock), 0, stream, d, lev, res, gated ? 1 : 0);
     return hipGetLastError();
 }
 
