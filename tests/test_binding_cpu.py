@@ -72,4 +72,6 @@ def test_simple_box_argument_errors_without_device():
     L = B.load()
     assert L.eqsimple_form_momentum(None, None, None, None, None, None, None, None) == B.EQS_ERR_STATE
     assert L.eqsimple_iterate(None, None, None, None, 1, None, None, None) == B.EQS_ERR_STATE
+    assert L.eqsimple_step(None, None, None, 1, 0.0, None, None, None) == B.EQS_ERR_STATE
+    assert L.eqsimple_set_pressure_preconditioner(None, 1, None) == B.EQS_ERR_STATE
     assert L.eqsimple_destroy(None) == B.EQS_OK
