@@ -35,8 +35,19 @@ WORDS = {"k1": 12, "k2": 9, "k3": 8}
 # the single-sync step (one launch): reads s, t, p, v of the previous step, y, r^, f and six
 # coefficients; writes y, p, v, s, t (18 words per cell and step)
 WORDS["fused"] = 18
+# its symmetric form (exactly symmetric matrices): a_E, a_N, a_T and 1/a_P in place of the six
+# scaled coefficients (16 words)
+WORDS["fused_sym"] = 16
 # algorithmic HBM words per cell-iteration of each iteration scheme (reductions per step -> words)
 STEP_WORDS = {1: 18, 3: 29}
+
+
+def step_words(syncs, symmetric):
+    """(dominant kernel's words per cell, words per cell-iteration) of the scheme that ran."""
+    if syncs == 1:
+        w = WORDS["fused_sym" if symmetric else "fused"]
+        return w, w
+    return WORDS["k1"], STEP_WORDS[syncs]
 
 
 def kernel_source_digest():
@@ -365,9 +376,10 @@ def gpu_leg(args):
     # the library counts only launches that did work (not the few enqueued past convergence)
     k1_cnt, k1_ms = kstats[kern]
     k1_avg_ms = k1_ms / k1_cnt
-    k1_bytes = WORDS[kern] * 8 * n
+    form_sym = bool(rec[-1][2]["symmetric"])
+    kw, sw = step_words(syncs, form_sym)
+    k1_bytes = kw * 8 * n
     achieved = k1_bytes / (k1_avg_ms * 1e-3) / 1e9
-    sw = STEP_WORDS[syncs]
     err64 = float(torch.max(torch.abs(x64 - xs)))
     err32 = float(torch.max(torch.abs(x32 - xs)))
     tmg, (xmg, img), mgp = time_mg(Context, [g.shape], lambda cm: cm.solve(D, b, torch.zeros_like(b), tol=tol,
@@ -387,12 +399,14 @@ def gpu_leg(args):
                            "rel_res": img["rel_res"],
                            "max_abs_err_vs_xstar": float(torch.max(torch.abs(xmg - xs))),
                            "speedup_vs_fp64_jacobi": t64 / tmg, "params": mgp},
-        "roofline": {"bound": "hbm", "kernel": kern + "_fp64", "achieved": achieved, "peak": HBM_PEAK_GBS,
+        "roofline": {"bound": "hbm", "kernel": kern + ("_sym" if form_sym and syncs == 1 else "") + "_fp64",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(args.config, kern),
-                     "bytes_per_launch": k1_bytes, "words_per_cell": WORDS[kern], "mean_launch_ms": k1_avg_ms,
+                     "bytes_per_launch": k1_bytes, "words_per_cell": kw, "mean_launch_ms": k1_avg_ms,
                      "launches": k1_cnt},
         "syncs_per_iteration": syncs,
+        "symmetric_form": {"fp64": form_sym, "fp32_refine": bool(rec[-1][3]["symmetric"])},
         "kernels_fp64_ms": {k: {"launches": v[0], "mean_ms": v[1] / v[0]} for k, v in kstats.items()},
         "layout": c64.layout(),
         "cells": n,
@@ -455,7 +469,6 @@ def gpu_leg_batched(args):
         step(None)
     syncs = c64.layout()["syncs"]
     kern = "fused" if syncs == 1 else "k1"
-    sw = STEP_WORDS[syncs]
     c64.profile([kern], every=1)
     rec = []
     torch.cuda.synchronize()
@@ -479,7 +492,10 @@ def gpu_leg_batched(args):
     t32 = float(np.mean([r[1] for r in rec]))
     ci64 = sum(n * inf["iters"] for n, inf in zip(n_all, rec[-1][2]))
     ci32 = sum(n * inf["iters"] for n, inf in zip(n_all, rec[-1][3]))
-    k1_bytes_total = sum(WORDS[kern] * 8 * n * inf["iters"] for n, inf in zip(n_all, rec[-1][2])) * len(rec)
+    # a batched launch takes the symmetric form only when every set does
+    form_sym = all(i["symmetric"] for i in rec[-1][2])
+    kw, sw = step_words(syncs, form_sym)
+    k1_bytes_total = sum(kw * 8 * n * inf["iters"] for n, inf in zip(n_all, rec[-1][2])) * len(rec)
     achieved = k1_bytes_total / (k1_ms * 1e-3) / 1e9
     err64 = max(float(torch.max(torch.abs(x - xs))) for x, xs in zip(x64, xss))
     tmg, (xmg, img), mgp = time_mg(Context, grids, lambda cm: cm.solve_batched(Ds, bs, tol=tol, maxit=maxit, check=False),
@@ -506,7 +522,7 @@ def gpu_leg_batched(args):
                            "speedup_vs_fp64_jacobi_batched": t64 / tmg, "params": mgp},
         "roofline": {"bound": "hbm", "kernel": kern + "_fp64 (batched launch)", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "bytes": "%d words x 8 B per active cell, summed over sets" % WORDS[kern],
+                     "bytes": "%d words x 8 B per active cell, summed over sets" % kw,
                      "launches": k1_cnt, "mean_launch_ms": k1_ms / max(k1_cnt, 1)},
         "syncs_per_iteration": syncs,
         "kernels_fp64_ms": {kern: {"launches": k1_cnt, "mean_ms": k1_ms / max(k1_cnt, 1)}},

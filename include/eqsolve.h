@@ -73,9 +73,20 @@ typedef struct {
     int32_t status;  /* EQS_* of this set */
     int32_t iters;   /* BiCGSTAB iterations (inner iterations for the FP32 forms) */
     int32_t outer;   /* refinement steps (FP32 forms), restarts (FP64) */
-    int32_t pad;
+    int32_t flags;   /* EQS_INFO_* bits describing how the solve ran */
     double rel_res;  /* ||b - A x||_2 / ||b||_2 of the returned x, in FP64 */
 } eqs_info;
+
+/*
+ * eqs_info.flags: EQS_INFO_SYMMETRIC -- the matrix was found exactly symmetric
+ * (a_W(c) = a_E(c-1), a_S(c) = a_N(c-nx), a_B(c) = a_T(c-nx*ny) wherever both
+ * cells are in the grid; checked once per solve, on the device) and the
+ * single-sync iteration ran in its symmetric form, reading a_E, a_N, a_T and
+ * 1/a_P instead of six scaled coefficients.  Set for a solve whose launch held
+ * only such sets (in a batched call: every set); EQS_SYM=0 in the environment
+ * at eqsolve_create turns the form off.
+ */
+enum { EQS_INFO_SYMMETRIC = 1 };
 
 /*
  * Create a context for nsets equation sets with the given grids (the sets

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libeqsolve.so")
 EQS_FP64, EQS_FP32_REFINE, EQS_FP32 = 0, 1, 2
 EQS_OK, EQS_NOT_CONVERGED, EQS_BREAKDOWN, EQS_NONFINITE = 0, 1, 2, 3
 EQS_ERR_ARG, EQS_ERR_NOMEM, EQS_ERR_HIP, EQS_ERR_STATE = -1, -2, -3, -4
+EQS_INFO_SYMMETRIC = 1
 PRECISIONS = {"fp64": EQS_FP64, "fp32_refine": EQS_FP32_REFINE, "fp32": EQS_FP32}
 
 # symbols declared in include/eqsolve.h
@@ -65,10 +66,11 @@ class EqsSimpleInfo(ctypes.Structure):
 
 class EqsInfo(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("outer", ctypes.c_int32),
-                ("pad", ctypes.c_int32), ("rel_res", ctypes.c_double)]
+                ("flags", ctypes.c_int32), ("rel_res", ctypes.c_double)]
 
     def as_dict(self):
-        return {"status": self.status, "iters": self.iters, "outer": self.outer, "rel_res": self.rel_res}
+        return {"status": self.status, "iters": self.iters, "outer": self.outer, "rel_res": self.rel_res,
+                "symmetric": bool(self.flags & EQS_INFO_SYMMETRIC)}
 
 
 _lock = threading.Lock()

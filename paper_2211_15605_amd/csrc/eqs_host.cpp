@@ -50,7 +50,9 @@ struct SetHost {
     double *r, *rh, *p[2], *v[2], *t, *y;
     double *as[6];
     double *s1, *t1, *f;
+    double *dinv;
     float *as32[6];
+    float *sym32[4];
     float *r32, *rh32, *p32[2], *v32[2], *t32, *d32;
     float *s1_32, *t1_32, *f32;
     double *partials;
@@ -58,6 +60,7 @@ struct SetHost {
     // convergence-rate tracking for chunk sizing
     int last_iters;
     int kc_jacobi;   // planes per chunk of the Jacobi iteration (tuned); 0 until first re-tiling
+    bool form_sym;   // the last solve ran the symmetric form of the single-sync step
     double last_log_rr;
 };
 
@@ -96,6 +99,8 @@ struct eqs_ctx {
     // iteration scheme: one fused launch and one reduction per step (true), or
     // three launches and three reductions per step (false)
     bool sync1 = true;
+    // exactly symmetric sets take the symmetric form of the single-sync step (EQS_SYM=0: never)
+    int sym_on = 1;
     std::vector<SetHost> sets;
     SetDesc *h_desc = nullptr;
     SetDesc *d_desc = nullptr;
@@ -111,11 +116,12 @@ struct eqs_ctx {
     int64_t kseen[2 * 32] = {0};  // launches of each kind since profiling started
     int kpos[2 * 32] = {0};       // launches of each kind since the last readback
     std::vector<int> ev_pos;      // position of each timed launch since the last readback
-    // captured iteration chunks: (first set, set count, transpose, fp32) -> graphs of 2^k iterations
+    // captured iteration chunks: (first set, set count, transpose, fp32, symmetric form) -> graphs
+    // of 2^k iterations
     bool use_graphs = true;
     bool use_small = true;      // one-block persistent solve for tiny FP64 sets (EQS_SMALL=0 disables)
     hipStream_t capture_stream = nullptr;
-    std::map<std::tuple<int, int, bool, bool>, std::array<hipGraphExec_t, 9>> graphs;
+    std::map<std::tuple<int, int, bool, bool, bool>, std::array<hipGraphExec_t, 9>> graphs;
     bool trace = false;         // print the state at every readback (EQS_TRACE=1)
     std::vector<hipEvent_t> ev_pool;
     std::vector<int> ev_kind;     // pending (start, stop) pairs: kind per pair
@@ -210,6 +216,8 @@ void fill_desc(eqs_ctx *c, int s) {
     d.f = h.f;
     for (int k = 0; k < 6; ++k) d.as[k] = h.as[k];
     for (int k = 0; k < 6; ++k) d.as32[k] = h.as32[k];
+    d.dinv = h.dinv;
+    for (int k = 0; k < 4; ++k) d.sym32[k] = h.sym32[k];
     d.r32 = h.r32;
     d.rh32 = h.rh32;
     d.p32[0] = h.p32[0];
@@ -256,6 +264,7 @@ struct Run {
     int ntiles, nflat;
     int max_nx;
     bool fp32, trans;
+    bool sym = false;   // every set exactly symmetric: the symmetric form of the single-sync step
     long guard_limit;
 
     int L(Kern k, const double *x = nullptr, double *y = nullptr, int arg = 0, bool f32 = false) {
@@ -333,7 +342,7 @@ struct Run {
         if (c->profile_mask || !c->use_graphs) {
             for (int i = 0; i < C; ++i) {
                 if (c->sync1) {
-                    if ((rc = L(K_FUSED, nullptr, nullptr, 0, f32))) return rc;
+                    if ((rc = L(K_FUSED, nullptr, nullptr, sym ? 1 : 0, f32))) return rc;
                     continue;
                 }
                 if ((rc = L(K_K1, nullptr, nullptr, 0, f32))) return rc;
@@ -343,7 +352,7 @@ struct Run {
             return 0;
         }
         const int per_iter = c->sync1 ? 1 : 3;
-        auto &slots = c->graphs[std::make_tuple(first, count, trans, f32)];
+        auto &slots = c->graphs[std::make_tuple(first, count, trans, f32, sym && c->sync1)];
         for (int b = 8; b >= 0; --b) {
             while (C >= (1 << b)) {
                 if (!slots[b]) {
@@ -353,7 +362,7 @@ struct Run {
                     for (int i = 0; i < (1 << b) && ok; ++i) {
                         if (c->sync1) {
                             ok = launch_kernel(K_FUSED, ls, ntiles, nflat, c->cpt, max_nx, f32, trans,
-                                               c->capture_stream, nullptr, nullptr, 0) == hipSuccess;
+                                               c->capture_stream, nullptr, nullptr, sym ? 1 : 0) == hipSuccess;
                             continue;
                         }
                         for (Kern k : {K_K1, K_K2, K_K3})
@@ -386,6 +395,12 @@ struct Run {
         return 0;
     }
     const SolveState &st(int i) const { return c->h_state[first + i]; }
+    // after the setup's readback: the symmetric form when every set of the run takes it
+    void pick_form() {
+        sym = count > 0 && c->sync1;
+        for (int i = 0; i < count; ++i) sym = sym && st(i).sym != 0;
+        for (int i = 0; i < count; ++i) c->sets[first + i].form_sym = sym;
+    }
     bool all_done() const {
         for (int i = 0; i < count; ++i)
             if (!st(i).done) return false;
@@ -459,10 +474,12 @@ int run_fp64(Run &R) {
         return R.readback();
     }
     const bool s1 = R.c->sync1;
-    if ((rc = R.L(K_SCALE))) return rc;  // coefficients of A D^-1 (A^T D^-1), once per solve
+    // coefficients of A D^-1 (A^T D^-1) and 1/a_P, once per solve; symmetry check
+    if ((rc = R.L(K_SCALE, nullptr, nullptr, R.c->sym_on))) return rc;
     if ((rc = R.L(K_SETUP))) return rc;
     if (s1 && (rc = R.L(K_FSETUP))) return rc;
     if ((rc = R.readback())) return rc;
+    R.pick_form();
     R.reset_rate();
     for (long guard = 0;; ++guard) {
         if (guard > R.guard_limit) { R.c->broken = true; return EQS_ERR_STATE; }
@@ -492,10 +509,11 @@ int run_fp64(Run &R) {
 int run_fp32(Run &R) {
     int rc;
     const bool s1 = R.c->sync1;
-    if ((rc = R.L(K_CAST))) return rc;
+    if ((rc = R.L(K_CAST, nullptr, nullptr, R.c->sym_on))) return rc;
     if ((rc = R.L(K_OUTER))) return rc;
     if (s1 && (rc = R.L(K_FSETUP, nullptr, nullptr, 0, true))) return rc;
     if ((rc = R.readback())) return rc;
+    R.pick_form();
     R.reset_rate();
     for (long guard = 0;; ++guard) {
         if (guard > R.guard_limit) { R.c->broken = true; return EQS_ERR_STATE; }
@@ -531,6 +549,7 @@ Run make_run(eqs_ctx *c, int first, int count, bool trans) {
     for (int i = 0; i < count; ++i) R.max_nx = std::max(R.max_nx, c->sets[first + i].g.nx);
     R.fp32 = false;
     R.trans = trans;
+    for (int i = 0; i < count; ++i) c->sets[first + i].form_sym = false;
     // every host loop turn either runs >= 1 iteration or one housekeeping
     // step that only follows an iteration, so 2*maxit + slack turns suffice
     long mx = 0;
@@ -545,7 +564,7 @@ void write_info(eqs_ctx *c, int s, eqs_info *info) {
     info->status = st.status;
     info->iters = st.iters;
     info->outer = (st.mode == MODE_REFINE || st.mode == MODE_FP32) ? st.outer : st.restarts;
-    info->pad = 0;
+    info->flags = c->sets[s].form_sym ? EQS_INFO_SYMMETRIC : 0;
     if (st.zero_rhs)
         info->rel_res = 0.0;
     else if (st.bb_outer > 0)
@@ -803,6 +822,7 @@ double time_iterations(eqs_ctx *c, int s, double *tmp, int iters) {
     const int saved = c->profile_mask;
     c->profile_mask = 0;
     if (f32) {
+        // the general form of the step (the synthetic system is symmetric)
         if (R.L(K_CAST) || R.L(K_OUTER)) return -1.0;
     } else if (R.L(K_SCALE) || R.L(K_SETUP)) {
         return -1.0;
@@ -895,6 +915,7 @@ int eqsolve_create(eqs_ctx **out, const eqs_grid *grids, int32_t nsets, int32_t 
     while (cpt > 1 && march_lds_bytes(cpt, max_nx, 8) > kMaxLds) cpt /= 2;
     // single-sync iteration (EQS_SYNC=3 selects the three-launch one) where its
     // wider planes fit in LDS; it may need the narrower segment
+    c->sym_on = env_int("EQS_SYM", 1) != 0 ? 1 : 0;
     c->sync1 = env_int("EQS_SYNC", 1) != 3 && halo_slots(max_nx) > 0 && halo_slots(max_nx) <= 4;
     if (c->sync1) {
         int fc = cpt;
@@ -937,8 +958,8 @@ int eqsolve_create(eqs_ctx **out, const eqs_grid *grids, int32_t nsets, int32_t 
         choose_tiling(h, cpt);
         if (tuned_ok) set_tiling(h, tuned_cpt, tuned[s].kc, tuned[s].nflat);
         base[s] = bytes;
-        bytes += 17 * align_up((size_t)h.n * 8);   // r, r^, p[2], v[2], t, y, 6 scaled coefficients, s1, t1, f
-        if (f32) bytes += 17 * align_up((size_t)h.n * 4);  // the same in FP32 (d = the inner iterate)
+        bytes += 18 * align_up((size_t)h.n * 8);   // r, r^, p[2], v[2], t, y, 6 scaled coefficients, s1, t1, f, 1/a_P
+        if (f32) bytes += 21 * align_up((size_t)h.n * 4);  // the same in FP32 (d = the inner iterate), a_E, a_N, a_T
         bytes += align_up(max_partials(h) * kMaxRed * 8);
         bytes += kAlign;  // counter
     }
@@ -971,7 +992,9 @@ int eqsolve_create(eqs_ctx **out, const eqs_grid *grids, int32_t nsets, int32_t 
         h.s1 = (double *)take((size_t)h.n * 8);
         h.t1 = (double *)take((size_t)h.n * 8);
         h.f = (double *)take((size_t)h.n * 8);
+        h.dinv = (double *)take((size_t)h.n * 8);
         if (f32) {
+            for (int k = 0; k < 4; ++k) h.sym32[k] = (float *)take((size_t)h.n * 4);
             for (int k = 0; k < 6; ++k) h.as32[k] = (float *)take((size_t)h.n * 4);
             h.r32 = (float *)take((size_t)h.n * 4);
             h.rh32 = (float *)take((size_t)h.n * 4);

@@ -65,8 +65,9 @@ struct SolveState {
                       // 2 y += alpha p + omega s; 3 as 2, plus r = s - omega t, r^ = r (restart);
                       // 4 no y change, r = s + alpha v, r^ = r (restart at the current iterate)
     int32_t weak_outer;  // consecutive refinement steps that reduced ||r|| by less than 2x
-    int32_t sym;      // multigrid iteration: the matrix is exactly symmetric (checked per solve), so
-                      // its finest-level passes read a_W, a_S, a_B as a_E, a_N, a_T of the neighbour
+    int32_t sym;      // the matrix is exactly symmetric (checked per solve): the single-sync step and
+                      // the multigrid finest-level passes read a_W, a_S, a_B as a_E, a_N, a_T of the
+                      // neighbour
 };
 
 struct SetDesc {
@@ -90,6 +91,11 @@ struct SetDesc {
     // the adjoint, those of A^T D^-1) and y = D x is its iterate.
     double *r, *rh, *p[2], *v[2], *t, *y;
     double *as[6];
+    // symmetric matrices: 1/a_P, with which the single-sync step forms the products of
+    // A D^-1 from the caller's a_E, a_N, a_T (FP32 forms: sym32 = those three rounded
+    // to FP32, then 1/a_P rounded)
+    double *dinv;
+    float *sym32[4];
     // single-sync iteration: s and t double-buffered with r (slot 0 of s) and
     // t (slot 0 of t); f = M^T r^ with M the scaled operator
     double *s1, *t1, *f;

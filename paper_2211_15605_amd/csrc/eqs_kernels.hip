@@ -381,9 +381,11 @@ struct FinFused {
     }
 };
 
-struct FinCast {  // sums: (b,b), #bad
+struct FinCast {  // sums: (b,b), #bad, #asymmetric rows
     const SetDesc *d;
+    int sym_on;
     __device__ void operator()(SolveState *st, const double *s) const {
+        st->sym = (sym_on && s[2] == 0.0) ? 1 : 0;
         st->mode = d->mode;
         st->weak_outer = 0;
         st->mat = 0;
@@ -678,6 +680,10 @@ struct Vecs<double> {
     __device__ static double *s(const SetDesc &d, int i) { return i ? d.s1 : d.r; }
     __device__ static double *t(const SetDesc &d, int i) { return i ? d.t1 : d.t; }
     __device__ static double *f(const SetDesc &d) { return d.f; }
+    // symmetric form: a_E, a_N, a_T (the caller's arrays), 1/a_P
+    __device__ static const double *sy(const SetDesc &d, int i) {
+        return i == 0 ? d.a[1] : i == 1 ? d.a[3] : i == 2 ? d.a[5] : d.dinv;
+    }
 };
 template <>
 struct Vecs<float> {
@@ -691,6 +697,7 @@ struct Vecs<float> {
     __device__ static float *s(const SetDesc &d, int i) { return i ? d.s1_32 : d.r32; }
     __device__ static float *t(const SetDesc &d, int i) { return i ? d.t1_32 : d.t32; }
     __device__ static float *f(const SetDesc &d) { return d.f32; }
+    __device__ static const float *sy(const SetDesc &d, int i) { return d.sym32[i]; }
 };
 
 // the six scaled coefficients of a row, zero where the neighbour is outside
@@ -705,6 +712,24 @@ struct Unit6 {
         s = ld(as[3], idx);
         t = ld(as[4], idx);
         b = ld(as[5], idx);
+        e = nb.e ? e : T(0);
+        w = nb.w ? w : T(0);
+        n = nb.n ? n : T(0);
+        s = nb.s ? s : T(0);
+        t = up ? t : T(0);
+        b = dn ? b : T(0);
+    }
+    // row idx of A of an exactly symmetric matrix: a_W(idx) = a_E(idx-1), a_S(idx) = a_N(idx-nx),
+    // a_B(idx) = a_T(idx-P), so three arrays hold all six links (the neighbour's entries are
+    // read from cache lines the neighbouring rows bring in)
+    __device__ __forceinline__ void load_sym(const T *aE, const T *aN, const T *aT, int idx, int nx, int P, Nb nb,
+                                             bool up, bool dn) {
+        e = ld(aE, idx);
+        w = ld(aE, max(idx - 1, 0));
+        n = ld(aN, idx);
+        s = ld(aN, max(idx - nx, 0));
+        t = ld(aT, idx);
+        b = ld(aT, max(idx - P, 0));
         e = nb.e ? e : T(0);
         w = nb.w ? w : T(0);
         n = nb.n ? n : T(0);
@@ -1111,18 +1136,21 @@ __device__ __forceinline__ float keep_if(bool c, float x) {
     return __int_as_float(__float_as_int(x) & (c ? ~0 : 0));
 }
 
-template <typename T, int CPT, int H>
-__global__ void __launch_bounds__(kBlock) fused_kernel(LaunchSets ls) {
+// SYM: the symmetric form.  The planes in LDS then hold p D^-1 and s D^-1 (each value
+// times 1/a_P of its cell), the products take a_E, a_N, a_T and the neighbours' a_E,
+// a_N, a_T for the W, S, B links, (A D^-1 p)_c = p_c - sum_nb a_nb(c) (p/a_P)_nb, and
+// the own cells' p and s come from registers: 4 coefficient words per cell instead of 6.
+template <typename T, int CPT, int H, bool SYM>
+__device__ __forceinline__ void fused_step(const TileRef &tr) {
     constexpr int Q = kBlock * CPT;
-    const TileRef tr = locate<false>(ls);
     const SetDesc &d = *tr.d;
     const SolveState *st_ = d.st;
-    if (!st_->active || st_->need_f) return;
     const int in = st_->fpar, out = in ^ 1;
     const bool fresh = st_->fresh != 0;
     const T al = (T)st_->alpha, ap = (T)st_->alpha_prev, om = (T)st_->omega, be = (T)st_->beta;
     const T *as[6];
     for (int k = 0; k < 6; ++k) as[k] = Vecs<T>::as(d)[k];
+    const T *aE = Vecs<T>::sy(d, 0), *aN = Vecs<T>::sy(d, 1), *aT = Vecs<T>::sy(d, 2), *gv = Vecs<T>::sy(d, 3);
     const T *sI = Vecs<T>::s(d, in), *tI = Vecs<T>::t(d, in), *pI = Vecs<T>::p(d, in), *vI = Vecs<T>::v(d, in);
     T *sO = Vecs<T>::s(d, out), *tO = Vecs<T>::t(d, out), *pO = Vecs<T>::p(d, out), *vO = Vecs<T>::v(d, out);
     T *yv = Vecs<T>::y(d);
@@ -1186,14 +1214,17 @@ __global__ void __launch_bounds__(kBlock) fused_kernel(LaunchSets ls) {
     // values carried between steps (own cells): f on planes kt+2d / kt+d / kt,
     // r^ and the coefficients on plane kt, r on plane kt+d (also inner ring)
     T fA[CPT], fB[CPT], fC[CPT], rhC[CPT], rBo[CPT], rBi[H];
+    // symmetric form: p and 1/a_P on plane kt+d (own cells, inner ring), s on plane kt (own)
+    T pBo[CPT], pBi[H], gBo[CPT], gBi[H], sCo[CPT];
     Unit6<T> cC[CPT];
 #pragma unroll
     for (int m = 0; m < CPT; ++m) {
         fA[m] = fB[m] = fC[m] = rhC[m] = rBo[m] = T(0);
+        pBo[m] = gBo[m] = sCo[m] = T(0);
         cC[m] = Unit6<T>{T(0), T(0), T(0), T(0), T(0), T(0)};
     }
 #pragma unroll
-    for (int h = 0; h < H; ++h) rBi[h] = T(0);
+    for (int h = 0; h < H; ++h) rBi[h] = pBi[h] = gBi[h] = T(0);
     double acc[11];
 #pragma unroll
     for (int i = 0; i < 11; ++i) acc[i] = 0.0;
@@ -1219,6 +1250,7 @@ __global__ void __launch_bounds__(kBlock) fused_kernel(LaunchSets ls) {
         // when the range is reached.
         T sIo[CPT], tIo[CPT], pIo[CPT], vIo[CPT], yo[CPT], rhN[CPT];
         T sIi[H], tIi[H], pIi[H], vIi[H], sIr[H], tIr[H], pIr[H], vIr[H];
+        T gAo[CPT], gAi[H], gAr[H];  // symmetric form: 1/a_P on plane kp
         Unit6<T> cN[CPT], cI[H];
         {
             const int kyb = min(max(kp, k0), k1 - 1) * P;  // y, f: own planes
@@ -1238,24 +1270,38 @@ __global__ void __launch_bounds__(kBlock) fused_kernel(LaunchSets ls) {
                 sIi[h] = ld(sI, i); tIi[h] = ld(tI, i); pIi[h] = ld(pI, i); vIi[h] = ld(vI, i);
                 sIr[h] = ld(sI, r); tIr[h] = ld(tI, r); pIr[h] = ld(pI, r); vIr[h] = ld(vI, r);
             }
+            if (SYM) {
+#pragma unroll
+                for (int m = 0; m < CPT; ++m) gAo[m] = ld(gv, qo[m] + kpb);
+#pragma unroll
+                for (int h = 0; h < H; ++h) {
+                    gAi[h] = ld(gv, qi[h] + kpb);
+                    gAr[h] = ld(gv, qr[h] + kpb);
+                }
+            }
 #pragma unroll
             for (int m = 0; m < CPT; ++m) {
-                cN[m].load(as, qo[m] + kcb, nbo[m], up, dn);
+                if (SYM) cN[m].load_sym(aE, aN, aT, qo[m] + kcb, nx, P, nbo[m], up, dn);
+                else cN[m].load(as, qo[m] + kcb, nbo[m], up, dn);
                 rhN[m] = ld(rhv, qo[m] + krb);
             }
 #pragma unroll
-            for (int h = 0; h < H; ++h) cI[h].load(as, qi[h] + kcb, nbi[h], up, dn);
+            for (int h = 0; h < H; ++h) {
+                if (SYM) cI[h].load_sym(aE, aN, aT, qi[h] + kcb, nx, P, nbi[h], up, dn);
+                else cI[h].load(as, qi[h] + kcb, nbi[h], up, dn);
+            }
         }
 
         // ---- p_j on plane kp (segment + both rings), r_j kept for plane kp
-        T rAo[CPT], rAi[H];
+        T rAo[CPT], rAi[H], pAo[CPT], pAi[H];
         T *pw = Pb + bp * W;
 #pragma unroll
         for (int m = 0; m < CPT; ++m) {
             const bool ok = pin && oko[m];
             const T r = keep_if(ok, fma(-omf, keep_if(cont, tIo[m]), sIo[m]));
             const T pv = keep_if(ok, fma(bef, keep_if(cont, fma(-om, vIo[m], pIo[m])), r));
-            pw[eo[m]] = pv;
+            pw[eo[m]] = SYM ? keep_if(ok, pv * gAo[m]) : pv;
+            pAo[m] = pv;
             rAo[m] = r;
             const bool own = pown && oko[m];
             const T yn = yo[m] + fma(ap, pIo[m], om * sIo[m]);
@@ -1274,15 +1320,19 @@ __global__ void __launch_bounds__(kBlock) fused_kernel(LaunchSets ls) {
             const T r = keep_if(ok, fma(-omf, keep_if(cont, tIi[h]), sIi[h]));
             const T pv = keep_if(ok, fma(bef, keep_if(cont, fma(-om, vIi[h], pIi[h])), r));
             rAi[h] = r;
-            (ei[h] >= 0 ? pw[ei[h]] : pad[tid]) = pv;
+            pAi[h] = pv;
+            (ei[h] >= 0 ? pw[ei[h]] : pad[tid]) = SYM ? keep_if(ok, pv * gAi[h]) : pv;
             const bool ok2 = pin && okr[h];
             const T r2 = keep_if(ok2, fma(-omf, keep_if(cont, tIr[h]), sIr[h]));
             const T pv2 = keep_if(ok2, fma(bef, keep_if(cont, fma(-om, vIr[h], pIr[h])), r2));
-            (er[h] >= 0 ? pw[er[h]] : pad[tid]) = pv2;
+            (er[h] >= 0 ? pw[er[h]] : pad[tid]) = SYM ? keep_if(ok2, pv2 * gAr[h]) : pv2;
         }
         __syncthreads();
 
         // ---- v_j = M p_j and s_j = r_j - alpha_j v_j on plane kv (segment + inner ring)
+        T sNo[CPT];
+#pragma unroll
+        for (int m = 0; m < CPT; ++m) sNo[m] = T(0);
         if (do2) {
             // plane kv's neighbours: kv + d = kp, kv - d = kt
             const T *pc = Pb + bv * W, *pu = Pb + (down ? bt : bp) * W, *pd = Pb + (down ? bp : bt) * W;
@@ -1290,10 +1340,12 @@ __global__ void __launch_bounds__(kBlock) fused_kernel(LaunchSets ls) {
 #pragma unroll
             for (int m = 0; m < CPT; ++m) {
                 const int e = eo[m];
-                const T v = cN[m].apply(pc[e], pc[e + 1], pc[e - 1], pc[e + nx], pc[e - nx], pu[e], pd[e]);
+                const T xc = SYM ? pBo[m] : pc[e];
+                const T v = cN[m].apply(xc, pc[e + 1], pc[e - 1], pc[e + nx], pc[e - nx], pu[e], pd[e]);
                 const bool ok = vin && oko[m];
                 const T sv = keep_if(ok, fma(-al, v, rBo[m]));
-                sw[e] = sv;
+                sw[e] = SYM ? keep_if(ok, sv * gBo[m]) : sv;
+                sNo[m] = sv;
                 const bool own = vown && oko[m];
                 if (own) {
                     const int i = qo[m] + kvb;
@@ -1310,9 +1362,11 @@ __global__ void __launch_bounds__(kBlock) fused_kernel(LaunchSets ls) {
 #pragma unroll
             for (int h = 0; h < H; ++h) {
                 const int e = ei[h] >= 0 ? ei[h] : 2 * nx;  // an unused slot reads a valid cell, writes its pad
-                const T v = cI[h].apply(pc[e], pc[e + 1], pc[e - 1], pc[e + nx], pc[e - nx], pu[e], pd[e]);
-                const T sv = keep_if(vin && oki[h], fma(-al, v, rBi[h]));
-                (ei[h] >= 0 ? sw[e] : pad[tid]) = sv;
+                const T xc = SYM ? pBi[h] : pc[e];
+                const T v = cI[h].apply(xc, pc[e + 1], pc[e - 1], pc[e + nx], pc[e - nx], pu[e], pd[e]);
+                const bool ok = vin && oki[h];
+                const T sv = keep_if(ok, fma(-al, v, rBi[h]));
+                (ei[h] >= 0 ? sw[e] : pad[tid]) = SYM ? keep_if(ok, sv * gBi[h]) : sv;
             }
         }
         __syncthreads();
@@ -1324,7 +1378,7 @@ __global__ void __launch_bounds__(kBlock) fused_kernel(LaunchSets ls) {
 #pragma unroll
             for (int m = 0; m < CPT; ++m) {
                 const int e = eo[m];
-                const T s0 = sc[e];
+                const T s0 = SYM ? sCo[m] : sc[e];
                 const T t = cC[m].apply(s0, sc[e + 1], sc[e - 1], sc[e + nx], sc[e - nx], su[e], sd[e]);
                 if (oko[m]) st(tO, qo[m] + kt * P, t);
                 const T tk = keep_if(oko[m], t);
@@ -1343,15 +1397,31 @@ __global__ void __launch_bounds__(kBlock) fused_kernel(LaunchSets ls) {
             rhC[m] = rhN[m];
             cC[m] = cN[m];
             rBo[m] = rAo[m];
+            pBo[m] = pAo[m];
+            gBo[m] = gAo[m];
+            sCo[m] = sNo[m];
         }
 #pragma unroll
-        for (int h = 0; h < H; ++h) rBi[h] = rAi[h];
+        for (int h = 0; h < H; ++h) {
+            rBi[h] = rAi[h];
+            pBi[h] = pAi[h];
+            gBi[h] = gAi[h];
+        }
         const int b0 = bt;
         bt = bv;
         bv = bp;
         bp = b0;
     }
     reduce_and_finalize<11>(d, tr.tile, d.ntiles, acc, FinFused{d.sigma_tol[sizeof(T) == 4 ? 1 : 0]});
+}
+
+// SYM is chosen on the host, for a launch whose sets are all exactly symmetric
+template <typename T, int CPT, int H, bool SYM>
+__global__ void __launch_bounds__(kBlock) fused_kernel(LaunchSets ls) {
+    const TileRef tr = locate<false>(ls);
+    const SolveState *st_ = tr.d->st;
+    if (!st_->active || st_->need_f) return;
+    fused_step<T, CPT, H, SYM>(tr);
 }
 
 // ------------------------------------------------------------------ pointwise kernels
@@ -1498,15 +1568,34 @@ __device__ __forceinline__ void scaled_row(const double *const *a, int idx, int 
     for (int q = 0; q < 6; ++q) o[q] = (T)c[q];
 }
 
+// 1 if a link of cell idx = (i, j, k) towards W, S or B inside the grid differs from the
+// neighbour's link back (a_W(c) != a_E(c-1) and so on), else 0
+__device__ __forceinline__ double asym_row(const double *const *a, int idx, int i, int j, int k, int nx, int P) {
+    const bool w = i > 0, ss = j > 0, dn = k > 0;
+    const double wv = ld(a[2], idx), sv = ld(a[4], idx), bv = ld(a[6], idx);
+    const double ev = ld(a[1], max(idx - 1, 0)), nv = ld(a[3], max(idx - nx, 0)), tv = ld(a[5], max(idx - P, 0));
+    return ((w && wv != ev) || (ss && sv != nv) || (dn && bv != tv)) ? 1.0 : 0.0;
+}
+
+// sums: #asymmetric rows; the set takes the symmetric form of the single-sync step when
+// there are none (and the form is enabled)
+struct FinSym {
+    int on;
+    __device__ void operator()(SolveState *st, const double *s) const { st->sym = (on && s[0] == 0.0) ? 1 : 0; }
+};
+
 template <bool TR>
-__global__ void __launch_bounds__(kBlock) scale_kernel(LaunchSets ls) {
+__global__ void __launch_bounds__(kBlock) scale_kernel(LaunchSets ls, int sym_on) {
     const TileRef tr = locate<true>(ls);
     const SetDesc &d = *tr.d;
     const int nx = d.nx, ny = d.ny, nz = d.nz, P = d.plane, n = d.n, nflat = d.nflat;
+    const bool chk = !TR && sym_on;
     const double *a[7];
     double *as[6];
+    double *dinv = d.dinv;
     for (int q = 0; q < 7; ++q) a[q] = d.a[q];
     for (int q = 0; q < 6; ++q) as[q] = d.as[q];
+    double acc[1] = {0.0};
     for (int ch = tr.tile; ch * kFlatChunk < n; ch += nflat) {
         const int base = ch * kFlatChunk + (int)threadIdx.x;
 #pragma unroll
@@ -1518,9 +1607,12 @@ __global__ void __launch_bounds__(kBlock) scale_kernel(LaunchSets ls) {
                 scaled_row<TR>(a, idx, i, j, k, nx, ny, nz, P, o);
 #pragma unroll
                 for (int z = 0; z < 6; ++z) st(as[z], idx, o[z]);
+                st(dinv, idx, 1.0 / ld(a[0], idx));
+                if (chk) acc[0] += asym_row(a, idx, i, j, k, nx, P);
             }
         }
     }
+    reduce_and_finalize<1>(d, tr.tile, nflat, acc, FinSym{chk ? 1 : 0});
 }
 
 // x = y / a_P for sets about to be rechecked or reported
@@ -1550,17 +1642,19 @@ __global__ void __launch_bounds__(kBlock) unscale_kernel(LaunchSets ls) {
 }
 
 // FP32 coefficients of A D^-1 (each rounded to nearest once from the FP64
-// quotient), (b, b), a_P check
-__global__ void __launch_bounds__(kBlock) cast_kernel(LaunchSets ls) {
+// quotient), (b, b), a_P check; with sym_on also the symmetry check and the
+// FP32 a_E, a_N, a_T and 1/a_P of the symmetric form of the step
+__global__ void __launch_bounds__(kBlock) cast_kernel(LaunchSets ls, int sym_on) {
     const TileRef tr = locate<true>(ls);
     const SetDesc &d = *tr.d;
     const int nx = d.nx, ny = d.ny, nz = d.nz, P = d.plane, n = d.n, nflat = d.nflat;
     const double *a[7];
-    float *as32[6];
+    float *as32[6], *sy[4];
     for (int q = 0; q < 7; ++q) a[q] = d.a[q];
     for (int q = 0; q < 6; ++q) as32[q] = d.as32[q];
+    for (int q = 0; q < 4; ++q) sy[q] = d.sym32[q];
     const double *bvec = d.b;
-    double acc[2] = {0.0, 0.0};
+    double acc[3] = {0.0, 0.0, 0.0};
     for (int ch = tr.tile; ch * kFlatChunk < n; ch += nflat) {
         const int base = ch * kFlatChunk + (int)threadIdx.x;
 #pragma unroll
@@ -1575,10 +1669,17 @@ __global__ void __launch_bounds__(kBlock) cast_kernel(LaunchSets ls) {
                 const double ap = ld(a[0], idx), bv = ld(bvec, idx);
                 acc[0] += bv * bv;
                 acc[1] += (ap == 0.0 || !isfinite(ap)) ? 1.0 : 0.0;
+                if (sym_on) {
+                    st(sy[0], idx, (float)ld(a[1], idx));
+                    st(sy[1], idx, (float)ld(a[3], idx));
+                    st(sy[2], idx, (float)ld(a[5], idx));
+                    st(sy[3], idx, (float)(1.0 / ap));
+                    acc[2] += asym_row(a, idx, i, j, k, nx, P);
+                }
             }
         }
     }
-    reduce_and_finalize<2>(d, tr.tile, nflat, acc, FinCast{&d});
+    reduce_and_finalize<3>(d, tr.tile, nflat, acc, FinCast{&d, sym_on});
 }
 
 // x += (d32 / scale) / a_P (FP64), for sets whose inner solve has finished
@@ -2559,8 +2660,8 @@ hipError_t launch_kernel(Kern k, const LaunchSets &ls, int ntiles, int nflat, in
         else EQS_DISPATCH(cpt, h, EQS_LAUNCH((k2_kernel<double, C, HH>), grid, block, lds64, ls));
         break;
     case K_SCALE:
-        if (trans) EQS_LAUNCH((scale_kernel<true>), fgrid, block, 0, ls);
-        else EQS_LAUNCH((scale_kernel<false>), fgrid, block, 0, ls);
+        if (trans) EQS_LAUNCH((scale_kernel<true>), fgrid, block, 0, ls, 0);
+        else EQS_LAUNCH((scale_kernel<false>), fgrid, block, 0, ls, arg);
         break;
     case K_UNSCALE:
         EQS_LAUNCH(unscale_kernel, fgrid, block, 0, ls);
@@ -2581,7 +2682,7 @@ hipError_t launch_kernel(Kern k, const LaunchSets &ls, int ntiles, int nflat, in
         EQS_DISPATCH(cpt, h, EQS_LAUNCH((outer_kernel<C, HH>), grid, block, lds64, ls));
         break;
     case K_CAST:
-        EQS_LAUNCH(cast_kernel, fgrid, block, 0, ls);
+        EQS_LAUNCH(cast_kernel, fgrid, block, 0, ls, arg);
         break;
     case K_UPDATE:
         EQS_LAUNCH(update_kernel, fgrid, block, 0, ls);
@@ -2596,11 +2697,16 @@ hipError_t launch_kernel(Kern k, const LaunchSets &ls, int ntiles, int nflat, in
         if (trans) EQS_DISPATCH(cpt, h, EQS_LAUNCH((apply_kernel<C, HH, true>), grid, block, lds64, ls, x, y));
         else EQS_DISPATCH(cpt, h, EQS_LAUNCH((apply_kernel<C, HH, false>), grid, block, lds64, ls, x, y));
         break;
-    case K_FUSED: {  // the scaled operator needs no transpose variant
+    case K_FUSED: {  // the scaled operator needs no transpose variant; arg: symmetric form
         if (h > 4) return hipErrorInvalidValue;
         const size_t fl = fused_lds_bytes(cpt, max_nx, fp32 ? 4 : 8);
-        if (fp32) EQS_DISPATCH_FUSED(cpt, h, EQS_LAUNCH((fused_kernel<float, C, HH>), grid, block, fl, ls));
-        else EQS_DISPATCH_FUSED(cpt, h, EQS_LAUNCH((fused_kernel<double, C, HH>), grid, block, fl, ls));
+        if (arg) {  // every set of the launch exactly symmetric
+            if (fp32) EQS_DISPATCH_FUSED(cpt, h, EQS_LAUNCH((fused_kernel<float, C, HH, true>), grid, block, fl, ls));
+            else EQS_DISPATCH_FUSED(cpt, h, EQS_LAUNCH((fused_kernel<double, C, HH, true>), grid, block, fl, ls));
+        } else {
+            if (fp32) EQS_DISPATCH_FUSED(cpt, h, EQS_LAUNCH((fused_kernel<float, C, HH, false>), grid, block, fl, ls));
+            else EQS_DISPATCH_FUSED(cpt, h, EQS_LAUNCH((fused_kernel<double, C, HH, false>), grid, block, fl, ls));
+        }
         break;
     }
     case K_FSETUP:

@@ -608,3 +608,117 @@ def test_preconditioner_switch_restores_the_jacobi_tiling(torch_dev, orc):
     assert ctx.layout()["kc"] == lay0["kc"] == 16
     x1, i1 = ctx.solve(D, bd, tol=1e-10, maxit=2000)
     assert i1 == i0 and np.array_equal(host(x1), host(x0))
+
+
+# ---------------------------------------------------------------- symmetric form of the single-sync step
+#
+# An exactly symmetric matrix (the pressure-like recipe) lets the single-sync step form the products
+# of A D^-1 from a_E, a_N, a_T and 1/a_P: the same operator, evaluated with other roundings.  The
+# form is reported in info["symmetric"]; EQS_SYM=0 turns it off.
+
+SYM_SHAPES = [(33, 64, 17), (130, 3, 40), (200, 7, 3), (97, 31, 5), (1, 300, 2), (3, 1, 700)]
+
+
+def _sym_solve(torch, dev, g, diags, b, precision="fp64", env=None, tol=1e-12, maxit=20000):
+    ctx = context([g.shape], precision=precision, env=dict(env or {}, EQS_SMALL=0))
+    x, info = ctx.solve(dev_arrays(torch, dev, diags), dev_arrays(torch, dev, [b])[0], tol=tol, maxit=maxit)
+    ctx.close()
+    return host(x), info
+
+
+@pytest.mark.parametrize("shape", SYM_SHAPES)
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+def test_symmetric_form_meets_tol_against_oracle(torch_dev, orc, shape, precision):
+    torch, dev = torch_dev
+    g, diags, b, xs = manufactured(orc, 1, grid=W.Grid(*shape))
+    tol = 1e-12 if precision == "fp64" else 1e-10
+    for env, sym in ((dict(), True), (dict(EQS_SYM=0), False)):
+        xg, info = _sym_solve(torch, dev, g, diags, b, precision, env, tol=tol)
+        print(shape, precision, env, info, flush=True)
+        assert info["status"] == 0 and info["symmetric"] is sym, (env, info)
+        rel = orc.rel_residual(g.shape, diags, b, xg)
+        assert rel <= tol, (env, rel)
+        assert abs(rel - info["rel_res"]) <= 1e-3 * rel
+        assert np.max(np.abs(xg - xs)) <= orc.forward_error_certificate(g.shape, diags, b, xg) * (1 + 1e-6)
+
+
+@pytest.mark.parametrize("tiling", TILINGS[1:] + [dict(EQS_SMALL=0, EQS_CPT=1, EQS_KC=5)],
+                         ids=["cpt1_kc1", "cpt2_kc3", "cpt2_kc7", "cpt1_kc5"])
+def test_symmetric_form_launch_layouts(torch_dev, orc, tiling):
+    """Every tile layout (cells per thread, planes per chunk, halo slots) of the symmetric form
+    against the oracle's FP64 residual, and against the general form's solution."""
+    torch, dev = torch_dev
+    g, diags, b, xs = manufactured(orc, 1, grid=W.Grid(37, 23, 19))
+    xo, oinfo = orc.bicgstab(g.shape, diags, b, tol=1e-13, maxit=20000)
+    assert oinfo["status"] == 0
+    xs1, i1 = _sym_solve(torch, dev, g, diags, b, env=tiling, tol=1e-13)
+    xg0, i0 = _sym_solve(torch, dev, g, diags, b, env=dict(tiling, EQS_SYM=0), tol=1e-13)
+    assert i1["symmetric"] and not i0["symmetric"]
+    for xg in (xs1, xg0):
+        assert orc.rel_residual(g.shape, diags, b, xg) <= 1e-13
+        cert = orc.forward_error_certificate(g.shape, diags, b, xg)
+        assert np.max(np.abs(xg - xo)) <= 2 * cert + orc.forward_error_certificate(g.shape, diags, b, xo)
+
+
+def test_symmetric_form_detection_is_exact(torch_dev, orc):
+    """The check compares the stored values bit for bit: one a_W one ulp off its partner a_E makes
+    the matrix non-symmetric (the general form, the same bits as with the form off), while
+    coefficients pointing out of the grid, which no product uses, do not count."""
+    torch, dev = torch_dev
+    g, diags, b, xs = manufactured(orc, 1, grid=W.Grid(24, 40, 20))
+    pert = [d.copy() for d in diags]
+    c = 5 + g.nx * (7 + g.ny * 9)
+    pert[2][c] = np.nextafter(pert[2][c], np.inf)  # a_W(c) != a_E(c - 1) by one ulp
+    bp = orc.apply(g.shape, pert, xs)
+    x1, i1 = _sym_solve(torch, dev, g, pert, bp, tol=1e-11)
+    x0, i0 = _sym_solve(torch, dev, g, pert, bp, env=dict(EQS_SYM=0), tol=1e-11)
+    assert not i1["symmetric"] and i1 == i0 and np.array_equal(x1, x0)
+    assert orc.rel_residual(g.shape, pert, bp, x1) <= 1e-11
+    # nonzero links out of the grid (a_W at i = 0, a_N at j = ny-1, a_B at k = 0): still symmetric,
+    # and the solution does not see them
+    outw = [d.copy() for d in diags]
+    rng = np.random.default_rng(7)
+    idx = np.arange(g.n).reshape(g.nz, g.ny, g.nx)
+    for arr, sel in ((2, idx[:, :, 0]), (3, idx[:, -1, :]), (6, idx[0, :, :])):
+        outw[arr][sel.ravel()] = rng.uniform(0.5, 2.0, sel.size)
+    x2, i2 = _sym_solve(torch, dev, g, outw, b, tol=1e-11)
+    assert i2["symmetric"] and i2["status"] == 0
+    xr, ir = _sym_solve(torch, dev, g, diags, b, tol=1e-11)
+    assert ir["symmetric"] and i2 == ir and np.array_equal(x2, xr)
+
+
+def test_symmetric_form_batched_and_graphs(torch_dev, orc):
+    """A batched call takes the form only when every set is symmetric; then each set equals its own
+    solve bit for bit, and graph replays equal eager launches.  A mixed batch runs the general form
+    for all of its sets (the same bits as with the form off)."""
+    torch, dev = torch_dev
+    shapes = [(24, 96, 24), (25, 96, 24)]
+    sym = [manufactured(orc, 1, grid=W.Grid(*s), set_id=i) for i, s in enumerate(shapes)]
+    cd = manufactured(orc, 2, grid=W.Grid(*shapes[1]), set_id=1)
+    for systems, want in ((sym, True), ([sym[0], cd], False)):
+        Ds = [dev_arrays(torch, dev, s[1]) for s in systems]
+        bs = [dev_arrays(torch, dev, [s[2]])[0] for s in systems]
+        ctx = context(shapes)
+        xb, infos = ctx.solve_batched(Ds, bs, tol=1e-11, maxit=3000)
+        for i, s in enumerate(systems):
+            assert infos[i]["status"] == 0 and infos[i]["symmetric"] is want, (i, infos[i])
+            assert orc.rel_residual(s[0].shape, s[1], s[2], host(xb[i])) <= 1e-11
+        if want:
+            for i in range(2):
+                xi, info = ctx.solve(Ds[i], bs[i], tol=1e-11, maxit=3000, set_id=i)
+                assert np.array_equal(host(xi), host(xb[i])) and info == infos[i], i
+            eager = context(shapes, env=dict(EQS_GRAPHS=0))
+            xe, ie = eager.solve_batched(Ds, bs, tol=1e-11, maxit=3000)
+            for rep in range(3):
+                junk = torch.randn(1 << 20, device=dev, dtype=torch.float64).cumsum(0)
+                torch.cuda.synchronize()
+                xr, ir = ctx.solve_batched(Ds, bs, tol=1e-11, maxit=3000)
+                assert ir == ie and all(np.array_equal(host(a), host(e)) for a, e in zip(xr, xe)), rep
+                del junk
+            eager.close()
+        else:
+            off = context(shapes, env=dict(EQS_SYM=0))
+            xo, io = off.solve_batched(Ds, bs, tol=1e-11, maxit=3000)
+            assert io == infos and all(np.array_equal(host(a), host(e)) for a, e in zip(xb, xo))
+            off.close()
+        ctx.close()
