@@ -719,23 +719,18 @@ struct Unit6 {
         t = up ? t : T(0);
         b = dn ? b : T(0);
     }
-    // row idx of A of an exactly symmetric matrix: a_W(idx) = a_E(idx-1), a_S(idx) = a_N(idx-nx),
-    // a_B(idx) = a_T(idx-P), so three arrays hold all six links (the neighbour's entries are
-    // read from cache lines the neighbouring rows bring in)
-    __device__ __forceinline__ void load_sym(const T *aE, const T *aN, const T *aT, int idx, int nx, int P, Nb nb,
-                                             bool up, bool dn) {
+    // in-plane links of row idx of an exactly symmetric matrix: a_W(idx) = a_E(idx-1) and
+    // a_S(idx) = a_N(idx-nx), so two arrays hold all four (the neighbour's entries are read from
+    // cache lines the neighbouring rows bring in); the T and B links are set by the caller
+    __device__ __forceinline__ void load_sym_plane(const T *aE, const T *aN, int idx, int nx, Nb nb) {
         e = ld(aE, idx);
         w = ld(aE, max(idx - 1, 0));
         n = ld(aN, idx);
         s = ld(aN, max(idx - nx, 0));
-        t = ld(aT, idx);
-        b = ld(aT, max(idx - P, 0));
         e = nb.e ? e : T(0);
         w = nb.w ? w : T(0);
         n = nb.n ? n : T(0);
         s = nb.s ? s : T(0);
-        t = up ? t : T(0);
-        b = dn ? b : T(0);
     }
     // row idx of M^T: the link to neighbour nb is row nb's coefficient towards idx
     __device__ __forceinline__ void load_transposed(const T *const *as, int idx, int nx, int P, int ncell, Nb nb,
@@ -1211,20 +1206,21 @@ __device__ __forceinline__ void fused_step(const TileRef &tr) {
         qr[h] = min(max(q2, 0), P - 1);
     }
 
-    // values carried between steps (own cells): f on planes kt+2d / kt+d / kt,
+    // values carried between steps (own cells): f on planes kt+d / kt,
     // r^ and the coefficients on plane kt, r on plane kt+d (also inner ring)
-    T fA[CPT], fB[CPT], fC[CPT], rhC[CPT], rBo[CPT], rBi[H];
-    // symmetric form: p and 1/a_P on plane kt+d (own cells, inner ring), s on plane kt (own)
-    T pBo[CPT], pBi[H], gBo[CPT], gBi[H], sCo[CPT];
+    T fB[CPT], fC[CPT], rhC[CPT], rBo[CPT], rBi[H];
+    // symmetric form: p and 1/a_P on plane kt+d (own cells, inner ring), s on plane kt (own);
+    // a_T of the plane loaded at the previous step (own cells, inner ring)
+    T pBo[CPT], pBi[H], gBo[CPT], gBi[H], sCo[CPT], tLo[CPT], tLi[H];
     Unit6<T> cC[CPT];
 #pragma unroll
     for (int m = 0; m < CPT; ++m) {
-        fA[m] = fB[m] = fC[m] = rhC[m] = rBo[m] = T(0);
-        pBo[m] = gBo[m] = sCo[m] = T(0);
+        fB[m] = fC[m] = rhC[m] = rBo[m] = T(0);
+        pBo[m] = gBo[m] = sCo[m] = tLo[m] = T(0);
         cC[m] = Unit6<T>{T(0), T(0), T(0), T(0), T(0), T(0)};
     }
 #pragma unroll
-    for (int h = 0; h < H; ++h) rBi[h] = pBi[h] = gBi[h] = T(0);
+    for (int h = 0; h < H; ++h) rBi[h] = pBi[h] = gBi[h] = tLi[h] = T(0);
     double acc[11];
 #pragma unroll
     for (int i = 0; i < 11; ++i) acc[i] = 0.0;
@@ -1233,6 +1229,40 @@ __device__ __forceinline__ void fused_step(const TileRef &tr) {
     // scalars zeroed, so no branch depends on `fresh` either.
     const T omf = fresh ? T(0) : om, bef = fresh ? T(0) : be;
     const bool cont = !fresh;
+
+    // The previous step's vectors that step `it` reads on plane kp (own cells and both rings),
+    // y and f (own cells) and, in the symmetric form, 1/a_P there.  Step it issues these loads
+    // for step it + 1 as soon as its p planes are in LDS, so they are in flight while it forms
+    // the products (its barriers wait for LDS only); the first step's are issued before the
+    // loop.  Every load is unconditional, at a plane index clamped into the grid (y, f: into
+    // the chunk), so the extra loads after the last step stay in bounds.
+    struct VecLoads {
+        T s[CPT], t[CPT], p[CPT], v[CPT], y[CPT], f[CPT], g[CPT];
+        T si[H], ti[H], pi[H], vi[H], gi[H], sr[H], tr[H], pr[H], vr[H], gr[H];
+    };
+    auto load_vectors = [&](int it, VecLoads &L) {
+        const int kp = (down ? k1 + 3 - it : k0 - 4 + it) + 2 * dk;
+        const int kpb = min(max(kp, 0), nz - 1) * P;
+        const int kyb = min(max(kp, k0), k1 - 1) * P;  // y, f: own planes
+#pragma unroll
+        for (int m = 0; m < CPT; ++m) {
+            const int i = qo[m] + kpb;
+            L.s[m] = ld(sI, i); L.t[m] = ld(tI, i); L.p[m] = ld(pI, i); L.v[m] = ld(vI, i);
+            L.y[m] = ld(yv, qo[m] + kyb);
+            L.f[m] = ld(fv, qo[m] + kyb);
+            L.g[m] = SYM ? ld(gv, i) : T(0);
+        }
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+            const int i = qi[h] + kpb, r = qr[h] + kpb;
+            L.si[h] = ld(sI, i); L.ti[h] = ld(tI, i); L.pi[h] = ld(pI, i); L.vi[h] = ld(vI, i);
+            L.sr[h] = ld(sI, r); L.tr[h] = ld(tI, r); L.pr[h] = ld(pI, r); L.vr[h] = ld(vI, r);
+            L.gi[h] = SYM ? ld(gv, i) : T(0);
+            L.gr[h] = SYM ? ld(gv, r) : T(0);
+        }
+    };
+    VecLoads nextv;
+    load_vectors(0, nextv);
 
     int bt = 0, bv = 1, bp = 2;  // LDS slots of planes kt, kt+d, kt+2d (kt-d shares kt+2d's slot)
     const int nsteps = k1 - k0 + 4;
@@ -1244,51 +1274,45 @@ __device__ __forceinline__ void fused_step(const TileRef &tr) {
         const bool do3 = it >= 4;
         const int kpb = min(max(kp, 0), nz - 1) * P, kvb = min(max(kv, 0), nz - 1) * P;
 
-        // ---- loads: step j-1 vectors on plane kp, coefficients on plane kv.
-        // Every load is unconditional, at a plane index clamped into the range
-        // where it is used; what a step outside that range loads is read again
-        // when the range is reached.
-        T sIo[CPT], tIo[CPT], pIo[CPT], vIo[CPT], yo[CPT], rhN[CPT];
-        T sIi[H], tIi[H], pIi[H], vIi[H], sIr[H], tIr[H], pIr[H], vIr[H];
-        T gAo[CPT], gAi[H], gAr[H];  // symmetric form: 1/a_P on plane kp
+        // ---- loads: coefficients and r^ on plane kv (the vectors on plane kp are in flight
+        // since the previous step).  Every load is unconditional, at a plane index clamped into
+        // the range where it is used; what a step outside that range loads is read again when
+        // the range is reached.
+        const VecLoads cv = nextv;
+        T rhN[CPT];
         Unit6<T> cN[CPT], cI[H];
         {
-            const int kyb = min(max(kp, k0), k1 - 1) * P;  // y, f: own planes
             const int krb = min(max(kv, k0), k1 - 1) * P;  // r^: own planes
             const int kcb = min(max(min(max(kv, k0 - 1), k1), 0), nz - 1) * P;  // coefficients: k0-1 .. k1
             const bool up = kv + 1 < nz, dn = kv > 0;
+            // symmetric form: the T and B links of plane kv are a_T on planes kv and kv - 1, which
+            // consecutive steps share: each step loads one of them (plane kv going up, kv - 1 going
+            // down, planes clamped into the grid) and takes the other from the previous step's load
+            const int ktb = min(max(down ? kv - 1 : kv, 0), nz - 1) * P;
 #pragma unroll
             for (int m = 0; m < CPT; ++m) {
-                const int i = qo[m] + kpb;
-                sIo[m] = ld(sI, i); tIo[m] = ld(tI, i); pIo[m] = ld(pI, i); vIo[m] = ld(vI, i);
-                yo[m] = ld(yv, qo[m] + kyb);
-                fA[m] = ld(fv, qo[m] + kyb);
-            }
-#pragma unroll
-            for (int h = 0; h < H; ++h) {
-                const int i = qi[h] + kpb, r = qr[h] + kpb;
-                sIi[h] = ld(sI, i); tIi[h] = ld(tI, i); pIi[h] = ld(pI, i); vIi[h] = ld(vI, i);
-                sIr[h] = ld(sI, r); tIr[h] = ld(tI, r); pIr[h] = ld(pI, r); vIr[h] = ld(vI, r);
-            }
-            if (SYM) {
-#pragma unroll
-                for (int m = 0; m < CPT; ++m) gAo[m] = ld(gv, qo[m] + kpb);
-#pragma unroll
-                for (int h = 0; h < H; ++h) {
-                    gAi[h] = ld(gv, qi[h] + kpb);
-                    gAr[h] = ld(gv, qr[h] + kpb);
+                if (SYM) {
+                    cN[m].load_sym_plane(aE, aN, qo[m] + kcb, nx, nbo[m]);
+                    const T tl = ld(aT, qo[m] + ktb);
+                    cN[m].t = up ? (down ? tLo[m] : tl) : T(0);
+                    cN[m].b = dn ? (down ? tl : tLo[m]) : T(0);
+                    tLo[m] = tl;
+                } else {
+                    cN[m].load(as, qo[m] + kcb, nbo[m], up, dn);
                 }
-            }
-#pragma unroll
-            for (int m = 0; m < CPT; ++m) {
-                if (SYM) cN[m].load_sym(aE, aN, aT, qo[m] + kcb, nx, P, nbo[m], up, dn);
-                else cN[m].load(as, qo[m] + kcb, nbo[m], up, dn);
                 rhN[m] = ld(rhv, qo[m] + krb);
             }
 #pragma unroll
             for (int h = 0; h < H; ++h) {
-                if (SYM) cI[h].load_sym(aE, aN, aT, qi[h] + kcb, nx, P, nbi[h], up, dn);
-                else cI[h].load(as, qi[h] + kcb, nbi[h], up, dn);
+                if (SYM) {
+                    cI[h].load_sym_plane(aE, aN, qi[h] + kcb, nx, nbi[h]);
+                    const T tl = ld(aT, qi[h] + ktb);
+                    cI[h].t = up ? (down ? tLi[h] : tl) : T(0);
+                    cI[h].b = dn ? (down ? tl : tLi[h]) : T(0);
+                    tLi[h] = tl;
+                } else {
+                    cI[h].load(as, qi[h] + kcb, nbi[h], up, dn);
+                }
             }
         }
 
@@ -1298,36 +1322,37 @@ __device__ __forceinline__ void fused_step(const TileRef &tr) {
 #pragma unroll
         for (int m = 0; m < CPT; ++m) {
             const bool ok = pin && oko[m];
-            const T r = keep_if(ok, fma(-omf, keep_if(cont, tIo[m]), sIo[m]));
-            const T pv = keep_if(ok, fma(bef, keep_if(cont, fma(-om, vIo[m], pIo[m])), r));
-            pw[eo[m]] = SYM ? keep_if(ok, pv * gAo[m]) : pv;
+            const T r = keep_if(ok, fma(-omf, keep_if(cont, cv.t[m]), cv.s[m]));
+            const T pv = keep_if(ok, fma(bef, keep_if(cont, fma(-om, cv.v[m], cv.p[m])), r));
+            pw[eo[m]] = SYM ? keep_if(ok, pv * cv.g[m]) : pv;
             pAo[m] = pv;
             rAo[m] = r;
             const bool own = pown && oko[m];
-            const T yn = yo[m] + fma(ap, pIo[m], om * sIo[m]);
+            const T yn = cv.y[m] + fma(ap, cv.p[m], om * cv.s[m]);
             asm volatile("" ::"v"(yn));  // formed on every lane, before the branch (no sunk loads)
             if (own) {
                 const int i = qo[m] + kpb;
                 st(pO, i, pv);
                 if (!fresh) st(yv, i, yn);
             }
-            acc[0] += (double)keep_if(own, fA[m]) * (double)pv;
+            acc[0] += (double)keep_if(own, cv.f[m]) * (double)pv;
             acc[8] += (double)keep_if(own, r) * (double)r;
         }
 #pragma unroll
         for (int h = 0; h < H; ++h) {
             const bool ok = pin && oki[h];
-            const T r = keep_if(ok, fma(-omf, keep_if(cont, tIi[h]), sIi[h]));
-            const T pv = keep_if(ok, fma(bef, keep_if(cont, fma(-om, vIi[h], pIi[h])), r));
+            const T r = keep_if(ok, fma(-omf, keep_if(cont, cv.ti[h]), cv.si[h]));
+            const T pv = keep_if(ok, fma(bef, keep_if(cont, fma(-om, cv.vi[h], cv.pi[h])), r));
             rAi[h] = r;
             pAi[h] = pv;
-            (ei[h] >= 0 ? pw[ei[h]] : pad[tid]) = SYM ? keep_if(ok, pv * gAi[h]) : pv;
+            (ei[h] >= 0 ? pw[ei[h]] : pad[tid]) = SYM ? keep_if(ok, pv * cv.gi[h]) : pv;
             const bool ok2 = pin && okr[h];
-            const T r2 = keep_if(ok2, fma(-omf, keep_if(cont, tIr[h]), sIr[h]));
-            const T pv2 = keep_if(ok2, fma(bef, keep_if(cont, fma(-om, vIr[h], pIr[h])), r2));
-            (er[h] >= 0 ? pw[er[h]] : pad[tid]) = SYM ? keep_if(ok2, pv2 * gAr[h]) : pv2;
+            const T r2 = keep_if(ok2, fma(-omf, keep_if(cont, cv.tr[h]), cv.sr[h]));
+            const T pv2 = keep_if(ok2, fma(bef, keep_if(cont, fma(-om, cv.vr[h], cv.pr[h])), r2));
+            (er[h] >= 0 ? pw[er[h]] : pad[tid]) = SYM ? keep_if(ok2, pv2 * cv.gr[h]) : pv2;
         }
         __syncthreads();
+        load_vectors(it + 1, nextv);  // in flight while the products below are formed
 
         // ---- v_j = M p_j and s_j = r_j - alpha_j v_j on plane kv (segment + inner ring)
         T sNo[CPT];
@@ -1393,19 +1418,19 @@ __device__ __forceinline__ void fused_step(const TileRef &tr) {
 #pragma unroll
         for (int m = 0; m < CPT; ++m) {
             fC[m] = fB[m];
-            fB[m] = fA[m];
+            fB[m] = cv.f[m];
             rhC[m] = rhN[m];
             cC[m] = cN[m];
             rBo[m] = rAo[m];
             pBo[m] = pAo[m];
-            gBo[m] = gAo[m];
+            gBo[m] = cv.g[m];
             sCo[m] = sNo[m];
         }
 #pragma unroll
         for (int h = 0; h < H; ++h) {
             rBi[h] = rAi[h];
             pBi[h] = pAi[h];
-            gBi[h] = gAi[h];
+            gBi[h] = cv.gi[h];
         }
         const int b0 = bt;
         bt = bv;
