@@ -546,29 +546,38 @@ __device__ __forceinline__ Geo geo_of(const SetDesc &d) {
 //   void pre(idx, nb, up, dn, Pre&)  loads for the centre pass of an own cell
 //   void center(idx, Pre, Aux, xc, xE..xB, acc)
 // Every step issues all of its loads (centre operands of plane k, raw inputs
-// of plane k+1 for the own cells and H halo slots per thread) before any
-// store, so they are in flight together.
+// of plane k+2 for the own cells and H halo slots per thread) before any
+// store, so they are in flight together.  load() must not read what own() or
+// center() write: the raw inputs of a plane are read a step before its stores.
 
-template <typename T, int CPT, int H, class Ph>
-__device__ __forceinline__ void ext_plane(Ph &ph, const Geo &d, int k, T *buf, const int *qo,
-                                          const bool *ok, int q0, T *vown, typename Ph::Aux *ax) {
+// raw inputs of plane k (own cells; H halo slots per thread: the row below and the row above
+// the segment), at indices clamped into the plane
+template <int CPT, int H, class Ph>
+__device__ __forceinline__ void load_plane(const Ph &ph, const Geo &d, int k, const int *qo, int q0,
+                                           typename Ph::Raw *ro, typename Ph::Raw *rh) {
     constexpr int Q = kBlock * CPT;
     const int nx = d.nx, P = d.P;
     const int kb = k * P;
-    typename Ph::Raw ro[CPT], rh[H];
-    int he[H];
-    bool hv[H];
 #pragma unroll
     for (int m = 0; m < CPT; ++m) ro[m] = ph.load(min(qo[m], P - 1) + kb, min(qo[m], P - 1), k);
 #pragma unroll
     for (int hh = 0; hh < H; ++hh) {
         const int h = (int)threadIdx.x + kBlock * hh;
         const int e = h < nx ? h : h + Q;
-        const int q = q0 - nx + e;
-        he[hh] = h < 2 * nx ? e : -1;
-        hv[hh] = h < 2 * nx && q >= 0 && q < P;
-        rh[hh] = ph.load(min(max(q, 0), P - 1) + kb, min(max(q, 0), P - 1), k);
+        const int q = min(max(q0 - nx + e, 0), P - 1);
+        rh[hh] = ph.load(q + kb, q, k);
     }
+}
+
+// plane k into an LDS buffer from its raw inputs: operand values of the own cells (with their
+// stores) and of the halo slots (out-of-grid cells hold 0)
+template <typename T, int CPT, int H, class Ph>
+__device__ __forceinline__ void store_plane(Ph &ph, const Geo &d, int k, T *buf, const int *qo, const bool *ok,
+                                            int q0, T *vown, typename Ph::Aux *ax, const typename Ph::Raw *ro,
+                                            const typename Ph::Raw *rh) {
+    constexpr int Q = kBlock * CPT;
+    const int nx = d.nx, P = d.P;
+    const int kb = k * P;
 #pragma unroll
     for (int m = 0; m < CPT; ++m) {
         const int e = nx + (int)threadIdx.x + kBlock * m;
@@ -577,10 +586,18 @@ __device__ __forceinline__ void ext_plane(Ph &ph, const Geo &d, int k, T *buf, c
         vown[m] = v;
     }
 #pragma unroll
-    for (int hh = 0; hh < H; ++hh)
-        if (he[hh] >= 0) buf[he[hh]] = hv[hh] ? ph.halo(rh[hh]) : T(0);
+    for (int hh = 0; hh < H; ++hh) {
+        const int h = (int)threadIdx.x + kBlock * hh;
+        const int e = h < nx ? h : h + Q;
+        const int q = q0 - nx + e;
+        if (h < 2 * nx) buf[e] = (q >= 0 && q < P) ? ph.halo(rh[hh]) : T(0);
+    }
 }
 
+// The march of a tile through its chunk of planes.  Step k forms the products on plane k
+// from the LDS buffer of plane k; before its barrier it stores plane k + 1 into the next
+// buffer from raw inputs loaded one step earlier, and issues the loads of plane k + 2, which
+// are then in flight through the step (its barrier waits for LDS only).
 template <typename T, int CPT, int H, class Ph>
 __device__ __forceinline__ void march(Ph &ph, const Geo &d, int tile, T *lds, double (&acc)[Ph::NV]) {
     constexpr int Q = kBlock * CPT;
@@ -614,7 +631,10 @@ __device__ __forceinline__ void march(Ph &ph, const Geo &d, int tile, T *lds, do
 #pragma unroll
         for (int m = 0; m < CPT; ++m) vm[m] = (k0 > 0 && ok[m]) ? ph.halo(rb[m]) : T(0);
     }
-    ext_plane<T, CPT, H>(ph, d, k0, lds, qo, ok, q0, vc, axc);
+    typename Ph::Raw rco[CPT], rch[H];  // raw inputs of plane k + 1 (clamped into the grid)
+    load_plane<CPT, H>(ph, d, k0, qo, q0, rco, rch);
+    store_plane<T, CPT, H>(ph, d, k0, lds, qo, ok, q0, vc, axc, rco, rch);
+    load_plane<CPT, H>(ph, d, min(k0 + 1, nz - 1), qo, q0, rco, rch);
 
     int bc = 0;  // buffer of plane k
     for (int k = k0; k < k1; ++k) {
@@ -622,15 +642,13 @@ __device__ __forceinline__ void march(Ph &ph, const Geo &d, int tile, T *lds, do
         const int bn = bc == 2 ? 0 : bc + 1;
 #pragma unroll
         for (int m = 0; m < CPT; ++m) ph.pre(min(qo[m], P - 1) + k * P, nb[m], up, dn, pre[m]);
+        typename Ph::Raw rno[CPT], rnh[H];
+        load_plane<CPT, H>(ph, d, min(k + 2, nz - 1), qo, q0, rno, rnh);
         if (up && k + 1 < k1) {
-            ext_plane<T, CPT, H>(ph, d, k + 1, lds + bn * L, qo, ok, q0, vp, axp);
+            store_plane<T, CPT, H>(ph, d, k + 1, lds + bn * L, qo, ok, q0, vp, axp, rco, rch);
         } else {
-            typename Ph::Raw rb[CPT];
 #pragma unroll
-            for (int m = 0; m < CPT; ++m)
-                rb[m] = ph.load(min(qo[m], P - 1) + min(k + 1, nz - 1) * P, min(qo[m], P - 1), min(k + 1, nz - 1));
-#pragma unroll
-            for (int m = 0; m < CPT; ++m) vp[m] = (up && ok[m]) ? ph.halo(rb[m]) : T(0);
+            for (int m = 0; m < CPT; ++m) vp[m] = (up && ok[m]) ? ph.halo(rco[m]) : T(0);
         }
         __syncthreads();
         const T *bufc = lds + bc * L;
@@ -652,7 +670,10 @@ __device__ __forceinline__ void march(Ph &ph, const Geo &d, int tile, T *lds, do
             vm[m] = vc[m];
             vc[m] = vp[m];
             axc[m] = axp[m];
+            rco[m] = rno[m];
         }
+#pragma unroll
+        for (int hh = 0; hh < H; ++hh) rch[hh] = rnh[hh];
         bc = bn;
     }
 }
