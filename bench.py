@@ -525,6 +525,7 @@ def gpu_leg_batched(args):
                      "bytes": "%d words x 8 B per active cell, summed over sets" % kw,
                      "launches": k1_cnt, "mean_launch_ms": k1_ms / max(k1_cnt, 1)},
         "syncs_per_iteration": syncs,
+        "symmetric_form": {"fp64": form_sym, "fp32_refine": all(i["symmetric"] for i in rec[-1][3])},
         "kernels_fp64_ms": {kern: {"launches": k1_cnt, "mean_ms": k1_ms / max(k1_cnt, 1)}},
         "layout": [c64.layout(i) for i in range(len(grids))],
         "cells": sum(n_all),
@@ -628,6 +629,7 @@ def main():
         "fp32_refine": r["fp32_refine"],
         "fp64_multigrid": r["fp64_multigrid"],
         "kernels_fp64_ms": r["kernels_fp64_ms"],
+        "symmetric_form": r.get("symmetric_form"),
         "simple_bed": simple,
         "latency_cd16": latency,
         "batching_small": batching,
