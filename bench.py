@@ -479,15 +479,25 @@ def gpu_leg_batched(args):
     t_total = time.perf_counter() - t_start
     k1_cnt, k1_ms = c64.kernel_stats(kern)
     c64.profile([])
-    # the same sets one after another (plain FP64, the comparison the batched forms are measured against)
+    # the same sets one after another (plain FP64, the comparison the batched forms are measured
+    # against), each in a context of its own with the launch shape tuned for it alone
+    singles = [Context([g], precision="fp64") for g in grids]
+    if not args.no_tune:
+        for cs in singles:
+            cs.autotune(None)
+    for i, cs in enumerate(singles):
+        cs.solve(Ds[i], bs[i], tol=tol, maxit=maxit, check=False)  # warm-up (graph capture)
     seq = []
     for _ in range(max(1, args.steps // 2)):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for i in range(len(grids)):
-            c64.solve(Ds[i], bs[i], tol=tol, maxit=maxit, set_id=i, check=False)
+        for i, cs in enumerate(singles):
+            cs.solve(Ds[i], bs[i], tol=tol, maxit=maxit, check=False)
         torch.cuda.synchronize()
         seq.append(time.perf_counter() - t0)
+    for cs in singles:
+        cs.close()
+    del singles
     t64 = float(np.mean([r[0] for r in rec]))
     t32 = float(np.mean([r[1] for r in rec]))
     ci64 = sum(n * inf["iters"] for n, inf in zip(n_all, rec[-1][2]))

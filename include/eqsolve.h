@@ -148,8 +148,11 @@ int eqsolve_apply(eqs_ctx *ctx, int32_t set, const double *const diag[7], const 
  * (cells per thread of the stencil passes, planes per k-chunk, then the block
  * count of the pointwise pass) time `iters` BiCGSTAB iterations with HIP
  * events on a synthetic system of the set's exact shape in the context's
- * precision, and keep the fastest.  The result applies to the context at once
- * and is appended to the JSON-lines file cache_path (or $EQS_TUNE_CACHE if
+ * precision, and keep the fastest.  A context of several sets then also times
+ * the batched launch (eqsolve_solve_batched) under that choice and under one
+ * common number of planes per chunk for every set, and keeps the fastest for
+ * the context.  The result applies to the context at once; the per-set choice
+ * is appended to the JSON-lines file cache_path (or $EQS_TUNE_CACHE if
  * cache_path is NULL; nothing is written if both are unset), which
  * eqsolve_create consults when $EQS_TUNE_CACHE is set.  Allocates and frees
  * 9 temporary arrays of the largest set while it runs.  Returns EQS_OK,

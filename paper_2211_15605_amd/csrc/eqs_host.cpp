@@ -852,6 +852,55 @@ double time_iterations(eqs_ctx *c, int s, double *tmp, int iters) {
     return 1e3 * ms / iters;
 }
 
+// Mean time of one iteration of all sets in one launch table (the batched solve) under their
+// current tilings, every set on the synthetic system held in `tmp` (7 diagonals, b, x of nmax
+// cells each; a set reads its first n cells, and nothing written here aliases them).  Returns
+// as time_iterations.
+double time_batch(eqs_ctx *c, double *tmp, size_t nmax, int iters) {
+    const bool f32 = c->precision != EQS_FP64;
+    for (int s = 0; s < c->nsets; ++s) {
+        fill_desc(c, s);
+        SetDesc &d = c->h_desc[s];
+        for (int k = 0; k < 7; ++k) d.a[k] = tmp + k * nmax;
+        d.b = tmp + 7 * nmax;
+        d.x = tmp + 8 * nmax;
+        d.xf = nullptr;
+        for (int k = 0; k < 7; ++k) d.g[k] = nullptr;
+        d.mode = f32 ? MODE_REFINE : MODE_FP64;
+        d.tol = 1e-15;
+        d.tol_inner = 1e-15;
+        d.maxit = 1 << 30;
+    }
+    if (upload_desc(c, 0, c->nsets)) return -1.0;
+    if (launch_fill(tmp + 8 * nmax, (long)nmax, 0.0, c->stream) != hipSuccess) return -1.0;
+    Run R = make_run(c, 0, c->nsets, false);
+    const int saved = c->profile_mask;
+    c->profile_mask = 0;
+    if (f32) {
+        if (R.L(K_CAST) || R.L(K_OUTER)) return -1.0;
+    } else if (R.L(K_SCALE) || R.L(K_SETUP)) {
+        return -1.0;
+    }
+    if (R.L(K_FSETUP, nullptr, nullptr, 0, f32)) return -1.0;
+    for (int i = 0; i < 2; ++i)
+        if (R.L(K_FUSED, nullptr, nullptr, 0, f32)) return -1.0;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return -1.0;
+    (void)hipEventRecord(e0, c->stream);
+    for (int i = 0; i < iters; ++i)
+        if (R.L(K_FUSED, nullptr, nullptr, 0, f32)) return -1.0;
+    (void)hipEventRecord(e1, c->stream);
+    float ms = 0.f;
+    const bool ok = hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->profile_mask = saved;
+    if (!ok || R.readback()) return -1.0;
+    for (int s = 0; s < c->nsets; ++s)
+        if (!c->h_state[s].active) return -2.0;
+    return 1e3 * ms / iters;
+}
+
 // planes per chunk of a multigrid-preconditioned solve: its fine-level passes stream few
 // operands per step, so they need more blocks in flight than the fused Jacobi step (measured on
 // the 128x256x128 pressure-like system, 2 cells per thread: 32 planes 12.3 ms per solve, 16 planes
@@ -1354,6 +1403,30 @@ int eqsolve_autotune(eqs_ctx *c, const char *cache_path, int32_t iters) {
             if (us > 0 && us < best[s].us) best[s] = TuneEntry{best_cpt, best[s].kc, nf, us};
         }
     }
+    // Several sets: their batched launch holds every set's tiles at once, so the depths that are
+    // fastest for each set alone can leave the last round of blocks part-empty.  Time the batched
+    // step under the per-set choice and under one common depth for all sets, and keep the fastest
+    // (for this context only: the cache keeps the per-set choice, which a context of one set wants).
+    std::vector<TuneEntry> chosen = best;
+    if (rc == EQS_OK && c->nsets > 1 && c->sync1) {
+        c->cpt = best_cpt;
+        for (int s = 0; s < c->nsets; ++s) set_tiling(c->sets[s], best_cpt, best[s].kc, best[s].nflat);
+        clear_graphs(c);
+        double best_us = time_batch(c, tmp, nmax, iters);
+        if (best_us == -1.0) rc = EQS_ERR_HIP;
+        const int common[] = {8, 12, 16, 24, 32, 48};
+        for (int kc : common) {
+            if (rc != EQS_OK || best_us <= 0) break;
+            for (int s = 0; s < c->nsets; ++s) set_tiling(c->sets[s], best_cpt, kc, best[s].nflat);
+            clear_graphs(c);
+            const double us = time_batch(c, tmp, nmax, iters);
+            if (us == -1.0) { rc = EQS_ERR_HIP; break; }
+            if (us > 0 && us < 0.98 * best_us) {
+                best_us = us;
+                for (int s = 0; s < c->nsets; ++s) chosen[s] = TuneEntry{best_cpt, c->sets[s].KC, best[s].nflat, us};
+            }
+        }
+    }
     (void)hipStreamSynchronize(c->stream);
     (void)hipFree(tmp);
     (void)hipGetLastError();
@@ -1361,7 +1434,7 @@ int eqsolve_autotune(eqs_ctx *c, const char *cache_path, int32_t iters) {
         c->broken = true;
         return rc;
     }
-    if ((rc = apply_tuning(c, best_cpt, best))) return rc;
+    if ((rc = apply_tuning(c, best_cpt, chosen))) return rc;
     const char *path = cache_path ? cache_path : getenv("EQS_TUNE_CACHE");
     for (int s = 0; s < c->nsets; ++s) cache_store(path, arch, c->sets[s].g, c->precision, best[s]);
     return EQS_OK;

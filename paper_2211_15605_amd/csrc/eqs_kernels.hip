@@ -1256,7 +1256,10 @@ __device__ __forceinline__ void fused_step(const TileRef &tr) {
     // for step it + 1 as soon as its p planes are in LDS, so they are in flight while it forms
     // the products (its barriers wait for LDS only); the first step's are issued before the
     // loop.  Every load is unconditional, at a plane index clamped into the grid (y, f: into
-    // the chunk), so the extra loads after the last step stay in bounds.
+    // the chunk), so the extra loads after the last step stay in bounds.  FP64 with more than
+    // one halo slot per ring issues them at the top of their own step instead: the values held
+    // a step longer would take it past 256 VGPRs and halve its occupancy.
+    constexpr bool PF = sizeof(T) == 4 || H == 1;
     struct VecLoads {
         T s[CPT], t[CPT], p[CPT], v[CPT], y[CPT], f[CPT], g[CPT];
         T si[H], ti[H], pi[H], vi[H], gi[H], sr[H], tr[H], pr[H], vr[H], gr[H];
@@ -1283,7 +1286,7 @@ __device__ __forceinline__ void fused_step(const TileRef &tr) {
         }
     };
     VecLoads nextv;
-    load_vectors(0, nextv);
+    if (PF) load_vectors(0, nextv);
 
     int bt = 0, bv = 1, bp = 2;  // LDS slots of planes kt, kt+d, kt+2d (kt-d shares kt+2d's slot)
     const int nsteps = k1 - k0 + 4;
@@ -1299,6 +1302,7 @@ __device__ __forceinline__ void fused_step(const TileRef &tr) {
         // since the previous step).  Every load is unconditional, at a plane index clamped into
         // the range where it is used; what a step outside that range loads is read again when
         // the range is reached.
+        if (!PF) load_vectors(it, nextv);
         const VecLoads cv = nextv;
         T rhN[CPT];
         Unit6<T> cN[CPT], cI[H];
@@ -1373,7 +1377,7 @@ __device__ __forceinline__ void fused_step(const TileRef &tr) {
             (er[h] >= 0 ? pw[er[h]] : pad[tid]) = SYM ? keep_if(ok2, pv2 * cv.gr[h]) : pv2;
         }
         __syncthreads();
-        load_vectors(it + 1, nextv);  // in flight while the products below are formed
+        if (PF) load_vectors(it + 1, nextv);  // in flight while the products below are formed
 
         // ---- v_j = M p_j and s_j = r_j - alpha_j v_j on plane kv (segment + inner ring)
         T sNo[CPT];

@@ -209,6 +209,32 @@ def test_autotune_and_cache_roundtrip(torch_dev, orc, tmp_path):
     assert np.array_equal(host(x2), host(x))
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+def test_autotune_batched_context(torch_dev, orc, precision, tmp_path):
+    """Tuning a context of four staggered sets also times their batched launch (one common depth
+    for all sets may beat each set's own choice there); whatever it keeps, the batched solve meets
+    tol, equals each set's own solve in the same context bit for bit, and the cache holds one
+    per-set entry for each grid."""
+    torch, dev = torch_dev
+    systems = [manufactured(orc, 2, grid=W.Grid(*s), set_id=i) for i, s in enumerate(STAGGERED_SMALL)]
+    cache = str(tmp_path / "tune.jsonl")
+    ctx = context(STAGGERED_SMALL, precision=precision)
+    lays = ctx.autotune(cache_path=cache, iters=4)
+    for lay, sh in zip(lays, STAGGERED_SMALL):
+        assert lay["tiles"] == lay["segments"] * lay["chunks"] and 1 <= lay["kc"] <= sh[2], lay
+        assert lay["chunks"] == -(-sh[2] // lay["kc"]), lay
+    Ds = [dev_arrays(torch, dev, s[1]) for s in systems]
+    bs = [dev_arrays(torch, dev, [s[2]])[0] for s in systems]
+    xb, infos = ctx.solve_batched(Ds, bs, tol=1e-10, maxit=3000)
+    for i, sy in enumerate(systems):
+        assert infos[i]["status"] == 0, infos[i]
+        assert orc.rel_residual(sy[0].shape, sy[1], sy[2], host(xb[i])) <= 1e-10
+        xi, info = ctx.solve(Ds[i], bs[i], tol=1e-10, maxit=3000, set_id=i)
+        assert np.array_equal(host(xi), host(xb[i])) and info == infos[i], i
+    lines = open(cache).read().strip().splitlines()
+    assert len(lines) == 4 and all('"nx": %d, "ny": %d, "nz": %d' % sh in ln for sh, ln in zip(STAGGERED_SMALL, lines))
+
+
 @pytest.mark.parametrize("path", PATHS, ids=PATH_IDS)
 def test_fp64_status_codes(torch_dev, orc, path):
     torch, dev = torch_dev
