@@ -7,6 +7,8 @@ import sys
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
 
+import numpy as np
+
 import bench  # noqa: E402
 
 
@@ -35,6 +37,23 @@ def test_algorithmic_words_per_step():
     assert bench.WORDS["fused"] == 13 + 5 == bench.STEP_WORDS[1]
     # three launches: K1 12, K2 9, K3 8
     assert bench.WORDS["k1"] + bench.WORDS["k2"] + bench.WORDS["k3"] == bench.STEP_WORDS[3] == 29
+
+
+def test_symmetric_form_words_and_which_workloads_take_it():
+    # the symmetric form reads s, t, p, v, y, r^, f, a_E, a_N, a_T and 1/a_P, writes y, p, v, s, t
+    assert bench.WORDS["fused_sym"] == 11 + 5
+    assert bench.step_words(1, True) == (16, 16) and bench.step_words(1, False) == (18, 18)
+    assert bench.step_words(3, True) == (bench.WORDS["k1"], 29)  # the three-launch iteration has no such form
+    # the device check wants a_W(c) == a_E(c-1), a_S(c) == a_N(c-nx), a_B(c) == a_T(c-nx*ny) bit for bit
+    # wherever both cells are in the grid: the pressure-like recipe (config 1) meets it, the
+    # convection-diffusion one (configs 0, 2-4) does not
+    from paper_2211_15605_amd import workloads as W
+    for recipe, want in (("sym", True), ("cd", False)):
+        s = W.make_set(1, 0, grid=W.Grid(7, 5, 4), recipe=recipe)
+        a = [d.reshape(4, 5, 7) for d in s["diags"]]
+        same = (np.array_equal(a[2][:, :, 1:], a[1][:, :, :-1]) and np.array_equal(a[4][:, 1:, :], a[3][:, :-1, :])
+                and np.array_equal(a[6][1:, :, :], a[5][:-1, :, :]))
+        assert same is want, recipe
 
 
 def test_multigrid_settings_per_recipe():
