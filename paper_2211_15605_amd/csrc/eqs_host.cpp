@@ -797,32 +797,33 @@ int run_fp64_mg(Run &R) {
     return 0;
 }
 
-// Mean time of one BiCGSTAB iteration (K1 + K2 + K3) of set s under its
-// current tiling, on the synthetic system held in `tmp` (7 diagonals, b, x).
-// Returns -1 on a HIP failure and -2 if the measurement is not a full-work timing
-// (the synthetic system stopped iterating meanwhile).
-double time_iterations(eqs_ctx *c, int s, double *tmp, int iters) {
-    SetHost &h = c->sets[s];
-    const size_t n = (size_t)h.n;
-    fill_desc(c, s);
-    SetDesc &d = c->h_desc[s];
-    for (int k = 0; k < 7; ++k) d.a[k] = tmp + k * n;
-    d.b = tmp + 7 * n;
-    d.x = tmp + 8 * n;
-    d.xf = nullptr;
-    for (int k = 0; k < 7; ++k) d.g[k] = nullptr;
+// Mean time of one BiCGSTAB iteration (K1 + K2 + K3, or the fused step) of sets
+// [first, first + count) in one launch table under their current tilings, every set on the
+// synthetic system held in `tmp` (7 diagonals, b, x, each `stride` cells apart; a set reads
+// its first n cells, and nothing the timed kernels write aliases them).  Returns -1 on a HIP
+// failure and -2 if the measurement is not a full-work timing (a set stopped iterating
+// meanwhile).  The general form of the step is timed (the synthetic system is symmetric).
+double time_steps(eqs_ctx *c, int first, int count, double *tmp, size_t stride, int iters) {
     const bool f32 = c->precision != EQS_FP64;
-    d.mode = f32 ? MODE_REFINE : MODE_FP64;
-    d.tol = 1e-15;
-    d.tol_inner = 1e-15;
-    d.maxit = 1 << 30;
-    if (upload_desc(c, s, 1)) return -1.0;
-    if (launch_fill(d.x, (long)n, 0.0, c->stream) != hipSuccess) return -1.0;
-    Run R = make_run(c, s, 1, false);
+    for (int s = first; s < first + count; ++s) {
+        fill_desc(c, s);
+        SetDesc &d = c->h_desc[s];
+        for (int k = 0; k < 7; ++k) d.a[k] = tmp + k * stride;
+        d.b = tmp + 7 * stride;
+        d.x = tmp + 8 * stride;
+        d.xf = nullptr;
+        for (int k = 0; k < 7; ++k) d.g[k] = nullptr;
+        d.mode = f32 ? MODE_REFINE : MODE_FP64;
+        d.tol = 1e-15;
+        d.tol_inner = 1e-15;
+        d.maxit = 1 << 30;
+    }
+    if (upload_desc(c, first, count)) return -1.0;
+    if (launch_fill(tmp + 8 * stride, (long)stride, 0.0, c->stream) != hipSuccess) return -1.0;
+    Run R = make_run(c, first, count, false);
     const int saved = c->profile_mask;
     c->profile_mask = 0;
     if (f32) {
-        // the general form of the step (the synthetic system is symmetric)
         if (R.L(K_CAST) || R.L(K_OUTER)) return -1.0;
     } else if (R.L(K_SCALE) || R.L(K_SETUP)) {
         return -1.0;
@@ -848,55 +849,7 @@ double time_iterations(eqs_ctx *c, int s, double *tmp, int iters) {
     (void)hipEventDestroy(e1);
     c->profile_mask = saved;
     if (!ok || R.readback()) return -1.0;
-    if (!c->h_state[s].active) return -2.0;  // stopped during the measurement: not a full-work timing
-    return 1e3 * ms / iters;
-}
-
-// Mean time of one iteration of all sets in one launch table (the batched solve) under their
-// current tilings, every set on the synthetic system held in `tmp` (7 diagonals, b, x of nmax
-// cells each; a set reads its first n cells, and nothing written here aliases them).  Returns
-// as time_iterations.
-double time_batch(eqs_ctx *c, double *tmp, size_t nmax, int iters) {
-    const bool f32 = c->precision != EQS_FP64;
-    for (int s = 0; s < c->nsets; ++s) {
-        fill_desc(c, s);
-        SetDesc &d = c->h_desc[s];
-        for (int k = 0; k < 7; ++k) d.a[k] = tmp + k * nmax;
-        d.b = tmp + 7 * nmax;
-        d.x = tmp + 8 * nmax;
-        d.xf = nullptr;
-        for (int k = 0; k < 7; ++k) d.g[k] = nullptr;
-        d.mode = f32 ? MODE_REFINE : MODE_FP64;
-        d.tol = 1e-15;
-        d.tol_inner = 1e-15;
-        d.maxit = 1 << 30;
-    }
-    if (upload_desc(c, 0, c->nsets)) return -1.0;
-    if (launch_fill(tmp + 8 * nmax, (long)nmax, 0.0, c->stream) != hipSuccess) return -1.0;
-    Run R = make_run(c, 0, c->nsets, false);
-    const int saved = c->profile_mask;
-    c->profile_mask = 0;
-    if (f32) {
-        if (R.L(K_CAST) || R.L(K_OUTER)) return -1.0;
-    } else if (R.L(K_SCALE) || R.L(K_SETUP)) {
-        return -1.0;
-    }
-    if (R.L(K_FSETUP, nullptr, nullptr, 0, f32)) return -1.0;
-    for (int i = 0; i < 2; ++i)
-        if (R.L(K_FUSED, nullptr, nullptr, 0, f32)) return -1.0;
-    hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return -1.0;
-    (void)hipEventRecord(e0, c->stream);
-    for (int i = 0; i < iters; ++i)
-        if (R.L(K_FUSED, nullptr, nullptr, 0, f32)) return -1.0;
-    (void)hipEventRecord(e1, c->stream);
-    float ms = 0.f;
-    const bool ok = hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    c->profile_mask = saved;
-    if (!ok || R.readback()) return -1.0;
-    for (int s = 0; s < c->nsets; ++s)
+    for (int s = first; s < first + count; ++s)
         if (!c->h_state[s].active) return -2.0;
     return 1e3 * ms / iters;
 }
@@ -1374,7 +1327,7 @@ int eqsolve_autotune(eqs_ctx *c, const char *cache_path, int32_t iters) {
             for (int kc : kcs) {
                 if (kc > h.g.nz) continue;
                 set_tiling(h, cpt, kc, h.nflat);
-                const double us = time_iterations(c, s, tmp, iters);
+                const double us = time_steps(c, s, 1, tmp, nmax, iters);
                 if (us == -1.0) { rc = EQS_ERR_HIP; break; }
                 if (us > 0 && us < b.us) b = TuneEntry{cpt, kc, h.nflat, us};
             }
@@ -1398,7 +1351,7 @@ int eqsolve_autotune(eqs_ctx *c, const char *cache_path, int32_t iters) {
         for (int nf : flats) {
             set_tiling(h, best_cpt, best[s].kc, nf);
             if (h.nflat != nf) continue;
-            const double us = time_iterations(c, s, tmp, iters);
+            const double us = time_steps(c, s, 1, tmp, nmax, iters);
             if (us == -1.0) { rc = EQS_ERR_HIP; break; }
             if (us > 0 && us < best[s].us) best[s] = TuneEntry{best_cpt, best[s].kc, nf, us};
         }
@@ -1412,14 +1365,14 @@ int eqsolve_autotune(eqs_ctx *c, const char *cache_path, int32_t iters) {
         c->cpt = best_cpt;
         for (int s = 0; s < c->nsets; ++s) set_tiling(c->sets[s], best_cpt, best[s].kc, best[s].nflat);
         clear_graphs(c);
-        double best_us = time_batch(c, tmp, nmax, iters);
+        double best_us = time_steps(c, 0, c->nsets, tmp, nmax, iters);
         if (best_us == -1.0) rc = EQS_ERR_HIP;
         const int common[] = {8, 12, 16, 24, 32, 48};
         for (int kc : common) {
             if (rc != EQS_OK || best_us <= 0) break;
             for (int s = 0; s < c->nsets; ++s) set_tiling(c->sets[s], best_cpt, kc, best[s].nflat);
             clear_graphs(c);
-            const double us = time_batch(c, tmp, nmax, iters);
+            const double us = time_steps(c, 0, c->nsets, tmp, nmax, iters);
             if (us == -1.0) { rc = EQS_ERR_HIP; break; }
             if (us > 0 && us < 0.98 * best_us) {
                 best_us = us;
