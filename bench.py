@@ -592,6 +592,8 @@ def main():
                     help="skip the SIMPLE-iteration, latency, small-batch and adjoint sections")
     ap.add_argument("--only-simple", action="store_true",
                     help="run only the SIMPLE-iteration section and print it as the JSON line (for profiling)")
+    ap.add_argument("--only-latency", action="store_true",
+                    help="run only the 16^3 latency section and print it as the JSON line (for profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the timed steps, copy 1 GiB three times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -603,6 +605,9 @@ def main():
 
     if args.only_simple:
         print(json.dumps({"simple_bed": time_simple()}))
+        return
+    if args.only_latency:
+        print(json.dumps({"latency_cd16": time_latency()}))
         return
     cfg = W.CONFIGS[args.config]
     g = cfg["grids"][0]
