@@ -642,7 +642,7 @@ def test_preconditioner_switch_restores_the_jacobi_tiling(torch_dev, orc):
 # of A D^-1 from a_E, a_N, a_T and 1/a_P: the same operator, evaluated with other roundings.  The
 # form is reported in info["symmetric"]; EQS_SYM=0 turns it off.
 
-SYM_SHAPES = [(33, 64, 17), (130, 3, 40), (200, 7, 3), (97, 31, 5), (1, 300, 2), (3, 1, 700)]
+SYM_SHAPES = [(33, 64, 17), (130, 3, 40), (200, 7, 3), (97, 31, 5), (1, 300, 2), (3, 1, 700), (60, 45, 1)]
 
 
 def _sym_solve(torch, dev, g, diags, b, precision="fp64", env=None, tol=1e-12, maxit=20000):
@@ -748,3 +748,23 @@ def test_symmetric_form_batched_and_graphs(torch_dev, orc):
             assert io == infos and all(np.array_equal(host(a), host(e)) for a, e in zip(xb, xo))
             off.close()
         ctx.close()
+
+
+def test_symmetric_matrix_adjoint_runs_the_transposed_general_form(torch_dev, orc):
+    """The adjoint iterates on A^T D^-1 through the transposed scale pass; it never takes the
+    symmetric form (reported clear), and on a symmetric matrix lambda = A^-T w equals the forward
+    solve with w as right-hand side to the solves' tolerance."""
+    torch, dev = torch_dev
+    g, diags, b, xs = manufactured(orc, 1, grid=W.Grid(20, 24, 16))
+    D = dev_arrays(torch, dev, diags)
+    ctx = context([g.shape], env=dict(EQS_SMALL=0))
+    x, fi = ctx.solve(D, dev_arrays(torch, dev, [b])[0], tol=1e-13, maxit=5000)
+    assert fi["symmetric"] and fi["status"] == 0
+    w = np.random.default_rng(5).standard_normal(g.n)
+    gb, gd, ai = ctx.adjoint(D, x, dev_arrays(torch, dev, [w])[0], tol=1e-13, maxit=5000)
+    assert ai["status"] == 0 and not ai["symmetric"], ai
+    lam = host(gb)
+    assert orc.rel_residual(g.shape, diags, w, lam) <= 1e-12  # A^T = A: lambda solves A lambda = w
+    xw, wi = ctx.solve(D, dev_arrays(torch, dev, [w])[0], tol=1e-13, maxit=5000)
+    cert = orc.forward_error_certificate(g.shape, diags, w, lam) + orc.forward_error_certificate(g.shape, diags, w, host(xw))
+    assert np.max(np.abs(lam - host(xw))) <= cert * (1 + 1e-6)
