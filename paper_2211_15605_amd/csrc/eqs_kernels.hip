@@ -1260,11 +1260,14 @@ __device__ __forceinline__ void fused_step(const TileRef &tr) {
     // one halo slot per ring issues them at the top of their own step instead: the values held
     // a step longer would take it past 256 VGPRs and halve its occupancy.
     constexpr bool PF = sizeof(T) == 4 || H == 1;
+    // the rings' loads (mostly L2 hits: the neighbouring segments load the same cells) go a
+    // step ahead too, except in the FP64 symmetric form, which has no registers to spare
+    constexpr bool PFR = PF && !(SYM && sizeof(T) == 8);
     struct VecLoads {
         T s[CPT], t[CPT], p[CPT], v[CPT], y[CPT], f[CPT], g[CPT];
         T si[H], ti[H], pi[H], vi[H], gi[H], sr[H], tr[H], pr[H], vr[H], gr[H];
     };
-    auto load_vectors = [&](int it, VecLoads &L) {
+    auto load_own = [&](int it, VecLoads &L) {
         const int kp = (down ? k1 + 3 - it : k0 - 4 + it) + 2 * dk;
         const int kpb = min(max(kp, 0), nz - 1) * P;
         const int kyb = min(max(kp, k0), k1 - 1) * P;  // y, f: own planes
@@ -1276,6 +1279,10 @@ __device__ __forceinline__ void fused_step(const TileRef &tr) {
             L.f[m] = ld(fv, qo[m] + kyb);
             L.g[m] = SYM ? ld(gv, i) : T(0);
         }
+    };
+    auto load_rings = [&](int it, VecLoads &L) {
+        const int kp = (down ? k1 + 3 - it : k0 - 4 + it) + 2 * dk;
+        const int kpb = min(max(kp, 0), nz - 1) * P;
 #pragma unroll
         for (int h = 0; h < H; ++h) {
             const int i = qi[h] + kpb, r = qr[h] + kpb;
@@ -1286,7 +1293,8 @@ __device__ __forceinline__ void fused_step(const TileRef &tr) {
         }
     };
     VecLoads nextv;
-    if (PF) load_vectors(0, nextv);
+    if (PF) load_own(0, nextv);
+    if (PFR) load_rings(0, nextv);
 
     int bt = 0, bv = 1, bp = 2;  // LDS slots of planes kt, kt+d, kt+2d (kt-d shares kt+2d's slot)
     const int nsteps = k1 - k0 + 4;
@@ -1302,7 +1310,8 @@ __device__ __forceinline__ void fused_step(const TileRef &tr) {
         // since the previous step).  Every load is unconditional, at a plane index clamped into
         // the range where it is used; what a step outside that range loads is read again when
         // the range is reached.
-        if (!PF) load_vectors(it, nextv);
+        if (!PF) load_own(it, nextv);
+        if (!PFR) load_rings(it, nextv);
         const VecLoads cv = nextv;
         T rhN[CPT];
         Unit6<T> cN[CPT], cI[H];
@@ -1377,7 +1386,8 @@ __device__ __forceinline__ void fused_step(const TileRef &tr) {
             (er[h] >= 0 ? pw[er[h]] : pad[tid]) = SYM ? keep_if(ok2, pv2 * cv.gr[h]) : pv2;
         }
         __syncthreads();
-        if (PF) load_vectors(it + 1, nextv);  // in flight while the products below are formed
+        if (PF) load_own(it + 1, nextv);  // in flight while the products below are formed
+        if (PFR) load_rings(it + 1, nextv);
 
         // ---- v_j = M p_j and s_j = r_j - alpha_j v_j on plane kv (segment + inner ring)
         T sNo[CPT];
