@@ -686,18 +686,20 @@ def test_symmetric_form_launch_layouts(torch_dev, orc, tiling):
         assert np.max(np.abs(xg - xo)) <= 2 * cert + orc.forward_error_certificate(g.shape, diags, b, xo)
 
 
-def test_symmetric_form_detection_is_exact(torch_dev, orc):
-    """The check compares the stored values bit for bit: one a_W one ulp off its partner a_E makes
-    the matrix non-symmetric (the general form, the same bits as with the form off), while
-    coefficients pointing out of the grid, which no product uses, do not count."""
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+def test_symmetric_form_detection_is_exact(torch_dev, orc, precision):
+    """The check (in the scale pass, or the cast pass of the FP32 forms) compares the stored values
+    bit for bit: one a_W one ulp off its partner a_E makes the matrix non-symmetric (the general
+    form, the same bits as with the form off), while coefficients pointing out of the grid, which
+    no product uses, do not count."""
     torch, dev = torch_dev
     g, diags, b, xs = manufactured(orc, 1, grid=W.Grid(24, 40, 20))
     pert = [d.copy() for d in diags]
     c = 5 + g.nx * (7 + g.ny * 9)
     pert[2][c] = np.nextafter(pert[2][c], np.inf)  # a_W(c) != a_E(c - 1) by one ulp
     bp = orc.apply(g.shape, pert, xs)
-    x1, i1 = _sym_solve(torch, dev, g, pert, bp, tol=1e-11)
-    x0, i0 = _sym_solve(torch, dev, g, pert, bp, env=dict(EQS_SYM=0), tol=1e-11)
+    x1, i1 = _sym_solve(torch, dev, g, pert, bp, precision, tol=1e-11)
+    x0, i0 = _sym_solve(torch, dev, g, pert, bp, precision, env=dict(EQS_SYM=0), tol=1e-11)
     assert not i1["symmetric"] and i1 == i0 and np.array_equal(x1, x0)
     assert orc.rel_residual(g.shape, pert, bp, x1) <= 1e-11
     # nonzero links out of the grid (a_W at i = 0, a_N at j = ny-1, a_B at k = 0): still symmetric,
@@ -707,9 +709,9 @@ def test_symmetric_form_detection_is_exact(torch_dev, orc):
     idx = np.arange(g.n).reshape(g.nz, g.ny, g.nx)
     for arr, sel in ((2, idx[:, :, 0]), (3, idx[:, -1, :]), (6, idx[0, :, :])):
         outw[arr][sel.ravel()] = rng.uniform(0.5, 2.0, sel.size)
-    x2, i2 = _sym_solve(torch, dev, g, outw, b, tol=1e-11)
+    x2, i2 = _sym_solve(torch, dev, g, outw, b, precision, tol=1e-11)
     assert i2["symmetric"] and i2["status"] == 0
-    xr, ir = _sym_solve(torch, dev, g, diags, b, tol=1e-11)
+    xr, ir = _sym_solve(torch, dev, g, diags, b, precision, tol=1e-11)
     assert ir["symmetric"] and i2 == ir and np.array_equal(x2, xr)
 
 
