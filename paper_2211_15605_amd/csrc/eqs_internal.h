@@ -30,7 +30,7 @@ enum : int32_t { ST_OK = 0, ST_NOT_CONVERGED = 1, ST_BREAKDOWN = 2, ST_NONFINITE
 // block at the start of the next launch.
 struct SolveState {
     double bb;        // (b, b) of the system being iterated
-    double lim2;      // (tol_iter)^2 * bb: stop when (r, r) <= lim2
+    double lim2;      // tol_iter * sqrt(bb): stop when sqrt((r, r)) <= lim2
     double rho, rho_prev, alpha, omega;
     double sigma, ts, tt, ss, rr;   // latest reductions
     double rr_true;   // (b - A x, b - A x) in FP64 of the returned x
