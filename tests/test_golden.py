@@ -16,9 +16,8 @@ def rows():
 
 
 def test_verification_mesh_count_includes_one_ghost_layer():
-    # Sec. 3 prints 27 x 162 x 27 cells "such that the total number of cells is 137,924":
-    # that total is (27+2)(162+2)(27+2), i.e. the mesh carries one ghost layer around the
-    # interior.  Reading taken: neighbours outside the interior grid contribute nothing.
+    # Sec. 3 gives 137,924 cells for the 27 x 162 x 27 verification mesh: that total is
+    # (27+2)(162+2)(27+2), i.e. the mesh carries one ghost layer around the interior.  Reading taken: neighbours outside the interior grid contribute nothing.
     name, nx, ny, nz, total, _ = [r for r in rows() if r[0] == "verification_bed"][0]
     assert nx * ny * nz != total
     assert (nx + 2) * (ny + 2) * (nz + 2) == total

@@ -42,6 +42,12 @@ MUTANTS = [
     ("mg_post_smooth_sign", "z[c] = z1[c] + w * (r[c] - q[c]) / ap[c];", "z[c] = z1[c] - w * (r[c] - q[c]) / ap[c];"),
     ("mg_prolongs_to_wrong_aggregate", "z1[c] += m->prm.gamma * e[i / 2 + (long)cx * (j / 2 + (long)cy * (k / 2))];",
      "z1[c] += m->prm.gamma * e[i / 2 + (long)cx * (j / 2 + (long)cy * (k / 4))];"),
+    ("mg_gamma_dropped", "z1[c] += m->prm.gamma * e[i / 2 + (long)cx * (j / 2 + (long)cy * (k / 2))];",
+     "z1[c] += e[i / 2 + (long)cx * (j / 2 + (long)cy * (k / 2))];"),
+    ("mg_one_coarse_sweep_short", "for (int it = 0; it < m->prm.coarse_sweeps; it++) {",
+     "for (int it = 1; it < m->prm.coarse_sweeps; it++) {"),
+    ("mg_coarse_sweep_undamped", "z[c] += w * (r[c] - q[c]) / ap[c];", "z[c] += (r[c] - q[c]) / ap[c];"),
+    ("mg_presmooth_undamped", "z1[c] = w * r[c] / ap[c];", "z1[c] = r[c] / ap[c];"),
 ]
 
 # the pins run against each mutant (cheap ones; each returns normally or raises)
@@ -62,6 +68,7 @@ BATTERY = [
     lambda o: pins.test_mg_vcycle_transpose_identity(o, "cd"),
     lambda o: pins.test_mg_vcycle_transpose_identity(o, "sym"),
     lambda o: pins.test_mg_bicgstab_matches_dense_lu(o),
+    lambda o: pins.test_mg_vcycle_matches_dense_definition(o, "cd", (7, 6, 5), 8, 1.6, 3),
 ]
 
 
@@ -86,3 +93,55 @@ def test_pins_catch_planted_mistake(tmp_path, name, old, new):
         except Exception as e:  # AssertionError or a numerical failure
             caught.append(type(e).__name__)
     assert caught, "no pin caught mutant %s" % name
+
+
+# Mistakes planted in the NumPy helper behind the forward-error certificate
+# (diag_dominance_margin): each mutated copy of the function is run through the
+# margin and certificate pins, and at least one must fail.
+MARGIN_MUTANTS = [
+    ("W_slot_unshifted", "off[:, :, 1:] += np.abs(a[2][:, :, 1:])", "off[:, :, 1:] += np.abs(a[2][:, :, :-1])"),
+    ("T_slot_dropped", "off[:-1, :, :] += np.abs(a[5][:-1, :, :])", "pass"),
+    ("N_slot_takes_outward_row", "off[:, :-1, :] += np.abs(a[3][:, :-1, :])", "off[:, :, :] += np.abs(a[3][:, :, :])"),
+    ("max_instead_of_min", "return float(np.min(s - off))", "return float(np.max(s - off))"),
+    ("sum_not_difference", "return float(np.min(s - off))", "return float(np.min(s + off))"),
+]
+
+
+def _margin_battery(fn):
+    import types
+    from oracle import oracle as O
+    saved = O.diag_dominance_margin
+    O.diag_dominance_margin = fn
+    caught = []
+    try:
+        o = O.default()
+        for pin in (lambda: pins.test_diag_dominance_margin_of_generated_systems(o, "cd", 0.1),
+                    lambda: pins.test_diag_dominance_margin_of_generated_systems(o, "sym", 1e-3),
+                    lambda: pins.test_diag_dominance_margin_ignores_outward_slots_and_finds_the_worst_row(o),
+                    lambda: pins.test_forward_error_certificate_bounds_the_true_error(o)):
+            try:
+                pin()
+            except Exception as e:
+                caught.append(type(e).__name__)
+    finally:
+        O.diag_dominance_margin = saved
+    return caught
+
+
+def test_margin_mutant_table_applies_to_current_source():
+    import inspect
+    src = inspect.getsource(O.diag_dominance_margin)
+    for name, old, new in MARGIN_MUTANTS:
+        assert src.count(old) == 1, name
+    assert not _margin_battery(O.diag_dominance_margin)   # the real helper passes
+
+
+@pytest.mark.parametrize("name,old,new", MARGIN_MUTANTS, ids=[m[0] for m in MARGIN_MUTANTS])
+def test_margin_pins_catch_planted_mistake(name, old, new):
+    import inspect
+    import textwrap
+    import numpy as np
+    src = textwrap.dedent(inspect.getsource(O.diag_dominance_margin))
+    ns = {"np": np, "_f64": O._f64}
+    exec(compile(src.replace(old, new), "<mutant %s>" % name, "exec"), ns)
+    assert _margin_battery(ns["diag_dominance_margin"]), "no pin caught mutant %s" % name

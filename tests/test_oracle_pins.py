@@ -477,3 +477,118 @@ def test_mg_bicgstab_residual_invariant_and_iterations(orc, cfg, shape):
     assert orc.rel_residual(g.shape, s["diags"], b, x) <= 1e-10
     _, jinfo = orc.bicgstab(g.shape, s["diags"], b, tol=1e-10, maxit=2000)
     assert 4 * info["iters"] <= jinfo["iters"], (info, jinfo)
+
+
+def _dense_vcycle(A_levels, P_levels, r, omega, gamma, sweeps):
+    """The V-cycle written as dense matrix algebra on an explicit hierarchy: A_levels[l] is
+    level l's matrix, P_levels[l] the piecewise-constant interpolation from level l + 1.
+    Level l < last: z1 = omega D^-1 r; e = V_{l+1}(P^T (r - A z1)); z2 = z1 + gamma P e;
+    z = z2 + omega D^-1 (r - A z2).  Last level: `sweeps` damped-Jacobi sweeps from zero."""
+    def vc(l, rl):
+        A = A_levels[l]
+        dinv = 1.0 / np.diag(A)
+        if l == len(A_levels) - 1:
+            z = np.zeros_like(rl)
+            for _ in range(sweeps):
+                z = z + omega * dinv * (rl - A @ z)
+            return z
+        P = P_levels[l]
+        z1 = omega * dinv * rl
+        e = vc(l + 1, P.T @ (rl - A @ z1))
+        z2 = z1 + gamma * (P @ e)
+        return z2 + omega * dinv * (rl - A @ z2)
+    return vc(0, r)
+
+
+@pytest.mark.parametrize("recipe,shape,coarse_cells,gamma,sweeps", [
+    ("cd", (7, 6, 5), 8, 1.6, 3),
+    ("sym", (6, 5, 4), 4, 0.7, 2),
+    ("general", (5, 4, 6), 10, 1.3, 4),
+])
+def test_mg_vcycle_matches_dense_definition(orc, recipe, shape, coarse_cells, gamma, sweeps):
+    # The hierarchy is rebuilt here from the dense matrix alone (Galerkin products with the
+    # aggregation matrix, dimensions halved rounding up until at most coarse_cells cells), and the
+    # V-cycle applied as matrix algebra, with gamma != 1 and several coarsest-level sweeps so that
+    # the coarse-correction scale and the sweep count both show in the result.
+    from oracle import oracle as O
+    g = W.Grid(*shape)
+    diags = W.random_general(g, seed=41) if recipe == "general" else W.coefficients(g, recipe, W.rng_for(0, 6))
+    A_levels, P_levels, sh = [orc.dense(shape, diags)], [], shape
+    while sh[0] * sh[1] * sh[2] > coarse_cells:
+        Pm = _aggregation_matrix(sh)
+        P_levels.append(Pm)
+        A_levels.append(Pm.T @ A_levels[-1] @ Pm)
+        sh = ((sh[0] + 1) // 2, (sh[1] + 1) // 2, (sh[2] + 1) // 2)
+    assert len(A_levels) >= 3
+    rng = np.random.default_rng(11)
+    r = rng.standard_normal(g.n)
+    prm = O.mg_params(omega=0.8, gamma=gamma, coarse_sweeps=sweeps, coarse_cells=coarse_cells)
+    z, lev = orc.mg_apply(shape, diags, r, prm)
+    ref = _dense_vcycle(A_levels, P_levels, r, 0.8, gamma, sweeps)
+    assert lev == len(A_levels)
+    assert np.max(np.abs(z - ref)) <= 1e-13 * np.max(np.abs(ref))
+    # the same V-cycle with gamma or the sweep count changed differs by far more than that
+    alt_g = _dense_vcycle(A_levels, P_levels, r, 0.8, 1.0, sweeps)
+    alt_s = _dense_vcycle(A_levels, P_levels, r, 0.8, gamma, sweeps - 1)
+    assert np.max(np.abs(alt_g - ref)) > 1e-6 * np.max(np.abs(ref))
+    assert np.max(np.abs(alt_s - ref)) > 1e-6 * np.max(np.abs(ref))
+
+
+# ---------------------------------------------------------------- forward-error certificate
+
+@pytest.mark.parametrize("recipe,margin", [("cd", 0.1), ("sym", 1e-3)])
+def test_diag_dominance_margin_of_generated_systems(orc, recipe, margin):
+    # both recipes give every row a_P = sum(in-grid a_nb) + margin with a_nb >= 0, so the
+    # smallest row excess a_P - sum |a_nb| is the margin itself, up to the rounding of a_P
+    from oracle import oracle as O
+    g = W.Grid(9, 7, 6)
+    diags = W.coefficients(g, recipe, W.rng_for(0, 7))
+    m = O.diag_dominance_margin(g.shape, diags)
+    assert abs(m - margin) <= 16 * EPS * float(np.max(diags[0]))
+    # brute force over the dense matrix: the same minimum row excess
+    A = orc.dense(g.shape, diags)
+    excess = np.abs(np.diag(A)) - (np.sum(np.abs(A), axis=1) - np.abs(np.diag(A)))
+    assert abs(m - float(np.min(excess))) <= 16 * EPS * float(np.max(diags[0]))
+
+
+def test_diag_dominance_margin_ignores_outward_slots_and_finds_the_worst_row(orc):
+    from oracle import oracle as O
+    g = W.Grid(5, 4, 3)
+    diags = W.random_general(g, seed=12, diag_shift=0.25)   # outward slots hold nonzero junk
+    A = orc.dense(g.shape, diags)
+    excess = np.abs(np.diag(A)) - (np.sum(np.abs(A), axis=1) - np.abs(np.diag(A)))
+    np.testing.assert_allclose(excess, 0.25, rtol=0, atol=32 * EPS * float(np.max(diags[0])))
+    # make one row the worst: raise a single in-grid link of cell (2, 1, 1)
+    c = 2 + 5 * (1 + 4 * 1)
+    bumped = [d.copy() for d in diags]
+    bumped[5][c] += 0.2   # its T link (k + 1 = 2 is inside the grid)
+    assert abs(O.diag_dominance_margin(g.shape, bumped) - 0.05) <= 64 * EPS
+    bumped = [d.copy() for d in diags]
+    bumped[2][0] += 0.2   # the W slot of cell i = 0 points out of the grid: no change
+    assert abs(O.diag_dominance_margin(g.shape, bumped) - 0.25) <= 64 * EPS
+
+
+def test_forward_error_certificate_bounds_the_true_error(orc):
+    # Varah (1975): ||A^-1||_inf <= 1 / margin for a strictly row-dominant A, so
+    # ||x - A^-1 b||_inf <= ||b - A x||_inf / margin for any x
+    g = W.Grid(6, 5, 4)
+    s = W.make_set(0, 0, grid=g)
+    A = orc.dense(g.shape, s["diags"])
+    assert np.max(np.sum(np.abs(np.linalg.inv(A)), axis=1)) <= 1.0 / 0.1 * (1 + 1e-12)
+    b = A @ s["x_star"]
+    xd = np.linalg.solve(A, b)
+    rng = np.random.default_rng(5)
+    for scale in (1e-3, 1e-8):
+        x = xd + scale * rng.standard_normal(g.n)
+        cert = orc.forward_error_certificate(g.shape, s["diags"], b, x)
+        err = float(np.max(np.abs(x - xd)))
+        assert err <= cert * (1 + 1e-10)
+        assert cert <= 1e4 * err   # and not vacuous
+    # a diagonal system: the certificate is exact where the residual and the smallest a_P meet
+    ap = np.full(g.n, 2.0)
+    ap[7] = 0.5
+    dg = [ap] + [np.zeros(g.n)] * 6
+    x = np.zeros(g.n)
+    bb = np.zeros(g.n)
+    bb[7] = 1.0
+    assert orc.forward_error_certificate(g.shape, dg, bb, x) == 2.0
