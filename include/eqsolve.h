@@ -75,6 +75,10 @@ typedef struct {
     int32_t outer;   /* refinement steps (FP32 forms), restarts (FP64) */
     int32_t flags;   /* EQS_INFO_* bits describing how the solve ran */
     double rel_res;  /* ||b - A x||_2 / ||b||_2 of the returned x, in FP64 */
+    int32_t sigma_restarts; /* fresh starts the single-sync iteration took when its expanded (r^, M p)
+                               parted from the directly summed one (all inner solves of the FP32 forms;
+                               at most 32 per BiCGSTAB solve, then that solve reports breakdown) */
+    int32_t reserved;
 } eqs_info;
 
 /*

@@ -101,7 +101,7 @@ struct eqs_ctx {
     bool sync1 = true;
     // exactly symmetric sets take the symmetric form of the single-sync step (EQS_SYM=0: never)
     int sym_on = 1;
-    std::vector<SetHost> sets;
+    SetHost sets[kMaxSets] = {};
     SetDesc *h_desc = nullptr;
     SetDesc *d_desc = nullptr;
     SolveState *h_state = nullptr;
@@ -188,6 +188,53 @@ void set_tiling(SetHost &s, int cpt, int kc, int nflat) {
 size_t max_partials(const SetHost &s) {
     const long long tiles = (long long)((s.plane + kBlock - 1) / kBlock) * s.g.nz;  // cpt = 1, KC = 1
     return (size_t)std::max<long long>(tiles, kMaxFlatBlocks);
+}
+
+// device workspace of one set: the FP64 vectors and scaled coefficients (18 arrays), for the
+// FP32 forms their FP32 counterparts (21 arrays), `partial_rows` rows of reduction partials and
+// the ticket counter
+size_t set_ws_bytes(const SetHost &h, bool f32, size_t partial_rows) {
+    size_t bytes = 18 * align_up((size_t)h.n * 8);   // r, r^, p[2], v[2], t, y, 6 scaled coefficients, s1, t1, f, 1/a_P
+    if (f32) bytes += 21 * align_up((size_t)h.n * 4);  // the same in FP32 (d = the inner iterate), a_E, a_N, a_T
+    bytes += align_up(partial_rows * kMaxRed * 8);
+    bytes += kAlign;  // counter
+    return bytes;
+}
+
+// lay the set's workspace out from q (set_ws_bytes(h, f32, partial_rows) bytes, 256-byte aligned)
+void carve_set(SetHost &h, char *q, bool f32, size_t partial_rows) {
+    auto take = [&](size_t nb) { char *r = q; q += align_up(nb); return r; };
+    h.r = (double *)take((size_t)h.n * 8);
+    h.rh = (double *)take((size_t)h.n * 8);
+    h.p[0] = (double *)take((size_t)h.n * 8);
+    h.p[1] = (double *)take((size_t)h.n * 8);
+    h.v[0] = (double *)take((size_t)h.n * 8);
+    h.v[1] = (double *)take((size_t)h.n * 8);
+    h.t = (double *)take((size_t)h.n * 8);
+    h.y = (double *)take((size_t)h.n * 8);
+    for (int k = 0; k < 6; ++k) h.as[k] = (double *)take((size_t)h.n * 8);
+    h.s1 = (double *)take((size_t)h.n * 8);
+    h.t1 = (double *)take((size_t)h.n * 8);
+    h.f = (double *)take((size_t)h.n * 8);
+    h.dinv = (double *)take((size_t)h.n * 8);
+    if (f32) {
+        for (int k = 0; k < 4; ++k) h.sym32[k] = (float *)take((size_t)h.n * 4);
+        for (int k = 0; k < 6; ++k) h.as32[k] = (float *)take((size_t)h.n * 4);
+        h.r32 = (float *)take((size_t)h.n * 4);
+        h.rh32 = (float *)take((size_t)h.n * 4);
+        h.p32[0] = (float *)take((size_t)h.n * 4);
+        h.p32[1] = (float *)take((size_t)h.n * 4);
+        h.v32[0] = (float *)take((size_t)h.n * 4);
+        h.v32[1] = (float *)take((size_t)h.n * 4);
+        h.t32 = (float *)take((size_t)h.n * 4);
+        h.d32 = (float *)take((size_t)h.n * 4);
+        h.s1_32 = (float *)take((size_t)h.n * 4);
+        h.t1_32 = (float *)take((size_t)h.n * 4);
+        h.f32 = (float *)take((size_t)h.n * 4);
+    }
+    h.partials = (double *)take(partial_rows * kMaxRed * 8);
+    h.counter = (uint32_t *)take(kAlign);
+    h.last_iters = -1;
 }
 
 void fill_desc(eqs_ctx *c, int s) {
@@ -565,6 +612,8 @@ void write_info(eqs_ctx *c, int s, eqs_info *info) {
     info->iters = st.iters;
     info->outer = (st.mode == MODE_REFINE || st.mode == MODE_FP32) ? st.outer : st.restarts;
     info->flags = c->sets[s].form_sym ? EQS_INFO_SYMMETRIC : 0;
+    info->sigma_restarts = st.sig_restarts;
+    info->reserved = 0;
     if (st.zero_rhs)
         info->rel_res = 0.0;
     else if (st.bb_outer > 0)
@@ -884,6 +933,35 @@ int apply_tuning(eqs_ctx *c, int cpt, const std::vector<TuneEntry> &e) {
     return upload_desc(c, 0, c->nsets);
 }
 
+// The iteration scheme (c->sync1, c->sym_on) and cells per thread of a context for these grids,
+// before any tuning: the single-sync iteration (EQS_SYNC=3 selects the three-launch one) where
+// its wider planes fit in LDS, with the narrower segment if need be.  Returns the cells per
+// thread, or -1 if nx is beyond what one LDS plane buffer or the halo slots cover.
+int default_shape(eqs_ctx *c, const eqs_grid *grids, int nsets, int *max_nx_out) {
+    int max_nx = 1;
+    long long max_plane = 1;
+    for (int s = 0; s < nsets; ++s) {
+        max_nx = std::max(max_nx, grids[s].nx);
+        max_plane = std::max(max_plane, (long long)grids[s].nx * grids[s].ny);
+    }
+    int cpt = env_int("EQS_CPT", 0);
+    if (cpt != 1 && cpt != 2) cpt = max_plane >= 4 * kBlock ? 2 : 1;
+    while (cpt > 1 && march_lds_bytes(cpt, max_nx, 8) > kMaxLds) cpt /= 2;
+    c->sym_on = env_int("EQS_SYM", 1) != 0 ? 1 : 0;
+    c->sync1 = env_int("EQS_SYNC", 1) != 3 && halo_slots(max_nx) > 0 && halo_slots(max_nx) <= 4;
+    if (c->sync1) {
+        int fc = cpt;
+        while (fc > 1 && fused_lds_bytes(fc, max_nx, 8) > kMaxLds) fc /= 2;
+        if (fused_lds_bytes(fc, max_nx, 8) > kMaxLds)
+            c->sync1 = false;
+        else
+            cpt = fc;
+    }
+    *max_nx_out = max_nx;
+    if (march_lds_bytes(cpt, max_nx, 8) > kMaxLds || halo_slots(max_nx) < 0) return -1;
+    return cpt;
+}
+
 }  // namespace
 
 extern "C" {
@@ -907,28 +985,8 @@ int eqsolve_create(eqs_ctx **out, const eqs_grid *grids, int32_t nsets, int32_t 
     if (hipGetDevice(&c->device) != hipSuccess) { delete c; return EQS_ERR_HIP; }
 
     int max_nx = 1;
-    long long max_plane = 1;
-    for (int s = 0; s < nsets; ++s) {
-        max_nx = std::max(max_nx, grids[s].nx);
-        max_plane = std::max(max_plane, (long long)grids[s].nx * grids[s].ny);
-    }
-    int cpt = env_int("EQS_CPT", 0);
-    if (cpt != 1 && cpt != 2) cpt = max_plane >= 4 * kBlock ? 2 : 1;
-    while (cpt > 1 && march_lds_bytes(cpt, max_nx, 8) > kMaxLds) cpt /= 2;
-    // single-sync iteration (EQS_SYNC=3 selects the three-launch one) where its
-    // wider planes fit in LDS; it may need the narrower segment
-    c->sym_on = env_int("EQS_SYM", 1) != 0 ? 1 : 0;
-    c->sync1 = env_int("EQS_SYNC", 1) != 3 && halo_slots(max_nx) > 0 && halo_slots(max_nx) <= 4;
-    if (c->sync1) {
-        int fc = cpt;
-        while (fc > 1 && fused_lds_bytes(fc, max_nx, 8) > kMaxLds) fc /= 2;
-        if (fused_lds_bytes(fc, max_nx, 8) > kMaxLds)
-            c->sync1 = false;
-        else
-            cpt = fc;
-    }
-    // nx beyond what one LDS plane buffer or the halo slots cover
-    if (march_lds_bytes(cpt, max_nx, 8) > kMaxLds || halo_slots(max_nx) < 0) { delete c; return EQS_ERR_ARG; }
+    int cpt = default_shape(c, grids, nsets, &max_nx);
+    if (cpt < 0) { delete c; return EQS_ERR_ARG; }
     // a tuning cache (EQS_TUNE_CACHE) entry for every set, with one common cpt, overrides the defaults
     std::vector<TuneEntry> tuned(nsets);
     bool tuned_ok = getenv("EQS_TUNE_CACHE") != nullptr && env_int("EQS_CPT", 0) == 0 && env_int("EQS_KC", 0) == 0;
@@ -947,7 +1005,6 @@ int eqsolve_create(eqs_ctx **out, const eqs_grid *grids, int32_t nsets, int32_t 
     c->cpt = cpt;
     c->max_nx = max_nx;
 
-    c->sets.resize(nsets);
     size_t bytes = 0;
     const bool f32 = precision != EQS_FP64;
     std::vector<size_t> base(nsets);
@@ -960,10 +1017,7 @@ int eqsolve_create(eqs_ctx **out, const eqs_grid *grids, int32_t nsets, int32_t 
         choose_tiling(h, cpt);
         if (tuned_ok) set_tiling(h, tuned_cpt, tuned[s].kc, tuned[s].nflat);
         base[s] = bytes;
-        bytes += 18 * align_up((size_t)h.n * 8);   // r, r^, p[2], v[2], t, y, 6 scaled coefficients, s1, t1, f, 1/a_P
-        if (f32) bytes += 21 * align_up((size_t)h.n * 4);  // the same in FP32 (d = the inner iterate), a_E, a_N, a_T
-        bytes += align_up(max_partials(h) * kMaxRed * 8);
-        bytes += kAlign;  // counter
+        bytes += set_ws_bytes(h, f32, max_partials(h));
     }
     c->ws_bytes = bytes;
     if (hipMalloc(&c->ws, bytes) != hipSuccess) { (void)hipGetLastError(); delete c; return EQS_ERR_NOMEM; }
@@ -980,39 +1034,7 @@ int eqsolve_create(eqs_ctx **out, const eqs_grid *grids, int32_t nsets, int32_t 
     char *w = (char *)c->ws;
     for (int s = 0; s < nsets; ++s) {
         SetHost &h = c->sets[s];
-        char *q = w + base[s];
-        auto take = [&](size_t nb) { char *r = q; q += align_up(nb); return r; };
-        h.r = (double *)take((size_t)h.n * 8);
-        h.rh = (double *)take((size_t)h.n * 8);
-        h.p[0] = (double *)take((size_t)h.n * 8);
-        h.p[1] = (double *)take((size_t)h.n * 8);
-        h.v[0] = (double *)take((size_t)h.n * 8);
-        h.v[1] = (double *)take((size_t)h.n * 8);
-        h.t = (double *)take((size_t)h.n * 8);
-        h.y = (double *)take((size_t)h.n * 8);
-        for (int k = 0; k < 6; ++k) h.as[k] = (double *)take((size_t)h.n * 8);
-        h.s1 = (double *)take((size_t)h.n * 8);
-        h.t1 = (double *)take((size_t)h.n * 8);
-        h.f = (double *)take((size_t)h.n * 8);
-        h.dinv = (double *)take((size_t)h.n * 8);
-        if (f32) {
-            for (int k = 0; k < 4; ++k) h.sym32[k] = (float *)take((size_t)h.n * 4);
-            for (int k = 0; k < 6; ++k) h.as32[k] = (float *)take((size_t)h.n * 4);
-            h.r32 = (float *)take((size_t)h.n * 4);
-            h.rh32 = (float *)take((size_t)h.n * 4);
-            h.p32[0] = (float *)take((size_t)h.n * 4);
-            h.p32[1] = (float *)take((size_t)h.n * 4);
-            h.v32[0] = (float *)take((size_t)h.n * 4);
-            h.v32[1] = (float *)take((size_t)h.n * 4);
-            h.t32 = (float *)take((size_t)h.n * 4);
-            h.d32 = (float *)take((size_t)h.n * 4);
-            h.s1_32 = (float *)take((size_t)h.n * 4);
-            h.t1_32 = (float *)take((size_t)h.n * 4);
-            h.f32 = (float *)take((size_t)h.n * 4);
-        }
-        h.partials = (double *)take(max_partials(h) * kMaxRed * 8);
-        h.counter = (uint32_t *)take(kAlign);
-        h.last_iters = -1;
+        carve_set(h, w + base[s], f32, max_partials(h));
         fill_desc(c, s);
     }
     // zero counters and states once (kernels leave every counter at zero)
@@ -1298,7 +1320,7 @@ int eqsolve_autotune(eqs_ctx *c, const char *cache_path, int32_t iters) {
     iters = std::min(iters, 64);
     const std::string arch = arch_name(c->device);
     size_t nmax = 0;
-    for (const SetHost &h : c->sets) nmax = std::max(nmax, (size_t)h.n);
+    for (int s = 0; s < c->nsets; ++s) nmax = std::max(nmax, (size_t)c->sets[s].n);
     double *tmp = nullptr;
     if (hipMalloc((void **)&tmp, 9 * nmax * sizeof(double)) != hipSuccess) {
         (void)hipGetLastError();

@@ -68,6 +68,11 @@ struct SolveState {
     int32_t sym;      // the matrix is exactly symmetric (checked per solve): the single-sync step and
                       // the multigrid finest-level passes read a_W, a_S, a_B as a_E, a_N, a_T of the
                       // neighbour
+    // single-sync iteration: restarts forced by the sigma consistency check, over the whole solve
+    // and within the current inner solve (FP32 forms: each refinement step's solve has its own
+    // budget; FP64: the solve's)
+    int32_t sig_restarts;
+    int32_t sig_inner;
 };
 
 struct SetDesc {

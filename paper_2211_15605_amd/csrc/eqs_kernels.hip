@@ -195,6 +195,8 @@ struct FinSetup {  // sums: (b,b), (r,r), #bad a_P
         st->maxit = d->maxit;
         st->iters = 0;
         st->restarts = 0;
+        st->sig_restarts = 0;
+        st->sig_inner = 0;
         st->rho_restarts = 0;
         st->outer = 0;
         st->active = 0;
@@ -312,6 +314,10 @@ struct FinFSetup {
     }
 };
 
+// sigma-consistency restarts one BiCGSTAB solve may take (each inner solve of the refinement has
+// its own budget) before it reports BREAKDOWN
+constexpr int kMaxSigmaRestarts = 32;
+
 // After launch j of the single-sync iteration: sums (f,p_j), (f,v_j), (f,s_j),
 // (f,t_j), (r^,s_j), (r^,t_j), (t_j,s_j), (t_j,t_j), (r_j,r_j), (s_j,s_j), (r^,v_j).
 struct FinFused {
@@ -339,8 +345,10 @@ struct FinFused {
         // from the current iterate instead (r_j = s_j + alpha_j v_j, r^ = r_j).
         const double sd = s[10];
         if (fabs(sd - st->sigma) > sig_tol * fabs(sd)) {
-            if (st->restarts >= 32) { stop_iter(st, ST_BREAKDOWN); return; }
+            if (st->sig_inner >= kMaxSigmaRestarts) { stop_iter(st, ST_BREAKDOWN); return; }
             st->restarts++;
+            st->sig_restarts++;
+            st->sig_inner++;
             st->mat = 4;
             st->need_f = 1;
             return;
@@ -394,6 +402,8 @@ struct FinCast {  // sums: (b,b), #bad, #asymmetric rows
         st->maxit = d->maxit;
         st->iters = 0;
         st->restarts = 0;
+        st->sig_restarts = 0;
+        st->sig_inner = 0;
         st->rho_restarts = 0;
         st->outer = 0;
         st->active = 0;
@@ -422,6 +432,7 @@ struct FinOuter {  // sums: (r,r) in FP64, (r32, r32)
     const SetDesc *d;
     __device__ void operator()(SolveState *st, const double *s) const {
         st->inner_done = 0;
+        st->sig_inner = 0;  // the next inner solve has its own restart budget
         st->outer_pending = 0;
         st->mat = 0;
         const double rr = s[0], rr32 = s[1];

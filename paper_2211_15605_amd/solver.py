@@ -8,6 +8,9 @@ holding nx*ny*nz values (flat, or shaped (nz, ny, nx)); ``b`` and ``x`` are
 likewise.  Arguments are checked here (TypeError / ValueError) before the C
 library is called; the library's own codes come back as ``info["status"]``
 and, unless ``check=False``, as exceptions for status != 0.
+
+Module-level call: ``solve(diags, b, x0, tol, maxit, precision, grid)`` (a
+one-off context per call).
 """
 from __future__ import annotations
 
@@ -209,3 +212,25 @@ class Context:
         if rc != 0:
             raise EqSolveError(rc, "eqsolve_apply")
         return y
+
+
+def _grid_of(diags, grid):
+    if grid is not None:
+        g = tuple(int(v) for v in grid)
+        if len(g) != 3 or min(g) < 1:
+            raise ValueError("grid must be an (nx, ny, nz) triple of positive sizes")
+        return g
+    shp = tuple(diags[0].shape) if len(diags) else ()
+    if len(shp) != 3:
+        raise ValueError("pass grid=(nx, ny, nz), or diagonals shaped (nz, ny, nx)")
+    return (shp[2], shp[1], shp[0])
+
+
+def solve(diags, b, x0=None, tol=1e-10, maxit=1000, precision="fp64", grid=None, check=True):
+    """Solve one system with a context made for it (workspace allocated, then released).
+    grid: (nx, ny, nz), or taken from diagonals shaped (nz, ny, nx).  Returns (x, info)."""
+    g = _grid_of(diags, grid)
+    with Context([g], precision=precision, device=b.device if isinstance(b, torch.Tensor) else None) as ctx:
+        x = torch.zeros_like(b) if x0 is None else x0.clone()
+        return ctx.solve(diags, b, x, tol=tol, maxit=maxit, check=check)
+

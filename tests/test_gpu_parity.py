@@ -434,18 +434,44 @@ def test_autograd_function_backward(torch_dev, orc):
 # regression case of the direct-sigma check and of the refinement's weak-step allowance)
 @pytest.mark.parametrize("scheme", SCHEMES + [dict(EQS_CPT=2, EQS_KC=16, EQS_FLAT_MAX=256)],
                          ids=SCHEME_IDS + ["sync1_kc16_flat256"])
-@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine", "fp32"])
 def test_config1_full_size_residual(torch_dev, orc, precision, scheme):
+    # FP64 and FP32 + refinement to 1e-10; pure FP32 (one FP32 solve of the FP64 system) to 1e-5,
+    # each in the oracle's FP64 residual of the returned x
     torch, dev = torch_dev
     g, diags, b, xs = manufactured(orc, 1)
+    tol = 1e-5 if precision == "fp32" else 1e-10
     ctx = context([g.shape], precision=precision, env=scheme)
-    x, info = ctx.solve(dev_arrays(torch, dev, diags), dev_arrays(torch, dev, [b])[0], tol=1e-10, maxit=20000)
+    x, info = ctx.solve(dev_arrays(torch, dev, diags), dev_arrays(torch, dev, [b])[0], tol=tol, maxit=20000)
     print("config1", precision, info, ctx.layout(), flush=True)
     assert info["status"] == 0
     xg = host(x)
     rel = orc.rel_residual(g.shape, diags, b, xg)
-    assert rel <= 1e-10
+    assert rel <= tol
     assert np.max(np.abs(xg - xs)) <= orc.forward_error_certificate(g.shape, diags, b, xg) * (1 + 1e-6)
+
+
+def test_fp32_refine_sigma_restart_budget_is_per_inner_solve(torch_dev, orc):
+    # A tight sigma consistency threshold makes the FP32 single-sync iteration restart often.
+    # Each inner solve of the refinement has its own budget of 32 restarts, so a solve whose
+    # inner solves restart more than 32 times in all still reaches the FP64 tolerance; the count
+    # is reported in info["sigma_restarts"].
+    torch, dev = torch_dev
+    g, diags, b, xs = manufactured(orc, 1)
+    D = dev_arrays(torch, dev, diags)
+    bd = dev_arrays(torch, dev, [b])[0]
+    seen = []
+    for stol in (3e-4, 1e-4, 3e-5):
+        ctx = context([g.shape], precision="fp32_refine", env=dict(EQS_SIGMA_TOL32=stol))
+        x, info = ctx.solve(D, bd, tol=1e-10, maxit=20000, check=False)
+        ctx.close()
+        print("sigma tol %g:" % stol, info, flush=True)
+        seen.append(info["sigma_restarts"])
+        if info["sigma_restarts"] > 32:
+            assert info["status"] == 0, info
+            assert orc.rel_residual(g.shape, diags, b, host(x)) <= 1e-10
+            return
+    pytest.fail("no threshold forced more than 32 restarts: %s" % seen)
 
 
 def _batched_full_size(torch, dev, orc, cfg, precisions, env=None):
@@ -770,3 +796,80 @@ def test_symmetric_matrix_adjoint_runs_the_transposed_general_form(torch_dev, or
     xw, wi = ctx.solve(D, dev_arrays(torch, dev, [w])[0], tol=1e-13, maxit=5000)
     cert = orc.forward_error_certificate(g.shape, diags, w, lam) + orc.forward_error_certificate(g.shape, diags, w, host(xw))
     assert np.max(np.abs(lam - host(xw))) <= cert * (1 + 1e-6)
+
+
+# ---------------------------------------------------------------- wide rows
+
+# rows of 203..266 cells take the single-sync step with one cell per thread, 257..512 four halo
+# slots per ring (266 the widest single-sync row in FP64, wider rows the three-launch iteration)
+WIDE = [(230, 5, 4), (260, 5, 4), (266, 3, 3), (400, 4, 3)]
+
+
+@pytest.mark.parametrize("shape", WIDE)
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+@pytest.mark.parametrize("scheme", SCHEMES, ids=SCHEME_IDS)
+def test_wide_rows_against_oracle(torch_dev, orc, shape, precision, scheme):
+    torch, dev = torch_dev
+    g, diags, b, xs = manufactured(orc, 0, grid=W.Grid(*shape))
+    tol = 1e-13 if precision == "fp64" else 1e-10
+    ctx = context([g.shape], precision=precision, env=scheme)
+    lay = ctx.layout()
+    print("wide", shape, precision, scheme, lay, flush=True)
+    x, info = ctx.solve(dev_arrays(torch, dev, diags), dev_arrays(torch, dev, [b])[0], tol=tol, maxit=5000)
+    ctx.close()
+    assert info["status"] == 0, info
+    xg = host(x)
+    assert orc.rel_residual(g.shape, diags, b, xg) <= tol
+    if precision == "fp64":
+        xo, _ = orc.bicgstab(g.shape, diags, b, tol=1e-13, maxit=5000)
+        assert np.linalg.norm(xg - xo) <= 1e-10 * np.linalg.norm(xo)
+
+
+# ---------------------------------------------------------------- adjoint against finite differences
+
+def test_adjoint_config3_central_finite_differences(torch_dev, orc):
+    # The adjoint workload (64^3 convection-diffusion, L = sum(w x)): the gradients the GPU adjoint
+    # returns for b and the 7 diagonals, against central differences of GPU forward solves with
+    # h = 1e-6 along sparse Rademacher directions.  The perturbed solves start from the converged x
+    # and run to 1e-15 (or until they stagnate), so the FD quotient is limited by h^2 and by the
+    # solves' rounding, far below 1e-5.
+    torch, dev = torch_dev
+    import math
+    g = W.Grid(64, 64, 64)
+    s = W.make_set(3, 0, grid=g, with_weights=True)
+    diags, w = s["diags"], s["w"]
+    b = orc.apply(g.shape, diags, s["x_star"])
+    ctx = context([g.shape])
+    D = dev_arrays(torch, dev, diags)
+    bd, wd = dev_arrays(torch, dev, [b, w])
+    x, info = ctx.solve(D, bd, tol=1e-15, maxit=3000, check=False)
+    assert info["rel_res"] <= 1e-14, info
+    gb, gd, ainfo = ctx.adjoint(D, x, wd, tol=1e-14, maxit=3000, check=False)
+    assert ainfo["rel_res"] <= 1e-13, ainfo
+    G = [host(gb)] + [host(t) for t in gd]   # dL/db, then P, E, W, N, S, T, B
+    h = 1e-6
+    rng = np.random.default_rng(2211)
+    base = [bd] + D
+    for direction in range(6):
+        # 8192 entries spread over the 8 arrays (b and the diagonals; 0.4 % of their 2.1 M
+        # entries), signs +-1: enough signal that the solves' rounding floor stays far below 1e-5
+        m = 8192
+        arr = rng.integers(0, 8, m)
+        idx = rng.integers(0, g.n, m)
+        sgn = rng.choice([-1.0, 1.0], m)
+        delta = [np.zeros(g.n) for _ in range(8)]
+        for a in range(8):
+            np.add.at(delta[a], idx[arr == a], h * sgn[arr == a])
+        dd = dev_arrays(torch, dev, delta)
+        plus = [t + e for t, e in zip(base, dd)]
+        minus = [t - e for t, e in zip(base, dd)]
+        # first-order change predicted by the adjoint, for the perturbation actually applied
+        pred = math.fsum(math.fsum((G[a] * host(plus[a] - minus[a])).tolist()) for a in range(8))
+        xp, ip = ctx.solve(plus[1:], plus[0], x.clone(), tol=1e-15, maxit=3000, check=False)
+        xm, im = ctx.solve(minus[1:], minus[0], x.clone(), tol=1e-15, maxit=3000, check=False)
+        assert ip["rel_res"] <= 1e-14 and im["rel_res"] <= 1e-14, (ip, im)
+        fd = math.fsum((w * (host(xp) - host(xm))).tolist())
+        print("direction %d: FD %.12e adjoint %.12e rel %.2e (%d, %d iterations)" % (
+            direction, fd, pred, abs(fd - pred) / abs(pred), ip["iters"], im["iters"]), flush=True)
+        assert abs(fd - pred) <= 1e-5 * abs(pred)
+    ctx.close()
