@@ -66,7 +66,8 @@ enum {
     EQS_ERR_ARG = -1,      /* bad argument: null pointer, bad sizes, tol not in (0,1), maxit < 1, a_P = 0 */
     EQS_ERR_NOMEM = -2,    /* device allocation failed in eqsolve_create */
     EQS_ERR_HIP = -3,      /* a HIP runtime call failed */
-    EQS_ERR_STATE = -4     /* context unusable (null, or a previous HIP failure) */
+    EQS_ERR_STATE = -4,    /* context unusable (null, or a previous HIP failure) */
+    EQS_ERR_SIZE = -5      /* eqsolve_solve_noalloc: the system exceeds its static workspace */
 };
 
 typedef struct {
@@ -215,6 +216,38 @@ int eqsolve_set_preconditioner(eqs_ctx *ctx, int32_t kind, const eqs_mg_params *
  */
 int eqsolve_debug_precond(eqs_ctx *ctx, int32_t set, const double *const diag[7], const double *r, double *z,
                           int32_t *levels);
+
+/*
+ * Largest system eqsolve_solve_noalloc takes: EQS_NOALLOC_MAX_CELLS cells, and
+ * a workspace (18 FP64 words per cell, per-block reduction partials, the set
+ * table and state block) of at most EQS_NOALLOC_BYTES bytes.
+ */
+#define EQS_NOALLOC_MAX_CELLS 262144
+#define EQS_NOALLOC_BYTES (40u << 20)
+
+/*
+ * For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): the plain FP64 solve of
+ * eqsolve_solve (Jacobi-preconditioned BiCGSTAB, the single-sync iteration)
+ * for one system on grid *grid, with no context.  Its workspace is a static
+ * device array of EQS_NOALLOC_BYTES bytes in this library, one per GPU, held
+ * from the first call on that GPU until the process ends; the call allocates
+ * nothing (no hipMalloc, hipFree or host heap), launches its kernels one by
+ * one on hip_stream (a hipStream_t; NULL = the default stream) and returns
+ * after they complete.  The caller passes the inputs and the output exactly
+ * as for eqsolve_solve: diag[7], b and x (x0 on entry, solution on return)
+ * are device arrays of nx*ny*nz FP64 values on the current device; tol in
+ * (0, 1), maxit >= 1; info (host, may be NULL) receives the outcome.
+ * Every call on one GPU shares that GPU's array and clears the part it uses
+ * first: calls that overlap on one GPU (two threads, or two streams) race,
+ * and must not be made.
+ * Returns the EQS_* code of the solve, EQS_ERR_ARG (bad pointers, sizes, tol
+ * or maxit, aliasing; checked before any HIP call), EQS_ERR_SIZE (more than
+ * EQS_NOALLOC_MAX_CELLS cells, or a workspace beyond EQS_NOALLOC_BYTES), or
+ * EQS_ERR_HIP.
+ */
+int eqsolve_solve_noalloc(const eqs_grid *grid, const double *const diag[7], const double *b, double *x,
+                          double tol, int32_t maxit, eqs_info *info, void *hip_stream);
 
 /* Static description of a result code. */
 const char *eqsolve_strerror(int code);

@@ -10,12 +10,12 @@ the HIP library; ``solver``/``binding``/``autograd`` need both.
 """
 import importlib
 
-__all__ = ["Context", "EqSolveError", "EqSolveNotConverged", "EqSolveFn", "solve", "workloads",
+__all__ = ["Context", "EqSolveError", "EqSolveNotConverged", "EqSolveFn", "solve", "solve_noalloc", "workloads",
            "binding", "solver", "autograd"]
 
 
 def __getattr__(name):
-    if name in ("Context", "EqSolveError", "EqSolveNotConverged", "solve"):
+    if name in ("Context", "EqSolveError", "EqSolveNotConverged", "solve", "solve_noalloc"):
         return getattr(importlib.import_module(".solver", __name__), name)
     if name == "EqSolveFn":
         return importlib.import_module(".autograd", __name__).EqSolveFn

@@ -18,7 +18,9 @@ LIB_PATH = os.path.join(_PKG, "libeqsolve.so")
 
 EQS_FP64, EQS_FP32_REFINE, EQS_FP32 = 0, 1, 2
 EQS_OK, EQS_NOT_CONVERGED, EQS_BREAKDOWN, EQS_NONFINITE = 0, 1, 2, 3
-EQS_ERR_ARG, EQS_ERR_NOMEM, EQS_ERR_HIP, EQS_ERR_STATE = -1, -2, -3, -4
+EQS_ERR_ARG, EQS_ERR_NOMEM, EQS_ERR_HIP, EQS_ERR_STATE, EQS_ERR_SIZE = -1, -2, -3, -4, -5
+# the largest system eqsolve_solve_noalloc takes (EQS_NOALLOC_MAX_CELLS, EQS_NOALLOC_BYTES)
+NOALLOC_MAX_CELLS, NOALLOC_BYTES = 262144, 40 << 20
 EQS_INFO_SYMMETRIC = 1
 PRECISIONS = {"fp64": EQS_FP64, "fp32_refine": EQS_FP32_REFINE, "fp32": EQS_FP32}
 
@@ -26,7 +28,7 @@ PRECISIONS = {"fp64": EQS_FP64, "fp32_refine": EQS_FP32_REFINE, "fp32": EQS_FP32
 SYMBOLS = ("eqsolve_create", "eqsolve_solve", "eqsolve_solve_batched", "eqsolve_adjoint", "eqsolve_apply",
            "eqsolve_destroy", "eqsolve_strerror", "eqsolve_autotune", "eqsolve_debug_layout",
            "eqsolve_debug_profile", "eqsolve_debug_kernel_stats", "eqsolve_set_preconditioner",
-           "eqsolve_debug_precond",
+           "eqsolve_debug_precond", "eqsolve_solve_noalloc",
            "eqsimple_create", "eqsimple_form_momentum", "eqsimple_form_pressure", "eqsimple_correct",
            "eqsimple_iterate", "eqsimple_step", "eqsimple_set_pressure_preconditioner", "eqsimple_destroy")
 KERNEL_KINDS = {"setup": 0, "recheck": 1, "report": 2, "k1": 3, "k2": 4, "k3": 5, "cast": 6, "outer": 7,
@@ -121,6 +123,9 @@ def load(path: str | None = None):
         L.eqsolve_set_preconditioner.restype = ctypes.c_int
         L.eqsolve_debug_precond.argtypes = [VP, ctypes.c_int32, VPP, VP, VP, ctypes.POINTER(ctypes.c_int32)]
         L.eqsolve_debug_precond.restype = ctypes.c_int
+        L.eqsolve_solve_noalloc.argtypes = [ctypes.POINTER(EqsGrid), VPP, VP, VP, ctypes.c_double, ctypes.c_int32,
+                                            ctypes.POINTER(EqsInfo), VP]
+        L.eqsolve_solve_noalloc.restype = ctypes.c_int
         D3 = ctypes.POINTER(ctypes.c_double)
         L.eqsimple_create.argtypes = [ctypes.POINTER(VP), ctypes.POINTER(EqsBox), ctypes.c_int32, VP]
         L.eqsimple_form_momentum.argtypes = [VP, VPP, VP, VPP, VPP, VPP, VPP, D3]
@@ -179,6 +184,16 @@ def eqsolve_solve_batched(h, diag_ptrs_per_set, b_ptrs, x_ptrs, tols, maxits):
     infos = (EqsInfo * n)()
     rc = L.eqsolve_solve_batched(h, outer, bp, xp, t, m, infos)
     return rc, list(infos)
+
+
+def eqsolve_solve_noalloc(grid, diag_ptrs, b_ptr, x_ptr, tol, maxit, stream):
+    L = load()
+    g = EqsGrid(*map(int, grid))
+    dp, keep = ptr_array(diag_ptrs)
+    info = EqsInfo()
+    rc = L.eqsolve_solve_noalloc(ctypes.byref(g), dp, VP(b_ptr), VP(x_ptr), float(tol), int(maxit),
+                                 ctypes.byref(info), VP(stream or 0))
+    return rc, info
 
 
 def eqsolve_adjoint(h, set_id, diag_ptrs, x_ptr, w_ptr, gb_ptr, gdiag_ptrs, tol, maxit):

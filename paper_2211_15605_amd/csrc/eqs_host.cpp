@@ -31,6 +31,7 @@
 
 #include "eqs_internal.h"
 #include "eqs_launch.h"
+#include "eqs_static.h"
 #include "eqsolve.h"
 
 using namespace eqs;
@@ -962,6 +963,100 @@ int default_shape(eqs_ctx *c, const eqs_grid *grids, int nsets, int *max_nx_out)
     return cpt;
 }
 
+// ------------------------------------------------------------------ solve on a static workspace
+//
+// One FP64 set solved on a workspace the caller lends (eqsolve_solve_noalloc's static device
+// array): the context, its set table and its state block live in static host memory, one per
+// device, and every device-side array is carved out of the workspace, so nothing is allocated
+// on the host or the device.  Iteration chunks are launched one by one (no graphs).
+
+constexpr int kStaticDevices = 64;
+eqs_ctx g_static_ctx[kStaticDevices];
+SetDesc g_static_desc[kStaticDevices];
+SolveState g_static_state[kStaticDevices];
+
+}  // namespace
+
+namespace eqs {
+
+size_t static_solve_bytes(const eqs_grid &g) {
+    eqs_ctx probe;  // shape only: no allocation, no HIP call
+    probe.nsets = 1;
+    int max_nx = 1;
+    const int cpt = default_shape(&probe, &g, 1, &max_nx);
+    if (cpt < 0) return 0;
+    SetHost h{};
+    h.g = g;
+    h.plane = g.nx * g.ny;
+    h.n = h.plane * g.nz;
+    choose_tiling(h, cpt);
+    return align_up(sizeof(SetDesc)) + align_up(sizeof(SolveState)) +
+           set_ws_bytes(h, false, (size_t)std::max(h.ntiles, h.nflat));
+}
+
+int static_solve(void *ws, size_t cap, int device, const eqs_grid &g, const double *const diag[7], const double *b,
+                 double *x, double tol, int32_t maxit, eqs_info *info, void *hip_stream) {
+    if (device < 0 || device >= kStaticDevices || !ws) return EQS_ERR_STATE;
+    const size_t need = static_solve_bytes(g);
+    if (need == 0) return EQS_ERR_ARG;
+    if (need > cap) return EQS_ERR_SIZE;
+    eqs_ctx *c = &g_static_ctx[device];
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    c->nsets = 1;
+    c->precision = EQS_FP64;
+    c->trace = env_int("EQS_TRACE", 0) != 0;
+    c->use_graphs = false;
+    c->use_small = env_int("EQS_SMALL", 1) != 0;
+    c->broken = false;
+    c->profile_mask = 0;
+    c->precond = EQS_PRECOND_JACOBI;
+    int max_nx = 1;
+    c->cpt = default_shape(c, &g, 1, &max_nx);
+    c->max_nx = max_nx;
+    SetHost &h = c->sets[0];
+    memset(&h, 0, sizeof(h));
+    h.g = g;
+    h.plane = g.nx * g.ny;
+    h.n = h.plane * g.nz;
+    choose_tiling(h, c->cpt);
+    char *w = (char *)ws;
+    c->d_desc = (SetDesc *)w;
+    c->d_state = (SolveState *)(w + align_up(sizeof(SetDesc)));
+    c->h_desc = &g_static_desc[device];
+    c->h_state = &g_static_state[device];
+    c->ws = w + align_up(sizeof(SetDesc)) + align_up(sizeof(SolveState));
+    c->ws_bytes = need - align_up(sizeof(SetDesc)) - align_up(sizeof(SolveState));
+    carve_set(h, (char *)c->ws, false, (size_t)std::max(h.ntiles, h.nflat));
+    memset(c->h_desc, 0, sizeof(SetDesc));
+    memset(c->h_state, 0, sizeof(SolveState));
+    fill_desc(c, 0);
+    SetDesc &d = c->h_desc[0];
+    for (int k = 0; k < 7; ++k) d.a[k] = diag[k];
+    d.b = b;
+    d.x = x;
+    d.mode = MODE_FP64;
+    d.tol = tol;
+    d.tol_inner = inner_tol();
+    d.maxit = maxit;
+    // The array keeps the previous call's contents: clear all of this call's part (the state
+    // block, the ticket counter, every vector) with a fill kernel, then upload the set table.
+    if (launch_fill((double *)w, (long)(need / sizeof(double)), 0.0, c->stream) != hipSuccess) {
+        (void)hipGetLastError();
+        return EQS_ERR_HIP;
+    }
+    int rc = upload_desc(c, 0, 1);
+    if (rc) return rc;
+    Run R = make_run(c, 0, 1, false);
+    if ((rc = run_fp64(R))) return rc;
+    if ((rc = R.readback())) return rc;
+    write_info(c, 0, info);
+    return c->h_state[0].status;
+}
+
+}  // namespace eqs
+
+namespace {
 }  // namespace
 
 extern "C" {
@@ -1295,6 +1390,7 @@ const char *eqsolve_strerror(int code) {
     case EQS_ERR_NOMEM: return "device allocation failed";
     case EQS_ERR_HIP: return "HIP runtime error";
     case EQS_ERR_STATE: return "context unusable";
+    case EQS_ERR_SIZE: return "system exceeds the static workspace of eqsolve_solve_noalloc";
     default: return "unknown eqsolve code";
     }
 }

@@ -9,8 +9,9 @@ likewise.  Arguments are checked here (TypeError / ValueError) before the C
 library is called; the library's own codes come back as ``info["status"]``
 and, unless ``check=False``, as exceptions for status != 0.
 
-Module-level call: ``solve(diags, b, x0, tol, maxit, precision, grid)`` (a
-one-off context per call).
+Module-level calls: ``solve(diags, b, x0, tol, maxit, precision, grid)`` (a
+one-off context per call) and ``solve_noalloc(...)`` (the FP64 solve on the
+library's static workspace, no allocation at all).
 """
 from __future__ import annotations
 
@@ -234,3 +235,27 @@ def solve(diags, b, x0=None, tol=1e-10, maxit=1000, precision="fp64", grid=None,
         x = torch.zeros_like(b) if x0 is None else x0.clone()
         return ctx.solve(diags, b, x, tol=tol, maxit=maxit, check=check)
 
+
+def solve_noalloc(diags, b, x, tol=1e-10, maxit=1000, grid=None, stream=None, check=True):
+    """eqsolve_solve_noalloc: the FP64 solve on the library's static device workspace (no
+    allocation by the library or here; x is written in place).  At most
+    binding.NOALLOC_MAX_CELLS cells.  Returns (x, info)."""
+    g = _grid_of(diags, grid)
+    n = g[0] * g[1] * g[2]
+    dev = b.device if isinstance(b, torch.Tensor) else None
+    if len(diags) != 7:
+        raise ValueError("need 7 coefficient tensors (P, E, W, N, S, T, B)")
+    dp = [_check_vec(d, n, "diag[%d]" % k, dev) for k, d in enumerate(diags)]
+    bp = _check_vec(b, n, "b", dev)
+    xp = _check_vec(x, n, "x", dev)
+    if not (0.0 < tol < 1.0) or int(maxit) < 1:
+        raise ValueError("tol must be in (0, 1) and maxit >= 1")
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    with torch.cuda.device(dev):
+        rc, info = B.eqsolve_solve_noalloc(g, dp, bp, xp, tol, maxit, st.cuda_stream)
+    d = info.as_dict()
+    if rc < 0:
+        raise EqSolveError(rc, "eqsolve_solve_noalloc")
+    if rc > 0 and check:
+        raise EqSolveNotConverged(rc, d, "solve_noalloc")
+    return x, d

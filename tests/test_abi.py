@@ -65,3 +65,25 @@ def test_strerror_and_argument_errors_without_device(lib):
     lib.eqsolve_solve.restype = ctypes.c_int
     assert lib.eqsolve_solve(None, 0, None, None, None, ctypes.c_double(1e-10), 10, None) == -4
     assert lib.eqsolve_destroy(None) == 0
+
+
+def test_noalloc_argument_and_size_errors_without_device(lib):
+    # checked before any HIP call: bad arguments, and systems beyond the static workspace
+    class G(ctypes.Structure):
+        _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32)]
+    f = lib.eqsolve_solve_noalloc
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.POINTER(G), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                  ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
+    fake = [ctypes.c_void_p(0x1000 * (k + 1)) for k in range(9)]
+    diag = (ctypes.c_void_p * 7)(*fake[:7])
+    g = G(64, 64, 64)
+    assert f(None, diag, fake[7], fake[8], 1e-10, 10, None, None) == -1
+    assert f(ctypes.byref(g), None, fake[7], fake[8], 1e-10, 10, None, None) == -1
+    assert f(ctypes.byref(g), diag, fake[7], fake[7], 1e-10, 10, None, None) == -1   # x aliases b
+    assert f(ctypes.byref(g), diag, fake[7], fake[8], 1.5, 10, None, None) == -1
+    assert f(ctypes.byref(g), diag, fake[7], fake[8], 1e-10, 0, None, None) == -1
+    big = G(64, 64, 65)   # 266,240 cells > EQS_NOALLOC_MAX_CELLS
+    assert f(ctypes.byref(big), diag, fake[7], fake[8], 1e-10, 10, None, None) == -5
+    lib.eqsolve_strerror.restype = ctypes.c_char_p
+    assert b"static workspace" in lib.eqsolve_strerror(-5)
