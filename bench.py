@@ -1,19 +1,26 @@
 #!/usr/bin/env python
 """Benchmark of the equation-set solve on one MI355X; prints one JSON line.
 
-Workload (default): the pressure-correction-like symmetric 7-point system on
-128 x 256 x 128 cells (near-singular, a_P = sum a_nb + 1e-3), b = A x* with
-x* ~ U[-1, 1], x0 = 0, relative tolerance 1e-10.  One step is the whole hot
-path on that system: a plain FP64 Jacobi-BiCGSTAB solve, then an FP32-inner /
-FP64-refinement solve, each from x0 = 0 to ||b - A x|| <= 1e-10 ||b||.
+Workload (default): the large tall bed, four 7-point convection-diffusion
+systems of 192 x 768 x 192 cells (113 M cells, the four equation sets of a
+time step), b = A x* with x* ~ U[-1, 1], x0 = 0, relative tolerance 1e-10.
+One step is the whole hot path on that batch: all four sets in one batched
+FP64 Jacobi-BiCGSTAB call, then all four in one FP32-inner / FP64-refinement
+call, each to ||b - A x|| <= 1e-10 ||b||.  The same four sets solved one after
+another in plain FP64 are timed beside them (untimed by the step clock).
 
-  value      FP64 BiCGSTAB cell-iterations per second (cells x iterations /
-             solve time, setup and exit recheck included), inputs resident in HBM
-  roofline   the dominant kernel (FP64 K1: p update + Jacobi + stencil product
-             + dot), algorithmic bytes per launch / mean launch time from HIP
-             events on the solver's stream, against 8 TB/s
-  cpu_baseline  the CPU oracle (plain C, OpenMP) on the same system, a bounded
-             number of iterations
+  value      FP64 BiCGSTAB cell-iterations per second of the batched call
+             (sum over sets of cells x iterations / solve time, setup and exit
+             recheck included), inputs resident in HBM
+  roofline   the dominant kernel (the FP64 single-sync step, batched launch):
+             algorithmic bytes per launch / mean launch time from HIP events on
+             the solver's stream, against 8 TB/s; traffic from the committed
+             rocprofv3 FETCH_SIZE / WRITE_SIZE record of the same code object
+  cpu_baseline  the CPU oracle (plain C, OpenMP) solving the same systems; its
+             solutions also give each GPU result's error and Eq. (6) digits
+
+--config 1 selects the pressure-like 128 x 256 x 128 system (one set); the
+default run also reports it as a section.
 """
 from __future__ import annotations
 
@@ -50,23 +57,35 @@ def step_words(syncs, symmetric):
     return WORDS["k1"], STEP_WORDS[syncs]
 
 
-def kernel_source_digest():
+def code_object_digest(lib=None):
+    """sha256 of the device code the library carries (its .hip_fatbin ELF section): it changes
+    with any change to a kernel, and not with host-only changes."""
     import hashlib
-    h = hashlib.sha256()
-    for f in ("eqs_kernels.hip", "eqs_internal.h"):
-        h.update(open(os.path.join(ROOT, "paper_2211_15605_amd", "csrc", f), "rb").read())
-    return h.hexdigest()
+    import struct
+    data = open(lib or os.path.join(ROOT, "paper_2211_15605_amd", "libeqsolve.so"), "rb").read()
+    shoff, = struct.unpack_from("<Q", data, 0x28)
+    shentsize, shnum, shstrndx = struct.unpack_from("<HHH", data, 0x3A)
+    secs = [struct.unpack_from("<IIQQQQ", data, shoff + i * shentsize) for i in range(shnum)]
+    stroff = secs[shstrndx][4]
+    for name, _t, _f, _a, off, size in secs:
+        if data[stroff + name: data.index(b"\0", stroff + name)] == b".hip_fatbin":
+            return hashlib.sha256(data[off:off + size]).hexdigest()
+    raise RuntimeError("no .hip_fatbin section in the library")
 
 
-def measured_traffic(cfg, kern):
-    """HBM bytes per launch of the FP64 iteration kernel `kern` from the committed
-    rocprofv3 counter record (FETCH_SIZE + WRITE_SIZE, scaled by a 1 GiB copy), or
-    None when the kernel source has changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "%s_fp64_sym128x256x128_traffic.json" % kern)
-    if cfg != 1 or not os.path.exists(path):
+def traffic_record_path(workload, kern):
+    return os.path.join(ROOT, "profiles", "%s_%s_traffic.json" % (kern, workload))
+
+
+def measured_traffic(workload, kern):
+    """HBM bytes per launch of the FP64 iteration kernel `kern` on `workload` from the committed
+    rocprofv3 counter record (FETCH_SIZE + WRITE_SIZE, scaled by a 1 GiB copy), or None when the
+    record is missing or was taken with other device code than the library holds now."""
+    path = traffic_record_path(workload, kern)
+    if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    if rec.get("kernel_source_sha256") != kernel_source_digest():
+    if rec.get("code_object_sha256") != code_object_digest():
         return None
     return rec["bytes_per_launch"]
 
@@ -310,17 +329,34 @@ def time_latency(runs=10, warm=3):
             "iters": info["iters"], "us_per_iteration": us / max(info["iters"], 1), "status": info["status"]}
 
 
-def gpu_leg(args):
+def copy_calibration(res, dev):
+    """A plain copy of known size, for scaling the HBM byte counters of a profiled run."""
+    import torch
+    nb = 1 << 30
+    src = torch.ones(nb // 8, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    res["copy_calibration_bytes"] = {"read": nb, "write": nb}
+    del src, dst
+
+
+def gpu_leg(args, cfg_id, steps=None, warmup=None, with_mg=True):
+    """One set (the pressure-like 128 x 256 x 128 system): FP64 and FP32 + refinement solves per step.
+    Returns (result dict, host solutions {"fp64": [x], "fp32_refine": [x]})."""
     import numpy as np
     import torch
 
     from paper_2211_15605_amd import workloads as W
     from paper_2211_15605_amd.solver import Context
 
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
     dev = torch.device("cuda", 0)
-    cfg = W.CONFIGS[args.config]
+    cfg = W.CONFIGS[cfg_id]
     g = cfg["grids"][0]
-    s = W.make_set(args.config, 0)
+    s = W.make_set(cfg_id, 0)
     D = [torch.from_numpy(d).to(dev) for d in s["diags"]]
     xs = torch.from_numpy(s["x_star"]).to(dev)
     del s
@@ -347,7 +383,7 @@ def gpu_leg(args):
             rec.append((t1 - t0, t2 - t1, i64, i32))
         return x64, x32
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step(None)
     # the dominant kernel: the fused step (single-sync iteration) or K1 (three launches per step)
     syncs = c64.layout()["syncs"]
@@ -358,7 +394,7 @@ def gpu_leg(args):
     rec = []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         x64, x32 = step(rec)
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
@@ -368,13 +404,9 @@ def gpu_leg(args):
     t32 = float(np.mean([r[1] for r in rec]))
     it64 = float(np.mean([r[2]["iters"] for r in rec]))
     it32 = float(np.mean([r[3]["iters"] for r in rec]))
-    kstats = {}
-    for k in (kern,):
-        cnt, ms = c64.kernel_stats(k)
-        if cnt:
-            kstats[k] = (cnt, ms)
     # the library counts only launches that did work (not the few enqueued past convergence)
-    k1_cnt, k1_ms = kstats[kern]
+    k1_cnt, k1_ms = c64.kernel_stats(kern)
+    c64.profile([])
     k1_avg_ms = k1_ms / k1_cnt
     form_sym = bool(rec[-1][2]["symmetric"])
     kw, sw = step_words(syncs, form_sym)
@@ -382,51 +414,47 @@ def gpu_leg(args):
     achieved = k1_bytes / (k1_avg_ms * 1e-3) / 1e9
     err64 = float(torch.max(torch.abs(x64 - xs)))
     err32 = float(torch.max(torch.abs(x32 - xs)))
-    tmg, (xmg, img), mgp = time_mg(Context, [g.shape], lambda cm: cm.solve(D, b, torch.zeros_like(b), tol=tol,
-                                                                           maxit=maxit, check=False), args.config)
     res = {
+        "workload": cfg["name"],
         "value": n * it64 / t64,
-        "ms_per_step": 1e3 * t_total / args.steps,
+        "ms_per_step": 1e3 * t_total / steps,
         "fp64": {"time_to_tol_ms": 1e3 * t64, "iters": it64, "status": rec[-1][2]["status"], "rel_res": rec[-1][2]["rel_res"],
                  "cell_iters_per_s": n * it64 / t64, "model_GBps": n * it64 * sw * 8 / t64 / 1e9,
                  "max_abs_err_vs_xstar": err64},
         "fp32_refine": {"time_to_tol_ms": 1e3 * t32, "inner_iters": it32, "outer": rec[-1][3]["outer"],
-                        "status": rec[-1][3]["status"],
+                        "sigma_restarts": rec[-1][3]["sigma_restarts"], "status": rec[-1][3]["status"],
                         "rel_res": rec[-1][3]["rel_res"], "cell_iters_per_s": n * it32 / t32,
                         "model_GBps": n * it32 * sw * 4 / t32 / 1e9, "max_abs_err_vs_xstar": err32,
                         "speedup_vs_fp64": t64 / t32},
-        "fp64_multigrid": {"time_to_tol_ms": 1e3 * tmg, "iters": img["iters"], "status": img["status"],
-                           "rel_res": img["rel_res"],
-                           "max_abs_err_vs_xstar": float(torch.max(torch.abs(xmg - xs))),
-                           "speedup_vs_fp64_jacobi": t64 / tmg, "params": mgp},
         "roofline": {"bound": "hbm", "kernel": kern + ("_sym" if form_sym and syncs == 1 else "") + "_fp64",
                      "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(args.config, kern),
+                     "traffic": measured_traffic(cfg["name"], kern + ("_sym" if form_sym and syncs == 1 else "")),
                      "bytes_per_launch": k1_bytes, "words_per_cell": kw, "mean_launch_ms": k1_avg_ms,
                      "launches": k1_cnt},
         "syncs_per_iteration": syncs,
         "symmetric_form": {"fp64": form_sym, "fp32_refine": bool(rec[-1][3]["symmetric"])},
-        "kernels_fp64_ms": {k: {"launches": v[0], "mean_ms": v[1] / v[0]} for k, v in kstats.items()},
+        "kernels_fp64_ms": {kern: {"launches": k1_cnt, "mean_ms": k1_avg_ms}},
         "layout": c64.layout(),
         "cells": n,
     }
+    if with_mg:
+        tmg, (xmg, img), mgp = time_mg(Context, [g.shape], lambda cm: cm.solve(D, b, torch.zeros_like(b), tol=tol,
+                                                                               maxit=maxit, check=False), cfg_id)
+        res["fp64_multigrid"] = {"time_to_tol_ms": 1e3 * tmg, "iters": img["iters"], "status": img["status"],
+                                 "rel_res": img["rel_res"], "max_abs_err_vs_xstar": float(torch.max(torch.abs(xmg - xs))),
+                                 "speedup_vs_fp64_jacobi": t64 / tmg, "params": mgp}
     if args.calibrate_copy:
-        # a plain copy of known size, for scaling the HBM byte counters of a profiled run
-        nb = 1 << 30
-        src = torch.ones(nb // 8, dtype=torch.float64, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        res["copy_calibration_bytes"] = {"read": nb, "write": nb}
+        copy_calibration(res, dev)
+    sols = {"fp64": [x64.cpu().numpy()], "fp32_refine": [x32.cpu().numpy()]}
     c64.close()
     c32.close()
-    return res
+    return res, sols
 
 
 def gpu_leg_batched(args):
-    """All equation sets of the workload in one call (the four-set time step, the large tall bed)."""
+    """All equation sets of the workload in one call (the four-set time step, the large tall bed).
+    Returns (result dict, host solutions {"fp64": [x per set], "fp32_refine": [...]})."""
     import numpy as np
     import torch
 
@@ -450,6 +478,7 @@ def gpu_leg_batched(args):
         Ds.append(D)
         xss.append(xs)
         bs.append(c64.apply(D, xs, set_id=i))
+        print("bench: set %d of %s on the device" % (i, cfg["name"]), file=sys.stderr, flush=True)
     tol, maxit = cfg["tol"], cfg["maxit"]
     n_all = [int(np.prod(g)) for g in grids]
 
@@ -469,6 +498,7 @@ def gpu_leg_batched(args):
         step(None)
     syncs = c64.layout()["syncs"]
     kern = "fused" if syncs == 1 else "k1"
+    # the kernel's own start and end stamps on every launch of the timed FP64 solves
     c64.profile([kern], every=1)
     rec = []
     torch.cuda.synchronize()
@@ -477,6 +507,7 @@ def gpu_leg_batched(args):
         x64, x32 = step(rec)
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
+    print("bench: %d timed steps done" % args.steps, file=sys.stderr, flush=True)
     k1_cnt, k1_ms = c64.kernel_stats(kern)
     c64.profile([])
     # the same sets one after another (plain FP64, the comparison the batched forms are measured
@@ -498,6 +529,7 @@ def gpu_leg_batched(args):
     for cs in singles:
         cs.close()
     del singles
+    print("bench: sequential FP64 solves done", file=sys.stderr, flush=True)
     t64 = float(np.mean([r[0] for r in rec]))
     t32 = float(np.mean([r[1] for r in rec]))
     ci64 = sum(n * inf["iters"] for n, inf in zip(n_all, rec[-1][2]))
@@ -505,12 +537,15 @@ def gpu_leg_batched(args):
     # a batched launch takes the symmetric form only when every set does
     form_sym = all(i["symmetric"] for i in rec[-1][2])
     kw, sw = step_words(syncs, form_sym)
+    # algorithmic bytes of the timed launches: kw words per cell of every set still iterating
+    # (a launch past a set's last iteration does nothing for it)
     k1_bytes_total = sum(kw * 8 * n * inf["iters"] for n, inf in zip(n_all, rec[-1][2])) * len(rec)
     achieved = k1_bytes_total / (k1_ms * 1e-3) / 1e9
     err64 = max(float(torch.max(torch.abs(x - xs))) for x, xs in zip(x64, xss))
-    tmg, (xmg, img), mgp = time_mg(Context, grids, lambda cm: cm.solve_batched(Ds, bs, tol=tol, maxit=maxit, check=False),
-                                   args.config, reps=2)
+    err32 = max(float(torch.max(torch.abs(x - xs))) for x, xs in zip(x32, xss))
+    kname = kern + ("_sym" if form_sym and syncs == 1 else "")
     res = {
+        "workload": cfg["name"],
         "value": ci64 / t64,
         "ms_per_step": 1e3 * t_total / args.steps,
         "fp64": {"time_to_tol_ms": 1e3 * t64, "iters": [i["iters"] for i in rec[-1][2]],
@@ -521,62 +556,181 @@ def gpu_leg_batched(args):
                  "batched_speedup_vs_sequential": float(np.mean(seq)) / t64},
         "fp32_refine": {"time_to_tol_ms": 1e3 * t32, "inner_iters": [i["iters"] for i in rec[-1][3]],
                         "status": [i["status"] for i in rec[-1][3]],
-                        "outer": [i["outer"] for i in rec[-1][3]], "rel_res": [i["rel_res"] for i in rec[-1][3]],
+                        "outer": [i["outer"] for i in rec[-1][3]],
+                        "sigma_restarts": [i["sigma_restarts"] for i in rec[-1][3]],
+                        "rel_res": [i["rel_res"] for i in rec[-1][3]],
                         "cell_iters_per_s": ci32 / t32, "model_GBps": ci32 * sw * 4 / t32 / 1e9,
+                        "max_abs_err_vs_xstar": err32,
                         "speedup_vs_fp64_batched": t64 / t32,
                         "speedup_vs_fp64_sequential": float(np.mean(seq)) / t32},
-        "fp64_multigrid": {"time_to_tol_ms": 1e3 * tmg, "iters": [i["iters"] for i in img],
-                           "status": [i["status"] for i in img],
-                           "rel_res": [i["rel_res"] for i in img],
-                           "max_abs_err_vs_xstar": max(float(torch.max(torch.abs(x - xs))) for x, xs in zip(xmg, xss)),
-                           "speedup_vs_fp64_jacobi_batched": t64 / tmg, "params": mgp},
-        "roofline": {"bound": "hbm", "kernel": kern + "_fp64 (batched launch)", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "bytes": "%d words x 8 B per active cell, summed over sets" % kw,
-                     "launches": k1_cnt, "mean_launch_ms": k1_ms / max(k1_cnt, 1)},
+        "roofline": {"bound": "hbm", "kernel": kname + "_fp64 (batched launch)", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(cfg["name"], kname),
+                     "bytes_per_launch": k1_bytes_total / max(k1_cnt, 1),
+                     "bytes": "%d words x 8 B per cell of every set still iterating, averaged over the timed "
+                              "launches" % kw,
+                     "words_per_cell": kw, "launches": k1_cnt, "mean_launch_ms": k1_ms / max(k1_cnt, 1)},
         "syncs_per_iteration": syncs,
         "symmetric_form": {"fp64": form_sym, "fp32_refine": all(i["symmetric"] for i in rec[-1][3])},
         "kernels_fp64_ms": {kern: {"launches": k1_cnt, "mean_ms": k1_ms / max(k1_cnt, 1)}},
         "layout": [c64.layout(i) for i in range(len(grids))],
         "cells": sum(n_all),
     }
-    c64.close()
+    sols = {"fp64": [x.cpu().numpy() for x in x64], "fp32_refine": [x.cpu().numpy() for x in x32]}
+    del x64, x32
     c32.close()
-    return res
+    if not args.no_mg:
+        tmg, (xmg, img), mgp = time_mg(Context, grids,
+                                       lambda cm: cm.solve_batched(Ds, bs, tol=tol, maxit=maxit, check=False),
+                                       args.config, reps=2)
+        res["fp64_multigrid"] = {"time_to_tol_ms": 1e3 * tmg, "iters": [i["iters"] for i in img],
+                                 "status": [i["status"] for i in img],
+                                 "rel_res": [i["rel_res"] for i in img],
+                                 "max_abs_err_vs_xstar": max(float(torch.max(torch.abs(x - xs)))
+                                                             for x, xs in zip(xmg, xss)),
+                                 "speedup_vs_fp64_jacobi_batched": t64 / tmg, "params": mgp}
+        del xmg
+    if args.calibrate_copy:
+        copy_calibration(res, dev)
+    c64.close()
+    return res, sols
 
 
-def cpu_leg(args):
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_leg(args, gpu_sols):
+    """The CPU oracle on the same systems: it solves every set to the workload's tolerance (the
+    cpu_baseline rate is taken on set 0's solve, with the thread count it used, and a tenth of its
+    iterations on one thread), and its solutions give each GPU result's error and the matching
+    digits of Eq. (6) (min / 1st percentile / median over the cells)."""
     import numpy as np
 
     from oracle import oracle as O
     from paper_2211_15605_amd import workloads as W
 
     o = O.default()
-    s = W.make_set(args.config, 0)
-    g = s["grid"]
-    b = o.apply(g.shape, s["diags"], s["x_star"])
-    t0 = time.perf_counter()
-    _, info = o.bicgstab(g.shape, s["diags"], b, tol=1e-10, maxit=4)
-    t_probe = time.perf_counter() - t0
-    per_it = t_probe / max(info["iters"], 1)
-    maxit = int(max(8, min(2000, args.cpu_seconds / per_it)))
-    t0 = time.perf_counter()
-    _, info = o.bicgstab(g.shape, s["diags"], b, tol=1e-10, maxit=maxit)
-    t = time.perf_counter() - t0
-    cores = o.get_threads()
-    # the same oracle on one thread, over a tenth of the iterations
-    o.set_threads(1)
-    try:
+    cfg = W.CONFIGS[args.config]
+    out, t0_rate = {}, None
+    digits = {k: [] for k in gpu_sols}
+    for i, g in enumerate(cfg["grids"]):
+        s = W.make_set(args.config, i)
+        b = o.apply(g.shape, s["diags"], s["x_star"])
         t0 = time.perf_counter()
-        _, info1 = o.bicgstab(g.shape, s["diags"], b, tol=1e-10, maxit=max(4, maxit // 10))
-        t1 = time.perf_counter() - t0
-    finally:
-        o.set_threads(cores)
-    return {"value": g.n * info["iters"] / t, "unit": "cell-iters/s", "cores": cores, "kind": "oracle",
-            "sample": "%d FP64 BiCGSTAB iterations (of a full solve) on the %dx%dx%d system%s, %.1f s" % (
-                info["iters"], g.nx, g.ny, g.nz, " of set 0" if len(W.CONFIGS[args.config]["grids"]) > 1 else "", t),
-            "single_thread": {"value": g.n * info1["iters"] / t1, "cores": 1,
-                              "sample": "%d iterations, %.1f s" % (info1["iters"], t1)}}
+        xo, info = o.bicgstab(g.shape, s["diags"], b, tol=cfg["tol"], maxit=cfg["maxit"])
+        t = time.perf_counter() - t0
+        print("bench: oracle solved set %d (%d iterations, %.1f s)" % (i, info["iters"], t), file=sys.stderr,
+              flush=True)
+        if i == 0:
+            t0_rate = (g.n * info["iters"] / t, info["iters"], t)
+        ref = np.max(np.abs(xo))
+        for prec, xs in gpu_sols.items():
+            d = O.matching_digits(xo, xs[i])
+            digits[prec].append({"set": i, "max_abs_err_vs_oracle": float(np.max(np.abs(xs[i] - xo))),
+                                 "max_rel_err_vs_oracle": float(np.max(np.abs(xs[i] - xo)) / ref),
+                                 "digits_min": float(np.min(d)), "digits_p1": float(np.percentile(d, 1)),
+                                 "digits_median": float(np.median(d)),
+                                 "oracle_rel_res": float(o.rel_residual(g.shape, s["diags"], b, xs[i]))})
+        if i == 0:
+            # the same oracle on one thread, over a tenth of the iterations
+            cores = o.get_threads()
+            o.set_threads(1)
+            try:
+                t1s = time.perf_counter()
+                _, info1 = o.bicgstab(g.shape, s["diags"], b, tol=cfg["tol"], maxit=max(4, info["iters"] // 10))
+                t1 = time.perf_counter() - t1s
+            finally:
+                o.set_threads(cores)
+            single = {"value": g.n * info1["iters"] / t1, "cores": 1,
+                      "sample": "%d iterations, %.1f s" % (info1["iters"], t1)}
+        del s, b, xo
+    out["cpu_baseline"] = {
+        "value": t0_rate[0], "unit": "cell-iters/s", "cores": o.get_threads(), "kind": "oracle",
+        "cpu": cpu_model(), "host_cpus": os.cpu_count(),
+        "sample": "the full FP64 BiCGSTAB solve of set 0 (%dx%dx%d, %d iterations to %g, %.1f s)" % (
+            cfg["grids"][0].nx, cfg["grids"][0].ny, cfg["grids"][0].nz, t0_rate[1], cfg["tol"], t0_rate[2]),
+        "single_thread": single}
+    out["vs_oracle"] = {"equation_6": "digits = -log10(|x_oracle - x_gpu| / |x_oracle|) per cell", **digits}
+    return out
+
+
+def reduce_pmc(args):
+    """Write the traffic record of one kernel from two rocprofv3 --pmc runs of the same bench
+    command (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch), each scaled by what the counter
+    reads for the 1 GiB copies of --calibrate-copy.  The kernel's dispatches are those with its
+    name and grid size; only dispatches that did work (above 1 % of the largest) count."""
+    import csv
+    import glob
+
+    def rows(d, counter):
+        f = sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True))
+        assert f, "no counter_collection.csv under %s" % d
+        out = []
+        for r in csv.DictReader(open(f[0])):
+            if r["Counter_Name"] == counter:
+                out.append((int(r["Dispatch_Id"]), r["Kernel_Name"], int(r["Grid_Size"]), float(r["Counter_Value"])))
+        out.sort()
+        return out
+
+    res = {}
+    for counter, d in (("FETCH_SIZE", args.reduce_pmc[0]), ("WRITE_SIZE", args.reduce_pmc[1])):
+        rs = rows(d, counter)
+        copies = [v for _, name, _, v in rs if "copy" in name.lower()
+                  and v * 1024 > 0.25 * (1 << 30)]
+        assert len(copies) >= 3, "no 1 GiB copy dispatches found (run with --calibrate-copy)"
+        scale = (1 << 30) / (1024.0 * sorted(copies[-3:])[1])
+        ks = [v for _, name, grid, v in rs if args.pmc_kernel in name and grid == args.pmc_grid]
+        assert ks, "no dispatch of %s with grid %d" % (args.pmc_kernel, args.pmc_grid)
+        work = [v for v in ks if v > 0.01 * max(ks)]
+        full = [v for v in work if v > 0.9 * max(ks)]
+        res[counter] = dict(scale=scale, dispatches=len(work), mean_kib=sum(work) / len(work),
+                            full_dispatches=len(full), full_mean_kib=sum(full) / len(full))
+    f, w = res["FETCH_SIZE"], res["WRITE_SIZE"]
+    per = 1024.0 * (f["mean_kib"] * f["scale"] + w["mean_kib"] * w["scale"])
+    per_full = 1024.0 * (f["full_mean_kib"] * f["scale"] + w["full_mean_kib"] * w["scale"])
+    alg_full = args.pmc_words * 8 * args.pmc_cells
+    rec = {"kernel": args.pmc_kernel, "grid_work_items": args.pmc_grid, "workload": args.pmc_workload,
+           "command_fetch": args.pmc_commands[0], "command_write": args.pmc_commands[1],
+           "fetch_scale": f["scale"], "write_scale": w["scale"],
+           "dispatches_with_work": f["dispatches"], "fetch_kib_mean": f["mean_kib"], "write_kib_mean": w["mean_kib"],
+           "bytes_per_launch": per,
+           "full_dispatches": f["full_dispatches"], "bytes_per_full_launch": per_full,
+           "algorithmic_bytes_per_full_launch": alg_full, "traffic_over_algorithmic_full": per_full / alg_full,
+           "code_object_sha256": code_object_digest()}
+    json.dump(rec, open(args.pmc_out, "w"), indent=1)
+    print(json.dumps(rec))
+
+
+def summarize_trace(args):
+    """Markdown summary of a rocprofv3 --kernel-trace run (kernel_trace.csv): per kernel and grid
+    size, the launches that did work (a launch past its sets' convergence returns in < 10 us) and
+    their mean duration."""
+    import csv
+    import glob
+    import collections
+    f = sorted(glob.glob(os.path.join(args.summarize_trace, "**", "*kernel_trace.csv"), recursive=True))
+    assert f, "no kernel_trace.csv under %s" % args.summarize_trace
+    g = collections.defaultdict(list)
+    for r in csv.DictReader(open(f[0])):
+        g[(r["Kernel_Name"], int(r["Grid_Size_X"]) // int(r["Workgroup_Size_X"]))].append(
+            int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    lines = ["| kernel | blocks per launch | launches | with work (> 10 us) | mean us (with work) | total ms |",
+             "|---|---|---|---|---|---|"]
+    tot = sum(sum(v) for v in g.values())
+    for (name, blocks), v in sorted(g.items(), key=lambda kv: -sum(kv[1])):
+        if sum(v) < args.trace_min_share * tot:
+            continue
+        w = [x for x in v if x > 10000]
+        lines.append("| `%s` | %d | %d | %d | %.1f | %.2f |" % (name.split("(")[0], blocks, len(v), len(w),
+                                                             (sum(w) / len(w) / 1e3) if w else 0.0, sum(v) / 1e6))
+    print("\n".join(lines))
 
 
 def main():
@@ -584,19 +738,37 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", type=int, default=1)
+    ap.add_argument("--config", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-tune", action="store_true", help="use the default launch shapes (no autotuning)")
+    ap.add_argument("--no-mg", action="store_true", help="skip the multigrid-preconditioned solves")
     ap.add_argument("--no-simple", action="store_true",
-                    help="skip the SIMPLE-iteration, latency, small-batch and adjoint sections")
+                    help="skip the sections beside the workload (SIMPLE iteration, 16^3 latency, small batches, "
+                         "adjoint, the pressure-like system)")
     ap.add_argument("--only-simple", action="store_true",
                     help="run only the SIMPLE-iteration section and print it as the JSON line (for profiling)")
     ap.add_argument("--only-latency", action="store_true",
                     help="run only the 16^3 latency section and print it as the JSON line (for profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the timed steps, copy 1 GiB three times (reference for HBM byte counters)")
+    ap.add_argument("--reduce-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write a traffic record from two rocprofv3 --pmc runs (no GPU needed)")
+    ap.add_argument("--pmc-kernel", default="fused_kernel<double, 2, 2, false>")
+    ap.add_argument("--pmc-grid", type=int, default=0, help="work-items of the kernel's launch")
+    ap.add_argument("--pmc-words", type=int, default=18)
+    ap.add_argument("--pmc-cells", type=int, default=0)
+    ap.add_argument("--pmc-workload", default="")
+    ap.add_argument("--pmc-out", default="")
+    ap.add_argument("--pmc-commands", nargs=2, default=["", ""])
+    ap.add_argument("--summarize-trace", metavar="TRACE_DIR", help="print a markdown summary of a kernel trace")
+    ap.add_argument("--trace-min-share", type=float, default=0.01)
     args = ap.parse_args()
+    if args.reduce_pmc:
+        reduce_pmc(args)
+        return
+    if args.summarize_trace:
+        summarize_trace(args)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the equation sets of a time step are solved on a single "
               "device here; --gpus %d is not supported" % args.gpus, file=sys.stderr)
@@ -610,14 +782,20 @@ def main():
         print(json.dumps({"latency_cd16": time_latency()}))
         return
     cfg = W.CONFIGS[args.config]
-    g = cfg["grids"][0]
     batched = len(cfg["grids"]) > 1
-    r = gpu_leg_batched(args) if batched else gpu_leg(args)
-    simple = None if args.no_simple else time_simple()
-    latency = None if args.no_simple else time_latency()
-    batching = None if args.no_simple else time_batching()
-    adjoint = None if args.no_simple else time_adjoint()
-    cpu = None if args.no_cpu_baseline else cpu_leg(args)
+    r, sols = gpu_leg_batched(args) if batched else gpu_leg(args, args.config, with_mg=not args.no_mg)
+    sections = {}
+    if not args.no_simple:
+        if args.config != 1:
+            c1, _ = gpu_leg(args, 1, steps=3, warmup=1, with_mg=not args.no_mg)
+            c1.pop("layout", None)
+            sections["pressure_like_128x256x128"] = c1
+        sections["simple_bed"] = time_simple()
+        sections["latency_cd16"] = time_latency()
+        sections["batching_small"] = time_batching()
+        sections["adjoint64"] = time_adjoint()
+        print("bench: sections done", file=sys.stderr, flush=True)
+    cpu = None if args.no_cpu_baseline else cpu_leg(args, sols)
     line = {
         "metric": METRIC,
         "value": r["value"],
@@ -639,17 +817,16 @@ def main():
                                    cfg["tol"], " (all sets in one call)" if batched else ""),
                    "cells": r["cells"], "layout": r["layout"]},
         "roofline": r["roofline"],
-        "cpu_baseline": cpu,
+        "cpu_baseline": cpu["cpu_baseline"] if cpu else None,
+        "vs_oracle": cpu["vs_oracle"] if cpu else None,
         "fp64": r["fp64"],
         "fp32_refine": r["fp32_refine"],
-        "fp64_multigrid": r["fp64_multigrid"],
+        "fp64_multigrid": r.get("fp64_multigrid"),
         "kernels_fp64_ms": r["kernels_fp64_ms"],
         "symmetric_form": r.get("symmetric_form"),
-        "simple_bed": simple,
-        "latency_cd16": latency,
-        "batching_small": batching,
-        "adjoint64": adjoint,
+        "copy_calibration_bytes": r.get("copy_calibration_bytes"),
     }
+    line.update(sections)
     print(json.dumps(line))
 
 

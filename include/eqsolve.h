@@ -254,11 +254,14 @@ const char *eqsolve_strerror(int code);
 
 /*
  * Diagnostics: the launch layout of set `set` (chosen at create time or by
- * eqsolve_autotune).  out8 (host, 8 entries) receives cells per thread,
+ * eqsolve_autotune).  out8 (host, 12 entries) receives cells per thread,
  * segments per plane, planes per chunk, chunks, tiles, the number of host
  * state readbacks so far, the grid-wide reductions per BiCGSTAB step of the
- * iteration in use (1: one fused launch per step; 3: three launches), and the
- * blocks of the pointwise kernels.  Returns EQS_OK or EQS_ERR_ARG.
+ * iteration in use (1: one fused launch per step; 3: three launches), the
+ * blocks of the pointwise kernels, and for the single-sync step its threads per
+ * block (256 or 512), segments per plane, tiles, and tile order (0: chunks of a
+ * segment adjacent in the launch, 1: segments of a chunk adjacent).  Returns
+ * EQS_OK or EQS_ERR_ARG.
  */
 int eqsolve_debug_layout(const eqs_ctx *ctx, int32_t set, int32_t *out8);
 

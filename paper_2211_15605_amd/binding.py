@@ -233,7 +233,7 @@ def eqsolve_debug_precond(h, set_id, diag_ptrs, r_ptr, z_ptr):
 
 
 def eqsolve_debug_layout(h, set_id):
-    out = (ctypes.c_int32 * 8)()
+    out = (ctypes.c_int32 * 12)()
     rc = load().eqsolve_debug_layout(h, int(set_id), out)
     return rc, list(out)
 

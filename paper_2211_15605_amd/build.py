@@ -27,9 +27,9 @@ def hipcc() -> str:
     return "hipcc"
 
 
-def flags():
+def flags(shared: bool = True):
     return [
-        "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared",
+        "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC"] + (["-shared"] if shared else []) + [
         "-Wall", "-Wno-unused-function",
         # no packed-FP32 instructions in device code
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -38,17 +38,34 @@ def flags():
 
 
 def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
+    """Compile every source to an object (in parallel, each with a fixed compilation-unit id, so
+    the same sources always give the same device code object), then link the library."""
+    objdir = os.path.join(PKG, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    procs, objs = [], []
+    for src in SOURCES:
+        stem = os.path.splitext(src)[0]
+        obj = os.path.join(objdir, stem + ".o")
+        cmd = [hipcc()] + flags(shared=False) + ["-cuid=" + stem, "-c", os.path.join(CSRC, src), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
+        objs.append(obj)
+    errors = []
+    for src, p in procs:
+        out = p.communicate()[0]
+        out = "\n".join(l for l in out.splitlines() if "packed-fp32-ops" not in l and "warning generated" not in l)
+        if p.returncode != 0:
+            errors.append("%s:\n%s" % (src, out))
+        elif verbose and out.strip():
+            print(out)
+    if errors:
+        raise RuntimeError("hipcc failed:\n" + "\n".join(errors))
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc()] + flags() + srcs + ["-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
+    cmd = [hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC"] + objs + ["-o", tmp]
     res = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
-    out = "\n".join(l for l in res.stdout.splitlines() if "packed-fp32-ops" not in l and "warning generated" not in l)
     if res.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + out)
-    if verbose and out.strip():
-        print(out)
+        raise RuntimeError("link failed:\n" + res.stdout)
     os.replace(tmp, LIB)
     return LIB
 

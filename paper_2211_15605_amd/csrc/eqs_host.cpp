@@ -47,6 +47,7 @@ struct SetHost {
     eqs_grid g;
     int n, plane;
     int S, KC, NKC, ntiles, nflat;
+    int fS, fntiles, ford;  // the single-sync step's tiling (segments of fnt * cpt cells) and tile order
     // workspace offsets resolved to pointers
     double *r, *rh, *p[2], *v[2], *t, *y;
     double *as[6];
@@ -102,6 +103,9 @@ struct eqs_ctx {
     bool sync1 = true;
     // exactly symmetric sets take the symmetric form of the single-sync step (EQS_SYM=0: never)
     int sym_on = 1;
+    // threads per block of the single-sync step (256 or 512) and the dynamic LDS it may take
+    int fnt = 256;
+    size_t fused_lds_cap = kMaxLds;
     SetHost sets[kMaxSets] = {};
     SetDesc *h_desc = nullptr;
     SetDesc *d_desc = nullptr;
@@ -158,8 +162,16 @@ bool grid_ok(const eqs_grid &g) {
     return n < (1ll << 31) - (1ll << 20);
 }
 
+// the single-sync step's tiles: segments of fnt * cpt cells, the march's chunks
+void fused_tiling(SetHost &s, int cpt, int fnt, int ford) {
+    const int Q = fnt * cpt;
+    s.fS = (s.plane + Q - 1) / Q;
+    s.fntiles = s.fS * s.NKC;
+    s.ford = ford ? 1 : 0;
+}
+
 // tiles: segments of Q = 256*cpt cells per plane, KC planes per chunk
-void choose_tiling(SetHost &s, int cpt) {
+void choose_tiling(SetHost &s, int cpt, int fnt) {
     const int Q = kBlock * cpt;
     s.S = (s.plane + Q - 1) / Q;
     const int target = std::max(1, env_int("EQS_TILE_TARGET", 1024));
@@ -173,16 +185,18 @@ void choose_tiling(SetHost &s, int cpt) {
     s.ntiles = s.S * s.NKC;
     const int fmax = std::min(std::max(1, env_int("EQS_FLAT_MAX", 1024)), kMaxFlatBlocks);
     s.nflat = std::min((s.n + kFlatChunk - 1) / kFlatChunk, fmax);
+    fused_tiling(s, cpt, fnt, env_int("EQS_FORD", 0));
 }
 
 // explicit tiling (tuner, tuning cache)
-void set_tiling(SetHost &s, int cpt, int kc, int nflat) {
+void set_tiling(SetHost &s, int cpt, int kc, int nflat, int fnt, int ford) {
     const int Q = kBlock * cpt;
     s.S = (s.plane + Q - 1) / Q;
     s.KC = std::max(1, std::min(kc, s.g.nz));
     s.NKC = (s.g.nz + s.KC - 1) / s.KC;
     s.ntiles = s.S * s.NKC;
     s.nflat = std::max(1, std::min(nflat, std::min((s.n + kFlatChunk - 1) / kFlatChunk, kMaxFlatBlocks)));
+    fused_tiling(s, cpt, fnt, ford);
 }
 
 // partial sums are sized for any tiling the tuner may choose
@@ -251,6 +265,9 @@ void fill_desc(eqs_ctx *c, int s) {
     d.NKC = h.NKC;
     d.ntiles = h.ntiles;
     d.nflat = h.nflat;
+    d.fS = h.fS;
+    d.fntiles = h.fntiles;
+    d.ford = h.ford;
     d.r = h.r;
     d.rh = h.rh;
     d.p[0] = h.p[0];
@@ -288,17 +305,21 @@ LaunchSets launch_table(eqs_ctx *c, int first, int count, int *total, int *total
     LaunchSets ls;
     memset(&ls, 0, sizeof(ls));
     ls.nsets = count;
-    int acc = 0, accf = 0;
+    int acc = 0, accf = 0, accu = 0;
     for (int i = 0; i < count; ++i) {
         ls.tile_begin[i] = acc;
         ls.flat_begin[i] = accf;
+        ls.ftile_begin[i] = accu;
         acc += c->sets[first + i].ntiles;
         accf += c->sets[first + i].nflat;
+        accu += c->sets[first + i].fntiles;
     }
     for (int i = count; i <= kMaxSets; ++i) {
         ls.tile_begin[i] = acc;
         ls.flat_begin[i] = accf;
+        ls.ftile_begin[i] = accu;
     }
+    ls.fnt = c->fnt;
     ls.desc = c->d_desc + first;
     *total = acc;
     *total_flat = accf;
@@ -663,6 +684,7 @@ std::string arch_name(int device) {
 
 struct TuneEntry {
     int cpt, kc, nflat;
+    int fnt, ford;  // the single-sync step's block size and tile order
     double us;
 };
 
@@ -674,14 +696,15 @@ bool cache_lookup(const char *path, const std::string &arch, const eqs_grid &g, 
     char line[512], a[64];
     bool found = false;
     while (fgets(line, sizeof line, f)) {
-        int nx, ny, nz, pr, cpt, kc, nflat;
+        int nx, ny, nz, pr, cpt, kc, nflat, fnt, ford;
         double us;
         if (sscanf(line,
                    "{\"arch\": \"%63[^\"]\", \"nx\": %d, \"ny\": %d, \"nz\": %d, \"precision\": %d, \"cpt\": %d, "
-                   "\"kc\": %d, \"nflat\": %d, \"us_per_iter\": %lf}",
-                   a, &nx, &ny, &nz, &pr, &cpt, &kc, &nflat, &us) == 9 &&
-            arch == a && nx == g.nx && ny == g.ny && nz == g.nz && pr == precision && (cpt == 1 || cpt == 2)) {
-            *out = TuneEntry{cpt, kc, nflat, us};
+                   "\"kc\": %d, \"nflat\": %d, \"fnt\": %d, \"ford\": %d, \"us_per_iter\": %lf}",
+                   a, &nx, &ny, &nz, &pr, &cpt, &kc, &nflat, &fnt, &ford, &us) == 11 &&
+            arch == a && nx == g.nx && ny == g.ny && nz == g.nz && pr == precision && (cpt == 1 || cpt == 2) &&
+            (fnt == 256 || fnt == 512) && (ford == 0 || ford == 1)) {
+            *out = TuneEntry{cpt, kc, nflat, fnt, ford, us};
             found = true;
         }
     }
@@ -695,8 +718,8 @@ void cache_store(const char *path, const std::string &arch, const eqs_grid &g, i
     if (!f) return;
     fprintf(f,
             "{\"arch\": \"%s\", \"nx\": %d, \"ny\": %d, \"nz\": %d, \"precision\": %d, \"cpt\": %d, \"kc\": %d, "
-            "\"nflat\": %d, \"us_per_iter\": %.3f}\n",
-            arch.c_str(), g.nx, g.ny, g.nz, precision, e.cpt, e.kc, e.nflat, e.us);
+            "\"nflat\": %d, \"fnt\": %d, \"ford\": %d, \"us_per_iter\": %.3f}\n",
+            arch.c_str(), g.nx, g.ny, g.nz, precision, e.cpt, e.kc, e.nflat, e.fnt, e.ford, e.us);
     fclose(f);
 }
 
@@ -917,15 +940,16 @@ void retile_for_precond(eqs_ctx *c) {
         SetHost &h = c->sets[s];
         if (h.kc_jacobi <= 0) h.kc_jacobi = h.KC;
         const int kc = c->precond == EQS_PRECOND_MG ? std::min(mg_kc(), h.kc_jacobi) : h.kc_jacobi;
-        set_tiling(h, c->cpt, kc, h.nflat);
+        set_tiling(h, c->cpt, kc, h.nflat, c->fnt, h.ford);
         fill_desc(c, s);
     }
 }
 
-int apply_tuning(eqs_ctx *c, int cpt, const std::vector<TuneEntry> &e) {
+int apply_tuning(eqs_ctx *c, int cpt, int fnt, const std::vector<TuneEntry> &e) {
     c->cpt = cpt;
+    c->fnt = fnt;
     for (int s = 0; s < c->nsets; ++s) {
-        set_tiling(c->sets[s], cpt, e[s].kc, e[s].nflat);
+        set_tiling(c->sets[s], cpt, e[s].kc, e[s].nflat, fnt, e[s].ford);
         c->sets[s].kc_jacobi = c->sets[s].KC;
         fill_desc(c, s);
     }
@@ -949,17 +973,25 @@ int default_shape(eqs_ctx *c, const eqs_grid *grids, int nsets, int *max_nx_out)
     if (cpt != 1 && cpt != 2) cpt = max_plane >= 4 * kBlock ? 2 : 1;
     while (cpt > 1 && march_lds_bytes(cpt, max_nx, 8) > kMaxLds) cpt /= 2;
     c->sym_on = env_int("EQS_SYM", 1) != 0 ? 1 : 0;
-    c->sync1 = env_int("EQS_SYNC", 1) != 3 && halo_slots(max_nx) > 0 && halo_slots(max_nx) <= 4;
+    // the single-sync step in blocks of 256 threads, or 512 where EQS_FNT=512 asks for it and the
+    // shape has that instantiation (the tuner chooses between them by measurement)
+    auto fits = [&](int fc, int nt) {
+        return fused_shape_ok(fc, max_nx, nt) && fused_lds_bytes(fc, max_nx, 8, nt) <= c->fused_lds_cap;
+    };
+    int fnt = env_int("EQS_FNT", 256) == 512 ? 512 : 256;
+    if (fnt == 512 && !(cpt == 2 && fits(2, 512))) fnt = 256;
+    c->sync1 = env_int("EQS_SYNC", 1) != 3;
     if (c->sync1) {
         int fc = cpt;
-        while (fc > 1 && fused_lds_bytes(fc, max_nx, 8) > kMaxLds) fc /= 2;
-        if (fused_lds_bytes(fc, max_nx, 8) > kMaxLds)
+        while (fc > 1 && !fits(fc, fnt)) fc /= 2;
+        if (!fits(fc, fnt))
             c->sync1 = false;
         else
             cpt = fc;
     }
+    c->fnt = c->sync1 ? fnt : 256;
     *max_nx_out = max_nx;
-    if (march_lds_bytes(cpt, max_nx, 8) > kMaxLds || halo_slots(max_nx) < 0) return -1;
+    if (march_lds_bytes(cpt, max_nx, 8) > kMaxLds || halo_slots(max_nx, kBlock) < 0) return -1;
     return cpt;
 }
 
@@ -980,7 +1012,7 @@ SolveState g_static_state[kStaticDevices];
 namespace eqs {
 
 size_t static_solve_bytes(const eqs_grid &g) {
-    eqs_ctx probe;  // shape only: no allocation, no HIP call
+    eqs_ctx probe;  // shape only: no allocation, no HIP call (64 KB of LDS per block at most)
     probe.nsets = 1;
     int max_nx = 1;
     const int cpt = default_shape(&probe, &g, 1, &max_nx);
@@ -989,7 +1021,7 @@ size_t static_solve_bytes(const eqs_grid &g) {
     h.g = g;
     h.plane = g.nx * g.ny;
     h.n = h.plane * g.nz;
-    choose_tiling(h, cpt);
+    choose_tiling(h, cpt, probe.fnt);
     return align_up(sizeof(SetDesc)) + align_up(sizeof(SolveState)) +
            set_ws_bytes(h, false, (size_t)std::max(h.ntiles, h.nflat));
 }
@@ -1011,6 +1043,7 @@ int static_solve(void *ws, size_t cap, int device, const eqs_grid &g, const doub
     c->broken = false;
     c->profile_mask = 0;
     c->precond = EQS_PRECOND_JACOBI;
+    c->fused_lds_cap = kMaxLds;
     int max_nx = 1;
     c->cpt = default_shape(c, &g, 1, &max_nx);
     c->max_nx = max_nx;
@@ -1019,7 +1052,7 @@ int static_solve(void *ws, size_t cap, int device, const eqs_grid &g, const doub
     h.g = g;
     h.plane = g.nx * g.ny;
     h.n = h.plane * g.nz;
-    choose_tiling(h, c->cpt);
+    choose_tiling(h, c->cpt, c->fnt);
     char *w = (char *)ws;
     c->d_desc = (SetDesc *)w;
     c->d_state = (SolveState *)(w + align_up(sizeof(SetDesc)));
@@ -1078,6 +1111,23 @@ int eqsolve_create(eqs_ctx **out, const eqs_grid *grids, int32_t nsets, int32_t 
     c->nsets = nsets;
     c->precision = precision;
     if (hipGetDevice(&c->device) != hipSuccess) { delete c; return EQS_ERR_HIP; }
+    // the single-sync step may take the device's whole per-block LDS (160 KB on gfx950; the march
+    // kernels stay within 64 KB); EQS_FUSED_LDS caps it for tests
+    {
+        int lds = 0;
+        if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) != hipSuccess) {
+            (void)hipGetLastError();
+            lds = (int)kMaxLds;
+        }
+        // (less 1 KB: the kernels' static LDS, the reduction scratch, counts against the same limit)
+        size_t cap = (size_t)std::max<long>((long)kMaxLds, std::min<long>((long)lds, 160L * 1024) - 1024);
+        cap = std::min(cap, (size_t)std::max(env_int("EQS_FUSED_LDS", (int)cap), (int)kMaxLds));
+        if (cap > kMaxLds && allow_fused_lds(cap) != hipSuccess) {
+            (void)hipGetLastError();
+            cap = kMaxLds;
+        }
+        c->fused_lds_cap = cap;
+    }
 
     int max_nx = 1;
     int cpt = default_shape(c, grids, nsets, &max_nx);
@@ -1092,10 +1142,17 @@ int eqsolve_create(eqs_ctx **out, const eqs_grid *grids, int32_t nsets, int32_t 
             tuned_ok = cache_lookup(getenv("EQS_TUNE_CACHE"), arch, grids[s], precision, &tuned[s]);
             if (tuned_ok && s > 0 && tuned[s].cpt != tuned[0].cpt) tuned_ok = false;
         }
+        for (int s = 1; s < nsets && tuned_ok; ++s) tuned_ok = tuned[s].fnt == tuned[0].fnt;
         if (tuned_ok) tuned_cpt = tuned[0].cpt;
         if (tuned_ok && march_lds_bytes(tuned_cpt, max_nx, 8) > kMaxLds) tuned_ok = false;
-        if (tuned_ok && c->sync1 && fused_lds_bytes(tuned_cpt, max_nx, 8) > kMaxLds) tuned_ok = false;
-        if (tuned_ok) cpt = tuned_cpt;
+        if (tuned_ok && c->sync1 &&
+            !(fused_shape_ok(tuned_cpt, max_nx, tuned[0].fnt) &&
+              fused_lds_bytes(tuned_cpt, max_nx, 8, tuned[0].fnt) <= c->fused_lds_cap))
+            tuned_ok = false;
+        if (tuned_ok) {
+            cpt = tuned_cpt;
+            if (c->sync1) c->fnt = tuned[0].fnt;
+        }
     }
     c->cpt = cpt;
     c->max_nx = max_nx;
@@ -1109,8 +1166,8 @@ int eqsolve_create(eqs_ctx **out, const eqs_grid *grids, int32_t nsets, int32_t 
         h.g = grids[s];
         h.plane = grids[s].nx * grids[s].ny;
         h.n = h.plane * grids[s].nz;
-        choose_tiling(h, cpt);
-        if (tuned_ok) set_tiling(h, tuned_cpt, tuned[s].kc, tuned[s].nflat);
+        choose_tiling(h, cpt, c->fnt);
+        if (tuned_ok) set_tiling(h, tuned_cpt, tuned[s].kc, tuned[s].nflat, c->fnt, c->sync1 ? tuned[s].ford : 0);
         base[s] = bytes;
         bytes += set_ws_bytes(h, f32, max_partials(h));
     }
@@ -1396,7 +1453,7 @@ const char *eqsolve_strerror(int code) {
 }
 
 // introspection used by tests and the benchmark (not part of the solver contract)
-int eqsolve_debug_layout(const eqs_ctx *c, int32_t set, int32_t *out8) {
+int eqsolve_debug_layout(const eqs_ctx *c, int32_t set, int32_t *out8) {  // 12 entries
     if (!c || set < 0 || set >= c->nsets || !out8) return EQS_ERR_ARG;
     const SetHost &h = c->sets[set];
     out8[0] = c->cpt;
@@ -1407,6 +1464,10 @@ int eqsolve_debug_layout(const eqs_ctx *c, int32_t set, int32_t *out8) {
     out8[5] = (int32_t)std::min<uint64_t>(c->readbacks, 0x7fffffff);
     out8[6] = c->sync1 ? 1 : 3;
     out8[7] = h.nflat;
+    out8[8] = c->fnt;
+    out8[9] = h.fS;
+    out8[10] = h.fntiles;
+    out8[11] = h.ford;
     return EQS_OK;
 }
 
@@ -1426,76 +1487,107 @@ int eqsolve_autotune(eqs_ctx *c, const char *cache_path, int32_t iters) {
     int rc = EQS_OK;
     for (int k = 0; k < 9 && rc == EQS_OK; ++k)
         if (launch_fill(tmp + k * nmax, (long)nmax, k == 0 ? 7.0 : 1.0, c->stream) != hipSuccess) rc = EQS_ERR_HIP;
-    const int kcs[] = {1, 2, 4, 8, 16, 32};
+    const int kcs[] = {1, 2, 4, 8, 16, 32, 48};
     const int flats[] = {256, 512, 1024, 2048, 4096};
-    const int old_cpt = c->cpt;
+    const int old_cpt = c->cpt, old_fnt = c->fnt;
     double best_total = 1e300;
-    int best_cpt = old_cpt;
+    int best_cpt = old_cpt, best_fnt = old_fnt;
     std::vector<TuneEntry> best(c->nsets), cur(c->nsets);
+    // cells per thread and, for the single-sync step, its block size (256 or 512 threads), which
+    // every set of the context shares; per set the planes per chunk and the tile order
     for (int cpt = 1; cpt <= 2 && rc == EQS_OK; ++cpt) {
         if (march_lds_bytes(cpt, c->max_nx, 8) > kMaxLds) continue;
-        if (c->sync1 && fused_lds_bytes(cpt, c->max_nx, 8) > kMaxLds) continue;
-        c->cpt = cpt;
-        clear_graphs(c);
-        double total = 0.0;
-        for (int s = 0; s < c->nsets && rc == EQS_OK; ++s) {
-            SetHost &h = c->sets[s];
-            const int kc0 = h.KC;
-            TuneEntry b{cpt, kc0, h.nflat, 1e300};
-            for (int kc : kcs) {
-                if (kc > h.g.nz) continue;
-                set_tiling(h, cpt, kc, h.nflat);
-                const double us = time_steps(c, s, 1, tmp, nmax, iters);
-                if (us == -1.0) { rc = EQS_ERR_HIP; break; }
-                if (us > 0 && us < b.us) b = TuneEntry{cpt, kc, h.nflat, us};
-            }
+        for (int fnt : {256, 512}) {
             if (rc != EQS_OK) break;
-            // a set too small to iterate this long keeps its default depth
-            if (b.us >= 1e300) b = TuneEntry{cpt, kc0, h.nflat, 0.0};
-            cur[s] = b;
-            total += b.us;
-        }
-        if (rc == EQS_OK && total < best_total) {
-            best_total = total;
-            best_cpt = cpt;
-            best = cur;
+            if (!c->sync1 && fnt != 256) continue;
+            if (c->sync1 && !(fused_shape_ok(cpt, c->max_nx, fnt) &&
+                              fused_lds_bytes(cpt, c->max_nx, 8, fnt) <= c->fused_lds_cap))
+                continue;
+            c->cpt = cpt;
+            c->fnt = fnt;
+            clear_graphs(c);
+            double total = 0.0;
+            for (int s = 0; s < c->nsets && rc == EQS_OK; ++s) {
+                SetHost &h = c->sets[s];
+                const int kc0 = h.KC;
+                TuneEntry b{cpt, kc0, h.nflat, fnt, 0, 1e300};
+                for (int kc : kcs) {
+                    if (kc > h.g.nz && kc != kcs[0]) continue;
+                    for (int ford = 0; ford <= (c->sync1 ? 1 : 0); ++ford) {
+                        set_tiling(h, cpt, kc, h.nflat, fnt, ford);
+                        const double us = time_steps(c, s, 1, tmp, nmax, iters);
+                        if (us == -1.0) { rc = EQS_ERR_HIP; break; }
+                        if (us > 0 && us < b.us) b = TuneEntry{cpt, kc, h.nflat, fnt, ford, us};
+                    }
+                    if (rc != EQS_OK) break;
+                }
+                if (rc != EQS_OK) break;
+                // a set too small to iterate this long keeps its default depth
+                if (b.us >= 1e300) b = TuneEntry{cpt, kc0, h.nflat, fnt, 0, 0.0};
+                cur[s] = b;
+                total += b.us;
+            }
+            if (rc == EQS_OK && total < best_total) {
+                best_total = total;
+                best_cpt = cpt;
+                best_fnt = fnt;
+                best = cur;
+            }
         }
     }
     // pointwise block count, with the chosen march tiling
     c->cpt = best_cpt;
+    c->fnt = best_fnt;
     clear_graphs(c);
     for (int s = 0; s < c->nsets && rc == EQS_OK; ++s) {
         SetHost &h = c->sets[s];
         for (int nf : flats) {
-            set_tiling(h, best_cpt, best[s].kc, nf);
+            set_tiling(h, best_cpt, best[s].kc, nf, best_fnt, best[s].ford);
             if (h.nflat != nf) continue;
             const double us = time_steps(c, s, 1, tmp, nmax, iters);
             if (us == -1.0) { rc = EQS_ERR_HIP; break; }
-            if (us > 0 && us < best[s].us) best[s] = TuneEntry{best_cpt, best[s].kc, nf, us};
+            if (us > 0 && us < best[s].us) best[s] = TuneEntry{best_cpt, best[s].kc, nf, best_fnt, best[s].ford, us};
         }
     }
     // Several sets: their batched launch holds every set's tiles at once, so the depths that are
     // fastest for each set alone can leave the last round of blocks part-empty.  Time the batched
     // step under the per-set choice and under one common depth for all sets, and keep the fastest
     // (for this context only: the cache keeps the per-set choice, which a context of one set wants).
+    // A batched launch holds every set's tiles at once, so it is also timed under one common
+    // depth for all sets, in either tile order, with either block size of the single-sync step
+    // (the batch fills the device where one set's launch leaves its last round part-empty); the
+    // fastest wins for this context (the cache keeps the per-set choice, which a context of one
+    // set wants).
     std::vector<TuneEntry> chosen = best;
+    int chosen_fnt = best_fnt;
     if (rc == EQS_OK && c->nsets > 1 && c->sync1) {
-        c->cpt = best_cpt;
-        for (int s = 0; s < c->nsets; ++s) set_tiling(c->sets[s], best_cpt, best[s].kc, best[s].nflat);
+        c->fnt = best_fnt;
+        for (int s = 0; s < c->nsets; ++s)
+            set_tiling(c->sets[s], best_cpt, best[s].kc, best[s].nflat, best_fnt, best[s].ford);
         clear_graphs(c);
         double best_us = time_steps(c, 0, c->nsets, tmp, nmax, iters);
         if (best_us == -1.0) rc = EQS_ERR_HIP;
         const int common[] = {8, 12, 16, 24, 32, 48};
-        for (int kc : common) {
-            if (rc != EQS_OK || best_us <= 0) break;
-            for (int s = 0; s < c->nsets; ++s) set_tiling(c->sets[s], best_cpt, kc, best[s].nflat);
-            clear_graphs(c);
-            const double us = time_steps(c, 0, c->nsets, tmp, nmax, iters);
-            if (us == -1.0) { rc = EQS_ERR_HIP; break; }
-            if (us > 0 && us < 0.98 * best_us) {
-                best_us = us;
-                for (int s = 0; s < c->nsets; ++s) chosen[s] = TuneEntry{best_cpt, c->sets[s].KC, best[s].nflat, us};
-            }
+        for (int fnt : {256, 512}) {
+            if (!(fused_shape_ok(best_cpt, c->max_nx, fnt) &&
+                  fused_lds_bytes(best_cpt, c->max_nx, 8, fnt) <= c->fused_lds_cap))
+                continue;
+            c->fnt = fnt;
+            for (int ford = 0; ford <= 1; ++ford)
+                for (int kc : common) {
+                    if (rc != EQS_OK || best_us <= 0) break;
+                    for (int s = 0; s < c->nsets; ++s)
+                        set_tiling(c->sets[s], best_cpt, kc, best[s].nflat, fnt, ford);
+                    clear_graphs(c);
+                    const double us = time_steps(c, 0, c->nsets, tmp, nmax, iters);
+                    if (us == -1.0) { rc = EQS_ERR_HIP; break; }
+                    if (us > 0 && us < 0.98 * best_us) {
+                        best_us = us;
+                        chosen_fnt = fnt;
+                        for (int s = 0; s < c->nsets; ++s)
+                            chosen[s] = TuneEntry{best_cpt, c->sets[s].KC, best[s].nflat, fnt, ford, us};
+                    }
+                }
         }
     }
     (void)hipStreamSynchronize(c->stream);
@@ -1505,7 +1597,7 @@ int eqsolve_autotune(eqs_ctx *c, const char *cache_path, int32_t iters) {
         c->broken = true;
         return rc;
     }
-    if ((rc = apply_tuning(c, best_cpt, chosen))) return rc;
+    if ((rc = apply_tuning(c, best_cpt, chosen_fnt, chosen))) return rc;
     const char *path = cache_path ? cache_path : getenv("EQS_TUNE_CACHE");
     for (int s = 0; s < c->nsets; ++s) cache_store(path, arch, c->sets[s].g, c->precision, best[s]);
     return EQS_OK;

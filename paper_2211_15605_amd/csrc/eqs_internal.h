@@ -79,6 +79,10 @@ struct SetDesc {
     int32_t nx, ny, nz, plane, n;
     // march tiling: S segments of Q = kBlock*cpt cells per plane, KC planes per chunk
     int32_t S, KC, NKC, ntiles;
+    // the single-sync step's own tiling: fS segments of fnt*cpt cells per plane (fnt = its block
+    // size, LaunchSets::fnt), the same chunks, fntiles tiles numbered chunk-fastest (ford = 0) or
+    // segment-fastest (ford = 1)
+    int32_t fS, fntiles, ford, fpad;
     // pointwise kernels: nflat blocks, block b takes chunks b, b + nflat, ... of kFlatChunk cells
     int32_t nflat;
     int32_t mode;
@@ -142,6 +146,8 @@ struct LaunchSets {
     int32_t nsets;
     int32_t tile_begin[kMaxSets + 1];
     int32_t flat_begin[kMaxSets + 1];
+    int32_t ftile_begin[kMaxSets + 1];  // the single-sync step's tiles (SetDesc::fntiles)
+    int32_t fnt;                        // threads per block of the single-sync step (256 or 512)
     const SetDesc *desc;   // device table, nsets entries
 };
 

@@ -67,6 +67,16 @@ __device__ __forceinline__ TileRef locate(const LaunchSets &ls) {
     return TileRef{ls.desc + s, L - (FLAT ? ls.flat_begin[s] : ls.tile_begin[s])};
 }
 
+// block -> (set, tile) for the single-sync step (its own tiling)
+__device__ __forceinline__ TileRef locate_fused(const LaunchSets &ls) {
+    const int L = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    int s = 0;
+#pragma unroll
+    for (int q = 1; q < kMaxSets; ++q)
+        if (q < ls.nsets && L >= ls.ftile_begin[q]) s = q;
+    return TileRef{ls.desc + s, L - ls.ftile_begin[s]};
+}
+
 // global-address-space accessors: pointers taken from the set table are
 // generic; these make every access a global (not flat) memory operation
 template <typename T>
@@ -77,8 +87,14 @@ template <typename T>
 __device__ __forceinline__ void st(T *p, int i, T v) {
     ((__attribute__((address_space(1))) T *)p)[i] = v;
 }
+// a nontemporal store: for vectors no block of the same launch reads back (the single-sync step
+// writes the buffer slot its neighbours do not read), so they need not be kept in L2
+template <typename T>
+__device__ __forceinline__ void st_nt(T *p, int i, T v) {
+    __builtin_nontemporal_store(v, (__attribute__((address_space(1))) T *)p + i);
+}
 
-template <int NV>
+template <int NV, int NT = kBlock>
 __device__ __forceinline__ void block_sum(double (&v)[NV], double *red) {
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
@@ -95,7 +111,12 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *red) {
     __syncthreads();
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int i = 0; i < NV; ++i) v[i] = ((red[i] + red[NV + i]) + red[2 * NV + i]) + red[3 * NV + i];
+        for (int i = 0; i < NV; ++i) {
+            double t = ((red[i] + red[NV + i]) + red[2 * NV + i]) + red[3 * NV + i];
+#pragma unroll
+            for (int w = 4; w < NT / 64; ++w) t += red[w * NV + i];
+            v[i] = t;
+        }
     }
 }
 
@@ -109,14 +130,14 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *red) {
 // ticket; an agent-scope release there would write back the XCD's whole L2,
 // once per block.  Nothing else written by the kernel is read by the last
 // block.
-template <int NV, class Fin>
+template <int NV, class Fin, int NT = kBlock>
 __device__ __forceinline__ void reduce_and_finalize(const SetDesc &d, int tile, int count, double (&acc)[NV],
                                                     Fin fin) {
-    __shared__ double red[4 * kMaxRed];
+    __shared__ double red[(NT / 64) * kMaxRed];
     __shared__ int last;
     double *partials = d.partials;
     uint32_t *counter = d.counter;
-    block_sum<NV>(acc, red);
+    block_sum<NV, NT>(acc, red);
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int i = 0; i < NV; ++i)
@@ -130,13 +151,13 @@ __device__ __forceinline__ void reduce_and_finalize(const SetDesc &d, int tile, 
     double s[NV];
 #pragma unroll
     for (int i = 0; i < NV; ++i) s[i] = 0.0;
-    for (int b = threadIdx.x; b < count; b += kBlock) {
+    for (int b = threadIdx.x; b < count; b += NT) {
 #pragma unroll
         for (int i = 0; i < NV; ++i)
             s[i] += __hip_atomic_load(partials + (size_t)b * NV + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
-    block_sum<NV>(s, red);
+    block_sum<NV, NT>(s, red);
     if (threadIdx.x == 0) {
         fin(d.st, s);
         __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1167,9 +1188,9 @@ __device__ __forceinline__ float keep_if(bool c, float x) {
 // times 1/a_P of its cell), the products take a_E, a_N, a_T and the neighbours' a_E,
 // a_N, a_T for the W, S, B links, (A D^-1 p)_c = p_c - sum_nb a_nb(c) (p/a_P)_nb, and
 // the own cells' p and s come from registers: 4 coefficient words per cell instead of 6.
-template <typename T, int CPT, int H, bool SYM>
+template <typename T, int CPT, int H, bool SYM, int NT>
 __device__ __forceinline__ void fused_step(const TileRef &tr) {
-    constexpr int Q = kBlock * CPT;
+    constexpr int Q = NT * CPT;
     const SetDesc &d = *tr.d;
     const SolveState *st_ = d.st;
     const int in = st_->fpar, out = in ^ 1;
@@ -1188,8 +1209,11 @@ __device__ __forceinline__ void fused_step(const TileRef &tr) {
     // touched last (still in the MALL, the memory-side cache) and ends on those
     // the next step will start from
     const bool flip = in != 0;
-    const int tl = flip ? d.ntiles - 1 - tr.tile : tr.tile;
-    const int chunk = tl % NKC, seg = tl / NKC;
+    const int tl = flip ? d.fntiles - 1 - tr.tile : tr.tile;
+    // chunk-fastest: the chunks of a column of segments are neighbours in the launch; segment-
+    // fastest: the segments of a chunk are, so neighbouring segments (whose rings read each
+    // other's cells) start together and march in step
+    const int chunk = d.ford ? tl / d.fS : tl % NKC, seg = d.ford ? tl % d.fS : tl / NKC;
     const int q0 = seg * Q, k0 = chunk * KC, k1 = min(k0 + KC, nz);
     const bool down = ((chunk & 1) != 0) != flip;
     const int dk = down ? -1 : 1;
@@ -1205,9 +1229,9 @@ __device__ __forceinline__ void fused_step(const TileRef &tr) {
     Nb nbo[CPT];
 #pragma unroll
     for (int m = 0; m < CPT; ++m) {
-        const int q = q0 + tid + kBlock * m;
+        const int q = q0 + tid + NT * m;
         qo[m] = min(q, P - 1);
-        eo[m] = 2 * nx + tid + kBlock * m;
+        eo[m] = 2 * nx + tid + NT * m;
         oko[m] = q < P;
         const int j = qo[m] / nx, i = qo[m] - j * nx;
         nbo[m] = Nb{i + 1 < nx, i > 0, j + 1 < ny, j > 0};
@@ -1220,7 +1244,7 @@ __device__ __forceinline__ void fused_step(const TileRef &tr) {
     Nb nbi[H];
 #pragma unroll
     for (int h = 0; h < H; ++h) {
-        const int hh = tid + kBlock * h;
+        const int hh = tid + NT * h;
         const bool use = hh < 2 * nx;
         // inner ring: e in [nx, 2nx) and [Q + 2nx, Q + 3nx)
         const int e1 = hh < nx ? nx + hh : Q + nx + hh;
@@ -1267,13 +1291,15 @@ __device__ __forceinline__ void fused_step(const TileRef &tr) {
     // for step it + 1 as soon as its p planes are in LDS, so they are in flight while it forms
     // the products (its barriers wait for LDS only); the first step's are issued before the
     // loop.  Every load is unconditional, at a plane index clamped into the grid (y, f: into
-    // the chunk), so the extra loads after the last step stay in bounds.  FP64 with more than
-    // one halo slot per ring issues them at the top of their own step instead: the values held
-    // a step longer would take it past 256 VGPRs and halve its occupancy.
-    constexpr bool PF = sizeof(T) == 4 || H == 1;
+    // the chunk), so the extra loads after the last step stay in bounds.  FP64 with four halo
+    // slots per ring issues them at the top of their own step instead: the values held a step
+    // longer would take it past 256 VGPRs and halve its occupancy.
+    constexpr bool PF = sizeof(T) == 4 || H <= 2;
     // the rings' loads (mostly L2 hits: the neighbouring segments load the same cells) go a
-    // step ahead too, except in the FP64 symmetric form, which has no registers to spare
-    constexpr bool PFR = PF && !(SYM && sizeof(T) == 8);
+    // step ahead too with one halo slot per ring, except in the FP64 symmetric form, which has
+    // no registers to spare (FP64 with two slots: 251 VGPRs with the own cells' loads a step
+    // ahead, past 256 with the rings' as well)
+    constexpr bool PFR = (sizeof(T) == 4 || H == 1) && !(SYM && sizeof(T) == 8);
     struct VecLoads {
         T s[CPT], t[CPT], p[CPT], v[CPT], y[CPT], f[CPT], g[CPT];
         T si[H], ti[H], pi[H], vi[H], gi[H], sr[H], tr[H], pr[H], vr[H], gr[H];
@@ -1377,8 +1403,8 @@ __device__ __forceinline__ void fused_step(const TileRef &tr) {
             asm volatile("" ::"v"(yn));  // formed on every lane, before the branch (no sunk loads)
             if (own) {
                 const int i = qo[m] + kpb;
-                st(pO, i, pv);
-                if (!fresh) st(yv, i, yn);
+                st_nt(pO, i, pv);
+                if (!fresh) st_nt(yv, i, yn);
             }
             acc[0] += (double)keep_if(own, cv.f[m]) * (double)pv;
             acc[8] += (double)keep_if(own, r) * (double)r;
@@ -1420,8 +1446,8 @@ __device__ __forceinline__ void fused_step(const TileRef &tr) {
                 const bool own = vown && oko[m];
                 if (own) {
                     const int i = qo[m] + kvb;
-                    st(vO, i, v);
-                    st(sO, i, sv);
+                    st_nt(vO, i, v);
+                    st_nt(sO, i, sv);
                 }
                 const T vk = keep_if(own, v), sk = keep_if(own, sv);
                 acc[1] += (double)fB[m] * (double)vk;
@@ -1451,7 +1477,7 @@ __device__ __forceinline__ void fused_step(const TileRef &tr) {
                 const int e = eo[m];
                 const T s0 = SYM ? sCo[m] : sc[e];
                 const T t = cC[m].apply(s0, sc[e + 1], sc[e - 1], sc[e + nx], sc[e - nx], su[e], sd[e]);
-                if (oko[m]) st(tO, qo[m] + kt * P, t);
+                if (oko[m]) st_nt(tO, qo[m] + kt * P, t);
                 const T tk = keep_if(oko[m], t);
                 acc[3] += (double)fC[m] * (double)tk;
                 acc[5] += (double)rhC[m] * (double)tk;
@@ -1483,16 +1509,17 @@ __device__ __forceinline__ void fused_step(const TileRef &tr) {
         bv = bp;
         bp = b0;
     }
-    reduce_and_finalize<11>(d, tr.tile, d.ntiles, acc, FinFused{d.sigma_tol[sizeof(T) == 4 ? 1 : 0]});
+    reduce_and_finalize<11, FinFused, NT>(d, tr.tile, d.fntiles, acc, FinFused{d.sigma_tol[sizeof(T) == 4 ? 1 : 0]});
 }
 
-// SYM is chosen on the host, for a launch whose sets are all exactly symmetric
-template <typename T, int CPT, int H, bool SYM>
-__global__ void __launch_bounds__(kBlock) fused_kernel(LaunchSets ls) {
-    const TileRef tr = locate<false>(ls);
+// SYM is chosen on the host, for a launch whose sets are all exactly symmetric; NT (256 or 512
+// threads) by the launch shape
+template <typename T, int CPT, int H, bool SYM, int NT>
+__global__ void __launch_bounds__(NT) fused_kernel(LaunchSets ls) {
+    const TileRef tr = locate_fused(ls);
     const SolveState *st_ = tr.d->st;
     if (!st_->active || st_->need_f) return;
-    fused_step<T, CPT, H, SYM>(tr);
+    fused_step<T, CPT, H, SYM, NT>(tr);
 }
 
 // ------------------------------------------------------------------ pointwise kernels
@@ -2641,31 +2668,64 @@ size_t march_lds_bytes(int cpt, int max_nx, int elem) {
     return (size_t)3 * (size_t)(kBlock * cpt + 2 * max_nx) * (size_t)elem;
 }
 
-int halo_slots(int max_nx) {
-    const int need = (2 * max_nx + kBlock - 1) / kBlock;
+int halo_slots(int max_nx, int nt) {
+    const int need = (2 * max_nx + nt - 1) / nt;
     return need <= 1 ? 1 : need <= 2 ? 2 : need <= 4 ? 4 : need <= 8 ? 8 : -1;
 }
 
-size_t fused_lds_bytes(int cpt, int max_nx, int elem) {
-    // p and s: three planes each; plus one pad cell per thread
-    return ((size_t)6 * (size_t)(kBlock * cpt + 4 * max_nx) + kBlock) * (size_t)elem;
+size_t fused_lds_bytes(int cpt, int max_nx, int elem, int nt) {
+    // p and s: three planes each of nt * cpt + 4 nx values; plus one pad cell per thread; the
+    // block's reduction scratch is static
+    return ((size_t)6 * (size_t)(nt * cpt + 4 * max_nx) + (size_t)nt) * (size_t)elem;
 }
 
-// the single-sync kernel takes 1, 2 or 4 halo slots per ring
-#define EQS_DISPATCH_FUSED(cpt, h, BODY)                                             \
+bool fused_shape_ok(int cpt, int max_nx, int nt) {
+    const int h = halo_slots(max_nx, nt);
+    if (nt == 256) return (cpt == 1 || cpt == 2) && h >= 1 && h <= 4;
+    return nt == 512 && cpt == 2 && h >= 1 && h <= 2;
+}
+
+// the single-sync kernel: 256 threads with 1 or 2 cells per thread and 1, 2 or 4 halo slots per
+// ring, or 512 threads with 2 cells per thread and 1 or 2 halo slots
+#define EQS_DISPATCH_FUSED(cpt, h, nt, BODY)                                         \
     do {                                                                             \
-        if ((cpt) == 1) {                                                            \
-            constexpr int C = 1;                                                     \
+        if ((nt) == 512) {                                                           \
+            constexpr int C = 2, NTT = 512;                                          \
+            if ((h) == 1) { constexpr int HH = 1; BODY; }                            \
+            else { constexpr int HH = 2; BODY; }                                     \
+        } else if ((cpt) == 1) {                                                     \
+            constexpr int C = 1, NTT = 256;                                          \
             if ((h) == 1) { constexpr int HH = 1; BODY; }                            \
             else if ((h) == 2) { constexpr int HH = 2; BODY; }                       \
             else { constexpr int HH = 4; BODY; }                                     \
         } else {                                                                     \
-            constexpr int C = 2;                                                     \
+            constexpr int C = 2, NTT = 256;                                          \
             if ((h) == 1) { constexpr int HH = 1; BODY; }                            \
             else if ((h) == 2) { constexpr int HH = 2; BODY; }                       \
             else { constexpr int HH = 4; BODY; }                                     \
         }                                                                            \
     } while (0)
+
+// Dynamic LDS beyond 64 KB must be allowed per kernel: every instantiation of the single-sync step
+// may take up to `bytes` (the device's per-block limit)
+hipError_t allow_fused_lds(size_t bytes) {
+    hipError_t e = hipSuccess;
+    auto allow = [&](const void *f) {
+        if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    };
+    auto all_forms = [&](int cpt, int h, int nt) {
+        EQS_DISPATCH_FUSED(cpt, h, nt, {
+            allow((const void *)fused_kernel<double, C, HH, false, NTT>);
+            allow((const void *)fused_kernel<double, C, HH, true, NTT>);
+            allow((const void *)fused_kernel<float, C, HH, false, NTT>);
+            allow((const void *)fused_kernel<float, C, HH, true, NTT>);
+        });
+    };
+    for (int cpt = 1; cpt <= 2; ++cpt)
+        for (int h : {1, 2, 4}) all_forms(cpt, h, 256);
+    for (int h : {1, 2}) all_forms(2, h, 512);
+    return e;
+}
 
 #define EQS_DISPATCH(cpt, h, BODY)                                                   \
     do {                                                                             \
@@ -2696,7 +2756,7 @@ size_t fused_lds_bytes(int cpt, int max_nx, int elem) {
 hipError_t launch_mg_fine(const LaunchSets &ls, int ntiles, int cpt, int max_nx, const MgLevel *lev, const double *rin,
                           double *res, double *zout, MgParams prm, bool gated, hipStream_t stream) {
     const dim3 grid(ntiles), block(kBlock);
-    const int h = halo_slots(max_nx);
+    const int h = halo_slots(max_nx, kBlock);
     if (h < 0 || (cpt != 1 && cpt != 2)) return hipErrorInvalidValue;
     const size_t lds64 = march_lds_bytes(cpt, max_nx, 8);
     if (res)
@@ -2718,7 +2778,7 @@ hipError_t launch_kernel(Kern k, const LaunchSets &ls, int ntiles, int nflat, in
                          bool trans, hipStream_t stream, const double *x, double *y, int arg, hipEvent_t e0,
                          hipEvent_t e1) {
     const dim3 grid(ntiles), fgrid(nflat), block(kBlock);
-    const int h = halo_slots(max_nx);
+    const int h = halo_slots(max_nx, kBlock);
     if (h < 0 || (cpt != 1 && cpt != 2)) return hipErrorInvalidValue;
     const size_t lds64 = march_lds_bytes(cpt, max_nx, 8), lds32 = march_lds_bytes(cpt, max_nx, 4);
     switch (k) {
@@ -2769,14 +2829,16 @@ hipError_t launch_kernel(Kern k, const LaunchSets &ls, int ntiles, int nflat, in
         else EQS_DISPATCH(cpt, h, EQS_LAUNCH((apply_kernel<C, HH, false>), grid, block, lds64, ls, x, y));
         break;
     case K_FUSED: {  // the scaled operator needs no transpose variant; arg: symmetric form
-        if (h > 4) return hipErrorInvalidValue;
-        const size_t fl = fused_lds_bytes(cpt, max_nx, fp32 ? 4 : 8);
+        const int nt = ls.fnt, fh = halo_slots(max_nx, nt);
+        if (!fused_shape_ok(cpt, max_nx, nt)) return hipErrorInvalidValue;
+        const dim3 fg(ls.ftile_begin[ls.nsets]), fb(nt);
+        const size_t fl = fused_lds_bytes(cpt, max_nx, fp32 ? 4 : 8, nt);
         if (arg) {  // every set of the launch exactly symmetric
-            if (fp32) EQS_DISPATCH_FUSED(cpt, h, EQS_LAUNCH((fused_kernel<float, C, HH, true>), grid, block, fl, ls));
-            else EQS_DISPATCH_FUSED(cpt, h, EQS_LAUNCH((fused_kernel<double, C, HH, true>), grid, block, fl, ls));
+            if (fp32) EQS_DISPATCH_FUSED(cpt, fh, nt, EQS_LAUNCH((fused_kernel<float, C, HH, true, NTT>), fg, fb, fl, ls));
+            else EQS_DISPATCH_FUSED(cpt, fh, nt, EQS_LAUNCH((fused_kernel<double, C, HH, true, NTT>), fg, fb, fl, ls));
         } else {
-            if (fp32) EQS_DISPATCH_FUSED(cpt, h, EQS_LAUNCH((fused_kernel<float, C, HH, false>), grid, block, fl, ls));
-            else EQS_DISPATCH_FUSED(cpt, h, EQS_LAUNCH((fused_kernel<double, C, HH, false>), grid, block, fl, ls));
+            if (fp32) EQS_DISPATCH_FUSED(cpt, fh, nt, EQS_LAUNCH((fused_kernel<float, C, HH, false, NTT>), fg, fb, fl, ls));
+            else EQS_DISPATCH_FUSED(cpt, fh, nt, EQS_LAUNCH((fused_kernel<double, C, HH, false, NTT>), fg, fb, fl, ls));
         }
         break;
     }

@@ -56,14 +56,22 @@ hipError_t launch_mg_aggregate(const SetDesc *d, const MgLevel *lev, int nc, con
 hipError_t launch_mg_prolong(const SetDesc *d, const MgLevel *lev, int l, int n, const double *rin, double *zout,
                              MgParams prm, bool gated, hipStream_t stream);
 
-// LDS bytes of the single-sync kernel (p and s, three planes each of Q + 4 nx values)
-size_t fused_lds_bytes(int cpt, int max_nx, int elem);
+// LDS bytes of the single-sync kernel with nt threads per block (p and s, three planes each of
+// nt * cpt + 4 nx values, and a pad cell per thread)
+size_t fused_lds_bytes(int cpt, int max_nx, int elem, int nt);
+
+// the single-sync kernel has an instantiation for this shape (nt = 256: cpt 1 or 2, up to 4 halo
+// slots; nt = 512: cpt 2, up to 2 halo slots)
+bool fused_shape_ok(int cpt, int max_nx, int nt);
+
+// let every instantiation of the single-sync kernel take up to `bytes` of dynamic LDS
+hipError_t allow_fused_lds(size_t bytes);
 
 // LDS bytes of a march kernel (three plane buffers of Q + 2 nx values)
 size_t march_lds_bytes(int cpt, int max_nx, int elem);
 
-// halo cells per thread per plane (1, 2, 4 or 8), or -1 if nx is too wide
-int halo_slots(int max_nx);
+// halo cells per thread per plane for blocks of nt threads (1, 2, 4 or 8), or -1 if nx is too wide
+int halo_slots(int max_nx, int nt);
 
 // cells of the largest set the one-block persistent solve takes
 constexpr int kSmallSolveMaxCells = 2048;

@@ -94,7 +94,8 @@ class Context:
 
     def layout(self, set_id=0):
         rc, v = B.eqsolve_debug_layout(self.h, set_id)
-        keys = ("cpt", "segments", "kc", "chunks", "tiles", "readbacks", "syncs", "flat_blocks")
+        keys = ("cpt", "segments", "kc", "chunks", "tiles", "readbacks", "syncs", "flat_blocks", "fused_threads",
+                "fused_segments", "fused_tiles", "fused_order")
         return dict(zip(keys, v))
 
     def set_preconditioner(self, kind="jacobi", **params):

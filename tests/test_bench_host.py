@@ -19,17 +19,58 @@ def test_more_than_one_gpu_is_refused_with_a_message():
     assert "one GPU" in r.stderr and r.stdout == ""
 
 
-def test_traffic_record_is_used_only_while_it_matches_the_kernel_source():
-    rec = json.load(open(os.path.join(ROOT, "profiles", "fused_fp64_sym128x256x128_traffic.json")))
-    got = bench.measured_traffic(1, "fused")
-    if rec["kernel_source_sha256"] == bench.kernel_source_digest():
-        assert got == rec["bytes_per_launch"]
-        # counted traffic is the algorithmic bytes plus halo re-reads: within 20 % above
-        assert rec["algorithmic_bytes_per_launch"] <= got <= 1.2 * rec["algorithmic_bytes_per_launch"]
-    else:
-        assert got is None
-    assert bench.measured_traffic(2, "fused") is None
-    assert bench.measured_traffic(1, "nonexistent") is None
+def test_traffic_records_are_used_only_with_the_device_code_they_were_taken_with():
+    import glob
+    lib = os.path.join(ROOT, "paper_2211_15605_amd", "libeqsolve.so")
+    if not os.path.exists(lib):
+        from paper_2211_15605_amd import build
+        build.build()
+    digest = bench.code_object_digest()
+    assert len(digest) == 64
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*_traffic.json")):
+        rec = json.load(open(path))
+        kern, workload = os.path.basename(path)[:-len("_traffic.json")].split("_", 1) \
+            if not os.path.basename(path).startswith("fused_sym_") else ("fused_sym", os.path.basename(path)[10:-13])
+        got = bench.measured_traffic(workload, kern)
+        if rec["code_object_sha256"] == digest:
+            assert got == rec["bytes_per_launch"]
+            # counted traffic is the algorithmic bytes plus halo re-reads: within 20 % above
+            assert 0.95 <= rec["traffic_over_algorithmic_full"] <= 1.2
+        else:
+            assert got is None
+    assert bench.measured_traffic("nonexistent_workload", "fused") is None
+
+
+def test_reduce_pmc_scales_by_the_copy_and_keeps_launches_that_did_work(tmp_path):
+    # two synthetic counter files: three 1 GiB copies that read as 512 MiB fetched (scale 2),
+    # 1 GiB written (scale 1), and four dispatches of the kernel, one of which did no work
+    import csv
+    hdr = ["Dispatch_Id", "Kernel_Name", "Grid_Size", "Counter_Name", "Counter_Value"]
+    for counter, copy_kib, kvals in (("FETCH_SIZE", 512 * 1024, [100.0, 100.0, 80.0, 0.1]),
+                                     ("WRITE_SIZE", 1024 * 1024, [50.0, 50.0, 40.0, 0.0])):
+        d = tmp_path / counter
+        d.mkdir()
+        with open(d / "run_counter_collection.csv", "w", newline="") as f:
+            w = csv.writer(f)
+            w.writerow(hdr)
+            i = 0
+            for v in kvals:
+                w.writerow([i, "void eqs::fused_kernel<double, 2, 2, false>(eqs::LaunchSets)", 1024, counter, v])
+                i += 1
+            w.writerow([i, "other_kernel", 1024, counter, 1e6])
+            for _ in range(3):
+                i += 1
+                w.writerow([i, "void at::native::copy_kernel_impl", 1 << 27, counter, copy_kib])
+    out = tmp_path / "rec.json"
+    ns = bench.argparse.Namespace(reduce_pmc=[str(tmp_path / "FETCH_SIZE"), str(tmp_path / "WRITE_SIZE")],
+                                  pmc_kernel="fused_kernel<double, 2, 2, false>", pmc_grid=1024, pmc_words=18,
+                                  pmc_cells=1, pmc_workload="synthetic", pmc_out=str(out), pmc_commands=["a", "b"])
+    bench.reduce_pmc(ns)
+    rec = json.load(open(out))
+    assert rec["fetch_scale"] == 2.0 and rec["write_scale"] == 1.0
+    assert rec["dispatches_with_work"] == 3 and rec["full_dispatches"] == 2
+    assert abs(rec["bytes_per_launch"] - 1024 * (2 * (280 / 3) + (140 / 3))) < 1e-6
+    assert rec["bytes_per_full_launch"] == 1024 * (2 * 100 + 50)
 
 
 def test_algorithmic_words_per_step():

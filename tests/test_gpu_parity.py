@@ -73,6 +73,10 @@ PATH_IDS = ["small", "sync1", "sync3"]
 # the two march iterations on sets above the one-block size
 SCHEMES = [dict(), dict(EQS_SYNC=3)]
 SCHEME_IDS = ["sync1", "sync3"]
+# launch shapes of the single-sync step: 512-thread blocks over segments of 1024 cells, and tiles
+# numbered segment-fastest (each combined with small chunks, so several chunks and tiles per set)
+FUSED_SHAPES = [dict(EQS_FNT=512), dict(EQS_FORD=1, EQS_KC=3), dict(EQS_FNT=512, EQS_FORD=1, EQS_KC=5)]
+FUSED_IDS = ["fnt512", "ford1_kc3", "fnt512_ford1_kc5"]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
@@ -145,7 +149,8 @@ def test_fp64_matches_oracle_solution(torch_dev, orc, cfg, shape):
     g, diags, b, xs = manufactured(orc, cfg, grid=W.Grid(*shape))
     xo, oinfo = orc.bicgstab(g.shape, diags, b, tol=1e-13, maxit=5000)
     assert oinfo["status"] == 0
-    for tl in [dict(), dict(EQS_SYNC=3)] + TILINGS[:3] + [dict(TILINGS[2], EQS_SYNC=3)]:
+    for tl in [dict(), dict(EQS_SYNC=3)] + TILINGS[:3] + [dict(TILINGS[2], EQS_SYNC=3)] + \
+            [dict(f, EQS_SMALL=0) for f in FUSED_SHAPES]:
         ctx = context([g.shape], env=tl)
         x, info = ctx.solve(dev_arrays(torch, dev, diags), dev_arrays(torch, dev, [b])[0], tol=1e-13, maxit=5000)
         xg = host(x)
@@ -331,7 +336,7 @@ def test_fp32_pure_residual(torch_dev, orc, scheme):
 STAGGERED_SMALL = [(24, 96, 24), (25, 96, 24), (24, 97, 24), (24, 96, 25)]
 
 
-@pytest.mark.parametrize("scheme", SCHEMES, ids=SCHEME_IDS)
+@pytest.mark.parametrize("scheme", SCHEMES + FUSED_SHAPES, ids=SCHEME_IDS + FUSED_IDS)
 @pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
 def test_batched_equals_sequential_bitwise(torch_dev, orc, precision, scheme):
     torch, dev = torch_dev
@@ -694,8 +699,9 @@ def test_symmetric_form_meets_tol_against_oracle(torch_dev, orc, shape, precisio
         assert np.max(np.abs(xg - xs)) <= orc.forward_error_certificate(g.shape, diags, b, xg) * (1 + 1e-6)
 
 
-@pytest.mark.parametrize("tiling", TILINGS[1:] + [dict(EQS_SMALL=0, EQS_CPT=1, EQS_KC=5)],
-                         ids=["cpt1_kc1", "cpt2_kc3", "cpt2_kc7", "cpt1_kc5"])
+@pytest.mark.parametrize("tiling", TILINGS[1:] + [dict(EQS_SMALL=0, EQS_CPT=1, EQS_KC=5)] +
+                         [dict(f, EQS_SMALL=0) for f in FUSED_SHAPES],
+                         ids=["cpt1_kc1", "cpt2_kc3", "cpt2_kc7", "cpt1_kc5"] + FUSED_IDS)
 def test_symmetric_form_launch_layouts(torch_dev, orc, tiling):
     """Every tile layout (cells per thread, planes per chunk, halo slots) of the symmetric form
     against the oracle's FP64 residual, and against the general form's solution."""
@@ -800,14 +806,16 @@ def test_symmetric_matrix_adjoint_runs_the_transposed_general_form(torch_dev, or
 
 # ---------------------------------------------------------------- wide rows
 
-# rows of 203..266 cells take the single-sync step with one cell per thread, 257..512 four halo
-# slots per ring (266 the widest single-sync row in FP64, wider rows the three-launch iteration)
+# with the single-sync step's LDS capped at 64 KB, rows of 203..266 cells take it with one cell per
+# thread (257..266 with four halo slots per ring) and wider rows the three-launch iteration; with
+# the device's 160 KB, two cells per thread up to 512 (257..512: four halo slots)
 WIDE = [(230, 5, 4), (260, 5, 4), (266, 3, 3), (400, 4, 3)]
 
 
 @pytest.mark.parametrize("shape", WIDE)
 @pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
-@pytest.mark.parametrize("scheme", SCHEMES, ids=SCHEME_IDS)
+@pytest.mark.parametrize("scheme", SCHEMES + [dict(EQS_FNT=512), dict(EQS_FUSED_LDS=65536)],
+                         ids=SCHEME_IDS + ["fnt512", "lds64k"])
 def test_wide_rows_against_oracle(torch_dev, orc, shape, precision, scheme):
     torch, dev = torch_dev
     g, diags, b, xs = manufactured(orc, 0, grid=W.Grid(*shape))
@@ -873,3 +881,21 @@ def test_adjoint_config3_central_finite_differences(torch_dev, orc):
             direction, fd, pred, abs(fd - pred) / abs(pred), ip["iters"], im["iters"]), flush=True)
         assert abs(fd - pred) <= 1e-5 * abs(pred)
     ctx.close()
+
+
+def test_fused_launch_shapes_are_taken(torch_dev, orc):
+    # the environment selects the single-sync step's block size and tile order, and the layout
+    # reports what runs: 512 threads over 1024-cell segments where the shape allows it
+    torch, dev = torch_dev
+    g, diags, b, xs = manufactured(orc, 2, grid=W.Grid(96, 40, 9))
+    lay = {}
+    for name, env in (("default", dict()), ("fnt512", dict(EQS_FNT=512)), ("ford1", dict(EQS_FORD=1))):
+        ctx = context([g.shape], env=env)
+        x, info = ctx.solve(dev_arrays(torch, dev, diags), dev_arrays(torch, dev, [b])[0], tol=1e-12, maxit=3000)
+        lay[name] = ctx.layout()
+        ctx.close()
+        assert info["status"] == 0 and orc.rel_residual(g.shape, diags, b, host(x)) <= 1e-12, name
+    assert lay["default"]["fused_threads"] == 256 and lay["default"]["fused_order"] == 0
+    assert lay["fnt512"]["fused_threads"] == 512 and lay["fnt512"]["fused_segments"] == (96 * 40 + 1023) // 1024
+    assert lay["fnt512"]["fused_tiles"] == lay["fnt512"]["fused_segments"] * lay["fnt512"]["chunks"]
+    assert lay["ford1"]["fused_order"] == 1
