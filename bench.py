@@ -57,20 +57,78 @@ def step_words(syncs, symmetric):
     return WORDS["k1"], STEP_WORDS[syncs]
 
 
-def code_object_digest(lib=None):
-    """sha256 of the device code the library carries (its .hip_fatbin ELF section): it changes
-    with any change to a kernel, and not with host-only changes."""
-    import hashlib
+def _elf_sections(data):
     import struct
-    data = open(lib or os.path.join(ROOT, "paper_2211_15605_amd", "libeqsolve.so"), "rb").read()
     shoff, = struct.unpack_from("<Q", data, 0x28)
     shentsize, shnum, shstrndx = struct.unpack_from("<HHH", data, 0x3A)
-    secs = [struct.unpack_from("<IIQQQQ", data, shoff + i * shentsize) for i in range(shnum)]
+    secs = [struct.unpack_from("<IIQQQQIIQQ", data, shoff + i * shentsize) for i in range(shnum)]
     stroff = secs[shstrndx][4]
-    for name, _t, _f, _a, off, size in secs:
-        if data[stroff + name: data.index(b"\0", stroff + name)] == b".hip_fatbin":
-            return hashlib.sha256(data[off:off + size]).hexdigest()
-    raise RuntimeError("no .hip_fatbin section in the library")
+    names = [data[stroff + s[0]: data.index(b"\0", stroff + s[0])].decode() for s in secs]
+    return secs, names
+
+
+def device_code_objects(lib=None):
+    """The gfx950 code objects the library carries: its .hip_fatbin section holds one clang
+    offload bundle per compiled source, each with a host entry and a device ELF."""
+    import struct
+    data = open(lib or os.path.join(ROOT, "paper_2211_15605_amd", "libeqsolve.so"), "rb").read()
+    secs, names = _elf_sections(data)
+    sec = secs[names.index(".hip_fatbin")]
+    fb = data[sec[4]:sec[4] + sec[5]]
+    magic = b"__CLANG_OFFLOAD_BUNDLE__"
+    out, pos = [], 0
+    while True:
+        i = fb.find(magic, pos)
+        if i < 0:
+            return out
+        n, = struct.unpack_from("<Q", fb, i + 24)
+        p = i + 32
+        for _ in range(n):
+            eoff, esize, tlen = struct.unpack_from("<QQQ", fb, p)
+            triple = fb[p + 24:p + 24 + tlen].decode()
+            p += 24 + tlen
+            if "amdgcn" in triple and esize:
+                out.append(fb[i + eoff:i + eoff + esize])
+        pos = i + 1
+
+
+def kernel_code(lib=None):
+    """{mangled kernel symbol: its machine code bytes} over the library's device code objects."""
+    import struct
+    out = {}
+    for elf in device_code_objects(lib):
+        secs, names = _elf_sections(elf)
+        for si, sec in enumerate(secs):
+            if sec[1] != 2:   # SHT_SYMTAB
+                continue
+            strsec = secs[sec[6]]
+            for k in range(sec[5] // 24):
+                st_name, st_info, _o, st_shndx, st_value, st_size = struct.unpack_from("<IBBHQQ", elf, sec[4] + 24 * k)
+                if (st_info & 0xF) != 2 or st_size == 0 or st_shndx >= len(secs):   # STT_FUNC with code
+                    continue
+                nm = elf[strsec[4] + st_name: elf.index(b"\0", strsec[4] + st_name)].decode()
+                tgt = secs[st_shndx]
+                off = tgt[4] + (st_value - tgt[3])
+                out[nm] = elf[off:off + st_size]
+    return out
+
+
+def kernel_code_digest(symbol, lib=None):
+    """sha256 of one kernel's machine code in the built library (None if it has no such kernel)."""
+    import hashlib
+    code = kernel_code(lib).get(symbol)
+    return hashlib.sha256(code).hexdigest() if code is not None else None
+
+
+def mangled_kernel_name(demangled, lib=None):
+    """The symbol of the kernel a profiler names `demangled` (as rocprofv3 prints it)."""
+    import subprocess
+    syms = sorted(kernel_code(lib))
+    res = subprocess.run(["c++filt"], input="\n".join(syms), capture_output=True, text=True, check=True)
+    for sym, dem in zip(syms, res.stdout.splitlines()):
+        if dem.strip() == demangled.strip():
+            return sym
+    raise KeyError(demangled)
 
 
 def traffic_record_path(workload, kern):
@@ -80,12 +138,12 @@ def traffic_record_path(workload, kern):
 def measured_traffic(workload, kern):
     """HBM bytes per launch of the FP64 iteration kernel `kern` on `workload` from the committed
     rocprofv3 counter record (FETCH_SIZE + WRITE_SIZE, scaled by a 1 GiB copy), or None when the
-    record is missing or was taken with other device code than the library holds now."""
+    record is missing or the kernel's machine code has changed since the counters were taken."""
     path = traffic_record_path(workload, kern)
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    if rec.get("code_object_sha256") != code_object_digest():
+    if rec.get("kernel_code_sha256") != kernel_code_digest(rec.get("symbol", "")):
         return None
     return rec["bytes_per_launch"]
 
@@ -702,8 +760,11 @@ def reduce_pmc(args):
            "dispatches_with_work": f["dispatches"], "fetch_kib_mean": f["mean_kib"], "write_kib_mean": w["mean_kib"],
            "bytes_per_launch": per,
            "full_dispatches": f["full_dispatches"], "bytes_per_full_launch": per_full,
-           "algorithmic_bytes_per_full_launch": alg_full, "traffic_over_algorithmic_full": per_full / alg_full,
-           "code_object_sha256": code_object_digest()}
+           "algorithmic_bytes_per_full_launch": alg_full, "traffic_over_algorithmic_full": per_full / alg_full}
+    kname = [name for _, name, grid, _v in rows(args.reduce_pmc[0], "FETCH_SIZE")
+             if args.pmc_kernel in name and grid == args.pmc_grid][0]
+    rec["symbol"] = mangled_kernel_name(kname)
+    rec["kernel_code_sha256"] = kernel_code_digest(rec["symbol"])
     json.dump(rec, open(args.pmc_out, "w"), indent=1)
     print(json.dumps(rec))
 
@@ -728,7 +789,10 @@ def summarize_trace(args):
         if sum(v) < args.trace_min_share * tot:
             continue
         w = [x for x in v if x > 10000]
-        lines.append("| `%s` | %d | %d | %d | %.1f | %.2f |" % (name.split("(")[0], blocks, len(v), len(w),
+        short = name[:name.rindex("(")] if name.endswith(")") and "(" in name else name
+        if args.trace_kernels and not any(k in short for k in args.trace_kernels.split(",")):
+            continue
+        lines.append("| `%s` | %d | %d | %d | %.1f | %.2f |" % (short, blocks, len(v), len(w),
                                                              (sum(w) / len(w) / 1e3) if w else 0.0, sum(v) / 1e6))
     print("\n".join(lines))
 
@@ -762,6 +826,7 @@ def main():
     ap.add_argument("--pmc-commands", nargs=2, default=["", ""])
     ap.add_argument("--summarize-trace", metavar="TRACE_DIR", help="print a markdown summary of a kernel trace")
     ap.add_argument("--trace-min-share", type=float, default=0.01)
+    ap.add_argument("--trace-kernels", default="", help="comma-separated name parts: only those kernels")
     args = ap.parse_args()
     if args.reduce_pmc:
         reduce_pmc(args)
@@ -776,7 +841,11 @@ def main():
     from paper_2211_15605_amd import workloads as W
 
     if args.only_simple:
-        print(json.dumps({"simple_bed": time_simple()}))
+        out = {"simple_bed": time_simple()}
+        if args.calibrate_copy:
+            import torch
+            copy_calibration(out, torch.device("cuda", 0))
+        print(json.dumps(out))
         return
     if args.only_latency:
         print(json.dumps({"latency_cd16": time_latency()}))
@@ -788,7 +857,6 @@ def main():
     if not args.no_simple:
         if args.config != 1:
             c1, _ = gpu_leg(args, 1, steps=3, warmup=1, with_mg=not args.no_mg)
-            c1.pop("layout", None)
             sections["pressure_like_128x256x128"] = c1
         sections["simple_bed"] = time_simple()
         sections["latency_cd16"] = time_latency()

@@ -19,14 +19,15 @@ struct BoxK {
     double Ax, Ay, Az, V, aP0, De, Dn, Dt, rAx, rAy, rAz, rgV, oma;
 };
 
-// logical blocks [0, nb[0]) form u, [nb[0], nb[0]+nb[1]) v, the rest w; block q of a grid
-// forms the contiguous cells [q cpb, (q + 1) cpb) of it, 256 at a time
+// block q of grid g (nb[g] blocks: u, v, w) forms the contiguous cells [q cpb, (q + 1) cpb) of
+// it, 256 at a time, and leaves its partial at partials[nb[0] + ... + nb[g-1] + q]; the grids'
+// blocks run interleaved (see form_momentum_kernel)
 struct MomArgs {
     BoxK bx;
     const double *u, *v, *w, *p, *u0, *v0, *w0;
     double *a[3][7];
     double *b[3], *d[3];
-    double *partials;   // per logical block: sum of squared row residuals
+    double *partials;   // per block: sum of squared row residuals
     int32_t nb[3], cpb[3];
 };
 

@@ -192,17 +192,37 @@ __device__ void form_w(const MomArgs &A, const Geo &g, const Idx &X, int i, int 
     finish(bx, g, aE, aW, aN, aS, aT, aB, bnd, src, w[c], g.Az, r);
 }
 
+// Logical block lb -> (grid, block of that grid).  The three grids' blocks are interleaved:
+// round r holds block r of u, of v and of w, which cover nearly the same cells of the box (the
+// grids differ by one face along one axis), then the few blocks one grid has beyond the others.
+// Each XCD takes a contiguous run of logical blocks, so the u, v and w rows of one region of
+// the box are formed by one XCD and every field is read into one L2 (with the three grids in
+// separate runs, each field was fetched from memory by three XCDs).
+__device__ __forceinline__ void momentum_block(const MomArgs &A, int lb, int &comp, int &local) {
+    const int m = min(A.nb[0], min(A.nb[1], A.nb[2]));
+    if (lb < 3 * m) {
+        comp = lb % 3;
+        local = lb / 3;
+        return;
+    }
+    int rem = lb - 3 * m;
+    comp = 0;
+    while (comp < 2 && rem >= A.nb[comp] - m) rem -= A.nb[comp++] - m;
+    local = m + rem;
+}
+
 __global__ void __launch_bounds__(kThreads) form_momentum_kernel(MomArgs A) {
     const int total = A.nb[0] + A.nb[1] + A.nb[2];
     const int lb = logical_block(total);
     if (lb >= total) return;   // whole block: no barrier below is skipped by part of it
-    const int comp = lb < A.nb[0] ? 0 : (lb < A.nb[0] + A.nb[1] ? 1 : 2);
+    int comp, local;
+    momentum_block(A, lb, comp, local);
     const int first = comp == 0 ? 0 : (comp == 1 ? A.nb[0] : A.nb[0] + A.nb[1]);
     const BoxK &bx = A.bx;
     const int NX = bx.nx + (comp == 0), NY = bx.ny + (comp == 1), NZ = bx.nz + (comp == 2);
     const int n = NX * NY * NZ;
     const int cpb = A.cpb[comp];
-    const int base = (lb - first) * cpb;
+    const int base = local * cpb;
     const Geo g(bx);
     const Idx X{bx.nx, bx.ny, bx.nz};
     double res2 = 0.0;
@@ -232,7 +252,7 @@ __global__ void __launch_bounds__(kThreads) form_momentum_kernel(MomArgs A) {
         res2 += e * e;
     }
     const double s = block_sum(res2);
-    if (threadIdx.x == 0) A.partials[lb] = s;
+    if (threadIdx.x == 0) A.partials[first + local] = s;   // each grid's partials stay contiguous
 }
 
 __global__ void __launch_bounds__(kThreads) form_pressure_kernel(PresArgs A, int total) {

@@ -19,26 +19,38 @@ def test_more_than_one_gpu_is_refused_with_a_message():
     assert "one GPU" in r.stderr and r.stdout == ""
 
 
-def test_traffic_records_are_used_only_with_the_device_code_they_were_taken_with():
+def test_traffic_records_are_used_only_with_the_kernel_code_they_were_taken_with():
     import glob
     lib = os.path.join(ROOT, "paper_2211_15605_amd", "libeqsolve.so")
     if not os.path.exists(lib):
         from paper_2211_15605_amd import build
         build.build()
-    digest = bench.code_object_digest()
-    assert len(digest) == 64
-    for path in glob.glob(os.path.join(ROOT, "profiles", "*_traffic.json")):
+    recs = glob.glob(os.path.join(ROOT, "profiles", "*_traffic.json"))
+    assert recs
+    for path in recs:
         rec = json.load(open(path))
-        kern, workload = os.path.basename(path)[:-len("_traffic.json")].split("_", 1) \
-            if not os.path.basename(path).startswith("fused_sym_") else ("fused_sym", os.path.basename(path)[10:-13])
+        base = os.path.basename(path)[:-len("_traffic.json")]
+        kern = "fused_sym" if base.startswith("fused_sym_") else base.split("_", 1)[0]
+        workload = base[len(kern) + 1:]
+        assert rec["workload"] == workload
         got = bench.measured_traffic(workload, kern)
-        if rec["code_object_sha256"] == digest:
+        if rec["kernel_code_sha256"] == bench.kernel_code_digest(rec["symbol"]):
             assert got == rec["bytes_per_launch"]
             # counted traffic is the algorithmic bytes plus halo re-reads: within 20 % above
             assert 0.95 <= rec["traffic_over_algorithmic_full"] <= 1.2
         else:
             assert got is None
     assert bench.measured_traffic("nonexistent_workload", "fused") is None
+
+
+def test_kernel_code_is_found_per_kernel_in_the_built_library():
+    code = bench.kernel_code()
+    fused = [k for k in code if "12fused_kernel" in k]
+    # FP64/FP32 x general/symmetric x (256 threads: 2 cpt x 3 halo slots; 512 threads: 2 halo slots)
+    assert len(fused) == 2 * 2 * (6 + 2), sorted(fused)
+    assert all(len(code[k]) > 1000 for k in fused)
+    sym = bench.mangled_kernel_name("void eqs::fused_kernel<double, 2, 1, false, 512>(eqs::LaunchSets)")
+    assert sym in code and bench.kernel_code_digest(sym) == bench.kernel_code_digest(sym)
 
 
 def test_reduce_pmc_scales_by_the_copy_and_keeps_launches_that_did_work(tmp_path):
@@ -65,7 +77,12 @@ def test_reduce_pmc_scales_by_the_copy_and_keeps_launches_that_did_work(tmp_path
     ns = bench.argparse.Namespace(reduce_pmc=[str(tmp_path / "FETCH_SIZE"), str(tmp_path / "WRITE_SIZE")],
                                   pmc_kernel="fused_kernel<double, 2, 2, false>", pmc_grid=1024, pmc_words=18,
                                   pmc_cells=1, pmc_workload="synthetic", pmc_out=str(out), pmc_commands=["a", "b"])
-    bench.reduce_pmc(ns)
+    real = bench.mangled_kernel_name
+    bench.mangled_kernel_name = lambda name, lib=None: "_ZN3eqs12fused_kernelIdLi2ELi1ELb0ELi512EEEvNS_10LaunchSetsE"
+    try:
+        bench.reduce_pmc(ns)
+    finally:
+        bench.mangled_kernel_name = real
     rec = json.load(open(out))
     assert rec["fetch_scale"] == 2.0 and rec["write_scale"] == 1.0
     assert rec["dispatches_with_work"] == 3 and rec["full_dispatches"] == 2
