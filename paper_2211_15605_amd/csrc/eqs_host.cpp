@@ -979,7 +979,7 @@ int default_shape(eqs_ctx *c, const eqs_grid *grids, int nsets, int *max_nx_out)
         return fused_shape_ok(fc, max_nx, nt) && fused_lds_bytes(fc, max_nx, 8, nt) <= c->fused_lds_cap;
     };
     int fnt = env_int("EQS_FNT", 256) == 512 ? 512 : 256;
-    if (fnt == 512 && !(cpt == 2 && fits(2, 512))) fnt = 256;
+    if (fnt == 512 && !fits(cpt, 512)) fnt = 256;
     c->sync1 = env_int("EQS_SYNC", 1) != 3;
     if (c->sync1) {
         int fc = cpt;

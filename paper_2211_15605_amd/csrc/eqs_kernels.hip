@@ -2682,14 +2682,18 @@ size_t fused_lds_bytes(int cpt, int max_nx, int elem, int nt) {
 bool fused_shape_ok(int cpt, int max_nx, int nt) {
     const int h = halo_slots(max_nx, nt);
     if (nt == 256) return (cpt == 1 || cpt == 2) && h >= 1 && h <= 4;
-    return nt == 512 && cpt == 2 && h >= 1 && h <= 2;
+    return nt == 512 && (cpt == 1 || cpt == 2) && h >= 1 && h <= 2;
 }
 
 // the single-sync kernel: 256 threads with 1 or 2 cells per thread and 1, 2 or 4 halo slots per
-// ring, or 512 threads with 2 cells per thread and 1 or 2 halo slots
+// ring, or 512 threads with 1 or 2 cells per thread and 1 or 2 halo slots
 #define EQS_DISPATCH_FUSED(cpt, h, nt, BODY)                                         \
     do {                                                                             \
-        if ((nt) == 512) {                                                           \
+        if ((nt) == 512 && (cpt) == 1) {                                             \
+            constexpr int C = 1, NTT = 512;                                          \
+            if ((h) == 1) { constexpr int HH = 1; BODY; }                            \
+            else { constexpr int HH = 2; BODY; }                                     \
+        } else if ((nt) == 512) {                                                    \
             constexpr int C = 2, NTT = 512;                                          \
             if ((h) == 1) { constexpr int HH = 1; BODY; }                            \
             else { constexpr int HH = 2; BODY; }                                     \
@@ -2721,9 +2725,10 @@ hipError_t allow_fused_lds(size_t bytes) {
             allow((const void *)fused_kernel<float, C, HH, true, NTT>);
         });
     };
-    for (int cpt = 1; cpt <= 2; ++cpt)
+    for (int cpt = 1; cpt <= 2; ++cpt) {
         for (int h : {1, 2, 4}) all_forms(cpt, h, 256);
-    for (int h : {1, 2}) all_forms(2, h, 512);
+        for (int h : {1, 2}) all_forms(cpt, h, 512);
+    }
     return e;
 }
 

@@ -60,8 +60,8 @@ hipError_t launch_mg_prolong(const SetDesc *d, const MgLevel *lev, int l, int n,
 // nt * cpt + 4 nx values, and a pad cell per thread)
 size_t fused_lds_bytes(int cpt, int max_nx, int elem, int nt);
 
-// the single-sync kernel has an instantiation for this shape (nt = 256: cpt 1 or 2, up to 4 halo
-// slots; nt = 512: cpt 2, up to 2 halo slots)
+// the single-sync kernel has an instantiation for this shape (nt = 256: up to 4 halo slots;
+// nt = 512: up to 2; cpt 1 or 2)
 bool fused_shape_ok(int cpt, int max_nx, int nt);
 
 // let every instantiation of the single-sync kernel take up to `bytes` of dynamic LDS

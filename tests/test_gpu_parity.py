@@ -75,8 +75,9 @@ SCHEMES = [dict(), dict(EQS_SYNC=3)]
 SCHEME_IDS = ["sync1", "sync3"]
 # launch shapes of the single-sync step: 512-thread blocks over segments of 1024 cells, and tiles
 # numbered segment-fastest (each combined with small chunks, so several chunks and tiles per set)
-FUSED_SHAPES = [dict(EQS_FNT=512), dict(EQS_FORD=1, EQS_KC=3), dict(EQS_FNT=512, EQS_FORD=1, EQS_KC=5)]
-FUSED_IDS = ["fnt512", "ford1_kc3", "fnt512_ford1_kc5"]
+FUSED_SHAPES = [dict(EQS_FNT=512), dict(EQS_FORD=1, EQS_KC=3), dict(EQS_FNT=512, EQS_FORD=1, EQS_KC=5),
+                dict(EQS_FNT=512, EQS_CPT=1, EQS_KC=4)]
+FUSED_IDS = ["fnt512", "ford1_kc3", "fnt512_ford1_kc5", "fnt512_cpt1_kc4"]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
