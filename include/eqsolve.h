@@ -89,9 +89,10 @@ typedef struct {
  * single-sync iteration ran in its symmetric form, reading a_E, a_N, a_T and
  * 1/a_P instead of six scaled coefficients.  Set for a solve whose launch held
  * only such sets (in a batched call: every set); EQS_SYM=0 in the environment
- * at eqsolve_create turns the form off.
+ * at eqsolve_create turns the form off.  EQS_INFO_UNSCALED -- the solve ran the
+ * single-sync iteration in its unscaled form (eqsolve_set_step_form).
  */
-enum { EQS_INFO_SYMMETRIC = 1 };
+enum { EQS_INFO_SYMMETRIC = 1, EQS_INFO_UNSCALED = 2 };
 
 /*
  * Create a context for nsets equation sets with the given grids (the sets
@@ -167,6 +168,27 @@ int eqsolve_autotune(eqs_ctx *ctx, const char *cache_path, int32_t iters);
 
 /* Release the context and its workspace (NULL is allowed). */
 int eqsolve_destroy(eqs_ctx *ctx);
+
+/* How the single-sync iteration of the FP64 forward solves forms its products. */
+enum { EQS_STEP_SCALED = 0, EQS_STEP_UNSCALED = 1 };
+
+/*
+ * The iteration runs on M = A D^-1 (D = diag(a_P), the right Jacobi
+ * preconditioner; Woo et al. Sec. 2.2.2 for the per-set solve).  EQS_STEP_SCALED
+ * (the default): a pass at the start of every solve writes M's six
+ * off-diagonal coefficients a_nb(c) / a_P(nb(c)) (and checks for exact
+ * symmetry, which selects the symmetric form), and every step reads those six.
+ * EQS_STEP_UNSCALED: no such pass; every step reads the caller's six arrays and
+ * 1/a_P (written by the setup pass) and forms (M p)_c = p_c - sum_nb a_nb(c)
+ * (p / a_P)_nb -- one word per cell more per step, about fourteen less per
+ * solve, so it pays for systems that converge in a few steps, such as the
+ * momentum rows of a SIMPLE iteration, whose transient term dominates.  Both
+ * give the same iterates up to rounding.  For EQS_FP64 contexts only; the
+ * adjoint and the multigrid-preconditioned solves are unaffected.  Returns
+ * EQS_OK, EQS_ERR_ARG (form, or a context that is not EQS_FP64) or
+ * EQS_ERR_STATE.
+ */
+int eqsolve_set_step_form(eqs_ctx *ctx, int32_t form);
 
 /* Preconditioners of the FP64 forward solves. */
 enum { EQS_PRECOND_JACOBI = 0, EQS_PRECOND_MG = 1 };

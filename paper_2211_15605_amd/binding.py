@@ -21,14 +21,15 @@ EQS_OK, EQS_NOT_CONVERGED, EQS_BREAKDOWN, EQS_NONFINITE = 0, 1, 2, 3
 EQS_ERR_ARG, EQS_ERR_NOMEM, EQS_ERR_HIP, EQS_ERR_STATE, EQS_ERR_SIZE = -1, -2, -3, -4, -5
 # the largest system eqsolve_solve_noalloc takes (EQS_NOALLOC_MAX_CELLS, EQS_NOALLOC_BYTES)
 NOALLOC_MAX_CELLS, NOALLOC_BYTES = 262144, 40 << 20
-EQS_INFO_SYMMETRIC = 1
+EQS_INFO_SYMMETRIC, EQS_INFO_UNSCALED = 1, 2
+EQS_STEP_SCALED, EQS_STEP_UNSCALED = 0, 1
 PRECISIONS = {"fp64": EQS_FP64, "fp32_refine": EQS_FP32_REFINE, "fp32": EQS_FP32}
 
 # symbols declared in include/eqsolve.h
 SYMBOLS = ("eqsolve_create", "eqsolve_solve", "eqsolve_solve_batched", "eqsolve_adjoint", "eqsolve_apply",
            "eqsolve_destroy", "eqsolve_strerror", "eqsolve_autotune", "eqsolve_debug_layout",
            "eqsolve_debug_profile", "eqsolve_debug_kernel_stats", "eqsolve_set_preconditioner",
-           "eqsolve_debug_precond", "eqsolve_solve_noalloc",
+           "eqsolve_debug_precond", "eqsolve_solve_noalloc", "eqsolve_set_step_form",
            "eqsimple_create", "eqsimple_form_momentum", "eqsimple_form_pressure", "eqsimple_correct",
            "eqsimple_iterate", "eqsimple_step", "eqsimple_set_pressure_preconditioner", "eqsimple_destroy")
 KERNEL_KINDS = {"setup": 0, "recheck": 1, "report": 2, "k1": 3, "k2": 4, "k3": 5, "cast": 6, "outer": 7,
@@ -73,7 +74,8 @@ class EqsInfo(ctypes.Structure):
 
     def as_dict(self):
         return {"status": self.status, "iters": self.iters, "outer": self.outer, "rel_res": self.rel_res,
-                "symmetric": bool(self.flags & EQS_INFO_SYMMETRIC), "sigma_restarts": self.sigma_restarts}
+                "symmetric": bool(self.flags & EQS_INFO_SYMMETRIC), "unscaled": bool(self.flags & EQS_INFO_UNSCALED),
+                "sigma_restarts": self.sigma_restarts}
 
 
 _lock = threading.Lock()
@@ -126,6 +128,8 @@ def load(path: str | None = None):
         L.eqsolve_solve_noalloc.argtypes = [ctypes.POINTER(EqsGrid), VPP, VP, VP, ctypes.c_double, ctypes.c_int32,
                                             ctypes.POINTER(EqsInfo), VP]
         L.eqsolve_solve_noalloc.restype = ctypes.c_int
+        L.eqsolve_set_step_form.argtypes = [VP, ctypes.c_int32]
+        L.eqsolve_set_step_form.restype = ctypes.c_int
         D3 = ctypes.POINTER(ctypes.c_double)
         L.eqsimple_create.argtypes = [ctypes.POINTER(VP), ctypes.POINTER(EqsBox), ctypes.c_int32, VP]
         L.eqsimple_form_momentum.argtypes = [VP, VPP, VP, VPP, VPP, VPP, VPP, D3]
@@ -223,6 +227,10 @@ def eqsolve_set_preconditioner(h, kind, params=None):
         prm = EqsMgParams(float(params.get("omega", 0.8)), float(params.get("gamma", 1.0)),
                           int(params.get("coarse_sweeps", 30)), int(params.get("coarse_cells", 512)))
     return load().eqsolve_set_preconditioner(h, int(kind), ctypes.byref(prm) if prm is not None else None)
+
+
+def eqsolve_set_step_form(h, form):
+    return load().eqsolve_set_step_form(h, int(form))
 
 
 def eqsolve_debug_precond(h, set_id, diag_ptrs, r_ptr, z_ptr):

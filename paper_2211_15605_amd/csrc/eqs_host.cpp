@@ -63,6 +63,7 @@ struct SetHost {
     int last_iters;
     int kc_jacobi;   // planes per chunk of the Jacobi iteration (tuned); 0 until first re-tiling
     bool form_sym;   // the last solve ran the symmetric form of the single-sync step
+    bool form_raw;   // the last solve ran the raw form of the single-sync step
     double last_log_rr;
 };
 
@@ -126,7 +127,11 @@ struct eqs_ctx {
     bool use_graphs = true;
     bool use_small = true;      // one-block persistent solve for tiny FP64 sets (EQS_SMALL=0 disables)
     hipStream_t capture_stream = nullptr;
-    std::map<std::tuple<int, int, bool, bool, bool>, std::array<hipGraphExec_t, 9>> graphs;
+    std::map<std::tuple<int, int, bool, bool, int>, std::array<hipGraphExec_t, 9>> graphs;
+    // the single-sync step's products of the FP64 forward solves: 0 from the coefficients of
+    // A D^-1 (a per-solve scale pass writes them), 1 from the caller's coefficients (no scale
+    // pass; eqsolve_set_step_form)
+    int step_form = 0;
     bool trace = false;         // print the state at every readback (EQS_TRACE=1)
     std::vector<hipEvent_t> ev_pool;
     std::vector<int> ev_kind;     // pending (start, stop) pairs: kind per pair
@@ -334,6 +339,8 @@ struct Run {
     int max_nx;
     bool fp32, trans;
     bool sym = false;   // every set exactly symmetric: the symmetric form of the single-sync step
+    bool raw = false;   // the raw form of the single-sync step (FP64 forward solves, asked for on the context)
+    int form() const { return raw ? 2 : (sym ? 1 : 0); }  // the step's form (kForm* of the kernels)
     long guard_limit;
 
     int L(Kern k, const double *x = nullptr, double *y = nullptr, int arg = 0, bool f32 = false) {
@@ -411,7 +418,7 @@ struct Run {
         if (c->profile_mask || !c->use_graphs) {
             for (int i = 0; i < C; ++i) {
                 if (c->sync1) {
-                    if ((rc = L(K_FUSED, nullptr, nullptr, sym ? 1 : 0, f32))) return rc;
+                    if ((rc = L(K_FUSED, nullptr, nullptr, form(), f32))) return rc;
                     continue;
                 }
                 if ((rc = L(K_K1, nullptr, nullptr, 0, f32))) return rc;
@@ -421,7 +428,7 @@ struct Run {
             return 0;
         }
         const int per_iter = c->sync1 ? 1 : 3;
-        auto &slots = c->graphs[std::make_tuple(first, count, trans, f32, sym && c->sync1)];
+        auto &slots = c->graphs[std::make_tuple(first, count, trans, f32, c->sync1 ? form() : 0)];
         for (int b = 8; b >= 0; --b) {
             while (C >= (1 << b)) {
                 if (!slots[b]) {
@@ -431,7 +438,7 @@ struct Run {
                     for (int i = 0; i < (1 << b) && ok; ++i) {
                         if (c->sync1) {
                             ok = launch_kernel(K_FUSED, ls, ntiles, nflat, c->cpt, max_nx, f32, trans,
-                                               c->capture_stream, nullptr, nullptr, sym ? 1 : 0) == hipSuccess;
+                                               c->capture_stream, nullptr, nullptr, form()) == hipSuccess;
                             continue;
                         }
                         for (Kern k : {K_K1, K_K2, K_K3})
@@ -466,9 +473,12 @@ struct Run {
     const SolveState &st(int i) const { return c->h_state[first + i]; }
     // after the setup's readback: the symmetric form when every set of the run takes it
     void pick_form() {
-        sym = count > 0 && c->sync1;
+        sym = !raw && count > 0 && c->sync1;
         for (int i = 0; i < count; ++i) sym = sym && st(i).sym != 0;
-        for (int i = 0; i < count; ++i) c->sets[first + i].form_sym = sym;
+        for (int i = 0; i < count; ++i) {
+            c->sets[first + i].form_sym = sym;
+            c->sets[first + i].form_raw = raw;
+        }
     }
     bool all_done() const {
         for (int i = 0; i < count; ++i)
@@ -543,10 +553,12 @@ int run_fp64(Run &R) {
         return R.readback();
     }
     const bool s1 = R.c->sync1;
+    // the raw form needs no per-solve coefficients: the setup pass writes 1/a_P
+    R.raw = s1 && !R.trans && R.c->step_form == EQS_STEP_UNSCALED;
     // coefficients of A D^-1 (A^T D^-1) and 1/a_P, once per solve; symmetry check
-    if ((rc = R.L(K_SCALE, nullptr, nullptr, R.c->sym_on))) return rc;
-    if ((rc = R.L(K_SETUP))) return rc;
-    if (s1 && (rc = R.L(K_FSETUP))) return rc;
+    if (!R.raw && (rc = R.L(K_SCALE, nullptr, nullptr, R.c->sym_on))) return rc;
+    if ((rc = R.L(K_SETUP, nullptr, nullptr, R.raw ? 1 : 0))) return rc;
+    if (s1 && (rc = R.L(K_FSETUP, nullptr, nullptr, R.raw ? 2 : 0))) return rc;
     if ((rc = R.readback())) return rc;
     R.pick_form();
     R.reset_rate();
@@ -560,7 +572,7 @@ int run_fp64(Run &R) {
             if ((rc = R.L(K_UNSCALE))) return rc;  // x = y / a_P
             if ((rc = R.L(K_RECHECK))) return rc;
             if ((rc = R.L(K_REPORT))) return rc;
-            if (s1 && (rc = R.L(K_FSETUP))) return rc;  // after a restart
+            if (s1 && (rc = R.L(K_FSETUP, nullptr, nullptr, R.raw ? 2 : 0))) return rc;  // after a restart
             if ((rc = R.readback())) return rc;
             R.reset_rate();
             continue;
@@ -618,7 +630,7 @@ Run make_run(eqs_ctx *c, int first, int count, bool trans) {
     for (int i = 0; i < count; ++i) R.max_nx = std::max(R.max_nx, c->sets[first + i].g.nx);
     R.fp32 = false;
     R.trans = trans;
-    for (int i = 0; i < count; ++i) c->sets[first + i].form_sym = false;
+    for (int i = 0; i < count; ++i) c->sets[first + i].form_sym = c->sets[first + i].form_raw = false;
     // every host loop turn either runs >= 1 iteration or one housekeeping
     // step that only follows an iteration, so 2*maxit + slack turns suffice
     long mx = 0;
@@ -633,7 +645,7 @@ void write_info(eqs_ctx *c, int s, eqs_info *info) {
     info->status = st.status;
     info->iters = st.iters;
     info->outer = (st.mode == MODE_REFINE || st.mode == MODE_FP32) ? st.outer : st.restarts;
-    info->flags = c->sets[s].form_sym ? EQS_INFO_SYMMETRIC : 0;
+    info->flags = (c->sets[s].form_sym ? EQS_INFO_SYMMETRIC : 0) | (c->sets[s].form_raw ? EQS_INFO_UNSCALED : 0);
     info->sigma_restarts = st.sig_restarts;
     info->reserved = 0;
     if (st.zero_rhs)
@@ -1110,6 +1122,7 @@ int eqsolve_create(eqs_ctx **out, const eqs_grid *grids, int32_t nsets, int32_t 
     c->use_small = env_int("EQS_SMALL", 1) != 0;
     c->nsets = nsets;
     c->precision = precision;
+    c->step_form = precision == EQS_FP64 && env_int("EQS_UNSCALED", 0) != 0 ? EQS_STEP_UNSCALED : EQS_STEP_SCALED;
     if (hipGetDevice(&c->device) != hipSuccess) { delete c; return EQS_ERR_HIP; }
     // the single-sync step may take the device's whole per-block LDS (160 KB on gfx950; the march
     // kernels stay within 64 KB); EQS_FUSED_LDS caps it for tests
@@ -1292,6 +1305,16 @@ int eqsolve_set_preconditioner(eqs_ctx *c, int32_t kind, const eqs_mg_params *pr
     retile_for_precond(c);
     clear_graphs(c);
     return upload_desc(c, 0, c->nsets);
+}
+
+int eqsolve_set_step_form(eqs_ctx *c, int32_t form) {
+    if (!c || c->broken) return EQS_ERR_STATE;
+    if ((form != EQS_STEP_SCALED && form != EQS_STEP_UNSCALED) || c->precision != EQS_FP64) return EQS_ERR_ARG;
+    if (form != c->step_form) {
+        c->step_form = form;
+        clear_graphs(c);
+    }
+    return EQS_OK;
 }
 
 int eqsolve_debug_precond(eqs_ctx *c, int32_t set, const double *const diag[7], const double *r, double *z,
@@ -1487,7 +1510,7 @@ int eqsolve_autotune(eqs_ctx *c, const char *cache_path, int32_t iters) {
     int rc = EQS_OK;
     for (int k = 0; k < 9 && rc == EQS_OK; ++k)
         if (launch_fill(tmp + k * nmax, (long)nmax, k == 0 ? 7.0 : 1.0, c->stream) != hipSuccess) rc = EQS_ERR_HIP;
-    const int kcs[] = {1, 2, 4, 8, 16, 32, 48};
+    const int kcs[] = {1, 2, 4, 8, 16, 32, 48, 64};
     const int flats[] = {256, 512, 1024, 2048, 4096};
     const int old_cpt = c->cpt, old_fnt = c->fnt;
     double best_total = 1e300;
@@ -1567,7 +1590,7 @@ int eqsolve_autotune(eqs_ctx *c, const char *cache_path, int32_t iters) {
         clear_graphs(c);
         double best_us = time_steps(c, 0, c->nsets, tmp, nmax, iters);
         if (best_us == -1.0) rc = EQS_ERR_HIP;
-        const int common[] = {8, 12, 16, 24, 32, 48};
+        const int common[] = {8, 12, 16, 24, 32, 48, 64, 96};
         for (int fnt : {256, 512}) {
             if (!(fused_shape_ok(best_cpt, c->max_nx, fnt) &&
                   fused_lds_bytes(best_cpt, c->max_nx, 8, fnt) <= c->fused_lds_cap))

@@ -901,9 +901,9 @@ struct PhRes {
     struct Pre { Coef6<double, TR> c; double ap, b; };
     const double *a[7];
     const double *x, *b;
-    double *r, *rh, *y;
+    double *r, *rh, *y, *dinv;
     int nx, P, ncell;
-    bool write;
+    bool write, wdinv;
     __device__ __forceinline__ Raw load(int idx, int, int) const { return Raw{ld(x, idx)}; }
     __device__ __forceinline__ double own(const Raw &w, int, Aux &) { return w.x; }
     __device__ __forceinline__ double halo(const Raw &w) const { return w.x; }
@@ -920,6 +920,7 @@ struct PhRes {
             st(r, idx, rv);
             st(rh, idx, rv);
             st(y, idx, pr.ap * xc);  // the scaled iterate y = D x that the iteration continues from
+            if (wdinv) st(dinv, idx, 1.0 / pr.ap);  // for the raw form of the single-sync step
         }
         acc[0] += pr.b * pr.b;
         acc[1] += rv * rv;
@@ -1008,6 +1009,35 @@ struct PhFSet {
     }
 };
 
+// f = M^T r^ from the caller's coefficients (the raw form of the single-sync step): row c of
+// M^T = D^-1 A^T is r^_c - (1/a_P)_c sum_nb a_{nb->c} r^_nb, the link from neighbour nb being row
+// nb's coefficient towards c
+struct PhFSetRaw {
+    static constexpr int NV = 2;
+    struct Raw { double x; };
+    struct Aux {};
+    struct Pre { Coef6<double, true> c; double g; };
+    const double *a[7];
+    const double *rh, *dinv;
+    double *f;
+    int nx, P, ncell;
+    __device__ __forceinline__ Raw load(int idx, int, int) const { return Raw{ld(rh, idx)}; }
+    __device__ __forceinline__ double own(const Raw &w, int, Aux &) { return w.x; }
+    __device__ __forceinline__ double halo(const Raw &w) const { return w.x; }
+    __device__ __forceinline__ void pre(int idx, Nb nb, bool up, bool dn, Pre &pr) const {
+        pr.c.load(a, idx, nx, P, ncell, nb, up, dn);
+        pr.g = ld(dinv, idx);
+    }
+    __device__ __forceinline__ void center(int idx, const Pre &pr, const Aux &, double xc, double xE, double xW,
+                                           double xN, double xS, double xT, double xB, double (&acc)[NV]) {
+        const double q = pr.c.apply(0.0, xc, xE, xW, xN, xS, xT, xB);  // -sum_nb a_{nb->c} r^_nb
+        const double fv = fma(pr.g, q, xc);
+        st(f, idx, fv);
+        acc[0] += fv * xc;
+        acc[1] += xc * xc;
+    }
+};
+
 // ------------------------------------------------------------------ march kernels
 
 template <typename T>
@@ -1060,7 +1090,7 @@ __global__ void __launch_bounds__(kBlock) k2_kernel(LaunchSets ls) {
 
 // mode: 0 setup, 1 recheck, 2 report
 template <int CPT, int H, bool TR>
-__global__ void __launch_bounds__(kBlock) res_kernel(LaunchSets ls, int mode) {
+__global__ void __launch_bounds__(kBlock) res_kernel(LaunchSets ls, int mode, int wdinv) {
     const TileRef tr = locate<false>(ls);
     const SetDesc &d = *tr.d;
     const SolveState *st_ = d.st;
@@ -1073,7 +1103,9 @@ __global__ void __launch_bounds__(kBlock) res_kernel(LaunchSets ls, int mode) {
     ph.r = d.r;
     ph.rh = d.rh;
     ph.y = d.y;
+    ph.dinv = d.dinv;
     ph.write = mode != 2;
+    ph.wdinv = wdinv != 0;
     ph.nx = d.nx;
     ph.P = d.plane;
     ph.ncell = d.n;
@@ -1142,6 +1174,25 @@ __global__ void __launch_bounds__(kBlock) fsetup_kernel(LaunchSets ls) {
     reduce_and_finalize<2>(d, tr.tile, d.ntiles, acc, FinFSetup{});
 }
 
+template <int CPT, int H>
+__global__ void __launch_bounds__(kBlock) fsetup_raw_kernel(LaunchSets ls) {
+    const TileRef tr = locate<false>(ls);
+    const SetDesc &d = *tr.d;
+    const SolveState *st_ = d.st;
+    if (st_->done || !st_->active || !st_->need_f) return;
+    PhFSetRaw ph;
+    for (int k = 0; k < 7; ++k) ph.a[k] = d.a[k];
+    ph.rh = d.rh;
+    ph.dinv = d.dinv;
+    ph.f = d.f;
+    ph.nx = d.nx;
+    ph.P = d.plane;
+    ph.ncell = d.n;
+    double acc[2] = {0.0, 0.0};
+    march<double, CPT, H>(ph, geo_of(d), tr.tile, lds_base<double>(), acc);
+    reduce_and_finalize<2>(d, tr.tile, d.ntiles, acc, FinFSetup{});
+}
+
 // ------------------------------------------------------------------ single-sync iteration
 //
 // One launch per BiCGSTAB step j on the scaled operator M = A D^-1.  From
@@ -1174,6 +1225,9 @@ __global__ void __launch_bounds__(kBlock) fsetup_kernel(LaunchSets ls) {
 // CPT cells of the segment and H cells of each of two halo rings: the inner
 // ring (the nx cells next to the segment on each side: v and s needed there)
 // and the outer ring (p only).
+// how the single-sync step forms its products (see fused_step)
+constexpr int kFormScaled = 0, kFormSym = 1, kFormRaw = 2;
+
 // x where c holds, else +0, as a bitwise mask: a use of x that does not depend on
 // c, so the compiler cannot move x's loads under a per-lane branch (whose join
 // would wait for every load in flight), and a NaN or Inf in x never leaks out
@@ -1184,12 +1238,20 @@ __device__ __forceinline__ float keep_if(bool c, float x) {
     return __int_as_float(__float_as_int(x) & (c ? ~0 : 0));
 }
 
-// SYM: the symmetric form.  The planes in LDS then hold p D^-1 and s D^-1 (each value
-// times 1/a_P of its cell), the products take a_E, a_N, a_T and the neighbours' a_E,
-// a_N, a_T for the W, S, B links, (A D^-1 p)_c = p_c - sum_nb a_nb(c) (p/a_P)_nb, and
-// the own cells' p and s come from registers: 4 coefficient words per cell instead of 6.
-template <typename T, int CPT, int H, bool SYM, int NT>
+// FORM (kFormScaled, kFormSym, kFormRaw) is how the step forms the products of M = A D^-1:
+//  - scaled: from the six coefficients of M written by the per-solve scale pass, p in LDS;
+//  - symmetric: the planes in LDS hold p D^-1 and s D^-1 (each value times 1/a_P of its
+//    cell), the products take a_E, a_N, a_T and the neighbours' a_E, a_N, a_T for the W, S, B
+//    links, (A D^-1 p)_c = p_c - sum_nb a_nb(c) (p/a_P)_nb, and the own cells' p and s come
+//    from registers: 4 coefficient words per cell instead of 6;
+//  - raw (FP64): the same with the caller's six coefficients of the row itself, so no scale
+//    pass is needed (1/a_P comes from the setup pass): 7 coefficient words per cell instead of 6,
+//    for solves of a few steps, where the per-solve pass costs more than the extra word.
+template <typename T, int CPT, int H, int FORM, int NT>
 __device__ __forceinline__ void fused_step(const TileRef &tr) {
+    constexpr bool SYM = FORM == kFormSym, RAW = FORM == kFormRaw;
+    constexpr bool PD = SYM || RAW;  // LDS planes hold p D^-1 and s D^-1
+    static_assert(!RAW || sizeof(T) == 8, "the raw form runs in FP64");
     constexpr int Q = NT * CPT;
     const SetDesc &d = *tr.d;
     const SolveState *st_ = d.st;
@@ -1197,7 +1259,7 @@ __device__ __forceinline__ void fused_step(const TileRef &tr) {
     const bool fresh = st_->fresh != 0;
     const T al = (T)st_->alpha, ap = (T)st_->alpha_prev, om = (T)st_->omega, be = (T)st_->beta;
     const T *as[6];
-    for (int k = 0; k < 6; ++k) as[k] = Vecs<T>::as(d)[k];
+    for (int k = 0; k < 6; ++k) as[k] = RAW ? (const T *)d.a[k + 1] : Vecs<T>::as(d)[k];
     const T *aE = Vecs<T>::sy(d, 0), *aN = Vecs<T>::sy(d, 1), *aT = Vecs<T>::sy(d, 2), *gv = Vecs<T>::sy(d, 3);
     const T *sI = Vecs<T>::s(d, in), *tI = Vecs<T>::t(d, in), *pI = Vecs<T>::p(d, in), *vI = Vecs<T>::v(d, in);
     T *sO = Vecs<T>::s(d, out), *tO = Vecs<T>::t(d, out), *pO = Vecs<T>::p(d, out), *vO = Vecs<T>::v(d, out);
@@ -1299,7 +1361,7 @@ __device__ __forceinline__ void fused_step(const TileRef &tr) {
     // step ahead too with one halo slot per ring, except in the FP64 symmetric form, which has
     // no registers to spare (FP64 with two slots: 251 VGPRs with the own cells' loads a step
     // ahead, past 256 with the rings' as well)
-    constexpr bool PFR = (sizeof(T) == 4 || H == 1) && !(SYM && sizeof(T) == 8);
+    constexpr bool PFR = (sizeof(T) == 4 || H == 1) && !(PD && sizeof(T) == 8);
     struct VecLoads {
         T s[CPT], t[CPT], p[CPT], v[CPT], y[CPT], f[CPT], g[CPT];
         T si[H], ti[H], pi[H], vi[H], gi[H], sr[H], tr[H], pr[H], vr[H], gr[H];
@@ -1314,7 +1376,7 @@ __device__ __forceinline__ void fused_step(const TileRef &tr) {
             L.s[m] = ld(sI, i); L.t[m] = ld(tI, i); L.p[m] = ld(pI, i); L.v[m] = ld(vI, i);
             L.y[m] = ld(yv, qo[m] + kyb);
             L.f[m] = ld(fv, qo[m] + kyb);
-            L.g[m] = SYM ? ld(gv, i) : T(0);
+            L.g[m] = PD ? ld(gv, i) : T(0);
         }
     };
     auto load_rings = [&](int it, VecLoads &L) {
@@ -1325,8 +1387,8 @@ __device__ __forceinline__ void fused_step(const TileRef &tr) {
             const int i = qi[h] + kpb, r = qr[h] + kpb;
             L.si[h] = ld(sI, i); L.ti[h] = ld(tI, i); L.pi[h] = ld(pI, i); L.vi[h] = ld(vI, i);
             L.sr[h] = ld(sI, r); L.tr[h] = ld(tI, r); L.pr[h] = ld(pI, r); L.vr[h] = ld(vI, r);
-            L.gi[h] = SYM ? ld(gv, i) : T(0);
-            L.gr[h] = SYM ? ld(gv, r) : T(0);
+            L.gi[h] = PD ? ld(gv, i) : T(0);
+            L.gr[h] = PD ? ld(gv, r) : T(0);
         }
     };
     VecLoads nextv;
@@ -1395,7 +1457,7 @@ __device__ __forceinline__ void fused_step(const TileRef &tr) {
             const bool ok = pin && oko[m];
             const T r = keep_if(ok, fma(-omf, keep_if(cont, cv.t[m]), cv.s[m]));
             const T pv = keep_if(ok, fma(bef, keep_if(cont, fma(-om, cv.v[m], cv.p[m])), r));
-            pw[eo[m]] = SYM ? keep_if(ok, pv * cv.g[m]) : pv;
+            pw[eo[m]] = PD ? keep_if(ok, pv * cv.g[m]) : pv;
             pAo[m] = pv;
             rAo[m] = r;
             const bool own = pown && oko[m];
@@ -1416,11 +1478,11 @@ __device__ __forceinline__ void fused_step(const TileRef &tr) {
             const T pv = keep_if(ok, fma(bef, keep_if(cont, fma(-om, cv.vi[h], cv.pi[h])), r));
             rAi[h] = r;
             pAi[h] = pv;
-            (ei[h] >= 0 ? pw[ei[h]] : pad[tid]) = SYM ? keep_if(ok, pv * cv.gi[h]) : pv;
+            (ei[h] >= 0 ? pw[ei[h]] : pad[tid]) = PD ? keep_if(ok, pv * cv.gi[h]) : pv;
             const bool ok2 = pin && okr[h];
             const T r2 = keep_if(ok2, fma(-omf, keep_if(cont, cv.tr[h]), cv.sr[h]));
             const T pv2 = keep_if(ok2, fma(bef, keep_if(cont, fma(-om, cv.vr[h], cv.pr[h])), r2));
-            (er[h] >= 0 ? pw[er[h]] : pad[tid]) = SYM ? keep_if(ok2, pv2 * cv.gr[h]) : pv2;
+            (er[h] >= 0 ? pw[er[h]] : pad[tid]) = PD ? keep_if(ok2, pv2 * cv.gr[h]) : pv2;
         }
         __syncthreads();
         if (PF) load_own(it + 1, nextv);  // in flight while the products below are formed
@@ -1437,11 +1499,11 @@ __device__ __forceinline__ void fused_step(const TileRef &tr) {
 #pragma unroll
             for (int m = 0; m < CPT; ++m) {
                 const int e = eo[m];
-                const T xc = SYM ? pBo[m] : pc[e];
+                const T xc = PD ? pBo[m] : pc[e];
                 const T v = cN[m].apply(xc, pc[e + 1], pc[e - 1], pc[e + nx], pc[e - nx], pu[e], pd[e]);
                 const bool ok = vin && oko[m];
                 const T sv = keep_if(ok, fma(-al, v, rBo[m]));
-                sw[e] = SYM ? keep_if(ok, sv * gBo[m]) : sv;
+                sw[e] = PD ? keep_if(ok, sv * gBo[m]) : sv;
                 sNo[m] = sv;
                 const bool own = vown && oko[m];
                 if (own) {
@@ -1459,11 +1521,11 @@ __device__ __forceinline__ void fused_step(const TileRef &tr) {
 #pragma unroll
             for (int h = 0; h < H; ++h) {
                 const int e = ei[h] >= 0 ? ei[h] : 2 * nx;  // an unused slot reads a valid cell, writes its pad
-                const T xc = SYM ? pBi[h] : pc[e];
+                const T xc = PD ? pBi[h] : pc[e];
                 const T v = cI[h].apply(xc, pc[e + 1], pc[e - 1], pc[e + nx], pc[e - nx], pu[e], pd[e]);
                 const bool ok = vin && oki[h];
                 const T sv = keep_if(ok, fma(-al, v, rBi[h]));
-                (ei[h] >= 0 ? sw[e] : pad[tid]) = SYM ? keep_if(ok, sv * gBi[h]) : sv;
+                (ei[h] >= 0 ? sw[e] : pad[tid]) = PD ? keep_if(ok, sv * gBi[h]) : sv;
             }
         }
         __syncthreads();
@@ -1475,7 +1537,7 @@ __device__ __forceinline__ void fused_step(const TileRef &tr) {
 #pragma unroll
             for (int m = 0; m < CPT; ++m) {
                 const int e = eo[m];
-                const T s0 = SYM ? sCo[m] : sc[e];
+                const T s0 = PD ? sCo[m] : sc[e];
                 const T t = cC[m].apply(s0, sc[e + 1], sc[e - 1], sc[e + nx], sc[e - nx], su[e], sd[e]);
                 if (oko[m]) st_nt(tO, qo[m] + kt * P, t);
                 const T tk = keep_if(oko[m], t);
@@ -1512,14 +1574,14 @@ __device__ __forceinline__ void fused_step(const TileRef &tr) {
     reduce_and_finalize<11, FinFused, NT>(d, tr.tile, d.fntiles, acc, FinFused{d.sigma_tol[sizeof(T) == 4 ? 1 : 0]});
 }
 
-// SYM is chosen on the host, for a launch whose sets are all exactly symmetric; NT (256 or 512
-// threads) by the launch shape
-template <typename T, int CPT, int H, bool SYM, int NT>
+// FORM is chosen on the host (symmetric: every set of the launch exactly symmetric; raw: asked
+// for on the context); NT (256 or 512 threads) by the launch shape
+template <typename T, int CPT, int H, int FORM, int NT>
 __global__ void __launch_bounds__(NT) fused_kernel(LaunchSets ls) {
     const TileRef tr = locate_fused(ls);
     const SolveState *st_ = tr.d->st;
     if (!st_->active || st_->need_f) return;
-    fused_step<T, CPT, H, SYM, NT>(tr);
+    fused_step<T, CPT, H, FORM, NT>(tr);
 }
 
 // ------------------------------------------------------------------ pointwise kernels
@@ -2719,10 +2781,11 @@ hipError_t allow_fused_lds(size_t bytes) {
     };
     auto all_forms = [&](int cpt, int h, int nt) {
         EQS_DISPATCH_FUSED(cpt, h, nt, {
-            allow((const void *)fused_kernel<double, C, HH, false, NTT>);
-            allow((const void *)fused_kernel<double, C, HH, true, NTT>);
-            allow((const void *)fused_kernel<float, C, HH, false, NTT>);
-            allow((const void *)fused_kernel<float, C, HH, true, NTT>);
+            allow((const void *)fused_kernel<double, C, HH, kFormScaled, NTT>);
+            allow((const void *)fused_kernel<double, C, HH, kFormSym, NTT>);
+            allow((const void *)fused_kernel<double, C, HH, kFormRaw, NTT>);
+            allow((const void *)fused_kernel<float, C, HH, kFormScaled, NTT>);
+            allow((const void *)fused_kernel<float, C, HH, kFormSym, NTT>);
         });
     };
     for (int cpt = 1; cpt <= 2; ++cpt) {
@@ -2810,8 +2873,9 @@ hipError_t launch_kernel(Kern k, const LaunchSets &ls, int ntiles, int nflat, in
     case K_RECHECK:
     case K_REPORT: {
         const int mode = k == K_SETUP ? 0 : (k == K_RECHECK ? 1 : 2);
-        if (trans) EQS_DISPATCH(cpt, h, EQS_LAUNCH((res_kernel<C, HH, true>), grid, block, lds64, ls, mode));
-        else EQS_DISPATCH(cpt, h, EQS_LAUNCH((res_kernel<C, HH, false>), grid, block, lds64, ls, mode));
+        const int wd = k == K_SETUP && arg == 1;  // the setup writes 1/a_P for the raw form
+        if (trans) EQS_DISPATCH(cpt, h, EQS_LAUNCH((res_kernel<C, HH, true>), grid, block, lds64, ls, mode, wd));
+        else EQS_DISPATCH(cpt, h, EQS_LAUNCH((res_kernel<C, HH, false>), grid, block, lds64, ls, mode, wd));
         break;
     }
     case K_OUTER:
@@ -2833,22 +2897,26 @@ hipError_t launch_kernel(Kern k, const LaunchSets &ls, int ntiles, int nflat, in
         if (trans) EQS_DISPATCH(cpt, h, EQS_LAUNCH((apply_kernel<C, HH, true>), grid, block, lds64, ls, x, y));
         else EQS_DISPATCH(cpt, h, EQS_LAUNCH((apply_kernel<C, HH, false>), grid, block, lds64, ls, x, y));
         break;
-    case K_FUSED: {  // the scaled operator needs no transpose variant; arg: symmetric form
+    case K_FUSED: {  // the scaled operator needs no transpose variant; arg: the form (kForm*)
         const int nt = ls.fnt, fh = halo_slots(max_nx, nt);
-        if (!fused_shape_ok(cpt, max_nx, nt)) return hipErrorInvalidValue;
+        if (!fused_shape_ok(cpt, max_nx, nt) || arg < kFormScaled || arg > kFormRaw || (fp32 && arg == kFormRaw))
+            return hipErrorInvalidValue;
         const dim3 fg(ls.ftile_begin[ls.nsets]), fb(nt);
         const size_t fl = fused_lds_bytes(cpt, max_nx, fp32 ? 4 : 8, nt);
-        if (arg) {  // every set of the launch exactly symmetric
-            if (fp32) EQS_DISPATCH_FUSED(cpt, fh, nt, EQS_LAUNCH((fused_kernel<float, C, HH, true, NTT>), fg, fb, fl, ls));
-            else EQS_DISPATCH_FUSED(cpt, fh, nt, EQS_LAUNCH((fused_kernel<double, C, HH, true, NTT>), fg, fb, fl, ls));
+        if (arg == kFormSym) {  // every set of the launch exactly symmetric
+            if (fp32) EQS_DISPATCH_FUSED(cpt, fh, nt, EQS_LAUNCH((fused_kernel<float, C, HH, kFormSym, NTT>), fg, fb, fl, ls));
+            else EQS_DISPATCH_FUSED(cpt, fh, nt, EQS_LAUNCH((fused_kernel<double, C, HH, kFormSym, NTT>), fg, fb, fl, ls));
+        } else if (arg == kFormRaw) {
+            EQS_DISPATCH_FUSED(cpt, fh, nt, EQS_LAUNCH((fused_kernel<double, C, HH, kFormRaw, NTT>), fg, fb, fl, ls));
         } else {
-            if (fp32) EQS_DISPATCH_FUSED(cpt, fh, nt, EQS_LAUNCH((fused_kernel<float, C, HH, false, NTT>), fg, fb, fl, ls));
-            else EQS_DISPATCH_FUSED(cpt, fh, nt, EQS_LAUNCH((fused_kernel<double, C, HH, false, NTT>), fg, fb, fl, ls));
+            if (fp32) EQS_DISPATCH_FUSED(cpt, fh, nt, EQS_LAUNCH((fused_kernel<float, C, HH, kFormScaled, NTT>), fg, fb, fl, ls));
+            else EQS_DISPATCH_FUSED(cpt, fh, nt, EQS_LAUNCH((fused_kernel<double, C, HH, kFormScaled, NTT>), fg, fb, fl, ls));
         }
         break;
     }
-    case K_FSETUP:
+    case K_FSETUP:  // arg: the form of the step that follows (kFormRaw: from the caller's coefficients)
         if (fp32) EQS_DISPATCH(cpt, h, EQS_LAUNCH((fsetup_kernel<float, C, HH>), grid, block, lds32, ls));
+        else if (arg == kFormRaw) EQS_DISPATCH(cpt, h, EQS_LAUNCH((fsetup_raw_kernel<C, HH>), grid, block, lds64, ls));
         else EQS_DISPATCH(cpt, h, EQS_LAUNCH((fsetup_kernel<double, C, HH>), grid, block, lds64, ls));
         break;
     case K_MAT:

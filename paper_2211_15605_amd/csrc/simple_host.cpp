@@ -12,6 +12,7 @@
 // formation and solve on the device, one call per time step).
 
 #include <hip/hip_runtime_api.h>
+#include <stdlib.h>
 
 #include <math.h>
 #include <stdint.h>
@@ -283,6 +284,13 @@ int eqsimple_create(eqsimple_ctx **out, const eqs_box *box, int32_t precision, v
     const eqs_grid pg = {box->nx, box->ny, box->nz};
     int rc = eqsolve_create(&c->mom, mg, 3, precision, hip_stream);
     if (rc == EQS_OK) rc = eqsolve_create(&c->prs, &pg, 1, EQS_FP64, hip_stream);
+    // The momentum rows converge in a step or two (their transient term dominates), so their FP64
+    // solves skip the per-solve scale pass and read the formed coefficients directly
+    // (EQS_SIMPLE_SCALED_MOM=1 keeps the scaled form, for comparison).
+    if (rc == EQS_OK && precision == EQS_FP64) {
+        const char *e = getenv("EQS_SIMPLE_SCALED_MOM");
+        rc = eqsolve_set_step_form(c->mom, e && atoi(e) != 0 ? EQS_STEP_SCALED : EQS_STEP_UNSCALED);
+    }
     if (rc != EQS_OK) {
         eqsolve_destroy(c->mom);
         eqsolve_destroy(c->prs);

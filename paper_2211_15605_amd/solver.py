@@ -108,6 +108,17 @@ class Context:
         if rc != 0:
             raise EqSolveError(rc, "eqsolve_set_preconditioner")
 
+    def set_step_form(self, form="scaled"):
+        """'scaled' (default: a per-solve pass writes the coefficients of A D^-1) or 'unscaled' (each
+        step reads the caller's coefficients and 1/a_P; for solves of a few steps).  FP64 contexts;
+        see eqsolve_set_step_form."""
+        k = {"scaled": B.EQS_STEP_SCALED, "unscaled": B.EQS_STEP_UNSCALED}.get(form)
+        if k is None:
+            raise ValueError("form must be 'scaled' or 'unscaled'")
+        rc = B.eqsolve_set_step_form(self.h, k)
+        if rc != 0:
+            raise EqSolveError(rc, "eqsolve_set_step_form")
+
     def precond_apply(self, diags, r, set_id=0, out=None):
         """z = B^-1 r, one V-cycle of the multigrid preconditioner (diagnostics); returns (z, levels)."""
         import torch

@@ -46,10 +46,11 @@ def test_traffic_records_are_used_only_with_the_kernel_code_they_were_taken_with
 def test_kernel_code_is_found_per_kernel_in_the_built_library():
     code = bench.kernel_code()
     fused = [k for k in code if "12fused_kernel" in k]
-    # FP64/FP32 x general/symmetric x 2 cells per thread x (256 threads: 3 halo slots; 512: 2)
-    assert len(fused) == 2 * 2 * 2 * (3 + 2), sorted(fused)
+    # (FP64: scaled, symmetric, raw forms; FP32: scaled, symmetric) x 2 cells per thread x
+    # (256 threads: 3 halo slot counts; 512: 2)
+    assert len(fused) == (3 + 2) * 2 * (3 + 2), sorted(fused)
     assert all(len(code[k]) > 1000 for k in fused)
-    sym = bench.mangled_kernel_name("void eqs::fused_kernel<double, 2, 1, false, 512>(eqs::LaunchSets)")
+    sym = bench.mangled_kernel_name("void eqs::fused_kernel<double, 2, 1, 0, 512>(eqs::LaunchSets)")
     assert sym in code and bench.kernel_code_digest(sym) == bench.kernel_code_digest(sym)
 
 

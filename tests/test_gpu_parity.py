@@ -68,8 +68,8 @@ TILINGS = [dict(EQS_SMALL=0), dict(EQS_SMALL=0, EQS_CPT=1, EQS_KC=1), dict(EQS_S
            dict(EQS_SMALL=0, EQS_CPT=2, EQS_KC=7)]
 # solve paths: the one-block persistent solve (sets of at most 2048 cells, by default), the
 # single-sync march iteration (one launch per step) and the three-launch iteration
-PATHS = [dict(), dict(EQS_SMALL=0), dict(EQS_SMALL=0, EQS_SYNC=3)]
-PATH_IDS = ["small", "sync1", "sync3"]
+PATHS = [dict(), dict(EQS_SMALL=0), dict(EQS_SMALL=0, EQS_SYNC=3), dict(EQS_SMALL=0, EQS_UNSCALED=1)]
+PATH_IDS = ["small", "sync1", "sync3", "sync1_unscaled"]
 # the two march iterations on sets above the one-block size
 SCHEMES = [dict(), dict(EQS_SYNC=3)]
 SCHEME_IDS = ["sync1", "sync3"]
@@ -900,3 +900,58 @@ def test_fused_launch_shapes_are_taken(torch_dev, orc):
     assert lay["fnt512"]["fused_threads"] == 512 and lay["fnt512"]["fused_segments"] == (96 * 40 + 1023) // 1024
     assert lay["fnt512"]["fused_tiles"] == lay["fnt512"]["fused_segments"] * lay["fnt512"]["chunks"]
     assert lay["ford1"]["fused_order"] == 1
+
+
+# ---------------------------------------------------------------- unscaled form of the step
+
+@pytest.mark.parametrize("cfg,shape", [(0, (16, 16, 16)), (0, (33, 17, 9)), (2, (97, 31, 5)), (0, (200, 7, 3)),
+                                       (1, (37, 23, 19)), (0, (1, 300, 2))])
+def test_unscaled_form_matches_oracle(torch_dev, orc, cfg, shape):
+    # the single-sync step from the caller's coefficients and 1/a_P (no scale pass), in several
+    # launch shapes, against the oracle's solution; a symmetric system runs it too (the symmetric
+    # form is not used: its check belongs to the scale pass)
+    torch, dev = torch_dev
+    g, diags, b, xs = manufactured(orc, cfg, grid=W.Grid(*shape))
+    xo, oinfo = orc.bicgstab(g.shape, diags, b, tol=1e-13, maxit=20000)
+    assert oinfo["status"] == 0
+    for env in (dict(EQS_SMALL=0), dict(EQS_SMALL=0, EQS_FNT=512), dict(EQS_SMALL=0, EQS_FORD=1, EQS_KC=3)):
+        ctx = context([g.shape], env=env)
+        ctx.set_step_form("unscaled")
+        x, info = ctx.solve(dev_arrays(torch, dev, diags), dev_arrays(torch, dev, [b])[0], tol=1e-13, maxit=20000)
+        ctx.close()
+        xg = host(x)
+        assert info["status"] == 0 and info["unscaled"] and not info["symmetric"], (env, info)
+        assert orc.rel_residual(g.shape, diags, b, xg) <= 1e-13
+        if cfg != 1:
+            assert np.linalg.norm(xg - xo) <= 1e-10 * np.linalg.norm(xo), env
+        else:   # near-singular: bounded by the certificates of both solutions
+            cert = orc.forward_error_certificate(g.shape, diags, b, xg)
+            assert np.max(np.abs(xg - xo)) <= 2 * cert + orc.forward_error_certificate(g.shape, diags, b, xo)
+
+
+def test_unscaled_form_batched_equals_sequential_and_graphs(torch_dev, orc):
+    torch, dev = torch_dev
+    systems = [manufactured(orc, 2, grid=W.Grid(*s), set_id=i) for i, s in enumerate(STAGGERED_SMALL)]
+    Ds = [dev_arrays(torch, dev, s[1]) for s in systems]
+    bs = [dev_arrays(torch, dev, [s[2]])[0] for s in systems]
+    out = []
+    for env in (dict(), dict(EQS_GRAPHS=0)):
+        ctx = context(STAGGERED_SMALL, env=env)
+        ctx.set_step_form("unscaled")
+        xb, infos = ctx.solve_batched(Ds, bs, tol=1e-10, maxit=2000)
+        for i, s in enumerate(systems):
+            xi, info = ctx.solve(Ds[i], bs[i], tol=1e-10, maxit=2000, set_id=i)
+            assert np.array_equal(host(xi), host(xb[i])), i
+            assert info == infos[i] and info["unscaled"]
+            assert orc.rel_residual(s[0].shape, s[1], s[2], host(xb[i])) <= 1e-10
+        out.append([host(x) for x in xb])
+        ctx.close()
+    assert all(np.array_equal(a, b) for a, b in zip(out[0], out[1]))   # graph replay == eager
+
+
+def test_step_form_is_for_fp64_contexts(torch_dev):
+    from paper_2211_15605_amd.solver import EqSolveError
+    ctx = context([(8, 8, 8)], precision="fp32_refine")
+    with pytest.raises(EqSolveError):
+        ctx.set_step_form("unscaled")
+    ctx.close()
