@@ -817,7 +817,7 @@ def main():
                     help="after the timed steps, copy 1 GiB three times (reference for HBM byte counters)")
     ap.add_argument("--reduce-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write a traffic record from two rocprofv3 --pmc runs (no GPU needed)")
-    ap.add_argument("--pmc-kernel", default="fused_kernel<double, 2, 2, false>")
+    ap.add_argument("--pmc-kernel", default="fused_kernel<double, 2, 1, 0, 512>")
     ap.add_argument("--pmc-grid", type=int, default=0, help="work-items of the kernel's launch")
     ap.add_argument("--pmc-words", type=int, default=18)
     ap.add_argument("--pmc-cells", type=int, default=0)

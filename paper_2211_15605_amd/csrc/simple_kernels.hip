@@ -33,6 +33,13 @@ __device__ __forceinline__ int logical_block(int total) {
 
 __device__ __forceinline__ double pos(double x) { return fmax(x, 0.0); }
 
+// Store that marks its line for early eviction: the rows a stage writes are read by the next
+// launch, not by this one, and left in L2 they evict the fields whose neighbouring planes the
+// stage is about to read again.
+__device__ __forceinline__ void st_nt(double *p, int i, double v) {
+    __builtin_nontemporal_store(v, (__attribute__((address_space(1))) double *)p + i);
+}
+
 // sum of v over the block, valid in thread 0
 __device__ double block_sum(double v) {
     __shared__ double part[kThreads / 64];
@@ -235,9 +242,9 @@ __global__ void __launch_bounds__(kThreads) form_momentum_kernel(MomArgs A) {
         else if (comp == 1) form_v(A, g, X, i, j, k, r);
         else form_w(A, g, X, i, j, k, r);
 #pragma unroll
-        for (int s = 0; s < 7; ++s) A.a[comp][s][c] = r.a[s];
-        A.b[comp][c] = r.b;
-        A.d[comp][c] = r.d;
+        for (int s = 0; s < 7; ++s) st_nt(A.a[comp][s], c, r.a[s]);
+        st_nt(A.b[comp], c, r.b);
+        st_nt(A.d[comp], c, r.d);
         // row residual at the incoming iterate x (neighbours outside the grid carry no term)
         const double *x = comp == 0 ? A.u : (comp == 1 ? A.v : A.w);
         const int PL = NX * NY;
@@ -280,14 +287,14 @@ __global__ void __launch_bounds__(kThreads) form_pressure_kernel(PresArgs A, int
         const double b = rh * ((A.u[X.u(i, j, k)] - A.u[X.u(i + 1, j, k)]) * g.Ax +
                                (A.v[X.v(i, j, k)] - A.v[X.v(i, j + 1, k)]) * g.Ay +
                                (A.w[X.w(i, j, k)] - A.w[X.w(i, j, k + 1)]) * g.Az);
-        A.a[0][c] = aP;
-        A.a[1][c] = aE;
-        A.a[2][c] = aW;
-        A.a[3][c] = aN;
-        A.a[4][c] = aS;
-        A.a[5][c] = aT;
-        A.a[6][c] = aB;
-        A.b[c] = b;
+        st_nt(A.a[0], c, aP);
+        st_nt(A.a[1], c, aE);
+        st_nt(A.a[2], c, aW);
+        st_nt(A.a[3], c, aN);
+        st_nt(A.a[4], c, aS);
+        st_nt(A.a[5], c, aT);
+        st_nt(A.a[6], c, aB);
+        st_nt(A.b, c, b);
         b2 += b * b;
     }
     const double s = block_sum(b2);
@@ -309,17 +316,17 @@ __global__ void __launch_bounds__(kThreads) correct_kernel(CorrArgs A) {
     const Idx X{nx, ny, nz};
     const double *pp = A.pp;
     if (comp == 0) {
-        if (i >= 1 && i <= nx - 1) A.u[c] = A.u[c] + A.du[c] * (pp[X.p(i - 1, j, k)] - pp[X.p(i, j, k)]);
+        if (i >= 1 && i <= nx - 1) st_nt(A.u, c, A.u[c] + A.du[c] * (pp[X.p(i - 1, j, k)] - pp[X.p(i, j, k)]));
     } else if (comp == 1) {
         if (j >= 1) {
             const double pa = pp[X.p(i, j < ny ? j : ny - 1, k)];
             const double above = j < ny ? pa : 0.0;
-            A.v[c] = A.v[c] + A.dv[c] * (pp[X.p(i, j - 1, k)] - above);
+            st_nt(A.v, c, A.v[c] + A.dv[c] * (pp[X.p(i, j - 1, k)] - above));
         }
     } else if (comp == 2) {
-        if (k >= 1 && k <= nz - 1) A.w[c] = A.w[c] + A.dw[c] * (pp[X.p(i, j, k - 1)] - pp[X.p(i, j, k)]);
+        if (k >= 1 && k <= nz - 1) st_nt(A.w, c, A.w[c] + A.dw[c] * (pp[X.p(i, j, k - 1)] - pp[X.p(i, j, k)]));
     } else {
-        A.p[c] = A.p[c] + bx.alpha_p * pp[c];
+        st_nt(A.p, c, A.p[c] + bx.alpha_p * pp[c]);
     }
 }
 
