@@ -77,9 +77,12 @@ typedef struct {
     int32_t flags;   /* EQS_INFO_* bits describing how the solve ran */
     double rel_res;  /* ||b - A x||_2 / ||b||_2 of the returned x, in FP64 */
     int32_t sigma_restarts; /* fresh starts the single-sync iteration took when its expanded (r^, M p)
-                               parted from the directly summed one (all inner solves of the FP32 forms;
-                               at most 32 per BiCGSTAB solve, then that solve reports breakdown) */
-    int32_t reserved;
+                               parted from the directly summed one (all inner solves of the FP32 forms).
+                               FP64: at most 32 a solve, then the check is off for the rest of it; an
+                               FP32 inner solve: at most 32, then it ends and the refinement decides */
+    int32_t sigma_reruns;   /* with EQS_SIGMA_REDO=1 at eqsolve_create, such steps run a second time
+                               with alpha from the directly summed value instead of restarting (a rerun
+                               reads the same inputs and is not counted in iters) */
 } eqs_info;
 
 /*

@@ -70,12 +70,12 @@ class EqsSimpleInfo(ctypes.Structure):
 class EqsInfo(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("outer", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("rel_res", ctypes.c_double), ("sigma_restarts", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("sigma_reruns", ctypes.c_int32)]
 
     def as_dict(self):
         return {"status": self.status, "iters": self.iters, "outer": self.outer, "rel_res": self.rel_res,
                 "symmetric": bool(self.flags & EQS_INFO_SYMMETRIC), "unscaled": bool(self.flags & EQS_INFO_UNSCALED),
-                "sigma_restarts": self.sigma_restarts}
+                "sigma_restarts": self.sigma_restarts, "sigma_reruns": self.sigma_reruns}
 
 
 _lock = threading.Lock()

@@ -304,6 +304,7 @@ void fill_desc(eqs_ctx *c, int s) {
     d.st = c->d_state + s;
     d.sigma_tol[0] = sigma_tol(false);
     d.sigma_tol[1] = sigma_tol(true);
+    d.sig_redo = env_int("EQS_SIGMA_REDO", 0) != 0 ? 1 : 0;
 }
 
 LaunchSets launch_table(eqs_ctx *c, int first, int count, int *total, int *total_flat) {
@@ -647,7 +648,7 @@ void write_info(eqs_ctx *c, int s, eqs_info *info) {
     info->outer = (st.mode == MODE_REFINE || st.mode == MODE_FP32) ? st.outer : st.restarts;
     info->flags = (c->sets[s].form_sym ? EQS_INFO_SYMMETRIC : 0) | (c->sets[s].form_raw ? EQS_INFO_UNSCALED : 0);
     info->sigma_restarts = st.sig_restarts;
-    info->reserved = 0;
+    info->sigma_reruns = st.sig_redos;
     if (st.zero_rhs)
         info->rel_res = 0.0;
     else if (st.bb_outer > 0)
@@ -765,12 +766,20 @@ hipError_t mg_vcycle(const Run &R, const double *r, double *z, bool gated, hipSt
         e = launch_mg_fine(R.ls, R.ntiles, c->cpt, R.max_nx, lev, r, res, nullptr, c->mgp, gated, stream);
         if (e == hipSuccess) e = launch_mg_aggregate(dd, lev, L[1].n, res, gated, stream);
     }
-    for (int l = 1; l + 1 < nl && e == hipSuccess; ++l)
+    // with EQS_MG_BOTTOM=1 the last coarse level above the coarsest, when small, restricts, sweeps
+    // the coarsest level and prolongs in one launch instead of three (one block: slower on the
+    // benchmark hierarchies, where that level has 7-8 k cells and one block takes its memory
+    // latency eight times over)
+    const bool bottom = nl >= 3 && L[nl - 2].n <= kMgBottomMax && env_int("EQS_MG_BOTTOM", 0) != 0;
+    const int lr = bottom ? nl - 2 : nl - 1;  // levels 1 .. lr-1 restrict on their own
+    for (int l = 1; l + 1 < nl && l < lr && e == hipSuccess; ++l)
         e = launch_mg_restrict(dd, lev, l, L[l + 1].n, L[l].r, c->mgp, gated, stream);
-    if (e == hipSuccess)
+    if (e == hipSuccess && bottom)
+        e = launch_mg_bottom(dd, lev, nl - 2, L[nl - 2].n, L[nl - 1].n, c->mgp, gated, stream);
+    else if (e == hipSuccess)
         e = launch_mg_coarsest(dd, lev, nl - 1, L[nl - 1].n, nl == 1 ? r : L[nl - 1].r, nl == 1 ? z : L[nl - 1].z,
                                c->mgp, gated, stream);
-    for (int l = nl - 2; l >= 1 && e == hipSuccess; --l)
+    for (int l = bottom ? nl - 3 : nl - 2; l >= 1 && e == hipSuccess; --l)
         e = launch_mg_prolong(dd, lev, l, L[l].n, L[l].r, L[l].z, c->mgp, gated, stream);
     if (nl > 1 && e == hipSuccess)
         e = launch_mg_fine(R.ls, R.ntiles, c->cpt, R.max_nx, lev, r, nullptr, z, c->mgp, gated, stream);
@@ -1301,6 +1310,7 @@ int eqsolve_set_preconditioner(eqs_ctx *c, int32_t kind, const eqs_mg_params *pr
     c->mg_ws = ws;
     c->mg = std::move(mg);
     c->mgp = p;
+    c->mgp.coarse_sym = env_int("EQS_MG_CSYM", 1) != 0 ? 1 : 0;
     c->precond = EQS_PRECOND_MG;
     retile_for_precond(c);
     clear_graphs(c);

@@ -73,6 +73,10 @@ struct SolveState {
     // budget; FP64: the solve's)
     int32_t sig_restarts;
     int32_t sig_inner;
+    // single-sync iteration: the next launch runs the last step again, with alpha from the
+    // directly summed sigma (its inputs are intact; y, which the first run formed, is kept)
+    int32_t redo;
+    int32_t sig_redos;   // such reruns over the whole solve
 };
 
 struct SetDesc {
@@ -82,7 +86,8 @@ struct SetDesc {
     // the single-sync step's own tiling: fS segments of fnt*cpt cells per plane (fnt = its block
     // size, LaunchSets::fnt), the same chunks, fntiles tiles numbered chunk-fastest (ford = 0) or
     // segment-fastest (ford = 1)
-    int32_t fS, fntiles, ford, fpad;
+    int32_t fS, fntiles, ford;
+    int32_t sig_redo;   // a sigma mismatch reruns the step (1) or restarts the iteration (0)
     // pointwise kernels: nflat blocks, block b takes chunks b, b + nflat, ... of kFlatChunk cells
     int32_t nflat;
     int32_t mode;
@@ -138,6 +143,8 @@ struct MgParams {
     double gamma;         // scale of the coarse correction
     int32_t coarse_sweeps;
     int32_t coarse_cells;
+    int32_t coarse_sym;   // coarse levels of an exactly symmetric matrix read W, S, B as E, N, T
+    int32_t pad;
 };
 
 // blocks of one launch -> (set, tile); set s owns logical tiles [tile_begin[s], tile_begin[s+1])

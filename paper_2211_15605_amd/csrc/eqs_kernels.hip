@@ -175,6 +175,7 @@ __device__ __forceinline__ void start_fresh(SolveState *st, double rr) {
     st->alpha = 1.0;
     st->omega = 1.0;
     st->fresh = 1;
+    st->redo = 0;
     st->half = 0;
     st->active = 1;
     st->fpar = 0;     // the residual is in slot 0 of s
@@ -218,6 +219,8 @@ struct FinSetup {  // sums: (b,b), (r,r), #bad a_P
         st->restarts = 0;
         st->sig_restarts = 0;
         st->sig_inner = 0;
+        st->sig_redos = 0;
+        st->redo = 0;
         st->rho_restarts = 0;
         st->outer = 0;
         st->active = 0;
@@ -322,6 +325,7 @@ struct FinFSetup {
         st->mat = 0;
         st->fpar = 0;
         st->fresh = 1;
+        st->redo = 0;
         const double sg = s[0], rr = s[1];
         st->rho = rr;
         st->sigma = sg;
@@ -343,9 +347,11 @@ constexpr int kMaxSigmaRestarts = 32;
 // (f,t_j), (r^,s_j), (r^,t_j), (t_j,s_j), (t_j,t_j), (r_j,r_j), (s_j,s_j), (r^,v_j).
 struct FinFused {
     double sig_tol;
+    int redo_on;
     __device__ void operator()(SolveState *st, const double *s) const {
         const double fp = s[0], fv = s[1], fs = s[2], ft = s[3], rs = s[4], rt = s[5];
         const double ts = s[6], tt = s[7], rr = s[8], ss = s[9];
+        const int was_fresh = st->fresh;
         st->fpar ^= 1;  // step j's s, t, p, v are in the other slot now
         if (!st->fresh) {
             // r_j (formed by this launch) decides convergence; y_j is stored
@@ -365,7 +371,24 @@ struct FinFused {
         // they can part, and a step with the wrong alpha derails the iteration: start afresh
         // from the current iterate instead (r_j = s_j + alpha_j v_j, r^ = r_j).
         const double sd = s[10];
-        if (fabs(sd - st->sigma) > sig_tol * fabs(sd)) {
+        // FP64 solves check at most kMaxSigmaRestarts times a solve; past that the iteration goes
+        // on with the expanded sigma (a relative gap of the FP64 threshold is harmless).  An FP32
+        // inner solve past its budget ends, and the refinement's FP64 residual decides.
+        const bool check = !iterating_fp64(st->mode) || st->sig_inner < kMaxSigmaRestarts;
+        if (check && fabs(sd - st->sigma) > sig_tol * fabs(sd)) {
+            if (redo_on && sd != 0.0) {
+                // Run step j again with alpha_j = rho_j / (r^, v_j): its inputs are still in the
+                // slot this launch read, p_j and v_j come out the same bit for bit (so the rerun
+                // passes this check), and y_j, which this launch formed from step j-1's values,
+                // stays as it is.  omega, beta and alpha_prev still hold step j-1's values.
+                st->fpar ^= 1;
+                st->fresh = was_fresh;
+                st->sigma = sd;
+                st->alpha = st->rho / sd;
+                st->redo = 1;
+                st->sig_redos++;
+                return;
+            }
             if (st->sig_inner >= kMaxSigmaRestarts) { stop_iter(st, ST_BREAKDOWN); return; }
             st->restarts++;
             st->sig_restarts++;
@@ -374,6 +397,7 @@ struct FinFused {
             st->need_f = 1;
             return;
         }
+        st->redo = 0;
         st->iters++;
         st->alpha_prev = st->alpha;  // alpha_j
         if (sqrt(ss) <= st->lim2) {  // half-step exit: x = y_j + alpha_j p_j
@@ -425,6 +449,8 @@ struct FinCast {  // sums: (b,b), #bad, #asymmetric rows
         st->restarts = 0;
         st->sig_restarts = 0;
         st->sig_inner = 0;
+        st->sig_redos = 0;
+        st->redo = 0;
         st->rho_restarts = 0;
         st->outer = 0;
         st->active = 0;
@@ -1257,6 +1283,7 @@ __device__ __forceinline__ void fused_step(const TileRef &tr) {
     const SolveState *st_ = d.st;
     const int in = st_->fpar, out = in ^ 1;
     const bool fresh = st_->fresh != 0;
+    const bool redo = st_->redo != 0;  // y_j is formed already: a rerun of the step leaves it
     const T al = (T)st_->alpha, ap = (T)st_->alpha_prev, om = (T)st_->omega, be = (T)st_->beta;
     const T *as[6];
     for (int k = 0; k < 6; ++k) as[k] = RAW ? (const T *)d.a[k + 1] : Vecs<T>::as(d)[k];
@@ -1466,7 +1493,7 @@ __device__ __forceinline__ void fused_step(const TileRef &tr) {
             if (own) {
                 const int i = qo[m] + kpb;
                 st_nt(pO, i, pv);
-                if (!fresh) st_nt(yv, i, yn);
+                if (!fresh && !redo) st_nt(yv, i, yn);
             }
             acc[0] += (double)keep_if(own, cv.f[m]) * (double)pv;
             acc[8] += (double)keep_if(own, r) * (double)r;
@@ -1571,7 +1598,7 @@ __device__ __forceinline__ void fused_step(const TileRef &tr) {
         bv = bp;
         bp = b0;
     }
-    reduce_and_finalize<11, FinFused, NT>(d, tr.tile, d.fntiles, acc, FinFused{d.sigma_tol[sizeof(T) == 4 ? 1 : 0]});
+    reduce_and_finalize<11, FinFused, NT>(d, tr.tile, d.fntiles, acc, FinFused{d.sigma_tol[sizeof(T) == 4 ? 1 : 0], d.sig_redo});
 }
 
 // FORM is chosen on the host (symmetric: every set of the launch exactly symmetric; raw: asked
@@ -2131,18 +2158,32 @@ __global__ void __launch_bounds__(kBlock) fill_kernel(double *p, long n, double 
 
 // the coefficients of level l as the V-cycle sees them: level 0 from its FP32 copy
 // (widened exactly to FP64), coarser levels from their FP64 Galerkin arrays
+// A level's coefficients.  Where the level-0 matrix is exactly symmetric (st->sym), every coarse
+// level is too, bit for bit: a coarse a_E and the a_W of the next coarse cell sum the same fine
+// links (a_W(c) = a_E(c-1)) in the same order.  Coarse levels then read W, S and B as the E, N
+// and T coefficients of the neighbouring cell (sym), four coefficient streams instead of seven.
+// A W/S/B coefficient is only read for a neighbour inside the grid.
 struct LevCoef {
     const double *d[7];
     const float *f[7];
-    bool f32;
+    bool f32, sym;
+    int nx, P;
     __device__ __forceinline__ double operator()(int q, int c) const {
-        return f32 ? (double)ld(f[q], c) : ld(d[q], c);
+        if (f32) return (double)ld(f[q], c);
+        if (q == 2 || q == 4 || q == 6) {
+            const int off = q == 2 ? 1 : (q == 4 ? nx : P);
+            return sym ? ld(d[q - 1], c - off) : ld(d[q], c);
+        }
+        return ld(d[q], c);
     }
 };
 
-__device__ __forceinline__ LevCoef mg_coef(const MgLevel &L, int l) {
+__device__ __forceinline__ LevCoef mg_coef(const MgLevel &L, int l, bool sym = false) {
     LevCoef k;
     k.f32 = l == 0;
+    k.sym = sym && l > 0;
+    k.nx = L.nx;
+    k.P = L.nx * L.ny;
     for (int q = 0; q < 7; ++q) {
         k.d[q] = L.a[q];
         k.f[q] = L.a32[q];
@@ -2232,20 +2273,18 @@ __global__ void __launch_bounds__(kBlock) mg_coarsen_kernel(const SetDesc *d, co
 // Eight consecutive lanes take the eight cells of one aggregate (lane bits:
 // i, j, k offsets), so a wave reads rows of 16 consecutive cells; lane 0 of
 // the group sums the group's values in cell-index order (the definition's).
-__global__ void __launch_bounds__(kBlock) mg_restrict_kernel(const SetDesc *d, const MgLevel *lev, int l,
-                                                             const double *rin, MgParams prm, int gated) {
+// gt: the thread's index among the nt threads taking the level; out(cc, sum) stores a coarse value
+template <class Out>
+__device__ __forceinline__ void mg_restrict_body(const MgLevel &F, const MgLevel &C, const LevCoef &a,
+                                                 const double *rin, double w, int gt, int nt, Out out) {
 #pragma clang fp contract(off)
-    if (gated && !d->st->active) return;
-    const MgLevel F = lev[l], C = lev[l + 1];
-    const LevCoef a = mg_coef(F, l);
     const int nx = F.nx, ny = F.ny, nz = F.nz, cx = C.nx, cy = C.ny;
-    const double w = prm.omega;
     auto z1 = [&](int x, int, int, int) { return w * ld(rin, x) / a(0, x); };
-    const int g8 = threadIdx.x & 7, di = g8 & 1, dj = (g8 >> 1) & 1, dk = g8 >> 2;
-    const int stride = (int)(gridDim.x * kBlock) >> 3;
+    const int g8 = gt & 7, di = g8 & 1, dj = (g8 >> 1) & 1, dk = g8 >> 2;
+    const int stride = nt >> 3;
     // the loop bound is uniform over a wave (the shuffles need every lane of a group)
-    for (int w0 = (int)(blockIdx.x * kBlock + (threadIdx.x & ~63)) >> 3; w0 < C.n; w0 += stride) {
-        const int cc = w0 + (int)((threadIdx.x & 63) >> 3);
+    for (int w0 = (gt & ~63) >> 3; w0 < C.n; w0 += stride) {
+        const int cc = w0 + ((gt & 63) >> 3);
         const bool inC = cc < C.n;
         const int ccl = min(cc, C.n - 1);
         const int I = ccl % cx, t = ccl / cx, J = t % cy, K = t / cy;
@@ -2268,46 +2307,60 @@ __global__ void __launch_bounds__(kBlock) mg_restrict_kernel(const SetDesc *d, c
 #pragma unroll
             for (int m = 0; m < 8; ++m)
                 if (oks[m]) sum += qs[m];
-            st(C.r, cc, sum);
+            out(cc, sum);
         }
     }
 }
 
-// z = z2 + omega D^-1 (r - A z2) with z2 = omega D^-1 r + gamma P e, e = level l + 1's result
-__global__ void __launch_bounds__(kBlock) mg_prolong_kernel(const SetDesc *d, const MgLevel *lev, int l,
-                                                            const double *rin, double *zout, MgParams prm,
-                                                            int gated) {
-#pragma clang fp contract(off)
+__global__ void __launch_bounds__(kBlock) mg_restrict_kernel(const SetDesc *d, const MgLevel *lev, int l,
+                                                             const double *rin, MgParams prm, int gated) {
     if (gated && !d->st->active) return;
     const MgLevel F = lev[l], C = lev[l + 1];
-    const LevCoef a = mg_coef(F, l);
+    const LevCoef a = mg_coef(F, l, prm.coarse_sym && d->st->sym != 0);
+    double *cr = C.r;
+    mg_restrict_body(F, C, a, rin, prm.omega, (int)(blockIdx.x * kBlock + threadIdx.x), (int)(gridDim.x * kBlock),
+                     [&](int cc, double v) { st(cr, cc, v); });
+}
+
+// z = z2 + omega D^-1 (r - A z2) with z2 = omega D^-1 r + gamma P e, e = level l + 1's result
+// eat(cc) gives the coarse level's result at coarse cell cc
+template <class E>
+__device__ __forceinline__ void mg_prolong_body(const MgLevel &F, const MgLevel &C, const LevCoef &a,
+                                                const double *rin, double *zout, double w, double gm, int gt,
+                                                int nt, E eat) {
+#pragma clang fp contract(off)
     const int nx = F.nx, ny = F.ny, nz = F.nz, cx = C.nx, cy = C.ny;
-    const double w = prm.omega, gm = prm.gamma;
-    const double *e = C.z;
     auto z2 = [&](int x, int i, int j, int k) {
-        return w * ld(rin, x) / a(0, x) + gm * ld(e, i / 2 + cx * (j / 2 + cy * (k / 2)));
+        return w * ld(rin, x) / a(0, x) + gm * eat(i / 2 + cx * (j / 2 + cy * (k / 2)));
     };
-    for (int c = blockIdx.x * kBlock + threadIdx.x; c < F.n; c += gridDim.x * kBlock) {
+    for (int c = gt; c < F.n; c += nt) {
         const int i = c % nx, t = c / nx, j = t % ny, k = t / ny;
         const double q = mg_row(a, nx, ny, nz, i, j, k, c, z2);
         st(zout, c, z2(c, i, j, k) + w * (ld(rin, c) - q) / a(0, c));
     }
 }
 
+__global__ void __launch_bounds__(kBlock) mg_prolong_kernel(const SetDesc *d, const MgLevel *lev, int l,
+                                                            const double *rin, double *zout, MgParams prm,
+                                                            int gated) {
+    if (gated && !d->st->active) return;
+    const MgLevel F = lev[l], C = lev[l + 1];
+    const LevCoef a = mg_coef(F, l, prm.coarse_sym && d->st->sym != 0);
+    const double *e = C.z;
+    mg_prolong_body(F, C, a, rin, zout, prm.omega, prm.gamma, (int)(blockIdx.x * kBlock + threadIdx.x),
+                    (int)(gridDim.x * kBlock), [&](int cc) { return ld(e, cc); });
+}
+
 // coarsest level: coarse_sweeps damped-Jacobi sweeps from zero in one block;
 // a thread keeps its cells' coefficients and right-hand side in registers
 constexpr int kMgCoarseThreads = 1024;
 constexpr int kMgCoarseCells = kMgCoarsestMax / kMgCoarseThreads;
-__global__ void __launch_bounds__(kMgCoarseThreads) mg_coarsest_kernel(const SetDesc *d, const MgLevel *lev, int l,
-                                                                       const double *rin, double *zout,
-                                                                       MgParams prm, int gated) {
+// rat(c): the level's right-hand side at cell c; the result is left in zb[returned slot]
+template <class R>
+__device__ __forceinline__ int mg_coarsest_body(const MgLevel &F, const LevCoef &a, double w, int sweeps,
+                                                double (*zb)[kMgCoarsestMax], R rat) {
 #pragma clang fp contract(off)
-    if (gated && !d->st->active) return;
-    __shared__ double zb[2][kMgCoarsestMax];
-    const MgLevel F = lev[l];
-    const LevCoef a = mg_coef(F, l);
     const int nx = F.nx, ny = F.ny, nz = F.nz, n = F.n, P = nx * ny;
-    const double w = prm.omega;
     double co[kMgCoarseCells][7], rr[kMgCoarseCells];
     int cell[kMgCoarseCells];
     bool has[kMgCoarseCells][6];
@@ -2323,14 +2376,15 @@ __global__ void __launch_bounds__(kMgCoarseThreads) mg_coarsest_kernel(const Set
         has[m][3] = j > 0;
         has[m][4] = k + 1 < nz;
         has[m][5] = k > 0;
-        for (int q = 0; q < 7; ++q) co[m][q] = a(q, cl);
-        rr[m] = ld(rin, cl);
+        co[m][0] = a(0, cl);
+        for (int q = 1; q < 7; ++q) co[m][q] = has[m][q - 1] ? a(q, cl) : 0.0;  // (unused where absent)
+        rr[m] = rat(cl);
         if (c < n) zb[0][c] = 0.0;
     }
     __syncthreads();
     const int off[6] = {1, -1, nx, -nx, P, -P};
     int cur = 0;
-    for (int it = 0; it < prm.coarse_sweeps; ++it) {
+    for (int it = 0; it < sweeps; ++it) {
         const double *zc = zb[cur];
 #pragma unroll
         for (int m = 0; m < kMgCoarseCells; ++m) {
@@ -2346,9 +2400,40 @@ __global__ void __launch_bounds__(kMgCoarseThreads) mg_coarsest_kernel(const Set
         __syncthreads();
         cur ^= 1;
     }
-#pragma unroll
-    for (int m = 0; m < kMgCoarseCells; ++m)
-        if (cell[m] < n) st(zout, cell[m], zb[cur][cell[m]]);
+    return cur;
+}
+
+__global__ void __launch_bounds__(kMgCoarseThreads) mg_coarsest_kernel(const SetDesc *d, const MgLevel *lev, int l,
+                                                                       const double *rin, double *zout,
+                                                                       MgParams prm, int gated) {
+    if (gated && !d->st->active) return;
+    __shared__ double zb[2][kMgCoarsestMax];
+    const MgLevel F = lev[l];
+    const LevCoef a = mg_coef(F, l, prm.coarse_sym && d->st->sym != 0);
+    const int cur = mg_coarsest_body(F, a, prm.omega, prm.coarse_sweeps, zb, [&](int c) { return ld(rin, c); });
+    for (int c = threadIdx.x; c < F.n; c += kMgCoarseThreads) st(zout, c, zb[cur][c]);
+}
+
+// The bottom of the V-cycle in one block: level l's restriction into the coarsest level l + 1
+// (its right-hand side kept in LDS), the coarsest level's sweeps, and level l's prolongation with
+// its smoothing step -- the operations of the three kernels above, in their order, for a level l
+// of at most kMgBottomMax cells (two launches fewer per V-cycle, where those small grids are
+// latency-bound).
+__global__ void __launch_bounds__(kMgCoarseThreads) mg_bottom_kernel(const SetDesc *d, const MgLevel *lev, int l,
+                                                                     MgParams prm, int gated) {
+    if (gated && !d->st->active) return;
+    __shared__ double zb[2][kMgCoarsestMax];
+    __shared__ double rc[kMgCoarsestMax];
+    const MgLevel F = lev[l], C = lev[l + 1];
+    const bool sym = prm.coarse_sym && d->st->sym != 0;
+    const LevCoef af = mg_coef(F, l, sym), ac = mg_coef(C, l + 1, sym);
+    mg_restrict_body(F, C, af, F.r, prm.omega, (int)threadIdx.x, kMgCoarseThreads,
+                     [&](int cc, double v) { rc[cc] = v; });
+    __syncthreads();
+    const int cur = mg_coarsest_body(C, ac, prm.omega, prm.coarse_sweeps, zb, [&](int c) { return rc[c]; });
+    const double *e = zb[cur];
+    mg_prolong_body(F, C, af, F.r, F.z, prm.omega, prm.gamma, (int)threadIdx.x, kMgCoarseThreads,
+                    [&](int cc) { return e[cc]; });
 }
 
 // ---- finest level through the k-march (operands staged in LDS like the
@@ -2711,6 +2796,13 @@ hipError_t launch_mg_coarsest(const SetDesc *d, const MgLevel *lev, int l, int n
     if (n > kMgCoarsestMax) return hipErrorInvalidValue;
     hipLaunchKernelGGL(mg_coarsest_kernel, dim3(1), dim3(kMgCoarseThreads), 0, stream, d, lev, l, rin, zout, prm,
                        gated ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_mg_bottom(const SetDesc *d, const MgLevel *lev, int l, int n, int nc, MgParams prm, bool gated,
+                            hipStream_t stream) {
+    if (n > kMgBottomMax || nc > kMgCoarsestMax || l < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(mg_bottom_kernel, dim3(1), dim3(kMgCoarseThreads), 0, stream, d, lev, l, prm, gated ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -43,6 +43,9 @@ hipError_t launch_mg_restrict(const SetDesc *d, const MgLevel *lev, int l, int n
                               bool gated, hipStream_t stream);
 // coarsest level l (n cells, at most kMgCoarsestMax): coarse_sweeps damped-Jacobi sweeps from zero
 constexpr int kMgCoarsestMax = 2048;
+// the bottom of the V-cycle in one block (restriction of a coarse level l >= 1 of at most
+// kMgBottomMax cells, the coarsest level's sweeps, the prolongation of level l)
+constexpr int kMgBottomMax = 16384;
 hipError_t launch_mg_coarsest(const SetDesc *d, const MgLevel *lev, int l, int n, const double *rin, double *zout,
                               MgParams prm, bool gated, hipStream_t stream);
 // finest level through the k-march (the set's tiles): res != NULL: res = r - A z1 per cell;
@@ -53,6 +56,8 @@ hipError_t launch_mg_fine(const LaunchSets &ls, int ntiles, int cpt, int max_nx,
 hipError_t launch_mg_aggregate(const SetDesc *d, const MgLevel *lev, int nc, const double *res, bool gated,
                                hipStream_t stream);
 // prolongation of level l+1's result and one smoothing sweep on level l (n = cells of level l)
+hipError_t launch_mg_bottom(const SetDesc *d, const MgLevel *lev, int l, int n, int nc, MgParams prm, bool gated,
+                            hipStream_t stream);
 hipError_t launch_mg_prolong(const SetDesc *d, const MgLevel *lev, int l, int n, const double *rin, double *zout,
                              MgParams prm, bool gated, hipStream_t stream);
 
