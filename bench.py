@@ -218,8 +218,9 @@ def time_simple(iters=8, warm=2):
                      "solver_iters_last": infos[-1]["iters"], "status_worst": max(i["status"] for i in infos),
                      "mass_residual_first_last": [first["mass_residual"], infos[-1]["mass_residual"]]}
         if kind == "mg":
-            # stage kernels on the current state, each enqueued `reps` times back to back between
-            # two events on the library's stream (torch's current stream), outputs preallocated
+            # stage kernels on the current state, `reps` calls each, every call between its own pair
+            # of events on the library's stream (torch's current stream): the median, so host time
+            # between calls does not count; outputs preallocated
             reps = 10
             mo = sb.momentum_outputs()
             po = sb.pressure_outputs()
@@ -238,14 +239,14 @@ def time_simple(iters=8, warm=2):
                   "form_pressure": 8 * (2 * (nu + nv + nw) + 8 * npc),
                   "correct": 8 * (3 * (nu + nv + nw) + 3 * npc)}
             for name, fn in calls.items():
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
                 torch.cuda.synchronize()
-                e0.record()
-                for _ in range(reps):
+                for e0, e1 in ev:
+                    e0.record()
                     fn()
-                e1.record()
+                    e1.record()
                 torch.cuda.synchronize()
-                ms = e0.elapsed_time(e1) / reps
+                ms = float(np.median([e0.elapsed_time(e1) for e0, e1 in ev]))
                 out["stage_" + name] = {"ms": ms, "algorithmic_MB": by[name] / 1e6,
                                         "GBps": by[name] / (ms * 1e-3) / 1e9}
             del mo, po
