@@ -414,12 +414,33 @@ struct Run {
     // 2^k iterations (the launch table and the set table's device address
     // are fixed per context, so a graph stays valid across calls), or
     // launched one by one when per-launch timing is on.
-    int iterate(int C, bool f32) {
+    // hk: after every step, the refinement's per-set housekeeping (form the inner iterate, update x,
+    // the FP64 residual, f = M^T r^ for the next inner solve), each launch doing work only for the
+    // sets whose state asks for it, so a set whose inner solve ends starts its next one at once
+    // instead of waiting for the others (FP32 forms, single-sync iteration)
+    int iterate(int C, bool f32, bool hk = false) {
         int rc;
+        auto housekeeping = [&](hipStream_t s) {
+            bool ok = launch_kernel(K_MAT, ls, ntiles, nflat, c->cpt, max_nx, true, trans, s, nullptr, nullptr, 0) ==
+                      hipSuccess;
+            ok = ok && launch_kernel(K_UPDATE, ls, ntiles, nflat, c->cpt, max_nx, false, trans, s, nullptr, nullptr,
+                                     0) == hipSuccess;
+            ok = ok && launch_kernel(K_OUTER, ls, ntiles, nflat, c->cpt, max_nx, false, trans, s, nullptr, nullptr,
+                                     0) == hipSuccess;
+            ok = ok && launch_kernel(K_FSETUP, ls, ntiles, nflat, c->cpt, max_nx, true, trans, s, nullptr, nullptr,
+                                     0) == hipSuccess;
+            return ok;
+        };
         if (c->profile_mask || !c->use_graphs) {
             for (int i = 0; i < C; ++i) {
                 if (c->sync1) {
                     if ((rc = L(K_FUSED, nullptr, nullptr, form(), f32))) return rc;
+                    if (hk) {
+                        if ((rc = L(K_MAT, nullptr, nullptr, 0, true))) return rc;
+                        if ((rc = L(K_UPDATE))) return rc;
+                        if ((rc = L(K_OUTER))) return rc;
+                        if ((rc = L(K_FSETUP, nullptr, nullptr, 0, true))) return rc;
+                    }
                     continue;
                 }
                 if ((rc = L(K_K1, nullptr, nullptr, 0, f32))) return rc;
@@ -428,8 +449,8 @@ struct Run {
             }
             return 0;
         }
-        const int per_iter = c->sync1 ? 1 : 3;
-        auto &slots = c->graphs[std::make_tuple(first, count, trans, f32, c->sync1 ? form() : 0)];
+        const int per_iter = c->sync1 ? (hk ? 5 : 1) : 3;
+        auto &slots = c->graphs[std::make_tuple(first, count, trans, f32, (c->sync1 ? form() : 0) + (hk ? 8 : 0))];
         for (int b = 8; b >= 0; --b) {
             while (C >= (1 << b)) {
                 if (!slots[b]) {
@@ -440,6 +461,7 @@ struct Run {
                         if (c->sync1) {
                             ok = launch_kernel(K_FUSED, ls, ntiles, nflat, c->cpt, max_nx, f32, trans,
                                                c->capture_stream, nullptr, nullptr, form()) == hipSuccess;
+                            if (hk) ok = ok && housekeeping(c->capture_stream);
                             continue;
                         }
                         for (Kern k : {K_K1, K_K2, K_K3})
@@ -597,9 +619,23 @@ int run_fp32(Run &R) {
     if ((rc = R.readback())) return rc;
     R.pick_form();
     R.reset_rate();
+    // A batch of large sets runs the refinement's housekeeping in the launch stream after every
+    // step (EQS_REFINE_INSTREAM=0: between chunks, when the host sees a set's inner solve end), so no
+    // set idles while the others finish their inner solves.  Small sets keep the host-driven
+    // rounds: there the extra launches would cost more than a step.
+    long cells = 0;
+    for (int i = 0; i < R.count; ++i) cells += R.c->sets[R.first + i].n;
+    const bool hk = s1 && R.count > 1 && env_int("EQS_REFINE_INSTREAM", 1) != 0 &&
+                    cells >= env_int("EQS_REFINE_INSTREAM_CELLS", 1 << 22);
     for (long guard = 0;; ++guard) {
         if (guard > R.guard_limit) { R.c->broken = true; return EQS_ERR_STATE; }
         if (R.all_done()) break;
+        if (hk) {
+            // every housekeeping step is already in the stream: look at the state every 16 steps
+            if ((rc = R.iterate(16, true, true))) return rc;
+            if ((rc = R.readback())) return rc;
+            continue;
+        }
         if (R.any([s1](const SolveState &s) {
                 return !s.done && (s.inner_done != 0 || (s1 && (s.mat || s.need_f)));
             })) {

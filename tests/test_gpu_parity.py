@@ -533,6 +533,42 @@ def test_fp64_sigma_check_budget_then_off(torch_dev, orc):
     assert orc.rel_residual(g.shape, diags, b, host(x)) <= 1e-10
 
 
+@pytest.mark.parametrize("precision", ["fp32_refine", "fp32"])
+def test_refinement_housekeeping_in_stream(torch_dev, orc, precision):
+    # The refinement's per-set housekeeping (form the inner iterate, update x, the FP64 residual,
+    # f for the next inner solve) either runs in the launch stream after every step, or between
+    # chunks when the host sees a set's inner solve end.  Every kernel acts only on the sets whose
+    # state asks for it, in the same order, so both give the bits of the sets solved one at a time;
+    # the pressure-like sets make the FP32 step restart on sigma mismatches along the way (the
+    # symmetric form is off, so that a set solved alone runs the form the mixed batch runs).
+    torch, dev = torch_dev
+    shapes = [(24, 96, 24), (33, 64, 17), (25, 96, 24), (20, 40, 30)]
+    cfgs = [2, 1, 2, 1]
+    systems = [manufactured(orc, c, grid=W.Grid(*sh), set_id=i) for i, (c, sh) in enumerate(zip(cfgs, shapes))]
+    Ds = [dev_arrays(torch, dev, s_[1]) for s_ in systems]
+    bs = [dev_arrays(torch, dev, [s_[2]])[0] for s_ in systems]
+    tol = 1e-10 if precision == "fp32_refine" else 1e-5
+    out = {}
+    for name, env in (("instream", dict(EQS_REFINE_INSTREAM_CELLS=0)), ("rounds", dict(EQS_REFINE_INSTREAM=0)),
+                      ("instream_eager", dict(EQS_REFINE_INSTREAM_CELLS=0, EQS_GRAPHS=0))):
+        ctx = context(shapes, precision=precision, env=dict(env, EQS_SYM=0))
+        xb, infos = ctx.solve_batched(Ds, bs, tol=tol, maxit=4000)
+        out[name] = ([host(x) for x in xb], infos)
+        if name == "instream":
+            for i, s_ in enumerate(systems):
+                xi, info = ctx.solve(Ds[i], bs[i], tol=tol, maxit=4000, set_id=i)
+                assert np.array_equal(host(xi), out[name][0][i]), i
+                assert info == infos[i]
+        ctx.close()
+    print(precision, [i["sigma_restarts"] for i in out["instream"][1]], [i["iters"] for i in out["instream"][1]], flush=True)
+    for i, s_ in enumerate(systems):
+        assert out["instream"][1][i]["status"] == 0, out["instream"][1][i]
+        assert orc.rel_residual(s_[0].shape, s_[1], s_[2], out["instream"][0][i]) <= tol
+        for other in ("rounds", "instream_eager"):
+            assert np.array_equal(out["instream"][0][i], out[other][0][i]), (i, other)
+            assert out["instream"][1][i] == out[other][1][i], (i, other)
+
+
 def _batched_full_size(torch, dev, orc, cfg, precisions, env=None):
     """Every set of workload cfg at full size, solved in one batched call to 1e-10 per precision;
     the oracle recomputes each set's residual and bounds its forward error."""
