@@ -350,11 +350,28 @@ def time_adjoint(runs=5, warm=2):
         if r >= warm:
             tf.append(t1 - t0)
             ta.append(t2 - t1)
+    # the same pair with the multigrid preconditioner (the adjoint then runs the V-cycle of A^T)
+    ctx.set_preconditioner("mg", **mg_params_for(3))
+    tfm, tam = [], []
+    for r in range(warm + runs):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, fim = ctx.solve(D, b, torch.zeros_like(b), tol=1e-10, maxit=1000, check=False)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        gb, gd, aim = ctx.adjoint(D, x, w, tol=1e-10, maxit=1000, check=False)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if r >= warm:
+            tfm.append(t1 - t0)
+            tam.append(t2 - t1)
     ctx.close()
     return {"workload": "adjoint64: 64x64x64 convection-diffusion, L = sum(w x), tol 1e-10, FP64",
             "forward_ms": 1e3 * float(np.median(tf)), "forward_iters": fi["iters"],
             "adjoint_ms": 1e3 * float(np.median(ta)), "adjoint_iters": ai["iters"],
-            "status": max(fi["status"], ai["status"])}
+            "multigrid": {"forward_ms": 1e3 * float(np.median(tfm)), "forward_iters": fim["iters"],
+                          "adjoint_ms": 1e3 * float(np.median(tam)), "adjoint_iters": aim["iters"]},
+            "status": max(fi["status"], ai["status"], fim["status"], aim["status"])}
 
 
 def time_latency(runs=10, warm=3):

@@ -133,7 +133,9 @@ int eqsolve_solve_batched(eqs_ctx *ctx, const double *const *const *diag, const 
 /*
  * Adjoint of x = A^{-1} b for a loss L(x): given x (the converged forward
  * solution) and w = dL/dx, solve A^T lambda = w in FP64 BiCGSTAB (Jacobi on
- * the same a_P) and return
+ * the same a_P; with EQS_PRECOND_MG selected, the multigrid V-cycle of A^T,
+ * whose rows -- a_P and the links pointing at each cell -- are formed into
+ * the context's workspace first) and return
  *     grad_b = lambda,
  *     grad_diag[P][c] = -lambda[c] x[c],
  *     grad_diag[nb][c] = +lambda[c] x[nb(c)]  (0 where nb(c) is outside the grid),
@@ -193,7 +195,7 @@ enum { EQS_STEP_SCALED = 0, EQS_STEP_UNSCALED = 1 };
  */
 int eqsolve_set_step_form(eqs_ctx *ctx, int32_t form);
 
-/* Preconditioners of the FP64 forward solves. */
+/* Preconditioners of the FP64 solves (forward and adjoint). */
 enum { EQS_PRECOND_JACOBI = 0, EQS_PRECOND_MG = 1 };
 
 /* Parameters of the multigrid V-cycle (see eqsolve_set_preconditioner). */
@@ -205,9 +207,9 @@ typedef struct {
 } eqs_mg_params;
 
 /*
- * Choose the right preconditioner of the forward solves of an EQS_FP64
- * context (eqsolve_solve and eqsolve_solve_batched; the adjoint keeps
- * Jacobi).  EQS_PRECOND_JACOBI is the default.  EQS_PRECOND_MG is an
+ * Choose the right preconditioner of the solves of an EQS_FP64 context
+ * (eqsolve_solve, eqsolve_solve_batched and eqsolve_adjoint, whose A^T solve
+ * then runs the V-cycle built from A^T).  EQS_PRECOND_JACOBI is the default.  EQS_PRECOND_MG is an
  * aggregation multigrid V-cycle, an addition to the paper's method aimed at
  * the pressure-correction system, whose Jacobi iteration count grows with
  * the grid: levels of 2 x 2 x 2 aggregates (dimensions halved, rounding up)

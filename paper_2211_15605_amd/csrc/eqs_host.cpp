@@ -1482,6 +1482,24 @@ int eqsolve_adjoint(eqs_ctx *c, int32_t set, const double *const diag[7], const 
     d.maxit = maxit;
     int rc = upload_desc(c, set, 1);
     if (rc) return rc;
+    if (c->precond == EQS_PRECOND_MG) {
+        // A^T's rows into the set's scaled-coefficient buffers (unused by the multigrid iteration),
+        // then the multigrid solve of A^T lambda = w on them: its hierarchy is built from A^T
+        Run T = make_run(c, set, 1, false);
+        if ((rc = T.L(K_TRANSPOSE))) return rc;
+        // the set table is pinned host memory, read by the upload when it executes: the transpose
+        // must have read this call's pointers before they are replaced
+        EQS_HIP(hipStreamSynchronize(c->stream));
+        for (int k = 1; k < 7; ++k) d.a[k] = c->sets[set].as[k - 1];
+        if ((rc = upload_desc(c, set, 1))) return rc;
+        Run R = make_run(c, set, 1, false);
+        if ((rc = R.L(K_ZERO, nullptr, nullptr, 1))) return rc;  // lambda0 = 0
+        if ((rc = run_fp64(R))) return rc;
+        if ((rc = R.L(K_GRAD))) return rc;
+        if ((rc = R.readback())) return rc;
+        write_info(c, set, info);
+        return c->h_state[set].status;
+    }
     Run R = make_run(c, set, 1, true);
     if ((rc = R.L(K_ZERO, nullptr, nullptr, 1))) return rc;  // lambda0 = 0
     if ((rc = run_fp64(R))) return rc;

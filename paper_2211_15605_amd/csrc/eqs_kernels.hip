@@ -1917,6 +1917,36 @@ __global__ void __launch_bounds__(kBlock) zero_kernel(LaunchSets ls, int force) 
     }
 }
 
+// The rows of A^T in the Patankar form of A: a_P on the diagonal, and the links of row c of A^T
+// are the links pointing at c in the neighbouring rows of A, aT_E(c) = a_W(c+1), aT_W(c) = a_E(c-1),
+// aT_N(c) = a_S(c+nx), aT_S(c) = a_N(c-nx), aT_T(c) = a_B(c+P), aT_B(c) = a_T(c-P) (0 where that
+// neighbour is outside the grid).  Written into the set's six scaled-coefficient buffers, which the
+// multigrid iteration does not use, so the multigrid solve of A^T x = b runs on them unchanged.
+__global__ void __launch_bounds__(kBlock) transpose_kernel(LaunchSets ls) {
+    const TileRef tr = locate<true>(ls);
+    const SetDesc &d = *tr.d;
+    const int nx = d.nx, ny = d.ny, nz = d.nz, P = d.plane, n = d.n, nflat = d.nflat;
+    const double *E = d.a[1], *Wc = d.a[2], *N = d.a[3], *S = d.a[4], *T = d.a[5], *B = d.a[6];
+    double *o[6];
+    for (int q = 0; q < 6; ++q) o[q] = d.as[q];
+    for (int ch = tr.tile; ch * kFlatChunk < n; ch += nflat) {
+        const int base = ch * kFlatChunk + (int)threadIdx.x;
+#pragma unroll
+        for (int u = 0; u < kFlatU; ++u) {
+            const int idx = base + kBlock * u;
+            if (idx < n) {
+                const int k = idx / P, q = idx - k * P, j = q / nx, i = q - j * nx;
+                st(o[0], idx, i + 1 < nx ? ld(Wc, idx + 1) : 0.0);
+                st(o[1], idx, i > 0 ? ld(E, idx - 1) : 0.0);
+                st(o[2], idx, j + 1 < ny ? ld(S, idx + nx) : 0.0);
+                st(o[3], idx, j > 0 ? ld(N, idx - nx) : 0.0);
+                st(o[4], idx, k + 1 < nz ? ld(B, idx + P) : 0.0);
+                st(o[5], idx, k > 0 ? ld(T, idx - P) : 0.0);
+            }
+        }
+    }
+}
+
 // adjoint gradients: g_P = -lambda x; g_nb = lambda x_nb (0 out of the grid)
 __global__ void __launch_bounds__(kBlock) grad_kernel(LaunchSets ls) {
     const TileRef tr = locate<true>(ls);
@@ -2984,6 +3014,9 @@ hipError_t launch_kernel(Kern k, const LaunchSets &ls, int ntiles, int nflat, in
         break;
     case K_GRAD:
         EQS_LAUNCH(grad_kernel, fgrid, block, 0, ls);
+        break;
+    case K_TRANSPOSE:
+        EQS_LAUNCH(transpose_kernel, fgrid, block, 0, ls);
         break;
     case K_APPLY:
         if (trans) EQS_DISPATCH(cpt, h, EQS_LAUNCH((apply_kernel<C, HH, true>), grid, block, lds64, ls, x, y));

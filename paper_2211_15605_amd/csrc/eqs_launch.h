@@ -31,7 +31,8 @@ enum Kern {
     K_PC_S,     // s = r - alpha v
     K_PC_T,     // t = A s^, (t,s), (t,t), (s,s)
     K_PC_X,     // x += alpha p^ + omega s^, r = s - omega t, (r^, r), (r, r)
-    K_MG        // one V-cycle level step (restriction, coarsest sweeps or prolongation + smoothing)
+    K_MG,       // one V-cycle level step (restriction, coarsest sweeps or prolongation + smoothing)
+    K_TRANSPOSE // the six neighbour coefficients of A^T into the set's scaled-coefficient buffers
 };
 
 // multigrid kernels of set `set` (d: its device table entry, lev: its device level table)

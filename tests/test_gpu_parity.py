@@ -690,6 +690,56 @@ def test_mg_batched_equals_sequential_and_statuses(torch_dev, orc):
     assert info["status"] == 0 and not np.any(host(x))
 
 
+@pytest.mark.parametrize("cfg,shape", [(0, (20, 30, 15)), (1, (32, 64, 32)), (2, (25, 48, 24))])
+def test_mg_adjoint_matches_oracle(torch_dev, orc, cfg, shape):
+    # With multigrid selected the adjoint solves A^T lambda = w with the V-cycle of A^T: lambda
+    # meets tol in the oracle's transposed residual, takes the oracle's multigrid iteration count
+    # on A^T's rows (formed here independently from the definition), and the gradients equal the
+    # oracle's from its own Jacobi adjoint
+    from oracle import oracle as O
+    torch, dev = torch_dev
+    g = W.Grid(*shape)
+    s_ = W.make_set(cfg, 0, grid=g, with_weights=True)
+    diags, w = s_["diags"], s_["w"]
+    b = orc.apply(g.shape, diags, s_["x_star"])
+    xo, _ = orc.bicgstab(g.shape, diags, b, tol=1e-13, maxit=5000)
+    lo, linfo = orc.bicgstab(g.shape, diags, w, tol=1e-13, maxit=5000, transpose=True)
+    assert linfo["status"] == 0
+    Go = orc.grad(g.shape, lo, xo)
+    # rows of A^T: a_P, and the links of the neighbours pointing at the cell
+    nx, ny, nz = g.nx, g.ny, g.nz
+    a = [d.reshape(nz, ny, nx) for d in diags]
+    at = [a[0].copy()] + [np.zeros_like(a[0]) for _ in range(6)]
+    at[1][:, :, :-1] = a[2][:, :, 1:]    # E^T(c) = W(c+1)
+    at[2][:, :, 1:] = a[1][:, :, :-1]    # W^T(c) = E(c-1)
+    at[3][:, :-1, :] = a[4][:, 1:, :]    # N^T(c) = S(c+nx)
+    at[4][:, 1:, :] = a[3][:, :-1, :]    # S^T(c) = N(c-nx)
+    at[5][:-1, :, :] = a[6][1:, :, :]    # T^T(c) = B(c+P)
+    at[6][1:, :, :] = a[5][:-1, :, :]    # B^T(c) = T(c-P)
+    at = [x.ravel() for x in at]
+    prm = dict(omega=0.8, gamma=1.6 if cfg == 1 else 1.0, coarse_sweeps=30, coarse_cells=512)
+    lm, minfo = orc.bicgstab_mg(g.shape, at, w, tol=1e-12, maxit=500, params=O.mg_params(**prm))
+    assert minfo["status"] == 0
+    ctx = context([g.shape])
+    ctx.set_preconditioner("mg", **prm)
+    D = dev_arrays(torch, dev, diags)
+    xd, wd = dev_arrays(torch, dev, [xo, w])
+    gb, gd, info = ctx.adjoint(D, xd, wd, tol=1e-12, maxit=500)
+    gb2, _, info2 = ctx.adjoint(D, xd, wd, tol=1e-12, maxit=500)   # again, in the same context
+    ctx.close()
+    print("mg adjoint", cfg, shape, info, "oracle mg on A^T", minfo["iters"], "jacobi", linfo["iters"], flush=True)
+    assert np.array_equal(host(gb), host(gb2)) and info == info2
+    assert info["status"] == 0
+    assert orc.rel_residual(g.shape, diags, w, host(gb), transpose=True) <= 1e-12
+    assert abs(info["iters"] - minfo["iters"]) <= 2
+    if cfg != 1:
+        assert np.linalg.norm(host(gb) - lo) <= 1e-9 * np.linalg.norm(lo)
+        for k in range(7):
+            assert np.linalg.norm(host(gd[k]) - Go[k]) <= 1e-9 * np.linalg.norm(Go[k]) + 1e-300, k
+    else:  # near-singular: the solutions agree to what the residual bound allows
+        assert np.linalg.norm(host(gb) - lo) <= 1e-6 * np.linalg.norm(lo)
+
+
 def test_mg_needs_an_fp64_context(torch_dev):
     from paper_2211_15605_amd.solver import EqSolveError
     ctx = context([(8, 8, 8)], precision="fp32_refine")
