@@ -217,8 +217,8 @@ typedef struct {
  * restriction by summing an aggregate, Galerkin coarse operators (again
  * 7-point), one damped-Jacobi step before and after the coarse correction
  * (scaled by gamma) and coarse_sweeps damped-Jacobi sweeps on the coarsest
- * level.  With it a set is iterated on its own (a batched call solves its
- * sets one after another), on the original A, with x updated in place.
+ * level.  The iteration runs on the original A, with x updated in place; a
+ * batched call iterates its sets together (every launch over all of them).
  * The finest level's operator is the system's with its coefficients rounded
  * to FP32 (arithmetic stays FP64); when a call's matrix is exactly symmetric
  * (a_W(c) = a_E(c-1), a_S(c) = a_N(c-nx), a_B(c) = a_T(c-P), checked per

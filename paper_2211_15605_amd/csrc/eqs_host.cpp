@@ -144,7 +144,7 @@ struct eqs_ctx {
     std::vector<std::vector<MgLevel>> mg;   // per set: the level table (host copy)
     MgLevel *d_mg = nullptr;                // device: nsets x kMgMaxLevels
     void *mg_ws = nullptr;
-    std::map<int, std::array<hipGraphExec_t, 4>> graphs_mg;  // per set: 2^k preconditioned iterations
+    std::map<std::pair<int, int>, std::array<hipGraphExec_t, 4>> graphs_mg;  // per run: 2^k preconditioned iterations
 };
 
 namespace {
@@ -305,6 +305,9 @@ void fill_desc(eqs_ctx *c, int s) {
     d.sigma_tol[0] = sigma_tol(false);
     d.sigma_tol[1] = sigma_tol(true);
     d.sig_redo = env_int("EQS_SIGMA_REDO", 0) != 0 ? 1 : 0;
+    const bool mg = c->d_mg && s < (int)c->mg.size() && !c->mg[s].empty();
+    d.mg = mg ? c->d_mg + (size_t)s * kMgMaxLevels : nullptr;
+    d.mg_levels = mg ? (int)c->mg[s].size() : 0;
 }
 
 LaunchSets launch_table(eqs_ctx *c, int first, int count, int *total, int *total_flat) {
@@ -555,14 +558,8 @@ Run make_run(eqs_ctx *c, int first, int count, bool trans);
 
 int run_fp64(Run &R) {
     int rc;
-    // forward FP64 solves with the multigrid preconditioner: one set at a time
-    if (R.c->precond == EQS_PRECOND_MG && !R.trans) {
-        for (int i = 0; i < R.count; ++i) {
-            Run Q = make_run(R.c, R.first + i, 1, false);
-            if ((rc = run_fp64_mg(Q))) return rc;
-        }
-        return 0;
-    }
+    // FP64 solves with the multigrid preconditioner: all the run's sets together
+    if (R.c->precond == EQS_PRECOND_MG && !R.trans) return run_fp64_mg(R);
     // tiny sets: the whole solve in one launch, one block per set
     int max_n = 0;
     for (int i = 0; i < R.count; ++i) max_n = std::max(max_n, R.c->sets[R.first + i].n);
@@ -785,40 +782,42 @@ void clear_graphs(eqs_ctx *c) {
 
 // ------------------------------------------------------------------ multigrid-preconditioned iteration
 
-// z = B^-1 r for the run's (single) set: one V-cycle; gated launches do nothing once the
-// set stops iterating.  The finest level goes through the k-march on the set's tiles
-// (its per-cell residual in the set's y buffer, unused by this iteration); the coarser
-// levels through per-cell kernels.
-hipError_t mg_vcycle(const Run &R, const double *r, double *z, bool gated, hipStream_t stream) {
+// z = B^-1 r for every set of the run: one V-cycle each, the sets sharing every launch (which: the
+// input and output, see launch_mg_restrict); gated launches do nothing for a set that stopped
+// iterating.  The finest level goes through the k-march on the run's tiles (the per-cell residual
+// in each set's y buffer, unused by this iteration); the coarser levels through per-cell kernels
+// that take the sets along blockIdx.y, a set doing its own levels in its own order (a set with fewer
+// levels skips the launches of levels it does not have).
+hipError_t mg_vcycle(const Run &R, int which, bool gated, hipStream_t stream) {
     eqs_ctx *c = R.c;
-    const int s = R.first;
-    const std::vector<MgLevel> &L = c->mg[s];
-    const int nl = (int)L.size();
-    const SetDesc *dd = c->d_desc + s;
-    const MgLevel *lev = c->d_mg + (size_t)s * kMgMaxLevels;
-    double *res = c->sets[s].y;
+    int nl = 0;
+    for (int i = 0; i < R.count; ++i) nl = std::max(nl, (int)c->mg[R.first + i].size());
+    // the largest set's cells on level l among the sets that have level `upto` or more levels
+    auto cells = [&](int l, int need) {
+        int m = 1;
+        for (int i = 0; i < R.count; ++i) {
+            const std::vector<MgLevel> &L = c->mg[R.first + i];
+            if ((int)L.size() >= need) m = std::max(m, L[l].n);
+        }
+        return m;
+    };
+    const SetDesc *dd = c->d_desc + R.first;
+    const MgLevel *lv = c->d_mg + (size_t)R.first * kMgMaxLevels;
+    const int ns = R.count;
+    MgCounts cnt{};
+    for (int i = 0; i < ns; ++i) cnt.n[i] = (int)c->mg[R.first + i].size();
     hipError_t e = hipSuccess;
     if (nl > 1) {
-        e = launch_mg_fine(R.ls, R.ntiles, c->cpt, R.max_nx, lev, r, res, nullptr, c->mgp, gated, stream);
-        if (e == hipSuccess) e = launch_mg_aggregate(dd, lev, L[1].n, res, gated, stream);
+        e = launch_mg_fine(R.ls, lv, cnt, R.ntiles, c->cpt, R.max_nx, which, true, c->mgp, gated, stream);
+        if (e == hipSuccess) e = launch_mg_aggregate(dd, lv, cnt, ns, cells(1, 2), gated, stream);
     }
-    // with EQS_MG_BOTTOM=1 the last coarse level above the coarsest, when small, restricts, sweeps
-    // the coarsest level and prolongs in one launch instead of three (one block: slower on the
-    // benchmark hierarchies, where that level has 7-8 k cells and one block takes its memory
-    // latency eight times over)
-    const bool bottom = nl >= 3 && L[nl - 2].n <= kMgBottomMax && env_int("EQS_MG_BOTTOM", 0) != 0;
-    const int lr = bottom ? nl - 2 : nl - 1;  // levels 1 .. lr-1 restrict on their own
-    for (int l = 1; l + 1 < nl && l < lr && e == hipSuccess; ++l)
-        e = launch_mg_restrict(dd, lev, l, L[l + 1].n, L[l].r, c->mgp, gated, stream);
-    if (e == hipSuccess && bottom)
-        e = launch_mg_bottom(dd, lev, nl - 2, L[nl - 2].n, L[nl - 1].n, c->mgp, gated, stream);
-    else if (e == hipSuccess)
-        e = launch_mg_coarsest(dd, lev, nl - 1, L[nl - 1].n, nl == 1 ? r : L[nl - 1].r, nl == 1 ? z : L[nl - 1].z,
-                               c->mgp, gated, stream);
-    for (int l = bottom ? nl - 3 : nl - 2; l >= 1 && e == hipSuccess; --l)
-        e = launch_mg_prolong(dd, lev, l, L[l].n, L[l].r, L[l].z, c->mgp, gated, stream);
+    for (int l = 1; l + 1 < nl && e == hipSuccess; ++l)
+        e = launch_mg_restrict(dd, lv, cnt, ns, l, cells(l + 1, l + 2), c->mgp, gated, stream);
+    if (e == hipSuccess) e = launch_mg_coarsest(dd, lv, cnt, ns, which, c->mgp, gated, stream);
+    for (int l = nl - 2; l >= 1 && e == hipSuccess; --l)
+        e = launch_mg_prolong(dd, lv, cnt, ns, l, cells(l, l + 2), c->mgp, gated, stream);
     if (nl > 1 && e == hipSuccess)
-        e = launch_mg_fine(R.ls, R.ntiles, c->cpt, R.max_nx, lev, r, nullptr, z, c->mgp, gated, stream);
+        e = launch_mg_fine(R.ls, lv, cnt, R.ntiles, c->cpt, R.max_nx, which, false, c->mgp, gated, stream);
     c->launches += 2 * nl;
     return e;
 }
@@ -834,19 +833,18 @@ hipError_t mg_coarsen_all(eqs_ctx *c, int s) {
     return e;
 }
 
-// one preconditioned BiCGSTAB iteration of the run's (single) set on `stream`
+// one preconditioned BiCGSTAB iteration of the run's sets on `stream`
 hipError_t mg_iteration(Run &R, hipStream_t stream) {
     eqs_ctx *c = R.c;
-    const SetHost &h = c->sets[R.first];
     auto K = [&](Kern k) {
         c->launches++;
         return launch_kernel(k, R.ls, R.ntiles, R.nflat, c->cpt, R.max_nx, false, false, stream, nullptr, nullptr, 0);
     };
     hipError_t e = K(K_PC_P);
-    if (e == hipSuccess) e = mg_vcycle(R, h.p[0], h.p[1], true, stream);  // p^ = B^-1 p
+    if (e == hipSuccess) e = mg_vcycle(R, 0, true, stream);  // p^ = B^-1 p
     if (e == hipSuccess) e = K(K_PC_V);
     if (e == hipSuccess) e = K(K_PC_S);
-    if (e == hipSuccess) e = mg_vcycle(R, h.s1, h.v[1], true, stream);    // s^ = B^-1 s
+    if (e == hipSuccess) e = mg_vcycle(R, 1, true, stream);  // s^ = B^-1 s
     if (e == hipSuccess) e = K(K_PC_T);
     if (e == hipSuccess) e = K(K_PC_X);
     return e;
@@ -865,7 +863,7 @@ int mg_iterate(Run &R, int C) {
             }
         return 0;
     }
-    auto &slots = c->graphs_mg[R.first];
+    auto &slots = c->graphs_mg[std::make_pair(R.first, R.count)];
     for (int b = 3; b >= 0; --b) {
         while (C >= (1 << b)) {
             if (!slots[b]) {
@@ -889,7 +887,7 @@ int mg_iterate(Run &R, int C) {
                 slots[b] = ex;
             }
             EQS_HIP(hipGraphLaunch(slots[b], c->stream));
-            c->launches += (uint64_t)(5 + 2 * (2 * (int)c->mg[R.first].size())) << b;
+            c->launches += (uint64_t)(5 + 2 * (2 * (int)c->mg[R.first].size())) << b;  // (first set's count)
             C -= 1 << b;
         }
     }
@@ -898,12 +896,14 @@ int mg_iterate(Run &R, int C) {
 
 int run_fp64_mg(Run &R) {
     int rc;
-    if (mg_coarsen_all(R.c, R.first) != hipSuccess) {
-        (void)hipGetLastError();
-        R.c->broken = true;
-        return EQS_ERR_HIP;
+    for (int i = 0; i < R.count; ++i) {
+        if (mg_coarsen_all(R.c, R.first + i) != hipSuccess) {
+            (void)hipGetLastError();
+            R.c->broken = true;
+            return EQS_ERR_HIP;
+        }
+        R.c->launches += R.c->mg[R.first + i].size();
     }
-    R.c->launches += R.c->mg[R.first].size();
     if ((rc = R.L(K_SETUP))) return rc;
     if ((rc = R.readback())) return rc;
     R.reset_rate();
@@ -1373,7 +1373,11 @@ int eqsolve_debug_precond(eqs_ctx *c, int32_t set, const double *const diag[7], 
     int rc = upload_desc(c, set, 1);
     if (rc) return rc;
     const Run R = make_run(c, set, 1, false);
-    if (mg_coarsen_all(c, set) != hipSuccess || mg_vcycle(R, r, z, false, c->stream) != hipSuccess ||
+    // through the set's own r and t buffers (the V-cycle takes its vectors from the set table)
+    const size_t bytes = (size_t)c->sets[set].n * sizeof(double);
+    if (hipMemcpyAsync(c->sets[set].r, r, bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
+        mg_coarsen_all(c, set) != hipSuccess || mg_vcycle(R, 2, false, c->stream) != hipSuccess ||
+        hipMemcpyAsync(z, c->sets[set].t, bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess) {
         (void)hipGetLastError();
         c->broken = true;

@@ -79,6 +79,8 @@ struct SolveState {
     int32_t sig_redos;   // such reruns over the whole solve
 };
 
+struct MgLevel;
+
 struct SetDesc {
     int32_t nx, ny, nz, plane, n;
     // march tiling: S segments of Q = kBlock*cpt cells per plane, KC planes per chunk
@@ -88,6 +90,9 @@ struct SetDesc {
     // segment-fastest (ford = 1)
     int32_t fS, fntiles, ford;
     int32_t sig_redo;   // a sigma mismatch reruns the step (1) or restarts the iteration (0)
+    // multigrid: the set's level table (device) and its number of levels (0: none)
+    const MgLevel *mg;
+    int32_t mg_levels, mg_pad;
     // pointwise kernels: nflat blocks, block b takes chunks b, b + nflat, ... of kFlatChunk cells
     int32_t nflat;
     int32_t mode;
@@ -137,6 +142,11 @@ struct MgLevel {
     double *r, *z;  // right-hand side and result of the level's V-cycle (levels >= 1)
     float *a32[7];  // level 0: the system's coefficients rounded to FP32, the operator the
                     // V-cycle takes on that level (and coarsens from); arithmetic stays FP64
+};
+// number of multigrid levels of each set of a launch (a kernel argument: no load before the first
+// level-table access)
+struct MgCounts {
+    int32_t n[kMaxSets];
 };
 struct MgParams {
     double omega;         // damped-Jacobi weight

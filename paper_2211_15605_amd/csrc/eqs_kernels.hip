@@ -2342,13 +2342,28 @@ __device__ __forceinline__ void mg_restrict_body(const MgLevel &F, const MgLevel
     }
 }
 
-__global__ void __launch_bounds__(kBlock) mg_restrict_kernel(const SetDesc *d, const MgLevel *lev, int l,
-                                                             const double *rin, MgParams prm, int gated) {
+// The coarse-level kernels take the sets of a launch along blockIdx.y (set blockIdx.y of the
+// table `desc`, its level table at lev + blockIdx.y * kMgMaxLevels, its level count in cnt); a set
+// without the level returns at once.
+
+// a V-cycle's input (which = 0: p, 1: s, 2: the diagnostic's r) and output (p^, s^, t)
+__device__ __forceinline__ const double *mg_in(const SetDesc &d, int which) {
+    return which == 0 ? d.p[0] : (which == 1 ? d.s1 : d.r);
+}
+__device__ __forceinline__ double *mg_out(const SetDesc &d, int which) {
+    return which == 0 ? d.p[1] : (which == 1 ? d.v[1] : d.t);
+}
+
+__global__ void __launch_bounds__(kBlock) mg_restrict_kernel(const SetDesc *desc, const MgLevel *levs, MgCounts cnt,
+                                                             int l, MgParams prm, int gated) {
+    if (l > cnt.n[blockIdx.y] - 2) return;
+    const SetDesc *d = desc + blockIdx.y;
+    const MgLevel *lev = levs + (size_t)blockIdx.y * kMgMaxLevels;
     if (gated && !d->st->active) return;
     const MgLevel F = lev[l], C = lev[l + 1];
     const LevCoef a = mg_coef(F, l, prm.coarse_sym && d->st->sym != 0);
     double *cr = C.r;
-    mg_restrict_body(F, C, a, rin, prm.omega, (int)(blockIdx.x * kBlock + threadIdx.x), (int)(gridDim.x * kBlock),
+    mg_restrict_body(F, C, a, F.r, prm.omega, (int)(blockIdx.x * kBlock + threadIdx.x), (int)(gridDim.x * kBlock),
                      [&](int cc, double v) { st(cr, cc, v); });
 }
 
@@ -2370,14 +2385,16 @@ __device__ __forceinline__ void mg_prolong_body(const MgLevel &F, const MgLevel 
     }
 }
 
-__global__ void __launch_bounds__(kBlock) mg_prolong_kernel(const SetDesc *d, const MgLevel *lev, int l,
-                                                            const double *rin, double *zout, MgParams prm,
-                                                            int gated) {
+__global__ void __launch_bounds__(kBlock) mg_prolong_kernel(const SetDesc *desc, const MgLevel *levs, MgCounts cnt,
+                                                            int l, MgParams prm, int gated) {
+    if (l > cnt.n[blockIdx.y] - 2) return;
+    const SetDesc *d = desc + blockIdx.y;
+    const MgLevel *lev = levs + (size_t)blockIdx.y * kMgMaxLevels;
     if (gated && !d->st->active) return;
     const MgLevel F = lev[l], C = lev[l + 1];
     const LevCoef a = mg_coef(F, l, prm.coarse_sym && d->st->sym != 0);
     const double *e = C.z;
-    mg_prolong_body(F, C, a, rin, zout, prm.omega, prm.gamma, (int)(blockIdx.x * kBlock + threadIdx.x),
+    mg_prolong_body(F, C, a, F.r, F.z, prm.omega, prm.gamma, (int)(blockIdx.x * kBlock + threadIdx.x),
                     (int)(gridDim.x * kBlock), [&](int cc) { return ld(e, cc); });
 }
 
@@ -2433,37 +2450,21 @@ __device__ __forceinline__ int mg_coarsest_body(const MgLevel &F, const LevCoef 
     return cur;
 }
 
-__global__ void __launch_bounds__(kMgCoarseThreads) mg_coarsest_kernel(const SetDesc *d, const MgLevel *lev, int l,
-                                                                       const double *rin, double *zout,
-                                                                       MgParams prm, int gated) {
+// one block per set (set blockIdx.x), each on its own coarsest level
+__global__ void __launch_bounds__(kMgCoarseThreads) mg_coarsest_kernel(const SetDesc *desc, const MgLevel *levs,
+                                                                       MgCounts cnt, int which, MgParams prm,
+                                                                       int gated) {
+    const SetDesc *d = desc + blockIdx.x;
     if (gated && !d->st->active) return;
     __shared__ double zb[2][kMgCoarsestMax];
+    const MgLevel *lev = levs + (size_t)blockIdx.x * kMgMaxLevels;
+    const int l = cnt.n[blockIdx.x] - 1;
     const MgLevel F = lev[l];
+    const double *rin = l == 0 ? mg_in(*d, which) : F.r;
+    double *zout = l == 0 ? mg_out(*d, which) : F.z;
     const LevCoef a = mg_coef(F, l, prm.coarse_sym && d->st->sym != 0);
     const int cur = mg_coarsest_body(F, a, prm.omega, prm.coarse_sweeps, zb, [&](int c) { return ld(rin, c); });
     for (int c = threadIdx.x; c < F.n; c += kMgCoarseThreads) st(zout, c, zb[cur][c]);
-}
-
-// The bottom of the V-cycle in one block: level l's restriction into the coarsest level l + 1
-// (its right-hand side kept in LDS), the coarsest level's sweeps, and level l's prolongation with
-// its smoothing step -- the operations of the three kernels above, in their order, for a level l
-// of at most kMgBottomMax cells (two launches fewer per V-cycle, where those small grids are
-// latency-bound).
-__global__ void __launch_bounds__(kMgCoarseThreads) mg_bottom_kernel(const SetDesc *d, const MgLevel *lev, int l,
-                                                                     MgParams prm, int gated) {
-    if (gated && !d->st->active) return;
-    __shared__ double zb[2][kMgCoarsestMax];
-    __shared__ double rc[kMgCoarsestMax];
-    const MgLevel F = lev[l], C = lev[l + 1];
-    const bool sym = prm.coarse_sym && d->st->sym != 0;
-    const LevCoef af = mg_coef(F, l, sym), ac = mg_coef(C, l + 1, sym);
-    mg_restrict_body(F, C, af, F.r, prm.omega, (int)threadIdx.x, kMgCoarseThreads,
-                     [&](int cc, double v) { rc[cc] = v; });
-    __syncthreads();
-    const int cur = mg_coarsest_body(C, ac, prm.omega, prm.coarse_sweeps, zb, [&](int c) { return rc[c]; });
-    const double *e = zb[cur];
-    mg_prolong_body(F, C, af, F.r, F.z, prm.omega, prm.gamma, (int)threadIdx.x, kMgCoarseThreads,
-                    [&](int cc) { return e[cc]; });
 }
 
 // ---- finest level through the k-march (operands staged in LDS like the
@@ -2556,16 +2557,19 @@ struct PhMgProlong {
 };
 
 template <int CPT, int H>
-__global__ void __launch_bounds__(kBlock) mg_resid0_kernel(LaunchSets ls, const MgLevel *lev, const double *rin,
-                                                           double *res, MgParams prm, int gated) {
+__global__ void __launch_bounds__(kBlock) mg_resid0_kernel(LaunchSets ls, const MgLevel *levs, MgCounts cnt, int which,
+                                                           MgParams prm, int gated) {
     const TileRef tr = locate<false>(ls);
+    const int si = (int)(tr.d - ls.desc);
+    if (cnt.n[si] < 2) return;
     const SetDesc &d = *tr.d;
+    const MgLevel *lev = levs + (size_t)si * kMgMaxLevels;
     if (gated && !d.st->active) return;
     PhMgResid ph;
     for (int k = 0; k < 7; ++k) ph.a[k] = lev[0].a32[k];
     ph.sym = d.st->sym != 0;
-    ph.rin = rin;
-    ph.res = res;
+    ph.rin = mg_in(d, which);
+    ph.res = d.y;  // the per-cell residual (the y buffer is unused by this iteration)
     ph.w = prm.omega;
     ph.nx = d.nx;
     ph.P = d.plane;
@@ -2575,17 +2579,20 @@ __global__ void __launch_bounds__(kBlock) mg_resid0_kernel(LaunchSets ls, const 
 }
 
 template <int CPT, int H>
-__global__ void __launch_bounds__(kBlock) mg_prolong0_kernel(LaunchSets ls, const MgLevel *lev, const double *rin,
-                                                             double *zout, MgParams prm, int gated) {
+__global__ void __launch_bounds__(kBlock) mg_prolong0_kernel(LaunchSets ls, const MgLevel *levs, MgCounts cnt,
+                                                             int which, MgParams prm, int gated) {
     const TileRef tr = locate<false>(ls);
+    const int si = (int)(tr.d - ls.desc);
+    if (cnt.n[si] < 2) return;
     const SetDesc &d = *tr.d;
+    const MgLevel *lev = levs + (size_t)si * kMgMaxLevels;
     if (gated && !d.st->active) return;
     PhMgProlong ph;
     for (int k = 0; k < 7; ++k) ph.a[k] = lev[0].a32[k];
     ph.sym = d.st->sym != 0;
-    ph.rin = rin;
+    ph.rin = mg_in(d, which);
     ph.e = lev[1].z;
-    ph.zout = zout;
+    ph.zout = mg_out(d, which);
     ph.w = prm.omega;
     ph.g = prm.gamma;
     ph.nx = d.nx;
@@ -2599,10 +2606,14 @@ __global__ void __launch_bounds__(kBlock) mg_prolong0_kernel(LaunchSets ls, cons
 
 // level 1's right-hand side: the sum of res over each aggregate of level 0, in
 // cell-index order (i fastest, then j, then k), one thread per aggregate
-__global__ void __launch_bounds__(kBlock) mg_aggregate_kernel(const SetDesc *d, const MgLevel *lev, const double *res,
+__global__ void __launch_bounds__(kBlock) mg_aggregate_kernel(const SetDesc *desc, const MgLevel *levs, MgCounts cnt,
                                                               int gated) {
 #pragma clang fp contract(off)
+    if (cnt.n[blockIdx.y] < 2) return;
+    const SetDesc *d = desc + blockIdx.y;
+    const MgLevel *lev = levs + (size_t)blockIdx.y * kMgMaxLevels;
     if (gated && !d->st->active) return;
+    const double *res = d->y;
     const MgLevel F = lev[0], C = lev[1];
     const int nx = F.nx, ny = F.ny, nz = F.nz, cx = C.nx, cy = C.ny;
     for (int cc = blockIdx.x * kBlock + threadIdx.x; cc < C.n; cc += gridDim.x * kBlock) {
@@ -2813,33 +2824,27 @@ hipError_t launch_mg_coarsen(const SetDesc *d, const MgLevel *lev, int l, int nc
     return hipGetLastError();
 }
 
-hipError_t launch_mg_restrict(const SetDesc *d, const MgLevel *lev, int l, int nc, const double *rin, MgParams prm,
-                              bool gated, hipStream_t stream) {
-    // eight lanes per coarse cell
-    hipLaunchKernelGGL(mg_restrict_kernel, mg_grid(8 * nc), dim3(kBlock), 0, stream, d, lev, l, rin, prm,
-                       gated ? 1 : 0);
-    return hipGetLastError();
-}
-
-hipError_t launch_mg_coarsest(const SetDesc *d, const MgLevel *lev, int l, int n, const double *rin, double *zout,
+hipError_t launch_mg_restrict(const SetDesc *desc, const MgLevel *levs, const MgCounts &cnt, int nsets, int l, int nc,
                               MgParams prm, bool gated, hipStream_t stream) {
-    if (n > kMgCoarsestMax) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(mg_coarsest_kernel, dim3(1), dim3(kMgCoarseThreads), 0, stream, d, lev, l, rin, zout, prm,
-                       gated ? 1 : 0);
+    // eight lanes per coarse cell of the largest set's level l + 1
+    dim3 grid = mg_grid(8 * nc);
+    grid.y = (unsigned)nsets;
+    hipLaunchKernelGGL(mg_restrict_kernel, grid, dim3(kBlock), 0, stream, desc, levs, cnt, l, prm, gated ? 1 : 0);
     return hipGetLastError();
 }
 
-hipError_t launch_mg_bottom(const SetDesc *d, const MgLevel *lev, int l, int n, int nc, MgParams prm, bool gated,
-                            hipStream_t stream) {
-    if (n > kMgBottomMax || nc > kMgCoarsestMax || l < 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(mg_bottom_kernel, dim3(1), dim3(kMgCoarseThreads), 0, stream, d, lev, l, prm, gated ? 1 : 0);
+hipError_t launch_mg_coarsest(const SetDesc *desc, const MgLevel *levs, const MgCounts &cnt, int nsets, int which,
+                              MgParams prm, bool gated, hipStream_t stream) {
+    hipLaunchKernelGGL(mg_coarsest_kernel, dim3((unsigned)nsets), dim3(kMgCoarseThreads), 0, stream, desc, levs, cnt,
+                       which, prm, gated ? 1 : 0);
     return hipGetLastError();
 }
 
-hipError_t launch_mg_prolong(const SetDesc *d, const MgLevel *lev, int l, int n, const double *rin, double *zout,
+hipError_t launch_mg_prolong(const SetDesc *desc, const MgLevel *levs, const MgCounts &cnt, int nsets, int l, int n,
                              MgParams prm, bool gated, hipStream_t stream) {
-    hipLaunchKernelGGL(mg_prolong_kernel, mg_grid(n), dim3(kBlock), 0, stream, d, lev, l, rin, zout, prm,
-                       gated ? 1 : 0);
+    dim3 grid = mg_grid(n);
+    grid.y = (unsigned)nsets;
+    hipLaunchKernelGGL(mg_prolong_kernel, grid, dim3(kBlock), 0, stream, desc, levs, cnt, l, prm, gated ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -2943,24 +2948,26 @@ hipError_t allow_fused_lds(size_t bytes) {
         else hipLaunchKernelGGL(KERN, GRID, BLOCK, LDS, stream, __VA_ARGS__);                   \
     } while (0)
 
-hipError_t launch_mg_fine(const LaunchSets &ls, int ntiles, int cpt, int max_nx, const MgLevel *lev, const double *rin,
-                          double *res, double *zout, MgParams prm, bool gated, hipStream_t stream) {
+hipError_t launch_mg_fine(const LaunchSets &ls, const MgLevel *levs, const MgCounts &cnt, int ntiles, int cpt,
+                          int max_nx, int which, bool resid, MgParams prm, bool gated, hipStream_t stream) {
     const dim3 grid(ntiles), block(kBlock);
     const int h = halo_slots(max_nx, kBlock);
     if (h < 0 || (cpt != 1 && cpt != 2)) return hipErrorInvalidValue;
     const size_t lds64 = march_lds_bytes(cpt, max_nx, 8);
-    if (res)
-        EQS_DISPATCH(cpt, h, hipLaunchKernelGGL((mg_resid0_kernel<C, HH>), grid, block, lds64, stream, ls, lev, rin,
-                                                res, prm, gated ? 1 : 0));
+    if (resid)
+        EQS_DISPATCH(cpt, h, hipLaunchKernelGGL((mg_resid0_kernel<C, HH>), grid, block, lds64, stream, ls, levs, cnt,
+                                                which, prm, gated ? 1 : 0));
     else
-        EQS_DISPATCH(cpt, h, hipLaunchKernelGGL((mg_prolong0_kernel<C, HH>), grid, block, lds64, stream, ls, lev, rin,
-                                                zout, prm, gated ? 1 : 0));
+        EQS_DISPATCH(cpt, h, hipLaunchKernelGGL((mg_prolong0_kernel<C, HH>), grid, block, lds64, stream, ls, levs,
+                                                cnt, which, prm, gated ? 1 : 0));
     return hipGetLastError();
 }
 
-hipError_t launch_mg_aggregate(const SetDesc *d, const MgLevel *lev, int nc, const double *res, bool gated,
-                               hipStream_t stream) {
-    hipLaunchKernelGGL(mg_aggregate_kernel, mg_grid(nc), dim3(kBlock), 0, stream, d, lev, res, gated ? 1 : 0);
+hipError_t launch_mg_aggregate(const SetDesc *desc, const MgLevel *levs, const MgCounts &cnt, int nsets, int nc,
+                               bool gated, hipStream_t stream) {
+    dim3 grid = mg_grid(nc);
+    grid.y = (unsigned)nsets;
+    hipLaunchKernelGGL(mg_aggregate_kernel, grid, dim3(kBlock), 0, stream, desc, levs, cnt, gated ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -35,31 +35,31 @@ enum Kern {
     K_TRANSPOSE // the six neighbour coefficients of A^T into the set's scaled-coefficient buffers
 };
 
-// multigrid kernels of set `set` (d: its device table entry, lev: its device level table)
+// multigrid setup of set `set` (d: its device table entry, lev: its device level table)
 hipError_t launch_mg_symcheck(const SetDesc *d, int n, int on, hipStream_t stream);
 hipError_t launch_mg_round0(const SetDesc *d, const MgLevel *lev, int n, hipStream_t stream);
 hipError_t launch_mg_coarsen(const SetDesc *d, const MgLevel *lev, int l, int nc, hipStream_t stream);
-// V-cycle: restriction from level l to l+1 (nc = cells of level l+1); rin = level l's right-hand side
-hipError_t launch_mg_restrict(const SetDesc *d, const MgLevel *lev, int l, int nc, const double *rin, MgParams prm,
-                              bool gated, hipStream_t stream);
-// coarsest level l (n cells, at most kMgCoarsestMax): coarse_sweeps damped-Jacobi sweeps from zero
-constexpr int kMgCoarsestMax = 2048;
-// the bottom of the V-cycle in one block (restriction of a coarse level l >= 1 of at most
-// kMgBottomMax cells, the coarsest level's sweeps, the prolongation of level l)
-constexpr int kMgBottomMax = 16384;
-hipError_t launch_mg_coarsest(const SetDesc *d, const MgLevel *lev, int l, int n, const double *rin, double *zout,
+// The V-cycle over the nsets sets of a launch (desc: the device table entry of its first set, levs:
+// that set's level table, the next sets' following kMgMaxLevels apart, cnt: each set's number of
+// levels; a set without the level returns).
+// which: the V-cycle's input and output, 0: p -> p^, 1: s -> s^, 2: r -> t (diagnostics).
+// restriction from level l to l + 1 (nc: the largest set's cells on level l + 1)
+hipError_t launch_mg_restrict(const SetDesc *desc, const MgLevel *levs, const MgCounts &cnt, int nsets, int l, int nc,
                               MgParams prm, bool gated, hipStream_t stream);
-// finest level through the k-march (the set's tiles): res != NULL: res = r - A z1 per cell;
-// res == NULL: zout = prolongation of level 1's result + one smoothing step
-hipError_t launch_mg_fine(const LaunchSets &ls, int ntiles, int cpt, int max_nx, const MgLevel *lev, const double *rin,
-                          double *res, double *zout, MgParams prm, bool gated, hipStream_t stream);
-// level 1's right-hand side from the per-cell residual of level 0 (nc = cells of level 1)
-hipError_t launch_mg_aggregate(const SetDesc *d, const MgLevel *lev, int nc, const double *res, bool gated,
-                               hipStream_t stream);
-// prolongation of level l+1's result and one smoothing sweep on level l (n = cells of level l)
-hipError_t launch_mg_bottom(const SetDesc *d, const MgLevel *lev, int l, int n, int nc, MgParams prm, bool gated,
-                            hipStream_t stream);
-hipError_t launch_mg_prolong(const SetDesc *d, const MgLevel *lev, int l, int n, const double *rin, double *zout,
+// each set's coarsest level (at most kMgCoarsestMax cells): coarse_sweeps damped-Jacobi sweeps from
+// zero, one block per set
+constexpr int kMgCoarsestMax = 2048;
+hipError_t launch_mg_coarsest(const SetDesc *desc, const MgLevel *levs, const MgCounts &cnt, int nsets, int which,
+                              MgParams prm, bool gated, hipStream_t stream);
+// finest level through the k-march (the launch's tiles): resid: the per-cell residual r - A z1 into
+// each set's y buffer; else the prolongation of level 1's result + one smoothing step
+hipError_t launch_mg_fine(const LaunchSets &ls, const MgLevel *levs, const MgCounts &cnt, int ntiles, int cpt,
+                          int max_nx, int which, bool resid, MgParams prm, bool gated, hipStream_t stream);
+// level 1's right-hand side from the per-cell residual of level 0 (nc: the largest set's level-1 cells)
+hipError_t launch_mg_aggregate(const SetDesc *desc, const MgLevel *levs, const MgCounts &cnt, int nsets, int nc,
+                               bool gated, hipStream_t stream);
+// prolongation of level l + 1's result and one smoothing sweep on level l (n: the largest set's cells)
+hipError_t launch_mg_prolong(const SetDesc *desc, const MgLevel *levs, const MgCounts &cnt, int nsets, int l, int n,
                              MgParams prm, bool gated, hipStream_t stream);
 
 // LDS bytes of the single-sync kernel with nt threads per block (p and s, three planes each of

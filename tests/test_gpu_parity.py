@@ -622,9 +622,8 @@ def test_mg_vcycle_matches_oracle(torch_dev, orc, cfg, shape):
     r = np.random.default_rng(11).standard_normal(g.n)
     rounded = [d.astype(np.float32).astype(np.float64) for d in diags]
     zo, lo = orc.mg_apply(g.shape, rounded, r, O.mg_params(**MG_SMALL))
-    # the bottom levels in one launch or in three; coarse levels read as symmetric where they are
-    # (the pressure-like recipe) or always in full
-    for env in (dict(), dict(EQS_MG_BOTTOM=1), dict(EQS_MG_SYM=0), dict(EQS_MG_CSYM=0)):
+    # coarse levels read as symmetric where they are (the pressure-like recipe) or always in full
+    for env in (dict(), dict(EQS_MG_SYM=0), dict(EQS_MG_CSYM=0)):
         old = {k: os.environ.get(k) for k in env}
         os.environ.update({k: str(v) for k, v in env.items()})
         try:
@@ -688,6 +687,29 @@ def test_mg_batched_equals_sequential_and_statuses(torch_dev, orc):
     assert info["iters"] == 0 and np.array_equal(host(x), xs)
     x, info = ctx.solve(Ds[0], torch.zeros_like(bs[0]), x=torch.ones_like(bs[0]), tol=1e-10)
     assert info["status"] == 0 and not np.any(host(x))
+
+
+def test_mg_batched_mixed_depths(torch_dev, orc):
+    # sets of different hierarchy depths in one batched multigrid call (4 levels, 1 level -- the
+    # whole set is the coarsest level --, 3 levels, 2 levels): each set follows its own V-cycle, the
+    # same bits as solved alone and as the oracle's V-cycle iteration count
+    from oracle import oracle as O
+    torch, dev = torch_dev
+    shapes = [(40, 40, 40), (8, 8, 8), (17, 9, 30), (12, 10, 6)]
+    systems = [manufactured(orc, 2, grid=W.Grid(*sh), set_id=i) for i, sh in enumerate(shapes)]
+    prm = dict(omega=0.8, gamma=1.0, coarse_sweeps=30, coarse_cells=512)
+    ctx = context(shapes)
+    ctx.set_preconditioner("mg", **prm)
+    Ds = [dev_arrays(torch, dev, s_[1]) for s_ in systems]
+    bs = [dev_arrays(torch, dev, [s_[2]])[0] for s_ in systems]
+    xb, infos = ctx.solve_batched(Ds, bs, tol=1e-11, maxit=500)
+    for i, s_ in enumerate(systems):
+        xi, info = ctx.solve(Ds[i], bs[i], tol=1e-11, maxit=500, set_id=i)
+        assert np.array_equal(host(xi), host(xb[i])) and info == infos[i], i
+        assert orc.rel_residual(s_[0].shape, s_[1], s_[2], host(xb[i])) <= 1e-11
+        _, oinfo = orc.bicgstab_mg(s_[0].shape, s_[1], s_[2], tol=1e-11, maxit=500, params=O.mg_params(**prm))
+        assert abs(infos[i]["iters"] - oinfo["iters"]) <= 2, (i, infos[i], oinfo)
+    ctx.close()
 
 
 @pytest.mark.parametrize("cfg,shape", [(0, (20, 30, 15)), (1, (32, 64, 32)), (2, (25, 48, 24))])
