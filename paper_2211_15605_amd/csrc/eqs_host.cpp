@@ -843,7 +843,11 @@ hipError_t mg_iteration(Run &R, hipStream_t stream) {
     hipError_t e = K(K_PC_P);
     if (e == hipSuccess) e = mg_vcycle(R, 0, true, stream);  // p^ = B^-1 p
     if (e == hipSuccess) e = K(K_PC_V);
-    if (e == hipSuccess) e = K(K_PC_S);
+    // s = r - alpha v: the s-cycle's residual pass forms it for sets with a finest-level pass; the
+    // pointwise kernel only for single-level sets
+    bool single = false;
+    for (int i = 0; i < R.count; ++i) single = single || c->mg[R.first + i].size() < 2;
+    if (e == hipSuccess && single) e = K(K_PC_S);
     if (e == hipSuccess) e = mg_vcycle(R, 1, true, stream);  // s^ = B^-1 s
     if (e == hipSuccess) e = K(K_PC_T);
     if (e == hipSuccess) e = K(K_PC_X);

@@ -2473,26 +2473,33 @@ __global__ void __launch_bounds__(kMgCoarseThreads) mg_coarsest_kernel(const Set
 // per-cell kernels above (an absent neighbour's coefficient is zero, so its
 // term subtracts an exact zero).
 
-// q = r - A z1 with z1 = omega D^-1 r, per cell (summed over aggregates by mg_aggregate_kernel)
+// q = r - A z1 with z1 = omega D^-1 r, per cell (summed over aggregates by mg_aggregate_kernel).
+// With sfused the V-cycle's input is the iteration's s = r - alpha v, formed here from r and v (the
+// operation of pc_s_kernel, the same bits) on every cell the pass reads, and stored for the own
+// cells (the prolongation and the products read it later): one pass less per iteration.
 struct PhMgResid {
     static constexpr int NV = 1;
-    struct Raw { double r, ap; };
+    struct Raw { double r, v, ap; };
     struct Aux { double r, ap; };
     struct Pre { Coef6<float, false> c; };  // level 0's FP32 coefficients, widened in use
     const float *a[7];
-    const double *rin;
-    double *res;
-    double w;
-    bool sym;
+    const double *rin, *vin;
+    double *res, *sout;
+    double w, al;
+    bool sym, sfused;
     int nx, P, ncell;
-    __device__ __forceinline__ Raw load(int idx, int, int) const { return Raw{ld(rin, idx), ld(a[0], idx)}; }
+    __device__ __forceinline__ Raw load(int idx, int, int) const {
+        return Raw{ld(rin, idx), sfused ? ld(vin, idx) : 0.0, ld(a[0], idx)};
+    }
+    __device__ __forceinline__ double rval(const Raw &v) const { return sfused ? fma(-al, v.v, v.r) : v.r; }
     __device__ __forceinline__ double zval(const Raw &v) const {
 #pragma clang fp contract(off)
-        return w * v.r / v.ap;
+        return w * rval(v) / v.ap;
     }
-    __device__ __forceinline__ double own(const Raw &v, int, Aux &ax) {
-        ax.r = v.r;
+    __device__ __forceinline__ double own(const Raw &v, int idx, Aux &ax) {
+        ax.r = rval(v);
         ax.ap = v.ap;
+        if (sfused) st(sout, idx, ax.r);
         return zval(v);
     }
     __device__ __forceinline__ double halo(const Raw &v) const { return zval(v); }
@@ -2568,7 +2575,12 @@ __global__ void __launch_bounds__(kBlock) mg_resid0_kernel(LaunchSets ls, const 
     PhMgResid ph;
     for (int k = 0; k < 7; ++k) ph.a[k] = lev[0].a32[k];
     ph.sym = d.st->sym != 0;
-    ph.rin = mg_in(d, which);
+    // the s-cycle of the iteration forms s = r - alpha v itself (pc_s_kernel skips such sets)
+    ph.sfused = which == 1;
+    ph.rin = ph.sfused ? d.r : mg_in(d, which);
+    ph.vin = d.v[0];
+    ph.sout = d.s1;
+    ph.al = d.st->alpha;
     ph.res = d.y;  // the per-cell residual (the y buffer is unused by this iteration)
     ph.w = prm.omega;
     ph.nx = d.nx;
@@ -2723,12 +2735,13 @@ __global__ void __launch_bounds__(kBlock) pc_prod_kernel(LaunchSets ls, int tste
     }
 }
 
-// s = r - alpha v
+// s = r - alpha v (only for sets whose V-cycle has no finest-level pass, i.e. a single level: the
+// others form s in the V-cycle's residual pass)
 __global__ void __launch_bounds__(kBlock) pc_s_kernel(LaunchSets ls) {
     const TileRef tr = locate<true>(ls);
     const SetDesc &d = *tr.d;
     const SolveState *st_ = d.st;
-    if (!st_->active) return;
+    if (!st_->active || d.mg_levels >= 2) return;
     const double al = st_->alpha;
     const double *r = d.r, *v = d.v[0];
     double *s = d.s1;
