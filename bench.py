@@ -15,7 +15,10 @@ another in plain FP64 are timed beside them (untimed by the step clock).
   roofline   the dominant kernel (the FP64 single-sync step, batched launch):
              algorithmic bytes per launch / mean launch time from HIP events on
              the solver's stream, against 8 TB/s; traffic from the committed
-             rocprofv3 FETCH_SIZE / WRITE_SIZE record of the same code object
+             rocprofv3 FETCH_SIZE / WRITE_SIZE record of the same code object;
+             attainable: the rate of a plain streaming kernel with the same words
+             per cell over the same cells (the practical ceiling), and the
+             step's fraction of it
   cpu_baseline  the CPU oracle (plain C, OpenMP) solving the same systems; its
              solutions also give each GPU result's error and Eq. (6) digits
 
@@ -146,6 +149,42 @@ def measured_traffic(workload, kern):
     if rec.get("kernel_code_sha256") != kernel_code_digest(rec.get("symbol", "")):
         return None
     return rec["bytes_per_launch"]
+
+
+def stream_ceiling(cells, nreads, reps=10):
+    """The rate (GB/s) of the library's plain streaming kernel with the step's byte mix (nreads FP64
+    reads and 5 FP64 writes per cell, nontemporal stores) over `cells` cells: the practical ceiling
+    against which the step's own rate is read.  Mean over `reps` back-to-back launches, timed with
+    HIP events on torch's current stream (the stream the kernel is launched on)."""
+    import torch
+    from paper_2211_15605_amd import binding
+    buf = torch.zeros((nreads + 5, cells), dtype=torch.float64, device="cuda")
+    ins = [buf[k].data_ptr() for k in range(nreads)]
+    outs = [buf[nreads + w].data_ptr() for w in range(5)]
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def launch():
+        rc = binding.eqsolve_debug_stream(ins, outs, cells, 1, stream)
+        if rc != 0:
+            raise RuntimeError("eqsolve_debug_stream: %s" % binding.strerror(rc))
+
+    for _ in range(3):
+        launch()
+    torch.cuda.synchronize()
+    # back-to-back launches between one event pair, as the step's launches follow each other
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        launch()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del buf
+    torch.cuda.empty_cache()
+    return {"value": (nreads + 5) * 8 * cells / (ms * 1e-3) / 1e9, "unit": "GB/s", "mean_launch_ms": ms,
+            "kernel": "plain streaming kernel, %d reads + 5 writes per cell (FP64, nontemporal stores, "
+                      "256-thread blocks, one cell per thread)" % nreads,
+            "cells": cells}
 
 
 def mg_params_for(cfg):
@@ -514,6 +553,10 @@ def gpu_leg(args, cfg_id, steps=None, warmup=None, with_mg=True):
         "layout": c64.layout(),
         "cells": n,
     }
+    # what a plain kernel streaming the same words per cell reaches over the same cells
+    att = stream_ceiling(n, kw - 5)
+    att["frac"] = achieved / att["value"]
+    res["roofline"]["attainable"] = att
     if with_mg:
         tmg, (xmg, img), mgp = time_mg(Context, [g.shape], lambda cm: cm.solve(D, b, torch.zeros_like(b), tol=tol,
                                                                                maxit=maxit, check=False), cfg_id)
@@ -655,6 +698,10 @@ def gpu_leg_batched(args):
     sols = {"fp64": [x.cpu().numpy() for x in x64], "fp32_refine": [x.cpu().numpy() for x in x32]}
     del x64, x32
     c32.close()
+    # what a plain kernel streaming the same words per cell reaches over the launch's cells
+    att = stream_ceiling(sum(n_all), kw - 5)
+    att["frac"] = achieved / att["value"]
+    res["roofline"]["attainable"] = att
     if not args.no_mg:
         tmg, (xmg, img), mgp = time_mg(Context, grids,
                                        lambda cm: cm.solve_batched(Ds, bs, tol=tol, maxit=maxit, check=False),

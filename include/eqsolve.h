@@ -315,6 +315,22 @@ int eqsolve_debug_profile(eqs_ctx *ctx, int32_t kind_mask, int32_t every);
 int eqsolve_debug_kernel_stats(const eqs_ctx *ctx, int32_t kind, int32_t fp32, int64_t *count,
                                double *total_ms);
 
+/*
+ * Diagnostics, for reading the single-sync step's HBM rate: one launch of a
+ * plain pointwise kernel over n cells that reads nr FP64 device arrays
+ * in[0..nr) and writes nw FP64 device arrays out[0..nw), every word once and
+ * coalesced (no stencil, halo, LDS or barrier); out[w][i] = w + sum_k (k+1)
+ * in[k][i].  nr = 13 or 11 with nw = 5 is the per-cell mix of the step's
+ * general or symmetric form; nontemporal != 0 writes with nontemporal stores,
+ * as the step does.  Its rate is the practical streaming ceiling for those
+ * words on the device.  in and out are host arrays of device pointers, each
+ * array n values, no output aliasing an input; stream is a hipStream_t (NULL:
+ * the default stream); the call enqueues and returns.  Returns EQS_OK,
+ * EQS_ERR_ARG (null pointers, n < 1, another mix, aliasing) or EQS_ERR_HIP.
+ */
+int eqsolve_debug_stream(const double *const *in, int32_t nr, double *const *out, int32_t nw, int64_t n,
+                         int32_t nontemporal, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

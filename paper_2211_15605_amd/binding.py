@@ -29,7 +29,7 @@ PRECISIONS = {"fp64": EQS_FP64, "fp32_refine": EQS_FP32_REFINE, "fp32": EQS_FP32
 SYMBOLS = ("eqsolve_create", "eqsolve_solve", "eqsolve_solve_batched", "eqsolve_adjoint", "eqsolve_apply",
            "eqsolve_destroy", "eqsolve_strerror", "eqsolve_autotune", "eqsolve_debug_layout",
            "eqsolve_debug_profile", "eqsolve_debug_kernel_stats", "eqsolve_set_preconditioner",
-           "eqsolve_debug_precond", "eqsolve_solve_noalloc", "eqsolve_set_step_form",
+           "eqsolve_debug_precond", "eqsolve_solve_noalloc", "eqsolve_set_step_form", "eqsolve_debug_stream",
            "eqsimple_create", "eqsimple_form_momentum", "eqsimple_form_pressure", "eqsimple_correct",
            "eqsimple_iterate", "eqsimple_step", "eqsimple_set_pressure_preconditioner", "eqsimple_destroy")
 KERNEL_KINDS = {"setup": 0, "recheck": 1, "report": 2, "k1": 3, "k2": 4, "k3": 5, "cast": 6, "outer": 7,
@@ -130,6 +130,9 @@ def load(path: str | None = None):
         L.eqsolve_solve_noalloc.restype = ctypes.c_int
         L.eqsolve_set_step_form.argtypes = [VP, ctypes.c_int32]
         L.eqsolve_set_step_form.restype = ctypes.c_int
+        L.eqsolve_debug_stream.argtypes = [VPP, ctypes.c_int32, VPP, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
+                                           VP]
+        L.eqsolve_debug_stream.restype = ctypes.c_int
         D3 = ctypes.POINTER(ctypes.c_double)
         L.eqsimple_create.argtypes = [ctypes.POINTER(VP), ctypes.POINTER(EqsBox), ctypes.c_int32, VP]
         L.eqsimple_form_momentum.argtypes = [VP, VPP, VP, VPP, VPP, VPP, VPP, D3]
@@ -238,6 +241,13 @@ def eqsolve_debug_precond(h, set_id, diag_ptrs, r_ptr, z_ptr):
     lv = ctypes.c_int32(0)
     rc = load().eqsolve_debug_precond(h, int(set_id), dp, VP(r_ptr), VP(z_ptr), ctypes.byref(lv))
     return rc, lv.value
+
+
+def eqsolve_debug_stream(in_ptrs, out_ptrs, n, nontemporal, stream):
+    ip, keep_i = ptr_array(in_ptrs)
+    op, keep_o = ptr_array(out_ptrs)
+    return load().eqsolve_debug_stream(ip, len(in_ptrs), op, len(out_ptrs), int(n), int(bool(nontemporal)),
+                                       VP(stream) if stream else None)
 
 
 def eqsolve_debug_layout(h, set_id):

@@ -16,7 +16,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libeqsolve.so")
-SOURCES = ["eqs_kernels.hip", "eqs_host.cpp", "eqs_noalloc.hip", "simple_kernels.hip", "simple_host.cpp"]
+SOURCES = ["eqs_kernels.hip", "eqs_host.cpp", "eqs_noalloc.hip", "eqs_probe.hip", "simple_kernels.hip", "simple_host.cpp"]
 ARCH = os.environ.get("EQS_OFFLOAD_ARCH", "gfx950")
 
 

@@ -87,3 +87,21 @@ def test_noalloc_argument_and_size_errors_without_device(lib):
     assert f(ctypes.byref(big), diag, fake[7], fake[8], 1e-10, 10, None, None) == -5
     lib.eqsolve_strerror.restype = ctypes.c_char_p
     assert b"static workspace" in lib.eqsolve_strerror(-5)
+
+
+def test_stream_probe_argument_errors_without_device(lib):
+    # checked before any HIP call: mixes other than 11 or 13 reads and 5 writes, null or aliased arrays
+    f = lib.eqsolve_debug_stream
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
+                  ctypes.c_void_p]
+    ins = (ctypes.c_void_p * 13)(*[0x1000 * (k + 1) for k in range(13)])
+    outs = (ctypes.c_void_p * 5)(*[0x100000 * (k + 1) for k in range(5)])
+    assert f(ins, 12, outs, 5, 100, 1, None) == -1
+    assert f(ins, 13, outs, 4, 100, 1, None) == -1
+    assert f(ins, 13, outs, 5, 0, 1, None) == -1
+    assert f(None, 13, outs, 5, 100, 1, None) == -1
+    aliased = (ctypes.c_void_p * 5)(*([0x1000] + [0x100000 * (k + 2) for k in range(4)]))
+    assert f(ins, 13, aliased, 5, 100, 1, None) == -1
+    holes = (ctypes.c_void_p * 13)(*([0x1000 * (k + 1) for k in range(12)] + [None]))
+    assert f(holes, 13, outs, 5, 100, 1, None) == -1

@@ -1130,3 +1130,26 @@ def test_step_form_is_for_fp64_contexts(torch_dev):
     with pytest.raises(EqSolveError):
         ctx.set_step_form("unscaled")
     ctx.close()
+
+
+@pytest.mark.parametrize("nreads,nt", [(13, 1), (11, 1), (13, 0)])
+def test_stream_probe_writes_its_definition(torch_dev, nreads, nt):
+    # the streaming kernel the step's rate is read against: out_w = w + sum_k (k+1) in_k on every
+    # cell, a ragged count (not a multiple of the 512 cells of a block), nothing written past n
+    torch, dev = torch_dev
+    from paper_2211_15605_amd import binding
+    n = 5 * 512 + 77
+    rng = np.random.default_rng(11)
+    ins = [torch.from_numpy(rng.uniform(-1, 1, n)).to(dev) for _ in range(nreads)]
+    outs = [torch.full((n + 64,), 7.0, dtype=torch.float64, device=dev) for _ in range(5)]
+    rc = binding.eqsolve_debug_stream([t.data_ptr() for t in ins], [t.data_ptr() for t in outs], n, nt,
+                                      torch.cuda.current_stream().cuda_stream)
+    assert rc == 0
+    torch.cuda.synchronize()
+    s = np.zeros(n)
+    for k in range(nreads):
+        s = s + (k + 1) * host(ins[k])
+    for w in range(5):
+        o = host(outs[w])
+        assert np.allclose(o[:n], s + w, rtol=0, atol=64 * EPS * np.max(np.abs(s) + w))
+        assert np.all(o[n:] == 7.0)
