@@ -551,6 +551,7 @@ def gpu_leg(args, cfg_id, steps=None, warmup=None, with_mg=True):
         "symmetric_form": {"fp64": form_sym, "fp32_refine": bool(rec[-1][3]["symmetric"])},
         "kernels_fp64_ms": {kern: {"launches": k1_cnt, "mean_ms": k1_avg_ms}},
         "layout": c64.layout(),
+        "layout_fp32_refine": c32.layout(),
         "cells": n,
     }
     # what a plain kernel streaming the same words per cell reaches over the same cells
@@ -693,6 +694,7 @@ def gpu_leg_batched(args):
         "symmetric_form": {"fp64": form_sym, "fp32_refine": all(i["symmetric"] for i in rec[-1][3])},
         "kernels_fp64_ms": {kern: {"launches": k1_cnt, "mean_ms": k1_ms / max(k1_cnt, 1)}},
         "layout": [c64.layout(i) for i in range(len(grids))],
+        "layout_fp32_refine": [c32.layout(i) for i in range(len(grids))],
         "cells": sum(n_all),
     }
     sols = {"fp64": [x.cpu().numpy() for x in x64], "fp32_refine": [x.cpu().numpy() for x in x32]}
@@ -948,7 +950,7 @@ def main():
                                    "symmetric near-singular" if cfg["recipe"] == "sym" else "convection-diffusion",
                                    "s" if batched else "", " + ".join("%dx%dx%d" % gg.shape for gg in cfg["grids"]),
                                    cfg["tol"], " (all sets in one call)" if batched else ""),
-                   "cells": r["cells"], "layout": r["layout"]},
+                   "cells": r["cells"], "layout": r["layout"], "layout_fp32_refine": r["layout_fp32_refine"]},
         "roofline": r["roofline"],
         "cpu_baseline": cpu["cpu_baseline"] if cpu else None,
         "vs_oracle": cpu["vs_oracle"] if cpu else None,

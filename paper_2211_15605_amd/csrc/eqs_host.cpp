@@ -1630,11 +1630,15 @@ int eqsolve_autotune(eqs_ctx *c, const char *cache_path, int32_t iters) {
             }
         }
     }
-    // pointwise block count, with the chosen march tiling
+    // pointwise block count, with the chosen march tiling.  The single-sync step launches no
+    // pointwise kernel, so timing it cannot choose one: those contexts keep the default count
+    // (measured on the 128x256x128 pressure-like system, whose multigrid iteration runs pointwise
+    // passes every step: 8.53-8.54 ms per solve with 512 or 1024 blocks, 8.62 with 2048, 8.93 with
+    // 4096, 8.82 with 256)
     c->cpt = best_cpt;
     c->fnt = best_fnt;
     clear_graphs(c);
-    for (int s = 0; s < c->nsets && rc == EQS_OK; ++s) {
+    for (int s = 0; s < c->nsets && rc == EQS_OK && !c->sync1; ++s) {
         SetHost &h = c->sets[s];
         for (int nf : flats) {
             set_tiling(h, best_cpt, best[s].kc, nf, best_fnt, best[s].ford);

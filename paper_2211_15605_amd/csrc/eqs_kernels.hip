@@ -1710,7 +1710,7 @@ __global__ void __launch_bounds__(kBlock) mat_kernel(LaunchSets ls) {
             Y[u] = ld(y, i);
             Pv[u] = ld(p, i);
             Sv[u] = ld(s, i);
-            Tt[u] = ld(t, i);
+            Tt[u] = mode == 3 ? ld(t, i) : T(0);  // t only for a restart residual
         }
 #pragma unroll
         for (int u = 0; u < kFlatU; ++u) {
