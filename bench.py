@@ -864,6 +864,65 @@ def summarize_trace(args):
     print("\n".join(lines))
 
 
+def trace_gaps(args):
+    """Launch boundaries of one kernel in a kernel trace: its launches of `--pmc-grid` work-items that
+    did work (> 100 us), grouped into solves (a pause of more than 3 ms starts a new one); per solve,
+    the launches' summed durations against their span, and the gaps between launches that follow
+    each other directly in the stream and between those with other work (a host readback, another
+    kernel) between them."""
+    import csv
+    import glob
+    f = sorted(glob.glob(os.path.join(args.trace_gaps, "**", "*kernel_trace.csv"), recursive=True))
+    assert f, "no kernel_trace.csv under %s" % args.trace_gaps
+    rows = sorted(csv.DictReader(open(f[0])), key=lambda r: int(r["Start_Timestamp"]))
+    t = [(int(r["Start_Timestamp"]), int(r["End_Timestamp"])) for r in rows]
+    sel = [i for i, r in enumerate(rows) if args.pmc_kernel in r["Kernel_Name"]
+           and (not args.pmc_grid or int(r["Grid_Size_X"]) == args.pmc_grid) and t[i][1] - t[i][0] > 100000]
+    groups = [[sel[0]]] if sel else []
+    for a, b in zip(sel, sel[1:]):
+        if t[b][0] - t[a][1] > 3000000:
+            groups.append([])
+        groups[-1].append(b)
+    print("| solve | launches | summed ms | span ms | idle share | back-to-back gaps: n, mean us | other gaps: n, total us |")
+    print("|---|---|---|---|---|---|---|")
+    for n, g in enumerate(groups):
+        busy = sum(t[i][1] - t[i][0] for i in g)
+        span = t[g[-1]][1] - t[g[0]][0]
+        adj = [t[b][0] - t[a][1] for a, b in zip(g, g[1:]) if b == a + 1]
+        oth = [t[b][0] - t[a][1] for a, b in zip(g, g[1:]) if b != a + 1]
+        print("| %d | %d | %.2f | %.2f | %.2f %% | %d, %.2f | %d, %.1f |" % (
+            n, len(g), busy / 1e6, span / 1e6, 100.0 * (span - busy) / span, len(adj),
+            (sum(adj) / len(adj) / 1e3) if adj else 0.0, len(oth), sum(oth) / 1e3))
+
+
+def summarize_counters(args):
+    """Mean of every counter of a rocprofv3 --pmc run (counter_collection.csv) per kernel, over its
+    dispatches of `--pmc-grid` work-items (all, if 0) that ran longer than 500 us."""
+    import csv
+    import glob
+    import collections
+    f = sorted(glob.glob(os.path.join(args.summarize_counters, "**", "*counter_collection.csv"), recursive=True))
+    assert f, "no counter_collection.csv under %s" % args.summarize_counters
+    disp = collections.defaultdict(dict)
+    for r in csv.DictReader(open(f[0])):
+        name = r["Kernel_Name"]
+        short = name[:name.rindex("(")] if name.endswith(")") and "(" in name else name
+        if args.trace_kernels and not any(k in short for k in args.trace_kernels.split(",")):
+            continue
+        if args.pmc_grid and int(r["Grid_Size"]) != args.pmc_grid:
+            continue
+        if int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) <= 500000:
+            continue
+        disp[(short, r["Dispatch_Id"])][r["Counter_Name"]] = float(r["Counter_Value"])
+    per = collections.defaultdict(list)
+    for (short, _), d in disp.items():
+        per[short].append(d)
+    for short, ds in sorted(per.items()):
+        names = sorted(ds[0])
+        print("`%s`: %d dispatches; " % (short, len(ds)) + ", ".join(
+            "%s %.4g" % (c, sum(d.get(c, 0.0) for d in ds) / len(ds)) for c in names))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -894,7 +953,17 @@ def main():
     ap.add_argument("--summarize-trace", metavar="TRACE_DIR", help="print a markdown summary of a kernel trace")
     ap.add_argument("--trace-min-share", type=float, default=0.01)
     ap.add_argument("--trace-kernels", default="", help="comma-separated name parts: only those kernels")
+    ap.add_argument("--trace-gaps", metavar="TRACE_DIR",
+                    help="launch boundaries of --pmc-kernel (launches of --pmc-grid work-items) per solve")
+    ap.add_argument("--summarize-counters", metavar="PMC_DIR",
+                    help="per-kernel means of every counter of a --pmc run (dispatches of --pmc-grid work-items)")
     args = ap.parse_args()
+    if args.trace_gaps:
+        trace_gaps(args)
+        return
+    if args.summarize_counters:
+        summarize_counters(args)
+        return
     if args.reduce_pmc:
         reduce_pmc(args)
         return
