@@ -330,6 +330,8 @@ LaunchSets launch_table(eqs_ctx *c, int first, int count, int *total, int *total
     }
     ls.fnt = c->fnt;
     ls.desc = c->d_desc + first;
+    // each XCD runs a share of every set ($EQS_XBAL=0: one contiguous run of the launch per XCD)
+    ls.xbal = env_int("EQS_XBAL", 1) != 0 ? 7 : 0;
     *total = acc;
     *total_flat = accf;
     return ls;

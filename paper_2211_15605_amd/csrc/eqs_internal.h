@@ -166,6 +166,9 @@ struct LaunchSets {
     int32_t ftile_begin[kMaxSets + 1];  // the single-sync step's tiles (SetDesc::fntiles)
     int32_t fnt;                        // threads per block of the single-sync step (256 or 512)
     const SetDesc *desc;   // device table, nsets entries
+    // bit 0: tiles, bit 1: pointwise blocks, bit 2: the single-sync step's tiles -- each XCD runs a
+    // share of every set (the balanced map of locate_in) instead of one run of the launch
+    int32_t xbal;
 };
 
 }  // namespace eqs

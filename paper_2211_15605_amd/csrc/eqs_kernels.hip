@@ -56,25 +56,51 @@ struct TileRef {
     int tile;
 };
 
-// block -> (set, tile) for march kernels (FLAT = false) or (set, block) for pointwise ones
-template <bool FLAT>
-__device__ __forceinline__ TileRef locate(const LaunchSets &ls) {
-    const int L = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+// block -> (set, index in the set's list) over the launch's concatenated lists (begin: each set's
+// first index, begin[nsets] the total).  The hardware hands block b to XCD b % 8, so XCD x runs
+// floor(n / 8) blocks, one more if x < n % 8.  Contiguous map (xcd_remap): XCD x takes one run of
+// the concatenated list, so neighbouring tiles, which read each other's halo cells, share its L2,
+// but a set's tiles then sit on one or two XCDs only, and a launch in which only some sets have work
+// (the others return at once) leaves the other XCDs idle.  Balanced map (bal): XCD x takes a run of
+// every set instead, set q giving each XCD floor(T_q / 8) of its T_q tiles and its T_q % 8 extra
+// ones to consecutive XCDs, the extras of the sets dealt round the eight XCDs in turn; that gives
+// each XCD exactly the number of blocks the hardware hands it.  Either map is a bijection, and each
+// block's partial sums go to its tile's slot, so results do not depend on the map.
+__device__ __forceinline__ TileRef locate_in(const LaunchSets &ls, const int32_t *begin, bool bal) {
+    const int b = (int)blockIdx.x;
+    if (bal) {
+        const int x = b % 8, slot = b / 8;
+        int c = 0, o = 0;  // XCD x's slots taken by the sets before q; extras dealt so far, mod 8
+#pragma unroll
+        for (int q = 0; q < kMaxSets; ++q) {
+            const int T = begin[q + 1] - begin[q], k = T >> 3, r = T & 7;
+            const int a = k + (((x - o) & 7) < r ? 1 : 0);  // set q's tiles on XCD x
+            if (q < ls.nsets && (slot < c + a || q == ls.nsets - 1)) {
+                int before = x * k;  // set q's tiles on the XCDs before x
+                for (int y = 0; y < x; ++y) before += ((y - o) & 7) < r ? 1 : 0;
+                return TileRef{ls.desc + q, before + slot - c};
+            }
+            c += a;
+            o = (o + r) & 7;
+        }
+    }
+    const int L = xcd_remap(b, (int)gridDim.x);
     int s = 0;
 #pragma unroll
     for (int q = 1; q < kMaxSets; ++q)
-        if (q < ls.nsets && L >= (FLAT ? ls.flat_begin[q] : ls.tile_begin[q])) s = q;
-    return TileRef{ls.desc + s, L - (FLAT ? ls.flat_begin[s] : ls.tile_begin[s])};
+        if (q < ls.nsets && L >= begin[q]) s = q;
+    return TileRef{ls.desc + s, L - begin[s]};
+}
+
+// block -> (set, tile) for march kernels (FLAT = false) or (set, block) for pointwise ones
+template <bool FLAT>
+__device__ __forceinline__ TileRef locate(const LaunchSets &ls) {
+    return FLAT ? locate_in(ls, ls.flat_begin, (ls.xbal & 2) != 0) : locate_in(ls, ls.tile_begin, (ls.xbal & 1) != 0);
 }
 
 // block -> (set, tile) for the single-sync step (its own tiling)
 __device__ __forceinline__ TileRef locate_fused(const LaunchSets &ls) {
-    const int L = xcd_remap((int)blockIdx.x, (int)gridDim.x);
-    int s = 0;
-#pragma unroll
-    for (int q = 1; q < kMaxSets; ++q)
-        if (q < ls.nsets && L >= ls.ftile_begin[q]) s = q;
-    return TileRef{ls.desc + s, L - ls.ftile_begin[s]};
+    return locate_in(ls, ls.ftile_begin, (ls.xbal & 4) != 0);
 }
 
 // global-address-space accessors: pointers taken from the set table are

@@ -1153,3 +1153,48 @@ def test_stream_probe_writes_its_definition(torch_dev, nreads, nt):
         o = host(outs[w])
         assert np.allclose(o[:n], s + w, rtol=0, atol=64 * EPS * np.max(np.abs(s) + w))
         assert np.all(o[n:] == 7.0)
+
+
+# ---------------------------------------------------------------- XCD-balanced block map
+
+# each XCD runs a share of every set of a batched launch; the shapes give tile, step-tile and
+# pointwise-block counts that are multiples of 8 (64 x 64 planes in 512-cell segments, 8-plane
+# chunks, 64 pointwise blocks) and counts that are not (the ragged grids)
+XBAL_CASES = {
+    "mult8": ([(64, 64, 32), (64, 64, 16), (64, 64, 24)],
+              dict(EQS_CPT=2, EQS_KC=8, EQS_FNT=256, EQS_FORD=1, EQS_FLAT_MAX=64, EQS_SMALL=0)),
+    "ragged": ([(33, 17, 9), (40, 24, 13), (20, 31, 7), (9, 50, 11)], dict(EQS_KC=3, EQS_SMALL=0)),
+}
+
+
+@pytest.mark.parametrize("case", ["mult8", "ragged"])
+@pytest.mark.parametrize("precision,mg", [("fp64", False), ("fp32_refine", False), ("fp64", True)],
+                         ids=["fp64", "fp32_refine_instream", "fp64_multigrid"])
+def test_xcd_balanced_map_equals_contiguous_map(torch_dev, orc, monkeypatch, case, precision, mg):
+    # the block -> (set, tile) map decides only which XCD runs a tile: batched solves under the
+    # balanced map equal those under the contiguous one and each set's own solve, bit for bit (FP32:
+    # with the refinement's housekeeping launched after every step, which acts on some sets only)
+    torch, dev = torch_dev
+    shapes, env = XBAL_CASES[case]
+    systems = [manufactured(orc, 1 if mg else 2, grid=W.Grid(*sh), set_id=i) for i, sh in enumerate(shapes)]
+    Ds = [dev_arrays(torch, dev, s[1]) for s in systems]
+    bs = [dev_arrays(torch, dev, [s[2]])[0] for s in systems]
+    monkeypatch.setenv("EQS_REFINE_INSTREAM_CELLS", "0")
+    out = {}
+    for xbal in ("1", "0"):
+        monkeypatch.setenv("EQS_XBAL", xbal)
+        ctx = context(shapes, precision=precision, env=env)
+        if mg:
+            ctx.set_preconditioner("mg", gamma=1.6, coarse_sweeps=15)
+        print("xbal", xbal, case, precision, mg, [ctx.layout(i) for i in range(len(shapes))], flush=True)
+        xb, infos = ctx.solve_batched(Ds, bs, tol=1e-10, maxit=5000)
+        out[xbal] = ([host(x) for x in xb], infos)
+        if xbal == "1":
+            for i in range(len(systems)):
+                xi, info = ctx.solve(Ds[i], bs[i], tol=1e-10, maxit=5000, set_id=i)
+                assert np.array_equal(host(xi), host(xb[i])) and info == infos[i], i
+        ctx.close()
+    for i, s in enumerate(systems):
+        assert np.array_equal(out["1"][0][i], out["0"][0][i]) and out["1"][1][i] == out["0"][1][i], i
+        assert out["1"][1][i]["status"] == 0
+        assert orc.rel_residual(s[0].shape, s[1], s[2], out["1"][0][i]) <= 1e-10
