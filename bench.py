@@ -839,7 +839,7 @@ def reduce_pmc(args):
 def summarize_trace(args):
     """Markdown summary of a rocprofv3 --kernel-trace run (kernel_trace.csv): per kernel and grid
     size, the launches that did work (a launch past its sets' convergence returns in < 10 us) and
-    their mean duration."""
+    their mean and median durations."""
     import csv
     import glob
     import collections
@@ -849,8 +849,8 @@ def summarize_trace(args):
     for r in csv.DictReader(open(f[0])):
         g[(r["Kernel_Name"], int(r["Grid_Size_X"]) // int(r["Workgroup_Size_X"]))].append(
             int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
-    lines = ["| kernel | blocks per launch | launches | with work (> 10 us) | mean us (with work) | total ms |",
-             "|---|---|---|---|---|---|"]
+    lines = ["| kernel | blocks per launch | launches | with work (> 10 us) | mean us (with work) | median us (with work) "
+             "| total ms |", "|---|---|---|---|---|---|---|"]
     tot = sum(sum(v) for v in g.values())
     for (name, blocks), v in sorted(g.items(), key=lambda kv: -sum(kv[1])):
         if sum(v) < args.trace_min_share * tot:
@@ -859,8 +859,10 @@ def summarize_trace(args):
         short = name[:name.rindex("(")] if name.endswith(")") and "(" in name else name
         if args.trace_kernels and not any(k in short for k in args.trace_kernels.split(",")):
             continue
-        lines.append("| `%s` | %d | %d | %d | %.1f | %.2f |" % (short, blocks, len(v), len(w),
-                                                             (sum(w) / len(w) / 1e3) if w else 0.0, sum(v) / 1e6))
+        med = sorted(w)[len(w) // 2] / 1e3 if w else 0.0
+        lines.append("| `%s` | %d | %d | %d | %.1f | %.1f | %.2f |" % (short, blocks, len(v), len(w),
+                                                                   (sum(w) / len(w) / 1e3) if w else 0.0, med,
+                                                                   sum(v) / 1e6))
     print("\n".join(lines))
 
 
@@ -893,6 +895,54 @@ def trace_gaps(args):
         print("| %d | %d | %.2f | %.2f | %.2f %% | %d, %.2f | %d, %.1f |" % (
             n, len(g), busy / 1e6, span / 1e6, 100.0 * (span - busy) / span, len(adj),
             (sum(adj) / len(adj) / 1e3) if adj else 0.0, len(oth), sum(oth) / 1e3))
+
+
+def simple_phases(args):
+    """Per SIMPLE iteration of a kernel trace of the SIMPLE section (from one momentum formation to the
+    next): the phases' means in us (momentum formation, momentum solve phase, p' formation, p' solve
+    phase, correction, the whole iteration, everything but the p' solve), grouped by the p' solver
+    (multigrid or Jacobi) and the number of momentum steps that did work, and the kernels of the
+    momentum solve phase summed per iteration."""
+    import csv
+    import glob
+    import collections
+    f = sorted(glob.glob(os.path.join(args.simple_phases, "**", "*kernel_trace.csv"), recursive=True))
+    assert f, "no kernel_trace.csv under %s" % args.simple_phases
+    rows = sorted(csv.DictReader(open(f[0])), key=lambda r: int(r["Start_Timestamp"]))
+    t0 = [int(r["Start_Timestamp"]) / 1e3 for r in rows]
+    t1 = [int(r["End_Timestamp"]) / 1e3 for r in rows]
+    name = [r["Kernel_Name"] for r in rows]
+    fm = [i for i, n in enumerate(name) if "form_momentum_kernel" in n]
+    groups = collections.defaultdict(list)
+    kern = collections.defaultdict(lambda: collections.defaultdict(float))
+    for a, b in zip(fm, fm[1:]):
+        try:
+            ip = next(i for i in range(a, b) if "form_pressure_kernel" in name[i])
+            ic = next(i for i in range(ip, b) if "correct_kernel" in name[i])
+        except StopIteration:
+            continue
+        mg = any("mg_" in name[i] for i in range(ip, ic))
+        steps = sum(1 for i in range(a + 1, ip) if "fused_kernel" in name[i] and t1[i] - t0[i] > 10)
+        key = ("multigrid" if mg else "Jacobi", steps)
+        ph = (t1[a] - t0[a], t0[ip] - t1[a], t1[ip] - t0[ip], t0[ic] - t1[ip], t1[ic] - t0[ic], t0[b] - t0[a])
+        groups[key].append(ph)
+        for i in range(a + 1, ip):
+            n = name[i]
+            kern[key][n[:n.rindex("(")] if n.endswith(")") and "(" in n else n] += t1[i] - t0[i]
+    print("| p' solver, momentum steps | iterations | momentum formation | momentum solve phase | p' formation | "
+          "p' solve phase | correction | iteration | everything but the p' solve |")
+    print("|---|---|---|---|---|---|---|---|---|")
+    for key in sorted(groups):
+        v = groups[key]
+        m = [sum(x[j] for x in v) / len(v) for j in range(6)]
+        print("| %s, %d | %d | %.0f | %.0f | %.0f | %.0f | %.0f | %.0f | %.0f |" % (
+            key[0], key[1], len(v), m[0], m[1], m[2], m[3], m[4], m[5], m[5] - m[3]))
+    for key in sorted(groups):
+        n = len(groups[key])
+        print("\n%s p' solves, %d momentum steps: kernels of the momentum solve phase, us per iteration" % key)
+        for k, t in sorted(kern[key].items(), key=lambda kv: -kv[1]):
+            if t / n >= 1.0:
+                print("  `%s`: %.1f" % (k, t / n))
 
 
 def summarize_counters(args):
@@ -955,6 +1005,8 @@ def main():
     ap.add_argument("--trace-kernels", default="", help="comma-separated name parts: only those kernels")
     ap.add_argument("--trace-gaps", metavar="TRACE_DIR",
                     help="launch boundaries of --pmc-kernel (launches of --pmc-grid work-items) per solve")
+    ap.add_argument("--simple-phases", metavar="TRACE_DIR",
+                    help="per-iteration phases of a kernel trace of the SIMPLE section")
     ap.add_argument("--summarize-counters", metavar="PMC_DIR",
                     help="per-kernel means of every counter of a --pmc run (dispatches of --pmc-grid work-items)")
     args = ap.parse_args()
@@ -963,6 +1015,9 @@ def main():
         return
     if args.summarize_counters:
         summarize_counters(args)
+        return
+    if args.simple_phases:
+        simple_phases(args)
         return
     if args.reduce_pmc:
         reduce_pmc(args)
