@@ -118,3 +118,66 @@ def test_symmetric_form_words_and_which_workloads_take_it():
 def test_multigrid_settings_per_recipe():
     assert bench.mg_params_for(1)["gamma"] == 1.6     # pressure-like, near-singular
     assert bench.mg_params_for(2)["gamma"] == 1.0     # convection-diffusion sets
+
+
+def _trace(tmp_path, rows):
+    import csv
+    d = tmp_path / "trace"
+    d.mkdir()
+    with open(d / "run_kernel_trace.csv", "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(["Kernel_Name", "Start_Timestamp", "End_Timestamp", "Grid_Size_X", "Workgroup_Size_X"])
+        for r in rows:
+            w.writerow(r)
+    return str(d)
+
+
+def test_trace_gaps_groups_solves_and_splits_the_gaps(tmp_path, capsys):
+    # two solves of three 200 us launches, 3 ms apart; in the first a copy sits between launches 2 and 3
+    K = "void eqs::fused_kernel<double, 2, 1, 0, 512>(eqs::LaunchSets)"
+    us = 1000
+    rows = [(K, 0, 200 * us, 1024, 512), (K, 205 * us, 405 * us, 1024, 512),
+            ("__amd_rocclr_copyBuffer", 410 * us, 412 * us, 128, 128), (K, 450 * us, 650 * us, 1024, 512),
+            (K, 5000 * us, 5200 * us, 1024, 512), (K, 5200 * us, 5400 * us, 1024, 512),
+            (K, 5400 * us, 5600 * us, 1024, 512), (K, 6000 * us, 6005 * us, 1024, 512)]
+    ns = bench.argparse.Namespace(trace_gaps=_trace(tmp_path, rows), pmc_kernel="fused_kernel<double, 2, 1, 0, 512>",
+                                  pmc_grid=1024)
+    bench.trace_gaps(ns)
+    out = [l for l in capsys.readouterr().out.splitlines() if l.startswith("| 0") or l.startswith("| 1")]
+    assert out[0] == "| 0 | 3 | 0.60 | 0.65 | 7.69 % | 1, 5.00 | 1, 45.0 |"
+    assert out[1] == "| 1 | 3 | 0.60 | 0.60 | 0.00 % | 2, 0.00 | 0, 0.0 |"
+
+
+def test_simple_phases_of_one_iteration(tmp_path, capsys):
+    # momentum formation 0-100, two momentum steps with work and one empty, p' formation, a multigrid
+    # p' solve, correction, then the next iteration's formation at 1000 us
+    us = 1000
+    F = "void eqs::fused_kernel<double, 2, 1, 2, 256>(eqs::LaunchSets)"
+    rows = [("form_momentum_kernel", 0, 100 * us, 1, 1), (F, 110 * us, 210 * us, 1, 1),
+            (F, 210 * us, 310 * us, 1, 1), (F, 310 * us, 312 * us, 1, 1),
+            ("form_pressure_kernel", 320 * us, 350 * us, 1, 1), ("eqs::mg_restrict_kernel", 360 * us, 370 * us, 1, 1),
+            ("correct_kernel", 900 * us, 950 * us, 1, 1), ("form_momentum_kernel", 1000 * us, 1100 * us, 1, 1)]
+    ns = bench.argparse.Namespace(simple_phases=_trace(tmp_path, rows))
+    bench.simple_phases(ns)
+    lines = capsys.readouterr().out.splitlines()
+    assert "| multigrid, 2 | 1 | 100 | 220 | 30 | 550 | 50 | 1000 | 450 |" in lines
+    assert any("fused_kernel<double, 2, 1, 2, 256>`: 202.0" in l for l in lines)
+
+
+def test_summarize_counters_means_over_long_dispatches(tmp_path, capsys):
+    import csv
+    d = tmp_path / "pmc"
+    d.mkdir()
+    with open(d / "run_counter_collection.csv", "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(["Dispatch_Id", "Kernel_Name", "Grid_Size", "Counter_Name", "Counter_Value",
+                    "Start_Timestamp", "End_Timestamp"])
+        for i, (v, dur) in enumerate([(10.0, 600000), (30.0, 700000), (1000.0, 1000)]):
+            w.writerow([i, "void eqs::fused_kernel<double, 2, 1, 0, 512>(eqs::LaunchSets)", 884736, "SQ_WAVES", v,
+                        0, dur])
+        w.writerow([9, "other_kernel(int)", 884736, "SQ_WAVES", 5.0, 0, 900000])
+    ns = bench.argparse.Namespace(summarize_counters=str(d), trace_kernels="fused_kernel", pmc_grid=884736)
+    bench.summarize_counters(ns)
+    out = capsys.readouterr().out
+    assert "`void eqs::fused_kernel<double, 2, 1, 0, 512>`: 2 dispatches; SQ_WAVES 20" in out
+    assert "other_kernel" not in out
