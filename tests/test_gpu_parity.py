@@ -1198,3 +1198,26 @@ def test_xcd_balanced_map_equals_contiguous_map(torch_dev, orc, monkeypatch, cas
         assert np.array_equal(out["1"][0][i], out["0"][0][i]) and out["1"][1][i] == out["0"][1][i], i
         assert out["1"][1][i]["status"] == 0
         assert orc.rel_residual(s[0].shape, s[1], s[2], out["1"][0][i]) <= 1e-10
+
+
+def test_eight_sets_batched_equal_their_own_solves(torch_dev, orc):
+    # the largest batch a context takes: eight sets of mixed sizes (two of them single-tile, the others
+    # ragged multi-tile grids; the one-block solve off, so a set takes the same path alone as in the
+    # batch), FP64 and FP32 + refinement, each equal to its own solve bit for bit; a ninth set is refused
+    torch, dev = torch_dev
+    shapes = [(33, 17, 9), (8, 16, 8), (40, 24, 13), (20, 31, 7), (9, 50, 11), (12, 12, 12), (64, 20, 10),
+              (17, 33, 19)]
+    systems = [manufactured(orc, 2, grid=W.Grid(*sh), set_id=i % 4) for i, sh in enumerate(shapes)]
+    Ds = [dev_arrays(torch, dev, s[1]) for s in systems]
+    bs = [dev_arrays(torch, dev, [s[2]])[0] for s in systems]
+    for precision in ("fp64", "fp32_refine"):
+        ctx = context(shapes, precision=precision, env=dict(EQS_KC=3, EQS_SMALL=0))
+        xb, infos = ctx.solve_batched(Ds, bs, tol=1e-10, maxit=5000)
+        for i, s in enumerate(systems):
+            xi, info = ctx.solve(Ds[i], bs[i], tol=1e-10, maxit=5000, set_id=i)
+            assert np.array_equal(host(xi), host(xb[i])) and info == infos[i], (precision, i)
+            assert infos[i]["status"] == 0 and orc.rel_residual(s[0].shape, s[1], s[2], host(xb[i])) <= 1e-10
+        ctx.close()
+    from paper_2211_15605_amd.solver import EqSolveError
+    with pytest.raises((EqSolveError, ValueError)):
+        context(shapes + [(8, 8, 8)])
