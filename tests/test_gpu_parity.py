@@ -984,8 +984,9 @@ def test_symmetric_matrix_adjoint_runs_the_transposed_general_form(torch_dev, or
 
 # with the single-sync step's LDS capped at 64 KB, rows of 203..266 cells take it with one cell per
 # thread (257..266 with four halo slots per ring) and wider rows the three-launch iteration; with
-# the device's 160 KB, two cells per thread up to 512 (257..512: four halo slots)
-WIDE = [(230, 5, 4), (260, 5, 4), (266, 3, 3), (400, 4, 3)]
+# the device's 160 KB, two cells per thread up to 512 (257..512: four halo slots); wider rows, up to
+# the largest the library takes (1024), run the three-launch iteration with eight halo slots
+WIDE = [(230, 5, 4), (260, 5, 4), (266, 3, 3), (400, 4, 3), (700, 3, 4), (1024, 3, 3)]
 
 
 @pytest.mark.parametrize("shape", WIDE)
