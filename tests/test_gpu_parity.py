@@ -580,7 +580,10 @@ def _batched_full_size(torch, dev, orc, cfg, precisions, env=None):
     Ds = [dev_arrays(torch, dev, s[1]) for s in systems]
     bs = [dev_arrays(torch, dev, [s[2]])[0] for s in systems]
     for precision in precisions:
-        ctx = context(grids, precision=precision, env=env)
+        # "fp64_mg": FP64 with the multigrid preconditioner, all sets iterating together
+        ctx = context(grids, precision="fp64" if precision == "fp64_mg" else precision, env=env)
+        if precision == "fp64_mg":
+            ctx.set_preconditioner("mg", gamma=1.0, coarse_sweeps=15, coarse_cells=2048)
         xb, infos = ctx.solve_batched(Ds, bs, tol=1e-10, maxit=W.CONFIGS[cfg]["maxit"])
         print("config%d batched %s" % (cfg, precision), infos, flush=True)
         for i, (g, diags, b, xs) in enumerate(systems):
@@ -593,15 +596,17 @@ def _batched_full_size(torch, dev, orc, cfg, precisions, env=None):
 
 
 def test_config2_full_size_batched(torch_dev, orc):
-    """The four staggered sets of a time step (96-97 x 384-385 x 96-97), FP64 and FP32 + refinement."""
+    """The four staggered sets of a time step (96-97 x 384-385 x 96-97), FP64, FP32 + refinement and
+    FP64 with the multigrid preconditioner."""
     torch, dev = torch_dev
-    _batched_full_size(torch, dev, orc, 2, ["fp64", "fp32_refine"])
+    _batched_full_size(torch, dev, orc, 2, ["fp64", "fp32_refine", "fp64_mg"])
 
 
 def test_config4_full_size_batched(torch_dev, orc):
-    """The large tall bed: four 192 x 768 x 192 sets (113 M cells) in one call, FP32 + refinement and FP64."""
+    """The large tall bed: four 192 x 768 x 192 sets (113 M cells) in one call, FP32 + refinement, FP64
+    and FP64 with the multigrid preconditioner."""
     torch, dev = torch_dev
-    _batched_full_size(torch, dev, orc, 4, ["fp32_refine", "fp64"])
+    _batched_full_size(torch, dev, orc, 4, ["fp32_refine", "fp64", "fp64_mg"])
 
 
 # ---------------------------------------------------------------- multigrid preconditioner
